@@ -1,0 +1,60 @@
+"""Checks of the seeded input generators (shapes, symmetry, semidefiniteness, DOF counts)."""
+import numpy as np
+import pytest
+
+import fegen
+
+
+def _check_blocks(prob, tol=1e-12):
+    for e in range(0, prob.n_elem, max(1, prob.n_elem // 50)):
+        _, B = prob.element(e)
+        assert np.abs(B - B.T).max() <= 1e-14 * np.abs(B).max()
+        w = np.linalg.eigvalsh(B)
+        assert w[0] >= -tol * w[-1]
+
+
+def test_elasticity_q1_counts_and_blocks():
+    prob, b = fegen.elasticity_small()
+    assert prob.n == 2178 and prob.n_elem == 1024 and b.shape == (2178,)
+    assert prob.meta["lam"] == pytest.approx(0.576923076923) and prob.meta["mu"] == pytest.approx(0.384615384615)
+    _check_blocks(prob)
+    assert prob.agg_of_dof.max() + 1 == 121
+    # every DOF is covered by at least one element
+    assert np.unique(prob.elem_dofs).size == prob.n
+
+
+def test_rtcf3_counts_and_blocks():
+    for N in (2, 5, 128):
+        dofs, node, n = fegen.hdiv.rtcf3_dofs(N)
+        assert n == 6 * N * (N + 1) + 12 * N * N
+    assert fegen.hdiv.rtcf3_dofs(128)[2] == 295680
+    prob, _ = fegen.graddiv_hdiv(N=6)
+    _check_blocks(prob)
+    # normal continuity: an edge DOF is shared by exactly the two cells of an interior edge
+    counts = np.bincount(prob.elem_dofs, minlength=prob.n)
+    assert set(np.unique(counts)) == {1, 2}
+
+
+def test_rtcf3_divergence_of_a_constant_field_vanishes():
+    """u = (1, 0) lies in RTCF_3; its element coefficients make the div-div block vanish."""
+    Div, Mass = fegen.hdiv.rtcf3_reference(0.25)
+    c = np.zeros(24)
+    c[:12] = 1.0            # Lagrange bases sum to one in each direction
+    assert abs(c @ Div @ c) <= 1e-12
+    assert c @ Mass @ c == pytest.approx(0.25 ** 2)
+
+
+def test_q2hex_blocks():
+    prob = fegen.elasticity_q2hex(2, nu=0.3)
+    assert prob.n == 3 * 5 ** 3 and prob.n_elem == 8
+    _check_blocks(prob, tol=1e-11)
+    # interior-type block: 81 DOFs minus 6 rigid modes
+    w = np.linalg.eigvalsh(prob.element(1)[1])
+    assert np.sum(w < 1e-10 * w[-1]) == 6
+
+
+def test_batch_preset_is_seeded():
+    a = fegen.elasticity_batch(n_inst=3, nmin=4, nmax=8, nrhs=2)
+    b = fegen.elasticity_batch(n_inst=3, nmin=4, nmax=8, nrhs=2)
+    for (pa, ba), (pb, bb) in zip(a, b):
+        assert pa.n == pb.n and np.array_equal(ba, bb) and ba.shape == (2, pa.n)
