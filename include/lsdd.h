@@ -1,0 +1,179 @@
+/*
+ * lsdd.h — C-ABI of the MI355X LS-AMG-DD library (liblsdd.so).
+ *
+ * The library builds and applies the least-squares AMG-DD multilevel
+ * preconditioner for an SPD matrix given in Gram form A = G^T G, where G stacks
+ * element-local Gram factors of a conforming finite-element assembly
+ * (Krzysik, Southworth, Wimmer: Sec. 2 for the method, Prop. "elementwise Gram
+ * formulation" of Sec. 5.1 for A = sum_T R_T^T A_T R_T = G^T G, Sec. 5.2 for the
+ * eigendecomposition factor G_T = Lambda_+^{1/2} Q_+^T), and solves A x = b with
+ * preconditioned CG whose preconditioner is one symmetric V-cycle.
+ *
+ * Conventions for every entry point:
+ *  - Every function returns an lsdd_status; no C++ exception crosses the ABI.
+ *    On failure lsdd_last_error() returns a thread-local message.
+ *  - Integer index arrays are 0-based.  Dense element blocks are row-major
+ *    (they are symmetric, so the order only matters for the asymmetry check).
+ *  - Buffers flagged "device" are HIP device pointers on the current device;
+ *    buffers flagged "host" are ordinary host memory.
+ *  - All device work is enqueued on the caller's hip stream (`hip_stream`,
+ *    a hipStream_t cast to void*; NULL = the null stream).  A function returns
+ *    after the work it must report on (status, iteration counts) is complete.
+ *  - Input arrays are caller-owned and are copied during setup; the hierarchy
+ *    owns all of its device memory until lsdd_destroy().
+ *  - Index validation happens on the host before any kernel launch.
+ *  - A hierarchy is not thread-safe; use one handle per host thread.
+ */
+#ifndef LSDD_H
+#define LSDD_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    LSDD_OK = 0,
+    LSDD_E_INVAL = 1,        /* bad argument, index out of range, asymmetric block, NaN/Inf   */
+    LSDD_E_NOT_SPSD = 2,     /* an element block has lambda_min < -spsd_tol * lambda_max     */
+    LSDD_E_NOMEM = 3,        /* device or host allocation failed                              */
+    LSDD_E_HIP = 4,          /* a HIP runtime call failed                                     */
+    LSDD_E_NOCONV = 5,       /* PCG reached max_iter; x holds the last iterate                */
+    LSDD_E_BREAKDOWN = 6,    /* PCG breakdown (p^T A p <= 0 or a non-finite scalar)            */
+    LSDD_E_UNSUPPORTED = 7,  /* a size or option this build does not handle                   */
+    LSDD_E_NUMERIC = 8       /* a local factorisation failed (a local matrix is not SPD)      */
+} lsdd_status;
+
+typedef struct lsdd_hierarchy lsdd_hierarchy;   /* opaque, library-owned */
+
+/* Setup and solve parameters.  Paper defaults (Sec. 6): two passes of standard
+ * aggregation, tau_cut = tau_const * max_j mult(j) (eq. tau-cut), at most three
+ * levels, stop below 10 DOFs or above 25 % density; the build adds the outer
+ * PCG tolerance and the precision of the cycle. */
+typedef struct {
+    int32_t max_levels;         /* level cap (>= 1); default 3                                */
+    int32_t agg_passes;         /* standard-aggregation passes on level 0; default 2          */
+    int32_t agg_passes_coarse;  /* passes on coarser levels; default 1                        */
+    int32_t modes_fixed;        /* > 0: keep this many smallest mu per aggregate; 0: tau_cut   */
+    int32_t min_coarse;         /* a level with fewer DOFs is the coarsest; default 10         */
+    int32_t max_iter;           /* PCG iteration cap; default 1000                             */
+    int32_t precision;          /* 0 = FP64 cycle, 1 = FP32 cycle inside FP64 PCG              */
+    int32_t reserved0;
+    double tau_const;           /* tau_cut = tau_const * max mult; default 0.75               */
+    double max_density;         /* nnz(A_l)/n_l^2 above this -> coarsest; default 0.25         */
+    double rtol;                /* PCG stop: ||r||_2 <= rtol ||b||_2; default 1e-8              */
+    double cluster_tol;         /* complete an eigenvalue cluster cut at its edge; 1e-9        */
+    double band_tol;            /* mu within band_tol above 1/tau_cut is retained; 1e-9        */
+    double rank_rtol;           /* element rank tolerance / lambda_max; 0 = n_T * eps          */
+    double spsd_tol;            /* lambda_min < -spsd_tol lambda_max -> LSDD_E_NOT_SPSD; 1e-12 */
+} lsdd_params;
+
+/* Per-solve report (one per right-hand side). */
+typedef struct {
+    int32_t iters;              /* PCG iterations = applications of A                         */
+    int32_t converged;          /* 1 if ||r|| <= rtol ||b||                                    */
+    double rel_res;             /* final ||r||_2 / ||b||_2 (recurrence residual)               */
+    double setup_s;             /* wall time of the setup that built the hierarchy             */
+    double solve_s;             /* wall time of this solve                                     */
+} lsdd_info;
+
+/* Fill *p with the defaults listed above. */
+void lsdd_params_default(lsdd_params* p);
+
+/* Build a hierarchy from element blocks and their DOF cover (Def. "DOF cover",
+ * Prop. "elementwise Gram formulation").
+ *   n            number of global DOFs (1 <= n < 2^31)
+ *   n_elem       number of elements (>= 1)
+ *   elem_ptr     host, int64[n_elem+1]: element e owns elem_dofs[elem_ptr[e] .. elem_ptr[e+1])
+ *   elem_dofs    host, int32[elem_ptr[n_elem]]: global DOFs, distinct within an element;
+ *                every DOF must belong to at least one element; 1 <= n_T <= 128
+ *   elem_blocks  host or device (mem_is_device), float64, the n_T x n_T blocks
+ *                concatenated, row-major; each must be symmetric and SPSD
+ *   node_of_dof  host, int32[n] or NULL: supernode of each DOF (all components of a
+ *                vertex, the DOFs of one edge, ...); supernodes are the vertices of
+ *                the aggregation graph.  NULL = every DOF is its own supernode
+ *   agg_of_dof   host, int32[n] or NULL: caller-given level-0 aggregates (values
+ *                0..n_agg-1, each used); NULL = standard aggregation
+ *   params       NULL = defaults
+ * Returns LSDD_E_NOT_SPSD (message names the element) for an indefinite block,
+ * LSDD_E_INVAL for bad indices or an asymmetric block. */
+lsdd_status lsdd_setup_elements(int64_t n, int64_t n_elem, const int64_t* elem_ptr,
+                                const int32_t* elem_dofs, const double* elem_blocks,
+                                const int32_t* node_of_dof, const int32_t* agg_of_dof,
+                                int mem_is_device, const lsdd_params* params, void* hip_stream,
+                                lsdd_hierarchy** out);
+
+/* Build a hierarchy from a black-box sparse Gram factor G (m x n, CSR, host),
+ * the input of Sec. 2 (A = G^T G, m >= n, full column rank).  Each row of G is
+ * its own cover member: row j contributes g_j g_j^T with support = its stored
+ * pattern (all stored entries count as support, zero values included).
+ * Rows with no stored entries are dropped (Sec. 2, after eq. row_multiplicity). */
+lsdd_status lsdd_setup_gram_csr(int64_t m, int64_t n, const int64_t* rowptr, const int32_t* col,
+                                const double* val, const int32_t* node_of_dof,
+                                const int32_t* agg_of_dof, const lsdd_params* params,
+                                void* hip_stream, lsdd_hierarchy** out);
+
+/* Solve A x = b for nrhs right-hand sides with PCG (x0 = 0) preconditioned by
+ * one V-cycle per iteration.
+ *   b, x   device, float64[nrhs * n] (right-hand side r at offset r*n); x is overwritten
+ *   info   host, lsdd_info[nrhs] or NULL
+ * NaN/Inf in b -> LSDD_E_INVAL.  LSDD_E_NOCONV leaves the last iterate in x. */
+lsdd_status lsdd_solve(lsdd_hierarchy* h, const double* b, double* x, int32_t nrhs,
+                       void* hip_stream, lsdd_info* info);
+
+/* Apply the preconditioner once: z = V(r) (the symmetric V-cycle of Sec. 2 with
+ * forward multiplicative Schwarz pre-smoothing and reverse-order post-smoothing).
+ *   r, z   device, float64[n] */
+lsdd_status lsdd_vcycle(lsdd_hierarchy* h, const double* r, double* z, void* hip_stream);
+
+/* y = A_l x on level l (A_0 = A, A_{l+1} = P_l^T A_l P_l).  x, y device float64[n_l]. */
+lsdd_status lsdd_apply(lsdd_hierarchy* h, int32_t level, const double* x, double* y,
+                       void* hip_stream);
+
+/* Level summary (host outputs, any may be NULL):
+ *   levels            number of levels L
+ *   n_l, nnz_l        int64[L] each (structural nonzeros of A_l)
+ *   oc, gc            operator complexity sum nnz_l / nnz_0, grid complexity sum n_l / n_0
+ *                     (the complexity measures of Sec. 6) */
+lsdd_status lsdd_hierarchy_info(const lsdd_hierarchy* h, int32_t* levels, int64_t* n_l,
+                                int64_t* nnz_l, double* oc, double* gc);
+
+/* Sizes of the arrays lsdd_export_level fills for level l (host int64[8]):
+ *   [0] n_l  [1] nnz(A_l)  [2] n_agg (0 on the coarsest level)  [3] sum |omega_i| * k_i
+ *   [4] sum |Omega_i|  [5] number of colours  [6] n_{l+1}  [7] number of elements on level l */
+lsdd_status lsdd_level_sizes(const lsdd_hierarchy* h, int32_t level, int64_t* sizes);
+
+/* Copy level-l data to host buffers (any may be NULL; sizes from lsdd_level_sizes):
+ *   agg_of_dof int32[n_l]; k int32[n_agg] (retained modes); Z float64[sum |w_i| k_i]
+ *   (aggregate-major, each Z_i row-major |omega_i| x k_i, rows in ascending DOF order,
+ *   columns in ascending mu); mu float64[sum |omega_i|] (sorted local spectra);
+ *   colors int32[n_agg]; rowptr int64[n_l+1], col int32[nnz], val float64[nnz] (A_l, CSR,
+ *   sorted columns); omega_sizes int32[n_agg] (|Omega_i|). */
+lsdd_status lsdd_export_level(const lsdd_hierarchy* h, int32_t level, int32_t* agg_of_dof,
+                              int32_t* k, double* Z, double* mu, int32_t* colors,
+                              int64_t* rowptr, int32_t* col, double* val, int32_t* omega_sizes);
+
+/* Level-0 element Gram factors (Sec. 5.2): ranks int32[n_elem] and, if G is not
+ * NULL, float64[sum n_T^2] with G_T stored row-major as an n_T x n_T array whose
+ * first r_T rows hold Lambda_+^{1/2} Q_+^T (remaining rows zero). */
+lsdd_status lsdd_export_gram(const lsdd_hierarchy* h, int32_t* ranks, double* G);
+
+/* Library allocator hook (e.g. a framework's caching allocator).  alloc returns a
+ * device pointer of at least `bytes` bytes on the current device or NULL; free
+ * releases it.  NULL functions restore hipMalloc/hipFree.  Call before setup. */
+typedef void* (*lsdd_alloc_fn)(uint64_t bytes, void* ctx);
+typedef void (*lsdd_free_fn)(void* ptr, void* ctx);
+void lsdd_set_allocator(lsdd_alloc_fn alloc, lsdd_free_fn free_fn, void* ctx);
+
+/* Thread-local text of the last error ("" if none). */
+const char* lsdd_last_error(void);
+
+/* Release the hierarchy and all of its device memory.  NULL is accepted. */
+lsdd_status lsdd_destroy(lsdd_hierarchy* h);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LSDD_H */

@@ -1,0 +1,310 @@
+// Host integer setup (see graph.hpp).  Sec. 2 of the paper: aggregates
+// (eq. agg_def), row-touching sets and overlaps (eqs. calR_def, overlap_def),
+// multiplicities (eq. row_multiplicity); Sec. 6: standard aggregation passes.
+#include "graph.hpp"
+
+#include <algorithm>
+#include <map>
+#include <stdexcept>
+
+namespace lsdd {
+
+namespace {
+
+// Build a CSR from (row, col) pairs, deduplicated and sorted per row.
+Csr pairs_to_csr(int64_t nrows, std::vector<std::pair<int32_t, int32_t>>& pr) {
+    std::sort(pr.begin(), pr.end());
+    pr.erase(std::unique(pr.begin(), pr.end()), pr.end());
+    Csr c;
+    c.ptr.assign(nrows + 1, 0);
+    c.idx.resize(pr.size());
+    for (size_t t = 0; t < pr.size(); ++t) {
+        c.ptr[pr[t].first + 1]++;
+        c.idx[t] = pr[t].second;
+    }
+    for (int64_t r = 0; r < nrows; ++r) c.ptr[r + 1] += c.ptr[r];
+    return c;
+}
+
+// Transpose of an incidence list: for each target, the sources listing it.
+Csr transpose(int64_t n_targets, const std::vector<int64_t>& ptr, const std::vector<int32_t>& idx) {
+    Csr t;
+    t.ptr.assign(n_targets + 1, 0);
+    for (int32_t v : idx) t.ptr[v + 1]++;
+    for (int64_t r = 0; r < n_targets; ++r) t.ptr[r + 1] += t.ptr[r];
+    t.idx.resize(idx.size());
+    std::vector<int64_t> fill(t.ptr.begin(), t.ptr.end() - 1);
+    int64_t nsrc = (int64_t)ptr.size() - 1;
+    for (int64_t s = 0; s < nsrc; ++s)
+        for (int64_t q = ptr[s]; q < ptr[s + 1]; ++q) t.idx[fill[idx[q]]++] = (int32_t)s;
+    return t;
+}
+
+}  // namespace
+
+Csr supernode_graph(int32_t n_super, const std::vector<int32_t>& node_of_dof, const ElemList& el) {
+    // element -> distinct supernodes, then supernode -> elements, then neighbours
+    std::vector<int64_t> eptr(el.count() + 1, 0);
+    std::vector<int32_t> enodes;
+    enodes.reserve(el.dofs.size());
+    for (int64_t e = 0; e < el.count(); ++e) {
+        size_t start = enodes.size();
+        for (int64_t q = el.ptr[e]; q < el.ptr[e + 1]; ++q) enodes.push_back(node_of_dof[el.dofs[q]]);
+        std::sort(enodes.begin() + start, enodes.end());
+        enodes.erase(std::unique(enodes.begin() + start, enodes.end()), enodes.end());
+        eptr[e + 1] = (int64_t)enodes.size();
+    }
+    Csr n2e = transpose(n_super, eptr, enodes);
+    Csr g;
+    g.ptr.assign(n_super + 1, 0);
+    std::vector<int32_t> mark(n_super, -1);
+    for (int32_t s = 0; s < n_super; ++s) {
+        mark[s] = s;
+        size_t start = g.idx.size();
+        for (int64_t q = n2e.ptr[s]; q < n2e.ptr[s + 1]; ++q) {
+            int32_t e = n2e.idx[q];
+            for (int64_t r = eptr[e]; r < eptr[e + 1]; ++r) {
+                int32_t t = enodes[r];
+                if (mark[t] != s) {
+                    mark[t] = s;
+                    g.idx.push_back(t);
+                }
+            }
+        }
+        std::sort(g.idx.begin() + start, g.idx.end());
+        g.ptr[s + 1] = (int64_t)g.idx.size();
+    }
+    return g;
+}
+
+std::vector<int32_t> standard_aggregation(const Csr& g, int32_t* n_agg) {
+    const int64_t n = g.rows();
+    std::vector<int32_t> agg(n, -1);
+    int32_t na = 0;
+    // roots: the whole neighbourhood is still free
+    for (int64_t i = 0; i < n; ++i) {
+        if (agg[i] >= 0) continue;
+        bool free_nb = true;
+        for (int64_t q = g.ptr[i]; q < g.ptr[i + 1] && free_nb; ++q) free_nb = agg[g.idx[q]] < 0;
+        if (!free_nb) continue;
+        agg[i] = na;
+        for (int64_t q = g.ptr[i]; q < g.ptr[i + 1]; ++q) agg[g.idx[q]] = na;
+        ++na;
+    }
+    // attach: lowest-index neighbour that was aggregated in the root phase
+    std::vector<int32_t> root_phase(agg);
+    for (int64_t i = 0; i < n; ++i) {
+        if (agg[i] >= 0) continue;
+        int32_t best = -1;
+        for (int64_t q = g.ptr[i]; q < g.ptr[i + 1]; ++q) {
+            int32_t j = g.idx[q];
+            if (root_phase[j] >= 0 && (best < 0 || j < best)) best = j;
+        }
+        if (best >= 0) agg[i] = root_phase[best];
+    }
+    // leftovers
+    for (int64_t i = 0; i < n; ++i) {
+        if (agg[i] >= 0) continue;
+        agg[i] = na;
+        for (int64_t q = g.ptr[i]; q < g.ptr[i + 1]; ++q)
+            if (agg[g.idx[q]] < 0) agg[g.idx[q]] = na;
+        ++na;
+    }
+    *n_agg = na;
+    return agg;
+}
+
+std::vector<int32_t> aggregate(const Csr& g0, int passes, int32_t* n_agg) {
+    const int64_t n = g0.rows();
+    std::vector<int32_t> agg(n);
+    for (int64_t i = 0; i < n; ++i) agg[i] = (int32_t)i;
+    int32_t na = (int32_t)n;
+    Csr g = g0;
+    for (int p = 0; p < passes; ++p) {
+        int32_t nn = 0;
+        std::vector<int32_t> a = standard_aggregation(g, &nn);
+        for (int64_t i = 0; i < n; ++i) agg[i] = a[agg[i]];
+        // quotient graph on the new aggregates
+        std::vector<std::pair<int32_t, int32_t>> pr;
+        for (int64_t u = 0; u < g.rows(); ++u)
+            for (int64_t q = g.ptr[u]; q < g.ptr[u + 1]; ++q) {
+                int32_t au = a[u], av = a[g.idx[q]];
+                if (au != av) pr.emplace_back(au, av);
+            }
+        g = pairs_to_csr(nn, pr);
+        na = nn;
+    }
+    *n_agg = na;
+    return agg;
+}
+
+Closure build_closure(int64_t n, const std::vector<int32_t>& agg_of_dof, int32_t n_agg, const ElemList& el) {
+    Closure c;
+    c.n_agg = n_agg;
+    // aggregates (ascending DOFs)
+    c.agg_ptr.assign(n_agg + 1, 0);
+    for (int64_t d = 0; d < n; ++d) c.agg_ptr[agg_of_dof[d] + 1]++;
+    for (int32_t i = 0; i < n_agg; ++i) c.agg_ptr[i + 1] += c.agg_ptr[i];
+    c.agg_dofs.resize(n);
+    c.pos_in_agg.resize(n);
+    {
+        std::vector<int64_t> fill(c.agg_ptr.begin(), c.agg_ptr.end() - 1);
+        for (int64_t d = 0; d < n; ++d) {
+            int32_t i = agg_of_dof[d];
+            c.pos_in_agg[d] = (int32_t)(fill[i] - c.agg_ptr[i]);
+            c.agg_dofs[fill[i]++] = (int32_t)d;
+        }
+    }
+    // element -> touched aggregates; multiplicity; aggregate -> touching elements
+    const int64_t ne = el.count();
+    c.mult.assign(ne, 0);
+    std::vector<int64_t> tptr(ne + 1, 0);
+    std::vector<int32_t> touched;
+    for (int64_t e = 0; e < ne; ++e) {
+        size_t start = touched.size();
+        for (int64_t q = el.ptr[e]; q < el.ptr[e + 1]; ++q) touched.push_back(agg_of_dof[el.dofs[q]]);
+        std::sort(touched.begin() + start, touched.end());
+        touched.erase(std::unique(touched.begin() + start, touched.end()), touched.end());
+        tptr[e + 1] = (int64_t)touched.size();
+        c.mult[e] = (int32_t)(tptr[e + 1] - tptr[e]);
+        c.max_mult = std::max(c.max_mult, c.mult[e]);
+    }
+    Csr a2e = transpose(n_agg, tptr, touched);
+    c.cl_ptr = a2e.ptr;
+    c.cl_elems = a2e.idx;
+    // overlaps: omega first, then the rest of the closure ascending
+    c.sub_ptr.assign(n_agg + 1, 0);
+    std::vector<int32_t> mark(n, -1);
+    std::vector<int32_t> gam;
+    for (int32_t i = 0; i < n_agg; ++i) {
+        for (int64_t q = c.agg_ptr[i]; q < c.agg_ptr[i + 1]; ++q) {
+            c.sub_dofs.push_back(c.agg_dofs[q]);
+            mark[c.agg_dofs[q]] = i;
+        }
+        gam.clear();
+        for (int64_t q = c.cl_ptr[i]; q < c.cl_ptr[i + 1]; ++q) {
+            int32_t e = c.cl_elems[q];
+            for (int64_t r = el.ptr[e]; r < el.ptr[e + 1]; ++r) {
+                int32_t d = el.dofs[r];
+                if (mark[d] != i) {
+                    mark[d] = i;
+                    gam.push_back(d);
+                }
+            }
+        }
+        std::sort(gam.begin(), gam.end());
+        c.sub_dofs.insert(c.sub_dofs.end(), gam.begin(), gam.end());
+        c.sub_ptr[i + 1] = (int64_t)c.sub_dofs.size();
+    }
+    return c;
+}
+
+std::vector<int32_t> color_subdomains(int64_t n, const Closure& c, const ElemList& el, int32_t* n_colors) {
+    const int32_t na = c.n_agg;
+    Csr d2s = transpose(n, c.sub_ptr, c.sub_dofs);        // DOF -> subdomains containing it
+    std::vector<std::pair<int32_t, int32_t>> pr;
+    std::vector<int32_t> subs;
+    for (int64_t e = 0; e < el.count(); ++e) {
+        subs.clear();
+        for (int64_t q = el.ptr[e]; q < el.ptr[e + 1]; ++q) {
+            int32_t d = el.dofs[q];
+            for (int64_t r = d2s.ptr[d]; r < d2s.ptr[d + 1]; ++r) subs.push_back(d2s.idx[r]);
+        }
+        std::sort(subs.begin(), subs.end());
+        subs.erase(std::unique(subs.begin(), subs.end()), subs.end());
+        for (size_t a = 0; a < subs.size(); ++a)
+            for (size_t b = 0; b < subs.size(); ++b)
+                if (a != b) pr.emplace_back(subs[a], subs[b]);
+    }
+    Csr conf = pairs_to_csr(na, pr);
+    std::vector<int32_t> color(na, -1);
+    std::vector<int32_t> seen;
+    int32_t nc = 0;
+    for (int32_t i = 0; i < na; ++i) {
+        seen.clear();
+        for (int64_t q = conf.ptr[i]; q < conf.ptr[i + 1]; ++q)
+            if (color[conf.idx[q]] >= 0) seen.push_back(color[conf.idx[q]]);
+        std::sort(seen.begin(), seen.end());
+        int32_t col = 0;
+        for (int32_t s : seen) {
+            if (s == col) ++col;
+            else if (s > col) break;
+        }
+        color[i] = col;
+        nc = std::max(nc, col + 1);
+    }
+    *n_colors = nc;
+    return color;
+}
+
+Csr assembled_pattern(int64_t n, const ElemList& el) {
+    Csr d2e = transpose(n, el.ptr, el.dofs);
+    Csr p;
+    p.ptr.assign(n + 1, 0);
+    std::vector<int64_t> mark(n, -1);
+    for (int64_t d = 0; d < n; ++d) {
+        size_t start = p.idx.size();
+        for (int64_t q = d2e.ptr[d]; q < d2e.ptr[d + 1]; ++q) {
+            int32_t e = d2e.idx[q];
+            for (int64_t r = el.ptr[e]; r < el.ptr[e + 1]; ++r) {
+                int32_t t = el.dofs[r];
+                if (mark[t] != d) {
+                    mark[t] = d;
+                    p.idx.push_back(t);
+                }
+            }
+        }
+        std::sort(p.idx.begin() + start, p.idx.end());
+        p.ptr[d + 1] = (int64_t)p.idx.size();
+    }
+    return p;
+}
+
+CoarseGroups group_coarse(const ElemList& el, const std::vector<int32_t>& agg_of_dof,
+                          const std::vector<int32_t>& k, const std::vector<int64_t>& coarse_off) {
+    CoarseGroups cg;
+    const int32_t na = (int32_t)k.size();
+    std::vector<int32_t> compact(na, -1);
+    int32_t ns = 0;
+    for (int32_t i = 0; i < na; ++i)
+        if (k[i] > 0) compact[i] = ns++;
+    cg.n_super = ns;
+    cg.node_of_cdof.resize(coarse_off[na]);
+    for (int32_t i = 0; i < na; ++i)
+        for (int64_t d = coarse_off[i]; d < coarse_off[i + 1]; ++d) cg.node_of_cdof[d] = compact[i];
+    std::map<std::vector<int32_t>, int32_t> key2g;
+    std::vector<std::vector<int32_t>> members;
+    std::vector<int32_t> t;
+    cg.coarse.ptr.assign(1, 0);
+    for (int64_t e = 0; e < el.count(); ++e) {
+        t.clear();
+        for (int64_t q = el.ptr[e]; q < el.ptr[e + 1]; ++q) {
+            int32_t a = agg_of_dof[el.dofs[q]];
+            if (k[a] > 0) t.push_back(a);
+        }
+        std::sort(t.begin(), t.end());
+        t.erase(std::unique(t.begin(), t.end()), t.end());
+        if (t.empty()) continue;
+        auto it = key2g.find(t);
+        int32_t g;
+        if (it == key2g.end()) {
+            g = (int32_t)members.size();
+            key2g.emplace(t, g);
+            members.emplace_back();
+            for (int32_t a : t)
+                for (int64_t d = coarse_off[a]; d < coarse_off[a + 1]; ++d) cg.coarse.dofs.push_back((int32_t)d);
+            cg.coarse.ptr.push_back((int64_t)cg.coarse.dofs.size());
+        } else {
+            g = it->second;
+        }
+        members[g].push_back((int32_t)e);
+    }
+    cg.mem_ptr.assign(members.size() + 1, 0);
+    for (size_t g = 0; g < members.size(); ++g) {
+        cg.mem_elems.insert(cg.mem_elems.end(), members[g].begin(), members[g].end());
+        cg.mem_ptr[g + 1] = (int64_t)cg.mem_elems.size();
+    }
+    return cg;
+}
+
+}  // namespace lsdd

@@ -1,0 +1,774 @@
+// HIP kernels of the LS-AMG-DD hot path for CDNA4 (gfx950).
+//
+// Setup: batched element eigendecompositions (element Gram factors, Sec. 5.2),
+// assembly, batched local problems per aggregate (exact SPSD splitting,
+// Schur complement, reduced generalized eigenproblem, mode selection,
+// subdomain inverses; Sec. 2), Galerkin products G_T P_T (Sec. 2).
+// Solve: CSR residuals, colour-parallel multiplicative Schwarz with
+// explicit subdomain inverses, block-diagonal transfer, dense coarsest solve,
+// PCG vector kernels.
+#include <hip/hip_runtime.h>
+
+#include <cfloat>
+#include <cmath>
+
+#include "dense.hpp"
+#include "kernels.hpp"
+
+namespace lsdd {
+
+namespace {
+
+constexpr int WG = LSDD_WG;
+constexpr int NE_LDS = 48;          // element blocks up to this size stay in LDS
+
+inline unsigned grid_for(int64_t n, int per_block = WG) {
+    int64_t g = (n + per_block - 1) / per_block;
+    if (g < 1) g = 1;
+    if (g > 65535LL * 64) g = 65535LL * 64;
+    return (unsigned)g;
+}
+
+__device__ inline int64_t find_slot(const int32_t* col, int64_t lo, int64_t hi, int32_t q) {
+    // binary search for column q in col[lo, hi)
+    while (lo < hi) {
+        int64_t mid = (lo + hi) >> 1;
+        int32_t c = col[mid];
+        if (c < q) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+
+// position of DOF q inside Omega = [omega ascending | Gamma ascending], or -1
+__device__ inline int local_index(const int32_t* dofs, int nw, int m, int32_t q) {
+    int lo = 0, hi = nw;
+    while (lo < hi) {
+        int mid = (lo + hi) >> 1;
+        if (dofs[mid] < q) lo = mid + 1;
+        else hi = mid;
+    }
+    if (lo < nw && dofs[lo] == q) return lo;
+    lo = nw;
+    hi = m;
+    while (lo < hi) {
+        int mid = (lo + hi) >> 1;
+        if (dofs[mid] < q) lo = mid + 1;
+        else hi = mid;
+    }
+    if (lo < m && dofs[lo] == q) return lo;
+    return -1;
+}
+
+// ====================================================================== K1: element Gram factors
+
+// One workgroup per element: eigendecomposition of the symmetric block A_T by
+// parallel Jacobi, SPSD check, rank, and G_T = Lambda_+^{1/2} Q_+^T stored
+// row-major as an n_T x n_T array whose first r_T rows are valid.
+__global__ void __launch_bounds__(WG) k_elem_eig(const int64_t* elem_ptr, const int64_t* blk_off,
+                                                 const double* blocks, double* G, int32_t* ranks,
+                                                 int32_t* status, double* scratch, int64_t scratch_stride,
+                                                 double rank_rtol, double spsd_tol) {
+    __shared__ double s_a[NE_LDS * NE_LDS];
+    __shared__ double s_v[NE_LDS * NE_LDS];
+    __shared__ double s_w[128];
+    __shared__ int s_rank[128];
+    __shared__ int s_pairs[128];
+    __shared__ double s_cs[128];
+    __shared__ int s_flag;
+    __shared__ double s_red[WG / 64];
+    const int64_t e = blockIdx.x;
+    const int n = (int)(elem_ptr[e + 1] - elem_ptr[e]);
+    const double* B = blocks + blk_off[e];
+    double* a;
+    double* v;
+    double* vs;
+    if (n <= NE_LDS) {
+        a = s_a;
+        v = s_v;
+        vs = scratch + e * scratch_stride;   // sorted vectors (global, n^2)
+    } else {
+        a = scratch + e * scratch_stride;
+        v = a + (int64_t)n * n;
+        vs = v + (int64_t)n * n;
+    }
+    if (n <= NE_LDS) vs = scratch + e * scratch_stride;
+    // load (column-major == row-major for symmetric), asymmetry and scale
+    double asym = 0.0, amax = 0.0;
+    for (int idx = tid(); idx < n * n; idx += WG) {
+        int i = idx % n, j = idx / n;
+        double x = B[(int64_t)i * n + j], y = B[(int64_t)j * n + i];
+        a[i + j * n] = 0.5 * (x + y);
+        asym = fmax(asym, fabs(x - y));
+        amax = fmax(amax, fabs(x));
+    }
+    __syncthreads();
+    asym = wg_max(asym, s_red);
+    amax = wg_max(amax, s_red);
+    if (!(asym <= 1e-12 * amax) || !(amax == amax) || amax > DBL_MAX) {
+        if (tid() == 0) status[e] = 1;   // asymmetric or non-finite
+        return;
+    }
+    wg_identity(v, n, n);
+    wg_jacobi(a, n, n, v, n, 60, 1e-15, 1e-18 * amax, s_pairs, s_cs, &s_flag);
+    wg_sort_eig(a, n, v, n, n, s_w, vs, n, s_rank);
+    const double lmax = fmax(s_w[n - 1], 0.0);
+    if (s_w[0] < -spsd_tol * lmax) {
+        if (tid() == 0) status[e] = 2;
+        return;
+    }
+    const double tol = (rank_rtol > 0.0 ? rank_rtol : n * DBL_EPSILON) * lmax;
+    int first = 0;
+    while (first < n && !(s_w[first] > tol)) ++first;   // eigenvalues ascending
+    const int r = n - first;
+    double* g = G + blk_off[e];
+    for (int idx = tid(); idx < n * n; idx += WG) {
+        int row = idx / n, c = idx % n;
+        double val = 0.0;
+        if (row < r) {
+            int t = first + row;
+            val = sqrt(s_w[t]) * vs[c + (int64_t)t * n];
+        }
+        g[idx] = val;
+    }
+    if (tid() == 0) {
+        ranks[e] = r;
+        status[e] = 0;
+    }
+}
+
+// ====================================================================== assembly into CSR
+
+// One workgroup per element / coarse group: add its block into the CSR values
+// (the CSR pattern contains every (p, q) of every support).
+__global__ void __launch_bounds__(WG) k_assemble_csr(const int64_t* elem_ptr, const int32_t* elem_dofs,
+                                                     const int64_t* blk_off, const double* blocks,
+                                                     const int64_t* rowptr, const int32_t* col, double* val) {
+    const int64_t e = blockIdx.x;
+    const int64_t base = elem_ptr[e];
+    const int n = (int)(elem_ptr[e + 1] - base);
+    const double* B = blocks + blk_off[e];
+    for (int64_t idx = tid(); idx < (int64_t)n * n; idx += WG) {
+        int a = (int)(idx / n), b = (int)(idx % n);
+        int32_t p = elem_dofs[base + a], q = elem_dofs[base + b];
+        int64_t slot = find_slot(col, rowptr[p], rowptr[p + 1], q);
+        atomicAdd(&val[slot], B[idx]);
+    }
+}
+
+// ====================================================================== local problems
+
+// Per aggregate: A~_Omega = sum_{T in cl(omega)} mult(T)^{-1} E_T^T A_T E_T
+// (eq. SPSD_splitting under structural support) and A_Omega = A[Omega, Omega].
+__global__ void __launch_bounds__(WG) k_local_assemble(LocalArgs A) {
+    const int b = blockIdx.x;
+    const int ag = A.first + b;
+    const int64_t s0 = A.sub_ptr[ag];
+    const int m = (int)(A.sub_ptr[ag + 1] - s0);
+    const int nw = (int)(A.agg_ptr[ag + 1] - A.agg_ptr[ag]);
+    const int32_t* dofs = A.sub_dofs + s0;
+    double* W1 = A.w1 + A.ws_off[b];
+    double* W2 = A.w2 + A.ws_off[b];
+    wg_zero(W1, (int64_t)m * m);
+    for (int64_t c = A.cl_ptr[ag]; c < A.cl_ptr[ag + 1]; ++c) {
+        const int32_t e = A.cl_elems[c];
+        const int ne = (int)(A.elem_ptr[e + 1] - A.elem_ptr[e]);
+        const int32_t* pos = A.clpos + A.clpos_off[c];
+        const double* Be = A.blocks + A.blk_off[e];
+        const double w = 1.0 / (double)A.mult[e];
+        for (int idx = tid(); idx < ne * ne; idx += WG) {
+            int i = idx / ne, j = idx % ne;
+            W1[pos[i] + (int64_t)pos[j] * m] += w * Be[idx];
+        }
+        __syncthreads();
+    }
+    wg_zero(W2, (int64_t)m * m);
+    for (int a = tid(); a < m; a += WG) {
+        const int32_t p = dofs[a];
+        for (int64_t q = A.rowptr[p]; q < A.rowptr[p + 1]; ++q) {
+            int li = local_index(dofs, nw, m, A.col[q]);
+            if (li >= 0) W2[a + (int64_t)li * m] = A.val[q];
+        }
+    }
+    __syncthreads();
+}
+
+// Per aggregate: Schur complement S~ (eq. gep_reduced), Cholesky of A_Omega
+// (its leading block is chol(A_ww)), C = L^{-1} S~ L^{-T}, Jacobi eigenpairs,
+// retained modes (eq. tau-cut, cluster completion), Z = L^{-T} V_k, and the
+// subdomain inverse A_Omega^{-1} for the Schwarz smoother.
+__global__ void __launch_bounds__(WG) k_local_solve(LocalArgs A) {
+    __shared__ double s_red[WG / 64];
+    __shared__ double s_sh[2];
+    __shared__ int s_flag;
+    __shared__ int s_k;
+    extern __shared__ char s_dyn[];   // pairs (int[2*np]), cs (double[2*np]), rank (int[nw])
+    const int b = blockIdx.x;
+    const int ag = A.first + b;
+    const int m = (int)(A.sub_ptr[ag + 1] - A.sub_ptr[ag]);
+    const int nw = (int)(A.agg_ptr[ag + 1] - A.agg_ptr[ag]);
+    const int ng = m - nw;
+    double* W1 = A.w1 + A.ws_off[b];
+    double* W2 = A.w2 + A.ws_off[b];
+    double* S = A.s_buf + A.sq_off[b];
+    double* V = A.v_buf + A.sq_off[b];
+    const int npair = (nw + 1) / 2;
+    int* pairs = (int*)s_dyn;
+    double* cs = (double*)(s_dyn + ((2 * npair * sizeof(int) + 15) / 16) * 16);
+    int* rank = (int*)((char*)cs + 2 * npair * sizeof(double));
+
+    // ---- Schur complement onto omega
+    if (ng == 0) {
+        for (int idx = tid(); idx < nw * nw; idx += WG) {
+            int i = idx % nw, j = idx / nw;
+            S[i + (int64_t)j * nw] = W1[i + (int64_t)j * m];
+        }
+        __syncthreads();
+    } else if (A.schur_mode == 0) {
+        double* G = W1 + nw + (int64_t)nw * m;      // A~_GG
+        double dmax = 0.0;
+        for (int i = tid(); i < ng; i += WG) dmax = fmax(dmax, G[i + (int64_t)i * m]);
+        dmax = wg_max(dmax, s_red);
+        double dmin = wg_potrf(G, m, ng, s_sh);
+        if (!(dmin > ng * DBL_EPSILON * dmax)) {
+            if (tid() == 0) A.status[ag] = 1;
+            return;
+        }
+        double* Wg = W1 + nw;                        // A~_Gw (ng x nw), ld m
+        wg_trsm_lower(G, m, ng, Wg, m, nw);          // W = L_G^{-1} A~_Gw
+        for (int idx = tid(); idx < nw * nw; idx += WG) {
+            int i = idx % nw, j = idx / nw;
+            if (i > j) continue;
+            const double* ci = Wg + (int64_t)i * m;
+            const double* cj = Wg + (int64_t)j * m;
+            double s = 0.0;
+            for (int t = 0; t < ng; ++t) s += ci[t] * cj[t];
+            double val = 0.5 * (W1[i + (int64_t)j * m] + W1[j + (int64_t)i * m]) - s;
+            S[i + (int64_t)j * nw] = val;
+            S[j + (int64_t)i * nw] = val;
+        }
+        __syncthreads();
+    } else {
+        // pseudo-inverse route: A~_GG = U diag(d) U^T, keep d > ng eps d_max
+        double* G = W1 + nw + (int64_t)nw * m;
+        double* U = A.w3 + A.w3_off[b];
+        double* Y = U + (int64_t)ng * ng;           // ng x nw: d^{-1/2} U^T A~_Gw
+        int* pr = (int*)s_dyn;                      // scratch sized for max(nw, ng) pairs by host
+        double* c2 = (double*)(s_dyn + ((2 * ((ng + 1) / 2) * sizeof(int) + 15) / 16) * 16);
+        double scale = 0.0;
+        for (int i = tid(); i < ng; i += WG) scale = fmax(scale, fabs(G[i + (int64_t)i * m]));
+        scale = wg_max(scale, s_red);
+        wg_identity(U, ng, ng);
+        wg_jacobi(G, m, ng, U, ng, 60, 1e-15, 1e-18 * scale, pr, c2, &s_flag);
+        double dmax = 0.0;
+        for (int i = tid(); i < ng; i += WG) dmax = fmax(dmax, G[i + (int64_t)i * m]);
+        dmax = wg_max(dmax, s_red);
+        const double tol = ng * DBL_EPSILON * dmax;
+        const double* AGw = W1 + nw;
+        for (int idx = tid(); idx < ng * nw; idx += WG) {
+            int t = idx % ng, j = idx / ng;
+            double d = G[t + (int64_t)t * m];
+            double s = 0.0;
+            if (d > tol && dmax > 0.0) {
+                for (int g = 0; g < ng; ++g) s += U[g + (int64_t)t * ng] * AGw[g + (int64_t)j * m];
+                s /= sqrt(d);
+            }
+            Y[t + (int64_t)j * ng] = s;
+        }
+        __syncthreads();
+        for (int idx = tid(); idx < nw * nw; idx += WG) {
+            int i = idx % nw, j = idx / nw;
+            if (i > j) continue;
+            double s = 0.0;
+            for (int t = 0; t < ng; ++t) s += Y[t + (int64_t)i * ng] * Y[t + (int64_t)j * ng];
+            double val = 0.5 * (W1[i + (int64_t)j * m] + W1[j + (int64_t)i * m]) - s;
+            S[i + (int64_t)j * nw] = val;
+            S[j + (int64_t)i * nw] = val;
+        }
+        __syncthreads();
+    }
+
+    // ---- Cholesky of A_Omega (leading nw block = chol(A_ww))
+    double dmin = wg_potrf(W2, m, m, s_sh);
+    if (!(dmin > 0.0)) {
+        if (tid() == 0) A.status[ag] = 2;
+        return;
+    }
+    // ---- C = L^{-1} S~ L^{-T}
+    wg_trsm_lower(W2, m, nw, S, nw, nw);
+    wg_transpose(S, nw, nw);
+    wg_trsm_lower(W2, m, nw, S, nw, nw);
+    wg_symmetrize(S, nw, nw);
+    // ---- eigenpairs of C (mu ascending)
+    double scale = 0.0;
+    for (int i = tid(); i < nw; i += WG) scale = fmax(scale, fabs(S[i + (int64_t)i * nw]));
+    scale = wg_max(scale, s_red);
+    wg_identity(V, nw, nw);
+    wg_jacobi(S, nw, nw, V, nw, 60, 1e-15, 1e-18 * fmax(scale, 1e-300), pairs, cs, &s_flag);
+    double* mu = A.mu + A.mu_off[ag];
+    double* VS = W1;                                 // sorted eigenvectors, nw x nw, ld nw
+    wg_sort_eig(S, nw, V, nw, nw, mu, VS, nw, rank);
+    for (int i = tid(); i < nw; i += WG) mu[i] = fmax(mu[i], 0.0);
+    __syncthreads();
+    // ---- retained modes
+    if (tid() == 0) {
+        int k;
+        if (A.modes_fixed > 0) {
+            k = A.modes_fixed < nw ? A.modes_fixed : nw;
+        } else {
+            k = 0;
+            while (k < nw && mu[k] < A.thr + A.band_tol) ++k;
+        }
+        while (k > 0 && k < nw && mu[k] - mu[k - 1] <= A.cluster_tol) ++k;
+        s_k = k;
+        A.k_out[ag] = k;
+    }
+    __syncthreads();
+    const int k = s_k;
+    // ---- Z = L_ww^{-T} V_k (A_ww-orthonormal), staged row-major nw x k
+    if (k > 0) {
+        wg_trsm_lower_t(W2, m, nw, VS, nw, k);
+        double* zs = A.zst + A.zst_off[ag];
+        for (int idx = tid(); idx < nw * k; idx += WG) {
+            int i = idx / k, s = idx % k;
+            zs[idx] = VS[i + (int64_t)s * nw];
+        }
+        __syncthreads();
+    }
+    // ---- subdomain inverse A_Omega^{-1} = L^{-T} L^{-1}
+    double* X = A.inv + A.inv_off[ag];
+    wg_identity(X, m, m);
+    wg_trsm_lower(W2, m, m, X, m, m);
+    wg_trsm_lower_t(W2, m, m, X, m, m);
+    wg_symmetrize(X, m, m);
+    if (tid() == 0) A.status[ag] = 0;
+}
+
+__global__ void k_z_compact(const int64_t* agg_ptr, const int32_t* k, const int64_t* zst_off, const double* zst,
+                            const int64_t* zoff, double* Z, float* Z32) {
+    const int ag = blockIdx.x;
+    const int nw = (int)(agg_ptr[ag + 1] - agg_ptr[ag]);
+    const int64_t cnt = (int64_t)nw * k[ag];
+    const double* src = zst + zst_off[ag];
+    for (int64_t i = tid(); i < cnt; i += WG) {
+        double v = src[i];
+        Z[zoff[ag] + i] = v;
+        if (Z32) Z32[zoff[ag] + i] = (float)v;
+    }
+}
+
+// ====================================================================== Galerkin products
+
+// One workgroup per coarse group g: for each member element e build
+// P_e = P[S_e, S_g] (block-structured by aggregate), then accumulate
+// (G_e P_e)^T (G_e P_e) (level 0, Gram factors) or P_e^T A_e P_e.
+__global__ void __launch_bounds__(WG) k_galerkin(GalerkinArgs g) {
+    const int gi = blockIdx.x;
+    const int c = (int)(g.cptr[gi + 1] - g.cptr[gi]);
+    double* out = g.cblocks + g.cblk_off[gi];
+    double* Pe = g.ws + g.ws_off[gi];
+    wg_zero(out, (int64_t)c * c);
+    for (int64_t mi = g.mem_ptr[gi]; mi < g.mem_ptr[gi + 1]; ++mi) {
+        const int32_t e = g.mem_elems[mi];
+        const int ne = (int)(g.felem_ptr[e + 1] - g.felem_ptr[e]);
+        double* X = Pe + (int64_t)ne * c;
+        const int64_t pm = g.pm_off[mi];
+        // P_e row-major ne x c
+        for (int idx = tid(); idx < ne * c; idx += WG) {
+            int a = idx / c, col = idx % c;
+            double v = 0.0;
+            int64_t zr = g.pm_zrow[pm + a];
+            if (zr >= 0) {
+                int s = col - g.pm_col[pm + a];
+                if (s >= 0 && s < g.pm_k[pm + a]) v = g.Z[zr + s];
+            }
+            Pe[idx] = v;
+        }
+        __syncthreads();
+        const double* F = g.fblocks + g.fblk_off[e];   // ne x ne row-major
+        // X = F P_e (ne x c)
+        for (int idx = tid(); idx < ne * c; idx += WG) {
+            int r = idx / c, col = idx % c;
+            double s = 0.0;
+            for (int a = 0; a < ne; ++a) s += F[r * ne + a] * Pe[a * c + col];
+            X[idx] = s;
+        }
+        __syncthreads();
+        if (g.use_gram) {
+            // out += X^T X  (rows of G beyond the rank are zero)
+            for (int idx = tid(); idx < c * c; idx += WG) {
+                int i = idx / c, j = idx % c;
+                double s = 0.0;
+                for (int r = 0; r < ne; ++r) s += X[r * c + i] * X[r * c + j];
+                out[idx] += s;
+            }
+        } else {
+            // out += P_e^T X
+            for (int idx = tid(); idx < c * c; idx += WG) {
+                int i = idx / c, j = idx % c;
+                double s = 0.0;
+                for (int a = 0; a < ne; ++a) s += Pe[a * c + i] * X[a * c + j];
+                out[idx] += s;
+            }
+        }
+        __syncthreads();
+    }
+    // exact symmetry
+    for (int idx = tid(); idx < c * c; idx += WG) {
+        int i = idx / c, j = idx % c;
+        if (i < j) {
+            double s = 0.5 * (out[i * c + j] + out[j * c + i]);
+            out[i * c + j] = s;
+            out[j * c + i] = s;
+        }
+    }
+}
+
+// ====================================================================== coarsest level
+
+__global__ void k_dense_from_csr(int64_t n, const int64_t* rowptr, const int32_t* col, const double* val,
+                                 double* D) {
+    int64_t p = blockIdx.x;
+    for (int64_t q = rowptr[p] + tid(); q < rowptr[p + 1]; q += WG) D[p + (int64_t)col[q] * n] = val[q];
+}
+
+// Single-workgroup Cholesky and explicit inverse of a dense SPD matrix.
+__global__ void __launch_bounds__(WG) k_dense_chol_inv(int n, double* W, double* inv, int32_t* status) {
+    __shared__ double s_sh[2];
+    double dmin = wg_potrf(W, n, n, s_sh);
+    if (!(dmin > 0.0)) {
+        if (tid() == 0) *status = 2;
+        return;
+    }
+    wg_identity(inv, n, n);
+    wg_trsm_lower(W, n, n, inv, n, n);
+    wg_trsm_lower_t(W, n, n, inv, n, n);
+    wg_symmetrize(inv, n, n);
+    if (tid() == 0) *status = 0;
+}
+
+// ====================================================================== conversions
+
+__global__ void k_to_f32(int64_t n, const double* a, float* b) {
+    for (int64_t i = blockIdx.x * (int64_t)WG + tid(); i < n; i += (int64_t)gridDim.x * WG) b[i] = (float)a[i];
+}
+__global__ void k_to_f64(int64_t n, const float* a, double* b) {
+    for (int64_t i = blockIdx.x * (int64_t)WG + tid(); i < n; i += (int64_t)gridDim.x * WG) b[i] = (double)a[i];
+}
+
+// ====================================================================== solve kernels
+
+// out[t] = r[rows[t]] - sum_q A[rows[t], q] x[q]  (16 lanes per row)
+template <typename T>
+__global__ void __launch_bounds__(WG) k_csr_resid_rows(int64_t nrows, const int32_t* rows, const int64_t* rowptr,
+                                                       const int32_t* col, const T* val, const T* x, const T* r,
+                                                       T* out, int x_zero) {
+    const int lane = tid() & 15;
+    const int64_t t = ((int64_t)blockIdx.x * WG + tid()) >> 4;
+    if (t >= nrows) return;
+    const int32_t p = rows[t];
+    T s = 0;
+    if (!x_zero) {
+        for (int64_t q = rowptr[p] + lane; q < rowptr[p + 1]; q += 16) s += val[q] * x[col[q]];
+    }
+    for (int off = 8; off > 0; off >>= 1) s += __shfl_xor(s, off, 16);
+    if (lane == 0) out[t] = r[p] - s;
+}
+
+// y = A x, or y = r_minus - A x when r_minus != nullptr
+template <typename T>
+__global__ void __launch_bounds__(WG) k_csr_spmv(int64_t n, const int64_t* rowptr, const int32_t* col, const T* val,
+                                                 const T* x, T* y, const T* r_minus) {
+    const int lane = tid() & 15;
+    const int64_t p = ((int64_t)blockIdx.x * WG + tid()) >> 4;
+    if (p >= n) return;
+    T s = 0;
+    for (int64_t q = rowptr[p] + lane; q < rowptr[p + 1]; q += 16) s += val[q] * x[col[q]];
+    for (int off = 8; off > 0; off >>= 1) s += __shfl_xor(s, off, 16);
+    if (lane == 0) y[p] = r_minus ? r_minus[p] - s : s;
+}
+
+// Subdomain correction x[Omega_s] += A_Omega_s^{-1} rloc_s for one 64-column
+// panel of one subdomain per workgroup: lane = column, waves split the rows.
+template <typename T>
+__global__ void __launch_bounds__(WG) k_sub_gemv(const int32_t* items, const int64_t* sub_off, const int64_t* inv_off,
+                                                 const T* inv, const T* rloc, const int32_t* sub_dofs, T* x) {
+    __shared__ T s_r[4096];
+    __shared__ T s_acc[WG];
+    const int s = items[2 * blockIdx.x];
+    const int col0 = items[2 * blockIdx.x + 1];
+    const int64_t o = sub_off[s];
+    const int m = (int)(sub_off[s + 1] - o);
+    const T* R = rloc + o;
+    for (int a = tid(); a < m; a += WG) s_r[a] = R[a];
+    __syncthreads();
+    const int lane = tid() & 63, w = tid() >> 6;
+    const int j = col0 + lane;
+    const T* M = inv + inv_off[s];
+    T acc = 0;
+    if (j < m) {
+        int a = w;
+        for (; a + 12 < m; a += 16) {
+            T v0 = M[(int64_t)a * m + j];
+            T v1 = M[(int64_t)(a + 4) * m + j];
+            T v2 = M[(int64_t)(a + 8) * m + j];
+            T v3 = M[(int64_t)(a + 12) * m + j];
+            acc += v0 * s_r[a] + v1 * s_r[a + 4] + v2 * s_r[a + 8] + v3 * s_r[a + 12];
+        }
+        for (; a < m; a += 4) acc += M[(int64_t)a * m + j] * s_r[a];
+    }
+    s_acc[tid()] = acc;
+    __syncthreads();
+    if (w == 0 && j < m) {
+        T y = s_acc[lane] + s_acc[64 + lane] + s_acc[128 + lane] + s_acc[192 + lane];
+        x[sub_dofs[o + j]] += y;
+    }
+}
+
+// rc[coff_i + s] = sum_a Z_i[a, s] t[omega_i[a]]   (Z_i row-major |omega_i| x k_i)
+template <typename T>
+__global__ void k_restrict(const int64_t* agg_ptr, const int32_t* agg_dofs, const int64_t* zoff, const int32_t* k,
+                           const int64_t* coff, const T* Z, const T* t, T* rc) {
+    const int ag = blockIdx.x;
+    const int kk = k[ag];
+    const int64_t a0 = agg_ptr[ag];
+    const int nw = (int)(agg_ptr[ag + 1] - a0);
+    const T* z = Z + zoff[ag];
+    for (int s = tid(); s < kk; s += WG) {
+        T acc = 0;
+        for (int a = 0; a < nw; ++a) acc += z[(int64_t)a * kk + s] * t[agg_dofs[a0 + a]];
+        rc[coff[ag] + s] = acc;
+    }
+}
+
+// x[omega_i[a]] += sum_s Z_i[a, s] ec[coff_i + s]
+template <typename T>
+__global__ void k_prolong(const int64_t* agg_ptr, const int32_t* agg_dofs, const int64_t* zoff, const int32_t* k,
+                          const int64_t* coff, const T* Z, const T* ec, T* x) {
+    const int ag = blockIdx.x;
+    const int kk = k[ag];
+    const int64_t a0 = agg_ptr[ag];
+    const int nw = (int)(agg_ptr[ag + 1] - a0);
+    const T* z = Z + zoff[ag];
+    const T* e = ec + coff[ag];
+    for (int a = tid(); a < nw; a += WG) {
+        T acc = 0;
+        for (int s = 0; s < kk; ++s) acc += z[(int64_t)a * kk + s] * e[s];
+        x[agg_dofs[a0 + a]] += acc;
+    }
+}
+
+template <typename T>
+__global__ void k_zero(int64_t n, T* x) {
+    for (int64_t i = blockIdx.x * (int64_t)WG + tid(); i < n; i += (int64_t)gridDim.x * WG) x[i] = 0;
+}
+
+// x = M r for the dense symmetric coarsest inverse, one 64-column panel per workgroup
+__global__ void __launch_bounds__(WG) k_dense_gemv(int64_t n, const double* M, const double* r, double* x) {
+    __shared__ double s_acc[WG];
+    const int lane = tid() & 63, w = tid() >> 6;
+    const int64_t j = (int64_t)blockIdx.x * 64 + lane;
+    double acc = 0.0;
+    if (j < n) {
+        for (int64_t a = w; a < n; a += 4) acc += M[a * n + j] * r[a];
+    }
+    s_acc[tid()] = acc;
+    __syncthreads();
+    if (w == 0 && j < n) x[j] = s_acc[lane] + s_acc[64 + lane] + s_acc[128 + lane] + s_acc[192 + lane];
+}
+
+// ---------------------------------------------------------------- PCG helpers
+
+__global__ void __launch_bounds__(WG) k_dot_partial(int64_t n, const double* a, const double* b, double* partials) {
+    __shared__ double red[WG / 64];
+    double s = 0.0;
+    for (int64_t i = blockIdx.x * (int64_t)WG + tid(); i < n; i += (int64_t)gridDim.x * WG) s += a[i] * b[i];
+    s = wg_sum(s, red);
+    if (tid() == 0) partials[blockIdx.x] = s;
+}
+
+__global__ void __launch_bounds__(WG) k_sum_partials(int np, const double* partials, double* out) {
+    __shared__ double red[WG / 64];
+    double s = 0.0;
+    for (int i = tid(); i < np; i += WG) s += partials[i];
+    s = wg_sum(s, red);
+    if (tid() == 0) *out = s;
+}
+
+__global__ void __launch_bounds__(WG) k_update_xr(int64_t n, const double* s_num, const double* s_den, const double* p,
+                                                  const double* q, double* x, double* r, double* partials) {
+    __shared__ double red[WG / 64];
+    const double alpha = *s_num / *s_den;
+    double s = 0.0;
+    for (int64_t i = blockIdx.x * (int64_t)WG + tid(); i < n; i += (int64_t)gridDim.x * WG) {
+        x[i] += alpha * p[i];
+        double ri = r[i] - alpha * q[i];
+        r[i] = ri;
+        s += ri * ri;
+    }
+    s = wg_sum(s, red);
+    if (tid() == 0) partials[blockIdx.x] = s;
+}
+
+__global__ void k_update_p(int64_t n, const double* s_num, const double* s_den, const double* z, double* p) {
+    const double beta = *s_num / *s_den;
+    for (int64_t i = blockIdx.x * (int64_t)WG + tid(); i < n; i += (int64_t)gridDim.x * WG) p[i] = z[i] + beta * p[i];
+}
+
+__global__ void k_copy(int64_t n, const double* a, double* b) {
+    for (int64_t i = blockIdx.x * (int64_t)WG + tid(); i < n; i += (int64_t)gridDim.x * WG) b[i] = a[i];
+}
+
+__global__ void k_check_finite(int64_t n, const double* a, int32_t* flag) {
+    for (int64_t i = blockIdx.x * (int64_t)WG + tid(); i < n; i += (int64_t)gridDim.x * WG)
+        if (!isfinite(a[i])) *flag = 1;
+}
+
+constexpr int NPART = 1024;
+
+}  // namespace
+
+// ====================================================================== launchers
+
+void launch_elem_eig(int64_t n_elem, const int64_t* elem_ptr, const int64_t* blk_off, const double* blocks, double* G,
+                     int32_t* ranks, int32_t* status, double* scratch, int64_t scratch_stride, double rank_rtol,
+                     double spsd_tol, hipStream_t st) {
+    if (n_elem <= 0) return;
+    hipLaunchKernelGGL(k_elem_eig, dim3((unsigned)n_elem), dim3(WG), 0, st, elem_ptr, blk_off, blocks, G, ranks, status,
+                       scratch, scratch_stride, rank_rtol, spsd_tol);
+}
+
+void launch_assemble_csr(int64_t n_blk, const int64_t* elem_ptr, const int32_t* elem_dofs, const int64_t* blk_off,
+                         const double* blocks, const int64_t* rowptr, const int32_t* col, double* val, hipStream_t st) {
+    if (n_blk <= 0) return;
+    hipLaunchKernelGGL(k_assemble_csr, dim3((unsigned)n_blk), dim3(WG), 0, st, elem_ptr, elem_dofs, blk_off, blocks,
+                       rowptr, col, val);
+}
+
+void launch_local_assemble(int32_t nbatch, const LocalArgs& a, hipStream_t st) {
+    if (nbatch <= 0) return;
+    hipLaunchKernelGGL(k_local_assemble, dim3(nbatch), dim3(WG), 0, st, a);
+}
+
+void launch_local_solve(int32_t nbatch, const LocalArgs& a, hipStream_t st) {
+    if (nbatch <= 0) return;
+    // dynamic LDS: Jacobi pairs and rotations for blocks of up to 2048 rows
+    // (aggregates and, in the pseudo-inverse route, interfaces) + the sort ranks
+    size_t lds = 16 + 1024 * 2 * sizeof(int) + 1024 * 2 * sizeof(double) + 2048 * sizeof(int);
+    hipLaunchKernelGGL(k_local_solve, dim3(nbatch), dim3(WG), lds, st, a);
+}
+
+void launch_z_compact(int32_t n_agg, const int64_t* agg_ptr, const int32_t* k, const int64_t* zst_off, const double* zst,
+                      const int64_t* zoff, double* Z, float* Z32, hipStream_t st) {
+    if (n_agg <= 0) return;
+    hipLaunchKernelGGL(k_z_compact, dim3(n_agg), dim3(WG), 0, st, agg_ptr, k, zst_off, zst, zoff, Z, Z32);
+}
+
+void launch_galerkin(const GalerkinArgs& g, hipStream_t st) {
+    if (g.n_groups <= 0) return;
+    hipLaunchKernelGGL(k_galerkin, dim3(g.n_groups), dim3(WG), 0, st, g);
+}
+
+void launch_dense_from_csr(int64_t n, const int64_t* rowptr, const int32_t* col, const double* val, double* D,
+                           hipStream_t st) {
+    hipLaunchKernelGGL(k_dense_from_csr, dim3((unsigned)n), dim3(WG), 0, st, n, rowptr, col, val, D);
+}
+
+void launch_dense_chol_inv(int64_t n, double* W, double* inv, int32_t* status, hipStream_t st) {
+    hipLaunchKernelGGL(k_dense_chol_inv, dim3(1), dim3(WG), 0, st, (int)n, W, inv, status);
+}
+
+void launch_to_f32(int64_t n, const double* a, float* b, hipStream_t st) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_to_f32, dim3(grid_for(n)), dim3(WG), 0, st, n, a, b);
+}
+void launch_to_f64(int64_t n, const float* a, double* b, hipStream_t st) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_to_f64, dim3(grid_for(n)), dim3(WG), 0, st, n, a, b);
+}
+
+template <typename T>
+void launch_csr_resid_rows(int64_t nrows, const int32_t* rows, const int64_t* rowptr, const int32_t* col, const T* val,
+                           const T* x, const T* r, T* out, bool x_zero, hipStream_t st) {
+    if (nrows <= 0) return;
+    hipLaunchKernelGGL(k_csr_resid_rows<T>, dim3(grid_for(nrows * 16)), dim3(WG), 0, st, nrows, rows, rowptr, col, val,
+                       x, r, out, x_zero ? 1 : 0);
+}
+template <typename T>
+void launch_csr_spmv(int64_t n, const int64_t* rowptr, const int32_t* col, const T* val, const T* x, T* y,
+                     const T* r_minus, hipStream_t st) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_csr_spmv<T>, dim3(grid_for(n * 16)), dim3(WG), 0, st, n, rowptr, col, val, x, y, r_minus);
+}
+template <typename T>
+void launch_sub_gemv(int64_t n_items, const int32_t* items, const int64_t* sub_off, const int64_t* inv_off,
+                     const T* inv, const T* rloc, const int32_t* sub_dofs, T* x, hipStream_t st) {
+    if (n_items <= 0) return;
+    hipLaunchKernelGGL(k_sub_gemv<T>, dim3((unsigned)n_items), dim3(WG), 0, st, items, sub_off, inv_off, inv, rloc,
+                       sub_dofs, x);
+}
+template <typename T>
+void launch_restrict(int32_t n_agg, const int64_t* agg_ptr, const int32_t* agg_dofs, const int64_t* zoff,
+                     const int32_t* k, const int64_t* coff, const T* Z, const T* t, T* rc, hipStream_t st) {
+    if (n_agg <= 0) return;
+    hipLaunchKernelGGL(k_restrict<T>, dim3(n_agg), dim3(WG), 0, st, agg_ptr, agg_dofs, zoff, k, coff, Z, t, rc);
+}
+template <typename T>
+void launch_prolong(int32_t n_agg, const int64_t* agg_ptr, const int32_t* agg_dofs, const int64_t* zoff,
+                    const int32_t* k, const int64_t* coff, const T* Z, const T* ec, T* x, hipStream_t st) {
+    if (n_agg <= 0) return;
+    hipLaunchKernelGGL(k_prolong<T>, dim3(n_agg), dim3(WG), 0, st, agg_ptr, agg_dofs, zoff, k, coff, Z, ec, x);
+}
+template <typename T>
+void launch_zero(int64_t n, T* x, hipStream_t st) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_zero<T>, dim3(grid_for(n)), dim3(WG), 0, st, n, x);
+}
+
+void launch_dense_gemv(int64_t n, const double* inv, const double* r, double* x, hipStream_t st) {
+    hipLaunchKernelGGL(k_dense_gemv, dim3((unsigned)((n + 63) / 64)), dim3(WG), 0, st, n, inv, r, x);
+}
+
+void launch_dot(int64_t n, const double* a, const double* b, double* partials, double* out, hipStream_t st) {
+    unsigned nb = grid_for(n);
+    if (nb > NPART) nb = NPART;
+    hipLaunchKernelGGL(k_dot_partial, dim3(nb), dim3(WG), 0, st, n, a, b, partials);
+    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(WG), 0, st, (int)nb, partials, out);
+}
+
+void launch_update_xr(int64_t n, const double* s_num, const double* s_den, const double* p, const double* q, double* x,
+                      double* r, double* partials, double* out_rr, hipStream_t st) {
+    unsigned nb = grid_for(n);
+    if (nb > NPART) nb = NPART;
+    hipLaunchKernelGGL(k_update_xr, dim3(nb), dim3(WG), 0, st, n, s_num, s_den, p, q, x, r, partials);
+    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(WG), 0, st, (int)nb, partials, out_rr);
+}
+
+void launch_update_p(int64_t n, const double* s_num, const double* s_den, const double* z, double* p, hipStream_t st) {
+    hipLaunchKernelGGL(k_update_p, dim3(grid_for(n)), dim3(WG), 0, st, n, s_num, s_den, z, p);
+}
+
+void launch_copy(int64_t n, const double* a, double* b, hipStream_t st) {
+    hipLaunchKernelGGL(k_copy, dim3(grid_for(n)), dim3(WG), 0, st, n, a, b);
+}
+
+void launch_check_finite(int64_t n, const double* a, int32_t* flag, hipStream_t st) {
+    hipLaunchKernelGGL(k_check_finite, dim3(grid_for(n)), dim3(WG), 0, st, n, a, flag);
+}
+
+#define LSDD_INST(T)                                                                                                  \
+    template void launch_csr_resid_rows<T>(int64_t, const int32_t*, const int64_t*, const int32_t*, const T*,        \
+                                           const T*, const T*, T*, bool, hipStream_t);                                \
+    template void launch_csr_spmv<T>(int64_t, const int64_t*, const int32_t*, const T*, const T*, T*, const T*,      \
+                                     hipStream_t);                                                                    \
+    template void launch_sub_gemv<T>(int64_t, const int32_t*, const int64_t*, const int64_t*, const T*, const T*,    \
+                                     const int32_t*, T*, hipStream_t);                                                \
+    template void launch_restrict<T>(int32_t, const int64_t*, const int32_t*, const int64_t*, const int32_t*,        \
+                                     const int64_t*, const T*, const T*, T*, hipStream_t);                            \
+    template void launch_prolong<T>(int32_t, const int64_t*, const int32_t*, const int64_t*, const int32_t*,         \
+                                    const int64_t*, const T*, const T*, T*, hipStream_t);                             \
+    template void launch_zero<T>(int64_t, T*, hipStream_t);
+LSDD_INST(double)
+LSDD_INST(float)
+
+}  // namespace lsdd

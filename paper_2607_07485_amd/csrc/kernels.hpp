@@ -1,0 +1,124 @@
+// Launchers of the HIP kernels (implemented in kernels.hip).  All take the
+// stream last and enqueue asynchronously.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace lsdd {
+
+struct LocalArgs {
+    // per aggregate (batch-relative index b, aggregate a = first + b)
+    int32_t first;                 // first aggregate of the batch
+    const int64_t* sub_ptr;        // Omega offsets into sub_dofs (aggregate order)
+    const int32_t* sub_dofs;
+    const int64_t* agg_ptr;        // omega sizes = agg_ptr[a+1]-agg_ptr[a]
+    const int64_t* cl_ptr;         // elements of cl(omega_a)
+    const int32_t* cl_elems;
+    const int64_t* clpos_off;      // per cl entry: offset of its n_e local positions
+    const int32_t* clpos;
+    const int32_t* mult;           // per element
+    const int64_t* elem_ptr;       // element supports (for n_e)
+    const int64_t* blk_off;        // element block offsets (n_e^2 each, row-major)
+    const double* blocks;
+    const int64_t* rowptr;         // CSR of A_l
+    const int32_t* col;
+    const double* val;
+    // workspace (batch-relative offsets)
+    const int64_t* ws_off;         // per batch entry: offset of its m x m slots
+    double* w1;                    // A~_Omega, later sorted eigenvectors / Z
+    double* w2;                    // A_Omega, then its Cholesky factor
+    const int64_t* sq_off;         // per batch entry: offset of its nw x nw slots
+    double* s_buf;                 // S~, then C
+    double* v_buf;                 // Jacobi eigenvectors
+    const int64_t* w3_off;         // eig-based Schur scratch (mode 1 only)
+    double* w3;
+    // outputs
+    const int64_t* inv_off;        // aggregate order: offset of A_Omega^{-1} (m x m)
+    double* inv;
+    const int64_t* zst_off;        // aggregate order: staging Z (nw x k, row-major)
+    double* zst;
+    const int64_t* mu_off;         // = agg_ptr (sorted mu per aggregate)
+    double* mu;
+    int32_t* k_out;
+    int32_t* status;               // 0 ok, 1 singular interface block, 2 A_Omega not SPD, 3 A_ww fail
+    // parameters
+    int32_t modes_fixed;
+    double thr;                    // 1 / tau_cut
+    double band_tol, cluster_tol;
+    int32_t schur_mode;            // 0 Cholesky (flag if singular), 1 eigendecomposition
+};
+
+void launch_elem_eig(int64_t n_elem, const int64_t* elem_ptr, const int64_t* blk_off, const double* blocks,
+                     double* G, int32_t* ranks, int32_t* status, double* scratch, int64_t scratch_stride,
+                     double rank_rtol, double spsd_tol, hipStream_t st);
+
+void launch_assemble_csr(int64_t n_blk, const int64_t* elem_ptr, const int32_t* elem_dofs, const int64_t* blk_off,
+                         const double* blocks, const int64_t* rowptr, const int32_t* col, double* val, hipStream_t st);
+
+void launch_local_assemble(int32_t nbatch, const LocalArgs& a, hipStream_t st);
+void launch_local_solve(int32_t nbatch, const LocalArgs& a, hipStream_t st);
+
+void launch_z_compact(int32_t n_agg, const int64_t* agg_ptr, const int32_t* k, const int64_t* zst_off,
+                      const double* zst, const int64_t* zoff, double* Z, float* Z32, hipStream_t st);
+
+struct GalerkinArgs {
+    int32_t n_groups;
+    const int64_t* cptr;           // coarse group supports (sizes c_g)
+    const int64_t* mem_ptr;        // members of group g
+    const int32_t* mem_elems;
+    const int64_t* felem_ptr;      // fine element supports (n_e)
+    const int64_t* pm_off;         // per member entry: offset of its n_e map entries
+    const int64_t* pm_zrow;        // per (member, local dof): Z row offset (-1: no mode)
+    const int32_t* pm_k;           //   modes of its aggregate
+    const int32_t* pm_col;         //   column offset of its aggregate in the group support
+    const double* Z;
+    int32_t use_gram;              // 1: X = G_e P_e, block += X^T X; 0: block += P_e^T A_e P_e
+    const int64_t* fblk_off;       // fine blocks (G padded n_e x n_e, or A_e), row-major
+    const double* fblocks;
+    const int64_t* ws_off;         // per group scratch offset (2 * n_e_max * c_g)
+    double* ws;
+    const int64_t* cblk_off;       // output coarse blocks c_g x c_g
+    double* cblocks;
+};
+void launch_galerkin(const GalerkinArgs& g, hipStream_t st);
+
+void launch_dense_from_csr(int64_t n, const int64_t* rowptr, const int32_t* col, const double* val, double* D,
+                           hipStream_t st);
+void launch_dense_chol_inv(int64_t n, double* W, double* inv, int32_t* status, hipStream_t st);
+
+void launch_to_f32(int64_t n, const double* a, float* b, hipStream_t st);
+void launch_to_f64(int64_t n, const float* a, double* b, hipStream_t st);
+
+// ---------------------------------------------------------------- solve
+template <typename T>
+void launch_csr_resid_rows(int64_t nrows, const int32_t* rows, const int64_t* rowptr, const int32_t* col,
+                           const T* val, const T* x, const T* r, T* out, bool x_zero, hipStream_t st);
+template <typename T>
+void launch_csr_spmv(int64_t n, const int64_t* rowptr, const int32_t* col, const T* val, const T* x, T* y,
+                     const T* r_minus, hipStream_t st);
+template <typename T>
+void launch_sub_gemv(int64_t n_items, const int32_t* items, const int64_t* sub_off, const int64_t* inv_off,
+                     const T* inv, const T* rloc, const int32_t* sub_dofs, T* x, hipStream_t st);
+template <typename T>
+void launch_restrict(int32_t n_agg, const int64_t* agg_ptr, const int32_t* agg_dofs, const int64_t* zoff,
+                     const int32_t* k, const int64_t* coff, const T* Z, const T* t, T* rc, hipStream_t st);
+template <typename T>
+void launch_prolong(int32_t n_agg, const int64_t* agg_ptr, const int32_t* agg_dofs, const int64_t* zoff,
+                    const int32_t* k, const int64_t* coff, const T* Z, const T* ec, T* x, hipStream_t st);
+template <typename T>
+void launch_zero(int64_t n, T* x, hipStream_t st);
+void launch_dense_gemv(int64_t n, const double* inv, const double* r, double* x, hipStream_t st);
+
+// PCG helpers (FP64).  `partials` holds at least 1024 doubles.
+void launch_dot(int64_t n, const double* a, const double* b, double* partials, double* out, hipStream_t st);
+// x += alpha p; r -= alpha q with alpha = s[0] / s[1]; out = ||r||^2
+void launch_update_xr(int64_t n, const double* s_num, const double* s_den, const double* p, const double* q,
+                      double* x, double* r, double* partials, double* out_rr, hipStream_t st);
+// p = z + (s_num / s_den) p
+void launch_update_p(int64_t n, const double* s_num, const double* s_den, const double* z, double* p,
+                     hipStream_t st);
+void launch_copy(int64_t n, const double* a, double* b, hipStream_t st);
+void launch_check_finite(int64_t n, const double* a, int32_t* flag, hipStream_t st);
+
+}  // namespace lsdd

@@ -1,0 +1,1074 @@
+// Host driver of the LS-AMG-DD library: hierarchy construction (integer work
+// on the host, numerics in HIP kernels), the V-cycle, PCG and the C-ABI.
+#include "lsdd.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <stdexcept>
+#include <string>
+#include <type_traits>
+#include <vector>
+
+#include "graph.hpp"
+#include "kernels.hpp"
+
+namespace {
+
+thread_local std::string g_err;
+lsdd_alloc_fn g_alloc = nullptr;
+lsdd_free_fn g_free = nullptr;
+void* g_alloc_ctx = nullptr;
+
+struct Error : std::runtime_error {
+    lsdd_status code;
+    Error(lsdd_status c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+
+#define HIPCHK(x)                                                                                  \
+    do {                                                                                           \
+        hipError_t e_ = (x);                                                                       \
+        if (e_ != hipSuccess)                                                                      \
+            throw Error(LSDD_E_HIP, std::string(#x) + ": " + hipGetErrorString(e_));               \
+    } while (0)
+
+double now_s() {
+    return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+}  // namespace
+
+namespace lsdd {
+
+// Device memory owned by one hierarchy; released in one go.
+struct Arena {
+    std::vector<void*> ptrs;
+    void* get(size_t bytes) {
+        if (bytes == 0) bytes = 8;
+        bytes = (bytes + 255) & ~size_t(255);
+        void* p = nullptr;
+        if (g_alloc) {
+            p = g_alloc(bytes, g_alloc_ctx);
+            if (!p) throw Error(LSDD_E_NOMEM, "allocator hook returned NULL for " + std::to_string(bytes) + " bytes");
+        } else {
+            hipError_t e = hipMalloc(&p, bytes);
+            if (e != hipSuccess) throw Error(LSDD_E_NOMEM, "hipMalloc(" + std::to_string(bytes) + "): " + hipGetErrorString(e));
+        }
+        ptrs.push_back(p);
+        return p;
+    }
+    template <typename T>
+    T* alloc(size_t count) { return static_cast<T*>(get(count * sizeof(T))); }
+    template <typename T>
+    T* upload(const std::vector<T>& v, hipStream_t st) {
+        T* p = alloc<T>(v.size());
+        if (!v.empty()) HIPCHK(hipMemcpyAsync(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, st));
+        return p;
+    }
+    void release(void* p) {
+        auto it = std::find(ptrs.begin(), ptrs.end(), p);
+        if (it == ptrs.end()) return;
+        if (g_free) g_free(p, g_alloc_ctx);
+        else (void)hipFree(p);
+        ptrs.erase(it);
+    }
+    void clear() {
+        for (void* p : ptrs) {
+            if (g_free) g_free(p, g_alloc_ctx);
+            else (void)hipFree(p);
+        }
+        ptrs.clear();
+    }
+};
+
+template <typename T>
+std::vector<T> download(const T* d, size_t count, hipStream_t st) {
+    std::vector<T> h(count);
+    if (count) {
+        HIPCHK(hipMemcpyAsync(h.data(), d, count * sizeof(T), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+    }
+    return h;
+}
+
+struct Level {
+    int32_t level = 0;
+    int64_t n = 0;
+    int64_t nnz = 0;
+    ElemList el;
+    std::vector<int64_t> blk_off;
+    int64_t* d_elem_ptr = nullptr;
+    int32_t* d_elem_dofs = nullptr;
+    int64_t* d_blk_off = nullptr;
+    double* d_blocks = nullptr;
+    // assembled operator
+    Csr pat;
+    int64_t* d_rowptr = nullptr;
+    int32_t* d_col = nullptr;
+    double* d_val = nullptr;
+    float* d_val32 = nullptr;
+    // level-0 Gram factors
+    double* d_G = nullptr;
+    std::vector<int32_t> ranks;
+    // supernodes
+    std::vector<int32_t> node_of_dof;
+    int32_t n_super = 0;
+    // coarsening
+    bool coarsest = false;
+    std::vector<int32_t> agg_of_dof;
+    Closure cl;
+    std::vector<int32_t> colors;
+    int32_t n_colors = 0;
+    std::vector<int32_t> k;
+    std::vector<int64_t> zoff, coff;
+    int64_t* d_agg_ptr = nullptr;
+    int32_t* d_agg_dofs = nullptr;
+    int64_t* d_zoff = nullptr;
+    int32_t* d_k = nullptr;
+    int64_t* d_coff = nullptr;
+    double* d_Z = nullptr;
+    float* d_Z32 = nullptr;
+    double* d_mu = nullptr;
+    // smoother, sweep order (colour-major, aggregate index within a colour)
+    std::vector<int32_t> sweep;
+    std::vector<int64_t> sw_sub_off;
+    std::vector<int64_t> color_row0, color_item0;
+    int64_t* d_sw_sub_off = nullptr;
+    int32_t* d_sw_sub_dofs = nullptr;
+    int64_t* d_sw_inv_off = nullptr;
+    int32_t* d_items = nullptr;
+    double* d_inv = nullptr;
+    float* d_inv32 = nullptr;
+    int64_t inv_len = 0;
+    // coarsest
+    double* d_cinv = nullptr;
+    // vectors
+    double *r64 = nullptr, *x64 = nullptr, *t64 = nullptr, *rloc64 = nullptr;
+    float *r32 = nullptr, *x32 = nullptr, *t32 = nullptr, *rloc32 = nullptr;
+    double *cr64 = nullptr, *cx64 = nullptr;   // FP64 staging for the FP32 coarsest solve
+};
+
+}  // namespace lsdd
+
+struct lsdd_hierarchy {
+    lsdd_params prm;
+    hipStream_t st = nullptr;
+    lsdd::Arena arena;
+    std::vector<std::unique_ptr<lsdd::Level>> L;
+    double setup_s = 0.0;
+    // PCG state
+    double *p = nullptr, *q = nullptr, *z = nullptr, *r = nullptr, *rold = nullptr;
+    double* scal = nullptr;       // device scalars
+    double* partials = nullptr;
+    int32_t* d_flag = nullptr;
+    double* h_scal = nullptr;     // pinned host mirror
+};
+
+namespace lsdd {
+
+namespace {
+
+void sync(hipStream_t st) { HIPCHK(hipStreamSynchronize(st)); }
+
+// Device copies of a level's element supports and blocks.
+void upload_elements(lsdd_hierarchy* h, Level& lv) {
+    lv.d_elem_ptr = h->arena.upload(lv.el.ptr, h->st);
+    lv.d_elem_dofs = h->arena.upload(lv.el.dofs, h->st);
+    lv.d_blk_off = h->arena.upload(lv.blk_off, h->st);
+}
+
+void assemble_operator(lsdd_hierarchy* h, Level& lv) {
+    lv.pat = assembled_pattern(lv.n, lv.el);
+    lv.nnz = (int64_t)lv.pat.idx.size();
+    lv.d_rowptr = h->arena.upload(lv.pat.ptr, h->st);
+    lv.d_col = h->arena.upload(lv.pat.idx, h->st);
+    lv.d_val = h->arena.alloc<double>(lv.nnz);
+    HIPCHK(hipMemsetAsync(lv.d_val, 0, lv.nnz * sizeof(double), h->st));
+    launch_assemble_csr(lv.el.count(), lv.d_elem_ptr, lv.d_elem_dofs, lv.d_blk_off, lv.d_blocks, lv.d_rowptr,
+                        lv.d_col, lv.d_val, h->st);
+    if (h->prm.precision == 1) {
+        lv.d_val32 = h->arena.alloc<float>(lv.nnz);
+        launch_to_f32(lv.nnz, lv.d_val, lv.d_val32, h->st);
+    }
+}
+
+void alloc_vectors(lsdd_hierarchy* h, Level& lv, int64_t rloc_len) {
+    Arena& a = h->arena;
+    if (h->prm.precision == 1) {
+        lv.r32 = a.alloc<float>(lv.n);
+        lv.x32 = a.alloc<float>(lv.n);
+        lv.t32 = a.alloc<float>(lv.n);
+        lv.rloc32 = a.alloc<float>(std::max<int64_t>(rloc_len, 1));
+        if (lv.coarsest) {
+            lv.cr64 = a.alloc<double>(lv.n);
+            lv.cx64 = a.alloc<double>(lv.n);
+        }
+    } else {
+        lv.r64 = a.alloc<double>(lv.n);
+        lv.x64 = a.alloc<double>(lv.n);
+        lv.t64 = a.alloc<double>(lv.n);
+        lv.rloc64 = a.alloc<double>(std::max<int64_t>(rloc_len, 1));
+    }
+}
+
+void make_coarsest(lsdd_hierarchy* h, Level& lv) {
+    lv.coarsest = true;
+    if (lv.n > 8192) throw Error(LSDD_E_UNSUPPORTED, "coarsest level too large: " + std::to_string(lv.n));
+    double* W = h->arena.alloc<double>((size_t)lv.n * lv.n);
+    HIPCHK(hipMemsetAsync(W, 0, (size_t)lv.n * lv.n * sizeof(double), h->st));
+    launch_dense_from_csr(lv.n, lv.d_rowptr, lv.d_col, lv.d_val, W, h->st);
+    lv.d_cinv = h->arena.alloc<double>((size_t)lv.n * lv.n);
+    int32_t* st = h->arena.alloc<int32_t>(1);
+    launch_dense_chol_inv(lv.n, W, lv.d_cinv, st, h->st);
+    int32_t hs = download(st, 1, h->st)[0];
+    h->arena.release(W);
+    if (hs != 0) throw Error(LSDD_E_NUMERIC, "coarsest-level Cholesky failed (matrix not SPD)");
+    alloc_vectors(h, lv, 0);
+}
+
+// Build level l+1 from level l; returns nullptr when no mode is retained.
+std::unique_ptr<Level> coarsen(lsdd_hierarchy* h, Level& lv, const int32_t* agg_given) {
+    const lsdd_params& P = h->prm;
+    hipStream_t st = h->st;
+    Arena& ar = h->arena;
+    const int64_t n = lv.n;
+    // ---- aggregates
+    int32_t n_agg = 0;
+    if (agg_given) {
+        lv.agg_of_dof.assign(agg_given, agg_given + n);
+        n_agg = 1 + *std::max_element(lv.agg_of_dof.begin(), lv.agg_of_dof.end());
+    } else {
+        Csr g = supernode_graph(lv.n_super, lv.node_of_dof, lv.el);
+        std::vector<int32_t> as = aggregate(g, lv.level == 0 ? P.agg_passes : P.agg_passes_coarse, &n_agg);
+        lv.agg_of_dof.resize(n);
+        for (int64_t d = 0; d < n; ++d) lv.agg_of_dof[d] = as[lv.node_of_dof[d]];
+    }
+    lv.cl = build_closure(n, lv.agg_of_dof, n_agg, lv.el);
+    const Closure& C = lv.cl;
+    for (int32_t i = 0; i < n_agg; ++i)
+        if (C.agg_ptr[i + 1] == C.agg_ptr[i]) throw Error(LSDD_E_INVAL, "empty aggregate " + std::to_string(i));
+    lv.colors = color_subdomains(n, C, lv.el, &lv.n_colors);
+    const double tau_cut = P.tau_const * (double)C.max_mult;
+    // ---- per-aggregate sizes and local positions of closure elements
+    std::vector<int64_t> sq(n_agg + 1, 0), msq(n_agg + 1, 0);
+    int64_t max_m = 0, max_nw = 0;
+    for (int32_t i = 0; i < n_agg; ++i) {
+        int64_t m = C.sub_ptr[i + 1] - C.sub_ptr[i], nw = C.agg_ptr[i + 1] - C.agg_ptr[i];
+        max_m = std::max(max_m, m);
+        max_nw = std::max(max_nw, nw);
+        sq[i + 1] = sq[i] + nw * nw;
+        msq[i + 1] = msq[i] + m * m;
+    }
+    if (max_m > 4096) throw Error(LSDD_E_UNSUPPORTED, "overlap larger than 4096 DOFs: " + std::to_string(max_m));
+    if (max_nw > 2048) throw Error(LSDD_E_UNSUPPORTED, "aggregate larger than 2048 DOFs");
+    std::vector<int64_t> clpos_off(C.cl_elems.size() + 1, 0);
+    std::vector<int32_t> clpos;
+    {
+        std::vector<int32_t> loc(n, -1);
+        for (int32_t i = 0; i < n_agg; ++i) {
+            for (int64_t q = C.sub_ptr[i]; q < C.sub_ptr[i + 1]; ++q) loc[C.sub_dofs[q]] = (int32_t)(q - C.sub_ptr[i]);
+            for (int64_t c = C.cl_ptr[i]; c < C.cl_ptr[i + 1]; ++c) {
+                int32_t e = C.cl_elems[c];
+                for (int64_t r = lv.el.ptr[e]; r < lv.el.ptr[e + 1]; ++r) clpos.push_back(loc[lv.el.dofs[r]]);
+                clpos_off[c + 1] = (int64_t)clpos.size();
+            }
+            for (int64_t q = C.sub_ptr[i]; q < C.sub_ptr[i + 1]; ++q) loc[C.sub_dofs[q]] = -1;
+        }
+    }
+    // ---- device inputs
+    int64_t* d_sub_ptr = ar.upload(C.sub_ptr, st);
+    int32_t* d_sub_dofs = ar.upload(C.sub_dofs, st);
+    lv.d_agg_ptr = ar.upload(C.agg_ptr, st);
+    lv.d_agg_dofs = ar.upload(C.agg_dofs, st);
+    int64_t* d_cl_ptr = ar.upload(C.cl_ptr, st);
+    int32_t* d_cl_elems = ar.upload(C.cl_elems, st);
+    int64_t* d_clpos_off = ar.upload(clpos_off, st);
+    int32_t* d_clpos = ar.upload(clpos, st);
+    int32_t* d_mult = ar.upload(C.mult, st);
+    int64_t* d_inv_off = ar.upload(msq, st);
+    int64_t* d_zst_off = ar.upload(sq, st);
+    lv.inv_len = msq[n_agg];
+    lv.d_inv = ar.alloc<double>(lv.inv_len);
+    double* d_zst = ar.alloc<double>(sq[n_agg]);
+    lv.d_mu = ar.alloc<double>(n);
+    lv.d_k = ar.alloc<int32_t>(n_agg);
+    int32_t* d_status = ar.alloc<int32_t>(n_agg);
+    HIPCHK(hipMemsetAsync(d_status, 0xff, n_agg * sizeof(int32_t), st));
+
+    LocalArgs A{};
+    A.sub_ptr = d_sub_ptr;
+    A.sub_dofs = d_sub_dofs;
+    A.agg_ptr = lv.d_agg_ptr;
+    A.cl_ptr = d_cl_ptr;
+    A.cl_elems = d_cl_elems;
+    A.clpos_off = d_clpos_off;
+    A.clpos = d_clpos;
+    A.mult = d_mult;
+    A.elem_ptr = lv.d_elem_ptr;
+    A.blk_off = lv.d_blk_off;
+    A.blocks = lv.d_blocks;
+    A.rowptr = lv.d_rowptr;
+    A.col = lv.d_col;
+    A.val = lv.d_val;
+    A.inv_off = d_inv_off;
+    A.inv = lv.d_inv;
+    A.zst_off = d_zst_off;
+    A.zst = d_zst;
+    A.mu_off = lv.d_agg_ptr;
+    A.mu = lv.d_mu;
+    A.k_out = lv.d_k;
+    A.status = d_status;
+    A.modes_fixed = P.modes_fixed;
+    A.thr = 1.0 / tau_cut;
+    A.band_tol = P.band_tol;
+    A.cluster_tol = P.cluster_tol;
+
+    // ---- batched local problems (workspace bounded)
+    const int64_t budget = int64_t(6) << 30;   // bytes of workspace per batch
+    auto run_batches = [&](const std::vector<int32_t>& aggs, int mode) {
+        size_t pos = 0;
+        while (pos < aggs.size()) {
+            std::vector<int64_t> ws_off(1, 0), sq_off(1, 0), w3_off(1, 0);
+            size_t end = pos;
+            int64_t bytes = 0;
+            while (end < aggs.size() && (end - pos) < 60000) {
+                int32_t i = aggs[end];
+                int64_t m = C.sub_ptr[i + 1] - C.sub_ptr[i], nw = C.agg_ptr[i + 1] - C.agg_ptr[i];
+                int64_t ng = m - nw;
+                if (mode && ng > 2048) throw Error(LSDD_E_UNSUPPORTED, "singular interface block larger than 2048");
+                int64_t need = (2 * m * m + 2 * nw * nw + (mode ? ng * ng + ng * nw : 0)) * 8;
+                if (end > pos && bytes + need > budget) break;
+                bytes += need;
+                ws_off.push_back(ws_off.back() + m * m);
+                sq_off.push_back(sq_off.back() + nw * nw);
+                w3_off.push_back(w3_off.back() + (mode ? ng * ng + ng * nw : 0));
+                ++end;
+            }
+            const int32_t nb = (int32_t)(end - pos);
+            // aggregates of a batch must be consecutive in this driver
+            for (size_t t = pos; t < end; ++t)
+                if (aggs[t] != aggs[pos] + (int32_t)(t - pos)) throw Error(LSDD_E_INVAL, "internal: non-consecutive batch");
+            double* w1 = ar.alloc<double>(ws_off.back());
+            double* w2 = ar.alloc<double>(ws_off.back());
+            double* sb = ar.alloc<double>(sq_off.back());
+            double* vb = ar.alloc<double>(sq_off.back());
+            double* w3 = mode ? ar.alloc<double>(w3_off.back()) : nullptr;
+            ws_off.pop_back();
+            sq_off.pop_back();
+            w3_off.pop_back();
+            int64_t* d_ws = ar.upload(ws_off, st);
+            int64_t* d_sq = ar.upload(sq_off, st);
+            int64_t* d_w3 = ar.upload(w3_off, st);
+            LocalArgs B = A;
+            B.first = aggs[pos];
+            B.ws_off = d_ws;
+            B.w1 = w1;
+            B.w2 = w2;
+            B.sq_off = d_sq;
+            B.s_buf = sb;
+            B.v_buf = vb;
+            B.w3_off = d_w3;
+            B.w3 = w3;
+            B.schur_mode = mode;
+            launch_local_assemble(nb, B, st);
+            launch_local_solve(nb, B, st);
+            HIPCHK(hipGetLastError());
+            sync(st);
+            ar.release(w1);
+            ar.release(w2);
+            ar.release(sb);
+            ar.release(vb);
+            if (w3) ar.release(w3);
+            ar.release(d_ws);
+            ar.release(d_sq);
+            ar.release(d_w3);
+            pos = end;
+        }
+    };
+    {
+        std::vector<int32_t> all(n_agg);
+        for (int32_t i = 0; i < n_agg; ++i) all[i] = i;
+        run_batches(all, 0);
+    }
+    std::vector<int32_t> status = download(d_status, n_agg, st);
+    for (int32_t i = 0; i < n_agg; ++i) {
+        if (status[i] == 1) {
+            std::vector<int32_t> one(1, i);
+            run_batches(one, 1);
+        }
+    }
+    status = download(d_status, n_agg, st);
+    for (int32_t i = 0; i < n_agg; ++i) {
+        if (status[i] != 0)
+            throw Error(LSDD_E_NUMERIC, "local problem of aggregate " + std::to_string(i) + " failed (status " +
+                                            std::to_string(status[i]) + ": overlap matrix not SPD)");
+    }
+    lv.k = download(lv.d_k, n_agg, st);
+    // ---- coarse numbering, compact Z
+    lv.coff.assign(n_agg + 1, 0);
+    lv.zoff.assign(n_agg + 1, 0);
+    for (int32_t i = 0; i < n_agg; ++i) {
+        lv.coff[i + 1] = lv.coff[i] + lv.k[i];
+        lv.zoff[i + 1] = lv.zoff[i] + (C.agg_ptr[i + 1] - C.agg_ptr[i]) * lv.k[i];
+    }
+    lv.d_coff = ar.upload(lv.coff, st);
+    lv.d_zoff = ar.upload(lv.zoff, st);
+    lv.d_Z = ar.alloc<double>(lv.zoff[n_agg]);
+    if (P.precision == 1) lv.d_Z32 = ar.alloc<float>(lv.zoff[n_agg]);
+    launch_z_compact(n_agg, lv.d_agg_ptr, lv.d_k, d_zst_off, d_zst, lv.d_zoff, lv.d_Z, lv.d_Z32, st);
+    sync(st);
+    ar.release(d_zst);
+    // ---- smoother arrays in sweep order
+    lv.sweep.resize(n_agg);
+    for (int32_t i = 0; i < n_agg; ++i) lv.sweep[i] = i;
+    std::stable_sort(lv.sweep.begin(), lv.sweep.end(),
+                     [&](int32_t a, int32_t b) { return lv.colors[a] < lv.colors[b]; });
+    std::vector<int32_t> sw_dofs;
+    std::vector<int64_t> sw_inv_off(n_agg);
+    std::vector<int32_t> items;
+    lv.sw_sub_off.assign(1, 0);
+    lv.color_row0.assign(lv.n_colors + 1, 0);
+    lv.color_item0.assign(lv.n_colors + 1, 0);
+    for (int32_t s = 0; s < n_agg; ++s) {
+        int32_t i = lv.sweep[s];
+        int64_t m = C.sub_ptr[i + 1] - C.sub_ptr[i];
+        sw_dofs.insert(sw_dofs.end(), C.sub_dofs.begin() + C.sub_ptr[i], C.sub_dofs.begin() + C.sub_ptr[i + 1]);
+        lv.sw_sub_off.push_back((int64_t)sw_dofs.size());
+        sw_inv_off[s] = msq[i];
+        for (int64_t c0 = 0; c0 < m; c0 += 64) {
+            items.push_back(s);
+            items.push_back((int32_t)c0);
+        }
+        int32_t c = lv.colors[i];
+        lv.color_row0[c + 1] = (int64_t)sw_dofs.size();
+        lv.color_item0[c + 1] = (int64_t)items.size() / 2;
+    }
+    for (int32_t c = 0; c < lv.n_colors; ++c) {
+        lv.color_row0[c + 1] = std::max(lv.color_row0[c + 1], lv.color_row0[c]);
+        lv.color_item0[c + 1] = std::max(lv.color_item0[c + 1], lv.color_item0[c]);
+    }
+    lv.d_sw_sub_off = ar.upload(lv.sw_sub_off, st);
+    lv.d_sw_sub_dofs = ar.upload(sw_dofs, st);
+    lv.d_sw_inv_off = ar.upload(sw_inv_off, st);
+    lv.d_items = ar.upload(items, st);
+    if (P.precision == 1) {
+        lv.d_inv32 = ar.alloc<float>(lv.inv_len);
+        launch_to_f32(lv.inv_len, lv.d_inv, lv.d_inv32, st);
+    }
+    alloc_vectors(h, lv, (int64_t)sw_dofs.size());
+    // free local-problem inputs that the solve does not use
+    for (void* p : {(void*)d_sub_ptr, (void*)d_sub_dofs, (void*)d_cl_ptr, (void*)d_cl_elems, (void*)d_clpos_off,
+                    (void*)d_clpos, (void*)d_mult, (void*)d_inv_off, (void*)d_zst_off, (void*)d_status})
+        ar.release(p);
+    const int64_t nc = lv.coff[n_agg];
+    if (nc == 0) return nullptr;
+    // ---- coarse level: grouped element rows and Galerkin products
+    CoarseGroups G = group_coarse(lv.el, lv.agg_of_dof, lv.k, lv.coff);
+    auto cv = std::make_unique<Level>();
+    cv->level = lv.level + 1;
+    cv->n = nc;
+    cv->el = std::move(G.coarse);
+    cv->node_of_dof = G.node_of_cdof;
+    cv->n_super = G.n_super;
+    const int64_t ng = cv->el.count();
+    cv->blk_off.assign(ng + 1, 0);
+    std::vector<int64_t> ws_off(ng, 0), pm_off(G.mem_elems.size() + 1, 0), pm_zrow;
+    std::vector<int32_t> pm_k, pm_col;
+    int64_t ws_tot = 0;
+    std::vector<int32_t> colof(n_agg, -1);
+    for (int64_t g = 0; g < ng; ++g) {
+        int64_t c = cv->el.ptr[g + 1] - cv->el.ptr[g];
+        cv->blk_off[g + 1] = cv->blk_off[g] + c * c;
+        // column offset of each aggregate inside the group support
+        int64_t off = 0;
+        std::vector<int32_t> touched;
+        for (int64_t q = cv->el.ptr[g]; q < cv->el.ptr[g + 1];) {
+            int32_t d = cv->el.dofs[q];
+            int32_t agg = (int32_t)(std::upper_bound(lv.coff.begin(), lv.coff.end(), (int64_t)d) - lv.coff.begin() - 1);
+            colof[agg] = (int32_t)off;
+            touched.push_back(agg);
+            off += lv.k[agg];
+            q += lv.k[agg];
+        }
+        int64_t ne_max = 0;
+        for (int64_t mi = G.mem_ptr[g]; mi < G.mem_ptr[g + 1]; ++mi) {
+            int32_t e = G.mem_elems[mi];
+            ne_max = std::max(ne_max, lv.el.ptr[e + 1] - lv.el.ptr[e]);
+            for (int64_t r = lv.el.ptr[e]; r < lv.el.ptr[e + 1]; ++r) {
+                int32_t d = lv.el.dofs[r];
+                int32_t agg = lv.agg_of_dof[d];
+                if (lv.k[agg] > 0) {
+                    pm_zrow.push_back(lv.zoff[agg] + (int64_t)C.pos_in_agg[d] * lv.k[agg]);
+                    pm_k.push_back(lv.k[agg]);
+                    pm_col.push_back(colof[agg]);
+                } else {
+                    pm_zrow.push_back(-1);
+                    pm_k.push_back(0);
+                    pm_col.push_back(0);
+                }
+            }
+            pm_off[mi + 1] = (int64_t)pm_zrow.size();
+        }
+        for (int32_t agg : touched) colof[agg] = -1;
+        ws_off[g] = ws_tot;
+        ws_tot += 2 * ne_max * c;
+    }
+    upload_elements(h, *cv);
+    cv->d_blocks = ar.alloc<double>(cv->blk_off[ng]);
+    GalerkinArgs ga{};
+    ga.n_groups = (int32_t)ng;
+    ga.cptr = cv->d_elem_ptr;
+    ga.mem_ptr = ar.upload(G.mem_ptr, st);
+    ga.mem_elems = ar.upload(G.mem_elems, st);
+    ga.felem_ptr = lv.d_elem_ptr;
+    ga.pm_off = ar.upload(pm_off, st);
+    ga.pm_zrow = ar.upload(pm_zrow, st);
+    ga.pm_k = ar.upload(pm_k, st);
+    ga.pm_col = ar.upload(pm_col, st);
+    ga.Z = lv.d_Z;
+    ga.use_gram = lv.level == 0 ? 1 : 0;
+    ga.fblk_off = lv.d_blk_off;
+    ga.fblocks = lv.level == 0 ? lv.d_G : lv.d_blocks;
+    ga.ws_off = ar.upload(ws_off, st);
+    ga.ws = ar.alloc<double>(ws_tot);
+    ga.cblk_off = cv->d_blk_off;
+    ga.cblocks = cv->d_blocks;
+    launch_galerkin(ga, st);
+    HIPCHK(hipGetLastError());
+    sync(st);
+    for (const void* p : {(const void*)ga.mem_ptr, (const void*)ga.mem_elems, (const void*)ga.pm_off,
+                          (const void*)ga.pm_zrow, (const void*)ga.pm_k, (const void*)ga.pm_col,
+                          (const void*)ga.ws_off, (const void*)ga.ws})
+        ar.release(const_cast<void*>(p));
+    assemble_operator(h, *cv);
+    return cv;
+}
+
+// ---------------------------------------------------------------- V-cycle
+
+template <typename T>
+struct LvVec;
+template <>
+struct LvVec<double> {
+    static double* r(Level& l) { return l.r64; }
+    static double* x(Level& l) { return l.x64; }
+    static double* t(Level& l) { return l.t64; }
+    static double* rloc(Level& l) { return l.rloc64; }
+    static const double* val(Level& l) { return l.d_val; }
+    static const double* Z(Level& l) { return l.d_Z; }
+    static const double* inv(Level& l) { return l.d_inv; }
+};
+template <>
+struct LvVec<float> {
+    static float* r(Level& l) { return l.r32; }
+    static float* x(Level& l) { return l.x32; }
+    static float* t(Level& l) { return l.t32; }
+    static float* rloc(Level& l) { return l.rloc32; }
+    static const float* val(Level& l) { return l.d_val32; }
+    static const float* Z(Level& l) { return l.d_Z32; }
+    static const float* inv(Level& l) { return l.d_inv32; }
+};
+
+template <typename T>
+void sweep(lsdd_hierarchy* h, Level& lv, const T* r, T* x, bool forward, bool x_zero_first) {
+    using V = LvVec<T>;
+    for (int32_t cc = 0; cc < lv.n_colors; ++cc) {
+        int32_t c = forward ? cc : lv.n_colors - 1 - cc;
+        int64_t r0 = lv.color_row0[c], r1 = lv.color_row0[c + 1];
+        int64_t i0 = lv.color_item0[c], i1 = lv.color_item0[c + 1];
+        if (i1 == i0) continue;
+        launch_csr_resid_rows<T>(r1 - r0, lv.d_sw_sub_dofs + r0, lv.d_rowptr, lv.d_col, V::val(lv), x, r,
+                                 V::rloc(lv) + r0, x_zero_first && cc == 0, h->st);
+        launch_sub_gemv<T>(i1 - i0, lv.d_items + 2 * i0, lv.d_sw_sub_off, lv.d_sw_inv_off, V::inv(lv), V::rloc(lv),
+                           lv.d_sw_sub_dofs, x, h->st);
+    }
+}
+
+template <typename T>
+void vcycle(lsdd_hierarchy* h, size_t l, const T* r, T* x) {
+    using V = LvVec<T>;
+    Level& lv = *h->L[l];
+    if (lv.coarsest) {
+        if constexpr (std::is_same<T, double>::value) {
+            launch_dense_gemv(lv.n, lv.d_cinv, r, x, h->st);
+        } else {
+            launch_to_f64(lv.n, r, lv.cr64, h->st);
+            launch_dense_gemv(lv.n, lv.d_cinv, lv.cr64, lv.cx64, h->st);
+            launch_to_f32(lv.n, lv.cx64, x, h->st);
+        }
+        return;
+    }
+    Level& nx = *h->L[l + 1];
+    launch_zero<T>(lv.n, x, h->st);
+    sweep<T>(h, lv, r, x, true, true);
+    launch_csr_spmv<T>(lv.n, lv.d_rowptr, lv.d_col, V::val(lv), x, V::t(lv), r, h->st);
+    launch_restrict<T>(lv.cl.n_agg, lv.d_agg_ptr, lv.d_agg_dofs, lv.d_zoff, lv.d_k, lv.d_coff, V::Z(lv), V::t(lv),
+                       V::r(nx), h->st);
+    vcycle<T>(h, l + 1, V::r(nx), V::x(nx));
+    launch_prolong<T>(lv.cl.n_agg, lv.d_agg_ptr, lv.d_agg_dofs, lv.d_zoff, lv.d_k, lv.d_coff, V::Z(lv), V::x(nx), x,
+                      h->st);
+    sweep<T>(h, lv, r, x, false, false);
+}
+
+void precond(lsdd_hierarchy* h, const double* r, double* z) {
+    Level& l0 = *h->L[0];
+    if (h->prm.precision == 1) {
+        launch_to_f32(l0.n, r, l0.r32, h->st);
+        vcycle<float>(h, 0, l0.r32, l0.x32);
+        launch_to_f64(l0.n, l0.x32, z, h->st);
+    } else {
+        vcycle<double>(h, 0, r, z);
+    }
+}
+
+// ---------------------------------------------------------------- setup driver
+
+lsdd_hierarchy* build(ElemList el0, const double* blocks, bool blocks_on_device, const double* gram_rows, int64_t n,
+                      const int32_t* node_of_dof, const int32_t* agg_of_dof, const lsdd_params* prm, void* stream) {
+    auto h = std::make_unique<lsdd_hierarchy>();
+    lsdd_params_default(&h->prm);
+    if (prm) h->prm = *prm;
+    const lsdd_params& P = h->prm;
+    if (P.max_levels < 1 || P.precision < 0 || P.precision > 1 || P.tau_const <= 0 || P.rtol <= 0 || P.max_iter < 1)
+        throw Error(LSDD_E_INVAL, "invalid parameters");
+    h->st = (hipStream_t)stream;
+    double t0 = now_s();
+    auto lv = std::make_unique<Level>();
+    lv->level = 0;
+    lv->n = n;
+    lv->el = std::move(el0);
+    const int64_t ne = lv->el.count();
+    lv->blk_off.assign(ne + 1, 0);
+    for (int64_t e = 0; e < ne; ++e) {
+        int64_t s = lv->el.ptr[e + 1] - lv->el.ptr[e];
+        lv->blk_off[e + 1] = lv->blk_off[e] + s * s;
+    }
+    if (node_of_dof) {
+        lv->node_of_dof.assign(node_of_dof, node_of_dof + n);
+        int32_t mx = -1;
+        for (int32_t v : lv->node_of_dof) {
+            if (v < 0) throw Error(LSDD_E_INVAL, "negative supernode id");
+            mx = std::max(mx, v);
+        }
+        std::vector<char> used(mx + 1, 0);
+        for (int32_t v : lv->node_of_dof) used[v] = 1;
+        for (char u : used)
+            if (!u) throw Error(LSDD_E_INVAL, "supernode ids must be 0..n_super-1, each used");
+        lv->n_super = mx + 1;
+    } else {
+        lv->node_of_dof.resize(n);
+        for (int64_t d = 0; d < n; ++d) lv->node_of_dof[d] = (int32_t)d;
+        lv->n_super = (int32_t)n;
+    }
+    Arena& ar = h->arena;
+    upload_elements(h.get(), *lv);
+    lv->d_blocks = ar.alloc<double>(lv->blk_off[ne]);
+    HIPCHK(hipMemcpyAsync(lv->d_blocks, blocks, lv->blk_off[ne] * sizeof(double),
+                          blocks_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, h->st));
+    // element Gram factors (Sec. 5.2)
+    lv->d_G = ar.alloc<double>(lv->blk_off[ne]);
+    if (!gram_rows) {
+        int32_t* d_ranks = ar.alloc<int32_t>(ne);
+        int32_t* d_status = ar.alloc<int32_t>(ne);
+        int64_t max_ne = 0;
+        for (int64_t e = 0; e < ne; ++e) max_ne = std::max(max_ne, lv->el.ptr[e + 1] - lv->el.ptr[e]);
+        const int64_t stride = 3 * max_ne * max_ne;
+        // process elements in chunks so the eigen scratch stays bounded
+        const int64_t chunk = std::max<int64_t>(1, std::min<int64_t>(ne, (int64_t(1) << 30) / (stride * 8)));
+        double* scratch = ar.alloc<double>(chunk * stride);
+        for (int64_t e0 = 0; e0 < ne; e0 += chunk) {
+            int64_t cnt = std::min(chunk, ne - e0);
+            launch_elem_eig(cnt, lv->d_elem_ptr + e0, lv->d_blk_off + e0, lv->d_blocks, lv->d_G, d_ranks + e0,
+                            d_status + e0, scratch, stride, P.rank_rtol, P.spsd_tol, h->st);
+        }
+        HIPCHK(hipGetLastError());
+        std::vector<int32_t> status = download(d_status, ne, h->st);
+        lv->ranks = download(d_ranks, ne, h->st);
+        for (int64_t e = 0; e < ne; ++e) {
+            if (status[e] == 1) throw Error(LSDD_E_INVAL, "element " + std::to_string(e) + ": block is not symmetric or not finite");
+            if (status[e] == 2) throw Error(LSDD_E_NOT_SPSD, "element " + std::to_string(e) + ": block is not SPSD");
+        }
+        ar.release(scratch);
+        ar.release(d_ranks);
+        ar.release(d_status);
+    } else {
+        // CSR G input: the level-0 blocks are g g^T and the Gram row is the factor
+        lv->ranks.assign(ne, 1);
+        HIPCHK(hipMemcpyAsync(lv->d_G, gram_rows, lv->blk_off[ne] * sizeof(double), hipMemcpyHostToDevice, h->st));
+    }
+    assemble_operator(h.get(), *lv);
+    HIPCHK(hipGetLastError());
+    h->L.push_back(std::move(lv));
+    while (true) {
+        Level& cur = *h->L.back();
+        const double density = (double)cur.nnz / ((double)cur.n * (double)cur.n);
+        bool last = (int)h->L.size() >= P.max_levels || cur.n < P.min_coarse || density > P.max_density;
+        std::unique_ptr<Level> nxt;
+        if (!last) {
+            nxt = coarsen(h.get(), cur, cur.level == 0 ? agg_of_dof : nullptr);
+            if (!nxt) last = true;
+        }
+        if (last) {
+            make_coarsest(h.get(), cur);
+            break;
+        }
+        h->L.push_back(std::move(nxt));
+    }
+    // PCG work vectors
+    const int64_t n0 = h->L[0]->n;
+    h->p = ar.alloc<double>(n0);
+    h->q = ar.alloc<double>(n0);
+    h->z = ar.alloc<double>(n0);
+    h->r = ar.alloc<double>(n0);
+    h->rold = ar.alloc<double>(n0);
+    h->scal = ar.alloc<double>(16);
+    h->partials = ar.alloc<double>(1024);
+    h->d_flag = ar.alloc<int32_t>(1);
+    HIPCHK(hipHostMalloc((void**)&h->h_scal, 16 * sizeof(double), hipHostMallocDefault));
+    sync(h->st);
+    h->setup_s = now_s() - t0;
+    return h.release();
+}
+
+}  // namespace
+}  // namespace lsdd
+
+using namespace lsdd;
+
+// ====================================================================== C-ABI
+
+extern "C" {
+
+void lsdd_params_default(lsdd_params* p) {
+    if (!p) return;
+    std::memset(p, 0, sizeof(*p));
+    p->max_levels = 3;
+    p->agg_passes = 2;
+    p->agg_passes_coarse = 1;
+    p->modes_fixed = 0;
+    p->min_coarse = 10;
+    p->max_iter = 1000;
+    p->precision = 0;
+    p->tau_const = 0.75;
+    p->max_density = 0.25;
+    p->rtol = 1e-8;
+    p->cluster_tol = 1e-9;
+    p->band_tol = 1e-9;
+    p->rank_rtol = 0.0;
+    p->spsd_tol = 1e-12;
+}
+
+const char* lsdd_last_error(void) { return g_err.c_str(); }
+
+void lsdd_set_allocator(lsdd_alloc_fn alloc, lsdd_free_fn free_fn, void* ctx) {
+    g_alloc = alloc;
+    g_free = free_fn;
+    g_alloc_ctx = ctx;
+}
+
+#define ABI_BEGIN \
+    g_err.clear(); \
+    try {
+#define ABI_END                                  \
+    }                                            \
+    catch (const Error& e) {                     \
+        g_err = e.what();                        \
+        return e.code;                           \
+    }                                            \
+    catch (const std::bad_alloc&) {              \
+        g_err = "host allocation failed";        \
+        return LSDD_E_NOMEM;                     \
+    }                                            \
+    catch (const std::exception& e) {            \
+        g_err = e.what();                        \
+        return LSDD_E_INVAL;                     \
+    }
+
+lsdd_status lsdd_setup_elements(int64_t n, int64_t n_elem, const int64_t* elem_ptr, const int32_t* elem_dofs,
+                                const double* elem_blocks, const int32_t* node_of_dof, const int32_t* agg_of_dof,
+                                int mem_is_device, const lsdd_params* params, void* hip_stream, lsdd_hierarchy** out) {
+    ABI_BEGIN
+    if (!out) throw Error(LSDD_E_INVAL, "out is NULL");
+    *out = nullptr;
+    if (n < 1 || n >= (int64_t(1) << 31) || n_elem < 1 || !elem_ptr || !elem_dofs || !elem_blocks)
+        throw Error(LSDD_E_INVAL, "bad sizes or NULL arrays");
+    ElemList el;
+    el.ptr.assign(elem_ptr, elem_ptr + n_elem + 1);
+    if (el.ptr[0] != 0) throw Error(LSDD_E_INVAL, "elem_ptr[0] must be 0");
+    std::vector<char> covered(n, 0), seen(n, 0);
+    for (int64_t e = 0; e < n_elem; ++e) {
+        int64_t s = el.ptr[e + 1] - el.ptr[e];
+        if (s < 1 || s > 128) throw Error(LSDD_E_INVAL, "element " + std::to_string(e) + " has " + std::to_string(s) + " DOFs (1..128 supported)");
+        for (int64_t q = el.ptr[e]; q < el.ptr[e + 1]; ++q) {
+            int32_t d = elem_dofs[q];
+            if (d < 0 || d >= n) throw Error(LSDD_E_INVAL, "element " + std::to_string(e) + ": DOF index out of range");
+            if (seen[d]) throw Error(LSDD_E_INVAL, "element " + std::to_string(e) + ": repeated DOF");
+            seen[d] = 1;
+            covered[d] = 1;
+        }
+        for (int64_t q = el.ptr[e]; q < el.ptr[e + 1]; ++q) seen[elem_dofs[q]] = 0;
+    }
+    for (int64_t d = 0; d < n; ++d)
+        if (!covered[d]) throw Error(LSDD_E_INVAL, "DOF " + std::to_string(d) + " belongs to no element");
+    el.dofs.assign(elem_dofs, elem_dofs + el.ptr[n_elem]);
+    if (agg_of_dof) {
+        int32_t mx = -1;
+        for (int64_t d = 0; d < n; ++d) {
+            if (agg_of_dof[d] < 0) throw Error(LSDD_E_INVAL, "negative aggregate id");
+            mx = std::max(mx, agg_of_dof[d]);
+        }
+        std::vector<char> used(mx + 1, 0);
+        for (int64_t d = 0; d < n; ++d) used[agg_of_dof[d]] = 1;
+        for (char u : used)
+            if (!u) throw Error(LSDD_E_INVAL, "aggregate ids must be 0..n_agg-1, each used");
+    }
+    *out = build(std::move(el), elem_blocks, mem_is_device != 0, nullptr, n, node_of_dof, agg_of_dof, params, hip_stream);
+    return LSDD_OK;
+    ABI_END
+}
+
+lsdd_status lsdd_setup_gram_csr(int64_t m, int64_t n, const int64_t* rowptr, const int32_t* col, const double* val,
+                                const int32_t* node_of_dof, const int32_t* agg_of_dof, const lsdd_params* params,
+                                void* hip_stream, lsdd_hierarchy** out) {
+    ABI_BEGIN
+    if (!out) throw Error(LSDD_E_INVAL, "out is NULL");
+    *out = nullptr;
+    if (m < 1 || n < 1 || n >= (int64_t(1) << 31) || !rowptr || !col || !val) throw Error(LSDD_E_INVAL, "bad arguments");
+    ElemList el;
+    el.ptr.assign(1, 0);
+    std::vector<double> blocks, grows;
+    std::vector<char> covered(n, 0);
+    for (int64_t j = 0; j < m; ++j) {
+        int64_t a = rowptr[j], b = rowptr[j + 1];
+        if (b < a) throw Error(LSDD_E_INVAL, "rowptr not monotone");
+        if (b == a) continue;                               // zero rows are dropped
+        if (b - a > 128) throw Error(LSDD_E_UNSUPPORTED, "a row of G has more than 128 entries");
+        for (int64_t q = a; q < b; ++q) {
+            if (col[q] < 0 || col[q] >= n) throw Error(LSDD_E_INVAL, "column index out of range");
+            if (!std::isfinite(val[q])) throw Error(LSDD_E_INVAL, "non-finite value in G");
+            covered[col[q]] = 1;
+            el.dofs.push_back(col[q]);
+        }
+        const int64_t s = b - a;
+        for (int64_t u = 0; u < s; ++u)
+            for (int64_t v = 0; v < s; ++v) blocks.push_back(val[a + u] * val[a + v]);
+        for (int64_t u = 0; u < s; ++u)
+            for (int64_t v = 0; v < s; ++v) grows.push_back(u == 0 ? val[a + v] : 0.0);
+        el.ptr.push_back((int64_t)el.dofs.size());
+    }
+    for (int64_t d = 0; d < n; ++d)
+        if (!covered[d]) throw Error(LSDD_E_INVAL, "column " + std::to_string(d) + " of G is empty (A singular)");
+    *out = build(std::move(el), blocks.data(), false, grows.data(), n, node_of_dof, agg_of_dof, params, hip_stream);
+    return LSDD_OK;
+    ABI_END
+}
+
+lsdd_status lsdd_destroy(lsdd_hierarchy* h) {
+    ABI_BEGIN
+    if (!h) return LSDD_OK;
+    if (h->st) (void)hipStreamSynchronize(h->st);
+    else (void)hipDeviceSynchronize();
+    h->arena.clear();
+    if (h->h_scal) (void)hipHostFree(h->h_scal);
+    delete h;
+    return LSDD_OK;
+    ABI_END
+}
+
+lsdd_status lsdd_vcycle(lsdd_hierarchy* h, const double* r, double* z, void* hip_stream) {
+    ABI_BEGIN
+    if (!h || !r || !z) throw Error(LSDD_E_INVAL, "NULL argument");
+    h->st = (hipStream_t)hip_stream;
+    precond(h, r, z);
+    HIPCHK(hipGetLastError());
+    sync(h->st);
+    return LSDD_OK;
+    ABI_END
+}
+
+lsdd_status lsdd_apply(lsdd_hierarchy* h, int32_t level, const double* x, double* y, void* hip_stream) {
+    ABI_BEGIN
+    if (!h || !x || !y || level < 0 || level >= (int32_t)h->L.size()) throw Error(LSDD_E_INVAL, "bad argument");
+    h->st = (hipStream_t)hip_stream;
+    Level& lv = *h->L[level];
+    launch_csr_spmv<double>(lv.n, lv.d_rowptr, lv.d_col, lv.d_val, x, y, nullptr, h->st);
+    HIPCHK(hipGetLastError());
+    sync(h->st);
+    return LSDD_OK;
+    ABI_END
+}
+
+lsdd_status lsdd_solve(lsdd_hierarchy* h, const double* b, double* x, int32_t nrhs, void* hip_stream, lsdd_info* info) {
+    ABI_BEGIN
+    if (!h || !b || !x || nrhs < 1) throw Error(LSDD_E_INVAL, "bad argument");
+    h->st = (hipStream_t)hip_stream;
+    hipStream_t st = h->st;
+    Level& l0 = *h->L[0];
+    const int64_t n = l0.n;
+    const bool flex = h->prm.precision == 1;
+    double* S = h->scal;   // [0] rz [1] pq [2] rr [3] bb [4] zr_new [5] z.(r - rold)
+    lsdd_status worst = LSDD_OK;
+    for (int32_t k = 0; k < nrhs; ++k) {
+        double t0 = now_s();
+        const double* bk = b + (int64_t)k * n;
+        double* xk = x + (int64_t)k * n;
+        HIPCHK(hipMemsetAsync(h->d_flag, 0, sizeof(int32_t), st));
+        launch_check_finite(n, bk, h->d_flag, st);
+        int32_t bad = download(h->d_flag, 1, st)[0];
+        if (bad) throw Error(LSDD_E_INVAL, "right-hand side " + std::to_string(k) + " has NaN/Inf");
+        launch_dot(n, bk, bk, h->partials, S + 3, st);
+        HIPCHK(hipMemcpyAsync(h->h_scal, S + 3, sizeof(double), hipMemcpyDeviceToHost, st));
+        sync(st);
+        const double bn = std::sqrt(h->h_scal[0]);
+        launch_zero<double>(n, xk, st);
+        lsdd_info inf{0, 1, 0.0, h->setup_s, 0.0};
+        if (bn == 0.0) {
+            sync(st);
+            inf.solve_s = now_s() - t0;
+            if (info) info[k] = inf;
+            continue;
+        }
+        launch_copy(n, bk, h->r, st);
+        precond(h, h->r, h->z);
+        launch_copy(n, h->z, h->p, st);
+        launch_dot(n, h->r, h->z, h->partials, S + 0, st);
+        lsdd_status stat = LSDD_E_NOCONV;
+        double rel = 1.0;
+        int it = 0;
+        for (it = 1; it <= h->prm.max_iter; ++it) {
+            launch_csr_spmv<double>(n, l0.d_rowptr, l0.d_col, l0.d_val, h->p, h->q, nullptr, st);
+            launch_dot(n, h->p, h->q, h->partials, S + 1, st);
+            if (flex) launch_copy(n, h->r, h->rold, st);
+            launch_update_xr(n, S + 0, S + 1, h->p, h->q, xk, h->r, h->partials, S + 2, st);
+            HIPCHK(hipMemcpyAsync(h->h_scal, S, 3 * sizeof(double), hipMemcpyDeviceToHost, st));
+            sync(st);
+            const double pq = h->h_scal[1], rr = h->h_scal[2];
+            if (!(pq > 0.0) || !std::isfinite(rr)) {
+                stat = LSDD_E_BREAKDOWN;
+                break;
+            }
+            rel = std::sqrt(rr) / bn;
+            if (rel <= h->prm.rtol) {
+                stat = LSDD_OK;
+                break;
+            }
+            precond(h, h->r, h->z);
+            launch_dot(n, h->r, h->z, h->partials, S + 4, st);
+            if (flex) {
+                launch_dot(n, h->rold, h->z, h->partials, S + 6, st);
+                // S[5] = S[4] - S[6] computed on the host side of the stream: use a tiny copy path
+                HIPCHK(hipMemcpyAsync(h->h_scal + 4, S + 4, 3 * sizeof(double), hipMemcpyDeviceToHost, st));
+                sync(st);
+                h->h_scal[5] = h->h_scal[4] - h->h_scal[6];
+                HIPCHK(hipMemcpyAsync(S + 5, h->h_scal + 5, sizeof(double), hipMemcpyHostToDevice, st));
+                launch_update_p(n, S + 5, S + 0, h->z, h->p, st);
+            } else {
+                launch_update_p(n, S + 4, S + 0, h->z, h->p, st);
+            }
+            launch_copy(1, S + 4, S + 0, st);
+        }
+        HIPCHK(hipGetLastError());
+        sync(st);
+        inf.iters = std::min(it, h->prm.max_iter);
+        inf.converged = stat == LSDD_OK;
+        inf.rel_res = rel;
+        inf.solve_s = now_s() - t0;
+        if (info) info[k] = inf;
+        if (stat == LSDD_E_BREAKDOWN) throw Error(LSDD_E_BREAKDOWN, "PCG breakdown (p^T A p <= 0 or non-finite)");
+        if (stat != LSDD_OK && worst == LSDD_OK) {
+            worst = stat;
+            g_err = "PCG did not reach rtol within max_iter";
+        }
+    }
+    return worst;
+    ABI_END
+}
+
+lsdd_status lsdd_hierarchy_info(const lsdd_hierarchy* h, int32_t* levels, int64_t* n_l, int64_t* nnz_l, double* oc,
+                                double* gc) {
+    ABI_BEGIN
+    if (!h) throw Error(LSDD_E_INVAL, "NULL hierarchy");
+    const size_t L = h->L.size();
+    if (levels) *levels = (int32_t)L;
+    double sn = 0, snnz = 0;
+    for (size_t l = 0; l < L; ++l) {
+        if (n_l) n_l[l] = h->L[l]->n;
+        if (nnz_l) nnz_l[l] = h->L[l]->nnz;
+        sn += (double)h->L[l]->n;
+        snnz += (double)h->L[l]->nnz;
+    }
+    if (oc) *oc = snnz / (double)h->L[0]->nnz;
+    if (gc) *gc = sn / (double)h->L[0]->n;
+    return LSDD_OK;
+    ABI_END
+}
+
+lsdd_status lsdd_level_sizes(const lsdd_hierarchy* h, int32_t level, int64_t* sizes) {
+    ABI_BEGIN
+    if (!h || !sizes || level < 0 || level >= (int32_t)h->L.size()) throw Error(LSDD_E_INVAL, "bad argument");
+    const Level& lv = *h->L[level];
+    for (int i = 0; i < 8; ++i) sizes[i] = 0;
+    sizes[0] = lv.n;
+    sizes[1] = lv.nnz;
+    sizes[7] = lv.el.count();
+    if (!lv.coarsest) {
+        sizes[2] = lv.cl.n_agg;
+        sizes[3] = lv.zoff.empty() ? 0 : lv.zoff.back();
+        sizes[4] = (int64_t)lv.cl.sub_dofs.size();
+        sizes[5] = lv.n_colors;
+        sizes[6] = lv.coff.empty() ? 0 : lv.coff.back();
+    }
+    return LSDD_OK;
+    ABI_END
+}
+
+lsdd_status lsdd_export_level(const lsdd_hierarchy* h, int32_t level, int32_t* agg_of_dof, int32_t* k, double* Z,
+                              double* mu, int32_t* colors, int64_t* rowptr, int32_t* col, double* val,
+                              int32_t* omega_sizes) {
+    ABI_BEGIN
+    if (!h || level < 0 || level >= (int32_t)h->L.size()) throw Error(LSDD_E_INVAL, "bad argument");
+    const Level& lv = *h->L[level];
+    hipStream_t st = h->st;
+    if (rowptr) std::copy(lv.pat.ptr.begin(), lv.pat.ptr.end(), rowptr);
+    if (col) std::copy(lv.pat.idx.begin(), lv.pat.idx.end(), col);
+    if (val) {
+        HIPCHK(hipMemcpyAsync(val, lv.d_val, lv.nnz * sizeof(double), hipMemcpyDeviceToHost, st));
+        sync(st);
+    }
+    if (lv.coarsest) return LSDD_OK;
+    if (agg_of_dof) std::copy(lv.agg_of_dof.begin(), lv.agg_of_dof.end(), agg_of_dof);
+    if (k) std::copy(lv.k.begin(), lv.k.end(), k);
+    if (colors) std::copy(lv.colors.begin(), lv.colors.end(), colors);
+    if (omega_sizes)
+        for (int32_t i = 0; i < lv.cl.n_agg; ++i) omega_sizes[i] = (int32_t)(lv.cl.sub_ptr[i + 1] - lv.cl.sub_ptr[i]);
+    if (Z && lv.zoff.back() > 0) {
+        HIPCHK(hipMemcpyAsync(Z, lv.d_Z, lv.zoff.back() * sizeof(double), hipMemcpyDeviceToHost, st));
+        sync(st);
+    }
+    if (mu) {
+        HIPCHK(hipMemcpyAsync(mu, lv.d_mu, lv.n * sizeof(double), hipMemcpyDeviceToHost, st));
+        sync(st);
+    }
+    return LSDD_OK;
+    ABI_END
+}
+
+lsdd_status lsdd_export_gram(const lsdd_hierarchy* h, int32_t* ranks, double* G) {
+    ABI_BEGIN
+    if (!h) throw Error(LSDD_E_INVAL, "NULL hierarchy");
+    const Level& l0 = *h->L[0];
+    if (ranks) std::copy(l0.ranks.begin(), l0.ranks.end(), ranks);
+    if (G) {
+        HIPCHK(hipMemcpyAsync(G, l0.d_G, l0.blk_off.back() * sizeof(double), hipMemcpyDeviceToHost, h->st));
+        sync(h->st);
+    }
+    return LSDD_OK;
+    ABI_END
+}
+
+}  // extern "C"

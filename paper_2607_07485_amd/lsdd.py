@@ -1,0 +1,275 @@
+"""ctypes binding of liblsdd.so (argument marshalling only).
+
+The names follow the C-ABI in include/lsdd.h.  Device arrays are torch CUDA
+(HIP) tensors; host arrays are numpy arrays.  The library must be built
+(python -m paper_2607_07485_amd.build); importing this module fails loudly
+when it is missing, and no operation has a CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+lib_path = os.path.join(_PKG, "liblsdd.so")
+
+LSDD_STATUS = {0: "LSDD_OK", 1: "LSDD_E_INVAL", 2: "LSDD_E_NOT_SPSD", 3: "LSDD_E_NOMEM", 4: "LSDD_E_HIP",
+               5: "LSDD_E_NOCONV", 6: "LSDD_E_BREAKDOWN", 7: "LSDD_E_UNSUPPORTED", 8: "LSDD_E_NUMERIC"}
+
+
+class LsddError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{LSDD_STATUS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class Params(C.Structure):
+    _fields_ = [("max_levels", C.c_int32), ("agg_passes", C.c_int32), ("agg_passes_coarse", C.c_int32),
+                ("modes_fixed", C.c_int32), ("min_coarse", C.c_int32), ("max_iter", C.c_int32),
+                ("precision", C.c_int32), ("reserved0", C.c_int32),
+                ("tau_const", C.c_double), ("max_density", C.c_double), ("rtol", C.c_double),
+                ("cluster_tol", C.c_double), ("band_tol", C.c_double), ("rank_rtol", C.c_double),
+                ("spsd_tol", C.c_double)]
+
+    @classmethod
+    def default(cls, **kw) -> "Params":
+        p = cls()
+        lib().lsdd_params_default(C.byref(p))
+        for k, v in kw.items():
+            if not hasattr(p, k):
+                raise AttributeError(k)
+            setattr(p, k, v)
+        return p
+
+
+class Info(C.Structure):
+    _fields_ = [("iters", C.c_int32), ("converged", C.c_int32), ("rel_res", C.c_double),
+                ("setup_s", C.c_double), ("solve_s", C.c_double)]
+
+
+_LIB = None
+_P = C.c_void_p
+
+
+def lib():
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(lib_path):
+            raise ImportError(f"{lib_path} is not built; run `python -m paper_2607_07485_amd.build`")
+        L = C.CDLL(lib_path)
+        i32p, i64p, f64p = C.POINTER(C.c_int32), C.POINTER(C.c_int64), C.POINTER(C.c_double)
+        L.lsdd_params_default.argtypes = [C.POINTER(Params)]
+        L.lsdd_params_default.restype = None
+        L.lsdd_last_error.restype = C.c_char_p
+        L.lsdd_setup_elements.argtypes = [C.c_int64, C.c_int64, i64p, i32p, _P, i32p, i32p, C.c_int,
+                                          C.POINTER(Params), _P, C.POINTER(_P)]
+        L.lsdd_setup_gram_csr.argtypes = [C.c_int64, C.c_int64, i64p, i32p, f64p, i32p, i32p,
+                                          C.POINTER(Params), _P, C.POINTER(_P)]
+        L.lsdd_solve.argtypes = [_P, _P, _P, C.c_int32, _P, C.POINTER(Info)]
+        L.lsdd_vcycle.argtypes = [_P, _P, _P, _P]
+        L.lsdd_apply.argtypes = [_P, C.c_int32, _P, _P, _P]
+        L.lsdd_hierarchy_info.argtypes = [_P, i32p, i64p, i64p, f64p, f64p]
+        L.lsdd_level_sizes.argtypes = [_P, C.c_int32, i64p]
+        L.lsdd_export_level.argtypes = [_P, C.c_int32, i32p, i32p, f64p, f64p, i32p, i64p, i32p, f64p, i32p]
+        L.lsdd_export_gram.argtypes = [_P, i32p, f64p]
+        L.lsdd_destroy.argtypes = [_P]
+        L.lsdd_set_allocator.argtypes = [_P, _P, _P]
+        L.lsdd_set_allocator.restype = None
+        for name in ("lsdd_setup_elements", "lsdd_setup_gram_csr", "lsdd_solve", "lsdd_vcycle", "lsdd_apply",
+                     "lsdd_hierarchy_info", "lsdd_level_sizes", "lsdd_export_level", "lsdd_export_gram",
+                     "lsdd_destroy"):
+            getattr(L, name).restype = C.c_int
+        _LIB = L
+    return _LIB
+
+
+def _check(code: int, allow=()):
+    if code != 0 and code not in allow:
+        raise LsddError(code, lib().lsdd_last_error().decode())
+    return code
+
+
+def _ptr(a: np.ndarray, ctype):
+    return a.ctypes.data_as(C.POINTER(ctype)) if a is not None else None
+
+
+def _stream():
+    import torch
+    if not torch.cuda.is_available():
+        return C.c_void_p(None)        # host-side validation still runs; device calls then fail
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dev_ptr(t):
+    import torch
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()):
+        raise TypeError("expected a contiguous float64 device tensor")
+    return C.c_void_p(t.data_ptr())
+
+
+class Hierarchy:
+    """An LS-AMG-DD hierarchy owned by the library (lsdd_hierarchy*)."""
+
+    def __init__(self, handle: C.c_void_p):
+        self._h = handle
+
+    # ---------------------------------------------------------------- setup
+    @classmethod
+    def setup_elements(cls, n, elem_ptr, elem_dofs, blocks, node_of_dof=None, agg_of_dof=None, params=None):
+        """lsdd_setup_elements; `blocks` is a host numpy array or a float64 device tensor."""
+        import torch
+        elem_ptr = np.ascontiguousarray(elem_ptr, dtype=np.int64)
+        elem_dofs = np.ascontiguousarray(elem_dofs, dtype=np.int32)
+        nod = None if node_of_dof is None else np.ascontiguousarray(node_of_dof, dtype=np.int32)
+        agg = None if agg_of_dof is None else np.ascontiguousarray(agg_of_dof, dtype=np.int32)
+        if isinstance(blocks, torch.Tensor):
+            bptr, on_dev = _dev_ptr(blocks), 1
+        else:
+            blocks = np.ascontiguousarray(blocks, dtype=np.float64)
+            bptr, on_dev = C.c_void_p(blocks.ctypes.data), 0
+        params = params or Params.default()
+        h = C.c_void_p()
+        _check(lib().lsdd_setup_elements(int(n), len(elem_ptr) - 1, _ptr(elem_ptr, C.c_int64),
+                                         _ptr(elem_dofs, C.c_int32), bptr, _ptr(nod, C.c_int32),
+                                         _ptr(agg, C.c_int32), on_dev, C.byref(params), _stream(), C.byref(h)))
+        return cls(h)
+
+    @classmethod
+    def setup_problem(cls, prob, params=None, blocks_on_device=False):
+        """Convenience: setup from an object with n/elem_ptr/elem_dofs/blocks/node_of_dof/agg_of_dof."""
+        blocks = prob.blocks
+        if blocks_on_device:
+            import torch
+            blocks = torch.from_numpy(np.ascontiguousarray(blocks)).cuda()
+        return cls.setup_elements(prob.n, prob.elem_ptr, prob.elem_dofs, blocks, prob.node_of_dof,
+                                  prob.agg_of_dof, params)
+
+    @classmethod
+    def setup_gram_csr(cls, m, n, rowptr, col, val, node_of_dof=None, agg_of_dof=None, params=None):
+        rowptr = np.ascontiguousarray(rowptr, dtype=np.int64)
+        col = np.ascontiguousarray(col, dtype=np.int32)
+        val = np.ascontiguousarray(val, dtype=np.float64)
+        nod = None if node_of_dof is None else np.ascontiguousarray(node_of_dof, dtype=np.int32)
+        agg = None if agg_of_dof is None else np.ascontiguousarray(agg_of_dof, dtype=np.int32)
+        params = params or Params.default()
+        h = C.c_void_p()
+        _check(lib().lsdd_setup_gram_csr(int(m), int(n), _ptr(rowptr, C.c_int64), _ptr(col, C.c_int32),
+                                         _ptr(val, C.c_double), _ptr(nod, C.c_int32), _ptr(agg, C.c_int32),
+                                         C.byref(params), _stream(), C.byref(h)))
+        return cls(h)
+
+    # ---------------------------------------------------------------- solve
+    def solve(self, b, x=None, allow_noconv=False):
+        """lsdd_solve for b of shape [n] or [nrhs, n]; returns (x, [Info])."""
+        import torch
+        nrhs = 1 if b.dim() == 1 else b.shape[0]
+        if x is None:
+            x = torch.empty_like(b)
+        infos = (Info * nrhs)()
+        _check(lib().lsdd_solve(self._h, _dev_ptr(b), _dev_ptr(x), nrhs, _stream(), infos),
+               allow=(5,) if allow_noconv else ())
+        return x, [infos[i] for i in range(nrhs)]
+
+    def vcycle(self, r, z=None):
+        import torch
+        z = torch.empty_like(r) if z is None else z
+        _check(lib().lsdd_vcycle(self._h, _dev_ptr(r), _dev_ptr(z), _stream()))
+        return z
+
+    def apply(self, x, level=0, y=None):
+        import torch
+        y = torch.empty_like(x) if y is None else y
+        _check(lib().lsdd_apply(self._h, int(level), _dev_ptr(x), _dev_ptr(y), _stream()))
+        return y
+
+    # ---------------------------------------------------------------- inspection
+    def info(self):
+        L = C.c_int32()
+        n = np.zeros(16, np.int64)
+        nnz = np.zeros(16, np.int64)
+        oc, gc = C.c_double(), C.c_double()
+        _check(lib().lsdd_hierarchy_info(self._h, C.byref(L), _ptr(n, C.c_int64), _ptr(nnz, C.c_int64),
+                                         C.byref(oc), C.byref(gc)))
+        return dict(levels=L.value, n=n[:L.value].tolist(), nnz=nnz[:L.value].tolist(), oc=oc.value, gc=gc.value)
+
+    def level_sizes(self, level):
+        s = np.zeros(8, np.int64)
+        _check(lib().lsdd_level_sizes(self._h, int(level), _ptr(s, C.c_int64)))
+        keys = ("n", "nnz", "n_agg", "z_len", "sub_len", "n_colors", "n_next", "n_elem")
+        return dict(zip(keys, s.tolist()))
+
+    def export_level(self, level):
+        s = self.level_sizes(level)
+        out = dict(sizes=s)
+        rowptr = np.zeros(s["n"] + 1, np.int64)
+        col = np.zeros(s["nnz"], np.int32)
+        val = np.zeros(s["nnz"], np.float64)
+        if s["n_agg"]:
+            agg = np.zeros(s["n"], np.int32)
+            k = np.zeros(s["n_agg"], np.int32)
+            Z = np.zeros(max(s["z_len"], 1), np.float64)
+            mu = np.zeros(s["n"], np.float64)
+            colors = np.zeros(s["n_agg"], np.int32)
+            osz = np.zeros(s["n_agg"], np.int32)
+        else:
+            agg = k = Z = mu = colors = osz = None
+        _check(lib().lsdd_export_level(self._h, int(level), _ptr(agg, C.c_int32), _ptr(k, C.c_int32),
+                                       _ptr(Z, C.c_double), _ptr(mu, C.c_double), _ptr(colors, C.c_int32),
+                                       _ptr(rowptr, C.c_int64), _ptr(col, C.c_int32), _ptr(val, C.c_double),
+                                       _ptr(osz, C.c_int32)))
+        out.update(rowptr=rowptr, col=col, val=val, agg_of_dof=agg, k=k, Z=Z, mu=mu, colors=colors,
+                   omega_sizes=osz)
+        return out
+
+    def export_gram(self, elem_ptr):
+        sizes = np.diff(np.asarray(elem_ptr, np.int64))
+        ranks = np.zeros(len(sizes), np.int32)
+        G = np.zeros(int(np.sum(sizes * sizes)), np.float64)
+        _check(lib().lsdd_export_gram(self._h, _ptr(ranks, C.c_int32), _ptr(G, C.c_double)))
+        return ranks, G
+
+    def close(self):
+        if self._h is not None and self._h.value:
+            _check(lib().lsdd_destroy(self._h))
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+
+_ALLOC_CB = None
+
+
+def set_torch_allocator(enable: bool = True):
+    """Route the library's device allocations through torch's caching allocator."""
+    global _ALLOC_CB
+    import torch
+    if not enable:
+        lib().lsdd_set_allocator(None, None, None)
+        _ALLOC_CB = None
+        return
+    AF = C.CFUNCTYPE(C.c_void_p, C.c_uint64, C.c_void_p)
+    FF = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
+
+    def _alloc(nbytes, ctx):
+        try:
+            return torch.cuda.caching_allocator_alloc(int(nbytes))
+        except Exception:
+            return None
+
+    def _free(ptr, ctx):
+        torch.cuda.caching_allocator_delete(ptr)
+
+    _ALLOC_CB = (AF(_alloc), FF(_free))
+    lib().lsdd_set_allocator(C.cast(_ALLOC_CB[0], C.c_void_p), C.cast(_ALLOC_CB[1], C.c_void_p), None)

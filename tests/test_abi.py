@@ -1,0 +1,62 @@
+"""CPU-side checks of the C-ABI library: it loads, exports every declared entry
+point, and rejects bad inputs during host validation (before any device call)."""
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    txt = open(os.path.join(ROOT, "include", "lsdd.h")).read()
+    return sorted(set(re.findall(r"\b(lsdd_[a-z_]+)\s*\(", txt)))
+
+
+def test_library_exports_every_declared_symbol():
+    import paper_2607_07485_amd as P
+    out = subprocess.run(["nm", "-D", "--defined-only", P.lib_path], capture_output=True, text=True).stdout
+    exported = set(re.findall(r"\sT\s(lsdd_\w+)", out))
+    missing = [s for s in _declared() if s not in exported]
+    assert not missing, missing
+    assert len(_declared()) >= 13
+
+
+def test_params_defaults_match_the_paper_settings():
+    import paper_2607_07485_amd as P
+    p = P.Params.default()
+    assert (p.max_levels, p.agg_passes, p.min_coarse) == (3, 2, 10)
+    assert p.max_density == 0.25 and p.tau_const == 0.75 and p.rtol == 1e-8
+
+
+def _elems():
+    import fegen
+    return fegen.elasticity_q1(3, nu=0.3)
+
+
+@pytest.mark.parametrize("mutate, msg", [
+    (lambda p: p.elem_dofs.__setitem__(5, 10 ** 6), "out of range"),
+    (lambda p: p.elem_dofs.__setitem__(1, p.elem_dofs[0]), "repeated DOF"),
+])
+def test_setup_rejects_bad_indices_before_any_device_call(mutate, msg):
+    import paper_2607_07485_amd as P
+    prob = _elems()
+    prob.elem_dofs = prob.elem_dofs.copy()
+    mutate(prob)
+    with pytest.raises(P.LsddError) as ei:
+        P.Hierarchy.setup_elements(prob.n, prob.elem_ptr, prob.elem_dofs, prob.blocks, prob.node_of_dof,
+                                   prob.agg_of_dof)
+    assert ei.value.code == 1 and msg in str(ei.value)
+
+
+def test_setup_rejects_uncovered_dof_and_bad_aggregates():
+    import paper_2607_07485_amd as P
+    prob = _elems()
+    with pytest.raises(P.LsddError, match="belongs to no element"):
+        P.Hierarchy.setup_elements(prob.n + 1, prob.elem_ptr, prob.elem_dofs, prob.blocks)
+    agg = prob.agg_of_dof.copy()
+    agg[agg == 0] = 7 + agg.max()           # leaves id 0 unused
+    with pytest.raises(P.LsddError, match="aggregate ids"):
+        P.Hierarchy.setup_elements(prob.n, prob.elem_ptr, prob.elem_dofs, prob.blocks, prob.node_of_dof, agg)
