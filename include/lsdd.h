@@ -122,6 +122,26 @@ lsdd_status lsdd_setup_gram_csr(int64_t m, int64_t n, const int64_t* rowptr, con
 lsdd_status lsdd_solve(lsdd_hierarchy* h, const double* b, double* x, int32_t nrhs,
                        void* hip_stream, lsdd_info* info);
 
+/* Switch the cycle precision of an existing hierarchy: 0 = FP64 cycle,
+ * 1 = FP32 cycle (the hierarchy must have been set up with precision = 1, which
+ * keeps FP32 copies of the cycle's operators next to the FP64 ones). */
+lsdd_status lsdd_set_cycle_precision(lsdd_hierarchy* h, int32_t precision);
+
+/* Change the PCG stopping tolerance and iteration cap of an existing hierarchy. */
+lsdd_status lsdd_set_solve_params(lsdd_hierarchy* h, double rtol, int32_t max_iter);
+
+/* Per-kernel timing: on != 0 clears the counters and records a pair of HIP
+ * events on the solve stream around every launch of the traced kernel classes
+ * (sub_gemv, csr_resid_rows, csr_spmv, restrict, prolong, coarse_gemv,
+ * pcg_spmv); on = 0 stops recording.  lsdd_trace_get reads class idx
+ * (0-based; LSDD_E_INVAL past the end): name (host char[name_len]), launches,
+ * summed event time in ms and summed algorithmic bytes of those launches (the
+ * bytes each launch must move at minimum: matrix entries, indices and vector
+ * entries read or written once). */
+lsdd_status lsdd_trace(lsdd_hierarchy* h, int32_t on);
+lsdd_status lsdd_trace_get(lsdd_hierarchy* h, int32_t idx, char* name, int32_t name_len, int64_t* launches,
+                           double* ms, double* bytes);
+
 /* Apply the preconditioner once: z = V(r) (the symmetric V-cycle of Sec. 2 with
  * forward multiplicative Schwarz pre-smoothing and reverse-order post-smoothing).
  *   r, z   device, float64[n] */

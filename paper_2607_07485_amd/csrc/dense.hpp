@@ -283,3 +283,325 @@ __device__ inline void wg_sort_eig(const double* a, int lda, const double* v, in
 }
 
 }  // namespace lsdd
+
+namespace lsdd {
+
+// ---------------------------------------------------------------- interface elimination
+
+// Schur complement onto the leading nw indices of a symmetric PSD m x m matrix
+// `a` (column-major, ld m) by diagonally pivoted elimination of the trailing
+// ng = m - nw (interface) indices: the largest remaining interface diagonal is
+// eliminated while it exceeds `tol`; the leading block of the updated matrix is
+// then S = A_ww - A_wP A_PP^{-1} A_Pw over the eliminated set P, a generalized
+// inverse of the interface block (the Moore-Penrose Schur complement when the
+// remaining interface part is zero).  LDS scratch: col (m doubles), done (m
+// chars), rv/ri (LSDD_WG/64 each).  Returns the number of eliminated indices.
+__device__ inline int wg_schur_pivoted(double* a, int m, int nw, double tol, double* col, unsigned char* done,
+                                       double* rv, int* ri) {
+    for (int i = tid(); i < m; i += LSDD_WG) done[i] = 0;
+    __syncthreads();
+    int npiv = 0;
+    while (true) {
+        // argmax of the remaining interface diagonal
+        double bv = -1.0;
+        int bi = -1;
+        for (int i = nw + tid(); i < m; i += LSDD_WG) {
+            if (done[i]) continue;
+            double d = a[i + (long long)i * m];
+            if (d > bv) { bv = d; bi = i; }
+        }
+        for (int off = 32; off > 0; off >>= 1) {
+            double ov = __shfl_xor(bv, off, 64);
+            int oi = __shfl_xor(bi, off, 64);
+            if (ov > bv || (ov == bv && oi >= 0 && (bi < 0 || oi < bi))) { bv = ov; bi = oi; }
+        }
+        if ((tid() & 63) == 0) { rv[tid() >> 6] = bv; ri[tid() >> 6] = bi; }
+        __syncthreads();
+        bv = rv[0];
+        bi = ri[0];
+        for (int w = 1; w < LSDD_WG / 64; ++w)
+            if (rv[w] > bv || (rv[w] == bv && ri[w] >= 0 && (bi < 0 || ri[w] < bi))) { bv = rv[w]; bi = ri[w]; }
+        __syncthreads();
+        if (bi < 0 || !(bv > tol)) break;
+        const double s = 1.0 / sqrt(bv);
+        for (int i = tid(); i < m; i += LSDD_WG) col[i] = done[i] ? 0.0 : a[i + (long long)bi * m] * s;
+        __syncthreads();
+        if (tid() == 0) done[bi] = 1;
+        for (long long idx = tid(); idx < (long long)m * m; idx += LSDD_WG) {
+            int i = (int)(idx % m), k = (int)(idx / m);
+            double ci = col[i], ck = col[k];
+            if (ci != 0.0 && ck != 0.0) a[i + (long long)k * m] -= ci * ck;
+        }
+        __syncthreads();
+        ++npiv;
+    }
+    return npiv;
+}
+
+// ---------------------------------------------------------------- tridiagonal eigensolver
+
+// Householder reduction of the symmetric n x n matrix a (column-major, both
+// triangles, ld n) to tridiagonal form T = Q^T A Q.  Outputs d[n], e[n-1],
+// tau[n-2]; the Householder vector of step j is stored in a[j+2.., j] (its
+// leading entry 1 implicit).  LDS scratch: v, w (n doubles each), red.
+__device__ inline void wg_tridiag(double* a, int n, double* d, double* e, double* tau, double* v, double* w,
+                                  double* red) {
+    for (int j = 0; j + 2 < n; ++j) {
+        const int m = n - j - 1;
+        double* x = a + (j + 1) + (long long)j * n;           // a[j+1.., j]
+        double s2 = 0.0;
+        for (int i = 1 + tid(); i < m; i += LSDD_WG) s2 += x[i] * x[i];
+        s2 = wg_sum(s2, red);
+        const double alpha = x[0];
+        double t = 0.0, beta = alpha;
+        if (s2 > 0.0) {
+            double nrm = sqrt(alpha * alpha + s2);
+            beta = alpha >= 0.0 ? -nrm : nrm;
+            t = (beta - alpha) / beta;
+            const double sc = 1.0 / (alpha - beta);
+            for (int i = tid(); i < m; i += LSDD_WG) v[i] = (i == 0) ? 1.0 : x[i] * sc;
+        } else {
+            for (int i = tid(); i < m; i += LSDD_WG) v[i] = (i == 0) ? 1.0 : 0.0;
+        }
+        __syncthreads();
+        if (tid() == 0) {
+            d[j] = a[j + (long long)j * n];
+            e[j] = beta;
+            tau[j] = t;
+        }
+        if (t != 0.0) {
+            // p = t * A22 v  (A22 = a[j+1.., j+1..])
+            double* A22 = a + (j + 1) + (long long)(j + 1) * n;
+            for (int i = tid(); i < m; i += LSDD_WG) {
+                double s = 0.0;
+                for (int k = 0; k < m; ++k) s += A22[i + (long long)k * n] * v[k];
+                w[i] = t * s;
+            }
+            __syncthreads();
+            double pv = 0.0;
+            for (int i = tid(); i < m; i += LSDD_WG) pv += w[i] * v[i];
+            pv = wg_sum(pv, red);
+            const double K = 0.5 * t * pv;
+            for (int i = tid(); i < m; i += LSDD_WG) w[i] -= K * v[i];
+            __syncthreads();
+            for (long long idx = tid(); idx < (long long)m * m; idx += LSDD_WG) {
+                int i = (int)(idx % m), k = (int)(idx / m);
+                A22[i + (long long)k * n] -= v[i] * w[k] + w[i] * v[k];
+            }
+        }
+        // keep the reflector below the subdiagonal
+        for (int i = 1 + tid(); i < m; i += LSDD_WG) x[i] = v[i];
+        __syncthreads();
+    }
+    if (tid() == 0) {
+        if (n >= 2) {
+            d[n - 2] = a[(n - 2) + (long long)(n - 2) * n];
+            e[n - 2] = a[(n - 1) + (long long)(n - 2) * n];
+        }
+        d[n - 1] = a[(n - 1) + (long long)(n - 1) * n];
+    }
+    __syncthreads();
+}
+
+// Number of eigenvalues of the tridiagonal (d, e) smaller than x (Sturm count).
+__device__ inline int sturm_count(const double* d, const double* e, int n, double x, double pivmin) {
+    int c = 0;
+    double q = d[0] - x;
+    if (fabs(q) < pivmin) q = -pivmin;
+    if (q < 0.0) ++c;
+    for (int k = 1; k < n; ++k) {
+        q = d[k] - x - e[k - 1] * e[k - 1] / q;
+        if (fabs(q) < pivmin) q = -pivmin;
+        if (q < 0.0) ++c;
+    }
+    return c;
+}
+
+// All eigenvalues of the symmetric tridiagonal (d, e), ascending, by bisection.
+__device__ inline void wg_bisect_all(const double* d, const double* e, int n, double* lam, double* red) {
+    double lo = INFINITY, hi = -INFINITY, emax2 = 0.0;
+    for (int i = tid(); i < n; i += LSDD_WG) {
+        double r = (i > 0 ? fabs(e[i - 1]) : 0.0) + (i + 1 < n ? fabs(e[i]) : 0.0);
+        lo = fmin(lo, d[i] - r);
+        hi = fmax(hi, d[i] + r);
+        if (i + 1 < n) emax2 = fmax(emax2, e[i] * e[i]);
+    }
+    lo = -wg_max(-lo, red);
+    hi = wg_max(hi, red);
+    emax2 = wg_max(emax2, red);
+    const double tnorm = fmax(fabs(lo), fabs(hi));
+    const double pivmin = fmax(2.2250738585072014e-308 * fmax(emax2, 1.0), 1e-300);
+    const double atol = 2.0 * 2.220446049250313e-16 * tnorm + 1e-300;
+    lo -= atol;
+    hi += atol;
+    for (int i = tid(); i < n; i += LSDD_WG) {
+        double a = lo, b = hi;
+        for (int it = 0; it < 200; ++it) {
+            double mid = 0.5 * (a + b);
+            if (b - a <= 2.0 * 2.220446049250313e-16 * fmax(fabs(a), fabs(b)) + atol || mid == a || mid == b) break;
+            if (sturm_count(d, e, n, mid, pivmin) > i) b = mid;
+            else a = mid;
+        }
+        lam[i] = 0.5 * (a + b);
+    }
+    __syncthreads();
+}
+
+// Solve (T - lam I) y = b in place for the tridiagonal (d, e) by Gaussian
+// elimination with partial pivoting; scratch u0,u1,u2,l (n each), piv (n).
+__device__ inline void tri_shift_solve(const double* d, const double* e, int n, double lam, double* b, double* u0,
+                                       double* u1, double* u2, double* l, unsigned char* piv, double tiny) {
+    // factor: rows k hold (u0[k], u1[k], u2[k]) on diagonals 0, +1, +2
+    double a0 = d[0] - lam, a1 = (n > 1) ? e[0] : 0.0;
+    for (int k = 0; k < n - 1; ++k) {
+        double sub = e[k];
+        double nd = d[k + 1] - lam;
+        double ns = (k + 2 < n) ? e[k + 1] : 0.0;
+        if (fabs(a0) >= fabs(sub)) {
+            piv[k] = 0;
+            if (fabs(a0) < tiny) a0 = (a0 >= 0.0 ? tiny : -tiny);
+            u0[k] = a0; u1[k] = a1; u2[k] = 0.0;
+            double f = sub / a0;
+            l[k] = f;
+            a0 = nd - f * a1;
+            a1 = ns;
+        } else {
+            piv[k] = 1;
+            u0[k] = sub; u1[k] = nd; u2[k] = ns;
+            double f = a0 / sub;
+            l[k] = f;
+            a0 = a1 - f * nd;
+            a1 = -f * ns;
+        }
+    }
+    if (fabs(a0) < tiny) a0 = (a0 >= 0.0 ? tiny : -tiny);
+    u0[n - 1] = a0; u1[n - 1] = 0.0; u2[n - 1] = 0.0;
+    // forward
+    for (int k = 0; k < n - 1; ++k) {
+        if (piv[k]) { double t = b[k]; b[k] = b[k + 1]; b[k + 1] = t; }
+        b[k + 1] -= l[k] * b[k];
+    }
+    // backward
+    for (int k = n - 1; k >= 0; --k) {
+        double s = b[k];
+        if (k + 1 < n) s -= u1[k] * b[k + 1];
+        if (k + 2 < n) s -= u2[k] * b[k + 2];
+        b[k] = s / u0[k];
+    }
+}
+
+// Eigenvectors of the tridiagonal (d, e) for the eigenvalues lam[0..kk) by
+// inverse iteration.  Eigenvalues closer than 1e-4 * tnorm form a cluster.
+// Single-member clusters run one per thread (threads 0..63, each with a
+// scratch slot of 5n doubles in `ws`); the vectors of a larger cluster are
+// computed one after another by the whole workgroup, each orthogonalised
+// against the earlier members by classical Gram-Schmidt applied twice.
+// Output V (n x kk, column-major, ld n).  LDS: cl_start (kk+1 ints) and
+// dots (kk doubles).
+__device__ inline void wg_inverse_iteration(const double* d, const double* e, int n, const double* lam, int kk,
+                                            double* V, double* ws, double tnorm, int* cl_start, double* dots,
+                                            double* red, int* ncl_sh) {
+    const double eps = 2.220446049250313e-16;
+    const double gaptol = 1e-4 * tnorm;
+    if (tid() == 0) {
+        int nc = 0;
+        for (int i = 0; i < kk; ++i)
+            if (i == 0 || lam[i] - lam[i - 1] > gaptol) cl_start[nc++] = i;
+        cl_start[nc] = kk;
+        *ncl_sh = nc;
+    }
+    __syncthreads();
+    const int ncl = *ncl_sh;
+    const double tiny = eps * fmax(tnorm, 1e-300);
+    auto start_vector = [&](double* y, int i, int k) {
+        unsigned h = (unsigned)(k * 2654435761u) ^ (unsigned)(i * 40503u);
+        y[k] = 1.0 + 0.25 * ((double)(h & 0xffff) / 65536.0 - 0.5);
+    };
+    // singletons, one per thread
+    for (int c = tid(); tid() < 64 && c < ncl; c += 64) {
+        const int i = cl_start[c];
+        if (cl_start[c + 1] - i != 1) continue;
+        double* u0 = ws + (long long)tid() * 5 * n;
+        double* u1 = u0 + n;
+        double* u2 = u1 + n;
+        double* l = u2 + n;
+        unsigned char* piv = (unsigned char*)(l + n);
+        double* y = V + (long long)i * n;
+        for (int k = 0; k < n; ++k) start_vector(y, i, k);
+        for (int it = 0; it < 4; ++it) {
+            tri_shift_solve(d, e, n, lam[i], y, u0, u1, u2, l, piv, tiny);
+            double nr = 0.0;
+            for (int k = 0; k < n; ++k) nr += y[k] * y[k];
+            nr = 1.0 / sqrt(nr);
+            for (int k = 0; k < n; ++k) y[k] *= nr;
+        }
+    }
+    __syncthreads();
+    // clusters, by the whole workgroup
+    for (int c = 0; c < ncl; ++c) {
+        const int c0 = cl_start[c], c1 = cl_start[c + 1];
+        if (c1 - c0 == 1) continue;
+        double* u0 = ws;
+        double* u1 = u0 + n;
+        double* u2 = u1 + n;
+        double* l = u2 + n;
+        unsigned char* piv = (unsigned char*)(l + n);
+        for (int i = c0; i < c1; ++i) {
+            double* y = V + (long long)i * n;
+            for (int k = tid(); k < n; k += LSDD_WG) start_vector(y, i, k);
+            __syncthreads();
+            const double shift = lam[i] + (i - c0) * 2.0 * tiny;
+            for (int it = 0; it < 4; ++it) {
+                if (tid() == 0) tri_shift_solve(d, e, n, shift, y, u0, u1, u2, l, piv, tiny);
+                __syncthreads();
+                for (int pass = 0; pass < 2; ++pass) {
+                    for (int j = c0 + tid(); j < i; j += LSDD_WG) {
+                        const double* q = V + (long long)j * n;
+                        double s = 0.0;
+                        for (int k = 0; k < n; ++k) s += q[k] * y[k];
+                        dots[j - c0] = s;
+                    }
+                    __syncthreads();
+                    for (int k = tid(); k < n; k += LSDD_WG) {
+                        double s = 0.0;
+                        for (int j = c0; j < i; ++j) s += V[(long long)j * n + k] * dots[j - c0];
+                        y[k] -= s;
+                    }
+                    __syncthreads();
+                }
+                double nr = 0.0;
+                for (int k = tid(); k < n; k += LSDD_WG) nr += y[k] * y[k];
+                nr = wg_sum(nr, red);
+                const double sc = 1.0 / sqrt(nr);
+                for (int k = tid(); k < n; k += LSDD_WG) y[k] *= sc;
+                __syncthreads();
+            }
+        }
+    }
+}
+
+// V <- Q V with Q = H_0 ... H_{n-3} from wg_tridiag (reflectors in a, tau).
+__device__ inline void wg_tridiag_backtransform(const double* a, int n, const double* tau, double* V, int kk,
+                                                double* vbuf, double* dots) {
+    for (int j = n - 3; j >= 0; --j) {
+        const double t = tau[j];
+        if (t == 0.0) continue;
+        const int m = n - j - 1;
+        for (int i = tid(); i < m; i += LSDD_WG) vbuf[i] = (i == 0) ? 1.0 : a[(j + 1 + i) + (long long)j * n];
+        __syncthreads();
+        for (int c = tid(); c < kk; c += LSDD_WG) {
+            const double* col = V + (long long)c * n + j + 1;
+            double s = 0.0;
+            for (int i = 0; i < m; ++i) s += vbuf[i] * col[i];
+            dots[c] = t * s;
+        }
+        __syncthreads();
+        for (long long idx = tid(); idx < (long long)m * kk; idx += LSDD_WG) {
+            int i = (int)(idx % m), c = (int)(idx / m);
+            V[(long long)c * n + j + 1 + i] -= dots[c] * vbuf[i];
+        }
+        __syncthreads();
+    }
+}
+
+}  // namespace lsdd

@@ -12,6 +12,7 @@
 #include <cfloat>
 #include <cmath>
 
+#include "batched.hpp"
 #include "dense.hpp"
 #include "kernels.hpp"
 
@@ -162,7 +163,7 @@ __global__ void __launch_bounds__(WG) k_assemble_csr(const int64_t* elem_ptr, co
 // (eq. SPSD_splitting under structural support) and A_Omega = A[Omega, Omega].
 __global__ void __launch_bounds__(WG) k_local_assemble(LocalArgs A) {
     const int b = blockIdx.x;
-    const int ag = A.first + b;
+    const int ag = A.agg_list ? A.agg_list[b] : A.first + b;
     const int64_t s0 = A.sub_ptr[ag];
     const int m = (int)(A.sub_ptr[ag + 1] - s0);
     const int nw = (int)(A.agg_ptr[ag + 1] - A.agg_ptr[ag]);
@@ -193,124 +194,44 @@ __global__ void __launch_bounds__(WG) k_local_assemble(LocalArgs A) {
     __syncthreads();
 }
 
-// Per aggregate: Schur complement S~ (eq. gep_reduced), Cholesky of A_Omega
-// (its leading block is chol(A_ww)), C = L^{-1} S~ L^{-T}, Jacobi eigenpairs,
-// retained modes (eq. tau-cut, cluster completion), Z = L^{-T} V_k, and the
-// subdomain inverse A_Omega^{-1} for the Schwarz smoother.
-__global__ void __launch_bounds__(WG) k_local_solve(LocalArgs A) {
+// Per aggregate: eigenpairs of C = L^{-1} S~ L^{-T} (held in the S buffer):
+// Jacobi for small aggregates, otherwise Householder tridiagonalisation +
+// bisection for all eigenvalues + inverse iteration for the retained vectors
+// only; then the retained-mode count (eq. tau-cut with cluster completion).
+// Writes mu (ascending, clamped at 0), k, and the first k eigenvectors of C into
+// W1 (nw x k, ld nw).
+__global__ void __launch_bounds__(WG) k_local_eig(LocalArgs A) {
     __shared__ double s_red[WG / 64];
-    __shared__ double s_sh[2];
     __shared__ int s_flag;
     __shared__ int s_k;
-    extern __shared__ char s_dyn[];   // pairs (int[2*np]), cs (double[2*np]), rank (int[nw])
+    __shared__ int s_ncl;
+    extern __shared__ double s_dyn[];
     const int b = blockIdx.x;
     const int ag = A.first + b;
-    const int m = (int)(A.sub_ptr[ag + 1] - A.sub_ptr[ag]);
     const int nw = (int)(A.agg_ptr[ag + 1] - A.agg_ptr[ag]);
-    const int ng = m - nw;
     double* W1 = A.w1 + A.ws_off[b];
-    double* W2 = A.w2 + A.ws_off[b];
     double* S = A.s_buf + A.sq_off[b];
     double* V = A.v_buf + A.sq_off[b];
-    const int npair = (nw + 1) / 2;
-    int* pairs = (int*)s_dyn;
-    double* cs = (double*)(s_dyn + ((2 * npair * sizeof(int) + 15) / 16) * 16);
-    int* rank = (int*)((char*)cs + 2 * npair * sizeof(double));
-
-    // ---- Schur complement onto omega
-    if (ng == 0) {
-        for (int idx = tid(); idx < nw * nw; idx += WG) {
-            int i = idx % nw, j = idx / nw;
-            S[i + (int64_t)j * nw] = W1[i + (int64_t)j * m];
-        }
-        __syncthreads();
-    } else if (A.schur_mode == 0) {
-        double* G = W1 + nw + (int64_t)nw * m;      // A~_GG
-        double dmax = 0.0;
-        for (int i = tid(); i < ng; i += WG) dmax = fmax(dmax, G[i + (int64_t)i * m]);
-        dmax = wg_max(dmax, s_red);
-        double dmin = wg_potrf(G, m, ng, s_sh);
-        if (!(dmin > ng * DBL_EPSILON * dmax)) {
-            if (tid() == 0) A.status[ag] = 1;
-            return;
-        }
-        double* Wg = W1 + nw;                        // A~_Gw (ng x nw), ld m
-        wg_trsm_lower(G, m, ng, Wg, m, nw);          // W = L_G^{-1} A~_Gw
-        for (int idx = tid(); idx < nw * nw; idx += WG) {
-            int i = idx % nw, j = idx / nw;
-            if (i > j) continue;
-            const double* ci = Wg + (int64_t)i * m;
-            const double* cj = Wg + (int64_t)j * m;
-            double s = 0.0;
-            for (int t = 0; t < ng; ++t) s += ci[t] * cj[t];
-            double val = 0.5 * (W1[i + (int64_t)j * m] + W1[j + (int64_t)i * m]) - s;
-            S[i + (int64_t)j * nw] = val;
-            S[j + (int64_t)i * nw] = val;
-        }
-        __syncthreads();
-    } else {
-        // pseudo-inverse route: A~_GG = U diag(d) U^T, keep d > ng eps d_max
-        double* G = W1 + nw + (int64_t)nw * m;
-        double* U = A.w3 + A.w3_off[b];
-        double* Y = U + (int64_t)ng * ng;           // ng x nw: d^{-1/2} U^T A~_Gw
-        int* pr = (int*)s_dyn;                      // scratch sized for max(nw, ng) pairs by host
-        double* c2 = (double*)(s_dyn + ((2 * ((ng + 1) / 2) * sizeof(int) + 15) / 16) * 16);
-        double scale = 0.0;
-        for (int i = tid(); i < ng; i += WG) scale = fmax(scale, fabs(G[i + (int64_t)i * m]));
-        scale = wg_max(scale, s_red);
-        wg_identity(U, ng, ng);
-        wg_jacobi(G, m, ng, U, ng, 60, 1e-15, 1e-18 * scale, pr, c2, &s_flag);
-        double dmax = 0.0;
-        for (int i = tid(); i < ng; i += WG) dmax = fmax(dmax, G[i + (int64_t)i * m]);
-        dmax = wg_max(dmax, s_red);
-        const double tol = ng * DBL_EPSILON * dmax;
-        const double* AGw = W1 + nw;
-        for (int idx = tid(); idx < ng * nw; idx += WG) {
-            int t = idx % ng, j = idx / ng;
-            double d = G[t + (int64_t)t * m];
-            double s = 0.0;
-            if (d > tol && dmax > 0.0) {
-                for (int g = 0; g < ng; ++g) s += U[g + (int64_t)t * ng] * AGw[g + (int64_t)j * m];
-                s /= sqrt(d);
-            }
-            Y[t + (int64_t)j * ng] = s;
-        }
-        __syncthreads();
-        for (int idx = tid(); idx < nw * nw; idx += WG) {
-            int i = idx % nw, j = idx / nw;
-            if (i > j) continue;
-            double s = 0.0;
-            for (int t = 0; t < ng; ++t) s += Y[t + (int64_t)i * ng] * Y[t + (int64_t)j * ng];
-            double val = 0.5 * (W1[i + (int64_t)j * m] + W1[j + (int64_t)i * m]) - s;
-            S[i + (int64_t)j * nw] = val;
-            S[j + (int64_t)i * nw] = val;
-        }
-        __syncthreads();
-    }
-
-    // ---- Cholesky of A_Omega (leading nw block = chol(A_ww))
-    double dmin = wg_potrf(W2, m, m, s_sh);
-    if (!(dmin > 0.0)) {
-        if (tid() == 0) A.status[ag] = 2;
-        return;
-    }
-    // ---- C = L^{-1} S~ L^{-T}
-    wg_trsm_lower(W2, m, nw, S, nw, nw);
-    wg_transpose(S, nw, nw);
-    wg_trsm_lower(W2, m, nw, S, nw, nw);
-    wg_symmetrize(S, nw, nw);
-    // ---- eigenpairs of C (mu ascending)
-    double scale = 0.0;
-    for (int i = tid(); i < nw; i += WG) scale = fmax(scale, fabs(S[i + (int64_t)i * nw]));
-    scale = wg_max(scale, s_red);
-    wg_identity(V, nw, nw);
-    wg_jacobi(S, nw, nw, V, nw, 60, 1e-15, 1e-18 * fmax(scale, 1e-300), pairs, cs, &s_flag);
+    double* T = A.t_buf + A.t_off[b];
     double* mu = A.mu + A.mu_off[ag];
-    double* VS = W1;                                 // sorted eigenvectors, nw x nw, ld nw
-    wg_sort_eig(S, nw, V, nw, nw, mu, VS, nw, rank);
+    double* VS = W1;
+    const bool small = nw <= 32;
+    if (small) {
+        int* pairs = (int*)s_dyn;
+        double* cs = s_dyn + 32;
+        int* rank = (int*)(s_dyn + 64);
+        double scale = 0.0;
+        for (int i = tid(); i < nw; i += WG) scale = fmax(scale, fabs(S[i + (int64_t)i * nw]));
+        scale = wg_max(scale, s_red);
+        wg_identity(V, nw, nw);
+        wg_jacobi(S, nw, nw, V, nw, 60, 1e-15, 1e-18 * fmax(scale, 1e-300), pairs, cs, &s_flag);
+        wg_sort_eig(S, nw, V, nw, nw, mu, VS, nw, rank);
+    } else {
+        wg_tridiag(S, nw, T, T + nw, T + 2 * nw, s_dyn, s_dyn + nw, s_red);
+        wg_bisect_all(T, T + nw, nw, mu, s_red);
+    }
     for (int i = tid(); i < nw; i += WG) mu[i] = fmax(mu[i], 0.0);
     __syncthreads();
-    // ---- retained modes
     if (tid() == 0) {
         int k;
         if (A.modes_fixed > 0) {
@@ -325,23 +246,66 @@ __global__ void __launch_bounds__(WG) k_local_solve(LocalArgs A) {
     }
     __syncthreads();
     const int k = s_k;
-    // ---- Z = L_ww^{-T} V_k (A_ww-orthonormal), staged row-major nw x k
-    if (k > 0) {
-        wg_trsm_lower_t(W2, m, nw, VS, nw, k);
-        double* zs = A.zst + A.zst_off[ag];
-        for (int idx = tid(); idx < nw * k; idx += WG) {
-            int i = idx / k, s = idx % k;
-            zs[idx] = VS[i + (int64_t)s * nw];
-        }
-        __syncthreads();
+    if (!small && k > 0) {
+        const double* d = T;
+        const double* e = T + nw;
+        double tnorm = 0.0;
+        for (int i = tid(); i < nw; i += WG)
+            tnorm = fmax(tnorm, fabs(d[i]) + (i > 0 ? fabs(e[i - 1]) : 0.0) + (i + 1 < nw ? fabs(e[i]) : 0.0));
+        tnorm = wg_max(tnorm, s_red);
+        wg_inverse_iteration(d, e, nw, mu, k, VS, T + 3 * nw, fmax(tnorm, 1e-300), (int*)s_dyn, s_dyn + 2048, s_red,
+                             &s_ncl);
+        wg_tridiag_backtransform(S, nw, T + 2 * nw, VS, k, s_dyn, s_dyn + nw);
     }
-    // ---- subdomain inverse A_Omega^{-1} = L^{-T} L^{-1}
-    double* X = A.inv + A.inv_off[ag];
-    wg_identity(X, m, m);
-    wg_trsm_lower(W2, m, m, X, m, m);
-    wg_trsm_lower_t(W2, m, m, X, m, m);
-    wg_symmetrize(X, m, m);
-    if (tid() == 0) A.status[ag] = 0;
+}
+
+// Z_i staged row-major (nw x k) from the column-major vectors in W1.
+__global__ void k_stage_z(LocalArgs A) {
+    const int b = blockIdx.x;
+    const int ag = A.first + b;
+    const int nw = (int)(A.agg_ptr[ag + 1] - A.agg_ptr[ag]);
+    const int k = A.k_out[ag];
+    const double* VS = A.w1 + A.ws_off[b];
+    double* zs = A.zst + A.zst_off[ag];
+    for (int idx = tid(); idx < nw * k; idx += WG) {
+        int i = idx / k, s = idx % k;
+        zs[idx] = VS[i + (int64_t)s * nw];
+    }
+}
+
+// Small per-view helpers for the batched pipeline.
+__global__ void k_views_max_diag(const double* base, const View* v, double* out) {
+    __shared__ double red[WG / 64];
+    const View x = v[blockIdx.x];
+    double m = 0.0;
+    for (int i = tid(); i < x.rows; i += WG) m = fmax(m, base[x.off + i + (int64_t)i * x.ld]);
+    m = wg_max(m, red);
+    if (tid() == 0) out[blockIdx.x] = m;
+}
+__global__ void k_views_add_diag(double* base, const View* v, const double* delta) {
+    const View x = v[blockIdx.x];
+    const double d = delta[blockIdx.x];
+    for (int i = tid(); i < x.rows; i += WG) base[x.off + i + (int64_t)i * x.ld] += d;
+}
+__global__ void k_views_symmetrize(double* base, const View* v) {
+    const View x = v[blockIdx.y];
+    const int64_t n = x.rows;
+    for (int64_t idx = (int64_t)blockIdx.x * WG + tid(); idx < n * n; idx += (int64_t)gridDim.x * WG) {
+        int64_t i = idx % n, j = idx / n;
+        if (i < j) {
+            double s = 0.5 * (base[x.off + i + j * x.ld] + base[x.off + j + i * x.ld]);
+            base[x.off + i + j * x.ld] = s;
+            base[x.off + j + i * x.ld] = s;
+        }
+    }
+}
+__global__ void k_views_identity(double* base, const View* v) {
+    const View x = v[blockIdx.y];
+    const int64_t n = x.rows;
+    for (int64_t idx = (int64_t)blockIdx.x * WG + tid(); idx < n * n; idx += (int64_t)gridDim.x * WG) {
+        int64_t i = idx % n, j = idx / n;
+        base[x.off + i + j * x.ld] = (i == j) ? 1.0 : 0.0;
+    }
 }
 
 __global__ void k_z_compact(const int64_t* agg_ptr, const int32_t* k, const int64_t* zst_off, const double* zst,
@@ -445,6 +409,177 @@ __global__ void __launch_bounds__(WG) k_dense_chol_inv(int n, double* W, double*
     wg_trsm_lower_t(W, n, n, inv, n, n);
     wg_symmetrize(inv, n, n);
     if (tid() == 0) *status = 0;
+}
+
+// ---------------------------------------------------------------- blocked dense Cholesky / inverse
+// Column-major n x n matrix, 32 x 32 tiles staged in LDS.  Used for the
+// coarsest level, where one matrix is large enough to fill the device.
+
+constexpr int TB = 32;
+
+__device__ inline void load_tile(double (*t)[TB + 1], const double* A, int n, int r0, int c0) {
+    for (int idx = tid(); idx < TB * TB; idx += WG) {
+        int i = idx % TB, j = idx / TB;
+        int r = r0 + i, c = c0 + j;
+        t[i][j] = (r < n && c < n) ? A[r + (int64_t)c * n] : 0.0;
+    }
+}
+
+// Cholesky of the diagonal tile kb (unblocked, in LDS).
+__global__ void __launch_bounds__(WG) k_potrf_tile(double* A, int n, int kb, int32_t* status) {
+    __shared__ double t[TB][TB + 1];
+    const int r0 = kb * TB;
+    const int nb = min(TB, n - r0);
+    load_tile(t, A, n, r0, r0);
+    __syncthreads();
+    for (int j = 0; j < nb; ++j) {
+        if (tid() == 0) {
+            double d = t[j][j];
+            if (!(d > 0.0)) *status = 2;
+            t[j][j] = d > 0.0 ? sqrt(d) : 1.0;
+        }
+        __syncthreads();
+        const double s = t[j][j];
+        for (int i = j + 1 + tid(); i < nb; i += WG) t[i][j] /= s;
+        __syncthreads();
+        for (int idx = tid(); idx < nb * nb; idx += WG) {
+            int i = idx % nb, k = idx / nb;
+            if (i > j && k > j && i >= k) t[i][k] -= t[i][j] * t[k][j];
+        }
+        __syncthreads();
+    }
+    for (int idx = tid(); idx < nb * nb; idx += WG) {
+        int i = idx % nb, j = idx / nb;
+        if (i >= j) A[(r0 + i) + (int64_t)(r0 + j) * n] = t[i][j];
+    }
+}
+
+// Panel: L_ib,kb = A_ib,kb L_kk^{-T} for ib = kb+1+blockIdx.x.
+__global__ void __launch_bounds__(WG) k_trsm_tile(double* A, int n, int kb) {
+    __shared__ double L[TB][TB + 1];
+    __shared__ double X[TB][TB + 1];
+    const int ib = kb + 1 + blockIdx.x;
+    const int r0 = ib * TB, c0 = kb * TB;
+    const int nb = min(TB, n - c0);
+    load_tile(L, A, n, c0, c0);
+    load_tile(X, A, n, r0, c0);
+    __syncthreads();
+    // rows of X are independent: x L^T = a  (forward over columns)
+    const int r = tid() % TB, part = tid() / TB;     // 8 threads per row cooperate on nothing; row owner = part 0
+    if (part == 0 && r0 + r < n) {
+        for (int j = 0; j < nb; ++j) {
+            double s = X[r][j];
+            for (int t = 0; t < j; ++t) s -= X[r][t] * L[j][t];
+            X[r][j] = s / L[j][j];
+        }
+    }
+    __syncthreads();
+    for (int idx = tid(); idx < TB * TB; idx += WG) {
+        int i = idx % TB, j = idx / TB;
+        if (r0 + i < n && c0 + j < n) A[(r0 + i) + (int64_t)(c0 + j) * n] = X[i][j];
+    }
+}
+
+// Trailing update A_ij -= L_ik L_jk^T over tiles kb < jb <= ib (lower part).
+__global__ void __launch_bounds__(WG) k_syrk_tile(double* A, int n, int kb, int nt) {
+    __shared__ double Li[TB][TB + 1];
+    __shared__ double Lj[TB][TB + 1];
+    // map blockIdx.x to (ib, jb) with kb < jb <= ib < nt
+    int t = blockIdx.x;
+    int m = nt - kb - 1;
+    int jj = 0;
+    while (t >= m - jj) { t -= m - jj; ++jj; }
+    const int jb = kb + 1 + jj, ib = jb + t;
+    load_tile(Li, A, n, ib * TB, kb * TB);
+    load_tile(Lj, A, n, jb * TB, kb * TB);
+    __syncthreads();
+    for (int idx = tid(); idx < TB * TB; idx += WG) {
+        int i = idx % TB, j = idx / TB;
+        int r = ib * TB + i, c = jb * TB + j;
+        if (r < n && c < n && r >= c) {
+            double s = 0.0;
+            for (int k = 0; k < TB; ++k) s += Li[i][k] * Lj[j][k];
+            A[r + (int64_t)c * n] -= s;
+        }
+    }
+}
+
+// W <- L^{-1} W for block row kb of the forward substitution (W starts as I):
+// step 1 solves the diagonal block for every tile column jb <= kb.
+__global__ void __launch_bounds__(WG) k_trinv_diag(const double* Lm, double* W, int n, int kb) {
+    __shared__ double L[TB][TB + 1];
+    __shared__ double B[TB][TB + 1];
+    const int jb = blockIdx.x;          // 0..kb
+    const int r0 = kb * TB, c0 = jb * TB;
+    const int nb = min(TB, n - r0);
+    load_tile(L, Lm, n, r0, r0);
+    load_tile(B, W, n, r0, c0);
+    __syncthreads();
+    const int c = tid() % TB, part = tid() / TB;
+    if (part == 0) {
+        for (int i = 0; i < nb; ++i) {
+            double s = B[i][c];
+            for (int t = 0; t < i; ++t) s -= L[i][t] * B[t][c];
+            B[i][c] = s / L[i][i];
+        }
+    }
+    __syncthreads();
+    for (int idx = tid(); idx < TB * TB; idx += WG) {
+        int i = idx % TB, j = idx / TB;
+        if (r0 + i < n && c0 + j < n) W[(r0 + i) + (int64_t)(c0 + j) * n] = B[i][j];
+    }
+}
+
+// step 2: W_ib,jb -= L_ib,kb W_kb,jb for ib > kb, jb <= kb.
+__global__ void __launch_bounds__(WG) k_trinv_update(const double* Lm, double* W, int n, int kb, int nt) {
+    __shared__ double L[TB][TB + 1];
+    __shared__ double Y[TB][TB + 1];
+    const int ib = kb + 1 + blockIdx.x % (nt - kb - 1);
+    const int jb = blockIdx.x / (nt - kb - 1);
+    load_tile(L, Lm, n, ib * TB, kb * TB);
+    load_tile(Y, W, n, kb * TB, jb * TB);
+    __syncthreads();
+    for (int idx = tid(); idx < TB * TB; idx += WG) {
+        int i = idx % TB, j = idx / TB;
+        int r = ib * TB + i, c = jb * TB + j;
+        if (r < n && c < n) {
+            double s = 0.0;
+            for (int k = 0; k < TB; ++k) s += L[i][k] * Y[k][j];
+            W[r + (int64_t)c * n] -= s;
+        }
+    }
+}
+
+// X = W^T W for W = L^{-1} (lower triangular): tile (ib, jb), ib >= jb, both halves written.
+__global__ void __launch_bounds__(WG) k_wtw(const double* W, double* X, int n, int nt) {
+    __shared__ double Wi[TB][TB + 1];
+    __shared__ double Wj[TB][TB + 1];
+    int t = blockIdx.x, ib = 0;
+    while (t > ib) { t -= ib + 1; ++ib; }
+    const int jb = t;   // jb <= ib
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int kb = ib; kb < nt; ++kb) {
+        load_tile(Wi, W, n, kb * TB, ib * TB);
+        load_tile(Wj, W, n, kb * TB, jb * TB);
+        __syncthreads();
+        for (int q = 0; q < 4; ++q) {
+            int idx = tid() + q * WG;
+            int i = idx % TB, j = idx / TB;
+            double s = 0.0;
+            for (int k = 0; k < TB; ++k) s += Wi[k][i] * Wj[k][j];
+            acc[q] += s;
+        }
+        __syncthreads();
+    }
+    for (int q = 0; q < 4; ++q) {
+        int idx = tid() + q * WG;
+        int i = idx % TB, j = idx / TB;
+        int r = ib * TB + i, c = jb * TB + j;
+        if (r < n && c < n) {
+            X[r + (int64_t)c * n] = acc[q];
+            X[c + (int64_t)r * n] = acc[q];
+        }
+    }
 }
 
 // ====================================================================== conversions
@@ -615,6 +750,10 @@ __global__ void k_update_p(int64_t n, const double* s_num, const double* s_den, 
     for (int64_t i = blockIdx.x * (int64_t)WG + tid(); i < n; i += (int64_t)gridDim.x * WG) p[i] = z[i] + beta * p[i];
 }
 
+__global__ void k_set_identity(int64_t n, double* a) {
+    for (int64_t i = blockIdx.x * (int64_t)WG + tid(); i < n; i += (int64_t)gridDim.x * WG) a[i + i * n] = 1.0;
+}
+
 __global__ void k_copy(int64_t n, const double* a, double* b) {
     for (int64_t i = blockIdx.x * (int64_t)WG + tid(); i < n; i += (int64_t)gridDim.x * WG) b[i] = a[i];
 }
@@ -650,12 +789,29 @@ void launch_local_assemble(int32_t nbatch, const LocalArgs& a, hipStream_t st) {
     hipLaunchKernelGGL(k_local_assemble, dim3(nbatch), dim3(WG), 0, st, a);
 }
 
-void launch_local_solve(int32_t nbatch, const LocalArgs& a, hipStream_t st) {
+void launch_local_eig(int32_t nbatch, const LocalArgs& a, hipStream_t st) {
     if (nbatch <= 0) return;
-    // dynamic LDS: Jacobi pairs and rotations for blocks of up to 2048 rows
-    // (aggregates and, in the pseudo-inverse route, interfaces) + the sort ranks
-    size_t lds = 16 + 1024 * 2 * sizeof(int) + 1024 * 2 * sizeof(double) + 2048 * sizeof(int);
-    hipLaunchKernelGGL(k_local_solve, dim3(nbatch), dim3(WG), lds, st, a);
+    // dynamic LDS: tridiagonal work vectors, cluster starts and dots (|omega| <= 2048)
+    size_t lds = 4096 * sizeof(double);
+    hipLaunchKernelGGL(k_local_eig, dim3(nbatch), dim3(WG), lds, st, a);
+}
+
+void launch_stage_z(int32_t nbatch, const LocalArgs& a, hipStream_t st) {
+    if (nbatch <= 0) return;
+    hipLaunchKernelGGL(k_stage_z, dim3(nbatch), dim3(WG), 0, st, a);
+}
+
+void launch_views_max_diag(int32_t nv, const double* base, const View* v, double* out, hipStream_t st) {
+    if (nv > 0) hipLaunchKernelGGL(k_views_max_diag, dim3(nv), dim3(WG), 0, st, base, v, out);
+}
+void launch_views_add_diag(int32_t nv, double* base, const View* v, const double* delta, hipStream_t st) {
+    if (nv > 0) hipLaunchKernelGGL(k_views_add_diag, dim3(nv), dim3(WG), 0, st, base, v, delta);
+}
+void launch_views_symmetrize(int32_t nv, double* base, const View* v, hipStream_t st) {
+    if (nv > 0) hipLaunchKernelGGL(k_views_symmetrize, dim3(64, nv), dim3(WG), 0, st, base, v);
+}
+void launch_views_identity(int32_t nv, double* base, const View* v, hipStream_t st) {
+    if (nv > 0) hipLaunchKernelGGL(k_views_identity, dim3(256, nv), dim3(WG), 0, st, base, v);
 }
 
 void launch_z_compact(int32_t n_agg, const int64_t* agg_ptr, const int32_t* k, const int64_t* zst_off, const double* zst,
@@ -675,7 +831,34 @@ void launch_dense_from_csr(int64_t n, const int64_t* rowptr, const int32_t* col,
 }
 
 void launch_dense_chol_inv(int64_t n, double* W, double* inv, int32_t* status, hipStream_t st) {
-    hipLaunchKernelGGL(k_dense_chol_inv, dim3(1), dim3(WG), 0, st, (int)n, W, inv, status);
+    if (n <= 256) {
+        hipLaunchKernelGGL(k_dense_chol_inv, dim3(1), dim3(WG), 0, st, (int)n, W, inv, status);
+        return;
+    }
+    // blocked: W <- chol(W) (lower), inv <- L^{-1} (forward substitution on I), then inv^T inv
+    const int nn = (int)n;
+    const int nt = (nn + TB - 1) / TB;
+    hipMemsetAsync(status, 0, sizeof(int32_t), st);
+    for (int kb = 0; kb < nt; ++kb) {
+        hipLaunchKernelGGL(k_potrf_tile, dim3(1), dim3(WG), 0, st, W, nn, kb, status);
+        const int below = nt - kb - 1;
+        if (below > 0) {
+            hipLaunchKernelGGL(k_trsm_tile, dim3(below), dim3(WG), 0, st, W, nn, kb);
+            hipLaunchKernelGGL(k_syrk_tile, dim3(below * (below + 1) / 2), dim3(WG), 0, st, W, nn, kb, nt);
+        }
+    }
+    double* Linv = inv;   // reuse the output as the L^{-1} workspace, then form the product into W
+    hipLaunchKernelGGL(k_zero<double>, dim3(grid_for(n * n)), dim3(WG), 0, st, n * n, Linv);
+    hipLaunchKernelGGL(k_set_identity, dim3(grid_for(n)), dim3(WG), 0, st, n, Linv);
+    for (int kb = 0; kb < nt; ++kb) {
+        hipLaunchKernelGGL(k_trinv_diag, dim3(kb + 1), dim3(WG), 0, st, W, Linv, nn, kb);
+        const int below = nt - kb - 1;
+        if (below > 0)
+            hipLaunchKernelGGL(k_trinv_update, dim3(below * (kb + 1)), dim3(WG), 0, st, W, Linv, nn, kb, nt);
+    }
+    // W (the factor) is no longer needed: X = Linv^T Linv into W, then copy to inv
+    hipLaunchKernelGGL(k_wtw, dim3(nt * (nt + 1) / 2), dim3(WG), 0, st, Linv, W, nn, nt);
+    hipMemcpyAsync(inv, W, (size_t)n * n * sizeof(double), hipMemcpyDeviceToDevice, st);
 }
 
 void launch_to_f32(int64_t n, const double* a, float* b, hipStream_t st) {

@@ -5,11 +5,14 @@
 
 #include <cstdint>
 
+#include "batched.hpp"
+
 namespace lsdd {
 
 struct LocalArgs {
     // per aggregate (batch-relative index b, aggregate a = first + b)
     int32_t first;                 // first aggregate of the batch
+    const int32_t* agg_list;       // optional: aggregate of batch entry b (assembly re-runs)
     const int64_t* sub_ptr;        // Omega offsets into sub_dofs (aggregate order)
     const int32_t* sub_dofs;
     const int64_t* agg_ptr;        // omega sizes = agg_ptr[a+1]-agg_ptr[a]
@@ -31,8 +34,8 @@ struct LocalArgs {
     const int64_t* sq_off;         // per batch entry: offset of its nw x nw slots
     double* s_buf;                 // S~, then C
     double* v_buf;                 // Jacobi eigenvectors
-    const int64_t* w3_off;         // eig-based Schur scratch (mode 1 only)
-    double* w3;
+    const int64_t* t_off;          // per batch entry: tridiagonal data + inverse-iteration scratch
+    double* t_buf;
     // outputs
     const int64_t* inv_off;        // aggregate order: offset of A_Omega^{-1} (m x m)
     double* inv;
@@ -41,12 +44,11 @@ struct LocalArgs {
     const int64_t* mu_off;         // = agg_ptr (sorted mu per aggregate)
     double* mu;
     int32_t* k_out;
-    int32_t* status;               // 0 ok, 1 singular interface block, 2 A_Omega not SPD, 3 A_ww fail
+    int32_t* status;               // 0 ok, 2 A_Omega not SPD
     // parameters
     int32_t modes_fixed;
     double thr;                    // 1 / tau_cut
     double band_tol, cluster_tol;
-    int32_t schur_mode;            // 0 Cholesky (flag if singular), 1 eigendecomposition
 };
 
 void launch_elem_eig(int64_t n_elem, const int64_t* elem_ptr, const int64_t* blk_off, const double* blocks,
@@ -57,7 +59,12 @@ void launch_assemble_csr(int64_t n_blk, const int64_t* elem_ptr, const int32_t* 
                          const double* blocks, const int64_t* rowptr, const int32_t* col, double* val, hipStream_t st);
 
 void launch_local_assemble(int32_t nbatch, const LocalArgs& a, hipStream_t st);
-void launch_local_solve(int32_t nbatch, const LocalArgs& a, hipStream_t st);
+void launch_local_eig(int32_t nbatch, const LocalArgs& a, hipStream_t st);
+void launch_stage_z(int32_t nbatch, const LocalArgs& a, hipStream_t st);
+void launch_views_max_diag(int32_t nv, const double* base, const View* v, double* out, hipStream_t st);
+void launch_views_add_diag(int32_t nv, double* base, const View* v, const double* delta, hipStream_t st);
+void launch_views_symmetrize(int32_t nv, double* base, const View* v, hipStream_t st);
+void launch_views_identity(int32_t nv, double* base, const View* v, hipStream_t st);
 
 void launch_z_compact(int32_t n_agg, const int64_t* agg_ptr, const int32_t* k, const int64_t* zst_off,
                       const double* zst, const int64_t* zoff, double* Z, float* Z32, hipStream_t st);

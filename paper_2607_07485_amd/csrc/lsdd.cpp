@@ -7,7 +7,10 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cfloat>
+#include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <memory>
 #include <stdexcept>
@@ -39,6 +42,28 @@ struct Error : std::runtime_error {
 
 double now_s() {
     return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+// LSDD_VERBOSE=1 prints setup phase timings to stderr.
+bool verbose() {
+    static int v = -1;
+    if (v < 0) {
+        const char* e = std::getenv("LSDD_VERBOSE");
+        v = (e && *e && *e != '0') ? 1 : 0;
+    }
+    return v == 1;
+}
+
+void vlog(const char* fmt, ...) __attribute__((format(printf, 1, 2)));
+void vlog(const char* fmt, ...) {
+    if (!verbose()) return;
+    va_list ap;
+    va_start(ap, fmt);
+    std::fprintf(stderr, "[lsdd] ");
+    std::vfprintf(stderr, fmt, ap);
+    std::fprintf(stderr, "\n");
+    std::fflush(stderr);
+    va_end(ap);
 }
 
 }  // namespace
@@ -138,6 +163,7 @@ struct Level {
     std::vector<int32_t> sweep;
     std::vector<int64_t> sw_sub_off;
     std::vector<int64_t> color_row0, color_item0;
+    std::vector<double> color_m2, color_m, color_nnz;   // sums of |Omega|^2, |Omega|, row nnz per colour
     int64_t* d_sw_sub_off = nullptr;
     int32_t* d_sw_sub_dofs = nullptr;
     int64_t* d_sw_inv_off = nullptr;
@@ -153,9 +179,68 @@ struct Level {
     double *cr64 = nullptr, *cx64 = nullptr;   // FP64 staging for the FP32 coarsest solve
 };
 
+// Per-kernel-class HIP-event timing on the hierarchy's stream, with the
+// algorithmic bytes of each traced launch (enabled by lsdd_trace).
+struct Trace {
+    struct Agg {
+        std::string name;
+        int64_t launches = 0;
+        double ms = 0.0;
+        double bytes = 0.0;
+    };
+    struct Pend {
+        int idx;
+        hipEvent_t a, b;
+        double bytes;
+    };
+    bool on = false;
+    std::vector<Agg> agg;
+    std::vector<Pend> pend;
+    std::vector<hipEvent_t> pool;
+    hipEvent_t get() {
+        if (pool.empty()) {
+            hipEvent_t e;
+            HIPCHK(hipEventCreate(&e));
+            return e;
+        }
+        hipEvent_t e = pool.back();
+        pool.pop_back();
+        return e;
+    }
+    int index(const char* name) {
+        for (size_t i = 0; i < agg.size(); ++i)
+            if (agg[i].name == name) return (int)i;
+        agg.push_back(Agg{name});
+        return (int)agg.size() - 1;
+    }
+    void flush() {   // the stream must be synchronised
+        for (Pend& p : pend) {
+            float ms = 0.f;
+            HIPCHK(hipEventElapsedTime(&ms, p.a, p.b));
+            agg[p.idx].launches++;
+            agg[p.idx].ms += ms;
+            agg[p.idx].bytes += p.bytes;
+            pool.push_back(p.a);
+            pool.push_back(p.b);
+        }
+        pend.clear();
+    }
+    void destroy() {
+        for (Pend& p : pend) {
+            pool.push_back(p.a);
+            pool.push_back(p.b);
+        }
+        pend.clear();
+        for (hipEvent_t e : pool) (void)hipEventDestroy(e);
+        pool.clear();
+    }
+};
+
 }  // namespace lsdd
 
 struct lsdd_hierarchy {
+    int32_t cycle_prec = 0;       // 0 FP64 cycle, 1 FP32 cycle (needs params.precision == 1)
+    lsdd::Trace tr;
     lsdd_params prm;
     hipStream_t st = nullptr;
     lsdd::Arena arena;
@@ -208,24 +293,38 @@ void alloc_vectors(lsdd_hierarchy* h, Level& lv, int64_t rloc_len) {
             lv.cr64 = a.alloc<double>(lv.n);
             lv.cx64 = a.alloc<double>(lv.n);
         }
-    } else {
-        lv.r64 = a.alloc<double>(lv.n);
-        lv.x64 = a.alloc<double>(lv.n);
-        lv.t64 = a.alloc<double>(lv.n);
-        lv.rloc64 = a.alloc<double>(std::max<int64_t>(rloc_len, 1));
     }
+    lv.r64 = a.alloc<double>(lv.n);
+    lv.x64 = a.alloc<double>(lv.n);
+    lv.t64 = a.alloc<double>(lv.n);
+    lv.rloc64 = a.alloc<double>(std::max<int64_t>(rloc_len, 1));
+}
+
+template <class F>
+void traced(lsdd_hierarchy* h, const char* name, double bytes, F&& launch) {
+    if (!h->tr.on) {
+        launch();
+        return;
+    }
+    hipEvent_t a = h->tr.get(), b = h->tr.get();
+    HIPCHK(hipEventRecord(a, h->st));
+    launch();
+    HIPCHK(hipEventRecord(b, h->st));
+    h->tr.pend.push_back(Trace::Pend{h->tr.index(name), a, b, bytes});
 }
 
 void make_coarsest(lsdd_hierarchy* h, Level& lv) {
     lv.coarsest = true;
-    if (lv.n > 8192) throw Error(LSDD_E_UNSUPPORTED, "coarsest level too large: " + std::to_string(lv.n));
+    if (lv.n > 32768) throw Error(LSDD_E_UNSUPPORTED, "coarsest level too large: " + std::to_string(lv.n));
     double* W = h->arena.alloc<double>((size_t)lv.n * lv.n);
     HIPCHK(hipMemsetAsync(W, 0, (size_t)lv.n * lv.n * sizeof(double), h->st));
     launch_dense_from_csr(lv.n, lv.d_rowptr, lv.d_col, lv.d_val, W, h->st);
     lv.d_cinv = h->arena.alloc<double>((size_t)lv.n * lv.n);
     int32_t* st = h->arena.alloc<int32_t>(1);
+    double t0 = now_s();
     launch_dense_chol_inv(lv.n, W, lv.d_cinv, st, h->st);
     int32_t hs = download(st, 1, h->st)[0];
+    vlog("coarsest level: n=%lld dense Cholesky + inverse %.3f s", (long long)lv.n, now_s() - t0);
     h->arena.release(W);
     if (hs != 0) throw Error(LSDD_E_NUMERIC, "coarsest-level Cholesky failed (matrix not SPD)");
     alloc_vectors(h, lv, 0);
@@ -250,6 +349,7 @@ std::unique_ptr<Level> coarsen(lsdd_hierarchy* h, Level& lv, const int32_t* agg_
     }
     lv.cl = build_closure(n, lv.agg_of_dof, n_agg, lv.el);
     const Closure& C = lv.cl;
+    double tc0 = now_s();
     for (int32_t i = 0; i < n_agg; ++i)
         if (C.agg_ptr[i + 1] == C.agg_ptr[i]) throw Error(LSDD_E_INVAL, "empty aggregate " + std::to_string(i));
     lv.colors = color_subdomains(n, C, lv.el, &lv.n_colors);
@@ -264,6 +364,8 @@ std::unique_ptr<Level> coarsen(lsdd_hierarchy* h, Level& lv, const int32_t* agg_
         sq[i + 1] = sq[i] + nw * nw;
         msq[i + 1] = msq[i] + m * m;
     }
+    vlog("level %d: n=%lld aggregates=%d colours=%d max|omega|=%lld max|Omega|=%lld max mult=%d",
+         lv.level, (long long)n, n_agg, lv.n_colors, (long long)max_nw, (long long)max_m, C.max_mult);
     if (max_m > 4096) throw Error(LSDD_E_UNSUPPORTED, "overlap larger than 4096 DOFs: " + std::to_string(max_m));
     if (max_nw > 2048) throw Error(LSDD_E_UNSUPPORTED, "aggregate larger than 2048 DOFs");
     std::vector<int64_t> clpos_off(C.cl_elems.size() + 1, 0);
@@ -328,85 +430,157 @@ std::unique_ptr<Level> coarsen(lsdd_hierarchy* h, Level& lv, const int32_t* agg_
     A.band_tol = P.band_tol;
     A.cluster_tol = P.cluster_tol;
 
-    // ---- batched local problems (workspace bounded)
+    // ---- batched local problems (workspace bounded); every dense step runs as
+    // tiled jobs of all aggregates of the batch at once
     const int64_t budget = int64_t(6) << 30;   // bytes of workspace per batch
-    auto run_batches = [&](const std::vector<int32_t>& aggs, int mode) {
-        size_t pos = 0;
-        while (pos < aggs.size()) {
-            std::vector<int64_t> ws_off(1, 0), sq_off(1, 0), w3_off(1, 0);
-            size_t end = pos;
-            int64_t bytes = 0;
-            while (end < aggs.size() && (end - pos) < 60000) {
-                int32_t i = aggs[end];
-                int64_t m = C.sub_ptr[i + 1] - C.sub_ptr[i], nw = C.agg_ptr[i + 1] - C.agg_ptr[i];
-                int64_t ng = m - nw;
-                if (mode && ng > 2048) throw Error(LSDD_E_UNSUPPORTED, "singular interface block larger than 2048");
-                int64_t need = (2 * m * m + 2 * nw * nw + (mode ? ng * ng + ng * nw : 0)) * 8;
-                if (end > pos && bytes + need > budget) break;
-                bytes += need;
-                ws_off.push_back(ws_off.back() + m * m);
-                sq_off.push_back(sq_off.back() + nw * nw);
-                w3_off.push_back(w3_off.back() + (mode ? ng * ng + ng * nw : 0));
-                ++end;
+    vlog("level %d: host graph work %.3f s", lv.level, now_s() - tc0);
+    double tl0 = now_s();
+    Batched bt;
+    bt.st = st;
+    bt.alloc = [](void* c, size_t b) { return static_cast<Arena*>(c)->get(b); };
+    bt.release = [](void* c, void* p) { static_cast<Arena*>(c)->release(p); };
+    bt.ctx = &ar;
+    std::vector<int32_t> status(n_agg, 0);
+    int32_t pos = 0;
+    while (pos < n_agg) {
+        std::vector<int64_t> ws_off(1, 0), sq_off(1, 0), t_off(1, 0);
+        int32_t end = pos;
+        int64_t bytes = 0;
+        while (end < n_agg && (end - pos) < 32768) {
+            int64_t m = C.sub_ptr[end + 1] - C.sub_ptr[end], nw = C.agg_ptr[end + 1] - C.agg_ptr[end];
+            int64_t tl = 3 * nw + 64 * 5 * nw;
+            int64_t need = (2 * m * m + 2 * nw * nw + tl) * 8;
+            if (end > pos && bytes + need > budget) break;
+            bytes += need;
+            ws_off.push_back(ws_off.back() + m * m);
+            sq_off.push_back(sq_off.back() + nw * nw);
+            t_off.push_back(t_off.back() + tl);
+            ++end;
+        }
+        const int32_t nb = end - pos;
+        double* w1 = ar.alloc<double>(ws_off.back());
+        double* w2 = ar.alloc<double>(ws_off.back());
+        double* sb = ar.alloc<double>(sq_off.back());
+        double* vb = ar.alloc<double>(sq_off.back());
+        double* tb = ar.alloc<double>(t_off.back());
+        ws_off.pop_back();
+        sq_off.pop_back();
+        t_off.pop_back();
+        int64_t* d_ws = ar.upload(ws_off, st);
+        int64_t* d_sq = ar.upload(sq_off, st);
+        int64_t* d_t = ar.upload(t_off, st);
+        double* d_maxd = ar.alloc<double>(nb);
+        double* d_minp = ar.alloc<double>(nb);
+        LocalArgs B = A;
+        B.first = pos;
+        B.agg_list = nullptr;
+        B.ws_off = d_ws;
+        B.w1 = w1;
+        B.w2 = w2;
+        B.sq_off = d_sq;
+        B.s_buf = sb;
+        B.v_buf = vb;
+        B.t_off = d_t;
+        B.t_buf = tb;
+        launch_local_assemble(nb, B, st);
+        std::vector<View> vGG, vGw, vww, vS, vAO, vLww;
+        std::vector<int64_t> ngs(nb);
+        for (int32_t b = 0; b < nb; ++b) {
+            const int32_t i = pos + b;
+            const int32_t m = (int32_t)(C.sub_ptr[i + 1] - C.sub_ptr[i]), nw = (int32_t)(C.agg_ptr[i + 1] - C.agg_ptr[i]);
+            const int32_t ng = m - nw;
+            ngs[b] = ng;
+            const int64_t o = ws_off[b];
+            vGG.push_back(View{o + nw + (int64_t)nw * m, m, ng, ng, 0});
+            vGw.push_back(View{o + nw, m, ng, nw, 0});
+            vww.push_back(View{o, m, nw, nw, 0});
+            vS.push_back(View{sq_off[b], nw, nw, nw, 0});
+            vAO.push_back(View{o, m, m, m, 0});
+            vLww.push_back(View{o, m, nw, nw, 0});
+        }
+        // Schur complement onto omega: Cholesky of the interface block; a block
+        // that is singular to working precision (pivot <= |Gamma| eps max diag)
+        // is factored again with that tolerance added to its diagonal
+        HIPCHK(hipMemsetAsync(d_minp, 0x7f, nb * sizeof(double), st));
+        launch_views_max_diag(nb, w1, bt.put(0, vGG), d_maxd, st);
+        bt.potrf(w1, vGG, d_minp);
+        {
+            std::vector<double> maxd = download(d_maxd, nb, st), minp = download(d_minp, nb, st);
+            std::vector<int32_t> sing;
+            std::vector<int64_t> sing_ws;
+            std::vector<double> delta;
+            std::vector<View> vs;
+            for (int32_t b = 0; b < nb; ++b) {
+                if (ngs[b] == 0) continue;
+                const double tol = (double)ngs[b] * DBL_EPSILON * maxd[b];
+                if (!(minp[b] > tol)) {
+                    sing.push_back(pos + b);
+                    sing_ws.push_back(ws_off[b]);
+                    delta.push_back(tol);
+                    vs.push_back(vGG[b]);
+                }
             }
-            const int32_t nb = (int32_t)(end - pos);
-            // aggregates of a batch must be consecutive in this driver
-            for (size_t t = pos; t < end; ++t)
-                if (aggs[t] != aggs[pos] + (int32_t)(t - pos)) throw Error(LSDD_E_INVAL, "internal: non-consecutive batch");
-            double* w1 = ar.alloc<double>(ws_off.back());
-            double* w2 = ar.alloc<double>(ws_off.back());
-            double* sb = ar.alloc<double>(sq_off.back());
-            double* vb = ar.alloc<double>(sq_off.back());
-            double* w3 = mode ? ar.alloc<double>(w3_off.back()) : nullptr;
-            ws_off.pop_back();
-            sq_off.pop_back();
-            w3_off.pop_back();
-            int64_t* d_ws = ar.upload(ws_off, st);
-            int64_t* d_sq = ar.upload(sq_off, st);
-            int64_t* d_w3 = ar.upload(w3_off, st);
-            LocalArgs B = A;
-            B.first = aggs[pos];
-            B.ws_off = d_ws;
-            B.w1 = w1;
-            B.w2 = w2;
-            B.sq_off = d_sq;
-            B.s_buf = sb;
-            B.v_buf = vb;
-            B.w3_off = d_w3;
-            B.w3 = w3;
-            B.schur_mode = mode;
-            launch_local_assemble(nb, B, st);
-            launch_local_solve(nb, B, st);
-            HIPCHK(hipGetLastError());
-            sync(st);
-            ar.release(w1);
-            ar.release(w2);
-            ar.release(sb);
-            ar.release(vb);
-            if (w3) ar.release(w3);
-            ar.release(d_ws);
-            ar.release(d_sq);
-            ar.release(d_w3);
-            pos = end;
+            if (!sing.empty()) {
+                vlog("  %zu interface blocks singular to working precision: regularised", sing.size());
+                int32_t* d_list = ar.upload(sing, st);
+                int64_t* d_sws = ar.upload(sing_ws, st);
+                double* d_delta = ar.upload(delta, st);
+                LocalArgs R = B;
+                R.agg_list = d_list;
+                R.ws_off = d_sws;
+                launch_local_assemble((int32_t)sing.size(), R, st);
+                launch_views_add_diag((int32_t)sing.size(), w1, bt.put(0, vs), d_delta, st);
+                double* d_mp2 = ar.alloc<double>(sing.size());
+                bt.potrf(w1, vs, d_mp2);
+                std::vector<double> mp2 = download(d_mp2, sing.size(), st);
+                for (size_t t = 0; t < sing.size(); ++t)
+                    if (!(mp2[t] > 0.0)) status[sing[t]] = 3;
+                for (void* p : {(void*)d_list, (void*)d_sws, (void*)d_delta, (void*)d_mp2}) ar.release(p);
+            }
         }
-    };
-    {
-        std::vector<int32_t> all(n_agg);
-        for (int32_t i = 0; i < n_agg; ++i) all[i] = i;
-        run_batches(all, 0);
-    }
-    std::vector<int32_t> status = download(d_status, n_agg, st);
-    for (int32_t i = 0; i < n_agg; ++i) {
-        if (status[i] == 1) {
-            std::vector<int32_t> one(1, i);
-            run_batches(one, 1);
+        bt.trsm(w1, vGG, w1, vGw, false);                                   // W = L_G^{-1} A~_Gw
+        bt.gemm_tn(w1, vGw, w1, vGw, w1, vww, 1.0, sb, vS, 1.0);            // S~ = A~_ww - W^T W
+        // Cholesky of A_Omega; its leading block is chol(A_ww)
+        bt.potrf(w2, vAO, d_minp);
+        {
+            std::vector<double> minp = download(d_minp, nb, st);
+            for (int32_t b = 0; b < nb; ++b)
+                if (!(minp[b] > 0.0)) status[pos + b] = 2;
         }
+        // C = L^{-1} S~ L^{-T}
+        bt.trsm(w2, vLww, sb, vS, false);
+        bt.transpose(sb, vS);
+        bt.trsm(w2, vLww, sb, vS, false);
+        launch_views_symmetrize(nb, sb, bt.put(0, vS), st);
+        // eigenpairs of C and retained modes
+        launch_local_eig(nb, B, st);
+        HIPCHK(hipGetLastError());
+        std::vector<int32_t> kb = download(lv.d_k + pos, nb, st);
+        // Z = L_ww^{-T} V_k
+        std::vector<View> vZ(nb);
+        for (int32_t b = 0; b < nb; ++b) vZ[b] = View{ws_off[b], vS[b].rows, vS[b].rows, kb[b], 0};
+        bt.trsm(w2, vLww, w1, vZ, true);
+        launch_stage_z(nb, B, st);
+        // subdomain inverse A_Omega^{-1} = L^{-T} L^{-1}
+        launch_views_identity(nb, w1, bt.put(0, vAO), st);
+        bt.trsm(w2, vAO, w1, vAO, false);
+        std::vector<View> vInv(nb);
+        for (int32_t b = 0; b < nb; ++b) vInv[b] = View{msq[pos + b], vAO[b].rows, vAO[b].rows, vAO[b].rows, 0};
+        bt.gemm_tn(w1, vAO, w1, vAO, nullptr, vInv, 0.0, lv.d_inv, vInv, -1.0, true);
+        HIPCHK(hipGetLastError());
+        sync(st);
+        vlog("  batch of %d aggregates from %d done (%.3f s since start)", nb, pos, now_s() - tc0);
+        bt.free_all();
+        for (void* p : {(void*)w1, (void*)w2, (void*)sb, (void*)vb, (void*)tb, (void*)d_ws, (void*)d_sq, (void*)d_t,
+                        (void*)d_maxd, (void*)d_minp})
+            ar.release(p);
+        pos = end;
     }
-    status = download(d_status, n_agg, st);
+    vlog("level %d: local problems %.3f s", lv.level, now_s() - tl0);
     for (int32_t i = 0; i < n_agg; ++i) {
         if (status[i] != 0)
-            throw Error(LSDD_E_NUMERIC, "local problem of aggregate " + std::to_string(i) + " failed (status " +
-                                            std::to_string(status[i]) + ": overlap matrix not SPD)");
+            throw Error(LSDD_E_NUMERIC, "local problem of aggregate " + std::to_string(i) + " failed (" +
+                                            (status[i] == 2 ? "overlap matrix not SPD" : "interface block") + ")");
     }
     lv.k = download(lv.d_k, n_agg, st);
     // ---- coarse numbering, compact Z
@@ -451,6 +625,18 @@ std::unique_ptr<Level> coarsen(lsdd_hierarchy* h, Level& lv, const int32_t* agg_
     for (int32_t c = 0; c < lv.n_colors; ++c) {
         lv.color_row0[c + 1] = std::max(lv.color_row0[c + 1], lv.color_row0[c]);
         lv.color_item0[c + 1] = std::max(lv.color_item0[c + 1], lv.color_item0[c]);
+    }
+    lv.color_m2.assign(lv.n_colors, 0.0);
+    lv.color_m.assign(lv.n_colors, 0.0);
+    lv.color_nnz.assign(lv.n_colors, 0.0);
+    for (int32_t i = 0; i < n_agg; ++i) {
+        double m = (double)(C.sub_ptr[i + 1] - C.sub_ptr[i]);
+        lv.color_m2[lv.colors[i]] += m * m;
+        lv.color_m[lv.colors[i]] += m;
+        for (int64_t q = C.sub_ptr[i]; q < C.sub_ptr[i + 1]; ++q) {
+            int32_t d = C.sub_dofs[q];
+            lv.color_nnz[lv.colors[i]] += (double)(lv.pat.ptr[d + 1] - lv.pat.ptr[d]);
+        }
     }
     lv.d_sw_sub_off = ar.upload(lv.sw_sub_off, st);
     lv.d_sw_sub_dofs = ar.upload(sw_dofs, st);
@@ -538,9 +724,11 @@ std::unique_ptr<Level> coarsen(lsdd_hierarchy* h, Level& lv, const int32_t* agg_
     ga.ws = ar.alloc<double>(ws_tot);
     ga.cblk_off = cv->d_blk_off;
     ga.cblocks = cv->d_blocks;
+    double tg0 = now_s();
     launch_galerkin(ga, st);
     HIPCHK(hipGetLastError());
     sync(st);
+    vlog("level %d: Galerkin products for %lld coarse elements %.3f s", lv.level, (long long)ng, now_s() - tg0);
     for (const void* p : {(const void*)ga.mem_ptr, (const void*)ga.mem_elems, (const void*)ga.pm_off,
                           (const void*)ga.pm_zrow, (const void*)ga.pm_k, (const void*)ga.pm_col,
                           (const void*)ga.ws_off, (const void*)ga.ws})
@@ -582,10 +770,18 @@ void sweep(lsdd_hierarchy* h, Level& lv, const T* r, T* x, bool forward, bool x_
         int64_t r0 = lv.color_row0[c], r1 = lv.color_row0[c + 1];
         int64_t i0 = lv.color_item0[c], i1 = lv.color_item0[c + 1];
         if (i1 == i0) continue;
-        launch_csr_resid_rows<T>(r1 - r0, lv.d_sw_sub_dofs + r0, lv.d_rowptr, lv.d_col, V::val(lv), x, r,
-                                 V::rloc(lv) + r0, x_zero_first && cc == 0, h->st);
-        launch_sub_gemv<T>(i1 - i0, lv.d_items + 2 * i0, lv.d_sw_sub_off, lv.d_sw_inv_off, V::inv(lv), V::rloc(lv),
-                           lv.d_sw_sub_dofs, x, h->st);
+        const double w = (double)sizeof(T);
+        const bool xz = x_zero_first && cc == 0;
+        const double rb = lv.color_m[c] * (4 + 8 + 3 * w) + (xz ? 0.0 : lv.color_nnz[c] * (4 + w));
+        traced(h, "csr_resid_rows", rb, [&] {
+            launch_csr_resid_rows<T>(r1 - r0, lv.d_sw_sub_dofs + r0, lv.d_rowptr, lv.d_col, V::val(lv), x, r,
+                                     V::rloc(lv) + r0, xz, h->st);
+        });
+        const double gb = lv.color_m2[c] * w + lv.color_m[c] * (4 + 3 * w);
+        traced(h, "sub_gemv", gb, [&] {
+            launch_sub_gemv<T>(i1 - i0, lv.d_items + 2 * i0, lv.d_sw_sub_off, lv.d_sw_inv_off, V::inv(lv),
+                               V::rloc(lv), lv.d_sw_sub_dofs, x, h->st);
+        });
     }
 }
 
@@ -593,12 +789,14 @@ template <typename T>
 void vcycle(lsdd_hierarchy* h, size_t l, const T* r, T* x) {
     using V = LvVec<T>;
     Level& lv = *h->L[l];
+    const double w = (double)sizeof(T);
     if (lv.coarsest) {
+        const double nb = (double)lv.n * lv.n * 8.0 + 2.0 * lv.n * 8.0;
         if constexpr (std::is_same<T, double>::value) {
-            launch_dense_gemv(lv.n, lv.d_cinv, r, x, h->st);
+            traced(h, "coarse_gemv", nb, [&] { launch_dense_gemv(lv.n, lv.d_cinv, r, x, h->st); });
         } else {
             launch_to_f64(lv.n, r, lv.cr64, h->st);
-            launch_dense_gemv(lv.n, lv.d_cinv, lv.cr64, lv.cx64, h->st);
+            traced(h, "coarse_gemv", nb, [&] { launch_dense_gemv(lv.n, lv.d_cinv, lv.cr64, lv.cx64, h->st); });
             launch_to_f32(lv.n, lv.cx64, x, h->st);
         }
         return;
@@ -606,18 +804,25 @@ void vcycle(lsdd_hierarchy* h, size_t l, const T* r, T* x) {
     Level& nx = *h->L[l + 1];
     launch_zero<T>(lv.n, x, h->st);
     sweep<T>(h, lv, r, x, true, true);
-    launch_csr_spmv<T>(lv.n, lv.d_rowptr, lv.d_col, V::val(lv), x, V::t(lv), r, h->st);
-    launch_restrict<T>(lv.cl.n_agg, lv.d_agg_ptr, lv.d_agg_dofs, lv.d_zoff, lv.d_k, lv.d_coff, V::Z(lv), V::t(lv),
-                       V::r(nx), h->st);
+    traced(h, "csr_spmv", (double)lv.nnz * (4 + w) + (double)lv.n * (8 + 3 * w), [&] {
+        launch_csr_spmv<T>(lv.n, lv.d_rowptr, lv.d_col, V::val(lv), x, V::t(lv), r, h->st);
+    });
+    const double zb = (double)lv.zoff.back() * w + (double)lv.n * (4 + w) + (double)nx.n * w;
+    traced(h, "restrict", zb, [&] {
+        launch_restrict<T>(lv.cl.n_agg, lv.d_agg_ptr, lv.d_agg_dofs, lv.d_zoff, lv.d_k, lv.d_coff, V::Z(lv),
+                           V::t(lv), V::r(nx), h->st);
+    });
     vcycle<T>(h, l + 1, V::r(nx), V::x(nx));
-    launch_prolong<T>(lv.cl.n_agg, lv.d_agg_ptr, lv.d_agg_dofs, lv.d_zoff, lv.d_k, lv.d_coff, V::Z(lv), V::x(nx), x,
-                      h->st);
+    traced(h, "prolong", zb + (double)lv.n * w, [&] {
+        launch_prolong<T>(lv.cl.n_agg, lv.d_agg_ptr, lv.d_agg_dofs, lv.d_zoff, lv.d_k, lv.d_coff, V::Z(lv),
+                          V::x(nx), x, h->st);
+    });
     sweep<T>(h, lv, r, x, false, false);
 }
 
 void precond(lsdd_hierarchy* h, const double* r, double* z) {
     Level& l0 = *h->L[0];
-    if (h->prm.precision == 1) {
+    if (h->cycle_prec == 1) {
         launch_to_f32(l0.n, r, l0.r32, h->st);
         vcycle<float>(h, 0, l0.r32, l0.x32);
         launch_to_f64(l0.n, l0.x32, z, h->st);
@@ -689,6 +894,7 @@ lsdd_hierarchy* build(ElemList el0, const double* blocks, bool blocks_on_device,
         HIPCHK(hipGetLastError());
         std::vector<int32_t> status = download(d_status, ne, h->st);
         lv->ranks = download(d_ranks, ne, h->st);
+        vlog("element Gram factors for %lld elements %.3f s", (long long)ne, now_s() - t0);
         for (int64_t e = 0; e < ne; ++e) {
             if (status[e] == 1) throw Error(LSDD_E_INVAL, "element " + std::to_string(e) + ": block is not symmetric or not finite");
             if (status[e] == 2) throw Error(LSDD_E_NOT_SPSD, "element " + std::to_string(e) + ": block is not SPSD");
@@ -732,6 +938,7 @@ lsdd_hierarchy* build(ElemList el0, const double* blocks, bool blocks_on_device,
     HIPCHK(hipHostMalloc((void**)&h->h_scal, 16 * sizeof(double), hipHostMallocDefault));
     sync(h->st);
     h->setup_s = now_s() - t0;
+    h->cycle_prec = P.precision;
     return h.release();
 }
 
@@ -873,6 +1080,7 @@ lsdd_status lsdd_destroy(lsdd_hierarchy* h) {
     if (!h) return LSDD_OK;
     if (h->st) (void)hipStreamSynchronize(h->st);
     else (void)hipDeviceSynchronize();
+    h->tr.destroy();
     h->arena.clear();
     if (h->h_scal) (void)hipHostFree(h->h_scal);
     delete h;
@@ -910,7 +1118,7 @@ lsdd_status lsdd_solve(lsdd_hierarchy* h, const double* b, double* x, int32_t nr
     hipStream_t st = h->st;
     Level& l0 = *h->L[0];
     const int64_t n = l0.n;
-    const bool flex = h->prm.precision == 1;
+    const bool flex = h->cycle_prec == 1;
     double* S = h->scal;   // [0] rz [1] pq [2] rr [3] bb [4] zr_new [5] z.(r - rold)
     lsdd_status worst = LSDD_OK;
     for (int32_t k = 0; k < nrhs; ++k) {
@@ -941,12 +1149,15 @@ lsdd_status lsdd_solve(lsdd_hierarchy* h, const double* b, double* x, int32_t nr
         double rel = 1.0;
         int it = 0;
         for (it = 1; it <= h->prm.max_iter; ++it) {
-            launch_csr_spmv<double>(n, l0.d_rowptr, l0.d_col, l0.d_val, h->p, h->q, nullptr, st);
+            traced(h, "pcg_spmv", (double)l0.nnz * 12.0 + (double)n * 24.0, [&] {
+                launch_csr_spmv<double>(n, l0.d_rowptr, l0.d_col, l0.d_val, h->p, h->q, nullptr, st);
+            });
             launch_dot(n, h->p, h->q, h->partials, S + 1, st);
             if (flex) launch_copy(n, h->r, h->rold, st);
             launch_update_xr(n, S + 0, S + 1, h->p, h->q, xk, h->r, h->partials, S + 2, st);
             HIPCHK(hipMemcpyAsync(h->h_scal, S, 3 * sizeof(double), hipMemcpyDeviceToHost, st));
             sync(st);
+            if (h->tr.on) h->tr.flush();
             const double pq = h->h_scal[1], rr = h->h_scal[2];
             if (!(pq > 0.0) || !std::isfinite(rr)) {
                 stat = LSDD_E_BREAKDOWN;
@@ -974,6 +1185,7 @@ lsdd_status lsdd_solve(lsdd_hierarchy* h, const double* b, double* x, int32_t nr
         }
         HIPCHK(hipGetLastError());
         sync(st);
+        if (h->tr.on) h->tr.flush();
         inf.iters = std::min(it, h->prm.max_iter);
         inf.converged = stat == LSDD_OK;
         inf.rel_res = rel;
@@ -986,6 +1198,55 @@ lsdd_status lsdd_solve(lsdd_hierarchy* h, const double* b, double* x, int32_t nr
         }
     }
     return worst;
+    ABI_END
+}
+
+lsdd_status lsdd_set_cycle_precision(lsdd_hierarchy* h, int32_t precision) {
+    ABI_BEGIN
+    if (!h || precision < 0 || precision > 1) throw Error(LSDD_E_INVAL, "bad argument");
+    if (precision == 1 && h->prm.precision != 1)
+        throw Error(LSDD_E_INVAL, "the FP32 cycle needs a hierarchy set up with precision = 1");
+    h->cycle_prec = precision;
+    return LSDD_OK;
+    ABI_END
+}
+
+lsdd_status lsdd_set_solve_params(lsdd_hierarchy* h, double rtol, int32_t max_iter) {
+    ABI_BEGIN
+    if (!h || !(rtol > 0.0) || max_iter < 1) throw Error(LSDD_E_INVAL, "bad argument");
+    h->prm.rtol = rtol;
+    h->prm.max_iter = max_iter;
+    return LSDD_OK;
+    ABI_END
+}
+
+lsdd_status lsdd_trace(lsdd_hierarchy* h, int32_t on) {
+    ABI_BEGIN
+    if (!h) throw Error(LSDD_E_INVAL, "NULL hierarchy");
+    if (h->st) HIPCHK(hipStreamSynchronize(h->st));
+    h->tr.flush();
+    if (on) h->tr.agg.clear();
+    h->tr.on = on != 0;
+    return LSDD_OK;
+    ABI_END
+}
+
+lsdd_status lsdd_trace_get(lsdd_hierarchy* h, int32_t idx, char* name, int32_t name_len, int64_t* launches,
+                           double* ms, double* bytes) {
+    ABI_BEGIN
+    if (!h) throw Error(LSDD_E_INVAL, "NULL hierarchy");
+    HIPCHK(hipStreamSynchronize(h->st));
+    h->tr.flush();
+    if (idx < 0 || idx >= (int32_t)h->tr.agg.size()) throw Error(LSDD_E_INVAL, "trace index out of range");
+    const Trace::Agg& a = h->tr.agg[idx];
+    if (name && name_len > 0) {
+        std::strncpy(name, a.name.c_str(), name_len - 1);
+        name[name_len - 1] = 0;
+    }
+    if (launches) *launches = a.launches;
+    if (ms) *ms = a.ms;
+    if (bytes) *bytes = a.bytes;
+    return LSDD_OK;
     ABI_END
 }
 

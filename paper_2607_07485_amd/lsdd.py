@@ -75,11 +75,16 @@ def lib():
         L.lsdd_export_level.argtypes = [_P, C.c_int32, i32p, i32p, f64p, f64p, i32p, i64p, i32p, f64p, i32p]
         L.lsdd_export_gram.argtypes = [_P, i32p, f64p]
         L.lsdd_destroy.argtypes = [_P]
+        L.lsdd_set_cycle_precision.argtypes = [_P, C.c_int32]
+        L.lsdd_trace.argtypes = [_P, C.c_int32]
+        L.lsdd_set_solve_params.argtypes = [_P, C.c_double, C.c_int32]
+        L.lsdd_trace_get.argtypes = [_P, C.c_int32, C.c_char_p, C.c_int32, i64p, f64p, f64p]
         L.lsdd_set_allocator.argtypes = [_P, _P, _P]
         L.lsdd_set_allocator.restype = None
         for name in ("lsdd_setup_elements", "lsdd_setup_gram_csr", "lsdd_solve", "lsdd_vcycle", "lsdd_apply",
                      "lsdd_hierarchy_info", "lsdd_level_sizes", "lsdd_export_level", "lsdd_export_gram",
-                     "lsdd_destroy"):
+                     "lsdd_destroy", "lsdd_set_cycle_precision", "lsdd_trace", "lsdd_trace_get",
+                     "lsdd_set_solve_params"):
             getattr(L, name).restype = C.c_int
         _LIB = L
     return _LIB
@@ -183,6 +188,28 @@ class Hierarchy:
         y = torch.empty_like(x) if y is None else y
         _check(lib().lsdd_apply(self._h, int(level), _dev_ptr(x), _dev_ptr(y), _stream()))
         return y
+
+    def set_cycle_precision(self, precision: int):
+        _check(lib().lsdd_set_cycle_precision(self._h, int(precision)))
+
+    def set_solve_params(self, rtol: float, max_iter: int = 1000):
+        _check(lib().lsdd_set_solve_params(self._h, float(rtol), int(max_iter)))
+
+    def trace(self, on: bool):
+        _check(lib().lsdd_trace(self._h, 1 if on else 0))
+
+    def trace_read(self):
+        out = {}
+        i = 0
+        while True:
+            name = C.create_string_buffer(64)
+            n, ms, by = C.c_int64(), C.c_double(), C.c_double()
+            code = lib().lsdd_trace_get(self._h, i, name, 64, C.byref(n), C.byref(ms), C.byref(by))
+            if code != 0:
+                break
+            out[name.value.decode()] = dict(launches=n.value, ms=ms.value, bytes=by.value)
+            i += 1
+        return out
 
     # ---------------------------------------------------------------- inspection
     def info(self):
