@@ -6,7 +6,7 @@ per iteration) plus setup seconds, FP32 cycle inside FP64 PCG versus the plain
 FP64 method, on the grad-div workload in H(div): RTCF_3 on a 128 x 128 quad
 mesh of the unit square (295,680 DOFs), kappa_T ~ lognormal(0, 1) on the div
 term, 1e-4 mass weight, two standard-aggregation passes on level 0, threshold
-tau_cut = 0.75 max mult, at most 4 levels.  Inputs are seeded synthetic data
+tau_cut = 0.75 max mult, at most 3 levels.  Inputs are seeded synthetic data
 (numpy default_rng(0)) already resident in HBM when timing starts.
 
 A step = one complete PCG solve on the resident hierarchy (V-cycles with the
@@ -35,7 +35,7 @@ HBM_PEAK_GBS = 8000.0
 
 
 def _params(P, **kw):
-    base = dict(max_levels=4, tau_const=0.75, agg_passes=2, agg_passes_coarse=1, precision=1, rtol=1e-8)
+    base = dict(max_levels=3, tau_const=0.75, agg_passes=2, agg_passes_coarse=1, precision=1, rtol=1e-8)
     base.update(kw)
     return P.Params.default(**base)
 
@@ -67,7 +67,7 @@ def cpu_baseline(N_sample: int):
     import oracle
     prob, b = fegen.graddiv_hdiv(N=N_sample)
     t0 = time.perf_counter()
-    h = oracle.setup(prob, oracle.Params(max_levels=4, tau_const=0.75, agg_passes=2, agg_passes_coarse=1))
+    h = oracle.setup(prob, oracle.Params(max_levels=3, tau_const=0.75, agg_passes=2, agg_passes_coarse=1))
     t1 = time.perf_counter()
     x, info = oracle.pcg(h, b)
     t2 = time.perf_counter()
