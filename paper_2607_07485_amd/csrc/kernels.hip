@@ -140,20 +140,25 @@ __global__ void __launch_bounds__(WG) k_elem_eig(const int64_t* elem_ptr, const 
 
 // ====================================================================== assembly into CSR
 
-// One workgroup per element / coarse group: add its block into the CSR values
-// (the CSR pattern contains every (p, q) of every support).
-__global__ void __launch_bounds__(WG) k_assemble_csr(const int64_t* elem_ptr, const int32_t* elem_dofs,
-                                                     const int64_t* blk_off, const double* blocks,
-                                                     const int64_t* rowptr, const int32_t* col, double* val) {
-    const int64_t e = blockIdx.x;
-    const int64_t base = elem_ptr[e];
-    const int n = (int)(elem_ptr[e + 1] - base);
-    const double* B = blocks + blk_off[e];
-    for (int64_t idx = tid(); idx < (int64_t)n * n; idx += WG) {
-        int a = (int)(idx / n), b = (int)(idx % n);
-        int32_t p = elem_dofs[base + a], q = elem_dofs[base + b];
-        int64_t slot = find_slot(col, rowptr[p], rowptr[p + 1], q);
-        atomicAdd(&val[slot], B[idx]);
+// Assembly A = sum_T R_T^T A_T R_T into a CSR pattern that contains every
+// (p, q) of every support: one thread per row p visits the elements holding p
+// in ascending order (deterministic summation order).
+__global__ void k_assemble_rows(int64_t n, const int64_t* d2e_ptr, const int32_t* d2e_elem, const int32_t* d2e_loc,
+                                const int64_t* elem_ptr, const int32_t* elem_dofs, const int64_t* blk_off,
+                                const double* blocks, const int64_t* rowptr, const int32_t* col, double* val) {
+    const int64_t p = blockIdx.x * (int64_t)WG + tid();
+    if (p >= n) return;
+    const int64_t lo = rowptr[p], hi = rowptr[p + 1];
+    for (int64_t q = d2e_ptr[p]; q < d2e_ptr[p + 1]; ++q) {
+        const int32_t e = d2e_elem[q];
+        const int a = d2e_loc[q];
+        const int64_t base = elem_ptr[e];
+        const int ne = (int)(elem_ptr[e + 1] - base);
+        const double* B = blocks + blk_off[e] + (int64_t)a * ne;
+        for (int b = 0; b < ne; ++b) {
+            int64_t slot = find_slot(col, lo, hi, elem_dofs[base + b]);
+            val[slot] += B[b];
+        }
     }
 }
 
@@ -308,16 +313,21 @@ __global__ void k_views_identity(double* base, const View* v) {
     }
 }
 
+// Compact the staged Z_i (row-major) into Z (row-major, for the Galerkin
+// products and export) and Zc / Zc32 (column-major, for the transfers).
 __global__ void k_z_compact(const int64_t* agg_ptr, const int32_t* k, const int64_t* zst_off, const double* zst,
-                            const int64_t* zoff, double* Z, float* Z32) {
+                            const int64_t* zoff, double* Z, double* Zc, float* Zc32) {
     const int ag = blockIdx.x;
     const int nw = (int)(agg_ptr[ag + 1] - agg_ptr[ag]);
-    const int64_t cnt = (int64_t)nw * k[ag];
+    const int kk = k[ag];
+    const int64_t cnt = (int64_t)nw * kk;
     const double* src = zst + zst_off[ag];
     for (int64_t i = tid(); i < cnt; i += WG) {
         double v = src[i];
         Z[zoff[ag] + i] = v;
-        if (Z32) Z32[zoff[ag] + i] = (float)v;
+        int64_t a = i / kk, s = i % kk;
+        Zc[zoff[ag] + a + s * nw] = v;
+        if (Zc32) Zc32[zoff[ag] + a + s * nw] = (float)v;
     }
 }
 
@@ -660,37 +670,166 @@ __global__ void __launch_bounds__(WG) k_sub_gemv(const int32_t* items, const int
     }
 }
 
-// rc[coff_i + s] = sum_a Z_i[a, s] t[omega_i[a]]   (Z_i row-major |omega_i| x k_i)
+// Subdomain correction with the packed symmetric inverse: A_Omega^{-1} is stored
+// as its lower 64 x 64 tiles (tile (I, J), I >= J, row-major inside the tile,
+// zero-padded past |Omega|; the diagonal tiles hold both triangles).  Work item
+// = (subdomain, tile row I): waves split the 64 rows of the tile row, lanes the
+// 64 columns.  Tile (I, J) is read once and used twice: its rows give
+// y_I += T x_J (per-lane partials, reduced across lanes once per item) and its
+// columns give y_J += T^T x_I (J < I; summed over the waves in LDS).  Partial
+// results go to a per-subdomain scratch (row parts: nt x 64, column parts:
+// nt(nt-1)/2 x 64) that k_sub_finalize sums in a fixed order, so the smoother is
+// the same linear map on every application (no order-dependent atomics).
 template <typename T>
-__global__ void k_restrict(const int64_t* agg_ptr, const int32_t* agg_dofs, const int64_t* zoff, const int32_t* k,
-                           const int64_t* coff, const T* Z, const T* t, T* rc) {
-    const int ag = blockIdx.x;
-    const int kk = k[ag];
-    const int64_t a0 = agg_ptr[ag];
-    const int nw = (int)(agg_ptr[ag + 1] - a0);
-    const T* z = Z + zoff[ag];
-    for (int s = tid(); s < kk; s += WG) {
-        T acc = 0;
-        for (int a = 0; a < nw; ++a) acc += z[(int64_t)a * kk + s] * t[agg_dofs[a0 + a]];
-        rc[coff[ag] + s] = acc;
+__global__ void __launch_bounds__(WG) k_sub_symv(const int32_t* items, const int64_t* sub_off, const int64_t* tp_off,
+                                                 const T* tiles, const T* rloc, const int64_t* scr_off, T* scr) {
+    __shared__ T s_r[4096];
+    __shared__ T s_c[4][64];
+    const int s = items[2 * blockIdx.x];
+    const int I = items[2 * blockIdx.x + 1];
+    const int64_t o = sub_off[s];
+    const int m = (int)(sub_off[s + 1] - o);
+    const int nt = (m + 63) >> 6;
+    const int mt = nt << 6;
+    for (int a = tid(); a < mt; a += WG) s_r[a] = a < m ? rloc[o + a] : (T)0;
+    __syncthreads();
+    const int lane = tid() & 63, w = tid() >> 6;
+    const T* row0 = tiles + tp_off[s] + (int64_t)(I * (I + 1) / 2) * 4096;
+    T* rowpart = scr + scr_off[s];
+    T* colpart = rowpart + (int64_t)nt * 64;
+    T p[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) p[q] = 0;
+    T xi[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) xi[q] = s_r[I * 64 + w + 4 * q];
+    for (int J = 0; J <= I; ++J) {
+        const T* t = row0 + (int64_t)J * 4096 + lane;
+        const T xj = s_r[J * 64 + lane];
+        T v[16];
+#pragma unroll
+        for (int q = 0; q < 16; ++q) v[q] = t[(w + 4 * q) * 64];
+        T col = 0;
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            p[q] += v[q] * xj;
+            col += v[q] * xi[q];
+        }
+        if (J < I) {
+            s_c[w][lane] = col;
+            __syncthreads();
+            if (w == 0)
+                colpart[((int64_t)I * (I - 1) / 2 + J) * 64 + lane] =
+                    (s_c[0][lane] + s_c[1][lane]) + (s_c[2][lane] + s_c[3][lane]);
+            __syncthreads();
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+        T v = p[q];
+        for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+        p[q] = v;
+    }
+    if (lane < 16) {
+        T y = 0;
+#pragma unroll
+        for (int q = 0; q < 16; ++q)
+            if (q == lane) y = p[q];
+        rowpart[(int64_t)I * 64 + w + 4 * lane] = y;
     }
 }
 
-// x[omega_i[a]] += sum_s Z_i[a, s] ec[coff_i + s]
+// x[Omega_s[c]] += row part of tile J(c) + column parts of the tile rows below,
+// in ascending tile-row order; one thread per subdomain DOF of the colour.
 template <typename T>
-__global__ void k_prolong(const int64_t* agg_ptr, const int32_t* agg_dofs, const int64_t* zoff, const int32_t* k,
-                          const int64_t* coff, const T* Z, const T* ec, T* x) {
-    const int ag = blockIdx.x;
+__global__ void k_sub_finalize(int64_t r0, int64_t r1, const int32_t* pos_sub, const int64_t* sub_off,
+                               const int64_t* scr_off, const T* scr, const int32_t* sub_dofs, T* x) {
+    const int64_t t = r0 + (int64_t)blockIdx.x * WG + tid();
+    if (t >= r1) return;
+    const int s = pos_sub[t];
+    const int64_t o = sub_off[s];
+    const int c = (int)(t - o);
+    const int nt = (int)((sub_off[s + 1] - o + 63) >> 6);
+    const int J = c >> 6, l = c & 63;
+    const T* rowpart = scr + scr_off[s];
+    const T* colpart = rowpart + (int64_t)nt * 64;
+    T y = rowpart[c];
+    for (int I = J + 1; I < nt; ++I) y += colpart[((int64_t)I * (I - 1) / 2 + J) * 64 + l];
+    x[sub_dofs[t]] += y;
+}
+
+// Pack full m x m symmetric inverses (aggregate order, column-major) into the
+// tiled lower storage of k_sub_symv (FP64 and, optionally, FP32).
+__global__ void k_pack_tiles(const int64_t* sub_ptr, const int64_t* inv_off, const double* inv, const int64_t* tp_off,
+                             double* tiles, float* tiles32) {
+    const int ag = blockIdx.y;
+    const int m = (int)(sub_ptr[ag + 1] - sub_ptr[ag]);
+    const int nt = (m + 63) / 64;
+    const int64_t ntile = (int64_t)nt * (nt + 1) / 2;
+    const double* M = inv + inv_off[ag];
+    for (int64_t idx = (int64_t)blockIdx.x * WG + tid(); idx < ntile * 4096; idx += (int64_t)gridDim.x * WG) {
+        int64_t t = idx >> 12;
+        int e = (int)(idx & 4095);
+        int I = 0;
+        while ((int64_t)(I + 1) * (I + 2) / 2 <= t) ++I;
+        int J = (int)(t - (int64_t)I * (I + 1) / 2);
+        int r = I * 64 + (e >> 6), c = J * 64 + (e & 63);
+        double v = (r < m && c < m) ? M[r + (int64_t)c * m] : 0.0;
+        tiles[tp_off[ag] + idx] = v;
+        if (tiles32) tiles32[tp_off[ag] + idx] = (float)v;
+    }
+}
+
+// Transfers with Z_i stored column-major (|omega_i| x k_i, column s contiguous).
+// Restriction rc[coff_i + s] = sum_a Z_i[a, s] t[omega_i[a]]: work item =
+// (aggregate, 16 columns); t on omega_i is staged in LDS, each wave takes
+// columns and its lanes stride the rows (coalesced), then a wave reduction.
+template <typename T>
+__global__ void __launch_bounds__(WG) k_restrict(const int32_t* items, const int64_t* agg_ptr, const int32_t* agg_dofs,
+                                                 const int64_t* zoff, const int32_t* k, const int64_t* coff, const T* Zc,
+                                                 const T* t, T* rc) {
+    __shared__ T s_t[2048];
+    const int ag = items[2 * blockIdx.x], s0 = items[2 * blockIdx.x + 1];
     const int kk = k[ag];
     const int64_t a0 = agg_ptr[ag];
     const int nw = (int)(agg_ptr[ag + 1] - a0);
-    const T* z = Z + zoff[ag];
-    const T* e = ec + coff[ag];
-    for (int a = tid(); a < nw; a += WG) {
+    for (int a = tid(); a < nw; a += WG) s_t[a] = t[agg_dofs[a0 + a]];
+    __syncthreads();
+    const int lane = tid() & 63, w = tid() >> 6;
+    const T* z = Zc + zoff[ag];
+    for (int s = s0 + w; s < s0 + 16 && s < kk; s += 4) {
+        const T* col = z + (int64_t)s * nw;
         T acc = 0;
-        for (int s = 0; s < kk; ++s) acc += z[(int64_t)a * kk + s] * e[s];
-        x[agg_dofs[a0 + a]] += acc;
+        for (int a = lane; a < nw; a += 64) acc += col[a] * s_t[a];
+        for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+        if (lane == 0) rc[coff[ag] + s] = acc;
     }
+}
+
+// Prolongation x[omega_i[a]] += sum_s Z_i[a, s] ec[coff_i + s]: work item =
+// (aggregate, 256 rows); thread per row, coalesced over rows, ec in LDS.
+template <typename T>
+__global__ void __launch_bounds__(WG) k_prolong(const int32_t* items, const int64_t* agg_ptr, const int32_t* agg_dofs,
+                                                const int64_t* zoff, const int32_t* k, const int64_t* coff, const T* Zc,
+                                                const T* ec, T* x) {
+    __shared__ T s_e[2048];
+    const int ag = items[2 * blockIdx.x], r0 = items[2 * blockIdx.x + 1];
+    const int kk = k[ag];
+    const int64_t a0 = agg_ptr[ag];
+    const int nw = (int)(agg_ptr[ag + 1] - a0);
+    for (int s = tid(); s < kk; s += WG) s_e[s] = ec[coff[ag] + s];
+    __syncthreads();
+    const int a = r0 + tid();
+    if (a >= nw) return;
+    const T* z = Zc + zoff[ag] + a;
+    T acc0 = 0, acc1 = 0;
+    int s = 0;
+    for (; s + 1 < kk; s += 2) {
+        acc0 += z[(int64_t)s * nw] * s_e[s];
+        acc1 += z[(int64_t)(s + 1) * nw] * s_e[s + 1];
+    }
+    if (s < kk) acc0 += z[(int64_t)s * nw] * s_e[s];
+    x[agg_dofs[a0 + a]] += acc0 + acc1;
 }
 
 template <typename T>
@@ -698,18 +837,57 @@ __global__ void k_zero(int64_t n, T* x) {
     for (int64_t i = blockIdx.x * (int64_t)WG + tid(); i < n; i += (int64_t)gridDim.x * WG) x[i] = 0;
 }
 
-// x = M r for the dense symmetric coarsest inverse, one 64-column panel per workgroup
-__global__ void __launch_bounds__(WG) k_dense_gemv(int64_t n, const double* M, const double* r, double* x) {
-    __shared__ double s_acc[WG];
+// x = M r for the dense symmetric coarsest inverse: work item = (128-column
+// panel, 1024-row chunk); each lane owns two adjacent columns (two 8-byte loads,
+// valid for any n), waves split the rows; each chunk writes its partial sums to
+// part[chunk * n + j] and k_chunk_sum adds the chunks in ascending order.
+__global__ void __launch_bounds__(WG) k_dense_gemv(int64_t n, const double* M, const double* r, double* part) {
+    __shared__ double s_r[1024];
+    __shared__ double s_a0[WG], s_a1[WG];
     const int lane = tid() & 63, w = tid() >> 6;
-    const int64_t j = (int64_t)blockIdx.x * 64 + lane;
-    double acc = 0.0;
-    if (j < n) {
-        for (int64_t a = w; a < n; a += 4) acc += M[a * n + j] * r[a];
-    }
-    s_acc[tid()] = acc;
+    const int64_t j = (int64_t)blockIdx.x * 128 + 2 * lane;
+    const int64_t r0 = (int64_t)blockIdx.y * 1024;
+    const int64_t r1 = r0 + 1024 < n ? r0 + 1024 : n;
+    for (int64_t a = r0 + tid(); a < r1; a += WG) s_r[a - r0] = r[a];
     __syncthreads();
-    if (w == 0 && j < n) x[j] = s_acc[lane] + s_acc[64 + lane] + s_acc[128 + lane] + s_acc[192 + lane];
+    double a0 = 0.0, a1 = 0.0;
+    if (j + 1 < n) {
+        int64_t a = r0 + w;
+        for (; a + 12 < r1; a += 16) {
+            const double* p0 = M + a * n + j;
+            const double* p1 = p0 + 4 * n;
+            const double* p2 = p0 + 8 * n;
+            const double* p3 = p0 + 12 * n;
+            double x00 = p0[0], x01 = p0[1], x10 = p1[0], x11 = p1[1];
+            double x20 = p2[0], x21 = p2[1], x30 = p3[0], x31 = p3[1];
+            double q0 = s_r[a - r0], q1 = s_r[a + 4 - r0], q2 = s_r[a + 8 - r0], q3 = s_r[a + 12 - r0];
+            a0 += x00 * q0 + x10 * q1 + x20 * q2 + x30 * q3;
+            a1 += x01 * q0 + x11 * q1 + x21 * q2 + x31 * q3;
+        }
+        for (; a < r1; a += 4) {
+            const double* p = M + a * n + j;
+            a0 += p[0] * s_r[a - r0];
+            a1 += p[1] * s_r[a - r0];
+        }
+    } else if (j < n) {
+        for (int64_t a = r0 + w; a < r1; a += 4) a0 += M[a * n + j] * s_r[a - r0];
+    }
+    s_a0[tid()] = a0;
+    s_a1[tid()] = a1;
+    __syncthreads();
+    if (w == 0 && j < n) {
+        double* out = part + (int64_t)blockIdx.y * n;
+        out[j] = (s_a0[lane] + s_a0[64 + lane]) + (s_a0[128 + lane] + s_a0[192 + lane]);
+        if (j + 1 < n) out[j + 1] = (s_a1[lane] + s_a1[64 + lane]) + (s_a1[128 + lane] + s_a1[192 + lane]);
+    }
+}
+
+__global__ void k_chunk_sum(int64_t n, int nchunk, const double* part, double* x) {
+    for (int64_t j = blockIdx.x * (int64_t)WG + tid(); j < n; j += (int64_t)gridDim.x * WG) {
+        double s = 0.0;
+        for (int c = 0; c < nchunk; ++c) s += part[(int64_t)c * n + j];
+        x[j] = s;
+    }
 }
 
 // ---------------------------------------------------------------- PCG helpers
@@ -777,11 +955,13 @@ void launch_elem_eig(int64_t n_elem, const int64_t* elem_ptr, const int64_t* blk
                        scratch, scratch_stride, rank_rtol, spsd_tol);
 }
 
-void launch_assemble_csr(int64_t n_blk, const int64_t* elem_ptr, const int32_t* elem_dofs, const int64_t* blk_off,
-                         const double* blocks, const int64_t* rowptr, const int32_t* col, double* val, hipStream_t st) {
-    if (n_blk <= 0) return;
-    hipLaunchKernelGGL(k_assemble_csr, dim3((unsigned)n_blk), dim3(WG), 0, st, elem_ptr, elem_dofs, blk_off, blocks,
-                       rowptr, col, val);
+void launch_assemble_rows(int64_t n, const int64_t* d2e_ptr, const int32_t* d2e_elem, const int32_t* d2e_loc,
+                          const int64_t* elem_ptr, const int32_t* elem_dofs, const int64_t* blk_off,
+                          const double* blocks, const int64_t* rowptr, const int32_t* col, double* val,
+                          hipStream_t st) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_assemble_rows, dim3(grid_for(n)), dim3(WG), 0, st, n, d2e_ptr, d2e_elem, d2e_loc, elem_ptr,
+                       elem_dofs, blk_off, blocks, rowptr, col, val);
 }
 
 void launch_local_assemble(int32_t nbatch, const LocalArgs& a, hipStream_t st) {
@@ -815,9 +995,9 @@ void launch_views_identity(int32_t nv, double* base, const View* v, hipStream_t 
 }
 
 void launch_z_compact(int32_t n_agg, const int64_t* agg_ptr, const int32_t* k, const int64_t* zst_off, const double* zst,
-                      const int64_t* zoff, double* Z, float* Z32, hipStream_t st) {
+                      const int64_t* zoff, double* Z, double* Zc, float* Zc32, hipStream_t st) {
     if (n_agg <= 0) return;
-    hipLaunchKernelGGL(k_z_compact, dim3(n_agg), dim3(WG), 0, st, agg_ptr, k, zst_off, zst, zoff, Z, Z32);
+    hipLaunchKernelGGL(k_z_compact, dim3(n_agg), dim3(WG), 0, st, agg_ptr, k, zst_off, zst, zoff, Z, Zc, Zc32);
 }
 
 void launch_galerkin(const GalerkinArgs& g, hipStream_t st) {
@@ -891,16 +1071,41 @@ void launch_sub_gemv(int64_t n_items, const int32_t* items, const int64_t* sub_o
                        sub_dofs, x);
 }
 template <typename T>
-void launch_restrict(int32_t n_agg, const int64_t* agg_ptr, const int32_t* agg_dofs, const int64_t* zoff,
-                     const int32_t* k, const int64_t* coff, const T* Z, const T* t, T* rc, hipStream_t st) {
-    if (n_agg <= 0) return;
-    hipLaunchKernelGGL(k_restrict<T>, dim3(n_agg), dim3(WG), 0, st, agg_ptr, agg_dofs, zoff, k, coff, Z, t, rc);
+void launch_sub_symv(int64_t n_items, const int32_t* items, const int64_t* sub_off, const int64_t* tp_off,
+                     const T* tiles, const T* rloc, const int64_t* scr_off, T* scr, hipStream_t st) {
+    if (n_items <= 0) return;
+    hipLaunchKernelGGL(k_sub_symv<T>, dim3((unsigned)n_items), dim3(WG), 0, st, items, sub_off, tp_off, tiles, rloc,
+                       scr_off, scr);
 }
 template <typename T>
-void launch_prolong(int32_t n_agg, const int64_t* agg_ptr, const int32_t* agg_dofs, const int64_t* zoff,
-                    const int32_t* k, const int64_t* coff, const T* Z, const T* ec, T* x, hipStream_t st) {
+void launch_sub_finalize(int64_t r0, int64_t r1, const int32_t* pos_sub, const int64_t* sub_off,
+                         const int64_t* scr_off, const T* scr, const int32_t* sub_dofs, T* x, hipStream_t st) {
+    if (r1 <= r0) return;
+    hipLaunchKernelGGL(k_sub_finalize<T>, dim3(grid_for(r1 - r0)), dim3(WG), 0, st, r0, r1, pos_sub, sub_off, scr_off,
+                       scr, sub_dofs, x);
+}
+
+void launch_pack_tiles(int32_t n_agg, const int64_t* sub_ptr, const int64_t* inv_off, const double* inv,
+                       const int64_t* tp_off, double* tiles, float* tiles32, hipStream_t st) {
     if (n_agg <= 0) return;
-    hipLaunchKernelGGL(k_prolong<T>, dim3(n_agg), dim3(WG), 0, st, agg_ptr, agg_dofs, zoff, k, coff, Z, ec, x);
+    hipLaunchKernelGGL(k_pack_tiles, dim3(64, n_agg), dim3(WG), 0, st, sub_ptr, inv_off, inv, tp_off, tiles, tiles32);
+}
+
+template <typename T>
+void launch_restrict(int64_t n_items, const int32_t* items, const int64_t* agg_ptr, const int32_t* agg_dofs,
+                     const int64_t* zoff, const int32_t* k, const int64_t* coff, const T* Zc, const T* t, T* rc,
+                     hipStream_t st) {
+    if (n_items <= 0) return;
+    hipLaunchKernelGGL(k_restrict<T>, dim3((unsigned)n_items), dim3(WG), 0, st, items, agg_ptr, agg_dofs, zoff, k, coff,
+                       Zc, t, rc);
+}
+template <typename T>
+void launch_prolong(int64_t n_items, const int32_t* items, const int64_t* agg_ptr, const int32_t* agg_dofs,
+                    const int64_t* zoff, const int32_t* k, const int64_t* coff, const T* Zc, const T* ec, T* x,
+                    hipStream_t st) {
+    if (n_items <= 0) return;
+    hipLaunchKernelGGL(k_prolong<T>, dim3((unsigned)n_items), dim3(WG), 0, st, items, agg_ptr, agg_dofs, zoff, k, coff,
+                       Zc, ec, x);
 }
 template <typename T>
 void launch_zero(int64_t n, T* x, hipStream_t st) {
@@ -908,8 +1113,10 @@ void launch_zero(int64_t n, T* x, hipStream_t st) {
     hipLaunchKernelGGL(k_zero<T>, dim3(grid_for(n)), dim3(WG), 0, st, n, x);
 }
 
-void launch_dense_gemv(int64_t n, const double* inv, const double* r, double* x, hipStream_t st) {
-    hipLaunchKernelGGL(k_dense_gemv, dim3((unsigned)((n + 63) / 64)), dim3(WG), 0, st, n, inv, r, x);
+void launch_dense_gemv(int64_t n, const double* inv, const double* r, double* x, double* part, hipStream_t st) {
+    const unsigned nchunk = (unsigned)((n + 1023) / 1024);
+    hipLaunchKernelGGL(k_dense_gemv, dim3((unsigned)((n + 127) / 128), nchunk), dim3(WG), 0, st, n, inv, r, part);
+    hipLaunchKernelGGL(k_chunk_sum, dim3(grid_for(n)), dim3(WG), 0, st, n, (int)nchunk, part, x);
 }
 
 void launch_dot(int64_t n, const double* a, const double* b, double* partials, double* out, hipStream_t st) {
@@ -946,10 +1153,14 @@ void launch_check_finite(int64_t n, const double* a, int32_t* flag, hipStream_t 
                                      hipStream_t);                                                                    \
     template void launch_sub_gemv<T>(int64_t, const int32_t*, const int64_t*, const int64_t*, const T*, const T*,    \
                                      const int32_t*, T*, hipStream_t);                                                \
-    template void launch_restrict<T>(int32_t, const int64_t*, const int32_t*, const int64_t*, const int32_t*,        \
-                                     const int64_t*, const T*, const T*, T*, hipStream_t);                            \
-    template void launch_prolong<T>(int32_t, const int64_t*, const int32_t*, const int64_t*, const int32_t*,         \
-                                    const int64_t*, const T*, const T*, T*, hipStream_t);                             \
+    template void launch_sub_symv<T>(int64_t, const int32_t*, const int64_t*, const int64_t*, const T*, const T*,    \
+                                     const int64_t*, T*, hipStream_t);                                                \
+    template void launch_sub_finalize<T>(int64_t, int64_t, const int32_t*, const int64_t*, const int64_t*, const T*, \
+                                         const int32_t*, T*, hipStream_t);                                            \
+    template void launch_restrict<T>(int64_t, const int32_t*, const int64_t*, const int32_t*, const int64_t*,        \
+                                     const int32_t*, const int64_t*, const T*, const T*, T*, hipStream_t);            \
+    template void launch_prolong<T>(int64_t, const int32_t*, const int64_t*, const int32_t*, const int64_t*,         \
+                                    const int32_t*, const int64_t*, const T*, const T*, T*, hipStream_t);             \
     template void launch_zero<T>(int64_t, T*, hipStream_t);
 LSDD_INST(double)
 LSDD_INST(float)

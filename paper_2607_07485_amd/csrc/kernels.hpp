@@ -55,8 +55,11 @@ void launch_elem_eig(int64_t n_elem, const int64_t* elem_ptr, const int64_t* blk
                      double* G, int32_t* ranks, int32_t* status, double* scratch, int64_t scratch_stride,
                      double rank_rtol, double spsd_tol, hipStream_t st);
 
-void launch_assemble_csr(int64_t n_blk, const int64_t* elem_ptr, const int32_t* elem_dofs, const int64_t* blk_off,
-                         const double* blocks, const int64_t* rowptr, const int32_t* col, double* val, hipStream_t st);
+// CSR values of sum_T R_T^T A_T R_T; d2e lists the (element, local index) pairs of every DOF, elements ascending
+void launch_assemble_rows(int64_t n, const int64_t* d2e_ptr, const int32_t* d2e_elem, const int32_t* d2e_loc,
+                          const int64_t* elem_ptr, const int32_t* elem_dofs, const int64_t* blk_off,
+                          const double* blocks, const int64_t* rowptr, const int32_t* col, double* val,
+                          hipStream_t st);
 
 void launch_local_assemble(int32_t nbatch, const LocalArgs& a, hipStream_t st);
 void launch_local_eig(int32_t nbatch, const LocalArgs& a, hipStream_t st);
@@ -67,7 +70,7 @@ void launch_views_symmetrize(int32_t nv, double* base, const View* v, hipStream_
 void launch_views_identity(int32_t nv, double* base, const View* v, hipStream_t st);
 
 void launch_z_compact(int32_t n_agg, const int64_t* agg_ptr, const int32_t* k, const int64_t* zst_off,
-                      const double* zst, const int64_t* zoff, double* Z, float* Z32, hipStream_t st);
+                      const double* zst, const int64_t* zoff, double* Z, double* Zc, float* Zc32, hipStream_t st);
 
 struct GalerkinArgs {
     int32_t n_groups;
@@ -108,14 +111,26 @@ template <typename T>
 void launch_sub_gemv(int64_t n_items, const int32_t* items, const int64_t* sub_off, const int64_t* inv_off,
                      const T* inv, const T* rloc, const int32_t* sub_dofs, T* x, hipStream_t st);
 template <typename T>
-void launch_restrict(int32_t n_agg, const int64_t* agg_ptr, const int32_t* agg_dofs, const int64_t* zoff,
-                     const int32_t* k, const int64_t* coff, const T* Z, const T* t, T* rc, hipStream_t st);
+void launch_sub_symv(int64_t n_items, const int32_t* items, const int64_t* sub_off, const int64_t* tp_off,
+                     const T* tiles, const T* rloc, const int64_t* scr_off, T* scr, hipStream_t st);
 template <typename T>
-void launch_prolong(int32_t n_agg, const int64_t* agg_ptr, const int32_t* agg_dofs, const int64_t* zoff,
-                    const int32_t* k, const int64_t* coff, const T* Z, const T* ec, T* x, hipStream_t st);
+void launch_sub_finalize(int64_t r0, int64_t r1, const int32_t* pos_sub, const int64_t* sub_off,
+                         const int64_t* scr_off, const T* scr, const int32_t* sub_dofs, T* x, hipStream_t st);
+void launch_pack_tiles(int32_t n_agg, const int64_t* sub_ptr, const int64_t* inv_off, const double* inv,
+                       const int64_t* tp_off, double* tiles, float* tiles32, hipStream_t st);
+// restriction items: (aggregate, first of 16 columns); prolongation items: (aggregate, first of 256 rows)
+template <typename T>
+void launch_restrict(int64_t n_items, const int32_t* items, const int64_t* agg_ptr, const int32_t* agg_dofs,
+                     const int64_t* zoff, const int32_t* k, const int64_t* coff, const T* Zc, const T* t, T* rc,
+                     hipStream_t st);
+template <typename T>
+void launch_prolong(int64_t n_items, const int32_t* items, const int64_t* agg_ptr, const int32_t* agg_dofs,
+                    const int64_t* zoff, const int32_t* k, const int64_t* coff, const T* Zc, const T* ec, T* x,
+                    hipStream_t st);
 template <typename T>
 void launch_zero(int64_t n, T* x, hipStream_t st);
-void launch_dense_gemv(int64_t n, const double* inv, const double* r, double* x, hipStream_t st);
+// x = M r; `part` holds ceil(n / 1024) * n doubles of chunk partial sums
+void launch_dense_gemv(int64_t n, const double* inv, const double* r, double* x, double* part, hipStream_t st);
 
 // PCG helpers (FP64).  `partials` holds at least 1024 doubles.
 void launch_dot(int64_t n, const double* a, const double* b, double* partials, double* out, hipStream_t st);

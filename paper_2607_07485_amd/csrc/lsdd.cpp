@@ -156,8 +156,12 @@ struct Level {
     int64_t* d_zoff = nullptr;
     int32_t* d_k = nullptr;
     int64_t* d_coff = nullptr;
-    double* d_Z = nullptr;
-    float* d_Z32 = nullptr;
+    double* d_Z = nullptr;        // row-major Z_i (Galerkin products, export)
+    double* d_Zc = nullptr;       // column-major Z_i (transfers)
+    float* d_Zc32 = nullptr;
+    int32_t* d_ritems = nullptr;  // restriction work items
+    int32_t* d_pitems = nullptr;  // prolongation work items
+    int64_t n_ritems = 0, n_pitems = 0;
     double* d_mu = nullptr;
     // smoother, sweep order (colour-major, aggregate index within a colour)
     std::vector<int32_t> sweep;
@@ -166,11 +170,17 @@ struct Level {
     std::vector<double> color_m2, color_m, color_nnz;   // sums of |Omega|^2, |Omega|, row nnz per colour
     int64_t* d_sw_sub_off = nullptr;
     int32_t* d_sw_sub_dofs = nullptr;
-    int64_t* d_sw_inv_off = nullptr;
-    int32_t* d_items = nullptr;
-    double* d_inv = nullptr;
-    float* d_inv32 = nullptr;
-    int64_t inv_len = 0;
+    int64_t* d_sw_tp_off = nullptr;   // packed-tile offset of each subdomain (sweep order)
+    int32_t* d_items = nullptr;       // (subdomain, tile row), grouped by colour
+    int32_t* d_pos_sub = nullptr;     // sweep-order subdomain of every Omega entry
+    int64_t* d_scr_off = nullptr;     // per subdomain: offset of its partial-sum scratch
+    double* scr64 = nullptr;
+    float* scr32 = nullptr;
+    double* d_cpart = nullptr;        // coarsest GEMV chunk partials
+    double* d_inv = nullptr;          // full inverses during setup only
+    double* d_tiles = nullptr;        // packed lower tiles of A_Omega^{-1}
+    float* d_tiles32 = nullptr;
+    int64_t inv_len = 0, tiles_len = 0;
     // coarsest
     double* d_cinv = nullptr;
     // vectors
@@ -274,8 +284,29 @@ void assemble_operator(lsdd_hierarchy* h, Level& lv) {
     lv.d_col = h->arena.upload(lv.pat.idx, h->st);
     lv.d_val = h->arena.alloc<double>(lv.nnz);
     HIPCHK(hipMemsetAsync(lv.d_val, 0, lv.nnz * sizeof(double), h->st));
-    launch_assemble_csr(lv.el.count(), lv.d_elem_ptr, lv.d_elem_dofs, lv.d_blk_off, lv.d_blocks, lv.d_rowptr,
-                        lv.d_col, lv.d_val, h->st);
+    {
+        // DOF -> (element, local index), elements ascending
+        std::vector<int64_t> dptr(lv.n + 1, 0);
+        for (int32_t d : lv.el.dofs) dptr[d + 1]++;
+        for (int64_t i = 0; i < lv.n; ++i) dptr[i + 1] += dptr[i];
+        std::vector<int32_t> de(lv.el.dofs.size()), dl(lv.el.dofs.size());
+        std::vector<int64_t> fill(dptr.begin(), dptr.end() - 1);
+        for (int64_t e = 0; e < lv.el.count(); ++e)
+            for (int64_t q = lv.el.ptr[e]; q < lv.el.ptr[e + 1]; ++q) {
+                int64_t t = fill[lv.el.dofs[q]]++;
+                de[t] = (int32_t)e;
+                dl[t] = (int32_t)(q - lv.el.ptr[e]);
+            }
+        int64_t* d_dptr = h->arena.upload(dptr, h->st);
+        int32_t* d_de = h->arena.upload(de, h->st);
+        int32_t* d_dl = h->arena.upload(dl, h->st);
+        launch_assemble_rows(lv.n, d_dptr, d_de, d_dl, lv.d_elem_ptr, lv.d_elem_dofs, lv.d_blk_off, lv.d_blocks,
+                             lv.d_rowptr, lv.d_col, lv.d_val, h->st);
+        HIPCHK(hipStreamSynchronize(h->st));
+        h->arena.release(d_dptr);
+        h->arena.release(d_de);
+        h->arena.release(d_dl);
+    }
     if (h->prm.precision == 1) {
         lv.d_val32 = h->arena.alloc<float>(lv.nnz);
         launch_to_f32(lv.nnz, lv.d_val, lv.d_val32, h->st);
@@ -327,6 +358,7 @@ void make_coarsest(lsdd_hierarchy* h, Level& lv) {
     vlog("coarsest level: n=%lld dense Cholesky + inverse %.3f s", (long long)lv.n, now_s() - t0);
     h->arena.release(W);
     if (hs != 0) throw Error(LSDD_E_NUMERIC, "coarsest-level Cholesky failed (matrix not SPD)");
+    lv.d_cpart = h->arena.alloc<double>((size_t)((lv.n + 1023) / 1024) * lv.n);
     alloc_vectors(h, lv, 0);
 }
 
@@ -593,8 +625,22 @@ std::unique_ptr<Level> coarsen(lsdd_hierarchy* h, Level& lv, const int32_t* agg_
     lv.d_coff = ar.upload(lv.coff, st);
     lv.d_zoff = ar.upload(lv.zoff, st);
     lv.d_Z = ar.alloc<double>(lv.zoff[n_agg]);
-    if (P.precision == 1) lv.d_Z32 = ar.alloc<float>(lv.zoff[n_agg]);
-    launch_z_compact(n_agg, lv.d_agg_ptr, lv.d_k, d_zst_off, d_zst, lv.d_zoff, lv.d_Z, lv.d_Z32, st);
+    lv.d_Zc = ar.alloc<double>(lv.zoff[n_agg]);
+    if (P.precision == 1) lv.d_Zc32 = ar.alloc<float>(lv.zoff[n_agg]);
+    launch_z_compact(n_agg, lv.d_agg_ptr, lv.d_k, d_zst_off, d_zst, lv.d_zoff, lv.d_Z, lv.d_Zc, lv.d_Zc32, st);
+    {
+        std::vector<int32_t> ri, pi;
+        for (int32_t i = 0; i < n_agg; ++i) {
+            const int32_t nw = (int32_t)(C.agg_ptr[i + 1] - C.agg_ptr[i]);
+            for (int32_t s0 = 0; s0 < lv.k[i]; s0 += 16) { ri.push_back(i); ri.push_back(s0); }
+            if (lv.k[i] > 0)
+                for (int32_t r0 = 0; r0 < nw; r0 += 256) { pi.push_back(i); pi.push_back(r0); }
+        }
+        lv.n_ritems = (int64_t)ri.size() / 2;
+        lv.n_pitems = (int64_t)pi.size() / 2;
+        lv.d_ritems = ar.upload(ri, st);
+        lv.d_pitems = ar.upload(pi, st);
+    }
     sync(st);
     ar.release(d_zst);
     // ---- smoother arrays in sweep order
@@ -603,23 +649,38 @@ std::unique_ptr<Level> coarsen(lsdd_hierarchy* h, Level& lv, const int32_t* agg_
     std::stable_sort(lv.sweep.begin(), lv.sweep.end(),
                      [&](int32_t a, int32_t b) { return lv.colors[a] < lv.colors[b]; });
     std::vector<int32_t> sw_dofs;
-    std::vector<int64_t> sw_inv_off(n_agg);
+    std::vector<int64_t> tp_agg(n_agg + 1, 0), sw_tp_off(n_agg);
+    for (int32_t i = 0; i < n_agg; ++i) {
+        int64_t nt = (C.sub_ptr[i + 1] - C.sub_ptr[i] + 63) / 64;
+        tp_agg[i + 1] = tp_agg[i] + nt * (nt + 1) / 2 * 4096;
+    }
+    lv.tiles_len = tp_agg[n_agg];
     std::vector<int32_t> items;
     lv.sw_sub_off.assign(1, 0);
     lv.color_row0.assign(lv.n_colors + 1, 0);
     lv.color_item0.assign(lv.n_colors + 1, 0);
     for (int32_t s = 0; s < n_agg; ++s) {
         int32_t i = lv.sweep[s];
-        int64_t m = C.sub_ptr[i + 1] - C.sub_ptr[i];
         sw_dofs.insert(sw_dofs.end(), C.sub_dofs.begin() + C.sub_ptr[i], C.sub_dofs.begin() + C.sub_ptr[i + 1]);
         lv.sw_sub_off.push_back((int64_t)sw_dofs.size());
-        sw_inv_off[s] = msq[i];
-        for (int64_t c0 = 0; c0 < m; c0 += 64) {
-            items.push_back(s);
-            items.push_back((int32_t)c0);
-        }
+        sw_tp_off[s] = tp_agg[i];
         int32_t c = lv.colors[i];
         lv.color_row0[c + 1] = (int64_t)sw_dofs.size();
+    }
+    // work items per colour: (subdomain, tile row), longest tile rows first
+    for (int32_t c = 0; c < lv.n_colors; ++c) {
+        std::vector<std::pair<int32_t, int32_t>> it;
+        for (int32_t s = 0; s < n_agg; ++s) {
+            if (lv.colors[lv.sweep[s]] != c) continue;
+            int32_t nt = (int32_t)((lv.sw_sub_off[s + 1] - lv.sw_sub_off[s] + 63) / 64);
+            for (int32_t I = 0; I < nt; ++I) it.emplace_back(I, s);
+        }
+        std::stable_sort(it.begin(), it.end(), [](const std::pair<int32_t, int32_t>& a,
+                                                  const std::pair<int32_t, int32_t>& b) { return a.first > b.first; });
+        for (auto& pr : it) {
+            items.push_back(pr.second);
+            items.push_back(pr.first);
+        }
         lv.color_item0[c + 1] = (int64_t)items.size() / 2;
     }
     for (int32_t c = 0; c < lv.n_colors; ++c) {
@@ -631,7 +692,7 @@ std::unique_ptr<Level> coarsen(lsdd_hierarchy* h, Level& lv, const int32_t* agg_
     lv.color_nnz.assign(lv.n_colors, 0.0);
     for (int32_t i = 0; i < n_agg; ++i) {
         double m = (double)(C.sub_ptr[i + 1] - C.sub_ptr[i]);
-        lv.color_m2[lv.colors[i]] += m * m;
+        lv.color_m2[lv.colors[i]] += m * (m + 1.0) / 2.0;     // entries of the symmetric inverse
         lv.color_m[lv.colors[i]] += m;
         for (int64_t q = C.sub_ptr[i]; q < C.sub_ptr[i + 1]; ++q) {
             int32_t d = C.sub_dofs[q];
@@ -640,11 +701,31 @@ std::unique_ptr<Level> coarsen(lsdd_hierarchy* h, Level& lv, const int32_t* agg_
     }
     lv.d_sw_sub_off = ar.upload(lv.sw_sub_off, st);
     lv.d_sw_sub_dofs = ar.upload(sw_dofs, st);
-    lv.d_sw_inv_off = ar.upload(sw_inv_off, st);
+    lv.d_sw_tp_off = ar.upload(sw_tp_off, st);
     lv.d_items = ar.upload(items, st);
-    if (P.precision == 1) {
-        lv.d_inv32 = ar.alloc<float>(lv.inv_len);
-        launch_to_f32(lv.inv_len, lv.d_inv, lv.d_inv32, st);
+    {
+        std::vector<int32_t> pos_sub(sw_dofs.size());
+        std::vector<int64_t> scr_off(n_agg + 1, 0);
+        for (int32_t s = 0; s < n_agg; ++s) {
+            for (int64_t q = lv.sw_sub_off[s]; q < lv.sw_sub_off[s + 1]; ++q) pos_sub[q] = s;
+            int64_t nt = (lv.sw_sub_off[s + 1] - lv.sw_sub_off[s] + 63) / 64;
+            scr_off[s + 1] = scr_off[s] + (nt + nt * (nt - 1) / 2) * 64;
+        }
+        lv.d_pos_sub = ar.upload(pos_sub, st);
+        lv.d_scr_off = ar.upload(scr_off, st);
+        lv.scr64 = ar.alloc<double>(scr_off[n_agg]);
+        if (P.precision == 1) lv.scr32 = ar.alloc<float>(scr_off[n_agg]);
+    }
+    {
+        int64_t* d_tp_agg = ar.upload(tp_agg, st);
+        lv.d_tiles = ar.alloc<double>(lv.tiles_len);
+        if (P.precision == 1) lv.d_tiles32 = ar.alloc<float>(lv.tiles_len);
+        launch_pack_tiles(n_agg, d_sub_ptr, d_inv_off, lv.d_inv, d_tp_agg, lv.d_tiles, lv.d_tiles32, st);
+        HIPCHK(hipGetLastError());
+        sync(st);
+        ar.release(d_tp_agg);
+        ar.release(lv.d_inv);
+        lv.d_inv = nullptr;
     }
     alloc_vectors(h, lv, (int64_t)sw_dofs.size());
     // free local-problem inputs that the solve does not use
@@ -748,8 +829,9 @@ struct LvVec<double> {
     static double* t(Level& l) { return l.t64; }
     static double* rloc(Level& l) { return l.rloc64; }
     static const double* val(Level& l) { return l.d_val; }
-    static const double* Z(Level& l) { return l.d_Z; }
-    static const double* inv(Level& l) { return l.d_inv; }
+    static const double* Z(Level& l) { return l.d_Zc; }
+    static const double* inv(Level& l) { return l.d_tiles; }
+    static double* scr(Level& l) { return l.scr64; }
 };
 template <>
 struct LvVec<float> {
@@ -758,8 +840,9 @@ struct LvVec<float> {
     static float* t(Level& l) { return l.t32; }
     static float* rloc(Level& l) { return l.rloc32; }
     static const float* val(Level& l) { return l.d_val32; }
-    static const float* Z(Level& l) { return l.d_Z32; }
-    static const float* inv(Level& l) { return l.d_inv32; }
+    static const float* Z(Level& l) { return l.d_Zc32; }
+    static const float* inv(Level& l) { return l.d_tiles32; }
+    static float* scr(Level& l) { return l.scr32; }
 };
 
 template <typename T>
@@ -778,10 +861,12 @@ void sweep(lsdd_hierarchy* h, Level& lv, const T* r, T* x, bool forward, bool x_
                                      V::rloc(lv) + r0, xz, h->st);
         });
         const double gb = lv.color_m2[c] * w + lv.color_m[c] * (4 + 3 * w);
-        traced(h, "sub_gemv", gb, [&] {
-            launch_sub_gemv<T>(i1 - i0, lv.d_items + 2 * i0, lv.d_sw_sub_off, lv.d_sw_inv_off, V::inv(lv),
-                               V::rloc(lv), lv.d_sw_sub_dofs, x, h->st);
+        traced(h, "sub_symv", gb, [&] {
+            launch_sub_symv<T>(i1 - i0, lv.d_items + 2 * i0, lv.d_sw_sub_off, lv.d_sw_tp_off, V::inv(lv),
+                               V::rloc(lv), lv.d_scr_off, V::scr(lv), h->st);
         });
+        launch_sub_finalize<T>(r0, r1, lv.d_pos_sub, lv.d_sw_sub_off, lv.d_scr_off, V::scr(lv), lv.d_sw_sub_dofs, x,
+                               h->st);
     }
 }
 
@@ -793,10 +878,12 @@ void vcycle(lsdd_hierarchy* h, size_t l, const T* r, T* x) {
     if (lv.coarsest) {
         const double nb = (double)lv.n * lv.n * 8.0 + 2.0 * lv.n * 8.0;
         if constexpr (std::is_same<T, double>::value) {
-            traced(h, "coarse_gemv", nb, [&] { launch_dense_gemv(lv.n, lv.d_cinv, r, x, h->st); });
+            traced(h, "coarse_gemv", nb, [&] { launch_dense_gemv(lv.n, lv.d_cinv, r, x, lv.d_cpart, h->st); });
         } else {
             launch_to_f64(lv.n, r, lv.cr64, h->st);
-            traced(h, "coarse_gemv", nb, [&] { launch_dense_gemv(lv.n, lv.d_cinv, lv.cr64, lv.cx64, h->st); });
+            traced(h, "coarse_gemv", nb, [&] {
+                launch_dense_gemv(lv.n, lv.d_cinv, lv.cr64, lv.cx64, lv.d_cpart, h->st);
+            });
             launch_to_f32(lv.n, lv.cx64, x, h->st);
         }
         return;
@@ -809,13 +896,13 @@ void vcycle(lsdd_hierarchy* h, size_t l, const T* r, T* x) {
     });
     const double zb = (double)lv.zoff.back() * w + (double)lv.n * (4 + w) + (double)nx.n * w;
     traced(h, "restrict", zb, [&] {
-        launch_restrict<T>(lv.cl.n_agg, lv.d_agg_ptr, lv.d_agg_dofs, lv.d_zoff, lv.d_k, lv.d_coff, V::Z(lv),
-                           V::t(lv), V::r(nx), h->st);
+        launch_restrict<T>(lv.n_ritems, lv.d_ritems, lv.d_agg_ptr, lv.d_agg_dofs, lv.d_zoff, lv.d_k, lv.d_coff,
+                           V::Z(lv), V::t(lv), V::r(nx), h->st);
     });
     vcycle<T>(h, l + 1, V::r(nx), V::x(nx));
     traced(h, "prolong", zb + (double)lv.n * w, [&] {
-        launch_prolong<T>(lv.cl.n_agg, lv.d_agg_ptr, lv.d_agg_dofs, lv.d_zoff, lv.d_k, lv.d_coff, V::Z(lv),
-                          V::x(nx), x, h->st);
+        launch_prolong<T>(lv.n_pitems, lv.d_pitems, lv.d_agg_ptr, lv.d_agg_dofs, lv.d_zoff, lv.d_k, lv.d_coff,
+                          V::Z(lv), V::x(nx), x, h->st);
     });
     sweep<T>(h, lv, r, x, false, false);
 }

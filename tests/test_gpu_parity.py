@@ -235,3 +235,22 @@ def test_error_paths_on_device(dev):
         assert ei.value.code == 1
     finally:
         h.close()
+
+
+def test_setup_and_solve_are_bitwise_reproducible(dev):
+    """Every reduction has a fixed order: two setups and solves give identical bits."""
+    P = _lsdd()
+    rng = np.random.default_rng(4)
+    N = 10
+    prob = fegen.graddiv_rtcf3(N, kappa=np.exp(rng.standard_normal(N * N)), beta=1e-4)
+    b = torch.from_numpy(rng.standard_normal(prob.n)).to(dev)
+    kw = dict(max_levels=3, tau_const=0.75, max_density=1.0, agg_passes=1, agg_passes_coarse=1)
+    xs = []
+    for _ in range(2):
+        with P.Hierarchy.setup_problem(prob, P.Params.default(**kw)) as h:
+            x, _ = h.solve(b)
+            z1 = h.vcycle(b)
+            z2 = h.vcycle(b)
+            assert torch.equal(z1, z2)
+            xs.append(x.cpu().numpy())
+    assert np.array_equal(xs[0], xs[1])
