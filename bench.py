@@ -33,6 +33,17 @@ sys.path.insert(0, ROOT)
 METRIC = "solve DOF/s to 1e-8 rel residual + setup s; FP32-cycle vs FP64, 1 MI355X"
 HBM_PEAK_GBS = 8000.0
 
+# HBM bytes per launch of the dominant solve kernel, from rocprofv3 FETCH_SIZE and WRITE_SIZE
+# runs of this bench (FP64 cycle, 128 x 128) scaled by a 1 GiB device-copy calibration (read
+# factor 2.0, write factor 1.0).  Valid only for the kernel source these counters were taken on.
+TRAFFIC = {("sub_symv", "graddiv_rtcf3_128x128", "f64"): ("7380094f6174f17c", 2.599e8)}
+
+
+def _kernels_hash():
+    import hashlib
+    path = os.path.join(ROOT, "paper_2607_07485_amd", "csrc", "kernels.hip")
+    return hashlib.sha256(open(path, "rb").read()).hexdigest()[:16]
+
 
 def _params(P, **kw):
     base = dict(max_levels=3, tau_const=0.75, agg_passes=2, agg_passes_coarse=1, precision=1, rtol=1e-8)
@@ -90,6 +101,8 @@ def main():
     ap.add_argument("--N", type=int, default=128)
     ap.add_argument("--cpu-sample", type=int, default=16)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a device copy of 1 GiB five times (HBM counter calibration for profiling)")
     a = ap.parse_args()
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py: this build measures one GPU only (the hot path has no multi-GPU leg); "
@@ -97,6 +110,15 @@ def main():
         sys.exit(2)
 
     import torch
+
+    if a.copy_calibration:
+        src = torch.ones(1 << 27, dtype=torch.float64, device="cuda:0")      # 1 GiB
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes_per_copy": src.numel() * 8, "copies": 5}))
+        return
 
     import fegen
     import paper_2607_07485_amd as P
@@ -166,17 +188,21 @@ def main():
         cb = cpu_baseline(a.cpu_sample)
         print(f"[bench] cpu baseline {cb['sample']}", file=sys.stderr, flush=True)
 
+    workload = f"graddiv_rtcf3_{a.N}x{a.N}"
+    rec = TRAFFIC.get((dname, workload, "f32" if use32 else "f64"))
+    traffic = rec[1] if rec is not None and rec[0] == _kernels_hash() else None
     res = {
         "metric": METRIC, "value": prob.n / dt, "unit": "DOF/s", "n_gpus": 1, "steps": a.steps,
         "warmup": a.warmup, "ms_per_step": dt * 1e3, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32+f64" if use32 else "f64", "data": "synthetic",
-        "config": {"workload": f"graddiv_rtcf3_{a.N}x{a.N}", "n_dofs": prob.n, "levels": info["n"],
+        "config": {"workload": workload, "n_dofs": prob.n, "levels": info["n"],
                    "oc": round(info["oc"], 3), "gc": round(info["gc"], 3), "rtol": 1e-8,
                    "cycle": "FP32 V-cycle in FP64 PCG" if use32 else "FP64 V-cycle in FP64 PCG"},
         "setup_s": setup_s,
         **out,
         "roofline": {"bound": "hbm", "kernel": dname, "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "algorithmic_bytes_per_launch": d["bytes"] / max(d["launches"], 1),
                      "avg_launch_us": d["ms"] * 1e3 / max(d["launches"], 1)},
         "kernels": kernels,
         "cpu_baseline": None if cb is None else {k: cb[k] for k in ("value", "unit", "cores", "kind", "sample")},
