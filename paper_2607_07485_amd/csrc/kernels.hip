@@ -11,6 +11,7 @@
 
 #include <cfloat>
 #include <cmath>
+#include <vector>
 
 #include "batched.hpp"
 #include "dense.hpp"
@@ -603,109 +604,110 @@ __global__ void k_to_f64(int64_t n, const float* a, double* b) {
 
 // ====================================================================== solve kernels
 
-// out[t] = r[rows[t]] - sum_q A[rows[t], q] x[q]  (16 lanes per row)
-template <typename T>
+// out[t] = r[rows[t]] - sum_q A[rows[t], q] x[q]; L lanes per row (16 for
+// short rows, a whole wave for the long rows of coarse levels)
+template <typename T, int L>
 __global__ void __launch_bounds__(WG) k_csr_resid_rows(int64_t nrows, const int32_t* rows, const int64_t* rowptr,
                                                        const int32_t* col, const T* val, const T* x, const T* r,
                                                        T* out, int x_zero) {
-    const int lane = tid() & 15;
-    const int64_t t = ((int64_t)blockIdx.x * WG + tid()) >> 4;
-    if (t >= nrows) return;
-    const int32_t p = rows[t];
-    T s = 0;
-    if (!x_zero) {
-        for (int64_t q = rowptr[p] + lane; q < rowptr[p + 1]; q += 16) s += val[q] * x[col[q]];
+    const int lane = tid() & (L - 1);
+    const int64_t stride = (int64_t)gridDim.x * (WG / L);
+    for (int64_t t = ((int64_t)blockIdx.x * WG + tid()) / L; t < nrows; t += stride) {
+        const int32_t p = rows[t];
+        T s = 0;
+        if (!x_zero) {
+            const int64_t q1 = rowptr[p + 1];
+            int64_t q = rowptr[p] + lane;
+            T s1 = 0;
+            for (; q + L < q1; q += 2 * L) {
+                s += val[q] * x[col[q]];
+                s1 += val[q + L] * x[col[q + L]];
+            }
+            if (q < q1) s += val[q] * x[col[q]];
+            s += s1;
+        }
+        for (int off = L / 2; off > 0; off >>= 1) s += __shfl_xor(s, off, L);
+        if (lane == 0) out[t] = r[p] - s;
     }
-    for (int off = 8; off > 0; off >>= 1) s += __shfl_xor(s, off, 16);
-    if (lane == 0) out[t] = r[p] - s;
 }
 
 // y = A x, or y = r_minus - A x when r_minus != nullptr
-template <typename T>
+template <typename T, int L>
 __global__ void __launch_bounds__(WG) k_csr_spmv(int64_t n, const int64_t* rowptr, const int32_t* col, const T* val,
                                                  const T* x, T* y, const T* r_minus) {
-    const int lane = tid() & 15;
-    const int64_t p = ((int64_t)blockIdx.x * WG + tid()) >> 4;
-    if (p >= n) return;
-    T s = 0;
-    for (int64_t q = rowptr[p] + lane; q < rowptr[p + 1]; q += 16) s += val[q] * x[col[q]];
-    for (int off = 8; off > 0; off >>= 1) s += __shfl_xor(s, off, 16);
-    if (lane == 0) y[p] = r_minus ? r_minus[p] - s : s;
-}
-
-// Subdomain correction x[Omega_s] += A_Omega_s^{-1} rloc_s for one 64-column
-// panel of one subdomain per workgroup: lane = column, waves split the rows.
-template <typename T>
-__global__ void __launch_bounds__(WG) k_sub_gemv(const int32_t* items, const int64_t* sub_off, const int64_t* inv_off,
-                                                 const T* inv, const T* rloc, const int32_t* sub_dofs, T* x) {
-    __shared__ T s_r[4096];
-    __shared__ T s_acc[WG];
-    const int s = items[2 * blockIdx.x];
-    const int col0 = items[2 * blockIdx.x + 1];
-    const int64_t o = sub_off[s];
-    const int m = (int)(sub_off[s + 1] - o);
-    const T* R = rloc + o;
-    for (int a = tid(); a < m; a += WG) s_r[a] = R[a];
-    __syncthreads();
-    const int lane = tid() & 63, w = tid() >> 6;
-    const int j = col0 + lane;
-    const T* M = inv + inv_off[s];
-    T acc = 0;
-    if (j < m) {
-        int a = w;
-        for (; a + 12 < m; a += 16) {
-            T v0 = M[(int64_t)a * m + j];
-            T v1 = M[(int64_t)(a + 4) * m + j];
-            T v2 = M[(int64_t)(a + 8) * m + j];
-            T v3 = M[(int64_t)(a + 12) * m + j];
-            acc += v0 * s_r[a] + v1 * s_r[a + 4] + v2 * s_r[a + 8] + v3 * s_r[a + 12];
+    const int lane = tid() & (L - 1);
+    const int64_t stride = (int64_t)gridDim.x * (WG / L);
+    for (int64_t p = ((int64_t)blockIdx.x * WG + tid()) / L; p < n; p += stride) {
+        const int64_t q1 = rowptr[p + 1];
+        int64_t q = rowptr[p] + lane;
+        T s = 0, s1 = 0;
+        for (; q + L < q1; q += 2 * L) {
+            s += val[q] * x[col[q]];
+            s1 += val[q + L] * x[col[q + L]];
         }
-        for (; a < m; a += 4) acc += M[(int64_t)a * m + j] * s_r[a];
-    }
-    s_acc[tid()] = acc;
-    __syncthreads();
-    if (w == 0 && j < m) {
-        T y = s_acc[lane] + s_acc[64 + lane] + s_acc[128 + lane] + s_acc[192 + lane];
-        x[sub_dofs[o + j]] += y;
+        if (q < q1) s += val[q] * x[col[q]];
+        s += s1;
+        for (int off = L / 2; off > 0; off >>= 1) s += __shfl_xor(s, off, L);
+        if (lane == 0) y[p] = r_minus ? r_minus[p] - s : s;
     }
 }
 
 // Subdomain correction with the packed symmetric inverse: A_Omega^{-1} is stored
 // as its lower 64 x 64 tiles (tile (I, J), I >= J, row-major inside the tile,
 // zero-padded past |Omega|; the diagonal tiles hold both triangles).  Work item
-// = (subdomain, tile row I): waves split the 64 rows of the tile row, lanes the
-// 64 columns.  Tile (I, J) is read once and used twice: its rows give
-// y_I += T x_J (per-lane partials, reduced across lanes once per item) and its
-// columns give y_J += T^T x_I (J < I; summed over the waves in LDS).  Partial
-// results go to a per-subdomain scratch (row parts: nt x 64, column parts:
-// nt(nt-1)/2 x 64) that k_sub_finalize sums in a fixed order, so the smoother is
-// the same linear map on every application (no order-dependent atomics).
+// = (subdomain, tile row I, chunk of up to SYMV_CH tiles J): waves split the 64
+// rows of the tile row, lanes the 64 columns.  Tile (I, J) is read once and
+// used twice: its rows give y_I += T x_J (per-lane partials, reduced across
+// lanes once per item) and its columns give y_J += T^T x_I (J < I; summed over
+// the waves in LDS).  Partial results go to a per-subdomain scratch -- row
+// parts per (tile row, chunk), column parts per tile -- that k_sub_finalize
+// sums in a fixed order, so the smoother is the same linear map on every
+// application (no order-dependent atomics).
+constexpr int SYMV_CH = 8;
+
+__host__ __device__ inline int64_t symv_rowpart_off(int I) {
+    // chunks of tile rows 0..I-1: sum_{i<I} ceil((i+1)/CH)
+    int64_t full = I / SYMV_CH, rem = I % SYMV_CH;
+    return SYMV_CH * full * (full + 1) / 2 + rem * (full + 1);
+}
+__host__ __device__ inline int64_t symv_scratch_len(int nt) {
+    return (symv_rowpart_off(nt) + (int64_t)nt * (nt - 1) / 2) * 64;
+}
+
 template <typename T>
 __global__ void __launch_bounds__(WG) k_sub_symv(const int32_t* items, const int64_t* sub_off, const int64_t* tp_off,
                                                  const T* tiles, const T* rloc, const int64_t* scr_off, T* scr) {
-    __shared__ T s_r[4096];
+    __shared__ T s_x[SYMV_CH * 64];
     __shared__ T s_c[4][64];
-    const int s = items[2 * blockIdx.x];
-    const int I = items[2 * blockIdx.x + 1];
+    const int s = items[3 * blockIdx.x];
+    const int I = items[3 * blockIdx.x + 1];
+    const int ch = items[3 * blockIdx.x + 2];
     const int64_t o = sub_off[s];
     const int m = (int)(sub_off[s + 1] - o);
     const int nt = (m + 63) >> 6;
-    const int mt = nt << 6;
-    for (int a = tid(); a < mt; a += WG) s_r[a] = a < m ? rloc[o + a] : (T)0;
-    __syncthreads();
+    const int J0 = ch * SYMV_CH;
+    const int J1 = min(J0 + SYMV_CH, I + 1);
+    for (int a = tid(); a < (J1 - J0) * 64; a += WG) {
+        int c = J0 * 64 + a;
+        s_x[a] = c < m ? rloc[o + c] : (T)0;
+    }
     const int lane = tid() & 63, w = tid() >> 6;
+    T xi[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+        int r = I * 64 + w + 4 * q;
+        xi[q] = r < m ? rloc[o + r] : (T)0;
+    }
+    __syncthreads();
     const T* row0 = tiles + tp_off[s] + (int64_t)(I * (I + 1) / 2) * 4096;
-    T* rowpart = scr + scr_off[s];
-    T* colpart = rowpart + (int64_t)nt * 64;
+    T* part = scr + scr_off[s];
+    T* colpart = part + symv_rowpart_off(nt) * 64;
     T p[16];
 #pragma unroll
     for (int q = 0; q < 16; ++q) p[q] = 0;
-    T xi[16];
-#pragma unroll
-    for (int q = 0; q < 16; ++q) xi[q] = s_r[I * 64 + w + 4 * q];
-    for (int J = 0; J <= I; ++J) {
+    for (int J = J0; J < J1; ++J) {
         const T* t = row0 + (int64_t)J * 4096 + lane;
-        const T xj = s_r[J * 64 + lane];
+        const T xj = s_x[(J - J0) * 64 + lane];
         T v[16];
 #pragma unroll
         for (int q = 0; q < 16; ++q) v[q] = t[(w + 4 * q) * 64];
@@ -735,15 +737,15 @@ __global__ void __launch_bounds__(WG) k_sub_symv(const int32_t* items, const int
 #pragma unroll
         for (int q = 0; q < 16; ++q)
             if (q == lane) y = p[q];
-        rowpart[(int64_t)I * 64 + w + 4 * lane] = y;
+        part[(symv_rowpart_off(I) + ch) * 64 + w + 4 * lane] = y;
     }
 }
 
-// x[Omega_s[c]] += row part of tile J(c) + column parts of the tile rows below,
-// in ascending tile-row order; one thread per subdomain DOF of the colour.
+// x[Omega_s[c]] (+)= row-part chunks of tile row J(c) + column parts of the
+// tile rows below, in ascending order; one thread per subdomain DOF.
 template <typename T>
 __global__ void k_sub_finalize(int64_t r0, int64_t r1, const int32_t* pos_sub, const int64_t* sub_off,
-                               const int64_t* scr_off, const T* scr, const int32_t* sub_dofs, T* x) {
+                               const int64_t* scr_off, const T* scr, const int32_t* sub_dofs, T* x, int accumulate) {
     const int64_t t = r0 + (int64_t)blockIdx.x * WG + tid();
     if (t >= r1) return;
     const int s = pos_sub[t];
@@ -751,11 +753,14 @@ __global__ void k_sub_finalize(int64_t r0, int64_t r1, const int32_t* pos_sub, c
     const int c = (int)(t - o);
     const int nt = (int)((sub_off[s + 1] - o + 63) >> 6);
     const int J = c >> 6, l = c & 63;
-    const T* rowpart = scr + scr_off[s];
-    const T* colpart = rowpart + (int64_t)nt * 64;
-    T y = rowpart[c];
+    const T* part = scr + scr_off[s];
+    const T* colpart = part + symv_rowpart_off(nt) * 64;
+    const int nch = (J + SYMV_CH) / SYMV_CH;
+    T y = 0;
+    for (int chn = 0; chn < nch; ++chn) y += part[(symv_rowpart_off(J) + chn) * 64 + l];
     for (int I = J + 1; I < nt; ++I) y += colpart[((int64_t)I * (I - 1) / 2 + J) * 64 + l];
-    x[sub_dofs[t]] += y;
+    const int32_t d = sub_dofs ? sub_dofs[t] : (int32_t)t;
+    x[d] = accumulate ? x[d] + y : y;
 }
 
 // Pack full m x m symmetric inverses (aggregate order, column-major) into the
@@ -770,7 +775,8 @@ __global__ void k_pack_tiles(const int64_t* sub_ptr, const int64_t* inv_off, con
     for (int64_t idx = (int64_t)blockIdx.x * WG + tid(); idx < ntile * 4096; idx += (int64_t)gridDim.x * WG) {
         int64_t t = idx >> 12;
         int e = (int)(idx & 4095);
-        int I = 0;
+        int I = (int)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
+        while ((int64_t)I * (I + 1) / 2 > t) --I;
         while ((int64_t)(I + 1) * (I + 2) / 2 <= t) ++I;
         int J = (int)(t - (int64_t)I * (I + 1) / 2);
         int r = I * 64 + (e >> 6), c = J * 64 + (e & 63);
@@ -835,59 +841,6 @@ __global__ void __launch_bounds__(WG) k_prolong(const int32_t* items, const int6
 template <typename T>
 __global__ void k_zero(int64_t n, T* x) {
     for (int64_t i = blockIdx.x * (int64_t)WG + tid(); i < n; i += (int64_t)gridDim.x * WG) x[i] = 0;
-}
-
-// x = M r for the dense symmetric coarsest inverse: work item = (128-column
-// panel, 1024-row chunk); each lane owns two adjacent columns (two 8-byte loads,
-// valid for any n), waves split the rows; each chunk writes its partial sums to
-// part[chunk * n + j] and k_chunk_sum adds the chunks in ascending order.
-__global__ void __launch_bounds__(WG) k_dense_gemv(int64_t n, const double* M, const double* r, double* part) {
-    __shared__ double s_r[1024];
-    __shared__ double s_a0[WG], s_a1[WG];
-    const int lane = tid() & 63, w = tid() >> 6;
-    const int64_t j = (int64_t)blockIdx.x * 128 + 2 * lane;
-    const int64_t r0 = (int64_t)blockIdx.y * 1024;
-    const int64_t r1 = r0 + 1024 < n ? r0 + 1024 : n;
-    for (int64_t a = r0 + tid(); a < r1; a += WG) s_r[a - r0] = r[a];
-    __syncthreads();
-    double a0 = 0.0, a1 = 0.0;
-    if (j + 1 < n) {
-        int64_t a = r0 + w;
-        for (; a + 12 < r1; a += 16) {
-            const double* p0 = M + a * n + j;
-            const double* p1 = p0 + 4 * n;
-            const double* p2 = p0 + 8 * n;
-            const double* p3 = p0 + 12 * n;
-            double x00 = p0[0], x01 = p0[1], x10 = p1[0], x11 = p1[1];
-            double x20 = p2[0], x21 = p2[1], x30 = p3[0], x31 = p3[1];
-            double q0 = s_r[a - r0], q1 = s_r[a + 4 - r0], q2 = s_r[a + 8 - r0], q3 = s_r[a + 12 - r0];
-            a0 += x00 * q0 + x10 * q1 + x20 * q2 + x30 * q3;
-            a1 += x01 * q0 + x11 * q1 + x21 * q2 + x31 * q3;
-        }
-        for (; a < r1; a += 4) {
-            const double* p = M + a * n + j;
-            a0 += p[0] * s_r[a - r0];
-            a1 += p[1] * s_r[a - r0];
-        }
-    } else if (j < n) {
-        for (int64_t a = r0 + w; a < r1; a += 4) a0 += M[a * n + j] * s_r[a - r0];
-    }
-    s_a0[tid()] = a0;
-    s_a1[tid()] = a1;
-    __syncthreads();
-    if (w == 0 && j < n) {
-        double* out = part + (int64_t)blockIdx.y * n;
-        out[j] = (s_a0[lane] + s_a0[64 + lane]) + (s_a0[128 + lane] + s_a0[192 + lane]);
-        if (j + 1 < n) out[j + 1] = (s_a1[lane] + s_a1[64 + lane]) + (s_a1[128 + lane] + s_a1[192 + lane]);
-    }
-}
-
-__global__ void k_chunk_sum(int64_t n, int nchunk, const double* part, double* x) {
-    for (int64_t j = blockIdx.x * (int64_t)WG + tid(); j < n; j += (int64_t)gridDim.x * WG) {
-        double s = 0.0;
-        for (int c = 0; c < nchunk; ++c) s += part[(int64_t)c * n + j];
-        x[j] = s;
-    }
 }
 
 // ---------------------------------------------------------------- PCG helpers
@@ -1052,23 +1005,25 @@ void launch_to_f64(int64_t n, const float* a, double* b, hipStream_t st) {
 
 template <typename T>
 void launch_csr_resid_rows(int64_t nrows, const int32_t* rows, const int64_t* rowptr, const int32_t* col, const T* val,
-                           const T* x, const T* r, T* out, bool x_zero, hipStream_t st) {
+                           const T* x, const T* r, T* out, bool x_zero, int lanes, hipStream_t st) {
     if (nrows <= 0) return;
-    hipLaunchKernelGGL(k_csr_resid_rows<T>, dim3(grid_for(nrows * 16)), dim3(WG), 0, st, nrows, rows, rowptr, col, val,
-                       x, r, out, x_zero ? 1 : 0);
+    if (lanes >= 64)
+        hipLaunchKernelGGL((k_csr_resid_rows<T, 64>), dim3(grid_for(nrows * 64)), dim3(WG), 0, st, nrows, rows, rowptr,
+                           col, val, x, r, out, x_zero ? 1 : 0);
+    else
+        hipLaunchKernelGGL((k_csr_resid_rows<T, 16>), dim3(grid_for(nrows * 16)), dim3(WG), 0, st, nrows, rows, rowptr,
+                           col, val, x, r, out, x_zero ? 1 : 0);
 }
 template <typename T>
 void launch_csr_spmv(int64_t n, const int64_t* rowptr, const int32_t* col, const T* val, const T* x, T* y,
-                     const T* r_minus, hipStream_t st) {
+                     const T* r_minus, int lanes, hipStream_t st) {
     if (n <= 0) return;
-    hipLaunchKernelGGL(k_csr_spmv<T>, dim3(grid_for(n * 16)), dim3(WG), 0, st, n, rowptr, col, val, x, y, r_minus);
-}
-template <typename T>
-void launch_sub_gemv(int64_t n_items, const int32_t* items, const int64_t* sub_off, const int64_t* inv_off,
-                     const T* inv, const T* rloc, const int32_t* sub_dofs, T* x, hipStream_t st) {
-    if (n_items <= 0) return;
-    hipLaunchKernelGGL(k_sub_gemv<T>, dim3((unsigned)n_items), dim3(WG), 0, st, items, sub_off, inv_off, inv, rloc,
-                       sub_dofs, x);
+    if (lanes >= 64)
+        hipLaunchKernelGGL((k_csr_spmv<T, 64>), dim3(grid_for(n * 64)), dim3(WG), 0, st, n, rowptr, col, val, x, y,
+                           r_minus);
+    else
+        hipLaunchKernelGGL((k_csr_spmv<T, 16>), dim3(grid_for(n * 16)), dim3(WG), 0, st, n, rowptr, col, val, x, y,
+                           r_minus);
 }
 template <typename T>
 void launch_sub_symv(int64_t n_items, const int32_t* items, const int64_t* sub_off, const int64_t* tp_off,
@@ -1079,16 +1034,30 @@ void launch_sub_symv(int64_t n_items, const int32_t* items, const int64_t* sub_o
 }
 template <typename T>
 void launch_sub_finalize(int64_t r0, int64_t r1, const int32_t* pos_sub, const int64_t* sub_off,
-                         const int64_t* scr_off, const T* scr, const int32_t* sub_dofs, T* x, hipStream_t st) {
+                         const int64_t* scr_off, const T* scr, const int32_t* sub_dofs, T* x, bool accumulate,
+                         hipStream_t st) {
     if (r1 <= r0) return;
     hipLaunchKernelGGL(k_sub_finalize<T>, dim3(grid_for(r1 - r0)), dim3(WG), 0, st, r0, r1, pos_sub, sub_off, scr_off,
-                       scr, sub_dofs, x);
+                       scr, sub_dofs, x, accumulate ? 1 : 0);
+}
+
+int64_t sub_symv_scratch_len(int64_t m) { return symv_scratch_len((int)((m + 63) / 64)); }
+
+void sub_symv_items(int32_t s, int64_t m, std::vector<int32_t>& items) {
+    const int nt = (int)((m + 63) / 64);
+    for (int I = 0; I < nt; ++I)
+        for (int ch = 0; ch * SYMV_CH <= I; ++ch) {
+            items.push_back(s);
+            items.push_back(I);
+            items.push_back(ch);
+        }
 }
 
 void launch_pack_tiles(int32_t n_agg, const int64_t* sub_ptr, const int64_t* inv_off, const double* inv,
                        const int64_t* tp_off, double* tiles, float* tiles32, hipStream_t st) {
     if (n_agg <= 0) return;
-    hipLaunchKernelGGL(k_pack_tiles, dim3(64, n_agg), dim3(WG), 0, st, sub_ptr, inv_off, inv, tp_off, tiles, tiles32);
+    hipLaunchKernelGGL(k_pack_tiles, dim3(n_agg == 1 ? 4096 : 64, n_agg), dim3(WG), 0, st, sub_ptr, inv_off, inv, tp_off,
+                       tiles, tiles32);
 }
 
 template <typename T>
@@ -1111,12 +1080,6 @@ template <typename T>
 void launch_zero(int64_t n, T* x, hipStream_t st) {
     if (n <= 0) return;
     hipLaunchKernelGGL(k_zero<T>, dim3(grid_for(n)), dim3(WG), 0, st, n, x);
-}
-
-void launch_dense_gemv(int64_t n, const double* inv, const double* r, double* x, double* part, hipStream_t st) {
-    const unsigned nchunk = (unsigned)((n + 1023) / 1024);
-    hipLaunchKernelGGL(k_dense_gemv, dim3((unsigned)((n + 127) / 128), nchunk), dim3(WG), 0, st, n, inv, r, part);
-    hipLaunchKernelGGL(k_chunk_sum, dim3(grid_for(n)), dim3(WG), 0, st, n, (int)nchunk, part, x);
 }
 
 void launch_dot(int64_t n, const double* a, const double* b, double* partials, double* out, hipStream_t st) {
@@ -1148,15 +1111,13 @@ void launch_check_finite(int64_t n, const double* a, int32_t* flag, hipStream_t 
 
 #define LSDD_INST(T)                                                                                                  \
     template void launch_csr_resid_rows<T>(int64_t, const int32_t*, const int64_t*, const int32_t*, const T*,        \
-                                           const T*, const T*, T*, bool, hipStream_t);                                \
-    template void launch_csr_spmv<T>(int64_t, const int64_t*, const int32_t*, const T*, const T*, T*, const T*,      \
+                                           const T*, const T*, T*, bool, int, hipStream_t);                           \
+    template void launch_csr_spmv<T>(int64_t, const int64_t*, const int32_t*, const T*, const T*, T*, const T*, int, \
                                      hipStream_t);                                                                    \
-    template void launch_sub_gemv<T>(int64_t, const int32_t*, const int64_t*, const int64_t*, const T*, const T*,    \
-                                     const int32_t*, T*, hipStream_t);                                                \
     template void launch_sub_symv<T>(int64_t, const int32_t*, const int64_t*, const int64_t*, const T*, const T*,    \
                                      const int64_t*, T*, hipStream_t);                                                \
     template void launch_sub_finalize<T>(int64_t, int64_t, const int32_t*, const int64_t*, const int64_t*, const T*, \
-                                         const int32_t*, T*, hipStream_t);                                            \
+                                         const int32_t*, T*, bool, hipStream_t);                                      \
     template void launch_restrict<T>(int64_t, const int32_t*, const int64_t*, const int32_t*, const int64_t*,        \
                                      const int32_t*, const int64_t*, const T*, const T*, T*, hipStream_t);            \
     template void launch_prolong<T>(int64_t, const int32_t*, const int64_t*, const int32_t*, const int64_t*,         \

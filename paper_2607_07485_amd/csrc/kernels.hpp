@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <vector>
 
 #include "batched.hpp"
 
@@ -101,21 +102,24 @@ void launch_to_f32(int64_t n, const double* a, float* b, hipStream_t st);
 void launch_to_f64(int64_t n, const float* a, double* b, hipStream_t st);
 
 // ---------------------------------------------------------------- solve
+// lanes per row: 16 or 64
 template <typename T>
 void launch_csr_resid_rows(int64_t nrows, const int32_t* rows, const int64_t* rowptr, const int32_t* col,
-                           const T* val, const T* x, const T* r, T* out, bool x_zero, hipStream_t st);
+                           const T* val, const T* x, const T* r, T* out, bool x_zero, int lanes, hipStream_t st);
 template <typename T>
 void launch_csr_spmv(int64_t n, const int64_t* rowptr, const int32_t* col, const T* val, const T* x, T* y,
-                     const T* r_minus, hipStream_t st);
-template <typename T>
-void launch_sub_gemv(int64_t n_items, const int32_t* items, const int64_t* sub_off, const int64_t* inv_off,
-                     const T* inv, const T* rloc, const int32_t* sub_dofs, T* x, hipStream_t st);
+                     const T* r_minus, int lanes, hipStream_t st);
 template <typename T>
 void launch_sub_symv(int64_t n_items, const int32_t* items, const int64_t* sub_off, const int64_t* tp_off,
                      const T* tiles, const T* rloc, const int64_t* scr_off, T* scr, hipStream_t st);
+// x[sub_dofs[t]] (+)= sum of the partials of entry t, for t in [r0, r1); sub_dofs NULL = identity
 template <typename T>
 void launch_sub_finalize(int64_t r0, int64_t r1, const int32_t* pos_sub, const int64_t* sub_off,
-                         const int64_t* scr_off, const T* scr, const int32_t* sub_dofs, T* x, hipStream_t st);
+                         const int64_t* scr_off, const T* scr, const int32_t* sub_dofs, T* x, bool accumulate,
+                         hipStream_t st);
+// scratch doubles for a subdomain of size m; append its work items (s, tile row, chunk)
+int64_t sub_symv_scratch_len(int64_t m);
+void sub_symv_items(int32_t s, int64_t m, std::vector<int32_t>& items);
 void launch_pack_tiles(int32_t n_agg, const int64_t* sub_ptr, const int64_t* inv_off, const double* inv,
                        const int64_t* tp_off, double* tiles, float* tiles32, hipStream_t st);
 // restriction items: (aggregate, first of 16 columns); prolongation items: (aggregate, first of 256 rows)
@@ -129,8 +133,6 @@ void launch_prolong(int64_t n_items, const int32_t* items, const int64_t* agg_pt
                     hipStream_t st);
 template <typename T>
 void launch_zero(int64_t n, T* x, hipStream_t st);
-// x = M r; `part` holds ceil(n / 1024) * n doubles of chunk partial sums
-void launch_dense_gemv(int64_t n, const double* inv, const double* r, double* x, double* part, hipStream_t st);
 
 // PCG helpers (FP64).  `partials` holds at least 1024 doubles.
 void launch_dot(int64_t n, const double* a, const double* b, double* partials, double* out, hipStream_t st);

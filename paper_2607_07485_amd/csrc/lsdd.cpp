@@ -133,6 +133,7 @@ struct Level {
     double* d_blocks = nullptr;
     // assembled operator
     Csr pat;
+    int lanes = 16;                    // CSR lanes per row (64 for long coarse rows)
     int64_t* d_rowptr = nullptr;
     int32_t* d_col = nullptr;
     double* d_val = nullptr;
@@ -176,7 +177,13 @@ struct Level {
     int64_t* d_scr_off = nullptr;     // per subdomain: offset of its partial-sum scratch
     double* scr64 = nullptr;
     float* scr32 = nullptr;
-    double* d_cpart = nullptr;        // coarsest GEMV chunk partials
+    // coarsest level as one packed symmetric "subdomain"
+    int64_t* c_sub_off = nullptr;
+    int64_t* c_tp_off = nullptr;
+    int64_t* c_scr_off = nullptr;
+    int32_t* c_pos = nullptr;
+    int32_t* c_items = nullptr;
+    int64_t c_nitems = 0;
     double* d_inv = nullptr;          // full inverses during setup only
     double* d_tiles = nullptr;        // packed lower tiles of A_Omega^{-1}
     float* d_tiles32 = nullptr;
@@ -280,6 +287,7 @@ void upload_elements(lsdd_hierarchy* h, Level& lv) {
 void assemble_operator(lsdd_hierarchy* h, Level& lv) {
     lv.pat = assembled_pattern(lv.n, lv.el);
     lv.nnz = (int64_t)lv.pat.idx.size();
+    lv.lanes = (lv.nnz > 96 * lv.n) ? 64 : 16;
     lv.d_rowptr = h->arena.upload(lv.pat.ptr, h->st);
     lv.d_col = h->arena.upload(lv.pat.idx, h->st);
     lv.d_val = h->arena.alloc<double>(lv.nnz);
@@ -358,7 +366,39 @@ void make_coarsest(lsdd_hierarchy* h, Level& lv) {
     vlog("coarsest level: n=%lld dense Cholesky + inverse %.3f s", (long long)lv.n, now_s() - t0);
     h->arena.release(W);
     if (hs != 0) throw Error(LSDD_E_NUMERIC, "coarsest-level Cholesky failed (matrix not SPD)");
-    lv.d_cpart = h->arena.alloc<double>((size_t)((lv.n + 1023) / 1024) * lv.n);
+    {
+        // packed lower tiles of the coarsest inverse, applied by the subdomain kernel
+        Arena& ar = h->arena;
+        const int64_t nt = (lv.n + 63) / 64;
+        std::vector<int64_t> sub_off = {0, lv.n}, tp_off = {0}, scr_off = {0, sub_symv_scratch_len(lv.n)};
+        lv.c_sub_off = ar.upload(sub_off, h->st);
+        lv.c_tp_off = ar.upload(tp_off, h->st);
+        lv.c_scr_off = ar.upload(scr_off, h->st);
+        lv.c_pos = ar.alloc<int32_t>(lv.n);
+        HIPCHK(hipMemsetAsync(lv.c_pos, 0, lv.n * sizeof(int32_t), h->st));
+        std::vector<int32_t> it, items;
+        sub_symv_items(0, lv.n, it);
+        std::vector<size_t> ord(it.size() / 3);
+        for (size_t q = 0; q < ord.size(); ++q) ord[q] = q;
+        std::stable_sort(ord.begin(), ord.end(), [&](size_t a, size_t b) {
+            int la = std::min(it[3 * a + 1] + 1 - 8 * it[3 * a + 2], 8), lb = std::min(it[3 * b + 1] + 1 - 8 * it[3 * b + 2], 8);
+            return la > lb;
+        });
+        for (size_t q : ord) items.insert(items.end(), {it[3 * q], it[3 * q + 1], it[3 * q + 2]});
+        lv.c_items = ar.upload(items, h->st);
+        lv.c_nitems = (int64_t)items.size() / 3;
+        lv.tiles_len = nt * (nt + 1) / 2 * 4096;
+        lv.d_tiles = ar.alloc<double>(lv.tiles_len);
+        std::vector<int64_t> inv_off = {0};
+        int64_t* d_inv_off = ar.upload(inv_off, h->st);
+        launch_pack_tiles(1, lv.c_sub_off, d_inv_off, lv.d_cinv, lv.c_tp_off, lv.d_tiles, nullptr, h->st);
+        HIPCHK(hipGetLastError());
+        sync(h->st);
+        ar.release(d_inv_off);
+        ar.release(lv.d_cinv);
+        lv.d_cinv = nullptr;
+        lv.scr64 = ar.alloc<double>(scr_off[1]);
+    }
     alloc_vectors(h, lv, 0);
 }
 
@@ -667,25 +707,25 @@ std::unique_ptr<Level> coarsen(lsdd_hierarchy* h, Level& lv, const int32_t* agg_
         int32_t c = lv.colors[i];
         lv.color_row0[c + 1] = (int64_t)sw_dofs.size();
     }
-    // work items per colour: (subdomain, tile row), longest tile rows first
+    // work items per colour: (subdomain, tile row, chunk), longest tile rows first
     for (int32_t c = 0; c < lv.n_colors; ++c) {
-        std::vector<std::pair<int32_t, int32_t>> it;
+        std::vector<int32_t> it;
         for (int32_t s = 0; s < n_agg; ++s) {
             if (lv.colors[lv.sweep[s]] != c) continue;
-            int32_t nt = (int32_t)((lv.sw_sub_off[s + 1] - lv.sw_sub_off[s] + 63) / 64);
-            for (int32_t I = 0; I < nt; ++I) it.emplace_back(I, s);
+            sub_symv_items(s, lv.sw_sub_off[s + 1] - lv.sw_sub_off[s], it);
         }
-        std::stable_sort(it.begin(), it.end(), [](const std::pair<int32_t, int32_t>& a,
-                                                  const std::pair<int32_t, int32_t>& b) { return a.first > b.first; });
-        for (auto& pr : it) {
-            items.push_back(pr.second);
-            items.push_back(pr.first);
+        std::vector<size_t> ord(it.size() / 3);
+        for (size_t q = 0; q < ord.size(); ++q) ord[q] = q;
+        std::stable_sort(ord.begin(), ord.end(), [&](size_t a, size_t b) {
+            int la = std::min(it[3 * a + 1] + 1 - 8 * it[3 * a + 2], 8), lb = std::min(it[3 * b + 1] + 1 - 8 * it[3 * b + 2], 8);
+            return la > lb;
+        });
+        for (size_t q : ord) {
+            items.push_back(it[3 * q]);
+            items.push_back(it[3 * q + 1]);
+            items.push_back(it[3 * q + 2]);
         }
-        lv.color_item0[c + 1] = (int64_t)items.size() / 2;
-    }
-    for (int32_t c = 0; c < lv.n_colors; ++c) {
-        lv.color_row0[c + 1] = std::max(lv.color_row0[c + 1], lv.color_row0[c]);
-        lv.color_item0[c + 1] = std::max(lv.color_item0[c + 1], lv.color_item0[c]);
+        lv.color_item0[c + 1] = (int64_t)items.size() / 3;
     }
     lv.color_m2.assign(lv.n_colors, 0.0);
     lv.color_m.assign(lv.n_colors, 0.0);
@@ -708,8 +748,7 @@ std::unique_ptr<Level> coarsen(lsdd_hierarchy* h, Level& lv, const int32_t* agg_
         std::vector<int64_t> scr_off(n_agg + 1, 0);
         for (int32_t s = 0; s < n_agg; ++s) {
             for (int64_t q = lv.sw_sub_off[s]; q < lv.sw_sub_off[s + 1]; ++q) pos_sub[q] = s;
-            int64_t nt = (lv.sw_sub_off[s + 1] - lv.sw_sub_off[s] + 63) / 64;
-            scr_off[s + 1] = scr_off[s] + (nt + nt * (nt - 1) / 2) * 64;
+            scr_off[s + 1] = scr_off[s] + sub_symv_scratch_len(lv.sw_sub_off[s + 1] - lv.sw_sub_off[s]);
         }
         lv.d_pos_sub = ar.upload(pos_sub, st);
         lv.d_scr_off = ar.upload(scr_off, st);
@@ -858,15 +897,15 @@ void sweep(lsdd_hierarchy* h, Level& lv, const T* r, T* x, bool forward, bool x_
         const double rb = lv.color_m[c] * (4 + 8 + 3 * w) + (xz ? 0.0 : lv.color_nnz[c] * (4 + w));
         traced(h, "csr_resid_rows", rb, [&] {
             launch_csr_resid_rows<T>(r1 - r0, lv.d_sw_sub_dofs + r0, lv.d_rowptr, lv.d_col, V::val(lv), x, r,
-                                     V::rloc(lv) + r0, xz, h->st);
+                                     V::rloc(lv) + r0, xz, lv.lanes, h->st);
         });
         const double gb = lv.color_m2[c] * w + lv.color_m[c] * (4 + 3 * w);
         traced(h, "sub_symv", gb, [&] {
-            launch_sub_symv<T>(i1 - i0, lv.d_items + 2 * i0, lv.d_sw_sub_off, lv.d_sw_tp_off, V::inv(lv),
+            launch_sub_symv<T>(i1 - i0, lv.d_items + 3 * i0, lv.d_sw_sub_off, lv.d_sw_tp_off, V::inv(lv),
                                V::rloc(lv), lv.d_scr_off, V::scr(lv), h->st);
         });
         launch_sub_finalize<T>(r0, r1, lv.d_pos_sub, lv.d_sw_sub_off, lv.d_scr_off, V::scr(lv), lv.d_sw_sub_dofs, x,
-                               h->st);
+                               true, h->st);
     }
 }
 
@@ -876,14 +915,20 @@ void vcycle(lsdd_hierarchy* h, size_t l, const T* r, T* x) {
     Level& lv = *h->L[l];
     const double w = (double)sizeof(T);
     if (lv.coarsest) {
-        const double nb = (double)lv.n * lv.n * 8.0 + 2.0 * lv.n * 8.0;
+        const double nb = (double)lv.n * (lv.n + 1) / 2.0 * 8.0 + 2.0 * lv.n * 8.0;
+        auto apply = [&](const double* rr, double* xx) {
+            traced(h, "coarse_symv", nb, [&] {
+                launch_sub_symv<double>(lv.c_nitems, lv.c_items, lv.c_sub_off, lv.c_tp_off, lv.d_tiles, rr,
+                                        lv.c_scr_off, lv.scr64, h->st);
+            });
+            launch_sub_finalize<double>(0, lv.n, lv.c_pos, lv.c_sub_off, lv.c_scr_off, lv.scr64, nullptr, xx, false,
+                                        h->st);
+        };
         if constexpr (std::is_same<T, double>::value) {
-            traced(h, "coarse_gemv", nb, [&] { launch_dense_gemv(lv.n, lv.d_cinv, r, x, lv.d_cpart, h->st); });
+            apply(r, x);
         } else {
             launch_to_f64(lv.n, r, lv.cr64, h->st);
-            traced(h, "coarse_gemv", nb, [&] {
-                launch_dense_gemv(lv.n, lv.d_cinv, lv.cr64, lv.cx64, lv.d_cpart, h->st);
-            });
+            apply(lv.cr64, lv.cx64);
             launch_to_f32(lv.n, lv.cx64, x, h->st);
         }
         return;
@@ -892,7 +937,7 @@ void vcycle(lsdd_hierarchy* h, size_t l, const T* r, T* x) {
     launch_zero<T>(lv.n, x, h->st);
     sweep<T>(h, lv, r, x, true, true);
     traced(h, "csr_spmv", (double)lv.nnz * (4 + w) + (double)lv.n * (8 + 3 * w), [&] {
-        launch_csr_spmv<T>(lv.n, lv.d_rowptr, lv.d_col, V::val(lv), x, V::t(lv), r, h->st);
+        launch_csr_spmv<T>(lv.n, lv.d_rowptr, lv.d_col, V::val(lv), x, V::t(lv), r, lv.lanes, h->st);
     });
     const double zb = (double)lv.zoff.back() * w + (double)lv.n * (4 + w) + (double)nx.n * w;
     traced(h, "restrict", zb, [&] {
@@ -1191,7 +1236,7 @@ lsdd_status lsdd_apply(lsdd_hierarchy* h, int32_t level, const double* x, double
     if (!h || !x || !y || level < 0 || level >= (int32_t)h->L.size()) throw Error(LSDD_E_INVAL, "bad argument");
     h->st = (hipStream_t)hip_stream;
     Level& lv = *h->L[level];
-    launch_csr_spmv<double>(lv.n, lv.d_rowptr, lv.d_col, lv.d_val, x, y, nullptr, h->st);
+    launch_csr_spmv<double>(lv.n, lv.d_rowptr, lv.d_col, lv.d_val, x, y, nullptr, lv.lanes, h->st);
     HIPCHK(hipGetLastError());
     sync(h->st);
     return LSDD_OK;
@@ -1237,7 +1282,7 @@ lsdd_status lsdd_solve(lsdd_hierarchy* h, const double* b, double* x, int32_t nr
         int it = 0;
         for (it = 1; it <= h->prm.max_iter; ++it) {
             traced(h, "pcg_spmv", (double)l0.nnz * 12.0 + (double)n * 24.0, [&] {
-                launch_csr_spmv<double>(n, l0.d_rowptr, l0.d_col, l0.d_val, h->p, h->q, nullptr, st);
+                launch_csr_spmv<double>(n, l0.d_rowptr, l0.d_col, l0.d_val, h->p, h->q, nullptr, l0.lanes, st);
             });
             launch_dot(n, h->p, h->q, h->partials, S + 1, st);
             if (flex) launch_copy(n, h->r, h->rold, st);
