@@ -655,39 +655,39 @@ __global__ void __launch_bounds__(WG) k_csr_spmv(int64_t n, const int64_t* rowpt
 // Subdomain correction with the packed symmetric inverse: A_Omega^{-1} is stored
 // as its lower 64 x 64 tiles (tile (I, J), I >= J, row-major inside the tile,
 // zero-padded past |Omega|; the diagonal tiles hold both triangles).  Work item
-// = (subdomain, tile row I, chunk of up to SYMV_CH tiles J): waves split the 64
+// = (subdomain, tile row I, chunk of up to `chl` tiles J): waves split the 64
 // rows of the tile row, lanes the 64 columns.  Tile (I, J) is read once and
 // used twice: its rows give y_I += T x_J (per-lane partials, reduced across
-// lanes once per item) and its columns give y_J += T^T x_I (J < I; summed over
-// the waves in LDS).  Partial results go to a per-subdomain scratch -- row
-// parts per (tile row, chunk), column parts per tile -- that k_sub_finalize
-// sums in a fixed order, so the smoother is the same linear map on every
-// application (no order-dependent atomics).
-constexpr int SYMV_CH = 8;
-
-__host__ __device__ inline int64_t symv_rowpart_off(int I) {
-    // chunks of tile rows 0..I-1: sum_{i<I} ceil((i+1)/CH)
-    int64_t full = I / SYMV_CH, rem = I % SYMV_CH;
-    return SYMV_CH * full * (full + 1) / 2 + rem * (full + 1);
+// lanes once per item) and its columns give y_J += T^T x_I (J < I; kept in
+// registers and summed over the waves in LDS once per item).  Partial results
+// go to a per-subdomain scratch -- row parts per (tile row, chunk), column
+// parts per tile -- that k_sub_finalize sums in a fixed order, so the smoother
+// is the same linear map on every application (no order-dependent atomics).
+__host__ __device__ inline int64_t symv_rowpart_off(int I, int chl) {
+    // chunks of tile rows 0..I-1: sum_{i<I} ceil((i+1)/chl)
+    int64_t full = I / chl, rem = I % chl;
+    return chl * full * (full + 1) / 2 + rem * (full + 1);
 }
-__host__ __device__ inline int64_t symv_scratch_len(int nt) {
-    return (symv_rowpart_off(nt) + (int64_t)nt * (nt - 1) / 2) * 64;
+__host__ __device__ inline int64_t symv_scratch_len(int nt, int chl) {
+    return (symv_rowpart_off(nt, chl) + (int64_t)nt * (nt - 1) / 2) * 64;
 }
 
 template <typename T>
 __global__ void __launch_bounds__(WG) k_sub_symv(const int32_t* items, const int64_t* sub_off, const int64_t* tp_off,
-                                                 const T* tiles, const T* rloc, const int64_t* scr_off, T* scr) {
-    __shared__ T s_x[SYMV_CH * 64];
-    __shared__ T s_c[4][64];
+                                                 const T* tiles, const T* rloc, const int64_t* scr_off, T* scr,
+                                                 int chl) {
+    __shared__ T s_x[SUB_MAX_CHUNK * 64];
+    __shared__ T s_c[4][SUB_MAX_CHUNK][64];
     const int s = items[3 * blockIdx.x];
     const int I = items[3 * blockIdx.x + 1];
     const int ch = items[3 * blockIdx.x + 2];
     const int64_t o = sub_off[s];
     const int m = (int)(sub_off[s + 1] - o);
     const int nt = (m + 63) >> 6;
-    const int J0 = ch * SYMV_CH;
-    const int J1 = min(J0 + SYMV_CH, I + 1);
-    for (int a = tid(); a < (J1 - J0) * 64; a += WG) {
+    const int J0 = ch * chl;
+    const int nJ = min(chl, I + 1 - J0);       // tiles J0 .. J0 + nJ - 1
+    const int ncol = min(nJ, I - J0);          // of which strictly below the diagonal
+    for (int a = tid(); a < nJ * 64; a += WG) {
         int c = J0 * 64 + a;
         s_x[a] = c < m ? rloc[o + c] : (T)0;
     }
@@ -699,33 +699,33 @@ __global__ void __launch_bounds__(WG) k_sub_symv(const int32_t* items, const int
         xi[q] = r < m ? rloc[o + r] : (T)0;
     }
     __syncthreads();
-    const T* row0 = tiles + tp_off[s] + (int64_t)(I * (I + 1) / 2) * 4096;
+    const T* row0 = tiles + tp_off[s] + (int64_t)I * (I + 1) / 2 * 4096;
     T* part = scr + scr_off[s];
-    T* colpart = part + symv_rowpart_off(nt) * 64;
-    T p[16];
+    T* colpart = part + symv_rowpart_off(nt, chl) * 64;
+    T p[16], cv[SUB_MAX_CHUNK];
 #pragma unroll
     for (int q = 0; q < 16; ++q) p[q] = 0;
-    for (int J = J0; J < J1; ++J) {
-        const T* t = row0 + (int64_t)J * 4096 + lane;
-        const T xj = s_x[(J - J0) * 64 + lane];
-        T v[16];
 #pragma unroll
-        for (int q = 0; q < 16; ++q) v[q] = t[(w + 4 * q) * 64];
-        T col = 0;
+    for (int jj = 0; jj < SUB_MAX_CHUNK; ++jj) {
+        cv[jj] = 0;
+        if (jj < nJ) {
+            const T* t = row0 + (int64_t)(J0 + jj) * 4096 + lane;
+            const T xj = s_x[jj * 64 + lane];
+            T v[16];
 #pragma unroll
-        for (int q = 0; q < 16; ++q) {
-            p[q] += v[q] * xj;
-            col += v[q] * xi[q];
-        }
-        if (J < I) {
-            s_c[w][lane] = col;
-            __syncthreads();
-            if (w == 0)
-                colpart[((int64_t)I * (I - 1) / 2 + J) * 64 + lane] =
-                    (s_c[0][lane] + s_c[1][lane]) + (s_c[2][lane] + s_c[3][lane]);
-            __syncthreads();
+            for (int q = 0; q < 16; ++q) v[q] = t[(w + 4 * q) * 64];
+            T col = 0;
+#pragma unroll
+            for (int q = 0; q < 16; ++q) {
+                p[q] += v[q] * xj;
+                col += v[q] * xi[q];
+            }
+            cv[jj] = col;
         }
     }
+#pragma unroll
+    for (int jj = 0; jj < SUB_MAX_CHUNK; ++jj)
+        if (jj < ncol) s_c[w][jj][lane] = cv[jj];
 #pragma unroll
     for (int q = 0; q < 16; ++q) {
         T v = p[q];
@@ -737,30 +737,56 @@ __global__ void __launch_bounds__(WG) k_sub_symv(const int32_t* items, const int
 #pragma unroll
         for (int q = 0; q < 16; ++q)
             if (q == lane) y = p[q];
-        part[(symv_rowpart_off(I) + ch) * 64 + w + 4 * lane] = y;
+        part[(symv_rowpart_off(I, chl) + ch) * 64 + w + 4 * lane] = y;
+    }
+    __syncthreads();
+    for (int a = tid(); a < ncol * 64; a += WG) {
+        const int jj = a >> 6, l = a & 63;
+        colpart[((int64_t)I * (I - 1) / 2 + J0 + jj) * 64 + l] =
+            (s_c[0][jj][l] + s_c[1][jj][l]) + (s_c[2][jj][l] + s_c[3][jj][l]);
     }
 }
 
 // x[Omega_s[c]] (+)= row-part chunks of tile row J(c) + column parts of the
-// tile rows below, in ascending order; one thread per subdomain DOF.
-template <typename T>
-__global__ void k_sub_finalize(int64_t r0, int64_t r1, const int32_t* pos_sub, const int64_t* sub_off,
-                               const int64_t* scr_off, const T* scr, const int32_t* sub_dofs, T* x, int accumulate) {
-    const int64_t t = r0 + (int64_t)blockIdx.x * WG + tid();
-    if (t >= r1) return;
-    const int s = pos_sub[t];
-    const int64_t o = sub_off[s];
-    const int c = (int)(t - o);
-    const int nt = (int)((sub_off[s + 1] - o + 63) >> 6);
-    const int J = c >> 6, l = c & 63;
-    const T* part = scr + scr_off[s];
-    const T* colpart = part + symv_rowpart_off(nt) * 64;
-    const int nch = (J + SYMV_CH) / SYMV_CH;
+// tile rows below.  FL threads per DOF each sum a fixed strided subset of the
+// partials; the FL sums are added in LDS in ascending order (fixed order).
+template <typename T, int FL>
+__global__ void __launch_bounds__(WG) k_sub_finalize(int64_t r0, int64_t r1, const int32_t* pos_sub,
+                                                     const int64_t* sub_off, const int64_t* scr_off, const T* scr,
+                                                     const int32_t* sub_dofs, T* x, int accumulate, int chl) {
+    constexpr int ND = WG / FL;
+    __shared__ T s_y[FL][ND];
+    const int dl = tid() % ND, j = tid() / ND;
+    const int64_t t = r0 + (int64_t)blockIdx.x * ND + dl;
     T y = 0;
-    for (int chn = 0; chn < nch; ++chn) y += part[(symv_rowpart_off(J) + chn) * 64 + l];
-    for (int I = J + 1; I < nt; ++I) y += colpart[((int64_t)I * (I - 1) / 2 + J) * 64 + l];
-    const int32_t d = sub_dofs ? sub_dofs[t] : (int32_t)t;
-    x[d] = accumulate ? x[d] + y : y;
+    if (t < r1) {
+        const int s = pos_sub[t];
+        const int64_t o = sub_off[s];
+        const int c = (int)(t - o);
+        const int nt = (int)((sub_off[s + 1] - o + 63) >> 6);
+        const int J = c >> 6, l = c & 63;
+        const T* part = scr + scr_off[s] + symv_rowpart_off(J, chl) * 64 + l;
+        const T* colpart = scr + scr_off[s] + symv_rowpart_off(nt, chl) * 64 + l;
+        const int nch = (J + chl) / chl;
+        const int K = nch + (nt - 1 - J);
+        for (int k = j; k < K; k += FL) {
+            if (k < nch) {
+                y += part[(int64_t)k * 64];
+            } else {
+                const int64_t I = J + 1 + (k - nch);
+                y += colpart[(I * (I - 1) / 2 + J) * 64];
+            }
+        }
+    }
+    s_y[j][dl] = y;
+    __syncthreads();
+    if (j == 0 && t < r1) {
+        T v = s_y[0][dl];
+#pragma unroll
+        for (int q = 1; q < FL; ++q) v += s_y[q][dl];
+        const int32_t d = sub_dofs ? sub_dofs[t] : (int32_t)t;
+        x[d] = accumulate ? x[d] + v : v;
+    }
 }
 
 // Pack full m x m symmetric inverses (aggregate order, column-major) into the
@@ -1027,26 +1053,30 @@ void launch_csr_spmv(int64_t n, const int64_t* rowptr, const int32_t* col, const
 }
 template <typename T>
 void launch_sub_symv(int64_t n_items, const int32_t* items, const int64_t* sub_off, const int64_t* tp_off,
-                     const T* tiles, const T* rloc, const int64_t* scr_off, T* scr, hipStream_t st) {
+                     const T* tiles, const T* rloc, const int64_t* scr_off, T* scr, int chl, hipStream_t st) {
     if (n_items <= 0) return;
     hipLaunchKernelGGL(k_sub_symv<T>, dim3((unsigned)n_items), dim3(WG), 0, st, items, sub_off, tp_off, tiles, rloc,
-                       scr_off, scr);
+                       scr_off, scr, chl);
 }
 template <typename T>
 void launch_sub_finalize(int64_t r0, int64_t r1, const int32_t* pos_sub, const int64_t* sub_off,
                          const int64_t* scr_off, const T* scr, const int32_t* sub_dofs, T* x, bool accumulate,
-                         hipStream_t st) {
+                         int chl, int fl, hipStream_t st) {
     if (r1 <= r0) return;
-    hipLaunchKernelGGL(k_sub_finalize<T>, dim3(grid_for(r1 - r0)), dim3(WG), 0, st, r0, r1, pos_sub, sub_off, scr_off,
-                       scr, sub_dofs, x, accumulate ? 1 : 0);
+    if (fl >= 32)
+        hipLaunchKernelGGL((k_sub_finalize<T, 32>), dim3(grid_for(r1 - r0, WG / 32)), dim3(WG), 0, st, r0, r1,
+                           pos_sub, sub_off, scr_off, scr, sub_dofs, x, accumulate ? 1 : 0, chl);
+    else
+        hipLaunchKernelGGL((k_sub_finalize<T, 8>), dim3(grid_for(r1 - r0, WG / 8)), dim3(WG), 0, st, r0, r1,
+                           pos_sub, sub_off, scr_off, scr, sub_dofs, x, accumulate ? 1 : 0, chl);
 }
 
-int64_t sub_symv_scratch_len(int64_t m) { return symv_scratch_len((int)((m + 63) / 64)); }
+int64_t sub_symv_scratch_len(int64_t m, int chl) { return symv_scratch_len((int)((m + 63) / 64), chl); }
 
-void sub_symv_items(int32_t s, int64_t m, std::vector<int32_t>& items) {
+void sub_symv_items(int32_t s, int64_t m, int chl, std::vector<int32_t>& items) {
     const int nt = (int)((m + 63) / 64);
     for (int I = 0; I < nt; ++I)
-        for (int ch = 0; ch * SYMV_CH <= I; ++ch) {
+        for (int ch = 0; ch * chl <= I; ++ch) {
             items.push_back(s);
             items.push_back(I);
             items.push_back(ch);
@@ -1115,9 +1145,9 @@ void launch_check_finite(int64_t n, const double* a, int32_t* flag, hipStream_t 
     template void launch_csr_spmv<T>(int64_t, const int64_t*, const int32_t*, const T*, const T*, T*, const T*, int, \
                                      hipStream_t);                                                                    \
     template void launch_sub_symv<T>(int64_t, const int32_t*, const int64_t*, const int64_t*, const T*, const T*,    \
-                                     const int64_t*, T*, hipStream_t);                                                \
+                                     const int64_t*, T*, int, hipStream_t);                                           \
     template void launch_sub_finalize<T>(int64_t, int64_t, const int32_t*, const int64_t*, const int64_t*, const T*, \
-                                         const int32_t*, T*, bool, hipStream_t);                                      \
+                                         const int32_t*, T*, bool, int, int, hipStream_t);                            \
     template void launch_restrict<T>(int64_t, const int32_t*, const int64_t*, const int32_t*, const int64_t*,        \
                                      const int32_t*, const int64_t*, const T*, const T*, T*, hipStream_t);            \
     template void launch_prolong<T>(int64_t, const int32_t*, const int64_t*, const int32_t*, const int64_t*,         \

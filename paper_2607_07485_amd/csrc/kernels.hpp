@@ -109,17 +109,20 @@ void launch_csr_resid_rows(int64_t nrows, const int32_t* rows, const int64_t* ro
 template <typename T>
 void launch_csr_spmv(int64_t n, const int64_t* rowptr, const int32_t* col, const T* val, const T* x, T* y,
                      const T* r_minus, int lanes, hipStream_t st);
+// chl: tiles per work item (1..8); the scratch layout depends on it
 template <typename T>
 void launch_sub_symv(int64_t n_items, const int32_t* items, const int64_t* sub_off, const int64_t* tp_off,
-                     const T* tiles, const T* rloc, const int64_t* scr_off, T* scr, hipStream_t st);
-// x[sub_dofs[t]] (+)= sum of the partials of entry t, for t in [r0, r1); sub_dofs NULL = identity
+                     const T* tiles, const T* rloc, const int64_t* scr_off, T* scr, int chl, hipStream_t st);
+// x[sub_dofs[t]] (+)= sum of the partials of entry t, for t in [r0, r1); sub_dofs NULL = identity;
+// fl: threads per entry (8 or 32)
 template <typename T>
 void launch_sub_finalize(int64_t r0, int64_t r1, const int32_t* pos_sub, const int64_t* sub_off,
                          const int64_t* scr_off, const T* scr, const int32_t* sub_dofs, T* x, bool accumulate,
-                         hipStream_t st);
-// scratch doubles for a subdomain of size m; append its work items (s, tile row, chunk)
-int64_t sub_symv_scratch_len(int64_t m);
-void sub_symv_items(int32_t s, int64_t m, std::vector<int32_t>& items);
+                         int chl, int fl, hipStream_t st);
+constexpr int SUB_MAX_CHUNK = 8;
+// scratch entries for a subdomain of size m; append its work items (s, tile row, chunk)
+int64_t sub_symv_scratch_len(int64_t m, int chl);
+void sub_symv_items(int32_t s, int64_t m, int chl, std::vector<int32_t>& items);
 void launch_pack_tiles(int32_t n_agg, const int64_t* sub_ptr, const int64_t* inv_off, const double* inv,
                        const int64_t* tp_off, double* tiles, float* tiles32, hipStream_t st);
 // restriction items: (aggregate, first of 16 columns); prolongation items: (aggregate, first of 256 rows)

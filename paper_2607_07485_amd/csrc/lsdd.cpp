@@ -134,6 +134,8 @@ struct Level {
     // assembled operator
     Csr pat;
     int lanes = 16;                    // CSR lanes per row (64 for long coarse rows)
+    int chl = SUB_MAX_CHUNK;           // tiles per subdomain-kernel work item
+    int fl = 8;                        // threads per DOF in the subdomain finalize
     int64_t* d_rowptr = nullptr;
     int32_t* d_col = nullptr;
     double* d_val = nullptr;
@@ -352,6 +354,19 @@ void traced(lsdd_hierarchy* h, const char* name, double bytes, F&& launch) {
     h->tr.pend.push_back(Trace::Pend{h->tr.index(name), a, b, bytes});
 }
 
+// Work items (subdomain, tile row, chunk) of the symmetric subdomain kernel for
+// the listed subdomains, longest chunks first (ties keep subdomain order).
+void append_symv_items(const std::vector<int64_t>& sub_off, const std::vector<int32_t>& subs, int chl,
+                       std::vector<int32_t>& items) {
+    std::vector<int32_t> it;
+    for (int32_t s : subs) sub_symv_items(s, sub_off[s + 1] - sub_off[s], chl, it);
+    std::vector<size_t> ord(it.size() / 3);
+    for (size_t q = 0; q < ord.size(); ++q) ord[q] = q;
+    auto len = [&](size_t q) { return std::min(it[3 * q + 1] + 1 - chl * it[3 * q + 2], chl); };
+    std::stable_sort(ord.begin(), ord.end(), [&](size_t a, size_t b) { return len(a) > len(b); });
+    for (size_t q : ord) items.insert(items.end(), {it[3 * q], it[3 * q + 1], it[3 * q + 2]});
+}
+
 void make_coarsest(lsdd_hierarchy* h, Level& lv) {
     lv.coarsest = true;
     if (lv.n > 32768) throw Error(LSDD_E_UNSUPPORTED, "coarsest level too large: " + std::to_string(lv.n));
@@ -370,21 +385,15 @@ void make_coarsest(lsdd_hierarchy* h, Level& lv) {
         // packed lower tiles of the coarsest inverse, applied by the subdomain kernel
         Arena& ar = h->arena;
         const int64_t nt = (lv.n + 63) / 64;
-        std::vector<int64_t> sub_off = {0, lv.n}, tp_off = {0}, scr_off = {0, sub_symv_scratch_len(lv.n)};
+        lv.fl = 32;
+        std::vector<int64_t> sub_off = {0, lv.n}, tp_off = {0}, scr_off = {0, sub_symv_scratch_len(lv.n, lv.chl)};
         lv.c_sub_off = ar.upload(sub_off, h->st);
         lv.c_tp_off = ar.upload(tp_off, h->st);
         lv.c_scr_off = ar.upload(scr_off, h->st);
         lv.c_pos = ar.alloc<int32_t>(lv.n);
         HIPCHK(hipMemsetAsync(lv.c_pos, 0, lv.n * sizeof(int32_t), h->st));
-        std::vector<int32_t> it, items;
-        sub_symv_items(0, lv.n, it);
-        std::vector<size_t> ord(it.size() / 3);
-        for (size_t q = 0; q < ord.size(); ++q) ord[q] = q;
-        std::stable_sort(ord.begin(), ord.end(), [&](size_t a, size_t b) {
-            int la = std::min(it[3 * a + 1] + 1 - 8 * it[3 * a + 2], 8), lb = std::min(it[3 * b + 1] + 1 - 8 * it[3 * b + 2], 8);
-            return la > lb;
-        });
-        for (size_t q : ord) items.insert(items.end(), {it[3 * q], it[3 * q + 1], it[3 * q + 2]});
+        std::vector<int32_t> items;
+        append_symv_items(sub_off, {0}, lv.chl, items);
         lv.c_items = ar.upload(items, h->st);
         lv.c_nitems = (int64_t)items.size() / 3;
         lv.tiles_len = nt * (nt + 1) / 2 * 4096;
@@ -707,24 +716,12 @@ std::unique_ptr<Level> coarsen(lsdd_hierarchy* h, Level& lv, const int32_t* agg_
         int32_t c = lv.colors[i];
         lv.color_row0[c + 1] = (int64_t)sw_dofs.size();
     }
-    // work items per colour: (subdomain, tile row, chunk), longest tile rows first
+    // work items per colour: (subdomain, tile row, chunk), longest chunks first
     for (int32_t c = 0; c < lv.n_colors; ++c) {
-        std::vector<int32_t> it;
-        for (int32_t s = 0; s < n_agg; ++s) {
-            if (lv.colors[lv.sweep[s]] != c) continue;
-            sub_symv_items(s, lv.sw_sub_off[s + 1] - lv.sw_sub_off[s], it);
-        }
-        std::vector<size_t> ord(it.size() / 3);
-        for (size_t q = 0; q < ord.size(); ++q) ord[q] = q;
-        std::stable_sort(ord.begin(), ord.end(), [&](size_t a, size_t b) {
-            int la = std::min(it[3 * a + 1] + 1 - 8 * it[3 * a + 2], 8), lb = std::min(it[3 * b + 1] + 1 - 8 * it[3 * b + 2], 8);
-            return la > lb;
-        });
-        for (size_t q : ord) {
-            items.push_back(it[3 * q]);
-            items.push_back(it[3 * q + 1]);
-            items.push_back(it[3 * q + 2]);
-        }
+        std::vector<int32_t> subs;
+        for (int32_t s = 0; s < n_agg; ++s)
+            if (lv.colors[lv.sweep[s]] == c) subs.push_back(s);
+        append_symv_items(lv.sw_sub_off, subs, lv.chl, items);
         lv.color_item0[c + 1] = (int64_t)items.size() / 3;
     }
     lv.color_m2.assign(lv.n_colors, 0.0);
@@ -739,6 +736,10 @@ std::unique_ptr<Level> coarsen(lsdd_hierarchy* h, Level& lv, const int32_t* agg_
             lv.color_nnz[lv.colors[i]] += (double)(lv.pat.ptr[d + 1] - lv.pat.ptr[d]);
         }
     }
+    for (int32_t c = 0; c < lv.n_colors; ++c)
+        vlog("  colour %d: %lld DOFs, %lld items, %.1f MB of inverse tiles", c,
+             (long long)(lv.color_row0[c + 1] - lv.color_row0[c]),
+             (long long)(lv.color_item0[c + 1] - lv.color_item0[c]), lv.color_m2[c] * 8e-6);
     lv.d_sw_sub_off = ar.upload(lv.sw_sub_off, st);
     lv.d_sw_sub_dofs = ar.upload(sw_dofs, st);
     lv.d_sw_tp_off = ar.upload(sw_tp_off, st);
@@ -748,7 +749,7 @@ std::unique_ptr<Level> coarsen(lsdd_hierarchy* h, Level& lv, const int32_t* agg_
         std::vector<int64_t> scr_off(n_agg + 1, 0);
         for (int32_t s = 0; s < n_agg; ++s) {
             for (int64_t q = lv.sw_sub_off[s]; q < lv.sw_sub_off[s + 1]; ++q) pos_sub[q] = s;
-            scr_off[s + 1] = scr_off[s] + sub_symv_scratch_len(lv.sw_sub_off[s + 1] - lv.sw_sub_off[s]);
+            scr_off[s + 1] = scr_off[s] + sub_symv_scratch_len(lv.sw_sub_off[s + 1] - lv.sw_sub_off[s], lv.chl);
         }
         lv.d_pos_sub = ar.upload(pos_sub, st);
         lv.d_scr_off = ar.upload(scr_off, st);
@@ -902,10 +903,10 @@ void sweep(lsdd_hierarchy* h, Level& lv, const T* r, T* x, bool forward, bool x_
         const double gb = lv.color_m2[c] * w + lv.color_m[c] * (4 + 3 * w);
         traced(h, "sub_symv", gb, [&] {
             launch_sub_symv<T>(i1 - i0, lv.d_items + 3 * i0, lv.d_sw_sub_off, lv.d_sw_tp_off, V::inv(lv),
-                               V::rloc(lv), lv.d_scr_off, V::scr(lv), h->st);
+                               V::rloc(lv), lv.d_scr_off, V::scr(lv), lv.chl, h->st);
         });
         launch_sub_finalize<T>(r0, r1, lv.d_pos_sub, lv.d_sw_sub_off, lv.d_scr_off, V::scr(lv), lv.d_sw_sub_dofs, x,
-                               true, h->st);
+                               true, lv.chl, lv.fl, h->st);
     }
 }
 
@@ -919,10 +920,10 @@ void vcycle(lsdd_hierarchy* h, size_t l, const T* r, T* x) {
         auto apply = [&](const double* rr, double* xx) {
             traced(h, "coarse_symv", nb, [&] {
                 launch_sub_symv<double>(lv.c_nitems, lv.c_items, lv.c_sub_off, lv.c_tp_off, lv.d_tiles, rr,
-                                        lv.c_scr_off, lv.scr64, h->st);
+                                        lv.c_scr_off, lv.scr64, lv.chl, h->st);
             });
             launch_sub_finalize<double>(0, lv.n, lv.c_pos, lv.c_sub_off, lv.c_scr_off, lv.scr64, nullptr, xx, false,
-                                        h->st);
+                                        lv.chl, lv.fl, h->st);
         };
         if constexpr (std::is_same<T, double>::value) {
             apply(r, x);
