@@ -115,10 +115,16 @@ lsdd_status lsdd_setup_gram_csr(int64_t m, int64_t n, const int64_t* rowptr, con
                                 void* hip_stream, lsdd_hierarchy** out);
 
 /* Solve A x = b for nrhs right-hand sides with PCG (x0 = 0) preconditioned by
- * one V-cycle per iteration.
+ * one V-cycle per iteration.  Every (segment, right-hand side) pair runs its own
+ * CG recurrence (its own step lengths and stopping test, Hestenes-Stiefel beta;
+ * with the FP32 cycle the flexible beta (r_new - r_old)^T z_new / r_old^T z_old);
+ * a hierarchy built by lsdd_setup_elements has one segment, a batched one has one
+ * per instance (lsdd_segments).  Right-hand sides are processed in blocks of 8
+ * whose vectors are interleaved per DOF, so every operator byte of a cycle serves
+ * all right-hand sides of the block.
  *   b, x   device, float64[nrhs * n] (right-hand side r at offset r*n); x is overwritten
- *   info   host, lsdd_info[nrhs] or NULL
- * NaN/Inf in b -> LSDD_E_INVAL.  LSDD_E_NOCONV leaves the last iterate in x. */
+ *   info   host, lsdd_info[nrhs * n_seg] or NULL; entry r * n_seg + s is pair (s, r)
+ * NaN/Inf in b -> LSDD_E_INVAL.  LSDD_E_NOCONV leaves the last iterates in x. */
 lsdd_status lsdd_solve(lsdd_hierarchy* h, const double* b, double* x, int32_t nrhs,
                        void* hip_stream, lsdd_info* info);
 
@@ -130,10 +136,22 @@ lsdd_status lsdd_set_cycle_precision(lsdd_hierarchy* h, int32_t precision);
 /* Change the PCG stopping tolerance and iteration cap of an existing hierarchy. */
 lsdd_status lsdd_set_solve_params(lsdd_hierarchy* h, double rtol, int32_t max_iter);
 
+/* on != 0: run each PCG iteration as two replays of HIP graphs captured on the
+ * first solve (operator apply, step and residual update, stopping test; then the
+ * V-cycle, the new search direction); on = 0: launch every kernel directly.  The
+ * results are bitwise the same either way.  Graphs need a non-NULL stream and are
+ * not used while lsdd_trace is on; they are re-captured after parameter changes. */
+lsdd_status lsdd_set_graph(lsdd_hierarchy* h, int32_t on);
+
+/* Segments of the level-0 vector (host outputs, either may be NULL):
+ *   n_seg     number of segments (1, or the instance count of a batched hierarchy)
+ *   seg_off   int64[n_seg + 1]: segment s is DOFs [seg_off[s], seg_off[s+1]) */
+lsdd_status lsdd_segments(const lsdd_hierarchy* h, int32_t* n_seg, int64_t* seg_off);
+
 /* Per-kernel timing: on != 0 clears the counters and records a pair of HIP
  * events on the solve stream around every launch of the traced kernel classes
- * (sub_gemv, csr_resid_rows, csr_spmv, restrict, prolong, coarse_gemv,
- * pcg_spmv); on = 0 stops recording.  lsdd_trace_get reads class idx
+ * (csr_resid_rows, sub_symv, sub_finalize, csr_spmv, restrict, prolong,
+ * coarse_symv, pcg_spmv); on = 0 stops recording.  lsdd_trace_get reads class idx
  * (0-based; LSDD_E_INVAL past the end): name (host char[name_len]), launches,
  * summed event time in ms and summed algorithmic bytes of those launches (the
  * bytes each launch must move at minimum: matrix entries, indices and vector

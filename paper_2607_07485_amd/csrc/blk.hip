@@ -1,0 +1,624 @@
+// Block (multi right-hand side) cycle kernels and the segmented PCG of the
+// batched solve, for CDNA4 (gfx950).
+//
+// Block vectors interleave NRB = 8 right-hand sides per DOF, so each matrix,
+// inverse or interpolation entry read from HBM is used for all of them: the
+// cycle's bytes per right-hand side drop by up to 8x against separate solves.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+#include "blk.hpp"
+#include "dense.hpp"
+#include "symv.hpp"
+
+namespace lsdd {
+
+namespace {
+
+constexpr int WG = LSDD_WG;
+constexpr int NB = NRB;
+
+inline unsigned grid_for(int64_t n, int per_block = WG) {
+    int64_t g = (n + per_block - 1) / per_block;
+    if (g < 1) g = 1;
+    if (g > 65535LL * 64) g = 65535LL * 64;
+    return (unsigned)g;
+}
+
+// ---------------------------------------------------------------- CSR
+// L lanes per row; lane = (nonzero slot, right-hand side): L / NB nonzeros per step.
+template <typename T, int L>
+__global__ void __launch_bounds__(WG) k_csr_resid_rows_b(int64_t nrows, const int32_t* rows, const int64_t* rowptr,
+                                                         const int32_t* col, const T* val, const T* x, const T* r,
+                                                         T* out, int x_zero) {
+    constexpr int NS = L / NB;
+    const int lane = tid() & (L - 1), k = lane & (NB - 1), slot = lane / NB;
+    const int64_t stride = (int64_t)gridDim.x * (WG / L);
+    for (int64_t t = ((int64_t)blockIdx.x * WG + tid()) / L; t < nrows; t += stride) {
+        const int32_t p = rows[t];
+        T s = 0;
+        if (!x_zero) {
+            const int64_t q1 = rowptr[p + 1];
+#pragma unroll 4
+            for (int64_t q = rowptr[p] + slot; q < q1; q += NS) s += val[q] * x[(int64_t)col[q] * NB + k];
+        }
+        for (int off = L / 2; off >= NB; off >>= 1) s += __shfl_xor(s, off, L);
+        if (slot == 0) out[t * NB + k] = r[(int64_t)p * NB + k] - s;
+    }
+}
+
+template <typename T, int L>
+__global__ void __launch_bounds__(WG) k_csr_spmv_b(int64_t n, const int64_t* rowptr, const int32_t* col,
+                                                   const T* val, const T* x, T* y, const T* r_minus) {
+    constexpr int NS = L / NB;
+    const int lane = tid() & (L - 1), k = lane & (NB - 1), slot = lane / NB;
+    const int64_t stride = (int64_t)gridDim.x * (WG / L);
+    for (int64_t p = ((int64_t)blockIdx.x * WG + tid()) / L; p < n; p += stride) {
+        const int64_t q1 = rowptr[p + 1];
+        T s = 0;
+#pragma unroll 4
+        for (int64_t q = rowptr[p] + slot; q < q1; q += NS) s += val[q] * x[(int64_t)col[q] * NB + k];
+        for (int off = L / 2; off >= NB; off >>= 1) s += __shfl_xor(s, off, L);
+        if (slot == 0) y[p * NB + k] = r_minus ? r_minus[p * NB + k] - s : s;
+    }
+}
+
+// ---------------------------------------------------------------- subdomain product
+// Same work items and partial layout as the single-vector kernel, with NB-wide
+// entries.  Each tile is staged once in LDS (rows padded to 65 entries, so both
+// row-wise and column-wise reads are free of bank conflicts); wave w owns
+// right-hand sides 2w and 2w+1: lane = row for the row part (accumulated over
+// the item's tiles in registers) and lane = column for the column part, so no
+// cross-lane reduction is needed.  The next tile is prefetched into registers
+// while the current one is used.
+template <typename T>
+__global__ void __launch_bounds__(WG) k_sub_symv_b(const int32_t* items, const int64_t* sub_off,
+                                                   const int64_t* tp_off, const T* tiles, const T* rloc,
+                                                   const int64_t* scr_off, T* scr, int chl) {
+    __shared__ T s_t[64 * 65];
+    __shared__ T s_xi[64 * NB];
+    __shared__ T s_xj[64 * NB];
+    const int s = items[3 * blockIdx.x];
+    const int I = items[3 * blockIdx.x + 1];
+    const int ch = items[3 * blockIdx.x + 2];
+    const int64_t o = sub_off[s];
+    const int m = (int)(sub_off[s + 1] - o);
+    const int nt = (m + 63) >> 6;
+    const int J0 = ch * chl;
+    const int nJ = min(chl, I + 1 - J0);
+    const int lane = tid() & 63, w = tid() >> 6;
+    const int k0 = 2 * w;
+    for (int a = tid(); a < 64 * NB; a += WG) {
+        const int r = I * 64 + a / NB;
+        s_xi[a] = r < m ? rloc[(o + r) * NB + (a & (NB - 1))] : (T)0;
+    }
+    T* part = scr + scr_off[s] * NB;
+    T* colpart = part + symv_rowpart_off(nt, chl) * 64 * NB;
+    const T* row0 = tiles + tp_off[s] + (int64_t)I * (I + 1) / 2 * 4096;
+    T v[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) v[i] = row0[(int64_t)J0 * 4096 + i * WG + tid()];
+    T ar0 = 0, ar1 = 0;
+    for (int jj = 0; jj < nJ; ++jj) {
+        const int J = J0 + jj;
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            const int e = i * WG + tid();
+            s_t[(e >> 6) * 65 + (e & 63)] = v[i];
+        }
+        for (int a = tid(); a < 64 * NB; a += WG) {
+            const int c = J * 64 + a / NB;
+            s_xj[a] = c < m ? rloc[(o + c) * NB + (a & (NB - 1))] : (T)0;
+        }
+        __syncthreads();
+        if (jj + 1 < nJ) {
+#pragma unroll
+            for (int i = 0; i < 16; ++i) v[i] = row0[(int64_t)(J + 1) * 4096 + i * WG + tid()];
+        }
+        const T* tr = s_t + lane * 65;
+#pragma unroll 8
+        for (int c = 0; c < 64; ++c) {
+            const T a = tr[c];
+            ar0 += a * s_xj[c * NB + k0];
+            ar1 += a * s_xj[c * NB + k0 + 1];
+        }
+        if (J < I) {
+            T ac0 = 0, ac1 = 0;
+#pragma unroll 8
+            for (int r = 0; r < 64; ++r) {
+                const T a = s_t[r * 65 + lane];
+                ac0 += a * s_xi[r * NB + k0];
+                ac1 += a * s_xi[r * NB + k0 + 1];
+            }
+            T* cp = colpart + (((int64_t)I * (I - 1) / 2 + J) * 64 + lane) * NB + k0;
+            cp[0] = ac0;
+            cp[1] = ac1;
+        }
+    }
+    T* rp = part + ((symv_rowpart_off(I, chl) + ch) * 64 + lane) * NB + k0;
+    rp[0] = ar0;
+    rp[1] = ar1;
+}
+
+// FL threads per DOF sum fixed strided subsets of its partials (all NB
+// right-hand sides at once); the FL sums are added in ascending order.
+template <typename T, int FL>
+__global__ void __launch_bounds__(WG) k_sub_finalize_b(int64_t r0, int64_t r1, const int32_t* pos_sub,
+                                                       const int64_t* sub_off, const int64_t* scr_off, const T* scr,
+                                                       const int32_t* sub_dofs, T* x, int accumulate, int chl) {
+    constexpr int ND = WG / FL;
+    __shared__ T s_y[FL][ND][NB];
+    const int dl = tid() % ND, j = tid() / ND;
+    const int64_t t = r0 + (int64_t)blockIdx.x * ND + dl;
+    T y[NB];
+#pragma unroll
+    for (int q = 0; q < NB; ++q) y[q] = 0;
+    if (t < r1) {
+        const int s = pos_sub[t];
+        const int64_t o = sub_off[s];
+        const int c = (int)(t - o);
+        const int nt = (int)((sub_off[s + 1] - o + 63) >> 6);
+        const int J = c >> 6, l = c & 63;
+        const T* part = scr + (scr_off[s] + symv_rowpart_off(J, chl) * 64 + l) * NB;
+        const T* colpart = scr + (scr_off[s] + symv_rowpart_off(nt, chl) * 64 + l) * NB;
+        const int nch = (J + chl) / chl;
+        const int K = nch + (nt - 1 - J);
+        for (int k = j; k < K; k += FL) {
+            const T* src;
+            if (k < nch) {
+                src = part + (int64_t)k * 64 * NB;
+            } else {
+                const int64_t I = J + 1 + (k - nch);
+                src = colpart + (I * (I - 1) / 2 + J) * 64 * NB;
+            }
+#pragma unroll
+            for (int q = 0; q < NB; ++q) y[q] += src[q];
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < NB; ++q) s_y[j][dl][q] = y[q];
+    __syncthreads();
+    if (j < NB && t < r1) {
+        T v = s_y[0][dl][j];
+        for (int q = 1; q < FL; ++q) v += s_y[q][dl][j];
+        const int64_t d = sub_dofs ? (int64_t)sub_dofs[t] : t;
+        x[d * NB + j] = accumulate ? x[d * NB + j] + v : v;
+    }
+}
+
+// ---------------------------------------------------------------- transfers
+// Restriction rc[coff_i + s] = sum_a Z_i[a, s] t[omega_i[a]] for all right-hand
+// sides: work item = (aggregate, 16 columns); t on omega_i is staged in LDS in
+// chunks of 256 rows, each wave takes 4 columns, lanes stride the rows.
+template <typename T>
+__global__ void __launch_bounds__(WG) k_restrict_b(const int32_t* items, const int64_t* agg_ptr,
+                                                   const int32_t* agg_dofs, const int64_t* zoff, const int32_t* k,
+                                                   const int64_t* coff, const T* Zc, const T* t, T* rc) {
+    __shared__ T s_t[256 * NB];
+    const int ag = items[2 * blockIdx.x], s0 = items[2 * blockIdx.x + 1];
+    const int kk = k[ag];
+    const int64_t a0 = agg_ptr[ag];
+    const int nw = (int)(agg_ptr[ag + 1] - a0);
+    const int lane = tid() & 63, w = tid() >> 6;
+    const T* z = Zc + zoff[ag];
+    T acc[4][NB];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int q = 0; q < NB; ++q) acc[i][q] = 0;
+    for (int c0 = 0; c0 < nw; c0 += 256) {
+        const int cn = min(256, nw - c0);
+        __syncthreads();
+        if (tid() < cn) {
+            const T* src = t + (int64_t)agg_dofs[a0 + c0 + tid()] * NB;
+#pragma unroll
+            for (int q = 0; q < NB; ++q) s_t[tid() * NB + q] = src[q];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int s = s0 + w + 4 * i;
+            if (s < kk) {
+                const T* col = z + (int64_t)s * nw + c0;
+                for (int a = lane; a < cn; a += 64) {
+                    const T zz = col[a];
+#pragma unroll
+                    for (int q = 0; q < NB; ++q) acc[i][q] += zz * s_t[a * NB + q];
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int s = s0 + w + 4 * i;
+        T mine = 0;
+#pragma unroll
+        for (int q = 0; q < NB; ++q) {
+            T v = acc[i][q];
+            for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+            if (lane == q) mine = v;
+        }
+        if (s < kk && lane < NB) rc[(coff[ag] + s) * NB + lane] = mine;
+    }
+}
+
+// Prolongation x[omega_i[a]] += sum_s Z_i[a, s] ec[coff_i + s]: work item =
+// (aggregate, 256 rows); thread per row, ec staged in LDS in chunks of 256 modes.
+template <typename T>
+__global__ void __launch_bounds__(WG) k_prolong_b(const int32_t* items, const int64_t* agg_ptr,
+                                                  const int32_t* agg_dofs, const int64_t* zoff, const int32_t* k,
+                                                  const int64_t* coff, const T* Zc, const T* ec, T* x) {
+    __shared__ T s_e[256 * NB];
+    const int ag = items[2 * blockIdx.x], r0 = items[2 * blockIdx.x + 1];
+    const int kk = k[ag];
+    const int64_t a0 = agg_ptr[ag];
+    const int nw = (int)(agg_ptr[ag + 1] - a0);
+    const int a = r0 + tid();
+    const T* z = Zc + zoff[ag] + a;
+    T acc[NB];
+#pragma unroll
+    for (int q = 0; q < NB; ++q) acc[q] = 0;
+    for (int sc = 0; sc < kk; sc += 256) {
+        const int sn = min(256, kk - sc);
+        __syncthreads();
+        for (int e = tid(); e < sn * NB; e += WG) s_e[e] = ec[(coff[ag] + sc) * NB + e];
+        __syncthreads();
+        if (a < nw) {
+            for (int s = 0; s < sn; ++s) {
+                const T zz = z[(int64_t)(sc + s) * nw];
+#pragma unroll
+                for (int q = 0; q < NB; ++q) acc[q] += zz * s_e[s * NB + q];
+            }
+        }
+    }
+    if (a < nw) {
+        T* dst = x + (int64_t)agg_dofs[a0 + a] * NB;
+#pragma unroll
+        for (int q = 0; q < NB; ++q) dst[q] += acc[q];
+    }
+}
+
+__global__ void k_gather_rhs(int64_t n, int nr, const double* b, int64_t ldb, double* B) {
+    for (int64_t e = blockIdx.x * (int64_t)WG + tid(); e < n * NB; e += (int64_t)gridDim.x * WG) {
+        const int64_t d = e / NB;
+        const int k = (int)(e % NB);
+        B[e] = k < nr ? b[k * ldb + d] : 0.0;
+    }
+}
+
+__global__ void k_scatter_sol(int64_t n, int nr, const double* X, double* x, int64_t ldx) {
+    for (int64_t e = blockIdx.x * (int64_t)WG + tid(); e < n * NB; e += (int64_t)gridDim.x * WG) {
+        const int64_t d = e / NB;
+        const int k = (int)(e % NB);
+        if (k < nr) x[k * ldx + d] = X[e];
+    }
+}
+
+// ---------------------------------------------------------------- segmented PCG
+// Block b of the table covers DOFs [lo, hi) of one segment; thread = (DOF lane,
+// right-hand side), a fixed-order tree over the DOF lanes gives NR sums.
+template <int NR>
+__global__ void __launch_bounds__(WG) k_seg_dot(const int64_t* blk_lo, const int64_t* blk_hi, const double* a0,
+                                                const double* b0, const double* a1, const double* b1, double* part,
+                                                int n_blk) {
+    __shared__ double s_r[2][WG];
+    const int b = blockIdx.x;
+    const int k = tid() % NR, dl = tid() / NR;
+    constexpr int DL = WG / NR;
+    double u = 0.0, v = 0.0;
+    for (int64_t d = blk_lo[b] + dl; d < blk_hi[b]; d += DL) {
+        const int64_t e = d * NR + k;
+        u += a0[e] * b0[e];
+        if (a1) v += a1[e] * b1[e];
+    }
+    s_r[0][tid()] = u;
+    s_r[1][tid()] = v;
+    __syncthreads();
+    for (int off = WG / 2; off >= NR; off >>= 1) {
+        if (tid() < off) {
+            s_r[0][tid()] += s_r[0][tid() + off];
+            s_r[1][tid()] += s_r[1][tid() + off];
+        }
+        __syncthreads();
+    }
+    if (tid() < NR) {
+        part[(int64_t)b * NR + tid()] = s_r[0][tid()];
+        part[((int64_t)n_blk + b) * NR + tid()] = s_r[1][tid()];
+    }
+}
+
+// out[s * NR + k] = sum over the blocks of segment s, in block order
+__global__ void k_seg_sum(int n_seg, int nr, const int32_t* seg_blk, const double* part, int n_blk, double* out0,
+                          double* out1) {
+    const int i = blockIdx.x * WG + tid();
+    if (i >= n_seg * nr) return;
+    const int s = i / nr, k = i % nr;
+    double u = 0.0, v = 0.0;
+    for (int b = seg_blk[s]; b < seg_blk[s + 1]; ++b) {
+        u += part[(int64_t)b * nr + k];
+        v += part[((int64_t)n_blk + b) * nr + k];
+    }
+    out0[i] = u;
+    if (out1) out1[i] = v;
+}
+
+__global__ void k_pcg_init(int n_s, const double* bb, int32_t* act, int32_t* iters, double* relres,
+                           int32_t* it_flag) {
+    const int i = blockIdx.x * WG + tid();
+    if (i == 0) {
+        it_flag[0] = 0;
+        it_flag[1] = 0;
+    }
+    if (i >= n_s) return;
+    act[i] = bb[i] > 0.0 ? 1 : 0;
+    iters[i] = 0;
+    relres[i] = bb[i] > 0.0 ? 1.0 : 0.0;
+}
+
+__global__ void k_pcg_alpha(int n_s, const int32_t* act, const double* rz, const double* pq, double* alpha,
+                            int32_t* flag) {
+    const int i = blockIdx.x * WG + tid();
+    if (i >= n_s) return;
+    double a = 0.0;
+    if (act[i]) {
+        const double d = pq[i];
+        if (!(d > 0.0) || !isfinite(d) || !isfinite(rz[i])) flag[0] = 1;
+        else a = rz[i] / d;
+    }
+    alpha[i] = a;
+}
+
+template <int NR>
+__global__ void __launch_bounds__(WG) k_pcg_update_xr(const int32_t* blk_seg, const int64_t* blk_lo,
+                                                      const int64_t* blk_hi, const int32_t* act, const double* alpha,
+                                                      const double* p, const double* q, double* x, double* r,
+                                                      double* part) {
+    __shared__ double s_r[WG];
+    const int b = blockIdx.x;
+    const int k = tid() % NR, dl = tid() / NR;
+    constexpr int DL = WG / NR;
+    const int i = blk_seg[b] * NR + k;
+    const bool on = act[i] != 0;
+    const double a = alpha[i];
+    double u = 0.0;
+    for (int64_t d = blk_lo[b] + dl; d < blk_hi[b]; d += DL) {
+        const int64_t e = d * NR + k;
+        double re = r[e];
+        if (on) {
+            x[e] += a * p[e];
+            re -= a * q[e];
+            r[e] = re;
+        }
+        u += re * re;
+    }
+    s_r[tid()] = u;
+    __syncthreads();
+    for (int off = WG / 2; off >= NR; off >>= 1) {
+        if (tid() < off) s_r[tid()] += s_r[tid() + off];
+        __syncthreads();
+    }
+    if (tid() < NR) part[(int64_t)b * NR + tid()] = s_r[tid()];
+}
+
+// single workgroup: state transitions and the active count (fixed-order sum)
+__global__ void __launch_bounds__(WG) k_pcg_check(int n_s, int32_t* it_dev, double tol2, const double* bb,
+                                                  const double* rr, int32_t* act, int32_t* iters, double* relres,
+                                                  int32_t* count, int32_t* flag) {
+    __shared__ int s_c[WG];
+    const int it = it_dev[0] + 1;
+    int c = 0;
+    for (int i = tid(); i < n_s; i += WG) {
+        if (!act[i]) continue;
+        const double v = rr[i];
+        if (!isfinite(v)) {
+            flag[0] = 1;
+            continue;
+        }
+        relres[i] = sqrt(v / bb[i]);
+        iters[i] = it;
+        if (v <= tol2 * bb[i]) act[i] = 0;
+        else ++c;
+    }
+    s_c[tid()] = c;
+    __syncthreads();
+    for (int off = WG / 2; off > 0; off >>= 1) {
+        if (tid() < off) s_c[tid()] += s_c[tid() + off];
+        __syncthreads();
+    }
+    if (tid() == 0) {
+        count[0] = s_c[0];
+        it_dev[0] = it;
+    }
+}
+
+__global__ void k_pcg_beta(int n_s, const int32_t* act, const double* rz_new, const double* rz_old_dot, double* rz,
+                           double* beta, int32_t* flag) {
+    const int i = blockIdx.x * WG + tid();
+    if (i >= n_s) return;
+    double bt = 0.0;
+    if (act[i]) {
+        const double num = rz_old_dot ? rz_new[i] - rz_old_dot[i] : rz_new[i];
+        bt = num / rz[i];
+        if (!isfinite(bt)) flag[0] = 1;
+        rz[i] = rz_new[i];
+    }
+    beta[i] = bt;
+}
+
+template <int NR>
+__global__ void __launch_bounds__(WG) k_pcg_update_p(const int32_t* blk_seg, const int64_t* blk_lo,
+                                                     const int64_t* blk_hi, const int32_t* act, const double* beta,
+                                                     const double* z, double* p) {
+    const int b = blockIdx.x;
+    const int k = tid() % NR, dl = tid() / NR;
+    constexpr int DL = WG / NR;
+    const int i = blk_seg[b] * NR + k;
+    if (!act[i]) return;
+    const double bt = beta[i];
+    for (int64_t d = blk_lo[b] + dl; d < blk_hi[b]; d += DL) {
+        const int64_t e = d * NR + k;
+        p[e] = z[e] + bt * p[e];
+    }
+}
+
+__global__ void k_pcg_start(int64_t len, const double* b, double* r, double* x) {
+    for (int64_t e = blockIdx.x * (int64_t)WG + tid(); e < len; e += (int64_t)gridDim.x * WG) {
+        r[e] = b[e];
+        x[e] = 0.0;
+    }
+}
+
+}  // namespace
+
+// ====================================================================== launchers
+
+template <typename T>
+void launch_csr_resid_rows_b(int64_t nrows, const int32_t* rows, const int64_t* rowptr, const int32_t* col,
+                             const T* val, const T* x, const T* r, T* out, bool x_zero, int lanes, hipStream_t st) {
+    if (nrows <= 0) return;
+    if (lanes >= 64)
+        hipLaunchKernelGGL((k_csr_resid_rows_b<T, 64>), dim3(grid_for(nrows * 64)), dim3(WG), 0, st, nrows, rows,
+                           rowptr, col, val, x, r, out, x_zero ? 1 : 0);
+    else
+        hipLaunchKernelGGL((k_csr_resid_rows_b<T, 16>), dim3(grid_for(nrows * 16)), dim3(WG), 0, st, nrows, rows,
+                           rowptr, col, val, x, r, out, x_zero ? 1 : 0);
+}
+
+template <typename T>
+void launch_csr_spmv_b(int64_t n, const int64_t* rowptr, const int32_t* col, const T* val, const T* x, T* y,
+                       const T* r_minus, int lanes, hipStream_t st) {
+    if (n <= 0) return;
+    if (lanes >= 64)
+        hipLaunchKernelGGL((k_csr_spmv_b<T, 64>), dim3(grid_for(n * 64)), dim3(WG), 0, st, n, rowptr, col, val, x, y,
+                           r_minus);
+    else
+        hipLaunchKernelGGL((k_csr_spmv_b<T, 16>), dim3(grid_for(n * 16)), dim3(WG), 0, st, n, rowptr, col, val, x, y,
+                           r_minus);
+}
+
+template <typename T>
+void launch_sub_symv_b(int64_t n_items, const int32_t* items, const int64_t* sub_off, const int64_t* tp_off,
+                       const T* tiles, const T* rloc, const int64_t* scr_off, T* scr, int chl, hipStream_t st) {
+    if (n_items <= 0) return;
+    hipLaunchKernelGGL(k_sub_symv_b<T>, dim3((unsigned)n_items), dim3(WG), 0, st, items, sub_off, tp_off, tiles, rloc,
+                       scr_off, scr, chl);
+}
+
+template <typename T>
+void launch_sub_finalize_b(int64_t r0, int64_t r1, const int32_t* pos_sub, const int64_t* sub_off,
+                           const int64_t* scr_off, const T* scr, const int32_t* sub_dofs, T* x, bool accumulate,
+                           int chl, int fl, hipStream_t st) {
+    if (r1 <= r0) return;
+    if (fl >= 32)
+        hipLaunchKernelGGL((k_sub_finalize_b<T, 32>), dim3(grid_for(r1 - r0, WG / 32)), dim3(WG), 0, st, r0, r1,
+                           pos_sub, sub_off, scr_off, scr, sub_dofs, x, accumulate ? 1 : 0, chl);
+    else
+        hipLaunchKernelGGL((k_sub_finalize_b<T, 8>), dim3(grid_for(r1 - r0, WG / 8)), dim3(WG), 0, st, r0, r1,
+                           pos_sub, sub_off, scr_off, scr, sub_dofs, x, accumulate ? 1 : 0, chl);
+}
+
+template <typename T>
+void launch_restrict_b(int64_t n_items, const int32_t* items, const int64_t* agg_ptr, const int32_t* agg_dofs,
+                       const int64_t* zoff, const int32_t* k, const int64_t* coff, const T* Zc, const T* t, T* rc,
+                       hipStream_t st) {
+    if (n_items <= 0) return;
+    hipLaunchKernelGGL(k_restrict_b<T>, dim3((unsigned)n_items), dim3(WG), 0, st, items, agg_ptr, agg_dofs, zoff, k,
+                       coff, Zc, t, rc);
+}
+
+template <typename T>
+void launch_prolong_b(int64_t n_items, const int32_t* items, const int64_t* agg_ptr, const int32_t* agg_dofs,
+                      const int64_t* zoff, const int32_t* k, const int64_t* coff, const T* Zc, const T* ec, T* x,
+                      hipStream_t st) {
+    if (n_items <= 0) return;
+    hipLaunchKernelGGL(k_prolong_b<T>, dim3((unsigned)n_items), dim3(WG), 0, st, items, agg_ptr, agg_dofs, zoff, k,
+                       coff, Zc, ec, x);
+}
+
+void launch_gather_rhs(int64_t n, int32_t nr, const double* b, int64_t ldb, double* B, hipStream_t st) {
+    hipLaunchKernelGGL(k_gather_rhs, dim3(grid_for(n * NB)), dim3(WG), 0, st, n, (int)nr, b, ldb, B);
+}
+
+void launch_scatter_sol(int64_t n, int32_t nr, const double* X, double* x, int64_t ldx, hipStream_t st) {
+    hipLaunchKernelGGL(k_scatter_sol, dim3(grid_for(n * NB)), dim3(WG), 0, st, n, (int)nr, X, x, ldx);
+}
+
+void launch_seg_dot(const SegTable& t, int nr, const double* a0, const double* b0, const double* a1,
+                    const double* b1, double* part, double* out0, double* out1, hipStream_t st) {
+    if (nr == NB)
+        hipLaunchKernelGGL(k_seg_dot<NB>, dim3((unsigned)t.n_blk), dim3(WG), 0, st, t.blk_lo, t.blk_hi, a0, b0, a1,
+                           b1, part, t.n_blk);
+    else
+        hipLaunchKernelGGL(k_seg_dot<1>, dim3((unsigned)t.n_blk), dim3(WG), 0, st, t.blk_lo, t.blk_hi, a0, b0, a1, b1,
+                           part, t.n_blk);
+    hipLaunchKernelGGL(k_seg_sum, dim3(grid_for((int64_t)t.n_seg * nr)), dim3(WG), 0, st, t.n_seg, nr, t.seg_blk,
+                       part, t.n_blk, out0, a1 ? out1 : nullptr);
+}
+
+void launch_pcg_init(int n_s, const double* bb, int32_t* act, int32_t* iters, double* relres, int32_t* it_flag,
+                     hipStream_t st) {
+    hipLaunchKernelGGL(k_pcg_init, dim3(grid_for(n_s)), dim3(WG), 0, st, n_s, bb, act, iters, relres, it_flag);
+}
+
+void launch_pcg_alpha(int n_s, const int32_t* act, const double* rz, const double* pq, double* alpha, int32_t* flag,
+                      hipStream_t st) {
+    hipLaunchKernelGGL(k_pcg_alpha, dim3(grid_for(n_s)), dim3(WG), 0, st, n_s, act, rz, pq, alpha, flag);
+}
+
+void launch_pcg_update_xr(const SegTable& t, int nr, const int32_t* act, const double* alpha, const double* p,
+                          const double* q, double* x, double* r, double* part, double* rr, hipStream_t st) {
+    if (nr == NB)
+        hipLaunchKernelGGL(k_pcg_update_xr<NB>, dim3((unsigned)t.n_blk), dim3(WG), 0, st, t.blk_seg, t.blk_lo,
+                           t.blk_hi, act, alpha, p, q, x, r, part);
+    else
+        hipLaunchKernelGGL(k_pcg_update_xr<1>, dim3((unsigned)t.n_blk), dim3(WG), 0, st, t.blk_seg, t.blk_lo,
+                           t.blk_hi, act, alpha, p, q, x, r, part);
+    hipLaunchKernelGGL(k_seg_sum, dim3(grid_for((int64_t)t.n_seg * nr)), dim3(WG), 0, st, t.n_seg, nr, t.seg_blk,
+                       part, 0, rr, nullptr);
+}
+
+void launch_pcg_check(int n_s, int32_t* it_dev, double tol2, const double* bb, const double* rr, int32_t* act,
+                      int32_t* iters, double* relres, int32_t* count, int32_t* flag, hipStream_t st) {
+    hipLaunchKernelGGL(k_pcg_check, dim3(1), dim3(WG), 0, st, n_s, it_dev, tol2, bb, rr, act, iters, relres, count,
+                       flag);
+}
+
+void launch_pcg_beta(int n_s, const int32_t* act, const double* rz_new, const double* rz_old_dot, double* rz,
+                     double* beta, int32_t* flag, hipStream_t st) {
+    hipLaunchKernelGGL(k_pcg_beta, dim3(grid_for(n_s)), dim3(WG), 0, st, n_s, act, rz_new, rz_old_dot, rz, beta,
+                       flag);
+}
+
+void launch_pcg_update_p(const SegTable& t, int nr, const int32_t* act, const double* beta, const double* z,
+                         double* p, hipStream_t st) {
+    if (nr == NB)
+        hipLaunchKernelGGL(k_pcg_update_p<NB>, dim3((unsigned)t.n_blk), dim3(WG), 0, st, t.blk_seg, t.blk_lo,
+                           t.blk_hi, act, beta, z, p);
+    else
+        hipLaunchKernelGGL(k_pcg_update_p<1>, dim3((unsigned)t.n_blk), dim3(WG), 0, st, t.blk_seg, t.blk_lo,
+                           t.blk_hi, act, beta, z, p);
+}
+
+void launch_pcg_start(int64_t len, const double* b, double* r, double* x, hipStream_t st) {
+    hipLaunchKernelGGL(k_pcg_start, dim3(grid_for(len)), dim3(WG), 0, st, len, b, r, x);
+}
+
+#define LSDD_BLK_INST(T)                                                                                            \
+    template void launch_csr_resid_rows_b<T>(int64_t, const int32_t*, const int64_t*, const int32_t*, const T*,      \
+                                             const T*, const T*, T*, bool, int, hipStream_t);                         \
+    template void launch_csr_spmv_b<T>(int64_t, const int64_t*, const int32_t*, const T*, const T*, T*, const T*,    \
+                                       int, hipStream_t);                                                             \
+    template void launch_sub_symv_b<T>(int64_t, const int32_t*, const int64_t*, const int64_t*, const T*, const T*,  \
+                                       const int64_t*, T*, int, hipStream_t);                                         \
+    template void launch_sub_finalize_b<T>(int64_t, int64_t, const int32_t*, const int64_t*, const int64_t*,         \
+                                           const T*, const int32_t*, T*, bool, int, int, hipStream_t);                \
+    template void launch_restrict_b<T>(int64_t, const int32_t*, const int64_t*, const int32_t*, const int64_t*,      \
+                                       const int32_t*, const int64_t*, const T*, const T*, T*, hipStream_t);          \
+    template void launch_prolong_b<T>(int64_t, const int32_t*, const int64_t*, const int32_t*, const int64_t*,       \
+                                      const int32_t*, const int64_t*, const T*, const T*, T*, hipStream_t);
+LSDD_BLK_INST(double)
+LSDD_BLK_INST(float)
+
+}  // namespace lsdd

@@ -16,6 +16,7 @@
 #include "batched.hpp"
 #include "dense.hpp"
 #include "kernels.hpp"
+#include "symv.hpp"
 
 namespace lsdd {
 
@@ -663,15 +664,6 @@ __global__ void __launch_bounds__(WG) k_csr_spmv(int64_t n, const int64_t* rowpt
 // go to a per-subdomain scratch -- row parts per (tile row, chunk), column
 // parts per tile -- that k_sub_finalize sums in a fixed order, so the smoother
 // is the same linear map on every application (no order-dependent atomics).
-__host__ __device__ inline int64_t symv_rowpart_off(int I, int chl) {
-    // chunks of tile rows 0..I-1: sum_{i<I} ceil((i+1)/chl)
-    int64_t full = I / chl, rem = I % chl;
-    return chl * full * (full + 1) / 2 + rem * (full + 1);
-}
-__host__ __device__ inline int64_t symv_scratch_len(int nt, int chl) {
-    return (symv_rowpart_off(nt, chl) + (int64_t)nt * (nt - 1) / 2) * 64;
-}
-
 template <typename T>
 __global__ void __launch_bounds__(WG) k_sub_symv(const int32_t* items, const int64_t* sub_off, const int64_t* tp_off,
                                                  const T* tiles, const T* rloc, const int64_t* scr_off, T* scr,

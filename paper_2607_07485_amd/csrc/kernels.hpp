@@ -7,6 +7,7 @@
 #include <vector>
 
 #include "batched.hpp"
+#include "symv.hpp"
 
 namespace lsdd {
 
@@ -119,7 +120,6 @@ template <typename T>
 void launch_sub_finalize(int64_t r0, int64_t r1, const int32_t* pos_sub, const int64_t* sub_off,
                          const int64_t* scr_off, const T* scr, const int32_t* sub_dofs, T* x, bool accumulate,
                          int chl, int fl, hipStream_t st);
-constexpr int SUB_MAX_CHUNK = 8;
 // scratch entries for a subdomain of size m; append its work items (s, tile row, chunk)
 int64_t sub_symv_scratch_len(int64_t m, int chl);
 void sub_symv_items(int32_t s, int64_t m, int chl, std::vector<int32_t>& items);

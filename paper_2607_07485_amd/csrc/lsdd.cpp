@@ -20,6 +20,7 @@
 
 #include "graph.hpp"
 #include "kernels.hpp"
+#include "blk.hpp"
 
 namespace {
 
@@ -121,6 +122,15 @@ std::vector<T> download(const T* d, size_t count, hipStream_t st) {
     return h;
 }
 
+template <typename T>
+struct VecSet {
+    T* r = nullptr;
+    T* x = nullptr;
+    T* t = nullptr;
+    T* rloc = nullptr;
+    T* scr = nullptr;
+};
+
 struct Level {
     int32_t level = 0;
     int64_t n = 0;
@@ -177,8 +187,6 @@ struct Level {
     int32_t* d_items = nullptr;       // (subdomain, tile row), grouped by colour
     int32_t* d_pos_sub = nullptr;     // sweep-order subdomain of every Omega entry
     int64_t* d_scr_off = nullptr;     // per subdomain: offset of its partial-sum scratch
-    double* scr64 = nullptr;
-    float* scr32 = nullptr;
     // coarsest level as one packed symmetric "subdomain"
     int64_t* c_sub_off = nullptr;
     int64_t* c_tp_off = nullptr;
@@ -192,10 +200,14 @@ struct Level {
     int64_t inv_len = 0, tiles_len = 0;
     // coarsest
     double* d_cinv = nullptr;
-    // vectors
-    double *r64 = nullptr, *x64 = nullptr, *t64 = nullptr, *rloc64 = nullptr;
-    float *r32 = nullptr, *x32 = nullptr, *t32 = nullptr, *rloc32 = nullptr;
-    double *cr64 = nullptr, *cx64 = nullptr;   // FP64 staging for the FP32 coarsest solve
+    // vectors: [0] single vectors, [1] blocks of NRB right-hand sides (allocated on first use)
+    VecSet<double> v64[2];
+    VecSet<float> v32[2];
+    double* cr64[2] = {nullptr, nullptr};   // FP64 staging for the FP32 coarsest solve
+    double* cx64[2] = {nullptr, nullptr};
+    int64_t rloc_len = 0;                   // gathered subdomain residual entries (sum |Omega_i|)
+    int64_t scr_len = 0;                    // partial-sum entries of the subdomain product
+    std::vector<double> color_scr;          // partial-sum entries per colour
 };
 
 // Per-kernel-class HIP-event timing on the hierarchy's stream, with the
@@ -265,12 +277,21 @@ struct lsdd_hierarchy {
     lsdd::Arena arena;
     std::vector<std::unique_ptr<lsdd::Level>> L;
     double setup_s = 0.0;
-    // PCG state
-    double *p = nullptr, *q = nullptr, *z = nullptr, *r = nullptr, *rold = nullptr;
-    double* scal = nullptr;       // device scalars
-    double* partials = nullptr;
-    int32_t* d_flag = nullptr;
-    double* h_scal = nullptr;     // pinned host mirror
+    // PCG work vectors: [0] single vectors, [1] blocks of NRB right-hand sides
+    struct PcgBuf {
+        double *B = nullptr, *X = nullptr, *r = nullptr, *p = nullptr, *q = nullptr, *z = nullptr, *rold = nullptr;
+    } pb[2];
+    // segments of the level-0 vector (one per problem instance) and the reduction table
+    std::vector<int64_t> seg_off;
+    lsdd::SegTable seg;
+    int32_t nsm = 0;              // n_seg * NRB: stride of the per-pair scalar arrays
+    double* sc = nullptr;         // per-pair scalars: bb rz pq rr rzn rzo alpha beta relres
+    int32_t* ic = nullptr;        // act, iters (nsm each), then count, it, flag, finite-check flag
+    double* part = nullptr;       // reduction partials, 2 * n_blk * NRB
+    int32_t* h_ic = nullptr;      // pinned host mirror of count, it, flag
+    // hipGraph-captured halves of the PCG iteration: [block][cycle precision][half]
+    bool use_graph = false;
+    hipGraphExec_t gx[2][2][2] = {};
 };
 
 namespace lsdd {
@@ -323,22 +344,30 @@ void assemble_operator(lsdd_hierarchy* h, Level& lv) {
     }
 }
 
-void alloc_vectors(lsdd_hierarchy* h, Level& lv, int64_t rloc_len) {
+// Cycle vectors of one level: set b = 0 holds single vectors, b = 1 blocks of
+// NRB interleaved right-hand sides.
+void alloc_vectors(lsdd_hierarchy* h, Level& lv, int b) {
     Arena& a = h->arena;
+    const int64_t w = b ? NRB : 1;
+    const int64_t nl = std::max<int64_t>(lv.rloc_len, 1) * w, ns = std::max<int64_t>(lv.scr_len, 1) * w;
     if (h->prm.precision == 1) {
-        lv.r32 = a.alloc<float>(lv.n);
-        lv.x32 = a.alloc<float>(lv.n);
-        lv.t32 = a.alloc<float>(lv.n);
-        lv.rloc32 = a.alloc<float>(std::max<int64_t>(rloc_len, 1));
+        VecSet<float>& v = lv.v32[b];
+        v.r = a.alloc<float>(lv.n * w);
+        v.x = a.alloc<float>(lv.n * w);
+        v.t = a.alloc<float>(lv.n * w);
+        v.rloc = a.alloc<float>(nl);
+        v.scr = a.alloc<float>(ns);
         if (lv.coarsest) {
-            lv.cr64 = a.alloc<double>(lv.n);
-            lv.cx64 = a.alloc<double>(lv.n);
+            lv.cr64[b] = a.alloc<double>(lv.n * w);
+            lv.cx64[b] = a.alloc<double>(lv.n * w);
         }
     }
-    lv.r64 = a.alloc<double>(lv.n);
-    lv.x64 = a.alloc<double>(lv.n);
-    lv.t64 = a.alloc<double>(lv.n);
-    lv.rloc64 = a.alloc<double>(std::max<int64_t>(rloc_len, 1));
+    VecSet<double>& v = lv.v64[b];
+    v.r = a.alloc<double>(lv.n * w);
+    v.x = a.alloc<double>(lv.n * w);
+    v.t = a.alloc<double>(lv.n * w);
+    v.rloc = a.alloc<double>(nl);
+    v.scr = a.alloc<double>(ns);
 }
 
 template <class F>
@@ -406,7 +435,7 @@ void make_coarsest(lsdd_hierarchy* h, Level& lv) {
         ar.release(d_inv_off);
         ar.release(lv.d_cinv);
         lv.d_cinv = nullptr;
-        lv.scr64 = ar.alloc<double>(scr_off[1]);
+        lv.scr_len = scr_off[1];
     }
     alloc_vectors(h, lv, 0);
 }
@@ -753,8 +782,9 @@ std::unique_ptr<Level> coarsen(lsdd_hierarchy* h, Level& lv, const int32_t* agg_
         }
         lv.d_pos_sub = ar.upload(pos_sub, st);
         lv.d_scr_off = ar.upload(scr_off, st);
-        lv.scr64 = ar.alloc<double>(scr_off[n_agg]);
-        if (P.precision == 1) lv.scr32 = ar.alloc<float>(scr_off[n_agg]);
+        lv.scr_len = scr_off[n_agg];
+        lv.color_scr.assign(lv.n_colors, 0.0);
+        for (int32_t q = 0; q < n_agg; ++q) lv.color_scr[lv.colors[lv.sweep[q]]] += (double)(scr_off[q + 1] - scr_off[q]);
     }
     {
         int64_t* d_tp_agg = ar.upload(tp_agg, st);
@@ -767,7 +797,8 @@ std::unique_ptr<Level> coarsen(lsdd_hierarchy* h, Level& lv, const int32_t* agg_
         ar.release(lv.d_inv);
         lv.d_inv = nullptr;
     }
-    alloc_vectors(h, lv, (int64_t)sw_dofs.size());
+    lv.rloc_len = (int64_t)sw_dofs.size();
+    alloc_vectors(h, lv, 0);
     // free local-problem inputs that the solve does not use
     for (void* p : {(void*)d_sub_ptr, (void*)d_sub_dofs, (void*)d_cl_ptr, (void*)d_cl_elems, (void*)d_clpos_off,
                     (void*)d_clpos, (void*)d_mult, (void*)d_inv_off, (void*)d_zst_off, (void*)d_status})
@@ -861,107 +892,277 @@ std::unique_ptr<Level> coarsen(lsdd_hierarchy* h, Level& lv, const int32_t* agg_
 // ---------------------------------------------------------------- V-cycle
 
 template <typename T>
-struct LvVec;
+struct LvOps;
 template <>
-struct LvVec<double> {
-    static double* r(Level& l) { return l.r64; }
-    static double* x(Level& l) { return l.x64; }
-    static double* t(Level& l) { return l.t64; }
-    static double* rloc(Level& l) { return l.rloc64; }
+struct LvOps<double> {
+    static VecSet<double>& v(Level& l, int b) { return l.v64[b]; }
     static const double* val(Level& l) { return l.d_val; }
     static const double* Z(Level& l) { return l.d_Zc; }
     static const double* inv(Level& l) { return l.d_tiles; }
-    static double* scr(Level& l) { return l.scr64; }
 };
 template <>
-struct LvVec<float> {
-    static float* r(Level& l) { return l.r32; }
-    static float* x(Level& l) { return l.x32; }
-    static float* t(Level& l) { return l.t32; }
-    static float* rloc(Level& l) { return l.rloc32; }
+struct LvOps<float> {
+    static VecSet<float>& v(Level& l, int b) { return l.v32[b]; }
     static const float* val(Level& l) { return l.d_val32; }
     static const float* Z(Level& l) { return l.d_Zc32; }
     static const float* inv(Level& l) { return l.d_tiles32; }
-    static float* scr(Level& l) { return l.scr32; }
 };
 
-template <typename T>
+// Cycle kernels for NR = 1 (single vectors) or NR = NRB (interleaved blocks).
+template <typename T, int NR>
+struct Cyc {
+    static void resid_rows(int64_t nrows, const int32_t* rows, Level& lv, const T* val, const T* x, const T* r, T* out,
+                           bool xz, hipStream_t st) {
+        if constexpr (NR == 1) launch_csr_resid_rows<T>(nrows, rows, lv.d_rowptr, lv.d_col, val, x, r, out, xz, lv.lanes, st);
+        else launch_csr_resid_rows_b<T>(nrows, rows, lv.d_rowptr, lv.d_col, val, x, r, out, xz, lv.lanes, st);
+    }
+    static void spmv(Level& lv, const T* val, const T* x, T* y, const T* r_minus, hipStream_t st) {
+        if constexpr (NR == 1) launch_csr_spmv<T>(lv.n, lv.d_rowptr, lv.d_col, val, x, y, r_minus, lv.lanes, st);
+        else launch_csr_spmv_b<T>(lv.n, lv.d_rowptr, lv.d_col, val, x, y, r_minus, lv.lanes, st);
+    }
+    static void symv(int64_t n_items, const int32_t* items, const int64_t* sub_off, const int64_t* tp_off,
+                     const T* tiles, const T* rloc, const int64_t* scr_off, T* scr, int chl, hipStream_t st) {
+        if constexpr (NR == 1) launch_sub_symv<T>(n_items, items, sub_off, tp_off, tiles, rloc, scr_off, scr, chl, st);
+        else launch_sub_symv_b<T>(n_items, items, sub_off, tp_off, tiles, rloc, scr_off, scr, chl, st);
+    }
+    static void finalize(int64_t r0, int64_t r1, const int32_t* pos, const int64_t* sub_off, const int64_t* scr_off,
+                         const T* scr, const int32_t* dofs, T* x, bool acc, int chl, int fl, hipStream_t st) {
+        if constexpr (NR == 1) launch_sub_finalize<T>(r0, r1, pos, sub_off, scr_off, scr, dofs, x, acc, chl, fl, st);
+        else launch_sub_finalize_b<T>(r0, r1, pos, sub_off, scr_off, scr, dofs, x, acc, chl, fl, st);
+    }
+    static void restrict_(Level& lv, const T* Z, const T* t, T* rc, hipStream_t st) {
+        if constexpr (NR == 1)
+            launch_restrict<T>(lv.n_ritems, lv.d_ritems, lv.d_agg_ptr, lv.d_agg_dofs, lv.d_zoff, lv.d_k, lv.d_coff, Z,
+                               t, rc, st);
+        else
+            launch_restrict_b<T>(lv.n_ritems, lv.d_ritems, lv.d_agg_ptr, lv.d_agg_dofs, lv.d_zoff, lv.d_k, lv.d_coff,
+                                 Z, t, rc, st);
+    }
+    static void prolong(Level& lv, const T* Z, const T* ec, T* x, hipStream_t st) {
+        if constexpr (NR == 1)
+            launch_prolong<T>(lv.n_pitems, lv.d_pitems, lv.d_agg_ptr, lv.d_agg_dofs, lv.d_zoff, lv.d_k, lv.d_coff, Z,
+                              ec, x, st);
+        else
+            launch_prolong_b<T>(lv.n_pitems, lv.d_pitems, lv.d_agg_ptr, lv.d_agg_dofs, lv.d_zoff, lv.d_k, lv.d_coff,
+                                Z, ec, x, st);
+    }
+};
+
+template <typename T, int NR>
 void sweep(lsdd_hierarchy* h, Level& lv, const T* r, T* x, bool forward, bool x_zero_first) {
-    using V = LvVec<T>;
+    using O = LvOps<T>;
+    using C = Cyc<T, NR>;
+    VecSet<T>& v = O::v(lv, NR > 1);
+    const double w = (double)sizeof(T), wv = w * NR;
     for (int32_t cc = 0; cc < lv.n_colors; ++cc) {
         int32_t c = forward ? cc : lv.n_colors - 1 - cc;
         int64_t r0 = lv.color_row0[c], r1 = lv.color_row0[c + 1];
         int64_t i0 = lv.color_item0[c], i1 = lv.color_item0[c + 1];
         if (i1 == i0) continue;
-        const double w = (double)sizeof(T);
         const bool xz = x_zero_first && cc == 0;
-        const double rb = lv.color_m[c] * (4 + 8 + 3 * w) + (xz ? 0.0 : lv.color_nnz[c] * (4 + w));
+        const double rb = lv.color_m[c] * (4 + 8 + 3 * wv) + (xz ? 0.0 : lv.color_nnz[c] * (4 + w));
         traced(h, "csr_resid_rows", rb, [&] {
-            launch_csr_resid_rows<T>(r1 - r0, lv.d_sw_sub_dofs + r0, lv.d_rowptr, lv.d_col, V::val(lv), x, r,
-                                     V::rloc(lv) + r0, xz, lv.lanes, h->st);
+            C::resid_rows(r1 - r0, lv.d_sw_sub_dofs + r0, lv, O::val(lv), x, r, v.rloc + r0 * NR, xz, h->st);
         });
-        const double gb = lv.color_m2[c] * w + lv.color_m[c] * (4 + 3 * w);
+        const double gb = lv.color_m2[c] * w + lv.color_m[c] * (4 + 3 * wv);
         traced(h, "sub_symv", gb, [&] {
-            launch_sub_symv<T>(i1 - i0, lv.d_items + 3 * i0, lv.d_sw_sub_off, lv.d_sw_tp_off, V::inv(lv),
-                               V::rloc(lv), lv.d_scr_off, V::scr(lv), lv.chl, h->st);
+            C::symv(i1 - i0, lv.d_items + 3 * i0, lv.d_sw_sub_off, lv.d_sw_tp_off, O::inv(lv), v.rloc, lv.d_scr_off,
+                    v.scr, lv.chl, h->st);
         });
-        launch_sub_finalize<T>(r0, r1, lv.d_pos_sub, lv.d_sw_sub_off, lv.d_scr_off, V::scr(lv), lv.d_sw_sub_dofs, x,
-                               true, lv.chl, lv.fl, h->st);
+        const double fb = lv.color_scr[c] * wv + lv.color_m[c] * (8 + 2 * wv);
+        traced(h, "sub_finalize", fb, [&] {
+            C::finalize(r0, r1, lv.d_pos_sub, lv.d_sw_sub_off, lv.d_scr_off, v.scr, lv.d_sw_sub_dofs, x, true, lv.chl,
+                        lv.fl, h->st);
+        });
     }
 }
 
-template <typename T>
+template <typename T, int NR>
 void vcycle(lsdd_hierarchy* h, size_t l, const T* r, T* x) {
-    using V = LvVec<T>;
+    using O = LvOps<T>;
+    using C = Cyc<T, NR>;
+    constexpr int b = NR > 1 ? 1 : 0;
     Level& lv = *h->L[l];
-    const double w = (double)sizeof(T);
+    const double w = (double)sizeof(T), wv = w * NR;
     if (lv.coarsest) {
-        const double nb = (double)lv.n * (lv.n + 1) / 2.0 * 8.0 + 2.0 * lv.n * 8.0;
+        using CD = Cyc<double, NR>;
+        const double nb = (double)lv.n * (lv.n + 1) / 2.0 * 8.0 + 2.0 * lv.n * 8.0 * NR;
         auto apply = [&](const double* rr, double* xx) {
             traced(h, "coarse_symv", nb, [&] {
-                launch_sub_symv<double>(lv.c_nitems, lv.c_items, lv.c_sub_off, lv.c_tp_off, lv.d_tiles, rr,
-                                        lv.c_scr_off, lv.scr64, lv.chl, h->st);
+                CD::symv(lv.c_nitems, lv.c_items, lv.c_sub_off, lv.c_tp_off, lv.d_tiles, rr, lv.c_scr_off,
+                         lv.v64[b].scr, lv.chl, h->st);
             });
-            launch_sub_finalize<double>(0, lv.n, lv.c_pos, lv.c_sub_off, lv.c_scr_off, lv.scr64, nullptr, xx, false,
-                                        lv.chl, lv.fl, h->st);
+            CD::finalize(0, lv.n, lv.c_pos, lv.c_sub_off, lv.c_scr_off, lv.v64[b].scr, nullptr, xx, false, lv.chl,
+                         lv.fl, h->st);
         };
         if constexpr (std::is_same<T, double>::value) {
             apply(r, x);
         } else {
-            launch_to_f64(lv.n, r, lv.cr64, h->st);
-            apply(lv.cr64, lv.cx64);
-            launch_to_f32(lv.n, lv.cx64, x, h->st);
+            launch_to_f64(lv.n * NR, r, lv.cr64[b], h->st);
+            apply(lv.cr64[b], lv.cx64[b]);
+            launch_to_f32(lv.n * NR, lv.cx64[b], x, h->st);
         }
         return;
     }
     Level& nx = *h->L[l + 1];
-    launch_zero<T>(lv.n, x, h->st);
-    sweep<T>(h, lv, r, x, true, true);
-    traced(h, "csr_spmv", (double)lv.nnz * (4 + w) + (double)lv.n * (8 + 3 * w), [&] {
-        launch_csr_spmv<T>(lv.n, lv.d_rowptr, lv.d_col, V::val(lv), x, V::t(lv), r, lv.lanes, h->st);
-    });
-    const double zb = (double)lv.zoff.back() * w + (double)lv.n * (4 + w) + (double)nx.n * w;
-    traced(h, "restrict", zb, [&] {
-        launch_restrict<T>(lv.n_ritems, lv.d_ritems, lv.d_agg_ptr, lv.d_agg_dofs, lv.d_zoff, lv.d_k, lv.d_coff,
-                           V::Z(lv), V::t(lv), V::r(nx), h->st);
-    });
-    vcycle<T>(h, l + 1, V::r(nx), V::x(nx));
-    traced(h, "prolong", zb + (double)lv.n * w, [&] {
-        launch_prolong<T>(lv.n_pitems, lv.d_pitems, lv.d_agg_ptr, lv.d_agg_dofs, lv.d_zoff, lv.d_k, lv.d_coff,
-                          V::Z(lv), V::x(nx), x, h->st);
-    });
-    sweep<T>(h, lv, r, x, false, false);
+    VecSet<T>& v = O::v(lv, b);
+    VecSet<T>& vn = O::v(nx, b);
+    launch_zero<T>(lv.n * NR, x, h->st);
+    sweep<T, NR>(h, lv, r, x, true, true);
+    traced(h, "csr_spmv", (double)lv.nnz * (4 + w) + (double)lv.n * (8 + 3 * wv),
+           [&] { C::spmv(lv, O::val(lv), x, v.t, r, h->st); });
+    const double zb = (double)lv.zoff.back() * w + (double)lv.n * (4 + wv) + (double)nx.n * wv;
+    traced(h, "restrict", zb, [&] { C::restrict_(lv, O::Z(lv), v.t, vn.r, h->st); });
+    vcycle<T, NR>(h, l + 1, vn.r, vn.x);
+    traced(h, "prolong", zb + (double)lv.n * wv, [&] { C::prolong(lv, O::Z(lv), vn.x, x, h->st); });
+    sweep<T, NR>(h, lv, r, x, false, false);
 }
 
+// block vectors of every level, on first use
+void ensure_block_vectors(lsdd_hierarchy* h) {
+    for (auto& lp : h->L)
+        if (!lp->v64[1].r) alloc_vectors(h, *lp, 1);
+}
+
+template <int NR>
 void precond(lsdd_hierarchy* h, const double* r, double* z) {
     Level& l0 = *h->L[0];
+    constexpr int b = NR > 1 ? 1 : 0;
     if (h->cycle_prec == 1) {
-        launch_to_f32(l0.n, r, l0.r32, h->st);
-        vcycle<float>(h, 0, l0.r32, l0.x32);
-        launch_to_f64(l0.n, l0.x32, z, h->st);
+        launch_to_f32(l0.n * NR, r, l0.v32[b].r, h->st);
+        vcycle<float, NR>(h, 0, l0.v32[b].r, l0.v32[b].x);
+        launch_to_f64(l0.n * NR, l0.v32[b].x, z, h->st);
     } else {
-        vcycle<double>(h, 0, r, z);
+        vcycle<double, NR>(h, 0, r, z);
     }
+}
+
+// ---------------------------------------------------------------- PCG
+
+void alloc_pcg(lsdd_hierarchy* h, int b) {
+    Arena& a = h->arena;
+    const int64_t len = h->L[0]->n * (b ? NRB : 1);
+    auto& B = h->pb[b];
+    B.B = a.alloc<double>(len);
+    B.X = a.alloc<double>(len);
+    B.r = a.alloc<double>(len);
+    B.p = a.alloc<double>(len);
+    B.q = a.alloc<double>(len);
+    B.z = a.alloc<double>(len);
+    B.rold = a.alloc<double>(len);
+}
+
+// Segment table: DOF ranges [seg_off[s], seg_off[s+1]) cut into reduction
+// blocks of at most 2048 DOFs.
+void init_segments(lsdd_hierarchy* h, const std::vector<int64_t>& seg_off) {
+    Arena& a = h->arena;
+    const int32_t ns = (int32_t)seg_off.size() - 1;
+    constexpr int64_t CH = 2048;
+    std::vector<int32_t> bseg, sblk(1, 0);
+    std::vector<int64_t> blo, bhi;
+    for (int32_t s = 0; s < ns; ++s) {
+        if (seg_off[s + 1] <= seg_off[s]) throw Error(LSDD_E_INVAL, "empty segment");
+        for (int64_t d = seg_off[s]; d < seg_off[s + 1]; d += CH) {
+            bseg.push_back(s);
+            blo.push_back(d);
+            bhi.push_back(std::min(d + CH, seg_off[s + 1]));
+        }
+        sblk.push_back((int32_t)bseg.size());
+    }
+    h->seg_off = seg_off;
+    h->seg.n_seg = ns;
+    h->seg.n_blk = (int32_t)bseg.size();
+    h->seg.blk_seg = a.upload(bseg, h->st);
+    h->seg.blk_lo = a.upload(blo, h->st);
+    h->seg.blk_hi = a.upload(bhi, h->st);
+    h->seg.seg_blk = a.upload(sblk, h->st);
+    h->nsm = ns * NRB;
+    h->sc = a.alloc<double>((size_t)9 * h->nsm);
+    h->ic = a.alloc<int32_t>((size_t)2 * h->nsm + 4);
+    h->part = a.alloc<double>((size_t)2 * h->seg.n_blk * NRB);
+    if (!h->h_ic) HIPCHK(hipHostMalloc((void**)&h->h_ic, 4 * sizeof(int32_t), hipHostMallocDefault));
+}
+
+void reset_graphs(lsdd_hierarchy* h) {
+    for (auto& a : h->gx)
+        for (auto& b : a)
+            for (auto& g : b)
+                if (g) {
+                    (void)hipGraphExecDestroy(g);
+                    g = nullptr;
+                }
+}
+
+// PCG (x0 = 0) on the NR right-hand sides in pb[b].B, one recurrence per
+// (segment, right-hand side) pair, preconditioned by one V-cycle; the solution
+// is left in pb[b].X.  Returns true on breakdown.  Every scalar stays on the
+// device; the host reads the active count once per iteration.
+template <int NR>
+bool pcg_run(lsdd_hierarchy* h) {
+    constexpr int b = NR > 1 ? 1 : 0;
+    auto& B = h->pb[b];
+    hipStream_t st = h->st;
+    Level& l0 = *h->L[0];
+    const int64_t n = l0.n;
+    const SegTable& T = h->seg;
+    const int ns = T.n_seg * NR, nsm = h->nsm;
+    double *bb = h->sc, *rz = bb + nsm, *pq = rz + nsm, *rr = pq + nsm, *rzn = rr + nsm, *rzo = rzn + nsm,
+           *alpha = rzo + nsm, *beta = alpha + nsm, *relres = beta + nsm;
+    int32_t *act = h->ic, *iters = act + nsm, *cnt = iters + nsm, *itf = cnt + 1;   // itf[0] it, itf[1] flag
+    const bool flex = h->cycle_prec == 1;
+    const double tol2 = h->prm.rtol * h->prm.rtol;
+    launch_seg_dot(T, NR, B.B, B.B, nullptr, nullptr, h->part, bb, nullptr, st);
+    launch_pcg_init(ns, bb, act, iters, relres, itf, st);
+    launch_pcg_start(n * NR, B.B, B.r, B.X, st);
+    precond<NR>(h, B.r, B.z);
+    launch_copy(n * NR, B.z, B.p, st);
+    launch_seg_dot(T, NR, B.r, B.z, nullptr, nullptr, h->part, rz, nullptr, st);
+    auto half_a = [&] {
+        traced(h, "pcg_spmv", (double)l0.nnz * 12.0 + (double)n * 8.0 * (1 + 2 * NR),
+               [&] { Cyc<double, NR>::spmv(l0, l0.d_val, B.p, B.q, nullptr, st); });
+        launch_seg_dot(T, NR, B.p, B.q, nullptr, nullptr, h->part, pq, nullptr, st);
+        launch_pcg_alpha(ns, act, rz, pq, alpha, itf + 1, st);
+        if (flex) launch_copy(n * NR, B.r, B.rold, st);
+        launch_pcg_update_xr(T, NR, act, alpha, B.p, B.q, B.X, B.r, h->part, rr, st);
+        launch_pcg_check(ns, itf, tol2, bb, rr, act, iters, relres, cnt, itf + 1, st);
+    };
+    auto half_b = [&] {
+        precond<NR>(h, B.r, B.z);
+        launch_seg_dot(T, NR, B.r, B.z, flex ? B.rold : nullptr, flex ? B.z : nullptr, h->part, rzn, rzo, st);
+        launch_pcg_beta(ns, act, rzn, flex ? rzo : nullptr, rz, beta, itf + 1, st);
+        launch_pcg_update_p(T, NR, act, beta, B.z, B.p, st);
+    };
+    auto run = [&](int half, auto&& fn) {
+        if (!h->use_graph || h->tr.on || !st) {
+            fn();
+            return;
+        }
+        hipGraphExec_t& g = h->gx[b][h->cycle_prec][half];
+        if (!g) {
+            hipGraph_t gr;
+            HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+            fn();
+            HIPCHK(hipStreamEndCapture(st, &gr));
+            HIPCHK(hipGraphInstantiate(&g, gr, nullptr, nullptr, 0));
+            HIPCHK(hipGraphDestroy(gr));
+        }
+        HIPCHK(hipGraphLaunch(g, st));
+    };
+    bool breakdown = false;
+    for (int it = 1; it <= h->prm.max_iter; ++it) {
+        run(0, half_a);
+        HIPCHK(hipMemcpyAsync(h->h_ic, cnt, 3 * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+        sync(st);
+        if (h->tr.on) h->tr.flush();
+        if (h->h_ic[2]) {
+            breakdown = true;
+            break;
+        }
+        if (h->h_ic[0] == 0) break;
+        run(1, half_b);
+    }
+    HIPCHK(hipGetLastError());
+    return breakdown;
 }
 
 // ---------------------------------------------------------------- setup driver
@@ -1058,17 +1259,8 @@ lsdd_hierarchy* build(ElemList el0, const double* blocks, bool blocks_on_device,
         }
         h->L.push_back(std::move(nxt));
     }
-    // PCG work vectors
-    const int64_t n0 = h->L[0]->n;
-    h->p = ar.alloc<double>(n0);
-    h->q = ar.alloc<double>(n0);
-    h->z = ar.alloc<double>(n0);
-    h->r = ar.alloc<double>(n0);
-    h->rold = ar.alloc<double>(n0);
-    h->scal = ar.alloc<double>(16);
-    h->partials = ar.alloc<double>(1024);
-    h->d_flag = ar.alloc<int32_t>(1);
-    HIPCHK(hipHostMalloc((void**)&h->h_scal, 16 * sizeof(double), hipHostMallocDefault));
+    init_segments(h.get(), {0, h->L[0]->n});
+    alloc_pcg(h.get(), 0);
     sync(h->st);
     h->setup_s = now_s() - t0;
     h->cycle_prec = P.precision;
@@ -1213,9 +1405,10 @@ lsdd_status lsdd_destroy(lsdd_hierarchy* h) {
     if (!h) return LSDD_OK;
     if (h->st) (void)hipStreamSynchronize(h->st);
     else (void)hipDeviceSynchronize();
+    reset_graphs(h);
     h->tr.destroy();
     h->arena.clear();
-    if (h->h_scal) (void)hipHostFree(h->h_scal);
+    if (h->h_ic) (void)hipHostFree(h->h_ic);
     delete h;
     return LSDD_OK;
     ABI_END
@@ -1225,7 +1418,7 @@ lsdd_status lsdd_vcycle(lsdd_hierarchy* h, const double* r, double* z, void* hip
     ABI_BEGIN
     if (!h || !r || !z) throw Error(LSDD_E_INVAL, "NULL argument");
     h->st = (hipStream_t)hip_stream;
-    precond(h, r, z);
+    precond<1>(h, r, z);
     HIPCHK(hipGetLastError());
     sync(h->st);
     return LSDD_OK;
@@ -1249,88 +1442,62 @@ lsdd_status lsdd_solve(lsdd_hierarchy* h, const double* b, double* x, int32_t nr
     if (!h || !b || !x || nrhs < 1) throw Error(LSDD_E_INVAL, "bad argument");
     h->st = (hipStream_t)hip_stream;
     hipStream_t st = h->st;
-    Level& l0 = *h->L[0];
-    const int64_t n = l0.n;
-    const bool flex = h->cycle_prec == 1;
-    double* S = h->scal;   // [0] rz [1] pq [2] rr [3] bb [4] zr_new [5] z.(r - rold)
-    lsdd_status worst = LSDD_OK;
-    for (int32_t k = 0; k < nrhs; ++k) {
-        double t0 = now_s();
-        const double* bk = b + (int64_t)k * n;
-        double* xk = x + (int64_t)k * n;
-        HIPCHK(hipMemsetAsync(h->d_flag, 0, sizeof(int32_t), st));
-        launch_check_finite(n, bk, h->d_flag, st);
-        int32_t bad = download(h->d_flag, 1, st)[0];
-        if (bad) throw Error(LSDD_E_INVAL, "right-hand side " + std::to_string(k) + " has NaN/Inf");
-        launch_dot(n, bk, bk, h->partials, S + 3, st);
-        HIPCHK(hipMemcpyAsync(h->h_scal, S + 3, sizeof(double), hipMemcpyDeviceToHost, st));
-        sync(st);
-        const double bn = std::sqrt(h->h_scal[0]);
-        launch_zero<double>(n, xk, st);
-        lsdd_info inf{0, 1, 0.0, h->setup_s, 0.0};
-        if (bn == 0.0) {
-            sync(st);
-            inf.solve_s = now_s() - t0;
-            if (info) info[k] = inf;
-            continue;
+    const int64_t n = h->L[0]->n;
+    const int32_t nseg = h->seg.n_seg;
+    const double t0 = now_s();
+    int32_t* fin = h->ic + 2 * h->nsm + 3;
+    HIPCHK(hipMemsetAsync(fin, 0, sizeof(int32_t), st));
+    launch_check_finite(n * nrhs, b, fin, st);
+    if (download(fin, 1, st)[0]) throw Error(LSDD_E_INVAL, "right-hand side has NaN/Inf");
+    std::vector<lsdd_info> out((size_t)nrhs * nseg);
+    bool breakdown = false;
+    auto collect = [&](int32_t k0, int32_t nr, int NR) {
+        std::vector<int32_t> it = download(h->ic + h->nsm, (size_t)nseg * NR, st);
+        std::vector<int32_t> act = download(h->ic, (size_t)nseg * NR, st);
+        std::vector<double> rel = download(h->sc + 8 * (size_t)h->nsm, (size_t)nseg * NR, st);
+        for (int32_t k = 0; k < nr; ++k)
+            for (int32_t sg = 0; sg < nseg; ++sg) {
+                const size_t i = (size_t)sg * NR + k;
+                lsdd_info& f = out[(size_t)(k0 + k) * nseg + sg];
+                f.iters = it[i];
+                f.rel_res = rel[i];
+                f.converged = (!act[i] && rel[i] <= h->prm.rtol) ? 1 : 0;
+                f.setup_s = h->setup_s;
+            }
+    };
+    if (nrhs == 1) {
+        launch_copy(n, b, h->pb[0].B, st);
+        breakdown = pcg_run<1>(h);
+        launch_copy(n, h->pb[0].X, x, st);
+        collect(0, 1, 1);
+    } else {
+        if (!h->pb[1].B) {
+            ensure_block_vectors(h);
+            alloc_pcg(h, 1);
         }
-        launch_copy(n, bk, h->r, st);
-        precond(h, h->r, h->z);
-        launch_copy(n, h->z, h->p, st);
-        launch_dot(n, h->r, h->z, h->partials, S + 0, st);
-        lsdd_status stat = LSDD_E_NOCONV;
-        double rel = 1.0;
-        int it = 0;
-        for (it = 1; it <= h->prm.max_iter; ++it) {
-            traced(h, "pcg_spmv", (double)l0.nnz * 12.0 + (double)n * 24.0, [&] {
-                launch_csr_spmv<double>(n, l0.d_rowptr, l0.d_col, l0.d_val, h->p, h->q, nullptr, l0.lanes, st);
-            });
-            launch_dot(n, h->p, h->q, h->partials, S + 1, st);
-            if (flex) launch_copy(n, h->r, h->rold, st);
-            launch_update_xr(n, S + 0, S + 1, h->p, h->q, xk, h->r, h->partials, S + 2, st);
-            HIPCHK(hipMemcpyAsync(h->h_scal, S, 3 * sizeof(double), hipMemcpyDeviceToHost, st));
-            sync(st);
-            if (h->tr.on) h->tr.flush();
-            const double pq = h->h_scal[1], rr = h->h_scal[2];
-            if (!(pq > 0.0) || !std::isfinite(rr)) {
-                stat = LSDD_E_BREAKDOWN;
-                break;
-            }
-            rel = std::sqrt(rr) / bn;
-            if (rel <= h->prm.rtol) {
-                stat = LSDD_OK;
-                break;
-            }
-            precond(h, h->r, h->z);
-            launch_dot(n, h->r, h->z, h->partials, S + 4, st);
-            if (flex) {
-                launch_dot(n, h->rold, h->z, h->partials, S + 6, st);
-                // S[5] = S[4] - S[6] computed on the host side of the stream: use a tiny copy path
-                HIPCHK(hipMemcpyAsync(h->h_scal + 4, S + 4, 3 * sizeof(double), hipMemcpyDeviceToHost, st));
-                sync(st);
-                h->h_scal[5] = h->h_scal[4] - h->h_scal[6];
-                HIPCHK(hipMemcpyAsync(S + 5, h->h_scal + 5, sizeof(double), hipMemcpyHostToDevice, st));
-                launch_update_p(n, S + 5, S + 0, h->z, h->p, st);
-            } else {
-                launch_update_p(n, S + 4, S + 0, h->z, h->p, st);
-            }
-            launch_copy(1, S + 4, S + 0, st);
-        }
-        HIPCHK(hipGetLastError());
-        sync(st);
-        if (h->tr.on) h->tr.flush();
-        inf.iters = std::min(it, h->prm.max_iter);
-        inf.converged = stat == LSDD_OK;
-        inf.rel_res = rel;
-        inf.solve_s = now_s() - t0;
-        if (info) info[k] = inf;
-        if (stat == LSDD_E_BREAKDOWN) throw Error(LSDD_E_BREAKDOWN, "PCG breakdown (p^T A p <= 0 or non-finite)");
-        if (stat != LSDD_OK && worst == LSDD_OK) {
-            worst = stat;
-            g_err = "PCG did not reach rtol within max_iter";
+        for (int32_t k0 = 0; k0 < nrhs && !breakdown; k0 += NRB) {
+            const int32_t nr = std::min<int32_t>(NRB, nrhs - k0);
+            launch_gather_rhs(n, nr, b + (int64_t)k0 * n, n, h->pb[1].B, st);
+            breakdown = pcg_run<NRB>(h);
+            launch_scatter_sol(n, nr, h->pb[1].X, x + (int64_t)k0 * n, n, st);
+            collect(k0, nr, NRB);
         }
     }
-    return worst;
+    HIPCHK(hipGetLastError());
+    sync(st);
+    const double ts = now_s() - t0;
+    bool allconv = true;
+    for (auto& f : out) {
+        f.solve_s = ts;
+        allconv = allconv && f.converged;
+    }
+    if (info) std::copy(out.begin(), out.end(), info);
+    if (breakdown) throw Error(LSDD_E_BREAKDOWN, "PCG breakdown (p^T A p <= 0 or non-finite)");
+    if (!allconv) {
+        g_err = "PCG did not reach rtol within max_iter";
+        return LSDD_E_NOCONV;
+    }
+    return LSDD_OK;
     ABI_END
 }
 
@@ -1349,6 +1516,26 @@ lsdd_status lsdd_set_solve_params(lsdd_hierarchy* h, double rtol, int32_t max_it
     if (!h || !(rtol > 0.0) || max_iter < 1) throw Error(LSDD_E_INVAL, "bad argument");
     h->prm.rtol = rtol;
     h->prm.max_iter = max_iter;
+    reset_graphs(h);
+    return LSDD_OK;
+    ABI_END
+}
+
+lsdd_status lsdd_set_graph(lsdd_hierarchy* h, int32_t on) {
+    ABI_BEGIN
+    if (!h) throw Error(LSDD_E_INVAL, "NULL hierarchy");
+    if (h->st) HIPCHK(hipStreamSynchronize(h->st));
+    h->use_graph = on != 0;
+    reset_graphs(h);
+    return LSDD_OK;
+    ABI_END
+}
+
+lsdd_status lsdd_segments(const lsdd_hierarchy* h, int32_t* n_seg, int64_t* seg_off) {
+    ABI_BEGIN
+    if (!h) throw Error(LSDD_E_INVAL, "NULL hierarchy");
+    if (n_seg) *n_seg = h->seg.n_seg;
+    if (seg_off) std::copy(h->seg_off.begin(), h->seg_off.end(), seg_off);
     return LSDD_OK;
     ABI_END
 }

@@ -80,6 +80,8 @@ def lib():
         L.lsdd_set_solve_params.argtypes = [_P, C.c_double, C.c_int32]
         L.lsdd_trace_get.argtypes = [_P, C.c_int32, C.c_char_p, C.c_int32, i64p, f64p, f64p]
         L.lsdd_set_allocator.argtypes = [_P, _P, _P]
+        L.lsdd_set_graph.argtypes = [_P, C.c_int32]
+        L.lsdd_segments.argtypes = [_P, i32p, i64p]
         L.lsdd_set_allocator.restype = None
         for name in ("lsdd_setup_elements", "lsdd_setup_gram_csr", "lsdd_solve", "lsdd_vcycle", "lsdd_apply",
                      "lsdd_hierarchy_info", "lsdd_level_sizes", "lsdd_export_level", "lsdd_export_gram",
@@ -167,15 +169,28 @@ class Hierarchy:
 
     # ---------------------------------------------------------------- solve
     def solve(self, b, x=None, allow_noconv=False):
-        """lsdd_solve for b of shape [n] or [nrhs, n]; returns (x, [Info])."""
+        """lsdd_solve for b of shape [n] or [nrhs, n]; returns (x, [Info]) with one
+        Info per (right-hand side, segment), right-hand side major."""
         import torch
         nrhs = 1 if b.dim() == 1 else b.shape[0]
         if x is None:
             x = torch.empty_like(b)
-        infos = (Info * nrhs)()
+        nseg = self.segments()[0]
+        infos = (Info * (nrhs * nseg))()
         _check(lib().lsdd_solve(self._h, _dev_ptr(b), _dev_ptr(x), nrhs, _stream(), infos),
                allow=(5,) if allow_noconv else ())
-        return x, [infos[i] for i in range(nrhs)]
+        return x, [infos[i] for i in range(nrhs * nseg)]
+
+    def set_graph(self, on: bool):
+        _check(lib().lsdd_set_graph(self._h, 1 if on else 0))
+
+    def segments(self):
+        """(n_seg, seg_off as a list)."""
+        ns = C.c_int32()
+        _check(lib().lsdd_segments(self._h, C.byref(ns), None))
+        off = np.zeros(ns.value + 1, dtype=np.int64)
+        _check(lib().lsdd_segments(self._h, None, off.ctypes.data_as(C.POINTER(C.c_int64))))
+        return ns.value, off.tolist()
 
     def vcycle(self, r, z=None):
         import torch

@@ -1,0 +1,105 @@
+"""GPU parity of the batched paths (blocks of right-hand sides, captured PCG
+iterations) against the FP64 oracle.
+
+Each (instance, right-hand side) pair runs its own CG recurrence, so every
+column is held to the single-solve bar: 1e-10 relative to the oracle's PCG
+iterate, iterations +-1; zero columns give x = 0 after no iteration.  HIP-graph
+replays must reproduce the eagerly launched solve bit for bit.
+"""
+import numpy as np
+import pytest
+import scipy.sparse.linalg as spla
+
+import fegen
+import oracle
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+ELAST_KW = dict(max_levels=2, modes_fixed=4)
+GD_KW = dict(max_levels=3, tau_const=0.75, max_density=1.0, agg_passes=1, agg_passes_coarse=1)
+
+
+def _lsdd():
+    import paper_2607_07485_amd as P
+    return P
+
+
+@pytest.fixture(scope="module")
+def dev():
+    assert torch.cuda.is_available(), "GPU tests need a device"
+    return torch.device("cuda:0")
+
+
+def _graddiv(N=10, seed=0):
+    rng = np.random.default_rng(seed)
+    return fegen.graddiv_rtcf3(N, kappa=np.exp(rng.standard_normal(N * N)), beta=1.0), rng
+
+
+@pytest.mark.parametrize("nrhs", [3, 9])
+def test_block_rhs_match_oracle(dev, nrhs):
+    """nrhs = 9 runs one full block of 8 and a ragged block of 1."""
+    P = _lsdd()
+    prob, rng = _graddiv()
+    B = rng.standard_normal((nrhs, prob.n))
+    B[1] = 0.0
+    h_or = oracle.setup(prob, oracle.Params(**GD_KW))
+    with P.Hierarchy.setup_problem(prob, P.Params.default(**GD_KW)) as h:
+        X, infos = h.solve(torch.from_numpy(B).to(dev))
+        X = X.cpu().numpy()
+        assert len(infos) == nrhs
+        for k in range(nrhs):
+            if k == 1:
+                assert infos[k].iters == 0 and infos[k].converged == 1 and np.all(X[k] == 0.0)
+                continue
+            x_or, inf_or = oracle.pcg(h_or, B[k])
+            assert infos[k].converged == 1
+            assert abs(infos[k].iters - inf_or.iters) <= 1
+            assert np.linalg.norm(X[k] - x_or) <= 1e-10 * np.linalg.norm(x_or)
+            x1, inf1 = h.solve(torch.from_numpy(B[k]).to(dev))     # the same column alone
+            assert inf1[0].iters == infos[k].iters
+            assert np.linalg.norm(X[k] - x1.cpu().numpy()) <= 1e-10 * np.linalg.norm(x_or)
+
+
+def test_block_fp32_cycle_anorm(dev):
+    """FP32 block cycle inside FP64 PCG (flexible beta): A-norm error <= 1e-8 per column."""
+    P = _lsdd()
+    prob, _ = fegen.elasticity_small(N=16)
+    rng = np.random.default_rng(3)
+    B = rng.standard_normal((3, prob.n))
+    A = oracle.assemble(prob.n, *[[prob.element(e)[i] for e in range(prob.n_elem)] for i in (0, 1)]).tocsc()
+    with P.Hierarchy.setup_problem(prob, P.Params.default(precision=1, rtol=1e-10, **ELAST_KW)) as h:
+        X, infos = h.solve(torch.from_numpy(B).to(dev))
+        X = X.cpu().numpy()
+        for k in range(3):
+            x_ref = spla.spsolve(A, B[k])
+            e = X[k] - x_ref
+            anorm = np.sqrt(e @ (A @ e)) / np.sqrt(x_ref @ (A @ x_ref))
+            assert infos[k].converged == 1 and anorm <= 1e-8
+
+
+def test_graph_replays_match_eager(dev):
+    """Captured PCG halves replayed over several solves, with eager work in
+    between, give the eager result bit for bit (single vectors and blocks)."""
+    P = _lsdd()
+    prob, rng = _graddiv(seed=5)
+    b1 = torch.from_numpy(rng.standard_normal(prob.n)).to(dev)
+    B3 = torch.from_numpy(rng.standard_normal((3, prob.n))).to(dev)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s), P.Hierarchy.setup_problem(prob, P.Params.default(**GD_KW)) as h:
+        x_e, inf_e = h.solve(b1)
+        X_e, infs_e = h.solve(B3)
+        h.set_graph(True)
+        for rep in range(3):
+            junk = torch.randn(4096, device=dev, dtype=torch.float64)
+            junk.mul_(2.0).sum().item()                 # eager work between replays
+            x_g, inf_g = h.solve(b1)
+            X_g, infs_g = h.solve(B3)
+            torch.cuda.synchronize()
+            assert torch.equal(x_g, x_e), f"replay {rep}"
+            assert torch.equal(X_g, X_e), f"replay {rep}"
+            assert inf_g[0].iters == inf_e[0].iters
+            assert [i.iters for i in infs_g] == [i.iters for i in infs_e]
+        h.set_graph(False)
+        x_2, _ = h.solve(b1)
+        assert torch.equal(x_2, x_e)
