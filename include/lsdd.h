@@ -104,6 +104,34 @@ lsdd_status lsdd_setup_elements(int64_t n, int64_t n_elem, const int64_t* elem_p
                                 int mem_is_device, const lsdd_params* params, void* hip_stream,
                                 lsdd_hierarchy** out);
 
+/* Build ONE hierarchy for a batch of independent problems: the method applied
+ * to their block-diagonal union (Sec. 2: aggregates, overlaps, colours and coarse
+ * spaces of different instances never meet, so the union's hierarchy restricted
+ * to an instance is that instance's own hierarchy).  Every setup and cycle kernel
+ * then runs over all instances at once; lsdd_solve runs one CG recurrence per
+ * (instance, right-hand side) pair.
+ *   n_inst       number of instances (>= 1)
+ *   inst_n       host, int64[n_inst]: DOFs of instance i (>= 1)
+ *   inst_n_elem  host, int64[n_inst]: elements of instance i (>= 1); the element
+ *                arrays list the elements of instance 0 first, then instance 1, ...
+ *   elem_ptr     host, int64[sum inst_n_elem + 1], elem_ptr[0] = 0
+ *   elem_dofs    host, int32: instance-local DOF indices (0 .. inst_n[i]-1)
+ *   elem_blocks  host or device (mem_is_device), float64 blocks as in lsdd_setup_elements
+ *   node_of_dof  host, int32[sum inst_n] or NULL: instance-local supernode ids, instances
+ *                concatenated (each instance uses 0..count-1)
+ *   agg_of_dof   host, int32[sum inst_n] or NULL: instance-local level-0 aggregates, concatenated
+ * DOF j of instance i is DOF inst_off[i] + j of the union (inst_off = prefix sums of
+ * inst_n), which is also the layout of b and x in lsdd_solve; lsdd_segments returns
+ * inst_off.  Per instance: tau_cut uses the instance's own largest multiplicity and the
+ * stopping tests (min_coarse, max_density, no retained mode) are applied to the
+ * instance's own level; instances that would reach their coarsest level at different
+ * depths -> LSDD_E_UNSUPPORTED.  The coarsest level is solved with one dense inverse
+ * per instance. */
+lsdd_status lsdd_setup_batched(int32_t n_inst, const int64_t* inst_n, const int64_t* inst_n_elem,
+                               const int64_t* elem_ptr, const int32_t* elem_dofs, const double* elem_blocks,
+                               const int32_t* node_of_dof, const int32_t* agg_of_dof, int mem_is_device,
+                               const lsdd_params* params, void* hip_stream, lsdd_hierarchy** out);
+
 /* Build a hierarchy from a black-box sparse Gram factor G (m x n, CSR, host),
  * the input of Sec. 2 (A = G^T G, m >= n, full column rank).  Each row of G is
  * its own cover member: row j contributes g_j g_j^T with support = its stored

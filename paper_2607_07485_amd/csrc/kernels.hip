@@ -245,7 +245,8 @@ __global__ void __launch_bounds__(WG) k_local_eig(LocalArgs A) {
             k = A.modes_fixed < nw ? A.modes_fixed : nw;
         } else {
             k = 0;
-            while (k < nw && mu[k] < A.thr + A.band_tol) ++k;
+            const double thr = A.thr_agg ? A.thr_agg[ag] : A.thr;
+            while (k < nw && mu[k] < thr + A.band_tol) ++k;
         }
         while (k > 0 && k < nw && mu[k] - mu[k - 1] <= A.cluster_tol) ++k;
         s_k = k;
@@ -402,10 +403,14 @@ __global__ void __launch_bounds__(WG) k_galerkin(GalerkinArgs g) {
 
 // ====================================================================== coarsest level
 
-__global__ void k_dense_from_csr(int64_t n, const int64_t* rowptr, const int32_t* col, const double* val,
-                                 double* D) {
-    int64_t p = blockIdx.x;
-    for (int64_t q = rowptr[p] + tid(); q < rowptr[p + 1]; q += WG) D[p + (int64_t)col[q] * n] = val[q];
+// D (n x n, column-major) = A[off:off+n, off:off+n]; entries outside the block are skipped
+__global__ void k_dense_from_csr(int64_t off, int64_t n, const int64_t* rowptr, const int32_t* col,
+                                 const double* val, double* D) {
+    const int64_t p = blockIdx.x;
+    for (int64_t q = rowptr[off + p] + tid(); q < rowptr[off + p + 1]; q += WG) {
+        const int64_t c = (int64_t)col[q] - off;
+        if (c >= 0 && c < n) D[p + c * n] = val[q];
+    }
 }
 
 // Single-workgroup Cholesky and explicit inverse of a dense SPD matrix.
@@ -976,9 +981,9 @@ void launch_galerkin(const GalerkinArgs& g, hipStream_t st) {
     hipLaunchKernelGGL(k_galerkin, dim3(g.n_groups), dim3(WG), 0, st, g);
 }
 
-void launch_dense_from_csr(int64_t n, const int64_t* rowptr, const int32_t* col, const double* val, double* D,
+void launch_dense_from_csr(int64_t off, int64_t n, const int64_t* rowptr, const int32_t* col, const double* val, double* D,
                            hipStream_t st) {
-    hipLaunchKernelGGL(k_dense_from_csr, dim3((unsigned)n), dim3(WG), 0, st, n, rowptr, col, val, D);
+    hipLaunchKernelGGL(k_dense_from_csr, dim3((unsigned)n), dim3(WG), 0, st, off, n, rowptr, col, val, D);
 }
 
 void launch_dense_chol_inv(int64_t n, double* W, double* inv, int32_t* status, hipStream_t st) {

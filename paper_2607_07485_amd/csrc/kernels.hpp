@@ -50,6 +50,7 @@ struct LocalArgs {
     // parameters
     int32_t modes_fixed;
     double thr;                    // 1 / tau_cut
+    const double* thr_agg;         // optional per-aggregate 1 / tau_cut (batched instances)
     double band_tol, cluster_tol;
 };
 
@@ -95,8 +96,9 @@ struct GalerkinArgs {
 };
 void launch_galerkin(const GalerkinArgs& g, hipStream_t st);
 
-void launch_dense_from_csr(int64_t n, const int64_t* rowptr, const int32_t* col, const double* val, double* D,
-                           hipStream_t st);
+// D = A[off:off+n, off:off+n] (column-major n x n; D must be zeroed first)
+void launch_dense_from_csr(int64_t off, int64_t n, const int64_t* rowptr, const int32_t* col, const double* val,
+                           double* D, hipStream_t st);
 void launch_dense_chol_inv(int64_t n, double* W, double* inv, int32_t* status, hipStream_t st);
 
 void launch_to_f32(int64_t n, const double* a, float* b, hipStream_t st);

@@ -135,6 +135,7 @@ struct Level {
     int32_t level = 0;
     int64_t n = 0;
     int64_t nnz = 0;
+    std::vector<int64_t> inst_off;     // DOF range of every problem instance (contiguous)
     ElemList el;
     std::vector<int64_t> blk_off;
     int64_t* d_elem_ptr = nullptr;
@@ -396,47 +397,69 @@ void append_symv_items(const std::vector<int64_t>& sub_off, const std::vector<in
     for (size_t q : ord) items.insert(items.end(), {it[3 * q], it[3 * q + 1], it[3 * q + 2]});
 }
 
+// Coarsest level: the dense Cholesky factorisation and explicit inverse of every
+// instance block of A_l (one block for a single problem), packed into lower
+// 64 x 64 tiles and applied by the symmetric subdomain kernel with one
+// "subdomain" per instance.
 void make_coarsest(lsdd_hierarchy* h, Level& lv) {
     lv.coarsest = true;
-    if (lv.n > 32768) throw Error(LSDD_E_UNSUPPORTED, "coarsest level too large: " + std::to_string(lv.n));
-    double* W = h->arena.alloc<double>((size_t)lv.n * lv.n);
-    HIPCHK(hipMemsetAsync(W, 0, (size_t)lv.n * lv.n * sizeof(double), h->st));
-    launch_dense_from_csr(lv.n, lv.d_rowptr, lv.d_col, lv.d_val, W, h->st);
-    lv.d_cinv = h->arena.alloc<double>((size_t)lv.n * lv.n);
-    int32_t* st = h->arena.alloc<int32_t>(1);
-    double t0 = now_s();
-    launch_dense_chol_inv(lv.n, W, lv.d_cinv, st, h->st);
-    int32_t hs = download(st, 1, h->st)[0];
-    vlog("coarsest level: n=%lld dense Cholesky + inverse %.3f s", (long long)lv.n, now_s() - t0);
-    h->arena.release(W);
-    if (hs != 0) throw Error(LSDD_E_NUMERIC, "coarsest-level Cholesky failed (matrix not SPD)");
-    {
-        // packed lower tiles of the coarsest inverse, applied by the subdomain kernel
-        Arena& ar = h->arena;
-        const int64_t nt = (lv.n + 63) / 64;
-        lv.fl = 32;
-        std::vector<int64_t> sub_off = {0, lv.n}, tp_off = {0}, scr_off = {0, sub_symv_scratch_len(lv.n, lv.chl)};
-        lv.c_sub_off = ar.upload(sub_off, h->st);
-        lv.c_tp_off = ar.upload(tp_off, h->st);
-        lv.c_scr_off = ar.upload(scr_off, h->st);
-        lv.c_pos = ar.alloc<int32_t>(lv.n);
-        HIPCHK(hipMemsetAsync(lv.c_pos, 0, lv.n * sizeof(int32_t), h->st));
-        std::vector<int32_t> items;
-        append_symv_items(sub_off, {0}, lv.chl, items);
-        lv.c_items = ar.upload(items, h->st);
-        lv.c_nitems = (int64_t)items.size() / 3;
-        lv.tiles_len = nt * (nt + 1) / 2 * 4096;
-        lv.d_tiles = ar.alloc<double>(lv.tiles_len);
-        std::vector<int64_t> inv_off = {0};
-        int64_t* d_inv_off = ar.upload(inv_off, h->st);
-        launch_pack_tiles(1, lv.c_sub_off, d_inv_off, lv.d_cinv, lv.c_tp_off, lv.d_tiles, nullptr, h->st);
-        HIPCHK(hipGetLastError());
-        sync(h->st);
-        ar.release(d_inv_off);
-        ar.release(lv.d_cinv);
-        lv.d_cinv = nullptr;
-        lv.scr_len = scr_off[1];
+    Arena& ar = h->arena;
+    const int32_t n_inst = (int32_t)lv.inst_off.size() - 1;
+    int64_t max_ni = 0;
+    std::vector<int64_t> inv_off(n_inst + 1, 0), tp_off(n_inst), scr_off(n_inst + 1, 0);
+    int64_t tiles = 0;
+    for (int32_t i = 0; i < n_inst; ++i) {
+        const int64_t ni = lv.inst_off[i + 1] - lv.inst_off[i];
+        max_ni = std::max(max_ni, ni);
+        inv_off[i + 1] = inv_off[i] + ni * ni;
+        tp_off[i] = tiles;
+        const int64_t nt = (ni + 63) / 64;
+        tiles += nt * (nt + 1) / 2 * 4096;
+        scr_off[i + 1] = scr_off[i] + sub_symv_scratch_len(ni, lv.chl);
     }
+    if (max_ni > 32768) throw Error(LSDD_E_UNSUPPORTED, "coarsest level too large: " + std::to_string(max_ni));
+    double* W = ar.alloc<double>((size_t)max_ni * max_ni);
+    lv.d_cinv = ar.alloc<double>((size_t)inv_off[n_inst]);
+    int32_t* d_st = ar.alloc<int32_t>(n_inst);
+    HIPCHK(hipMemsetAsync(d_st, 0, n_inst * sizeof(int32_t), h->st));
+    double t0 = now_s();
+    for (int32_t i = 0; i < n_inst; ++i) {
+        const int64_t a = lv.inst_off[i], ni = lv.inst_off[i + 1] - a;
+        HIPCHK(hipMemsetAsync(W, 0, (size_t)ni * ni * sizeof(double), h->st));
+        launch_dense_from_csr(a, ni, lv.d_rowptr, lv.d_col, lv.d_val, W, h->st);
+        launch_dense_chol_inv(ni, W, lv.d_cinv + inv_off[i], d_st + i, h->st);
+    }
+    std::vector<int32_t> hs = download(d_st, n_inst, h->st);
+    vlog("coarsest level: n=%lld in %d block(s), dense Cholesky + inverse %.3f s", (long long)lv.n, n_inst,
+         now_s() - t0);
+    ar.release(W);
+    ar.release(d_st);
+    for (int32_t i = 0; i < n_inst; ++i)
+        if (hs[i] != 0)
+            throw Error(LSDD_E_NUMERIC, "coarsest-level Cholesky failed (matrix not SPD), block " + std::to_string(i));
+    lv.fl = 32;
+    lv.c_sub_off = ar.upload(lv.inst_off, h->st);
+    lv.c_tp_off = ar.upload(tp_off, h->st);
+    lv.c_scr_off = ar.upload(scr_off, h->st);
+    std::vector<int32_t> pos(lv.n);
+    for (int32_t i = 0; i < n_inst; ++i)
+        for (int64_t d = lv.inst_off[i]; d < lv.inst_off[i + 1]; ++d) pos[d] = i;
+    lv.c_pos = ar.upload(pos, h->st);
+    std::vector<int32_t> subs(n_inst), items;
+    for (int32_t i = 0; i < n_inst; ++i) subs[i] = i;
+    append_symv_items(lv.inst_off, subs, lv.chl, items);
+    lv.c_items = ar.upload(items, h->st);
+    lv.c_nitems = (int64_t)items.size() / 3;
+    lv.tiles_len = tiles;
+    lv.d_tiles = ar.alloc<double>(lv.tiles_len);
+    int64_t* d_inv_off = ar.upload(inv_off, h->st);
+    launch_pack_tiles(n_inst, lv.c_sub_off, d_inv_off, lv.d_cinv, lv.c_tp_off, lv.d_tiles, nullptr, h->st);
+    HIPCHK(hipGetLastError());
+    sync(h->st);
+    ar.release(d_inv_off);
+    ar.release(lv.d_cinv);
+    lv.d_cinv = nullptr;
+    lv.scr_len = scr_off[n_inst];
     alloc_vectors(h, lv, 0);
 }
 
@@ -457,6 +480,32 @@ std::unique_ptr<Level> coarsen(lsdd_hierarchy* h, Level& lv, const int32_t* agg_
         lv.agg_of_dof.resize(n);
         for (int64_t d = 0; d < n; ++d) lv.agg_of_dof[d] = as[lv.node_of_dof[d]];
     }
+    // aggregates never span instances; number them instance-major (the order
+    // inside an instance is kept), so every instance owns a contiguous range of
+    // aggregates and hence of coarse DOFs
+    const int32_t n_inst = (int32_t)lv.inst_off.size() - 1;
+    std::vector<int32_t> inst_of_agg(n_agg, -1), agg_first(n_inst + 1, 0);
+    {
+        for (int32_t i = 0; i < n_inst; ++i)
+            for (int64_t d = lv.inst_off[i]; d < lv.inst_off[i + 1]; ++d) {
+                int32_t& ia = inst_of_agg[lv.agg_of_dof[d]];
+                if (ia >= 0 && ia != i) throw Error(LSDD_E_INVAL, "an aggregate spans two instances");
+                ia = i;
+            }
+        std::vector<int32_t> order(n_agg), newid(n_agg);
+        for (int32_t a = 0; a < n_agg; ++a) order[a] = a;
+        std::stable_sort(order.begin(), order.end(),
+                         [&](int32_t a, int32_t b) { return inst_of_agg[a] < inst_of_agg[b]; });
+        std::vector<int32_t> ia2(n_agg);
+        for (int32_t q = 0; q < n_agg; ++q) {
+            newid[order[q]] = q;
+            ia2[q] = inst_of_agg[order[q]];
+        }
+        for (int64_t d = 0; d < n; ++d) lv.agg_of_dof[d] = newid[lv.agg_of_dof[d]];
+        inst_of_agg = ia2;
+        for (int32_t a = 0; a < n_agg; ++a) agg_first[inst_of_agg[a] + 1]++;
+        for (int32_t i = 0; i < n_inst; ++i) agg_first[i + 1] += agg_first[i];
+    }
     lv.cl = build_closure(n, lv.agg_of_dof, n_agg, lv.el);
     const Closure& C = lv.cl;
     double tc0 = now_s();
@@ -464,6 +513,19 @@ std::unique_ptr<Level> coarsen(lsdd_hierarchy* h, Level& lv, const int32_t* agg_
         if (C.agg_ptr[i + 1] == C.agg_ptr[i]) throw Error(LSDD_E_INVAL, "empty aggregate " + std::to_string(i));
     lv.colors = color_subdomains(n, C, lv.el, &lv.n_colors);
     const double tau_cut = P.tau_const * (double)C.max_mult;
+    // tau_cut of every aggregate from the largest multiplicity of its own instance
+    std::vector<double> thr_agg;
+    if (n_inst > 1) {
+        std::vector<int32_t> mm(n_inst, 0);
+        for (int64_t e = 0; e < lv.el.count(); ++e) {
+            const int32_t d = lv.el.dofs[lv.el.ptr[e]];
+            const int32_t i = (int32_t)(std::upper_bound(lv.inst_off.begin(), lv.inst_off.end(), (int64_t)d) -
+                                        lv.inst_off.begin() - 1);
+            mm[i] = std::max(mm[i], C.mult[e]);
+        }
+        thr_agg.resize(n_agg);
+        for (int32_t a = 0; a < n_agg; ++a) thr_agg[a] = 1.0 / (P.tau_const * (double)mm[inst_of_agg[a]]);
+    }
     // ---- per-aggregate sizes and local positions of closure elements
     std::vector<int64_t> sq(n_agg + 1, 0), msq(n_agg + 1, 0);
     int64_t max_m = 0, max_nw = 0;
@@ -537,6 +599,8 @@ std::unique_ptr<Level> coarsen(lsdd_hierarchy* h, Level& lv, const int32_t* agg_
     A.status = d_status;
     A.modes_fixed = P.modes_fixed;
     A.thr = 1.0 / tau_cut;
+    double* d_thr = thr_agg.empty() ? nullptr : ar.upload(thr_agg, st);
+    A.thr_agg = d_thr;
     A.band_tol = P.band_tol;
     A.cluster_tol = P.cluster_tol;
 
@@ -803,13 +867,24 @@ std::unique_ptr<Level> coarsen(lsdd_hierarchy* h, Level& lv, const int32_t* agg_
     for (void* p : {(void*)d_sub_ptr, (void*)d_sub_dofs, (void*)d_cl_ptr, (void*)d_cl_elems, (void*)d_clpos_off,
                     (void*)d_clpos, (void*)d_mult, (void*)d_inv_off, (void*)d_zst_off, (void*)d_status})
         ar.release(p);
+    if (d_thr) ar.release(d_thr);
     const int64_t nc = lv.coff[n_agg];
+    // coarse DOF ranges of the instances; an instance without retained modes
+    // would end its hierarchy here while the others continue
+    std::vector<int64_t> c_inst_off(n_inst + 1);
+    int32_t n_empty = 0;
+    for (int32_t i = 0; i <= n_inst; ++i) c_inst_off[i] = lv.coff[agg_first[i]];
+    for (int32_t i = 0; i < n_inst; ++i) n_empty += c_inst_off[i + 1] == c_inst_off[i];
     if (nc == 0) return nullptr;
+    if (n_empty > 0)
+        throw Error(LSDD_E_UNSUPPORTED, "batched instances reach their coarsest level at different depths "
+                                        "(an instance retains no mode on level " + std::to_string(lv.level) + ")");
     // ---- coarse level: grouped element rows and Galerkin products
     CoarseGroups G = group_coarse(lv.el, lv.agg_of_dof, lv.k, lv.coff);
     auto cv = std::make_unique<Level>();
     cv->level = lv.level + 1;
     cv->n = nc;
+    cv->inst_off = c_inst_off;
     cv->el = std::move(G.coarse);
     cv->node_of_dof = G.node_of_cdof;
     cv->n_super = G.n_super;
@@ -1168,7 +1243,8 @@ bool pcg_run(lsdd_hierarchy* h) {
 // ---------------------------------------------------------------- setup driver
 
 lsdd_hierarchy* build(ElemList el0, const double* blocks, bool blocks_on_device, const double* gram_rows, int64_t n,
-                      const int32_t* node_of_dof, const int32_t* agg_of_dof, const lsdd_params* prm, void* stream) {
+                      const int32_t* node_of_dof, const int32_t* agg_of_dof, const lsdd_params* prm, void* stream,
+                      std::vector<int64_t> inst_off = {}) {
     auto h = std::make_unique<lsdd_hierarchy>();
     lsdd_params_default(&h->prm);
     if (prm) h->prm = *prm;
@@ -1181,6 +1257,7 @@ lsdd_hierarchy* build(ElemList el0, const double* blocks, bool blocks_on_device,
     lv->level = 0;
     lv->n = n;
     lv->el = std::move(el0);
+    lv->inst_off = inst_off.empty() ? std::vector<int64_t>{0, n} : inst_off;
     const int64_t ne = lv->el.count();
     lv->blk_off.assign(ne + 1, 0);
     for (int64_t e = 0; e < ne; ++e) {
@@ -1246,8 +1323,19 @@ lsdd_hierarchy* build(ElemList el0, const double* blocks, bool blocks_on_device,
     h->L.push_back(std::move(lv));
     while (true) {
         Level& cur = *h->L.back();
-        const double density = (double)cur.nnz / ((double)cur.n * (double)cur.n);
-        bool last = (int)h->L.size() >= P.max_levels || cur.n < P.min_coarse || density > P.max_density;
+        // stopping tests per instance (one instance: the level itself)
+        const int32_t n_inst = (int32_t)cur.inst_off.size() - 1;
+        int32_t n_last = 0;
+        for (int32_t i = 0; i < n_inst; ++i) {
+            const int64_t a = cur.inst_off[i], b = cur.inst_off[i + 1];
+            const double ni = (double)(b - a);
+            const double density = (double)(cur.pat.ptr[b] - cur.pat.ptr[a]) / (ni * ni);
+            n_last += (int)h->L.size() >= P.max_levels || ni < P.min_coarse || density > P.max_density;
+        }
+        if (n_last != 0 && n_last != n_inst)
+            throw Error(LSDD_E_UNSUPPORTED, "batched instances reach their coarsest level at different depths "
+                                            "(level " + std::to_string(cur.level) + ")");
+        bool last = n_last == n_inst;
         std::unique_ptr<Level> nxt;
         if (!last) {
             nxt = coarsen(h.get(), cur, cur.level == 0 ? agg_of_dof : nullptr);
@@ -1259,7 +1347,7 @@ lsdd_hierarchy* build(ElemList el0, const double* blocks, bool blocks_on_device,
         }
         h->L.push_back(std::move(nxt));
     }
-    init_segments(h.get(), {0, h->L[0]->n});
+    init_segments(h.get(), h->L[0]->inst_off);
     alloc_pcg(h.get(), 0);
     sync(h->st);
     h->setup_s = now_s() - t0;
@@ -1360,6 +1448,75 @@ lsdd_status lsdd_setup_elements(int64_t n, int64_t n_elem, const int64_t* elem_p
             if (!u) throw Error(LSDD_E_INVAL, "aggregate ids must be 0..n_agg-1, each used");
     }
     *out = build(std::move(el), elem_blocks, mem_is_device != 0, nullptr, n, node_of_dof, agg_of_dof, params, hip_stream);
+    return LSDD_OK;
+    ABI_END
+}
+
+lsdd_status lsdd_setup_batched(int32_t n_inst, const int64_t* inst_n, const int64_t* inst_n_elem,
+                               const int64_t* elem_ptr, const int32_t* elem_dofs, const double* elem_blocks,
+                               const int32_t* node_of_dof, const int32_t* agg_of_dof, int mem_is_device,
+                               const lsdd_params* params, void* hip_stream, lsdd_hierarchy** out) {
+    ABI_BEGIN
+    if (!out) throw Error(LSDD_E_INVAL, "out is NULL");
+    *out = nullptr;
+    if (n_inst < 1 || !inst_n || !inst_n_elem || !elem_ptr || !elem_dofs || !elem_blocks)
+        throw Error(LSDD_E_INVAL, "bad sizes or NULL arrays");
+    std::vector<int64_t> inst_off(n_inst + 1, 0), elem_off(n_inst + 1, 0);
+    for (int32_t i = 0; i < n_inst; ++i) {
+        if (inst_n[i] < 1 || inst_n_elem[i] < 1) throw Error(LSDD_E_INVAL, "instance " + std::to_string(i) + " is empty");
+        inst_off[i + 1] = inst_off[i] + inst_n[i];
+        elem_off[i + 1] = elem_off[i] + inst_n_elem[i];
+    }
+    const int64_t n = inst_off[n_inst], n_elem = elem_off[n_inst];
+    if (n >= (int64_t(1) << 31)) throw Error(LSDD_E_INVAL, "too many DOFs in the batch");
+    if (elem_ptr[0] != 0) throw Error(LSDD_E_INVAL, "elem_ptr[0] must be 0");
+    // union numbering: instance-local DOF, supernode and aggregate ids shifted by the instance offsets
+    ElemList el;
+    el.ptr.assign(elem_ptr, elem_ptr + n_elem + 1);
+    el.dofs.resize(el.ptr[n_elem]);
+    std::vector<char> covered(n, 0), seen(n, 0);
+    for (int32_t i = 0; i < n_inst; ++i)
+        for (int64_t e = elem_off[i]; e < elem_off[i + 1]; ++e) {
+            const int64_t sz = el.ptr[e + 1] - el.ptr[e];
+            if (sz < 1 || sz > 128)
+                throw Error(LSDD_E_INVAL, "element " + std::to_string(e) + " has " + std::to_string(sz) + " DOFs (1..128 supported)");
+            for (int64_t q = el.ptr[e]; q < el.ptr[e + 1]; ++q) {
+                const int32_t dl = elem_dofs[q];
+                if (dl < 0 || dl >= inst_n[i])
+                    throw Error(LSDD_E_INVAL, "element " + std::to_string(e) + ": DOF index out of its instance's range");
+                const int64_t d = inst_off[i] + dl;
+                if (seen[d]) throw Error(LSDD_E_INVAL, "element " + std::to_string(e) + ": repeated DOF");
+                seen[d] = 1;
+                covered[d] = 1;
+                el.dofs[q] = (int32_t)d;
+            }
+            for (int64_t q = el.ptr[e]; q < el.ptr[e + 1]; ++q) seen[el.dofs[q]] = 0;
+        }
+    for (int64_t d = 0; d < n; ++d)
+        if (!covered[d]) throw Error(LSDD_E_INVAL, "DOF " + std::to_string(d) + " belongs to no element");
+    auto shift = [&](const int32_t* v, const char* what) {
+        std::vector<int32_t> u(n);
+        int32_t base = 0;
+        for (int32_t i = 0; i < n_inst; ++i) {
+            int32_t mx = -1;
+            for (int64_t d = inst_off[i]; d < inst_off[i + 1]; ++d) {
+                if (v[d] < 0) throw Error(LSDD_E_INVAL, std::string("negative ") + what + " id");
+                mx = std::max(mx, v[d]);
+                u[d] = base + v[d];
+            }
+            std::vector<char> used(mx + 1, 0);
+            for (int64_t d = inst_off[i]; d < inst_off[i + 1]; ++d) used[v[d]] = 1;
+            for (char c : used)
+                if (!c) throw Error(LSDD_E_INVAL, std::string(what) + " ids of an instance must be 0..count-1, each used");
+            base += mx + 1;
+        }
+        return u;
+    };
+    std::vector<int32_t> nodes, aggs;
+    if (node_of_dof) nodes = shift(node_of_dof, "supernode");
+    if (agg_of_dof) aggs = shift(agg_of_dof, "aggregate");
+    *out = build(std::move(el), elem_blocks, mem_is_device != 0, nullptr, n, node_of_dof ? nodes.data() : nullptr,
+                 agg_of_dof ? aggs.data() : nullptr, params, hip_stream, inst_off);
     return LSDD_OK;
     ABI_END
 }

@@ -81,12 +81,14 @@ def lib():
         L.lsdd_trace_get.argtypes = [_P, C.c_int32, C.c_char_p, C.c_int32, i64p, f64p, f64p]
         L.lsdd_set_allocator.argtypes = [_P, _P, _P]
         L.lsdd_set_graph.argtypes = [_P, C.c_int32]
+        L.lsdd_setup_batched.argtypes = [C.c_int32, i64p, i64p, i64p, i32p, _P, i32p, i32p, C.c_int,
+                                         C.POINTER(Params), _P, C.POINTER(_P)]
         L.lsdd_segments.argtypes = [_P, i32p, i64p]
         L.lsdd_set_allocator.restype = None
         for name in ("lsdd_setup_elements", "lsdd_setup_gram_csr", "lsdd_solve", "lsdd_vcycle", "lsdd_apply",
                      "lsdd_hierarchy_info", "lsdd_level_sizes", "lsdd_export_level", "lsdd_export_gram",
                      "lsdd_destroy", "lsdd_set_cycle_precision", "lsdd_trace", "lsdd_trace_get",
-                     "lsdd_set_solve_params"):
+                     "lsdd_set_solve_params", "lsdd_set_graph", "lsdd_segments", "lsdd_setup_batched"):
             getattr(L, name).restype = C.c_int
         _LIB = L
     return _LIB
@@ -152,6 +154,31 @@ class Hierarchy:
             blocks = torch.from_numpy(np.ascontiguousarray(blocks)).cuda()
         return cls.setup_elements(prob.n, prob.elem_ptr, prob.elem_dofs, blocks, prob.node_of_dof,
                                   prob.agg_of_dof, params)
+
+    @classmethod
+    def setup_batched(cls, problems, params=None):
+        """lsdd_setup_batched over a list of problem objects (instance-local numbering);
+        the union's DOFs are the instances' DOFs in list order."""
+        probs = list(problems)
+        inst_n = np.array([p.n for p in probs], dtype=np.int64)
+        inst_ne = np.array([len(p.elem_ptr) - 1 for p in probs], dtype=np.int64)
+        sizes = np.concatenate([np.diff(np.asarray(p.elem_ptr, dtype=np.int64)) for p in probs])
+        elem_ptr = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+        elem_dofs = np.ascontiguousarray(np.concatenate([np.asarray(p.elem_dofs) for p in probs]), dtype=np.int32)
+        blocks = np.ascontiguousarray(np.concatenate([np.asarray(p.blocks) for p in probs]), dtype=np.float64)
+        nod = None
+        if all(p.node_of_dof is not None for p in probs):
+            nod = np.ascontiguousarray(np.concatenate([p.node_of_dof for p in probs]), dtype=np.int32)
+        agg = None
+        if all(p.agg_of_dof is not None for p in probs):
+            agg = np.ascontiguousarray(np.concatenate([p.agg_of_dof for p in probs]), dtype=np.int32)
+        params = params or Params.default()
+        h = C.c_void_p()
+        _check(lib().lsdd_setup_batched(len(probs), _ptr(inst_n, C.c_int64), _ptr(inst_ne, C.c_int64),
+                                        _ptr(elem_ptr, C.c_int64), _ptr(elem_dofs, C.c_int32),
+                                        C.c_void_p(blocks.ctypes.data), _ptr(nod, C.c_int32), _ptr(agg, C.c_int32),
+                                        0, C.byref(params), _stream(), C.byref(h)))
+        return cls(h)
 
     @classmethod
     def setup_gram_csr(cls, m, n, rowptr, col, val, node_of_dof=None, agg_of_dof=None, params=None):

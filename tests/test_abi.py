@@ -60,3 +60,22 @@ def test_setup_rejects_uncovered_dof_and_bad_aggregates():
     agg[agg == 0] = 7 + agg.max()           # leaves id 0 unused
     with pytest.raises(P.LsddError, match="aggregate ids"):
         P.Hierarchy.setup_elements(prob.n, prob.elem_ptr, prob.elem_dofs, prob.blocks, prob.node_of_dof, agg)
+
+
+def test_batched_setup_validates_instance_local_indices():
+    """A DOF index valid in the union but outside its own instance is rejected."""
+    import copy
+
+    import paper_2607_07485_amd as P
+    a, b = _elems(), _elems()
+    bad = copy.copy(b)
+    bad.elem_dofs = b.elem_dofs.copy()
+    bad.elem_dofs[3] = b.n + 2                   # would land in the next instance's range
+    with pytest.raises(P.LsddError, match="instance's range"):
+        P.Hierarchy.setup_batched([a, bad, _elems()])
+    agg = b.agg_of_dof.copy()
+    agg[agg == 0] = 5 + agg.max()
+    bad2 = copy.copy(b)
+    bad2.agg_of_dof = agg
+    with pytest.raises(P.LsddError, match="aggregate ids of an instance"):
+        P.Hierarchy.setup_batched([a, bad2])

@@ -103,3 +103,59 @@ def test_graph_replays_match_eager(dev):
         h.set_graph(False)
         x_2, _ = h.solve(b1)
         assert torch.equal(x_2, x_e)
+
+
+BATCH_KW = dict(max_levels=3, tau_const=0.75, max_density=1.0, min_coarse=1, agg_passes=2, agg_passes_coarse=1)
+
+
+def _batch():
+    """Uneven Q1 elasticity instances (vertex-patch cover, threshold modes)."""
+    return [fegen.elasticity_q1(N, nu=nu) for N, nu in ((6, 0.3), (11, 0.45), (8, 0.38))]
+
+
+def test_batched_instances_match_per_instance_oracle(dev):
+    """One union hierarchy over uneven instances: per instance, every level's
+    aggregates and retained modes equal the instance's own oracle hierarchy, and
+    every (instance, right-hand side) solve matches the oracle's PCG."""
+    P = _lsdd()
+    probs = _batch()
+    h_ors = [oracle.setup(p, oracle.Params(**BATCH_KW)) for p in probs]
+    n_tot = sum(p.n for p in probs)
+    rng = np.random.default_rng(21)
+    B = rng.standard_normal((3, n_tot))
+    with P.Hierarchy.setup_batched(probs, P.Params.default(**BATCH_KW)) as h:
+        nseg, off = h.segments()
+        assert nseg == 3 and off == list(np.cumsum([0] + [p.n for p in probs]))
+        info = h.info()
+        L = len(h_ors[0].levels)
+        assert all(len(ho.levels) == L for ho in h_ors)
+        assert info["n"] == [sum(ho.levels[l].n for ho in h_ors) for l in range(L)]
+        for l in range(L - 1):
+            ex = h.export_level(l)
+            d0 = a0 = 0
+            for ho in h_ors:
+                lv = ho.levels[l]
+                n_agg = len(lv.k)
+                assert np.array_equal(ex["agg_of_dof"][d0:d0 + lv.n] - a0, lv.agg_of_dof)
+                assert np.array_equal(ex["k"][a0:a0 + n_agg], lv.k)
+                d0 += lv.n
+                a0 += n_agg
+        for nrhs in (1, 3):
+            X, infos = h.solve(torch.from_numpy(B[:nrhs].copy()).to(dev))
+            X = X.cpu().numpy().reshape(nrhs, n_tot)
+            for k in range(nrhs):
+                for i, (p, ho) in enumerate(zip(probs, h_ors)):
+                    x_or, inf_or = oracle.pcg(ho, B[k, off[i]:off[i + 1]])
+                    f = infos[k * nseg + i]
+                    assert f.converged == 1 and abs(f.iters - inf_or.iters) <= 1
+                    xi = X[k, off[i]:off[i + 1]]
+                    assert np.linalg.norm(xi - x_or) <= 1e-10 * np.linalg.norm(x_or)
+
+
+def test_batched_uneven_depths_are_rejected(dev):
+    """An instance that would stop a level earlier than the others is reported."""
+    P = _lsdd()
+    probs = [fegen.elasticity_q1(2, nu=0.3), fegen.elasticity_q1(9, nu=0.3)]
+    with pytest.raises(P.LsddError) as ei:
+        P.Hierarchy.setup_batched(probs, P.Params.default(max_levels=3, tau_const=0.75))
+    assert ei.value.code == 7 and "different depths" in str(ei.value)
