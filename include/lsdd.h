@@ -123,10 +123,11 @@ lsdd_status lsdd_setup_elements(int64_t n, int64_t n_elem, const int64_t* elem_p
  * DOF j of instance i is DOF inst_off[i] + j of the union (inst_off = prefix sums of
  * inst_n), which is also the layout of b and x in lsdd_solve; lsdd_segments returns
  * inst_off.  Per instance: tau_cut uses the instance's own largest multiplicity and the
- * stopping tests (min_coarse, max_density, no retained mode) are applied to the
- * instance's own level; instances that would reach their coarsest level at different
- * depths -> LSDD_E_UNSUPPORTED.  The coarsest level is solved with one dense inverse
- * per instance. */
+ * stopping tests (max_levels, min_coarse, max_density) are applied to the instance's
+ * own level, so every instance gets the hierarchy it would get alone; an instance whose
+ * hierarchy ends on level l is solved there with the dense inverse of its block of A_l
+ * while the others continue (lsdd_level_segments).  An instance that retains no mode
+ * on a level while others do -> LSDD_E_UNSUPPORTED. */
 lsdd_status lsdd_setup_batched(int32_t n_inst, const int64_t* inst_n, const int64_t* inst_n_elem,
                                const int64_t* elem_ptr, const int32_t* elem_dofs, const double* elem_blocks,
                                const int32_t* node_of_dof, const int32_t* agg_of_dof, int mem_is_device,
@@ -176,6 +177,13 @@ lsdd_status lsdd_set_graph(lsdd_hierarchy* h, int32_t on);
  *   seg_off   int64[n_seg + 1]: segment s is DOFs [seg_off[s], seg_off[s+1]) */
 lsdd_status lsdd_segments(const lsdd_hierarchy* h, int32_t* n_seg, int64_t* seg_off);
 
+/* Instances on level l of a batched hierarchy (host outputs, either may be NULL):
+ *   inst_off  int64[n_seg + 1]: instance i owns DOFs [inst_off[i], inst_off[i+1]) of
+ *             level l (empty once its hierarchy has ended on a finer level)
+ *   terminal  int32[n_seg]: 1 if instance i's hierarchy ends on level l (its block of
+ *             A_l is solved directly there; it owns no aggregate on level l) */
+lsdd_status lsdd_level_segments(const lsdd_hierarchy* h, int32_t level, int64_t* inst_off, int32_t* terminal);
+
 /* Per-kernel timing: on != 0 clears the counters and records a pair of HIP
  * events on the solve stream around every launch of the traced kernel classes
  * (csr_resid_rows, sub_symv, sub_finalize, csr_spmv, restrict, prolong,
@@ -211,7 +219,7 @@ lsdd_status lsdd_hierarchy_info(const lsdd_hierarchy* h, int32_t* levels, int64_
 lsdd_status lsdd_level_sizes(const lsdd_hierarchy* h, int32_t level, int64_t* sizes);
 
 /* Copy level-l data to host buffers (any may be NULL; sizes from lsdd_level_sizes):
- *   agg_of_dof int32[n_l]; k int32[n_agg] (retained modes); Z float64[sum |w_i| k_i]
+ *   agg_of_dof int32[n_l] (-1 on the DOFs of instances whose hierarchy ends on level l); k int32[n_agg] (retained modes); Z float64[sum |w_i| k_i]
  *   (aggregate-major, each Z_i row-major |omega_i| x k_i, rows in ascending DOF order,
  *   columns in ascending mu); mu float64[sum |omega_i|] (sorted local spectra);
  *   colors int32[n_agg]; rowptr int64[n_l+1], col int32[nnz], val float64[nnz] (A_l, CSR,

@@ -143,14 +143,16 @@ Closure build_closure(int64_t n, const std::vector<int32_t>& agg_of_dof, int32_t
     c.n_agg = n_agg;
     // aggregates (ascending DOFs)
     c.agg_ptr.assign(n_agg + 1, 0);
-    for (int64_t d = 0; d < n; ++d) c.agg_ptr[agg_of_dof[d] + 1]++;
+    for (int64_t d = 0; d < n; ++d)
+        if (agg_of_dof[d] >= 0) c.agg_ptr[agg_of_dof[d] + 1]++;
     for (int32_t i = 0; i < n_agg; ++i) c.agg_ptr[i + 1] += c.agg_ptr[i];
-    c.agg_dofs.resize(n);
-    c.pos_in_agg.resize(n);
+    c.agg_dofs.resize(c.agg_ptr[n_agg]);
+    c.pos_in_agg.assign(n, -1);
     {
         std::vector<int64_t> fill(c.agg_ptr.begin(), c.agg_ptr.end() - 1);
         for (int64_t d = 0; d < n; ++d) {
             int32_t i = agg_of_dof[d];
+            if (i < 0) continue;
             c.pos_in_agg[d] = (int32_t)(fill[i] - c.agg_ptr[i]);
             c.agg_dofs[fill[i]++] = (int32_t)d;
         }
@@ -162,7 +164,8 @@ Closure build_closure(int64_t n, const std::vector<int32_t>& agg_of_dof, int32_t
     std::vector<int32_t> touched;
     for (int64_t e = 0; e < ne; ++e) {
         size_t start = touched.size();
-        for (int64_t q = el.ptr[e]; q < el.ptr[e + 1]; ++q) touched.push_back(agg_of_dof[el.dofs[q]]);
+        for (int64_t q = el.ptr[e]; q < el.ptr[e + 1]; ++q)
+            if (agg_of_dof[el.dofs[q]] >= 0) touched.push_back(agg_of_dof[el.dofs[q]]);
         std::sort(touched.begin() + start, touched.end());
         touched.erase(std::unique(touched.begin() + start, touched.end()), touched.end());
         tptr[e + 1] = (int64_t)touched.size();
@@ -280,7 +283,7 @@ CoarseGroups group_coarse(const ElemList& el, const std::vector<int32_t>& agg_of
         t.clear();
         for (int64_t q = el.ptr[e]; q < el.ptr[e + 1]; ++q) {
             int32_t a = agg_of_dof[el.dofs[q]];
-            if (k[a] > 0) t.push_back(a);
+            if (a >= 0 && k[a] > 0) t.push_back(a);
         }
         std::sort(t.begin(), t.end());
         t.erase(std::unique(t.begin(), t.end()), t.end());

@@ -38,7 +38,7 @@ struct Closure {
     int32_t n_agg = 0;
     std::vector<int64_t> agg_ptr;   // omega_i = agg_dofs[agg_ptr[i] .. agg_ptr[i+1]) ascending
     std::vector<int32_t> agg_dofs;
-    std::vector<int32_t> pos_in_agg;    // per DOF: its index inside its aggregate
+    std::vector<int32_t> pos_in_agg;    // per DOF: its index inside its aggregate (-1: none)
     std::vector<int64_t> sub_ptr;   // Omega_i: omega_i ascending, then Gamma_i ascending
     std::vector<int32_t> sub_dofs;
     std::vector<int64_t> cl_ptr;    // elements with a DOF in omega_i, ascending
@@ -47,6 +47,8 @@ struct Closure {
     int32_t max_mult = 0;
 };
 
+// DOFs with agg_of_dof < 0 belong to no aggregate (problem instances whose
+// hierarchy ended on this level); elements made of such DOFs touch no aggregate.
 Closure build_closure(int64_t n, const std::vector<int32_t>& agg_of_dof, int32_t n_agg, const ElemList& el);
 
 // Greedy colouring of subdomains: i and k conflict iff an element meets both

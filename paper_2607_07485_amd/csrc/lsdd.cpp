@@ -189,18 +189,24 @@ struct Level {
     int32_t* d_pos_sub = nullptr;     // sweep-order subdomain of every Omega entry
     int64_t* d_scr_off = nullptr;     // per subdomain: offset of its partial-sum scratch
     // coarsest level as one packed symmetric "subdomain"
-    int64_t* c_sub_off = nullptr;
+    // terminal blocks: the instances whose hierarchy ends on this level (every
+    // instance present on the coarsest level), each solved with its dense inverse
+    std::vector<int32_t> term;        // instance ids
+    int64_t term_len = 0;             // DOFs in terminal blocks (entries, instance order)
+    int64_t c_scr_len = 0;            // partial-sum entries of the terminal product
+    double c_entries = 0.0;           // sum n_i (n_i + 1) / 2 over the blocks
+    int64_t* c_sub_off = nullptr;     // entry ranges of the blocks
     int64_t* c_tp_off = nullptr;
     int64_t* c_scr_off = nullptr;
-    int32_t* c_pos = nullptr;
+    int32_t* c_pos = nullptr;         // entry -> block
+    int32_t* c_dofs = nullptr;        // entry -> DOF (NULL: the blocks cover the level in order)
     int32_t* c_items = nullptr;
     int64_t c_nitems = 0;
+    double* c_tiles = nullptr;
     double* d_inv = nullptr;          // full inverses during setup only
     double* d_tiles = nullptr;        // packed lower tiles of A_Omega^{-1}
     float* d_tiles32 = nullptr;
     int64_t inv_len = 0, tiles_len = 0;
-    // coarsest
-    double* d_cinv = nullptr;
     // vectors: [0] single vectors, [1] blocks of NRB right-hand sides (allocated on first use)
     VecSet<double> v64[2];
     VecSet<float> v32[2];
@@ -350,7 +356,8 @@ void assemble_operator(lsdd_hierarchy* h, Level& lv) {
 void alloc_vectors(lsdd_hierarchy* h, Level& lv, int b) {
     Arena& a = h->arena;
     const int64_t w = b ? NRB : 1;
-    const int64_t nl = std::max<int64_t>(lv.rloc_len, 1) * w, ns = std::max<int64_t>(lv.scr_len, 1) * w;
+    const int64_t nl = std::max<int64_t>({lv.rloc_len, lv.c_dofs ? lv.term_len : 0, 1}) * w;
+    const int64_t ns = std::max<int64_t>({lv.scr_len, lv.c_scr_len, 1}) * w;
     if (h->prm.precision == 1) {
         VecSet<float>& v = lv.v32[b];
         v.r = a.alloc<float>(lv.n * w);
@@ -358,7 +365,7 @@ void alloc_vectors(lsdd_hierarchy* h, Level& lv, int b) {
         v.t = a.alloc<float>(lv.n * w);
         v.rloc = a.alloc<float>(nl);
         v.scr = a.alloc<float>(ns);
-        if (lv.coarsest) {
+        if (!lv.term.empty()) {
             lv.cr64[b] = a.alloc<double>(lv.n * w);
             lv.cx64[b] = a.alloc<double>(lv.n * w);
         }
@@ -397,70 +404,80 @@ void append_symv_items(const std::vector<int64_t>& sub_off, const std::vector<in
     for (size_t q : ord) items.insert(items.end(), {it[3 * q], it[3 * q + 1], it[3 * q + 2]});
 }
 
-// Coarsest level: the dense Cholesky factorisation and explicit inverse of every
-// instance block of A_l (one block for a single problem), packed into lower
-// 64 x 64 tiles and applied by the symmetric subdomain kernel with one
-// "subdomain" per instance.
-void make_coarsest(lsdd_hierarchy* h, Level& lv) {
-    lv.coarsest = true;
+// Terminal blocks of a level: the dense Cholesky factorisation and explicit
+// inverse of the instance blocks of A_l listed in `term` (on the coarsest level:
+// every instance present, i.e. the whole level for a single problem), packed into
+// lower 64 x 64 tiles and applied by the symmetric subdomain kernel with one
+// "subdomain" per block.
+void make_terminal(lsdd_hierarchy* h, Level& lv, const std::vector<int32_t>& term, bool coarsest) {
     Arena& ar = h->arena;
-    const int32_t n_inst = (int32_t)lv.inst_off.size() - 1;
-    int64_t max_ni = 0;
-    std::vector<int64_t> inv_off(n_inst + 1, 0), tp_off(n_inst), scr_off(n_inst + 1, 0);
-    int64_t tiles = 0;
-    for (int32_t i = 0; i < n_inst; ++i) {
-        const int64_t ni = lv.inst_off[i + 1] - lv.inst_off[i];
+    const int32_t nb = (int32_t)term.size();
+    lv.term = term;
+    std::vector<int64_t> sub_off(nb + 1, 0), inv_off(nb + 1, 0), tp_off(nb), scr_off(nb + 1, 0);
+    std::vector<int32_t> dofs, pos;
+    int64_t tiles = 0, max_ni = 0;
+    lv.c_entries = 0.0;
+    for (int32_t q = 0; q < nb; ++q) {
+        const int64_t a = lv.inst_off[term[q]], ni = lv.inst_off[term[q] + 1] - a;
         max_ni = std::max(max_ni, ni);
-        inv_off[i + 1] = inv_off[i] + ni * ni;
-        tp_off[i] = tiles;
+        sub_off[q + 1] = sub_off[q] + ni;
+        inv_off[q + 1] = inv_off[q] + ni * ni;
+        tp_off[q] = tiles;
         const int64_t nt = (ni + 63) / 64;
         tiles += nt * (nt + 1) / 2 * 4096;
-        scr_off[i + 1] = scr_off[i] + sub_symv_scratch_len(ni, lv.chl);
+        scr_off[q + 1] = scr_off[q] + sub_symv_scratch_len(ni, lv.chl);
+        lv.c_entries += (double)ni * (ni + 1) / 2.0;
+        for (int64_t d = a; d < a + ni; ++d) {
+            dofs.push_back((int32_t)d);
+            pos.push_back(q);
+        }
     }
-    if (max_ni > 32768) throw Error(LSDD_E_UNSUPPORTED, "coarsest level too large: " + std::to_string(max_ni));
+    lv.term_len = sub_off[nb];
+    bool identity = lv.term_len == lv.n;
+    for (int64_t t = 0; identity && t < lv.term_len; ++t) identity = dofs[t] == t;
+    if (max_ni > 32768) throw Error(LSDD_E_UNSUPPORTED, "terminal block too large: " + std::to_string(max_ni));
     double* W = ar.alloc<double>((size_t)max_ni * max_ni);
-    lv.d_cinv = ar.alloc<double>((size_t)inv_off[n_inst]);
-    int32_t* d_st = ar.alloc<int32_t>(n_inst);
-    HIPCHK(hipMemsetAsync(d_st, 0, n_inst * sizeof(int32_t), h->st));
+    double* inv = ar.alloc<double>((size_t)inv_off[nb]);
+    int32_t* d_st = ar.alloc<int32_t>(nb);
+    HIPCHK(hipMemsetAsync(d_st, 0, nb * sizeof(int32_t), h->st));
     double t0 = now_s();
-    for (int32_t i = 0; i < n_inst; ++i) {
-        const int64_t a = lv.inst_off[i], ni = lv.inst_off[i + 1] - a;
+    for (int32_t q = 0; q < nb; ++q) {
+        const int64_t a = lv.inst_off[term[q]], ni = sub_off[q + 1] - sub_off[q];
         HIPCHK(hipMemsetAsync(W, 0, (size_t)ni * ni * sizeof(double), h->st));
         launch_dense_from_csr(a, ni, lv.d_rowptr, lv.d_col, lv.d_val, W, h->st);
-        launch_dense_chol_inv(ni, W, lv.d_cinv + inv_off[i], d_st + i, h->st);
+        launch_dense_chol_inv(ni, W, inv + inv_off[q], d_st + q, h->st);
     }
-    std::vector<int32_t> hs = download(d_st, n_inst, h->st);
-    vlog("coarsest level: n=%lld in %d block(s), dense Cholesky + inverse %.3f s", (long long)lv.n, n_inst,
-         now_s() - t0);
+    std::vector<int32_t> hs = download(d_st, nb, h->st);
+    vlog("level %d: %d terminal block(s), %lld DOFs, dense Cholesky + inverse %.3f s", lv.level, nb,
+         (long long)lv.term_len, now_s() - t0);
     ar.release(W);
     ar.release(d_st);
-    for (int32_t i = 0; i < n_inst; ++i)
-        if (hs[i] != 0)
-            throw Error(LSDD_E_NUMERIC, "coarsest-level Cholesky failed (matrix not SPD), block " + std::to_string(i));
-    lv.fl = 32;
-    lv.c_sub_off = ar.upload(lv.inst_off, h->st);
+    for (int32_t q = 0; q < nb; ++q)
+        if (hs[q] != 0)
+            throw Error(LSDD_E_NUMERIC, "dense Cholesky of a terminal block failed (matrix not SPD), instance " +
+                                            std::to_string(term[q]) + " on level " + std::to_string(lv.level));
+    lv.c_sub_off = ar.upload(sub_off, h->st);
     lv.c_tp_off = ar.upload(tp_off, h->st);
     lv.c_scr_off = ar.upload(scr_off, h->st);
-    std::vector<int32_t> pos(lv.n);
-    for (int32_t i = 0; i < n_inst; ++i)
-        for (int64_t d = lv.inst_off[i]; d < lv.inst_off[i + 1]; ++d) pos[d] = i;
     lv.c_pos = ar.upload(pos, h->st);
-    std::vector<int32_t> subs(n_inst), items;
-    for (int32_t i = 0; i < n_inst; ++i) subs[i] = i;
-    append_symv_items(lv.inst_off, subs, lv.chl, items);
+    lv.c_dofs = identity ? nullptr : ar.upload(dofs, h->st);
+    std::vector<int32_t> subs(nb), items;
+    for (int32_t q = 0; q < nb; ++q) subs[q] = q;
+    append_symv_items(sub_off, subs, lv.chl, items);
     lv.c_items = ar.upload(items, h->st);
     lv.c_nitems = (int64_t)items.size() / 3;
-    lv.tiles_len = tiles;
-    lv.d_tiles = ar.alloc<double>(lv.tiles_len);
+    lv.c_tiles = ar.alloc<double>(tiles);
     int64_t* d_inv_off = ar.upload(inv_off, h->st);
-    launch_pack_tiles(n_inst, lv.c_sub_off, d_inv_off, lv.d_cinv, lv.c_tp_off, lv.d_tiles, nullptr, h->st);
+    launch_pack_tiles(nb, lv.c_sub_off, d_inv_off, inv, lv.c_tp_off, lv.c_tiles, nullptr, h->st);
     HIPCHK(hipGetLastError());
     sync(h->st);
     ar.release(d_inv_off);
-    ar.release(lv.d_cinv);
-    lv.d_cinv = nullptr;
-    lv.scr_len = scr_off[n_inst];
-    alloc_vectors(h, lv, 0);
+    ar.release(inv);
+    lv.c_scr_len = scr_off[nb];
+    if (coarsest) {
+        lv.coarsest = true;
+        alloc_vectors(h, lv, 0);
+    }
 }
 
 // Build level l+1 from level l; returns nullptr when no mode is retained.
@@ -480,14 +497,29 @@ std::unique_ptr<Level> coarsen(lsdd_hierarchy* h, Level& lv, const int32_t* agg_
         lv.agg_of_dof.resize(n);
         for (int64_t d = 0; d < n; ++d) lv.agg_of_dof[d] = as[lv.node_of_dof[d]];
     }
+    const int32_t n_inst = (int32_t)lv.inst_off.size() - 1;
+    // instances whose hierarchy ends on this level take no part in aggregation
+    if (!lv.term.empty()) {
+        for (int32_t i : lv.term)
+            for (int64_t d = lv.inst_off[i]; d < lv.inst_off[i + 1]; ++d) lv.agg_of_dof[d] = -1;
+        std::vector<int32_t> newid(n_agg, -1);
+        for (int64_t d = 0; d < n; ++d)
+            if (lv.agg_of_dof[d] >= 0) newid[lv.agg_of_dof[d]] = 0;
+        int32_t na = 0;
+        for (int32_t a = 0; a < n_agg; ++a)
+            if (newid[a] == 0) newid[a] = na++;
+        for (int64_t d = 0; d < n; ++d)
+            if (lv.agg_of_dof[d] >= 0) lv.agg_of_dof[d] = newid[lv.agg_of_dof[d]];
+        n_agg = na;
+    }
     // aggregates never span instances; number them instance-major (the order
     // inside an instance is kept), so every instance owns a contiguous range of
     // aggregates and hence of coarse DOFs
-    const int32_t n_inst = (int32_t)lv.inst_off.size() - 1;
     std::vector<int32_t> inst_of_agg(n_agg, -1), agg_first(n_inst + 1, 0);
     {
         for (int32_t i = 0; i < n_inst; ++i)
             for (int64_t d = lv.inst_off[i]; d < lv.inst_off[i + 1]; ++d) {
+                if (lv.agg_of_dof[d] < 0) continue;
                 int32_t& ia = inst_of_agg[lv.agg_of_dof[d]];
                 if (ia >= 0 && ia != i) throw Error(LSDD_E_INVAL, "an aggregate spans two instances");
                 ia = i;
@@ -501,7 +533,8 @@ std::unique_ptr<Level> coarsen(lsdd_hierarchy* h, Level& lv, const int32_t* agg_
             newid[order[q]] = q;
             ia2[q] = inst_of_agg[order[q]];
         }
-        for (int64_t d = 0; d < n; ++d) lv.agg_of_dof[d] = newid[lv.agg_of_dof[d]];
+        for (int64_t d = 0; d < n; ++d)
+            if (lv.agg_of_dof[d] >= 0) lv.agg_of_dof[d] = newid[lv.agg_of_dof[d]];
         inst_of_agg = ia2;
         for (int32_t a = 0; a < n_agg; ++a) agg_first[inst_of_agg[a] + 1]++;
         for (int32_t i = 0; i < n_inst; ++i) agg_first[i + 1] += agg_first[i];
@@ -874,11 +907,12 @@ std::unique_ptr<Level> coarsen(lsdd_hierarchy* h, Level& lv, const int32_t* agg_
     std::vector<int64_t> c_inst_off(n_inst + 1);
     int32_t n_empty = 0;
     for (int32_t i = 0; i <= n_inst; ++i) c_inst_off[i] = lv.coff[agg_first[i]];
-    for (int32_t i = 0; i < n_inst; ++i) n_empty += c_inst_off[i + 1] == c_inst_off[i];
+    for (int32_t i = 0; i < n_inst; ++i)
+        n_empty += agg_first[i + 1] > agg_first[i] && c_inst_off[i + 1] == c_inst_off[i];
     if (nc == 0) return nullptr;
     if (n_empty > 0)
-        throw Error(LSDD_E_UNSUPPORTED, "batched instances reach their coarsest level at different depths "
-                                        "(an instance retains no mode on level " + std::to_string(lv.level) + ")");
+        throw Error(LSDD_E_UNSUPPORTED, "an instance of the batch retains no mode on level " +
+                                            std::to_string(lv.level) + " while others do");
     // ---- coarse level: grouped element rows and Galerkin products
     CoarseGroups G = group_coarse(lv.el, lv.agg_of_dof, lv.k, lv.coff);
     auto cv = std::make_unique<Level>();
@@ -1052,6 +1086,27 @@ void sweep(lsdd_hierarchy* h, Level& lv, const T* r, T* x, bool forward, bool x_
     }
 }
 
+// Terminal blocks of a level in FP64: x[T] = A_T^{-1} r[T] for every block T
+// (r, x level vectors of NR interleaved right-hand sides; x is written only on
+// the blocks' DOFs).
+template <int NR>
+void terminal_solve(lsdd_hierarchy* h, Level& lv, const double* r, double* x) {
+    using CD = Cyc<double, NR>;
+    constexpr int b = NR > 1 ? 1 : 0;
+    VecSet<double>& v = lv.v64[b];
+    const double* rr = r;
+    if (lv.c_dofs) {
+        CD::resid_rows(lv.term_len, lv.c_dofs, lv, lv.d_val, r, r, v.rloc, true, h->st);   // gather
+        rr = v.rloc;
+    }
+    const double nb = lv.c_entries * 8.0 + 2.0 * lv.term_len * 8.0 * NR;
+    traced(h, "coarse_symv", nb, [&] {
+        CD::symv(lv.c_nitems, lv.c_items, lv.c_sub_off, lv.c_tp_off, lv.c_tiles, rr, lv.c_scr_off, v.scr, lv.chl,
+                 h->st);
+    });
+    CD::finalize(0, lv.term_len, lv.c_pos, lv.c_sub_off, lv.c_scr_off, v.scr, lv.c_dofs, x, false, lv.chl, 32, h->st);
+}
+
 template <typename T, int NR>
 void vcycle(lsdd_hierarchy* h, size_t l, const T* r, T* x) {
     using O = LvOps<T>;
@@ -1059,30 +1114,26 @@ void vcycle(lsdd_hierarchy* h, size_t l, const T* r, T* x) {
     constexpr int b = NR > 1 ? 1 : 0;
     Level& lv = *h->L[l];
     const double w = (double)sizeof(T), wv = w * NR;
-    if (lv.coarsest) {
-        using CD = Cyc<double, NR>;
-        const double nb = (double)lv.n * (lv.n + 1) / 2.0 * 8.0 + 2.0 * lv.n * 8.0 * NR;
-        auto apply = [&](const double* rr, double* xx) {
-            traced(h, "coarse_symv", nb, [&] {
-                CD::symv(lv.c_nitems, lv.c_items, lv.c_sub_off, lv.c_tp_off, lv.d_tiles, rr, lv.c_scr_off,
-                         lv.v64[b].scr, lv.chl, h->st);
-            });
-            CD::finalize(0, lv.n, lv.c_pos, lv.c_sub_off, lv.c_scr_off, lv.v64[b].scr, nullptr, xx, false, lv.chl,
-                         lv.fl, h->st);
-        };
+    // terminal blocks (all of the coarsest level) in FP64
+    auto terminal = [&] {
         if constexpr (std::is_same<T, double>::value) {
-            apply(r, x);
+            terminal_solve<NR>(h, lv, r, x);
         } else {
             launch_to_f64(lv.n * NR, r, lv.cr64[b], h->st);
-            apply(lv.cr64[b], lv.cx64[b]);
+            if (!lv.coarsest) launch_zero<double>(lv.n * NR, lv.cx64[b], h->st);
+            terminal_solve<NR>(h, lv, lv.cr64[b], lv.cx64[b]);
             launch_to_f32(lv.n * NR, lv.cx64[b], x, h->st);
         }
+    };
+    if (lv.coarsest) {
+        terminal();
         return;
     }
     Level& nx = *h->L[l + 1];
     VecSet<T>& v = O::v(lv, b);
     VecSet<T>& vn = O::v(nx, b);
     launch_zero<T>(lv.n * NR, x, h->st);
+    if (!lv.term.empty()) terminal();     // instances whose hierarchy ends on this level
     sweep<T, NR>(h, lv, r, x, true, true);
     traced(h, "csr_spmv", (double)lv.nnz * (4 + w) + (double)lv.n * (8 + 3 * wv),
            [&] { C::spmv(lv, O::val(lv), x, v.t, r, h->st); });
@@ -1323,26 +1374,30 @@ lsdd_hierarchy* build(ElemList el0, const double* blocks, bool blocks_on_device,
     h->L.push_back(std::move(lv));
     while (true) {
         Level& cur = *h->L.back();
-        // stopping tests per instance (one instance: the level itself)
+        // stopping tests per instance (one instance: the level itself); an
+        // instance that stops here gets its terminal block on this level
         const int32_t n_inst = (int32_t)cur.inst_off.size() - 1;
-        int32_t n_last = 0;
+        std::vector<int32_t> term, active;
         for (int32_t i = 0; i < n_inst; ++i) {
             const int64_t a = cur.inst_off[i], b = cur.inst_off[i + 1];
+            if (b == a) continue;                       // ended on a finer level
             const double ni = (double)(b - a);
             const double density = (double)(cur.pat.ptr[b] - cur.pat.ptr[a]) / (ni * ni);
-            n_last += (int)h->L.size() >= P.max_levels || ni < P.min_coarse || density > P.max_density;
+            const bool last = (int)h->L.size() >= P.max_levels || ni < P.min_coarse || density > P.max_density;
+            (last ? term : active).push_back(i);
         }
-        if (n_last != 0 && n_last != n_inst)
-            throw Error(LSDD_E_UNSUPPORTED, "batched instances reach their coarsest level at different depths "
-                                            "(level " + std::to_string(cur.level) + ")");
-        bool last = n_last == n_inst;
-        std::unique_ptr<Level> nxt;
-        if (!last) {
-            nxt = coarsen(h.get(), cur, cur.level == 0 ? agg_of_dof : nullptr);
-            if (!nxt) last = true;
+        if (active.empty()) {
+            make_terminal(h.get(), cur, term, true);
+            break;
         }
-        if (last) {
-            make_coarsest(h.get(), cur);
+        if (!term.empty()) make_terminal(h.get(), cur, term, false);
+        std::unique_ptr<Level> nxt = coarsen(h.get(), cur, cur.level == 0 ? agg_of_dof : nullptr);
+        if (!nxt) {
+            // no mode retained anywhere: every instance present ends here
+            std::vector<int32_t> all(term);
+            all.insert(all.end(), active.begin(), active.end());
+            std::sort(all.begin(), all.end());
+            make_terminal(h.get(), cur, all, true);
             break;
         }
         h->L.push_back(std::move(nxt));
@@ -1693,6 +1748,19 @@ lsdd_status lsdd_segments(const lsdd_hierarchy* h, int32_t* n_seg, int64_t* seg_
     if (!h) throw Error(LSDD_E_INVAL, "NULL hierarchy");
     if (n_seg) *n_seg = h->seg.n_seg;
     if (seg_off) std::copy(h->seg_off.begin(), h->seg_off.end(), seg_off);
+    return LSDD_OK;
+    ABI_END
+}
+
+lsdd_status lsdd_level_segments(const lsdd_hierarchy* h, int32_t level, int64_t* inst_off, int32_t* terminal) {
+    ABI_BEGIN
+    if (!h || level < 0 || level >= (int32_t)h->L.size()) throw Error(LSDD_E_INVAL, "bad argument");
+    const Level& lv = *h->L[level];
+    if (inst_off) std::copy(lv.inst_off.begin(), lv.inst_off.end(), inst_off);
+    if (terminal) {
+        std::fill(terminal, terminal + lv.inst_off.size() - 1, 0);
+        for (int32_t i : lv.term) terminal[i] = 1;
+    }
     return LSDD_OK;
     ABI_END
 }

@@ -84,11 +84,13 @@ def lib():
         L.lsdd_setup_batched.argtypes = [C.c_int32, i64p, i64p, i64p, i32p, _P, i32p, i32p, C.c_int,
                                          C.POINTER(Params), _P, C.POINTER(_P)]
         L.lsdd_segments.argtypes = [_P, i32p, i64p]
+        L.lsdd_level_segments.argtypes = [_P, C.c_int32, i64p, i32p]
         L.lsdd_set_allocator.restype = None
         for name in ("lsdd_setup_elements", "lsdd_setup_gram_csr", "lsdd_solve", "lsdd_vcycle", "lsdd_apply",
                      "lsdd_hierarchy_info", "lsdd_level_sizes", "lsdd_export_level", "lsdd_export_gram",
                      "lsdd_destroy", "lsdd_set_cycle_precision", "lsdd_trace", "lsdd_trace_get",
-                     "lsdd_set_solve_params", "lsdd_set_graph", "lsdd_segments", "lsdd_setup_batched"):
+                     "lsdd_set_solve_params", "lsdd_set_graph", "lsdd_segments", "lsdd_setup_batched",
+                     "lsdd_level_segments"):
             getattr(L, name).restype = C.c_int
         _LIB = L
     return _LIB
@@ -210,6 +212,15 @@ class Hierarchy:
 
     def set_graph(self, on: bool):
         _check(lib().lsdd_set_graph(self._h, 1 if on else 0))
+
+    def level_segments(self, level: int):
+        """(inst_off list, terminal flags list) of one level."""
+        ns = self.segments()[0]
+        off = np.zeros(ns + 1, dtype=np.int64)
+        term = np.zeros(ns, dtype=np.int32)
+        _check(lib().lsdd_level_segments(self._h, int(level), off.ctypes.data_as(C.POINTER(C.c_int64)),
+                                         term.ctypes.data_as(C.POINTER(C.c_int32))))
+        return off.tolist(), term.tolist()
 
     def segments(self):
         """(n_seg, seg_off as a list)."""

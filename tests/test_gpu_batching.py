@@ -113,38 +113,47 @@ def _batch():
     return [fegen.elasticity_q1(N, nu=nu) for N, nu in ((6, 0.3), (11, 0.45), (8, 0.38))]
 
 
-def test_batched_instances_match_per_instance_oracle(dev):
-    """One union hierarchy over uneven instances: per instance, every level's
-    aggregates and retained modes equal the instance's own oracle hierarchy, and
-    every (instance, right-hand side) solve matches the oracle's PCG."""
+def _check_batch_against_oracle(dev, probs, kw, nrhs_list=(1, 3), seed=21):
+    """Per instance: level count and sizes, aggregates and retained modes on every
+    level where the instance is coarsened, and every (instance, right-hand side)
+    solve, against the instance's own oracle hierarchy."""
     P = _lsdd()
-    probs = _batch()
-    h_ors = [oracle.setup(p, oracle.Params(**BATCH_KW)) for p in probs]
+    h_ors = [oracle.setup(p, oracle.Params(**kw)) for p in probs]
     n_tot = sum(p.n for p in probs)
-    rng = np.random.default_rng(21)
-    B = rng.standard_normal((3, n_tot))
-    with P.Hierarchy.setup_batched(probs, P.Params.default(**BATCH_KW)) as h:
+    B = np.random.default_rng(seed).standard_normal((max(nrhs_list), n_tot))
+    with P.Hierarchy.setup_batched(probs, P.Params.default(**kw)) as h:
         nseg, off = h.segments()
-        assert nseg == 3 and off == list(np.cumsum([0] + [p.n for p in probs]))
+        assert nseg == len(probs) and off == list(np.cumsum([0] + [p.n for p in probs]))
         info = h.info()
-        L = len(h_ors[0].levels)
-        assert all(len(ho.levels) == L for ho in h_ors)
-        assert info["n"] == [sum(ho.levels[l].n for ho in h_ors) for l in range(L)]
-        for l in range(L - 1):
+        depth = [len(ho.levels) for ho in h_ors]
+        assert info["levels"] == max(depth)
+        for l in range(info["levels"]):
+            loff, term = h.level_segments(l)
+            for i, ho in enumerate(h_ors):
+                n_il = ho.levels[l].n if l < depth[i] else 0
+                assert loff[i + 1] - loff[i] == n_il
+                assert term[i] == (1 if l == depth[i] - 1 else 0)
+            if l == info["levels"] - 1:
+                continue
             ex = h.export_level(l)
-            d0 = a0 = 0
-            for ho in h_ors:
+            a0 = 0
+            for i, ho in enumerate(h_ors):
+                if l >= depth[i]:
+                    continue
+                agg = ex["agg_of_dof"][loff[i]:loff[i + 1]]
+                if l == depth[i] - 1:
+                    assert np.all(agg == -1)
+                    continue
                 lv = ho.levels[l]
                 n_agg = len(lv.k)
-                assert np.array_equal(ex["agg_of_dof"][d0:d0 + lv.n] - a0, lv.agg_of_dof)
+                assert np.array_equal(agg - a0, lv.agg_of_dof)
                 assert np.array_equal(ex["k"][a0:a0 + n_agg], lv.k)
-                d0 += lv.n
                 a0 += n_agg
-        for nrhs in (1, 3):
+        for nrhs in nrhs_list:
             X, infos = h.solve(torch.from_numpy(B[:nrhs].copy()).to(dev))
             X = X.cpu().numpy().reshape(nrhs, n_tot)
             for k in range(nrhs):
-                for i, (p, ho) in enumerate(zip(probs, h_ors)):
+                for i, ho in enumerate(h_ors):
                     x_or, inf_or = oracle.pcg(ho, B[k, off[i]:off[i + 1]])
                     f = infos[k * nseg + i]
                     assert f.converged == 1 and abs(f.iters - inf_or.iters) <= 1
@@ -152,10 +161,16 @@ def test_batched_instances_match_per_instance_oracle(dev):
                     assert np.linalg.norm(xi - x_or) <= 1e-10 * np.linalg.norm(x_or)
 
 
-def test_batched_uneven_depths_are_rejected(dev):
-    """An instance that would stop a level earlier than the others is reported."""
-    P = _lsdd()
-    probs = [fegen.elasticity_q1(2, nu=0.3), fegen.elasticity_q1(9, nu=0.3)]
-    with pytest.raises(P.LsddError) as ei:
-        P.Hierarchy.setup_batched(probs, P.Params.default(max_levels=3, tau_const=0.75))
-    assert ei.value.code == 7 and "different depths" in str(ei.value)
+def test_batched_instances_match_per_instance_oracle(dev):
+    """One union hierarchy over uneven instances of the same depth."""
+    _check_batch_against_oracle(dev, _batch(), BATCH_KW)
+
+
+def test_batched_instances_with_their_own_depths(dev):
+    """Paper stopping tests per instance: the instances end their hierarchies on
+    different levels (1, 2 and 3 levels) and are solved there directly."""
+    probs = [fegen.elasticity_q1(N, nu=nu) for N, nu in ((2, 0.3), (20, 0.42), (9, 0.35))]
+    kw = dict(max_levels=3, tau_const=0.75, agg_passes=2, agg_passes_coarse=1)
+    depths = [len(oracle.setup(p, oracle.Params(**kw)).levels) for p in probs]
+    assert depths == [1, 3, 2]
+    _check_batch_against_oracle(dev, probs, kw)
