@@ -280,6 +280,85 @@ __global__ void __launch_bounds__(WG) k_prolong_b(const int32_t* items, const in
     }
 }
 
+// ---------------------------------------------------------------- small overlaps
+// Overlaps with |Omega| <= SMALL_M: the inverse is stored as its packed lower
+// triangle (entry (i, j), j <= i, at i (i + 1) / 2 + j), staged in LDS by one
+// wave per subdomain; lane i forms y_i = sum_j (A_Omega^{-1})_{ij} r_j over all j in
+// ascending order (fixed order) and adds it to x: subdomains of one colour are
+// disjoint, so the update needs no partial sums.
+template <typename T, int NR>
+__global__ void __launch_bounds__(64) k_small_sub(int32_t s0, const int64_t* sub_off, const int32_t* sub_dofs,
+                                                  const int64_t* pk_off, const T* pk, const T* rloc, T* x) {
+    __shared__ T s_a[SMALL_M * (SMALL_M + 1) / 2];
+    __shared__ T s_x[SMALL_M * NR];
+    const int s = s0 + blockIdx.x;
+    const int lane = tid();
+    const int64_t o = sub_off[s];
+    const int m = (int)(sub_off[s + 1] - o);
+    const T* A = pk + pk_off[s];
+    const int np = m * (m + 1) / 2;
+    for (int e = lane; e < np; e += 64) s_a[e] = A[e];
+    for (int e = lane; e < m * NR; e += 64) s_x[e] = rloc[o * NR + e];
+    __syncthreads();
+    if (lane < m) {
+        const int i = lane;
+        const int ri = i * (i + 1) / 2;
+        T y[NR];
+#pragma unroll
+        for (int k = 0; k < NR; ++k) y[k] = 0;
+        for (int j = 0; j < m; ++j) {
+            const T a = s_a[j <= i ? ri + j : j * (j + 1) / 2 + i];
+#pragma unroll
+            for (int k = 0; k < NR; ++k) y[k] += a * s_x[j * NR + k];
+        }
+        T* dst = x + (int64_t)sub_dofs[o + i] * NR;
+#pragma unroll
+        for (int k = 0; k < NR; ++k) dst[k] += y[k];
+    }
+}
+
+// Transfers for aggregates with |omega| <= SMALL_M, one thread per (coarse DOF,
+// right-hand side) for the restriction and per (aggregate entry, right-hand side)
+// for the prolongation.
+template <typename T, int NR>
+__global__ void __launch_bounds__(WG) k_restrict_small(int64_t nc, const int32_t* agg_of_c, const int64_t* agg_ptr,
+                                                       const int32_t* agg_dofs, const int64_t* zoff,
+                                                       const int64_t* coff, const T* Zc, const T* t, T* rc) {
+    for (int64_t e = blockIdx.x * (int64_t)WG + tid(); e < nc * NR; e += (int64_t)gridDim.x * WG) {
+        const int64_t c = e / NR;
+        const int k = (int)(e % NR);
+        const int ag = agg_of_c[c];
+        if (ag < 0) continue;
+        const int64_t a0 = agg_ptr[ag];
+        const int nw = (int)(agg_ptr[ag + 1] - a0);
+        const T* z = Zc + zoff[ag] + (c - coff[ag]) * nw;
+        T acc = 0;
+        for (int a = 0; a < nw; ++a) acc += z[a] * t[(int64_t)agg_dofs[a0 + a] * NR + k];
+        rc[e] = acc;
+    }
+}
+
+template <typename T, int NR>
+__global__ void __launch_bounds__(WG) k_prolong_small(int64_t na, const int32_t* agg_of_p, const int64_t* agg_ptr,
+                                                      const int32_t* agg_dofs, const int64_t* zoff,
+                                                      const int32_t* k, const int64_t* coff, const T* Zc,
+                                                      const T* ec, T* x) {
+    for (int64_t e = blockIdx.x * (int64_t)WG + tid(); e < na * NR; e += (int64_t)gridDim.x * WG) {
+        const int64_t p = e / NR;
+        const int q = (int)(e % NR);
+        const int ag = agg_of_p[p];
+        if (ag < 0) continue;
+        const int64_t a0 = agg_ptr[ag];
+        const int nw = (int)(agg_ptr[ag + 1] - a0);
+        const int kk = k[ag];
+        const T* z = Zc + zoff[ag] + (p - a0);
+        const T* ev = ec + coff[ag] * NR + q;
+        T acc = 0;
+        for (int s = 0; s < kk; ++s) acc += z[(int64_t)s * nw] * ev[(int64_t)s * NR];
+        x[(int64_t)agg_dofs[p] * NR + q] += acc;
+    }
+}
+
 __global__ void k_gather_rhs(int64_t n, int nr, const double* b, int64_t ldb, double* B) {
     for (int64_t e = blockIdx.x * (int64_t)WG + tid(); e < n * NB; e += (int64_t)gridDim.x * WG) {
         const int64_t d = e / NB;
@@ -604,6 +683,44 @@ void launch_pcg_update_p(const SegTable& t, int nr, const int32_t* act, const do
 void launch_pcg_start(int64_t len, const double* b, double* r, double* x, hipStream_t st) {
     hipLaunchKernelGGL(k_pcg_start, dim3(grid_for(len)), dim3(WG), 0, st, len, b, r, x);
 }
+
+template <typename T, int NR>
+void launch_small_sub(int64_t s0, int64_t n_sub, const int64_t* sub_off, const int32_t* sub_dofs,
+                      const int64_t* pk_off, const T* pk, const T* rloc, T* x, hipStream_t st) {
+    if (n_sub <= 0) return;
+    hipLaunchKernelGGL((k_small_sub<T, NR>), dim3((unsigned)n_sub), dim3(64), 0, st, (int32_t)s0, sub_off, sub_dofs,
+                       pk_off, pk, rloc, x);
+}
+
+template <typename T, int NR>
+void launch_restrict_small(int64_t nc, const int32_t* agg_of_c, const int64_t* agg_ptr, const int32_t* agg_dofs,
+                           const int64_t* zoff, const int64_t* coff, const T* Zc, const T* t, T* rc, hipStream_t st) {
+    if (nc <= 0) return;
+    hipLaunchKernelGGL((k_restrict_small<T, NR>), dim3(grid_for(nc * NR)), dim3(WG), 0, st, nc, agg_of_c, agg_ptr,
+                       agg_dofs, zoff, coff, Zc, t, rc);
+}
+
+template <typename T, int NR>
+void launch_prolong_small(int64_t na, const int32_t* agg_of_p, const int64_t* agg_ptr, const int32_t* agg_dofs,
+                          const int64_t* zoff, const int32_t* k, const int64_t* coff, const T* Zc, const T* ec, T* x,
+                          hipStream_t st) {
+    if (na <= 0) return;
+    hipLaunchKernelGGL((k_prolong_small<T, NR>), dim3(grid_for(na * NR)), dim3(WG), 0, st, na, agg_of_p, agg_ptr,
+                       agg_dofs, zoff, k, coff, Zc, ec, x);
+}
+
+#define LSDD_SMALL_INST(T, NR)                                                                                     \
+    template void launch_small_sub<T, NR>(int64_t, int64_t, const int64_t*, const int32_t*, const int64_t*,        \
+                                          const T*, const T*, T*, hipStream_t);                                     \
+    template void launch_restrict_small<T, NR>(int64_t, const int32_t*, const int64_t*, const int32_t*,            \
+                                               const int64_t*, const int64_t*, const T*, const T*, T*, hipStream_t); \
+    template void launch_prolong_small<T, NR>(int64_t, const int32_t*, const int64_t*, const int32_t*,             \
+                                              const int64_t*, const int32_t*, const int64_t*, const T*, const T*,   \
+                                              T*, hipStream_t);
+LSDD_SMALL_INST(double, 1)
+LSDD_SMALL_INST(double, NRB)
+LSDD_SMALL_INST(float, 1)
+LSDD_SMALL_INST(float, NRB)
 
 #define LSDD_BLK_INST(T)                                                                                            \
     template void launch_csr_resid_rows_b<T>(int64_t, const int32_t*, const int64_t*, const int32_t*, const T*,      \

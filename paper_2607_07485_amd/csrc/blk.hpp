@@ -33,6 +33,25 @@ void launch_prolong_b(int64_t n_items, const int32_t* items, const int64_t* agg_
                       const int64_t* zoff, const int32_t* k, const int64_t* coff, const T* Zc, const T* ec, T* x,
                       hipStream_t st);
 
+// ---------------------------------------------------------------- small overlaps (NR = 1 or NRB)
+constexpr int SMALL_M = 64;   // overlaps and aggregates up to this size use the kernels below
+
+// x[Omega_s] += A_Omega_s^{-1} rloc[Omega_s] for the sweep-order subdomains s0 .. s0+n_sub-1
+// (packed lower inverses at pk + pk_off[s]; rloc and x hold NR interleaved vectors)
+template <typename T, int NR>
+void launch_small_sub(int64_t s0, int64_t n_sub, const int64_t* sub_off, const int32_t* sub_dofs,
+                      const int64_t* pk_off, const T* pk, const T* rloc, T* x, hipStream_t st);
+// rc[c] = Z_i[:, c - coff_i]^T t[omega_i] for every coarse DOF c of an aggregate i
+// with agg_of_c[c] = i (agg_of_c[c] < 0: skipped)
+template <typename T, int NR>
+void launch_restrict_small(int64_t nc, const int32_t* agg_of_c, const int64_t* agg_ptr, const int32_t* agg_dofs,
+                           const int64_t* zoff, const int64_t* coff, const T* Zc, const T* t, T* rc, hipStream_t st);
+// x[agg_dofs[p]] += Z_i[p - agg_ptr_i, :] ec[coff_i ..] for aggregate entries p with agg_of_p[p] = i
+template <typename T, int NR>
+void launch_prolong_small(int64_t na, const int32_t* agg_of_p, const int64_t* agg_ptr, const int32_t* agg_dofs,
+                          const int64_t* zoff, const int32_t* k, const int64_t* coff, const T* Zc, const T* ec, T* x,
+                          hipStream_t st);
+
 // B[d * NRB + k] = k < nr ? b[k * ldb + d] : 0 (d < n); and the inverse copy
 void launch_gather_rhs(int64_t n, int32_t nr, const double* b, int64_t ldb, double* B, hipStream_t st);
 void launch_scatter_sol(int64_t n, int32_t nr, const double* X, double* x, int64_t ldx, hipStream_t st);

@@ -791,6 +791,7 @@ __global__ void __launch_bounds__(WG) k_sub_finalize(int64_t r0, int64_t r1, con
 __global__ void k_pack_tiles(const int64_t* sub_ptr, const int64_t* inv_off, const double* inv, const int64_t* tp_off,
                              double* tiles, float* tiles32) {
     const int ag = blockIdx.y;
+    if (tp_off[ag] < 0) return;                   // stored in the small (packed) format
     const int m = (int)(sub_ptr[ag + 1] - sub_ptr[ag]);
     const int nt = (m + 63) / 64;
     const int64_t ntile = (int64_t)nt * (nt + 1) / 2;
@@ -806,6 +807,25 @@ __global__ void k_pack_tiles(const int64_t* sub_ptr, const int64_t* inv_off, con
         double v = (r < m && c < m) ? M[r + (int64_t)c * m] : 0.0;
         tiles[tp_off[ag] + idx] = v;
         if (tiles32) tiles32[tp_off[ag] + idx] = (float)v;
+    }
+}
+
+// Packed lower triangles of the inverses of the aggregates with pk_off[a] >= 0
+// (row-major packed: entry (i, j), j <= i, at i (i + 1) / 2 + j).
+__global__ void k_pack_small(const int64_t* sub_ptr, const int64_t* inv_off, const double* inv,
+                             const int64_t* pk_off, double* pk, float* pk32) {
+    const int ag = blockIdx.x;
+    if (pk_off[ag] < 0) return;
+    const int m = (int)(sub_ptr[ag + 1] - sub_ptr[ag]);
+    const double* M = inv + inv_off[ag];
+    for (int e = tid(); e < m * (m + 1) / 2; e += WG) {
+        int i = (int)((sqrt(8.0 * e + 1.0) - 1.0) * 0.5);
+        while (i * (i + 1) / 2 > e) --i;
+        while ((i + 1) * (i + 2) / 2 <= e) ++i;
+        const int j = e - i * (i + 1) / 2;
+        const double v = M[i + (int64_t)j * m];
+        pk[pk_off[ag] + e] = v;
+        if (pk32) pk32[pk_off[ag] + e] = (float)v;
     }
 }
 
@@ -1078,6 +1098,12 @@ void sub_symv_items(int32_t s, int64_t m, int chl, std::vector<int32_t>& items) 
             items.push_back(I);
             items.push_back(ch);
         }
+}
+
+void launch_pack_small(int32_t n_agg, const int64_t* sub_ptr, const int64_t* inv_off, const double* inv,
+                       const int64_t* pk_off, double* pk, float* pk32, hipStream_t st) {
+    if (n_agg <= 0) return;
+    hipLaunchKernelGGL(k_pack_small, dim3((unsigned)n_agg), dim3(WG), 0, st, sub_ptr, inv_off, inv, pk_off, pk, pk32);
 }
 
 void launch_pack_tiles(int32_t n_agg, const int64_t* sub_ptr, const int64_t* inv_off, const double* inv,

@@ -125,6 +125,9 @@ void launch_sub_finalize(int64_t r0, int64_t r1, const int32_t* pos_sub, const i
 // scratch entries for a subdomain of size m; append its work items (s, tile row, chunk)
 int64_t sub_symv_scratch_len(int64_t m, int chl);
 void sub_symv_items(int32_t s, int64_t m, int chl, std::vector<int32_t>& items);
+// packed lower triangles of the inverses of the aggregates with pk_off[a] >= 0
+void launch_pack_small(int32_t n_agg, const int64_t* sub_ptr, const int64_t* inv_off, const double* inv,
+                       const int64_t* pk_off, double* pk, float* pk32, hipStream_t st);
 void launch_pack_tiles(int32_t n_agg, const int64_t* sub_ptr, const int64_t* inv_off, const double* inv,
                        const int64_t* tp_off, double* tiles, float* tiles32, hipStream_t st);
 // restriction items: (aggregate, first of 16 columns); prolongation items: (aggregate, first of 256 rows)

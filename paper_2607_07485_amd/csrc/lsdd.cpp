@@ -181,6 +181,17 @@ struct Level {
     std::vector<int32_t> sweep;
     std::vector<int64_t> sw_sub_off;
     std::vector<int64_t> color_row0, color_item0;
+    // inside a colour: large overlaps (tiled product) first, then small ones (packed, one wave each)
+    std::vector<int64_t> color_rmid;  // first row of the colour's small overlaps
+    std::vector<int32_t> color_sub0;  // first sweep position of the colour
+    std::vector<int32_t> color_smid;  // first small sweep position of the colour
+    std::vector<double> color_pk;     // packed entries of the colour's small overlaps
+    int64_t* d_sw_pk_off = nullptr;   // packed-inverse offset of each small subdomain (sweep order)
+    double* d_pk = nullptr;
+    float* d_pk32 = nullptr;
+    int32_t* d_agg_of_c = nullptr;    // coarse DOF -> aggregate for small aggregates (-1: large)
+    int32_t* d_agg_of_p = nullptr;    // aggregate entry -> aggregate for small aggregates (-1: large)
+    int64_t n_aggent = 0;             // sum |omega_i|
     std::vector<double> color_m2, color_m, color_nnz;   // sums of |Omega|^2, |Omega|, row nnz per colour
     int64_t* d_sw_sub_off = nullptr;
     int32_t* d_sw_sub_dofs = nullptr;
@@ -804,9 +815,17 @@ std::unique_ptr<Level> coarsen(lsdd_hierarchy* h, Level& lv, const int32_t* agg_
     if (P.precision == 1) lv.d_Zc32 = ar.alloc<float>(lv.zoff[n_agg]);
     launch_z_compact(n_agg, lv.d_agg_ptr, lv.d_k, d_zst_off, d_zst, lv.d_zoff, lv.d_Z, lv.d_Zc, lv.d_Zc32, st);
     {
-        std::vector<int32_t> ri, pi;
+        // aggregates up to SMALL_M DOFs: one thread per coarse DOF / entry; larger ones: work items
+        std::vector<int32_t> ri, pi, aoc(std::max<int64_t>(lv.coff[n_agg], 1), -1),
+            aop(std::max<int64_t>(C.agg_ptr[n_agg], 1), -1);
         for (int32_t i = 0; i < n_agg; ++i) {
             const int32_t nw = (int32_t)(C.agg_ptr[i + 1] - C.agg_ptr[i]);
+            if (nw <= SMALL_M) {
+                for (int64_t c = lv.coff[i]; c < lv.coff[i + 1]; ++c) aoc[c] = i;
+                if (lv.k[i] > 0)
+                    for (int64_t q = C.agg_ptr[i]; q < C.agg_ptr[i + 1]; ++q) aop[q] = i;
+                continue;
+            }
             for (int32_t s0 = 0; s0 < lv.k[i]; s0 += 16) { ri.push_back(i); ri.push_back(s0); }
             if (lv.k[i] > 0)
                 for (int32_t r0 = 0; r0 < nw; r0 += 256) { pi.push_back(i); pi.push_back(r0); }
@@ -815,47 +834,78 @@ std::unique_ptr<Level> coarsen(lsdd_hierarchy* h, Level& lv, const int32_t* agg_
         lv.n_pitems = (int64_t)pi.size() / 2;
         lv.d_ritems = ar.upload(ri, st);
         lv.d_pitems = ar.upload(pi, st);
+        lv.d_agg_of_c = ar.upload(aoc, st);
+        lv.d_agg_of_p = ar.upload(aop, st);
+        lv.n_aggent = C.agg_ptr[n_agg];
     }
     sync(st);
     ar.release(d_zst);
-    // ---- smoother arrays in sweep order
+    // ---- smoother arrays in sweep order: colour-major; inside a colour the large
+    // overlaps (tiled product) come first, then the small ones (|Omega| <= SMALL_M);
+    // subdomains of one colour commute, so this order gives the same smoother
+    auto is_small = [&](int32_t i) { return C.sub_ptr[i + 1] - C.sub_ptr[i] <= SMALL_M; };
     lv.sweep.resize(n_agg);
     for (int32_t i = 0; i < n_agg; ++i) lv.sweep[i] = i;
-    std::stable_sort(lv.sweep.begin(), lv.sweep.end(),
-                     [&](int32_t a, int32_t b) { return lv.colors[a] < lv.colors[b]; });
+    std::stable_sort(lv.sweep.begin(), lv.sweep.end(), [&](int32_t a, int32_t b) {
+        if (lv.colors[a] != lv.colors[b]) return lv.colors[a] < lv.colors[b];
+        return (int)is_small(a) < (int)is_small(b);
+    });
     std::vector<int32_t> sw_dofs;
-    std::vector<int64_t> tp_agg(n_agg + 1, 0), sw_tp_off(n_agg);
+    std::vector<int64_t> tp_agg(n_agg, -1), pk_agg(n_agg, -1), sw_tp_off(n_agg, -1), sw_pk_off(n_agg, -1);
+    int64_t tiles = 0, pks = 0;
     for (int32_t i = 0; i < n_agg; ++i) {
-        int64_t nt = (C.sub_ptr[i + 1] - C.sub_ptr[i] + 63) / 64;
-        tp_agg[i + 1] = tp_agg[i] + nt * (nt + 1) / 2 * 4096;
+        const int64_t m = C.sub_ptr[i + 1] - C.sub_ptr[i];
+        if (is_small(i)) {
+            pk_agg[i] = pks;
+            pks += m * (m + 1) / 2;
+        } else {
+            const int64_t nt = (m + 63) / 64;
+            tp_agg[i] = tiles;
+            tiles += nt * (nt + 1) / 2 * 4096;
+        }
     }
-    lv.tiles_len = tp_agg[n_agg];
+    lv.tiles_len = tiles;
     std::vector<int32_t> items;
     lv.sw_sub_off.assign(1, 0);
     lv.color_row0.assign(lv.n_colors + 1, 0);
+    lv.color_rmid.assign(lv.n_colors, 0);
+    lv.color_sub0.assign(lv.n_colors + 1, 0);
+    lv.color_smid.assign(lv.n_colors, 0);
     lv.color_item0.assign(lv.n_colors + 1, 0);
+    for (int32_t c = 0; c < lv.n_colors; ++c) lv.color_smid[c] = -1;
     for (int32_t s = 0; s < n_agg; ++s) {
         int32_t i = lv.sweep[s];
+        int32_t c = lv.colors[i];
+        if (is_small(i) && lv.color_smid[c] < 0) {
+            lv.color_smid[c] = s;
+            lv.color_rmid[c] = (int64_t)sw_dofs.size();
+        }
         sw_dofs.insert(sw_dofs.end(), C.sub_dofs.begin() + C.sub_ptr[i], C.sub_dofs.begin() + C.sub_ptr[i + 1]);
         lv.sw_sub_off.push_back((int64_t)sw_dofs.size());
         sw_tp_off[s] = tp_agg[i];
-        int32_t c = lv.colors[i];
+        sw_pk_off[s] = pk_agg[i];
         lv.color_row0[c + 1] = (int64_t)sw_dofs.size();
+        lv.color_sub0[c + 1] = s + 1;
     }
-    // work items per colour: (subdomain, tile row, chunk), longest chunks first
+    for (int32_t c = 0; c < lv.n_colors; ++c)
+        if (lv.color_smid[c] < 0) {            // no small overlap in this colour
+            lv.color_smid[c] = lv.color_sub0[c + 1];
+            lv.color_rmid[c] = lv.color_row0[c + 1];
+        }
+    // work items of the large overlaps per colour: (subdomain, tile row, chunk), longest chunks first
     for (int32_t c = 0; c < lv.n_colors; ++c) {
         std::vector<int32_t> subs;
-        for (int32_t s = 0; s < n_agg; ++s)
-            if (lv.colors[lv.sweep[s]] == c) subs.push_back(s);
+        for (int32_t s = lv.color_sub0[c]; s < lv.color_smid[c]; ++s) subs.push_back(s);
         append_symv_items(lv.sw_sub_off, subs, lv.chl, items);
         lv.color_item0[c + 1] = (int64_t)items.size() / 3;
     }
     lv.color_m2.assign(lv.n_colors, 0.0);
     lv.color_m.assign(lv.n_colors, 0.0);
     lv.color_nnz.assign(lv.n_colors, 0.0);
+    lv.color_pk.assign(lv.n_colors, 0.0);
     for (int32_t i = 0; i < n_agg; ++i) {
         double m = (double)(C.sub_ptr[i + 1] - C.sub_ptr[i]);
-        lv.color_m2[lv.colors[i]] += m * (m + 1.0) / 2.0;     // entries of the symmetric inverse
+        (is_small(i) ? lv.color_pk : lv.color_m2)[lv.colors[i]] += m * (m + 1.0) / 2.0;   // inverse entries
         lv.color_m[lv.colors[i]] += m;
         for (int64_t q = C.sub_ptr[i]; q < C.sub_ptr[i + 1]; ++q) {
             int32_t d = C.sub_dofs[q];
@@ -863,9 +913,10 @@ std::unique_ptr<Level> coarsen(lsdd_hierarchy* h, Level& lv, const int32_t* agg_
         }
     }
     for (int32_t c = 0; c < lv.n_colors; ++c)
-        vlog("  colour %d: %lld DOFs, %lld items, %.1f MB of inverse tiles", c,
+        vlog("  colour %d: %lld DOFs, %lld items, %.1f MB of inverse tiles; %d small overlaps, %.1f MB packed", c,
              (long long)(lv.color_row0[c + 1] - lv.color_row0[c]),
-             (long long)(lv.color_item0[c + 1] - lv.color_item0[c]), lv.color_m2[c] * 8e-6);
+             (long long)(lv.color_item0[c + 1] - lv.color_item0[c]), lv.color_m2[c] * 8e-6,
+             lv.color_sub0[c + 1] - lv.color_smid[c], lv.color_pk[c] * 8e-6);
     lv.d_sw_sub_off = ar.upload(lv.sw_sub_off, st);
     lv.d_sw_sub_dofs = ar.upload(sw_dofs, st);
     lv.d_sw_tp_off = ar.upload(sw_tp_off, st);
@@ -875,7 +926,8 @@ std::unique_ptr<Level> coarsen(lsdd_hierarchy* h, Level& lv, const int32_t* agg_
         std::vector<int64_t> scr_off(n_agg + 1, 0);
         for (int32_t s = 0; s < n_agg; ++s) {
             for (int64_t q = lv.sw_sub_off[s]; q < lv.sw_sub_off[s + 1]; ++q) pos_sub[q] = s;
-            scr_off[s + 1] = scr_off[s] + sub_symv_scratch_len(lv.sw_sub_off[s + 1] - lv.sw_sub_off[s], lv.chl);
+            const int64_t m = lv.sw_sub_off[s + 1] - lv.sw_sub_off[s];
+            scr_off[s + 1] = scr_off[s] + (m <= SMALL_M ? 0 : sub_symv_scratch_len(m, lv.chl));
         }
         lv.d_pos_sub = ar.upload(pos_sub, st);
         lv.d_scr_off = ar.upload(scr_off, st);
@@ -885,12 +937,18 @@ std::unique_ptr<Level> coarsen(lsdd_hierarchy* h, Level& lv, const int32_t* agg_
     }
     {
         int64_t* d_tp_agg = ar.upload(tp_agg, st);
-        lv.d_tiles = ar.alloc<double>(lv.tiles_len);
-        if (P.precision == 1) lv.d_tiles32 = ar.alloc<float>(lv.tiles_len);
+        int64_t* d_pk_agg = ar.upload(pk_agg, st);
+        lv.d_sw_pk_off = ar.upload(sw_pk_off, st);
+        lv.d_tiles = ar.alloc<double>(std::max<int64_t>(lv.tiles_len, 1));
+        if (P.precision == 1) lv.d_tiles32 = ar.alloc<float>(std::max<int64_t>(lv.tiles_len, 1));
+        lv.d_pk = ar.alloc<double>(std::max<int64_t>(pks, 1));
+        if (P.precision == 1) lv.d_pk32 = ar.alloc<float>(std::max<int64_t>(pks, 1));
         launch_pack_tiles(n_agg, d_sub_ptr, d_inv_off, lv.d_inv, d_tp_agg, lv.d_tiles, lv.d_tiles32, st);
+        launch_pack_small(n_agg, d_sub_ptr, d_inv_off, lv.d_inv, d_pk_agg, lv.d_pk, lv.d_pk32, st);
         HIPCHK(hipGetLastError());
         sync(st);
         ar.release(d_tp_agg);
+        ar.release(d_pk_agg);
         ar.release(lv.d_inv);
         lv.d_inv = nullptr;
     }
@@ -1008,6 +1066,7 @@ struct LvOps<double> {
     static const double* val(Level& l) { return l.d_val; }
     static const double* Z(Level& l) { return l.d_Zc; }
     static const double* inv(Level& l) { return l.d_tiles; }
+    static const double* pk(Level& l) { return l.d_pk; }
 };
 template <>
 struct LvOps<float> {
@@ -1015,6 +1074,7 @@ struct LvOps<float> {
     static const float* val(Level& l) { return l.d_val32; }
     static const float* Z(Level& l) { return l.d_Zc32; }
     static const float* inv(Level& l) { return l.d_tiles32; }
+    static const float* pk(Level& l) { return l.d_pk32; }
 };
 
 // Cycle kernels for NR = 1 (single vectors) or NR = NRB (interleaved blocks).
@@ -1039,7 +1099,12 @@ struct Cyc {
         if constexpr (NR == 1) launch_sub_finalize<T>(r0, r1, pos, sub_off, scr_off, scr, dofs, x, acc, chl, fl, st);
         else launch_sub_finalize_b<T>(r0, r1, pos, sub_off, scr_off, scr, dofs, x, acc, chl, fl, st);
     }
+    static void small(Level& lv, int64_t s0, int64_t n_sub, const T* pk, const T* rloc, T* x, hipStream_t st) {
+        launch_small_sub<T, NR>(s0, n_sub, lv.d_sw_sub_off, lv.d_sw_sub_dofs, lv.d_sw_pk_off, pk, rloc, x, st);
+    }
     static void restrict_(Level& lv, const T* Z, const T* t, T* rc, hipStream_t st) {
+        launch_restrict_small<T, NR>(lv.coff.back(), lv.d_agg_of_c, lv.d_agg_ptr, lv.d_agg_dofs, lv.d_zoff, lv.d_coff,
+                                     Z, t, rc, st);
         if constexpr (NR == 1)
             launch_restrict<T>(lv.n_ritems, lv.d_ritems, lv.d_agg_ptr, lv.d_agg_dofs, lv.d_zoff, lv.d_k, lv.d_coff, Z,
                                t, rc, st);
@@ -1048,6 +1113,8 @@ struct Cyc {
                                  Z, t, rc, st);
     }
     static void prolong(Level& lv, const T* Z, const T* ec, T* x, hipStream_t st) {
+        launch_prolong_small<T, NR>(lv.n_aggent, lv.d_agg_of_p, lv.d_agg_ptr, lv.d_agg_dofs, lv.d_zoff, lv.d_k,
+                                    lv.d_coff, Z, ec, x, st);
         if constexpr (NR == 1)
             launch_prolong<T>(lv.n_pitems, lv.d_pitems, lv.d_agg_ptr, lv.d_agg_dofs, lv.d_zoff, lv.d_k, lv.d_coff, Z,
                               ec, x, st);
@@ -1065,24 +1132,31 @@ void sweep(lsdd_hierarchy* h, Level& lv, const T* r, T* x, bool forward, bool x_
     const double w = (double)sizeof(T), wv = w * NR;
     for (int32_t cc = 0; cc < lv.n_colors; ++cc) {
         int32_t c = forward ? cc : lv.n_colors - 1 - cc;
-        int64_t r0 = lv.color_row0[c], r1 = lv.color_row0[c + 1];
-        int64_t i0 = lv.color_item0[c], i1 = lv.color_item0[c + 1];
-        if (i1 == i0) continue;
+        const int64_t r0 = lv.color_row0[c], r1 = lv.color_row0[c + 1], rm = lv.color_rmid[c];
+        const int64_t i0 = lv.color_item0[c], i1 = lv.color_item0[c + 1];
+        const int64_t s0 = lv.color_smid[c], ns = lv.color_sub0[c + 1] - lv.color_smid[c];
+        if (r1 == r0) continue;
         const bool xz = x_zero_first && cc == 0;
         const double rb = lv.color_m[c] * (4 + 8 + 3 * wv) + (xz ? 0.0 : lv.color_nnz[c] * (4 + w));
         traced(h, "csr_resid_rows", rb, [&] {
             C::resid_rows(r1 - r0, lv.d_sw_sub_dofs + r0, lv, O::val(lv), x, r, v.rloc + r0 * NR, xz, h->st);
         });
-        const double gb = lv.color_m2[c] * w + lv.color_m[c] * (4 + 3 * wv);
-        traced(h, "sub_symv", gb, [&] {
-            C::symv(i1 - i0, lv.d_items + 3 * i0, lv.d_sw_sub_off, lv.d_sw_tp_off, O::inv(lv), v.rloc, lv.d_scr_off,
-                    v.scr, lv.chl, h->st);
-        });
-        const double fb = lv.color_scr[c] * wv + lv.color_m[c] * (8 + 2 * wv);
-        traced(h, "sub_finalize", fb, [&] {
-            C::finalize(r0, r1, lv.d_pos_sub, lv.d_sw_sub_off, lv.d_scr_off, v.scr, lv.d_sw_sub_dofs, x, true, lv.chl,
-                        lv.fl, h->st);
-        });
+        if (i1 > i0) {
+            const double gb = lv.color_m2[c] * w + (double)(rm - r0) * (4 + 3 * wv);
+            traced(h, "sub_symv", gb, [&] {
+                C::symv(i1 - i0, lv.d_items + 3 * i0, lv.d_sw_sub_off, lv.d_sw_tp_off, O::inv(lv), v.rloc,
+                        lv.d_scr_off, v.scr, lv.chl, h->st);
+            });
+            const double fb = lv.color_scr[c] * wv + (double)(rm - r0) * (8 + 2 * wv);
+            traced(h, "sub_finalize", fb, [&] {
+                C::finalize(r0, rm, lv.d_pos_sub, lv.d_sw_sub_off, lv.d_scr_off, v.scr, lv.d_sw_sub_dofs, x, true,
+                            lv.chl, lv.fl, h->st);
+            });
+        }
+        if (ns > 0) {
+            const double sb = lv.color_pk[c] * w + (double)(r1 - rm) * (4 + 3 * wv);
+            traced(h, "small_sub", sb, [&] { C::small(lv, s0, ns, O::pk(lv), v.rloc, x, h->st); });
+        }
     }
 }
 
