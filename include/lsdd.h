@@ -184,10 +184,24 @@ lsdd_status lsdd_segments(const lsdd_hierarchy* h, int32_t* n_seg, int64_t* seg_
  *             A_l is solved directly there; it owns no aggregate on level l) */
 lsdd_status lsdd_level_segments(const lsdd_hierarchy* h, int32_t level, int64_t* inst_off, int32_t* terminal);
 
+/* Autotuner: on this hierarchy, time every candidate of the per-level launch
+ * shapes with HIP events (three runs after a warm-up, on the level's own
+ * operators) and keep the fastest: CSR lanes per row of the residual kernel (16 or
+ * 64 for single vectors; 16, 32 or 64 for blocks), tiles per work item of the
+ * tiled subdomain product of the large overlaps (2, 4 or 8) and threads per DOF of
+ * its finalize (8 or 32).  block != 0 tunes the shapes of the 8-right-hand-side
+ * blocks, 0 those of single vectors, for the current cycle precision.  The choice
+ * changes only the summation order of the sums involved. */
+lsdd_status lsdd_autotune(lsdd_hierarchy* h, int32_t block, void* hip_stream);
+
+/* Launch shapes of level l (host int32[4]): CSR lanes per row for single vectors,
+ * for blocks, tiles per work item, finalize threads per DOF. */
+lsdd_status lsdd_level_tuning(const lsdd_hierarchy* h, int32_t level, int32_t* out);
+
 /* Per-kernel timing: on != 0 clears the counters and records a pair of HIP
  * events on the solve stream around every launch of the traced kernel classes
- * (csr_resid_rows, sub_symv, sub_finalize, csr_spmv, restrict, prolong,
- * coarse_symv, pcg_spmv); on = 0 stops recording.  lsdd_trace_get reads class idx
+ * (csr_resid_rows, sub_symv, sub_finalize, small_sub, csr_spmv, restrict,
+ * prolong, coarse_symv, pcg_spmv); on = 0 stops recording.  lsdd_trace_get reads class idx
  * (0-based; LSDD_E_INVAL past the end): name (host char[name_len]), launches,
  * summed event time in ms and summed algorithmic bytes of those launches (the
  * bytes each launch must move at minimum: matrix entries, indices and vector

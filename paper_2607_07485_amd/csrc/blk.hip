@@ -560,6 +560,9 @@ void launch_csr_resid_rows_b(int64_t nrows, const int32_t* rows, const int64_t* 
     if (lanes >= 64)
         hipLaunchKernelGGL((k_csr_resid_rows_b<T, 64>), dim3(grid_for(nrows * 64)), dim3(WG), 0, st, nrows, rows,
                            rowptr, col, val, x, r, out, x_zero ? 1 : 0);
+    else if (lanes >= 32)
+        hipLaunchKernelGGL((k_csr_resid_rows_b<T, 32>), dim3(grid_for(nrows * 32)), dim3(WG), 0, st, nrows, rows,
+                           rowptr, col, val, x, r, out, x_zero ? 1 : 0);
     else
         hipLaunchKernelGGL((k_csr_resid_rows_b<T, 16>), dim3(grid_for(nrows * 16)), dim3(WG), 0, st, nrows, rows,
                            rowptr, col, val, x, r, out, x_zero ? 1 : 0);
@@ -571,6 +574,9 @@ void launch_csr_spmv_b(int64_t n, const int64_t* rowptr, const int32_t* col, con
     if (n <= 0) return;
     if (lanes >= 64)
         hipLaunchKernelGGL((k_csr_spmv_b<T, 64>), dim3(grid_for(n * 64)), dim3(WG), 0, st, n, rowptr, col, val, x, y,
+                           r_minus);
+    else if (lanes >= 32)
+        hipLaunchKernelGGL((k_csr_spmv_b<T, 32>), dim3(grid_for(n * 32)), dim3(WG), 0, st, n, rowptr, col, val, x, y,
                            r_minus);
     else
         hipLaunchKernelGGL((k_csr_spmv_b<T, 16>), dim3(grid_for(n * 16)), dim3(WG), 0, st, n, rowptr, col, val, x, y,

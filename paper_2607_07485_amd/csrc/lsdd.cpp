@@ -144,7 +144,8 @@ struct Level {
     double* d_blocks = nullptr;
     // assembled operator
     Csr pat;
-    int lanes = 16;                    // CSR lanes per row (64 for long coarse rows)
+    int lanes = 16;                    // CSR lanes per row, single vectors (16 or 64)
+    int lanes_b = 32;                  // CSR lanes per row, blocks of NRB vectors (16, 32 or 64)
     int chl = SUB_MAX_CHUNK;           // tiles per subdomain-kernel work item
     int fl = 8;                        // threads per DOF in the subdomain finalize
     int64_t* d_rowptr = nullptr;
@@ -205,6 +206,7 @@ struct Level {
     std::vector<int32_t> term;        // instance ids
     int64_t term_len = 0;             // DOFs in terminal blocks (entries, instance order)
     int64_t c_scr_len = 0;            // partial-sum entries of the terminal product
+    int c_chl = SUB_MAX_CHUNK;        // tiles per work item of the terminal product
     double c_entries = 0.0;           // sum n_i (n_i + 1) / 2 over the blocks
     int64_t* c_sub_off = nullptr;     // entry ranges of the blocks
     int64_t* c_tp_off = nullptr;
@@ -329,6 +331,7 @@ void assemble_operator(lsdd_hierarchy* h, Level& lv) {
     lv.pat = assembled_pattern(lv.n, lv.el);
     lv.nnz = (int64_t)lv.pat.idx.size();
     lv.lanes = (lv.nnz > 96 * lv.n) ? 64 : 16;
+    lv.lanes_b = (lv.nnz > 40 * lv.n) ? 64 : 32;
     lv.d_rowptr = h->arena.upload(lv.pat.ptr, h->st);
     lv.d_col = h->arena.upload(lv.pat.idx, h->st);
     lv.d_val = h->arena.alloc<double>(lv.nnz);
@@ -436,7 +439,7 @@ void make_terminal(lsdd_hierarchy* h, Level& lv, const std::vector<int32_t>& ter
         tp_off[q] = tiles;
         const int64_t nt = (ni + 63) / 64;
         tiles += nt * (nt + 1) / 2 * 4096;
-        scr_off[q + 1] = scr_off[q] + sub_symv_scratch_len(ni, lv.chl);
+        scr_off[q + 1] = scr_off[q] + sub_symv_scratch_len(ni, lv.c_chl);
         lv.c_entries += (double)ni * (ni + 1) / 2.0;
         for (int64_t d = a; d < a + ni; ++d) {
             dofs.push_back((int32_t)d);
@@ -474,7 +477,7 @@ void make_terminal(lsdd_hierarchy* h, Level& lv, const std::vector<int32_t>& ter
     lv.c_dofs = identity ? nullptr : ar.upload(dofs, h->st);
     std::vector<int32_t> subs(nb), items;
     for (int32_t q = 0; q < nb; ++q) subs[q] = q;
-    append_symv_items(sub_off, subs, lv.chl, items);
+    append_symv_items(sub_off, subs, lv.c_chl, items);
     lv.c_items = ar.upload(items, h->st);
     lv.c_nitems = (int64_t)items.size() / 3;
     lv.c_tiles = ar.alloc<double>(tiles);
@@ -1083,11 +1086,11 @@ struct Cyc {
     static void resid_rows(int64_t nrows, const int32_t* rows, Level& lv, const T* val, const T* x, const T* r, T* out,
                            bool xz, hipStream_t st) {
         if constexpr (NR == 1) launch_csr_resid_rows<T>(nrows, rows, lv.d_rowptr, lv.d_col, val, x, r, out, xz, lv.lanes, st);
-        else launch_csr_resid_rows_b<T>(nrows, rows, lv.d_rowptr, lv.d_col, val, x, r, out, xz, lv.lanes, st);
+        else launch_csr_resid_rows_b<T>(nrows, rows, lv.d_rowptr, lv.d_col, val, x, r, out, xz, lv.lanes_b, st);
     }
     static void spmv(Level& lv, const T* val, const T* x, T* y, const T* r_minus, hipStream_t st) {
         if constexpr (NR == 1) launch_csr_spmv<T>(lv.n, lv.d_rowptr, lv.d_col, val, x, y, r_minus, lv.lanes, st);
-        else launch_csr_spmv_b<T>(lv.n, lv.d_rowptr, lv.d_col, val, x, y, r_minus, lv.lanes, st);
+        else launch_csr_spmv_b<T>(lv.n, lv.d_rowptr, lv.d_col, val, x, y, r_minus, lv.lanes_b, st);
     }
     static void symv(int64_t n_items, const int32_t* items, const int64_t* sub_off, const int64_t* tp_off,
                      const T* tiles, const T* rloc, const int64_t* scr_off, T* scr, int chl, hipStream_t st) {
@@ -1175,10 +1178,11 @@ void terminal_solve(lsdd_hierarchy* h, Level& lv, const double* r, double* x) {
     }
     const double nb = lv.c_entries * 8.0 + 2.0 * lv.term_len * 8.0 * NR;
     traced(h, "coarse_symv", nb, [&] {
-        CD::symv(lv.c_nitems, lv.c_items, lv.c_sub_off, lv.c_tp_off, lv.c_tiles, rr, lv.c_scr_off, v.scr, lv.chl,
+        CD::symv(lv.c_nitems, lv.c_items, lv.c_sub_off, lv.c_tp_off, lv.c_tiles, rr, lv.c_scr_off, v.scr, lv.c_chl,
                  h->st);
     });
-    CD::finalize(0, lv.term_len, lv.c_pos, lv.c_sub_off, lv.c_scr_off, v.scr, lv.c_dofs, x, false, lv.chl, 32, h->st);
+    CD::finalize(0, lv.term_len, lv.c_pos, lv.c_sub_off, lv.c_scr_off, v.scr, lv.c_dofs, x, false, lv.c_chl, 32,
+                 h->st);
 }
 
 template <typename T, int NR>
@@ -1363,6 +1367,129 @@ bool pcg_run(lsdd_hierarchy* h) {
     }
     HIPCHK(hipGetLastError());
     return breakdown;
+}
+
+// ---------------------------------------------------------------- autotuner
+
+// Rebuild the work items and the partial-sum layout of the tiled subdomain
+// product of a level for `chl` tiles per item.
+void set_chunk(lsdd_hierarchy* h, Level& lv, int chl) {
+    Arena& ar = h->arena;
+    const int32_t n_sub = (int32_t)lv.sw_sub_off.size() - 1;
+    lv.chl = chl;
+    std::vector<int32_t> items;
+    lv.color_item0.assign(lv.n_colors + 1, 0);
+    for (int32_t c = 0; c < lv.n_colors; ++c) {
+        std::vector<int32_t> subs;
+        for (int32_t q = lv.color_sub0[c]; q < lv.color_smid[c]; ++q) subs.push_back(q);
+        append_symv_items(lv.sw_sub_off, subs, chl, items);
+        lv.color_item0[c + 1] = (int64_t)items.size() / 3;
+    }
+    std::vector<int64_t> scr_off(n_sub + 1, 0);
+    lv.color_scr.assign(lv.n_colors, 0.0);
+    for (int32_t q = 0; q < n_sub; ++q) {
+        const int64_t m = lv.sw_sub_off[q + 1] - lv.sw_sub_off[q];
+        scr_off[q + 1] = scr_off[q] + (m <= SMALL_M ? 0 : sub_symv_scratch_len(m, chl));
+        lv.color_scr[lv.colors[lv.sweep[q]]] += (double)(scr_off[q + 1] - scr_off[q]);
+    }
+    ar.release(lv.d_items);
+    ar.release(lv.d_scr_off);
+    lv.d_items = ar.upload(items, h->st);
+    lv.d_scr_off = ar.upload(scr_off, h->st);
+    const int64_t need = std::max<int64_t>({scr_off[n_sub], lv.c_scr_len, 1});
+    if (need > std::max<int64_t>({lv.scr_len, lv.c_scr_len, 1})) {
+        for (int b = 0; b < 2; ++b) {
+            const int64_t w = b ? NRB : 1;
+            if (lv.v64[b].scr) {
+                ar.release(lv.v64[b].scr);
+                lv.v64[b].scr = ar.alloc<double>(need * w);
+            }
+            if (lv.v32[b].scr) {
+                ar.release(lv.v32[b].scr);
+                lv.v32[b].scr = ar.alloc<float>(need * w);
+            }
+        }
+    }
+    lv.scr_len = scr_off[n_sub];
+    sync(h->st);
+}
+
+template <class F>
+double time_ms(lsdd_hierarchy* h, F&& fn, int reps = 3) {
+    fn();
+    hipEvent_t a, b;
+    HIPCHK(hipEventCreate(&a));
+    HIPCHK(hipEventCreate(&b));
+    HIPCHK(hipEventRecord(a, h->st));
+    for (int r = 0; r < reps; ++r) fn();
+    HIPCHK(hipEventRecord(b, h->st));
+    HIPCHK(hipEventSynchronize(b));
+    float ms = 0.0f;
+    HIPCHK(hipEventElapsedTime(&ms, a, b));
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    return ms / reps;
+}
+
+// Time the candidates of every per-level launch shape on the level's own data
+// and keep the fastest.  Values in the work vectors are irrelevant (zeroed).
+template <typename T, int NR>
+void autotune_levels(lsdd_hierarchy* h) {
+    using O = LvOps<T>;
+    using C = Cyc<T, NR>;
+    constexpr int b = NR > 1 ? 1 : 0;
+    for (auto& lp : h->L) {
+        Level& lv = *lp;
+        if (lv.coarsest) continue;
+        VecSet<T>& v = O::v(lv, b);
+        launch_zero<T>(lv.n * NR, v.r, h->st);
+        launch_zero<T>(lv.n * NR, v.x, h->st);
+        int& lanes = NR > 1 ? lv.lanes_b : lv.lanes;
+        const std::vector<int> lane_c = NR > 1 ? std::vector<int>{16, 32, 64} : std::vector<int>{16, 64};
+        double best = 1e300;
+        int pick = lanes;
+        for (int L : lane_c) {
+            lanes = L;
+            const double ms = time_ms(h, [&] {
+                for (int32_t c = 0; c < lv.n_colors; ++c)
+                    C::resid_rows(lv.color_row0[c + 1] - lv.color_row0[c], lv.d_sw_sub_dofs + lv.color_row0[c], lv,
+                                  O::val(lv), v.x, v.r, v.rloc + lv.color_row0[c] * NR, false, h->st);
+            });
+            vlog("autotune level %d: CSR lanes %d: %.3f ms", lv.level, L, ms);
+            if (ms < best) best = ms, pick = L;
+        }
+        lanes = pick;
+        if (lv.color_item0.back() == 0) continue;   // no large overlap on this level
+        auto run_large = [&] {
+            for (int32_t c = 0; c < lv.n_colors; ++c) {
+                const int64_t i0 = lv.color_item0[c], i1 = lv.color_item0[c + 1];
+                if (i1 == i0) continue;
+                C::symv(i1 - i0, lv.d_items + 3 * i0, lv.d_sw_sub_off, lv.d_sw_tp_off, O::inv(lv), v.rloc,
+                        lv.d_scr_off, v.scr, lv.chl, h->st);
+                C::finalize(lv.color_row0[c], lv.color_rmid[c], lv.d_pos_sub, lv.d_sw_sub_off, lv.d_scr_off, v.scr,
+                            lv.d_sw_sub_dofs, v.x, true, lv.chl, lv.fl, h->st);
+            }
+        };
+        best = 1e300;
+        int pick_chl = lv.chl;
+        for (int chl : {2, 4, 8}) {
+            set_chunk(h, lv, chl);
+            const double ms = time_ms(h, run_large);
+            vlog("autotune level %d: %d tiles per item: %.3f ms", lv.level, chl, ms);
+            if (ms < best) best = ms, pick_chl = chl;
+        }
+        set_chunk(h, lv, pick_chl);
+        best = 1e300;
+        int pick_fl = lv.fl;
+        for (int fl : {8, 32}) {
+            lv.fl = fl;
+            const double ms = time_ms(h, run_large);
+            vlog("autotune level %d: finalize threads per DOF %d: %.3f ms", lv.level, fl, ms);
+            if (ms < best) best = ms, pick_fl = fl;
+        }
+        lv.fl = pick_fl;
+    }
+    sync(h->st);
 }
 
 // ---------------------------------------------------------------- setup driver
@@ -1822,6 +1949,39 @@ lsdd_status lsdd_segments(const lsdd_hierarchy* h, int32_t* n_seg, int64_t* seg_
     if (!h) throw Error(LSDD_E_INVAL, "NULL hierarchy");
     if (n_seg) *n_seg = h->seg.n_seg;
     if (seg_off) std::copy(h->seg_off.begin(), h->seg_off.end(), seg_off);
+    return LSDD_OK;
+    ABI_END
+}
+
+lsdd_status lsdd_autotune(lsdd_hierarchy* h, int32_t block, void* hip_stream) {
+    ABI_BEGIN
+    if (!h) throw Error(LSDD_E_INVAL, "NULL hierarchy");
+    h->st = (hipStream_t)hip_stream;
+    if (block) {
+        if (!h->pb[1].B) {
+            ensure_block_vectors(h);
+            alloc_pcg(h, 1);
+        }
+        if (h->cycle_prec == 1) autotune_levels<float, NRB>(h);
+        else autotune_levels<double, NRB>(h);
+    } else {
+        if (h->cycle_prec == 1) autotune_levels<float, 1>(h);
+        else autotune_levels<double, 1>(h);
+    }
+    reset_graphs(h);
+    HIPCHK(hipGetLastError());
+    return LSDD_OK;
+    ABI_END
+}
+
+lsdd_status lsdd_level_tuning(const lsdd_hierarchy* h, int32_t level, int32_t* out) {
+    ABI_BEGIN
+    if (!h || !out || level < 0 || level >= (int32_t)h->L.size()) throw Error(LSDD_E_INVAL, "bad argument");
+    const Level& lv = *h->L[level];
+    out[0] = lv.lanes;
+    out[1] = lv.lanes_b;
+    out[2] = lv.chl;
+    out[3] = lv.fl;
     return LSDD_OK;
     ABI_END
 }

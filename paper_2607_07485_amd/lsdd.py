@@ -85,12 +85,14 @@ def lib():
                                          C.POINTER(Params), _P, C.POINTER(_P)]
         L.lsdd_segments.argtypes = [_P, i32p, i64p]
         L.lsdd_level_segments.argtypes = [_P, C.c_int32, i64p, i32p]
+        L.lsdd_autotune.argtypes = [_P, C.c_int32, _P]
+        L.lsdd_level_tuning.argtypes = [_P, C.c_int32, i32p]
         L.lsdd_set_allocator.restype = None
         for name in ("lsdd_setup_elements", "lsdd_setup_gram_csr", "lsdd_solve", "lsdd_vcycle", "lsdd_apply",
                      "lsdd_hierarchy_info", "lsdd_level_sizes", "lsdd_export_level", "lsdd_export_gram",
                      "lsdd_destroy", "lsdd_set_cycle_precision", "lsdd_trace", "lsdd_trace_get",
                      "lsdd_set_solve_params", "lsdd_set_graph", "lsdd_segments", "lsdd_setup_batched",
-                     "lsdd_level_segments"):
+                     "lsdd_level_segments", "lsdd_autotune", "lsdd_level_tuning"):
             getattr(L, name).restype = C.c_int
         _LIB = L
     return _LIB
@@ -221,6 +223,16 @@ class Hierarchy:
         _check(lib().lsdd_level_segments(self._h, int(level), off.ctypes.data_as(C.POINTER(C.c_int64)),
                                          term.ctypes.data_as(C.POINTER(C.c_int32))))
         return off.tolist(), term.tolist()
+
+    def autotune(self, block: bool = False):
+        """lsdd_autotune; returns the chosen shapes per level (lsdd_level_tuning)."""
+        _check(lib().lsdd_autotune(self._h, 1 if block else 0, _stream()))
+        return [self.level_tuning(l) for l in range(self.info()["levels"])]
+
+    def level_tuning(self, level: int):
+        out = np.zeros(4, dtype=np.int32)
+        _check(lib().lsdd_level_tuning(self._h, int(level), out.ctypes.data_as(C.POINTER(C.c_int32))))
+        return dict(lanes=int(out[0]), lanes_block=int(out[1]), tiles_per_item=int(out[2]), finalize_threads=int(out[3]))
 
     def segments(self):
         """(n_seg, seg_off as a list)."""

@@ -174,3 +174,29 @@ def test_batched_instances_with_their_own_depths(dev):
     depths = [len(oracle.setup(p, oracle.Params(**kw)).levels) for p in probs]
     assert depths == [1, 3, 2]
     _check_batch_against_oracle(dev, probs, kw)
+
+
+def test_autotuned_shapes_keep_parity(dev):
+    """The autotuner only changes launch shapes (and summation orders): solves
+    still match the oracle for single vectors and blocks."""
+    P = _lsdd()
+    prob, rng = _graddiv(seed=8)
+    h_or = oracle.setup(prob, oracle.Params(**GD_KW))
+    b = rng.standard_normal(prob.n)
+    B = rng.standard_normal((3, prob.n))
+    with P.Hierarchy.setup_problem(prob, P.Params.default(**GD_KW)) as h:
+        t1 = h.autotune(block=False)
+        t8 = h.autotune(block=True)
+        for t in t1 + t8:
+            assert t["lanes"] in (16, 64) and t["lanes_block"] in (16, 32, 64)
+            assert t["tiles_per_item"] in (2, 4, 8) and t["finalize_threads"] in (8, 32)
+        x, inf = h.solve(torch.from_numpy(b).to(dev))
+        x_or, inf_or = oracle.pcg(h_or, b)
+        assert abs(inf[0].iters - inf_or.iters) <= 1
+        assert np.linalg.norm(x.cpu().numpy() - x_or) <= 1e-10 * np.linalg.norm(x_or)
+        X, infs = h.solve(torch.from_numpy(B).to(dev))
+        X = X.cpu().numpy()
+        for k in range(3):
+            x_or, inf_or = oracle.pcg(h_or, B[k])
+            assert abs(infs[k].iters - inf_or.iters) <= 1
+            assert np.linalg.norm(X[k] - x_or) <= 1e-10 * np.linalg.norm(x_or)
