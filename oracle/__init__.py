@@ -9,3 +9,6 @@ from .lsdd import (  # noqa: F401
     schur_pinv, select_modes, setup, standard_aggregation, stationary, structural_pattern,
     supernode_graph, vcycle,
 )
+from .adjoint import (  # noqa: F401,E402
+    adjoint_gradient, assemble_scaled, compliance_gradient, element_bilinear,
+)
