@@ -133,6 +133,34 @@ lsdd_status lsdd_setup_batched(int32_t n_inst, const int64_t* inst_n, const int6
                                const int32_t* node_of_dof, const int32_t* agg_of_dof, int mem_is_device,
                                const lsdd_params* params, void* hip_stream, lsdd_hierarchy** out);
 
+/* As lsdd_setup_elements with element coefficients: the blocks passed are the
+ * unit blocks A_e^(1) and the hierarchy is built for A_e = theta_e A_e^(1)
+ * (elem_scale = theta, float64[n_elem], host or device like the blocks; NULL =
+ * all ones).  theta is kept for lsdd_update_theta. */
+lsdd_status lsdd_setup_elements_scaled(int64_t n, int64_t n_elem, const int64_t* elem_ptr,
+                                       const int32_t* elem_dofs, const double* elem_blocks,
+                                       const double* elem_scale, const int32_t* node_of_dof,
+                                       const int32_t* agg_of_dof, int mem_is_device,
+                                       const lsdd_params* params, void* hip_stream, lsdd_hierarchy** out);
+
+/* Replace the level-0 operator by A(theta') = sum_e theta'_e A_e^(1) (theta' device
+ * float64[n_elem]) while keeping the rest of the hierarchy: later solves run PCG on
+ * A(theta') preconditioned by the cycle built for the setup's theta (its level-0
+ * residuals use A(theta')).  Meant for nearby theta' (finite differences); passing
+ * the setup's theta restores the original operator bit for bit.
+ * LSDD_E_UNSUPPORTED for a hierarchy built from a CSR Gram factor. */
+lsdd_status lsdd_update_theta(lsdd_hierarchy* h, const double* theta, void* hip_stream);
+
+/* Element bilinear forms out[e] = u_{S_e}^T B_e v_{S_e} (all device pointers but
+ * elem_ptr): the contraction of the adjoint gradient dL/dtheta_e = -lambda_e^T
+ * A_e^(1) u_e of u = A(theta)^{-1} b (A linear in theta, Sec. 5.1 assembly).
+ *   elem_ptr   host int64[n_elem + 1]; elem_dofs device int32; blocks device float64,
+ *              the n_e x n_e blocks row-major, concatenated
+ *   u, v       device float64[n]; out device float64[n_elem] */
+lsdd_status lsdd_elem_bilinear(int64_t n_elem, const int64_t* elem_ptr, const int32_t* elem_dofs,
+                               const double* blocks, const double* u, const double* v, double* out,
+                               void* hip_stream);
+
 /* Build a hierarchy from a black-box sparse Gram factor G (m x n, CSR, host),
  * the input of Sec. 2 (A = G^T G, m >= n, full column rank).  Each row of G is
  * its own cover member: row j contributes g_j g_j^T with support = its stored

@@ -9,6 +9,7 @@
 // PCG vector kernels.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cfloat>
 #include <cmath>
 #include <vector>
@@ -147,7 +148,8 @@ __global__ void __launch_bounds__(WG) k_elem_eig(const int64_t* elem_ptr, const 
 // in ascending order (deterministic summation order).
 __global__ void k_assemble_rows(int64_t n, const int64_t* d2e_ptr, const int32_t* d2e_elem, const int32_t* d2e_loc,
                                 const int64_t* elem_ptr, const int32_t* elem_dofs, const int64_t* blk_off,
-                                const double* blocks, const int64_t* rowptr, const int32_t* col, double* val) {
+                                const double* blocks, const double* factor, const int64_t* rowptr, const int32_t* col,
+                                double* val) {
     const int64_t p = blockIdx.x * (int64_t)WG + tid();
     if (p >= n) return;
     const int64_t lo = rowptr[p], hi = rowptr[p + 1];
@@ -157,11 +159,50 @@ __global__ void k_assemble_rows(int64_t n, const int64_t* d2e_ptr, const int32_t
         const int64_t base = elem_ptr[e];
         const int ne = (int)(elem_ptr[e + 1] - base);
         const double* B = blocks + blk_off[e] + (int64_t)a * ne;
+        const double f = factor ? factor[e] : 1.0;
         for (int b = 0; b < ne; ++b) {
             int64_t slot = find_slot(col, lo, hi, elem_dofs[base + b]);
-            val[slot] += B[b];
+            val[slot] += f * B[b];
         }
     }
+}
+
+// factor[e] = theta[e] / theta0[e] (theta0 NULL: theta[e])
+__global__ void k_theta_factor(int64_t n, const double* theta, const double* theta0, double* factor) {
+    for (int64_t e = blockIdx.x * (int64_t)WG + tid(); e < n; e += (int64_t)gridDim.x * WG)
+        factor[e] = theta0 ? theta[e] / theta0[e] : theta[e];
+}
+
+// blocks of element e *= scale[e]
+__global__ void k_scale_blocks(int64_t n_elem, const int64_t* blk_off, const double* scale, double* blocks) {
+    for (int64_t e = blockIdx.x; e < n_elem; e += gridDim.x) {
+        const double s = scale[e];
+        for (int64_t q = blk_off[e] + tid(); q < blk_off[e + 1]; q += WG) blocks[q] *= s;
+    }
+}
+
+// out[e] = u_e^T B_e v_e (B_e row-major n_e x n_e at blk_off[e]); one wave per
+// element: lane j sums u_i B_ij v_j over the rows i (coalesced row reads), then
+// a fixed-order wave reduction.
+__global__ void __launch_bounds__(WG) k_elem_bilinear(int64_t n_elem, const int64_t* elem_ptr,
+                                                      const int32_t* elem_dofs, const int64_t* blk_off,
+                                                      const double* blocks, const double* u, const double* v,
+                                                      double* out) {
+    const int lane = tid() & 63;
+    const int64_t e = (int64_t)blockIdx.x * (WG / 64) + (tid() >> 6);
+    if (e >= n_elem) return;
+    const int64_t base = elem_ptr[e];
+    const int ne = (int)(elem_ptr[e + 1] - base);
+    const double* B = blocks + blk_off[e];
+    double acc = 0.0;
+    for (int j = lane; j < ne; j += 64) {
+        const double vj = v[elem_dofs[base + j]];
+        double t = 0.0;
+        for (int i = 0; i < ne; ++i) t += u[elem_dofs[base + i]] * B[(int64_t)i * ne + j];
+        acc += t * vj;
+    }
+    acc = wave_sum(acc);
+    if (lane == 0) out[e] = acc;
 }
 
 // ====================================================================== local problems
@@ -953,11 +994,30 @@ void launch_elem_eig(int64_t n_elem, const int64_t* elem_ptr, const int64_t* blk
 
 void launch_assemble_rows(int64_t n, const int64_t* d2e_ptr, const int32_t* d2e_elem, const int32_t* d2e_loc,
                           const int64_t* elem_ptr, const int32_t* elem_dofs, const int64_t* blk_off,
-                          const double* blocks, const int64_t* rowptr, const int32_t* col, double* val,
-                          hipStream_t st) {
+                          const double* blocks, const double* factor, const int64_t* rowptr, const int32_t* col,
+                          double* val, hipStream_t st) {
     if (n <= 0) return;
     hipLaunchKernelGGL(k_assemble_rows, dim3(grid_for(n)), dim3(WG), 0, st, n, d2e_ptr, d2e_elem, d2e_loc, elem_ptr,
-                       elem_dofs, blk_off, blocks, rowptr, col, val);
+                       elem_dofs, blk_off, blocks, factor, rowptr, col, val);
+}
+
+void launch_theta_factor(int64_t n, const double* theta, const double* theta0, double* factor, hipStream_t st) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_theta_factor, dim3(grid_for(n)), dim3(WG), 0, st, n, theta, theta0, factor);
+}
+
+void launch_scale_blocks(int64_t n_elem, const int64_t* blk_off, const double* scale, double* blocks,
+                         hipStream_t st) {
+    if (n_elem <= 0) return;
+    hipLaunchKernelGGL(k_scale_blocks, dim3((unsigned)std::min<int64_t>(n_elem, 65535 * 16)), dim3(WG), 0, st, n_elem,
+                       blk_off, scale, blocks);
+}
+
+void launch_elem_bilinear(int64_t n_elem, const int64_t* elem_ptr, const int32_t* elem_dofs, const int64_t* blk_off,
+                          const double* blocks, const double* u, const double* v, double* out, hipStream_t st) {
+    if (n_elem <= 0) return;
+    hipLaunchKernelGGL(k_elem_bilinear, dim3(grid_for(n_elem * 64)), dim3(WG), 0, st, n_elem, elem_ptr, elem_dofs,
+                       blk_off, blocks, u, v, out);
 }
 
 void launch_local_assemble(int32_t nbatch, const LocalArgs& a, hipStream_t st) {

@@ -58,11 +58,19 @@ void launch_elem_eig(int64_t n_elem, const int64_t* elem_ptr, const int64_t* blk
                      double* G, int32_t* ranks, int32_t* status, double* scratch, int64_t scratch_stride,
                      double rank_rtol, double spsd_tol, hipStream_t st);
 
-// CSR values of sum_T R_T^T A_T R_T; d2e lists the (element, local index) pairs of every DOF, elements ascending
+// CSR values += sum_T f_T R_T^T A_T R_T (f = factor, NULL = 1); d2e lists the
+// (element, local index) pairs of every DOF, elements ascending
 void launch_assemble_rows(int64_t n, const int64_t* d2e_ptr, const int32_t* d2e_elem, const int32_t* d2e_loc,
                           const int64_t* elem_ptr, const int32_t* elem_dofs, const int64_t* blk_off,
-                          const double* blocks, const int64_t* rowptr, const int32_t* col, double* val,
-                          hipStream_t st);
+                          const double* blocks, const double* factor, const int64_t* rowptr, const int32_t* col,
+                          double* val, hipStream_t st);
+// factor[e] = theta[e] / theta0[e] (theta0 NULL: theta[e])
+void launch_theta_factor(int64_t n, const double* theta, const double* theta0, double* factor, hipStream_t st);
+// blocks of element e *= scale[e]
+void launch_scale_blocks(int64_t n_elem, const int64_t* blk_off, const double* scale, double* blocks, hipStream_t st);
+// out[e] = u_e^T B_e v_e
+void launch_elem_bilinear(int64_t n_elem, const int64_t* elem_ptr, const int32_t* elem_dofs, const int64_t* blk_off,
+                          const double* blocks, const double* u, const double* v, double* out, hipStream_t st);
 
 void launch_local_assemble(int32_t nbatch, const LocalArgs& a, hipStream_t st);
 void launch_local_eig(int32_t nbatch, const LocalArgs& a, hipStream_t st);

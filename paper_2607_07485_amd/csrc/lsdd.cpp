@@ -151,6 +151,9 @@ struct Level {
     int64_t* d_rowptr = nullptr;
     int32_t* d_col = nullptr;
     double* d_val = nullptr;
+    int64_t* d_d2e_ptr = nullptr;     // level 0: DOF -> (element, local index), kept for re-assembly
+    int32_t* d_d2e_elem = nullptr;
+    int32_t* d_d2e_loc = nullptr;
     float* d_val32 = nullptr;
     // level-0 Gram factors
     double* d_G = nullptr;
@@ -309,6 +312,9 @@ struct lsdd_hierarchy {
     int32_t* ic = nullptr;        // act, iters (nsm each), then count, it, flag, finite-check flag
     double* part = nullptr;       // reduction partials, 2 * n_blk * NRB
     int32_t* h_ic = nullptr;      // pinned host mirror of count, it, flag
+    // element coefficients the level-0 blocks were scaled with at setup (NULL: none)
+    double* d_scale0 = nullptr;
+    double* d_factor = nullptr;   // scratch for lsdd_update_theta
     // hipGraph-captured halves of the PCG iteration: [block][cycle precision][half]
     bool use_graph = false;
     hipGraphExec_t gx[2][2][2] = {};
@@ -353,11 +359,17 @@ void assemble_operator(lsdd_hierarchy* h, Level& lv) {
         int32_t* d_de = h->arena.upload(de, h->st);
         int32_t* d_dl = h->arena.upload(dl, h->st);
         launch_assemble_rows(lv.n, d_dptr, d_de, d_dl, lv.d_elem_ptr, lv.d_elem_dofs, lv.d_blk_off, lv.d_blocks,
-                             lv.d_rowptr, lv.d_col, lv.d_val, h->st);
+                             nullptr, lv.d_rowptr, lv.d_col, lv.d_val, h->st);
         HIPCHK(hipStreamSynchronize(h->st));
-        h->arena.release(d_dptr);
-        h->arena.release(d_de);
-        h->arena.release(d_dl);
+        if (lv.level == 0) {
+            lv.d_d2e_ptr = d_dptr;
+            lv.d_d2e_elem = d_de;
+            lv.d_d2e_loc = d_dl;
+        } else {
+            h->arena.release(d_dptr);
+            h->arena.release(d_de);
+            h->arena.release(d_dl);
+        }
     }
     if (h->prm.precision == 1) {
         lv.d_val32 = h->arena.alloc<float>(lv.nnz);
@@ -1496,7 +1508,7 @@ void autotune_levels(lsdd_hierarchy* h) {
 
 lsdd_hierarchy* build(ElemList el0, const double* blocks, bool blocks_on_device, const double* gram_rows, int64_t n,
                       const int32_t* node_of_dof, const int32_t* agg_of_dof, const lsdd_params* prm, void* stream,
-                      std::vector<int64_t> inst_off = {}) {
+                      std::vector<int64_t> inst_off = {}, const double* elem_scale = nullptr) {
     auto h = std::make_unique<lsdd_hierarchy>();
     lsdd_params_default(&h->prm);
     if (prm) h->prm = *prm;
@@ -1538,6 +1550,13 @@ lsdd_hierarchy* build(ElemList el0, const double* blocks, bool blocks_on_device,
     lv->d_blocks = ar.alloc<double>(lv->blk_off[ne]);
     HIPCHK(hipMemcpyAsync(lv->d_blocks, blocks, lv->blk_off[ne] * sizeof(double),
                           blocks_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, h->st));
+    if (elem_scale) {
+        // A_e = theta_e A_e^(1): scale the blocks on the device, keep theta for lsdd_update_theta
+        h->d_scale0 = ar.alloc<double>(ne);
+        HIPCHK(hipMemcpyAsync(h->d_scale0, elem_scale, ne * sizeof(double),
+                              blocks_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, h->st));
+        launch_scale_blocks(ne, lv->d_blk_off, h->d_scale0, lv->d_blocks, h->st);
+    }
     // element Gram factors (Sec. 5.2)
     lv->d_G = ar.alloc<double>(lv->blk_off[ne]);
     if (!gram_rows) {
@@ -1665,9 +1684,22 @@ void lsdd_set_allocator(lsdd_alloc_fn alloc, lsdd_free_fn free_fn, void* ctx) {
         return LSDD_E_INVAL;                     \
     }
 
+lsdd_status lsdd_setup_elements_scaled(int64_t n, int64_t n_elem, const int64_t* elem_ptr, const int32_t* elem_dofs,
+                                       const double* elem_blocks, const double* elem_scale,
+                                       const int32_t* node_of_dof, const int32_t* agg_of_dof, int mem_is_device,
+                                       const lsdd_params* params, void* hip_stream, lsdd_hierarchy** out);
+
 lsdd_status lsdd_setup_elements(int64_t n, int64_t n_elem, const int64_t* elem_ptr, const int32_t* elem_dofs,
                                 const double* elem_blocks, const int32_t* node_of_dof, const int32_t* agg_of_dof,
                                 int mem_is_device, const lsdd_params* params, void* hip_stream, lsdd_hierarchy** out) {
+    return lsdd_setup_elements_scaled(n, n_elem, elem_ptr, elem_dofs, elem_blocks, nullptr, node_of_dof, agg_of_dof,
+                                      mem_is_device, params, hip_stream, out);
+}
+
+lsdd_status lsdd_setup_elements_scaled(int64_t n, int64_t n_elem, const int64_t* elem_ptr, const int32_t* elem_dofs,
+                                       const double* elem_blocks, const double* elem_scale,
+                                       const int32_t* node_of_dof, const int32_t* agg_of_dof, int mem_is_device,
+                                       const lsdd_params* params, void* hip_stream, lsdd_hierarchy** out) {
     ABI_BEGIN
     if (!out) throw Error(LSDD_E_INVAL, "out is NULL");
     *out = nullptr;
@@ -1703,7 +1735,53 @@ lsdd_status lsdd_setup_elements(int64_t n, int64_t n_elem, const int64_t* elem_p
         for (char u : used)
             if (!u) throw Error(LSDD_E_INVAL, "aggregate ids must be 0..n_agg-1, each used");
     }
-    *out = build(std::move(el), elem_blocks, mem_is_device != 0, nullptr, n, node_of_dof, agg_of_dof, params, hip_stream);
+    *out = build(std::move(el), elem_blocks, mem_is_device != 0, nullptr, n, node_of_dof, agg_of_dof, params, hip_stream,
+                 {}, elem_scale);
+    return LSDD_OK;
+    ABI_END
+}
+
+lsdd_status lsdd_update_theta(lsdd_hierarchy* h, const double* theta, void* hip_stream) {
+    ABI_BEGIN
+    if (!h || !theta) throw Error(LSDD_E_INVAL, "NULL argument");
+    if (!h->L[0]->d_d2e_ptr) throw Error(LSDD_E_UNSUPPORTED, "the hierarchy was not built from element blocks");
+    h->st = (hipStream_t)hip_stream;
+    Level& l0 = *h->L[0];
+    const int64_t ne = l0.el.count();
+    if (!h->d_factor) h->d_factor = h->arena.alloc<double>(ne);
+    launch_theta_factor(ne, theta, h->d_scale0, h->d_factor, h->st);
+    HIPCHK(hipMemsetAsync(l0.d_val, 0, l0.nnz * sizeof(double), h->st));
+    launch_assemble_rows(l0.n, l0.d_d2e_ptr, l0.d_d2e_elem, l0.d_d2e_loc, l0.d_elem_ptr, l0.d_elem_dofs, l0.d_blk_off,
+                         l0.d_blocks, h->d_factor, l0.d_rowptr, l0.d_col, l0.d_val, h->st);
+    if (l0.d_val32) launch_to_f32(l0.nnz, l0.d_val, l0.d_val32, h->st);
+    HIPCHK(hipGetLastError());
+    sync(h->st);
+    return LSDD_OK;
+    ABI_END
+}
+
+lsdd_status lsdd_elem_bilinear(int64_t n_elem, const int64_t* elem_ptr, const int32_t* elem_dofs, const double* blocks,
+                               const double* u, const double* v, double* out, void* hip_stream) {
+    ABI_BEGIN
+    if (n_elem < 1 || !elem_ptr || !elem_dofs || !blocks || !u || !v || !out) throw Error(LSDD_E_INVAL, "bad argument");
+    if (elem_ptr[0] != 0) throw Error(LSDD_E_INVAL, "elem_ptr[0] must be 0");
+    std::vector<int64_t> boff(n_elem + 1, 0);
+    for (int64_t e = 0; e < n_elem; ++e) {
+        const int64_t s = elem_ptr[e + 1] - elem_ptr[e];
+        if (s < 1 || s > 4096) throw Error(LSDD_E_INVAL, "bad element size");
+        boff[e + 1] = boff[e] + s * s;
+    }
+    hipStream_t st = (hipStream_t)hip_stream;
+    struct Scoped {
+        Arena a;
+        ~Scoped() { a.clear(); }
+    } sc;
+    const std::vector<int64_t> ptr(elem_ptr, elem_ptr + n_elem + 1);
+    int64_t* d_ptr = sc.a.upload(ptr, st);
+    int64_t* d_boff = sc.a.upload(boff, st);
+    launch_elem_bilinear(n_elem, d_ptr, elem_dofs, d_boff, blocks, u, v, out, st);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(st));
     return LSDD_OK;
     ABI_END
 }

@@ -86,13 +86,18 @@ def lib():
         L.lsdd_segments.argtypes = [_P, i32p, i64p]
         L.lsdd_level_segments.argtypes = [_P, C.c_int32, i64p, i32p]
         L.lsdd_autotune.argtypes = [_P, C.c_int32, _P]
+        L.lsdd_setup_elements_scaled.argtypes = [C.c_int64, C.c_int64, i64p, i32p, _P, _P, i32p, i32p, C.c_int,
+                                                 C.POINTER(Params), _P, C.POINTER(_P)]
+        L.lsdd_update_theta.argtypes = [_P, _P, _P]
+        L.lsdd_elem_bilinear.argtypes = [C.c_int64, i64p, _P, _P, _P, _P, _P, _P]
         L.lsdd_level_tuning.argtypes = [_P, C.c_int32, i32p]
         L.lsdd_set_allocator.restype = None
         for name in ("lsdd_setup_elements", "lsdd_setup_gram_csr", "lsdd_solve", "lsdd_vcycle", "lsdd_apply",
                      "lsdd_hierarchy_info", "lsdd_level_sizes", "lsdd_export_level", "lsdd_export_gram",
                      "lsdd_destroy", "lsdd_set_cycle_precision", "lsdd_trace", "lsdd_trace_get",
                      "lsdd_set_solve_params", "lsdd_set_graph", "lsdd_segments", "lsdd_setup_batched",
-                     "lsdd_level_segments", "lsdd_autotune", "lsdd_level_tuning"):
+                     "lsdd_level_segments", "lsdd_autotune", "lsdd_level_tuning", "lsdd_setup_elements_scaled",
+                     "lsdd_update_theta", "lsdd_elem_bilinear"):
             getattr(L, name).restype = C.c_int
         _LIB = L
     return _LIB
@@ -122,6 +127,21 @@ def _dev_ptr(t):
     return C.c_void_p(t.data_ptr())
 
 
+def elem_bilinear(elem_ptr, elem_dofs, blocks, u, v, out=None):
+    """lsdd_elem_bilinear: out[e] = u_e^T B_e v_e.  elem_ptr host int64 array; elem_dofs
+    a device int32 tensor; blocks, u, v float64 device tensors."""
+    import torch
+    elem_ptr = np.ascontiguousarray(elem_ptr, dtype=np.int64)
+    if not (isinstance(elem_dofs, torch.Tensor) and elem_dofs.is_cuda and elem_dofs.dtype == torch.int32
+            and elem_dofs.is_contiguous()):
+        raise TypeError("elem_dofs: expected a contiguous int32 device tensor")
+    ne = len(elem_ptr) - 1
+    out = torch.empty(ne, dtype=torch.float64, device=u.device) if out is None else out
+    _check(lib().lsdd_elem_bilinear(ne, _ptr(elem_ptr, C.c_int64), C.c_void_p(elem_dofs.data_ptr()), _dev_ptr(blocks),
+                                    _dev_ptr(u), _dev_ptr(v), _dev_ptr(out), _stream()))
+    return out
+
+
 class Hierarchy:
     """An LS-AMG-DD hierarchy owned by the library (lsdd_hierarchy*)."""
 
@@ -148,6 +168,34 @@ class Hierarchy:
                                          _ptr(elem_dofs, C.c_int32), bptr, _ptr(nod, C.c_int32),
                                          _ptr(agg, C.c_int32), on_dev, C.byref(params), _stream(), C.byref(h)))
         return cls(h)
+
+    @classmethod
+    def setup_elements_scaled(cls, n, elem_ptr, elem_dofs, blocks, theta, node_of_dof=None, agg_of_dof=None,
+                              params=None):
+        """lsdd_setup_elements_scaled: blocks (unit blocks) and theta both host numpy arrays or
+        both float64 device tensors."""
+        import torch
+        elem_ptr = np.ascontiguousarray(elem_ptr, dtype=np.int64)
+        elem_dofs = np.ascontiguousarray(elem_dofs, dtype=np.int32)
+        nod = None if node_of_dof is None else np.ascontiguousarray(node_of_dof, dtype=np.int32)
+        agg = None if agg_of_dof is None else np.ascontiguousarray(agg_of_dof, dtype=np.int32)
+        if isinstance(blocks, torch.Tensor):
+            bptr, tptr, on_dev = _dev_ptr(blocks), _dev_ptr(theta), 1
+        else:
+            blocks = np.ascontiguousarray(blocks, dtype=np.float64)
+            theta = np.ascontiguousarray(theta, dtype=np.float64)
+            bptr, tptr, on_dev = C.c_void_p(blocks.ctypes.data), C.c_void_p(theta.ctypes.data), 0
+        params = params or Params.default()
+        h = C.c_void_p()
+        _check(lib().lsdd_setup_elements_scaled(int(n), len(elem_ptr) - 1, _ptr(elem_ptr, C.c_int64),
+                                                _ptr(elem_dofs, C.c_int32), bptr, tptr, _ptr(nod, C.c_int32),
+                                                _ptr(agg, C.c_int32), on_dev, C.byref(params), _stream(),
+                                                C.byref(h)))
+        return cls(h)
+
+    def update_theta(self, theta):
+        """lsdd_update_theta (theta: float64 device tensor)."""
+        _check(lib().lsdd_update_theta(self._h, _dev_ptr(theta), _stream()))
 
     @classmethod
     def setup_problem(cls, prob, params=None, blocks_on_device=False):
