@@ -302,7 +302,7 @@ __global__ void __launch_bounds__(WG) k_local_eig(LocalArgs A) {
         for (int i = tid(); i < nw; i += WG)
             tnorm = fmax(tnorm, fabs(d[i]) + (i > 0 ? fabs(e[i - 1]) : 0.0) + (i + 1 < nw ? fabs(e[i]) : 0.0));
         tnorm = wg_max(tnorm, s_red);
-        wg_inverse_iteration(d, e, nw, mu, k, VS, T + 3 * nw, fmax(tnorm, 1e-300), (int*)s_dyn, s_dyn + 2048, s_red,
+        wg_inverse_iteration(d, e, nw, mu, k, VS, T + 3 * nw, fmax(tnorm, 1e-300), (int*)s_dyn, s_dyn + nw, s_red,
                              &s_ncl);
         wg_tridiag_backtransform(S, nw, T + 2 * nw, VS, k, s_dyn, s_dyn + nw);
     }
@@ -872,8 +872,9 @@ __global__ void k_pack_small(const int64_t* sub_ptr, const int64_t* inv_off, con
 
 // Transfers with Z_i stored column-major (|omega_i| x k_i, column s contiguous).
 // Restriction rc[coff_i + s] = sum_a Z_i[a, s] t[omega_i[a]]: work item =
-// (aggregate, 16 columns); t on omega_i is staged in LDS, each wave takes
-// columns and its lanes stride the rows (coalesced), then a wave reduction.
+// (aggregate, 16 columns); t on omega_i is staged in LDS in chunks of 2048
+// rows, each wave takes 4 columns and its lanes stride the rows (coalesced),
+// then a wave reduction per column.
 template <typename T>
 __global__ void __launch_bounds__(WG) k_restrict(const int32_t* items, const int64_t* agg_ptr, const int32_t* agg_dofs,
                                                  const int64_t* zoff, const int32_t* k, const int64_t* coff, const T* Zc,
@@ -883,21 +884,35 @@ __global__ void __launch_bounds__(WG) k_restrict(const int32_t* items, const int
     const int kk = k[ag];
     const int64_t a0 = agg_ptr[ag];
     const int nw = (int)(agg_ptr[ag + 1] - a0);
-    for (int a = tid(); a < nw; a += WG) s_t[a] = t[agg_dofs[a0 + a]];
-    __syncthreads();
     const int lane = tid() & 63, w = tid() >> 6;
     const T* z = Zc + zoff[ag];
-    for (int s = s0 + w; s < s0 + 16 && s < kk; s += 4) {
-        const T* col = z + (int64_t)s * nw;
-        T acc = 0;
-        for (int a = lane; a < nw; a += 64) acc += col[a] * s_t[a];
-        for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
-        if (lane == 0) rc[coff[ag] + s] = acc;
+    T acc[4] = {0, 0, 0, 0};
+    for (int c0 = 0; c0 < nw; c0 += 2048) {
+        const int cn = min(2048, nw - c0);
+        __syncthreads();
+        for (int a = tid(); a < cn; a += WG) s_t[a] = t[agg_dofs[a0 + c0 + a]];
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int s = s0 + w + 4 * i;
+            if (s < kk) {
+                const T* col = z + (int64_t)s * nw + c0;
+                for (int a = lane; a < cn; a += 64) acc[i] += col[a] * s_t[a];
+            }
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int s = s0 + w + 4 * i;
+        T v = acc[i];
+        for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+        if (lane == 0 && s < kk) rc[coff[ag] + s] = v;
     }
 }
 
 // Prolongation x[omega_i[a]] += sum_s Z_i[a, s] ec[coff_i + s]: work item =
-// (aggregate, 256 rows); thread per row, coalesced over rows, ec in LDS.
+// (aggregate, 256 rows); thread per row, coalesced over rows, ec staged in LDS
+// in chunks of 2048 modes.
 template <typename T>
 __global__ void __launch_bounds__(WG) k_prolong(const int32_t* items, const int64_t* agg_ptr, const int32_t* agg_dofs,
                                                 const int64_t* zoff, const int32_t* k, const int64_t* coff, const T* Zc,
@@ -907,19 +922,24 @@ __global__ void __launch_bounds__(WG) k_prolong(const int32_t* items, const int6
     const int kk = k[ag];
     const int64_t a0 = agg_ptr[ag];
     const int nw = (int)(agg_ptr[ag + 1] - a0);
-    for (int s = tid(); s < kk; s += WG) s_e[s] = ec[coff[ag] + s];
-    __syncthreads();
     const int a = r0 + tid();
-    if (a >= nw) return;
     const T* z = Zc + zoff[ag] + a;
     T acc0 = 0, acc1 = 0;
-    int s = 0;
-    for (; s + 1 < kk; s += 2) {
-        acc0 += z[(int64_t)s * nw] * s_e[s];
-        acc1 += z[(int64_t)(s + 1) * nw] * s_e[s + 1];
+    for (int c0 = 0; c0 < kk; c0 += 2048) {
+        const int cn = min(2048, kk - c0);
+        __syncthreads();
+        for (int s = tid(); s < cn; s += WG) s_e[s] = ec[coff[ag] + c0 + s];
+        __syncthreads();
+        if (a < nw) {
+            int s = 0;
+            for (; s + 1 < cn; s += 2) {
+                acc0 += z[(int64_t)(c0 + s) * nw] * s_e[s];
+                acc1 += z[(int64_t)(c0 + s + 1) * nw] * s_e[s + 1];
+            }
+            if (s < cn) acc0 += z[(int64_t)(c0 + s) * nw] * s_e[s];
+        }
     }
-    if (s < kk) acc0 += z[(int64_t)s * nw] * s_e[s];
-    x[agg_dofs[a0 + a]] += acc0 + acc1;
+    if (a < nw) x[agg_dofs[a0 + a]] += acc0 + acc1;
 }
 
 template <typename T>
@@ -1025,10 +1045,10 @@ void launch_local_assemble(int32_t nbatch, const LocalArgs& a, hipStream_t st) {
     hipLaunchKernelGGL(k_local_assemble, dim3(nbatch), dim3(WG), 0, st, a);
 }
 
-void launch_local_eig(int32_t nbatch, const LocalArgs& a, hipStream_t st) {
+void launch_local_eig(int32_t nbatch, const LocalArgs& a, int32_t max_nw, hipStream_t st) {
     if (nbatch <= 0) return;
-    // dynamic LDS: tridiagonal work vectors, cluster starts and dots (|omega| <= 2048)
-    size_t lds = 4096 * sizeof(double);
+    // dynamic LDS: tridiagonal work vectors, cluster starts and dots, 2 |omega| doubles
+    const size_t lds = (size_t)std::max(2 * max_nw, 4096) * sizeof(double);
     hipLaunchKernelGGL(k_local_eig, dim3(nbatch), dim3(WG), lds, st, a);
 }
 

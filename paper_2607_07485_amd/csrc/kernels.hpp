@@ -73,7 +73,8 @@ void launch_elem_bilinear(int64_t n_elem, const int64_t* elem_ptr, const int32_t
                           const double* blocks, const double* u, const double* v, double* out, hipStream_t st);
 
 void launch_local_assemble(int32_t nbatch, const LocalArgs& a, hipStream_t st);
-void launch_local_eig(int32_t nbatch, const LocalArgs& a, hipStream_t st);
+// max_nw: largest |omega| of the batch (<= 4096)
+void launch_local_eig(int32_t nbatch, const LocalArgs& a, int32_t max_nw, hipStream_t st);
 void launch_stage_z(int32_t nbatch, const LocalArgs& a, hipStream_t st);
 void launch_views_max_diag(int32_t nv, const double* base, const View* v, double* out, hipStream_t st);
 void launch_views_add_diag(int32_t nv, double* base, const View* v, const double* delta, hipStream_t st);

@@ -461,7 +461,7 @@ void make_terminal(lsdd_hierarchy* h, Level& lv, const std::vector<int32_t>& ter
     lv.term_len = sub_off[nb];
     bool identity = lv.term_len == lv.n;
     for (int64_t t = 0; identity && t < lv.term_len; ++t) identity = dofs[t] == t;
-    if (max_ni > 32768) throw Error(LSDD_E_UNSUPPORTED, "terminal block too large: " + std::to_string(max_ni));
+    if (max_ni > 49152) throw Error(LSDD_E_UNSUPPORTED, "terminal block too large: " + std::to_string(max_ni));
     double* W = ar.alloc<double>((size_t)max_ni * max_ni);
     double* inv = ar.alloc<double>((size_t)inv_off[nb]);
     int32_t* d_st = ar.alloc<int32_t>(nb);
@@ -597,8 +597,8 @@ std::unique_ptr<Level> coarsen(lsdd_hierarchy* h, Level& lv, const int32_t* agg_
     }
     vlog("level %d: n=%lld aggregates=%d colours=%d max|omega|=%lld max|Omega|=%lld max mult=%d",
          lv.level, (long long)n, n_agg, lv.n_colors, (long long)max_nw, (long long)max_m, C.max_mult);
-    if (max_m > 4096) throw Error(LSDD_E_UNSUPPORTED, "overlap larger than 4096 DOFs: " + std::to_string(max_m));
-    if (max_nw > 2048) throw Error(LSDD_E_UNSUPPORTED, "aggregate larger than 2048 DOFs");
+    if (max_m > 16384) throw Error(LSDD_E_UNSUPPORTED, "overlap larger than 16384 DOFs: " + std::to_string(max_m));
+    if (max_nw > 4096) throw Error(LSDD_E_UNSUPPORTED, "aggregate larger than 4096 DOFs: " + std::to_string(max_nw));
     std::vector<int64_t> clpos_off(C.cl_elems.size() + 1, 0);
     std::vector<int32_t> clpos;
     {
@@ -786,7 +786,11 @@ std::unique_ptr<Level> coarsen(lsdd_hierarchy* h, Level& lv, const int32_t* agg_
         bt.trsm(w2, vLww, sb, vS, false);
         launch_views_symmetrize(nb, sb, bt.put(0, vS), st);
         // eigenpairs of C and retained modes
-        launch_local_eig(nb, B, st);
+        {
+            int32_t mx = 0;
+            for (int32_t b = 0; b < nb; ++b) mx = std::max(mx, (int32_t)(C.agg_ptr[pos + b + 1] - C.agg_ptr[pos + b]));
+            launch_local_eig(nb, B, mx, st);
+        }
         HIPCHK(hipGetLastError());
         std::vector<int32_t> kb = download(lv.d_k + pos, nb, st);
         // Z = L_ww^{-T} V_k
