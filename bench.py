@@ -16,6 +16,11 @@ products, subdomain and coarsest inverses) is timed separately and reported
 as setup_s.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--N 128] [--no-cpu-baseline]
+
+Other workloads (not the default line): --workload batch (64 uneven Q1 elasticity
+instances, 8 right-hand sides each, one batched hierarchy) and --workload q2grad
+(Q2 hexahedral elasticity on 24^3 with per-element coefficients: solve, adjoint
+gradient of the compliance and central differences on 32 elements).
 """
 from __future__ import annotations
 
@@ -34,9 +39,10 @@ METRIC = "solve DOF/s to 1e-8 rel residual + setup s; FP32-cycle vs FP64, 1 MI35
 HBM_PEAK_GBS = 8000.0
 
 # HBM bytes per launch of the dominant solve kernel, from rocprofv3 FETCH_SIZE and WRITE_SIZE
-# runs of this bench (FP64 cycle, 128 x 128) scaled by a 1 GiB device-copy calibration (read
-# factor 2.0, write factor 1.0).  Valid only for the kernel source these counters were taken on.
-TRAFFIC = {("sub_symv", "graddiv_rtcf3_128x128", "f64"): ("7380094f6174f17c", 2.599e8)}
+# runs of this bench (FP64 cycle, 128 x 128; average over the 22 launches of one solve) scaled by
+# a 1 GiB device-copy calibration (read factor 2.0, write factor 1.0).  Valid only for the kernel
+# source these counters were taken on.
+TRAFFIC = {("sub_symv", "graddiv_rtcf3_128x128", "f64"): ("64882a4d6c4c5b4a", 2.610e8)}
 
 
 def _kernels_hash():
@@ -93,6 +99,147 @@ def cpu_baseline(N_sample: int):
             "setup_s": t1 - t0}
 
 
+def _trace_dominant(h, torch, run):
+    """Per-kernel HIP-event timing of one more run; returns (kernels dict, dominant (name, rec))."""
+    h.trace(True)
+    run()
+    h.trace(False)
+    tr = h.trace_read()
+    dom = max(tr.items(), key=lambda kv: kv[1]["ms"])
+    kernels = {k: dict(launches=v["launches"], ms=round(v["ms"], 4),
+                       gbs=round(v["bytes"] / max(v["ms"], 1e-9) / 1e6, 1)) for k, v in tr.items()}
+    return kernels, dom
+
+
+def run_batch(a, torch, P, fegen, dev):
+    """64 uneven Q1 elasticity instances (N_i ~ U{48..256}, nu_i ~ U(0.3, 0.49)), 8 RHS each, one
+    batched hierarchy (vertex-patch cover on level 0, threshold modes, paper stopping tests per
+    instance); FP64 and FP32 cycles in FP64 PCG, one recurrence per (instance, RHS)."""
+    batch = fegen.elasticity_batch(64, 48, 256, seed=0, nrhs=8)
+    probs = [p for p, _ in batch]
+    B_np = np.ascontiguousarray(np.concatenate([bb for _, bb in batch], axis=1))
+    n_tot, nrhs = B_np.shape[1], B_np.shape[0]
+    B = torch.from_numpy(B_np).to(dev)
+    prm = _params(P, max_levels=3)
+    P.Hierarchy.setup_batched([fegen.elasticity_q1(4)], prm).close()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    h = P.Hierarchy.setup_batched(probs, prm)
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+    info = h.info()
+    print(f"[bench] batch setup {setup_s:.2f} s, levels {info['n']}", file=sys.stderr, flush=True)
+    res = {}
+    for prec in (0, 1):
+        h.set_cycle_precision(prec)
+        h.set_graph(False)
+        tuning = h.autotune(block=True)
+        h.set_graph(True)
+        X, infs = h.solve(B)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(a.steps):
+            X, infs = h.solve(B)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / a.steps
+        its = [f.iters for f in infs]
+        res["fp32" if prec else "fp64"] = {"value": n_tot * nrhs / dt, "ms_per_step": dt * 1e3,
+                                          "iters_min": min(its), "iters_max": max(its),
+                                          "converged": all(f.converged for f in infs), "tuning": tuning}
+        print(f"[bench] batch prec {prec}: {dt * 1e3:.1f} ms, its {min(its)}..{max(its)}", file=sys.stderr,
+              flush=True)
+    h.set_graph(False)
+    kernels, (dname, d) = _trace_dominant(h, torch, lambda: h.solve(B))
+    h.close()
+    best = max(("fp64", "fp32"), key=lambda k: res[k]["value"])
+    achieved = d["bytes"] / (d["ms"] * 1e-3) / 1e9
+    out = {"metric": METRIC, "value": res[best]["value"], "unit": "DOF/s", "n_gpus": 1, "steps": a.steps,
+           "warmup": 1, "ms_per_step": res[best]["ms_per_step"], "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f32+f64" if best == "fp32" else "f64", "data": "synthetic",
+           "config": {"workload": f"elasticity_q1_batch64_{nrhs}rhs", "n_dofs": n_tot, "nrhs": nrhs,
+                      "levels": info["n"], "oc": round(info["oc"], 3)},
+           "setup_s": setup_s, **res,
+           "roofline": {"bound": "hbm", "kernel": dname, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                        "avg_launch_us": d["ms"] * 1e3 / max(d["launches"], 1)},
+           "kernels": kernels, "cpu_baseline": None}
+    print(json.dumps(out))
+
+
+def run_q2grad(a, torch, P, fegen, dev):
+    """Q2 hex elasticity on N^3 (default 24^3), theta ~ lognormal(0, 0.5); compliance J = b^T u and its
+    gradient through the autograd Function (adjoint solve on the same hierarchy), checked by central
+    differences on 32 elements with the hierarchy kept as the preconditioner."""
+    from paper_2607_07485_amd import autograd as AG
+    N = a.N if a.N != 128 else 24
+    rng = np.random.default_rng(0)
+    theta = np.exp(0.5 * rng.standard_normal(N ** 3))
+    prob = fegen.elasticity_q2hex(N, nu=0.3)
+    b_np = rng.standard_normal(prob.n)
+    prm = _params(P, max_levels=3, agg_passes=1, agg_passes_coarse=1)
+    system = AG.ElementSystem(prob, prm)
+    th = torch.tensor(theta, device=dev, requires_grad=True)
+    b = torch.tensor(b_np, device=dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    u = AG.solve(th, b, system)
+    J = torch.dot(b, u)
+    J.backward()
+    torch.cuda.synchronize()
+    t_grad = time.perf_counter() - t0
+    g = th.grad.cpu().numpy()
+    homog = abs(float(theta @ g) + J.item()) / J.item()
+    print(f"[bench] q2grad forward+backward {t_grad:.2f} s", file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    h = system.hierarchy(torch.tensor(theta, device=dev))
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+    info = h.info()
+    res = {}
+    for prec in (0, 1):
+        h.set_cycle_precision(prec)
+        x, inf = h.solve(b)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(a.steps):
+            x, inf = h.solve(b)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / a.steps
+        res["fp32" if prec else "fp64"] = {"value": prob.n / dt, "ms_per_step": dt * 1e3, "iters": inf[0].iters}
+    h.set_cycle_precision(0)
+    h.set_solve_params(1e-11, 1000)
+    errs = []
+    for e in rng.choice(len(theta), size=32, replace=False):
+        step = 1e-4 * theta[e]
+        Js = []
+        for sgn in (1.0, -1.0):
+            tp = theta.copy()
+            tp[e] += sgn * step
+            h.update_theta(torch.tensor(tp, device=dev))
+            x, _ = h.solve(b)
+            Js.append(torch.dot(b, x).item())
+        errs.append(abs((Js[0] - Js[1]) / (2 * step) - g[e]) / abs(g[e]))
+    h.update_theta(torch.tensor(theta, device=dev))
+    h.set_solve_params(1e-8, 1000)
+    kernels, (dname, d) = _trace_dominant(h, torch, lambda: h.solve(b))
+    h.close()
+    best = max(("fp64", "fp32"), key=lambda k: res[k]["value"])
+    achieved = d["bytes"] / (d["ms"] * 1e-3) / 1e9
+    out = {"metric": METRIC, "value": res[best]["value"], "unit": "DOF/s", "n_gpus": 1, "steps": a.steps,
+           "warmup": 1, "ms_per_step": res[best]["ms_per_step"], "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f32+f64" if best == "fp32" else "f64", "data": "synthetic",
+           "config": {"workload": f"elasticity_q2hex_{N}cubed_grad", "n_dofs": prob.n, "levels": info["n"]},
+           "setup_s": setup_s, **res,
+           "gradient": {"forward_backward_s": t_grad, "homogeneity_rel": homog,
+                        "fd_max_rel_err": max(errs), "fd_median_rel_err": float(np.median(errs)),
+                        "fd_elements": 32},
+           "roofline": {"bound": "hbm", "kernel": dname, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                        "avg_launch_us": d["ms"] * 1e3 / max(d["launches"], 1)},
+           "kernels": kernels, "cpu_baseline": None}
+    print(json.dumps(out))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -101,6 +248,7 @@ def main():
     ap.add_argument("--N", type=int, default=128)
     ap.add_argument("--cpu-sample", type=int, default=16)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--workload", choices=["graddiv", "batch", "q2grad"], default="graddiv")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a device copy of 1 GiB five times (HBM counter calibration for profiling)")
     a = ap.parse_args()
@@ -125,6 +273,17 @@ def main():
 
     dev = torch.device("cuda:0")
     print(f"[bench] device {torch.cuda.get_device_name(0)}", file=sys.stderr, flush=True)
+    # a stream of our own (default priority), so the PCG iteration can run as captured HIP graphs
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        if a.workload == "batch":
+            return run_batch(a, torch, P, fegen, dev)
+        if a.workload == "q2grad":
+            return run_q2grad(a, torch, P, fegen, dev)
+        return run_graddiv(a, torch, P, fegen, dev)
+
+
+def run_graddiv(a, torch, P, fegen, dev):
     # load code objects once on a tiny instance so setup timing excludes module loading
     pw, bw = fegen.graddiv_hdiv(N=4)
     P.Hierarchy.setup_problem(pw, _params(P)).close()
@@ -138,6 +297,13 @@ def main():
     setup_s = time.perf_counter() - t0
     info = h.info()
     print(f"[bench] setup {setup_s:.2f} s, levels {info['n']}, oc {info['oc']:.2f}", file=sys.stderr, flush=True)
+    # launch shapes picked by the autotuner on this hierarchy (single vectors, FP64 cycle), graphs on
+    h.set_cycle_precision(0)
+    t0 = time.perf_counter()
+    tuning = h.autotune(block=False)
+    torch.cuda.synchronize()
+    autotune_s = time.perf_counter() - t0
+    h.set_graph(True)
 
     # plain FP64 method: FP64 V-cycle inside FP64 PCG
     h.set_cycle_precision(0)
@@ -199,6 +365,7 @@ def main():
                    "oc": round(info["oc"], 3), "gc": round(info["gc"], 3), "rtol": 1e-8,
                    "cycle": "FP32 V-cycle in FP64 PCG" if use32 else "FP64 V-cycle in FP64 PCG"},
         "setup_s": setup_s,
+        "autotune_s": autotune_s, "tuning": tuning, "graphs": True,
         **out,
         "roofline": {"bound": "hbm", "kernel": dname, "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
