@@ -493,11 +493,13 @@ __device__ inline void tri_shift_solve(const double* d, const double* e, int n, 
 // Eigenvectors of the tridiagonal (d, e) for the eigenvalues lam[0..kk) by
 // inverse iteration.  Eigenvalues closer than 1e-4 * tnorm form a cluster.
 // Single-member clusters run one per thread (threads 0..63, each with a
-// scratch slot of 5n doubles in `ws`); the vectors of a larger cluster are
-// computed one after another by the whole workgroup, each orthogonalised
-// against the earlier members by classical Gram-Schmidt applied twice.
-// Output V (n x kk, column-major, ld n).  LDS: cl_start (kk+1 ints) and
-// dots (kk doubles).
+// scratch slot of 5n doubles in `ws`).  The members of a larger cluster are
+// processed in batches of up to 64: each iteration solves every member's
+// shifted system on its own thread, then orthogonalises the batch by classical
+// Gram-Schmidt applied twice against the earlier members of the cluster and,
+// in index order, within the batch, and normalises it.  Output V (n x kk,
+// column-major, ld n).  `ws` holds 64 * 5n doubles of slots followed by
+// 64 * max(n, 64) doubles of batch dots.  LDS: cl_start (kk+1 ints), dots (64).
 __device__ inline void wg_inverse_iteration(const double* d, const double* e, int n, const double* lam, int kk,
                                             double* V, double* ws, double tnorm, int* cl_start, double* dots,
                                             double* red, int* ncl_sh) {
@@ -517,19 +519,23 @@ __device__ inline void wg_inverse_iteration(const double* d, const double* e, in
         unsigned h = (unsigned)(k * 2654435761u) ^ (unsigned)(i * 40503u);
         y[k] = 1.0 + 0.25 * ((double)(h & 0xffff) / 65536.0 - 0.5);
     };
-    // singletons, one per thread
-    for (int c = tid(); tid() < 64 && c < ncl; c += 64) {
-        const int i = cl_start[c];
-        if (cl_start[c + 1] - i != 1) continue;
-        double* u0 = ws + (long long)tid() * 5 * n;
+    auto slot_solve = [&](int slot, int i, double shift) {
+        double* u0 = ws + (long long)slot * 5 * n;
         double* u1 = u0 + n;
         double* u2 = u1 + n;
         double* l = u2 + n;
         unsigned char* piv = (unsigned char*)(l + n);
+        tri_shift_solve(d, e, n, shift, V + (long long)i * n, u0, u1, u2, l, piv, tiny);
+    };
+    double* dd = ws + (long long)64 * 5 * n;        // batch dots, 64 x 64
+    // singletons, one per thread
+    for (int c = tid(); tid() < 64 && c < ncl; c += 64) {
+        const int i = cl_start[c];
+        if (cl_start[c + 1] - i != 1) continue;
         double* y = V + (long long)i * n;
         for (int k = 0; k < n; ++k) start_vector(y, i, k);
         for (int it = 0; it < 4; ++it) {
-            tri_shift_solve(d, e, n, lam[i], y, u0, u1, u2, l, piv, tiny);
+            slot_solve(tid(), i, lam[i]);
             double nr = 0.0;
             for (int k = 0; k < n; ++k) nr += y[k] * y[k];
             nr = 1.0 / sqrt(nr);
@@ -537,44 +543,67 @@ __device__ inline void wg_inverse_iteration(const double* d, const double* e, in
         }
     }
     __syncthreads();
-    // clusters, by the whole workgroup
+    // clusters, in batches of up to 64 members
     for (int c = 0; c < ncl; ++c) {
         const int c0 = cl_start[c], c1 = cl_start[c + 1];
         if (c1 - c0 == 1) continue;
-        double* u0 = ws;
-        double* u1 = u0 + n;
-        double* u2 = u1 + n;
-        double* l = u2 + n;
-        unsigned char* piv = (unsigned char*)(l + n);
-        for (int i = c0; i < c1; ++i) {
-            double* y = V + (long long)i * n;
-            for (int k = tid(); k < n; k += LSDD_WG) start_vector(y, i, k);
+        for (int b0 = c0; b0 < c1; b0 += 64) {
+            const int bn = min(64, c1 - b0), np = b0 - c0;
+            for (long long idx = tid(); idx < (long long)bn * n; idx += LSDD_WG) {
+                const int i = b0 + (int)(idx / n), k = (int)(idx % n);
+                start_vector(V + (long long)i * n, i, k);
+            }
             __syncthreads();
-            const double shift = lam[i] + (i - c0) * 2.0 * tiny;
             for (int it = 0; it < 4; ++it) {
-                if (tid() == 0) tri_shift_solve(d, e, n, shift, y, u0, u1, u2, l, piv, tiny);
+                if (tid() < bn) slot_solve(tid(), b0 + tid(), lam[b0 + tid()] + (b0 + tid() - c0) * 2.0 * tiny);
                 __syncthreads();
                 for (int pass = 0; pass < 2; ++pass) {
-                    for (int j = c0 + tid(); j < i; j += LSDD_WG) {
-                        const double* q = V + (long long)j * n;
-                        double s = 0.0;
-                        for (int k = 0; k < n; ++k) s += q[k] * y[k];
-                        dots[j - c0] = s;
+                    // against the earlier members of the cluster (in chunks of 64 members)
+                    for (int q0 = c0; q0 < b0; q0 += 64) {
+                        const int qn = min(64, b0 - q0);
+                        for (int pr = tid(); pr < qn * bn; pr += LSDD_WG) {
+                            const int j = q0 + pr % qn, t = pr / qn;
+                            const double* q = V + (long long)j * n;
+                            const double* y = V + (long long)(b0 + t) * n;
+                            double s = 0.0;
+                            for (int k = 0; k < n; ++k) s += q[k] * y[k];
+                            dd[pr] = s;
+                        }
+                        __syncthreads();
+                        for (long long idx = tid(); idx < (long long)bn * n; idx += LSDD_WG) {
+                            const int t = (int)(idx / n), k = (int)(idx % n);
+                            double s = 0.0;
+                            for (int j = 0; j < qn; ++j) s += V[(long long)(q0 + j) * n + k] * dd[j + t * qn];
+                            V[(long long)(b0 + t) * n + k] -= s;
+                        }
+                        __syncthreads();
                     }
-                    __syncthreads();
-                    for (int k = tid(); k < n; k += LSDD_WG) {
-                        double s = 0.0;
-                        for (int j = c0; j < i; ++j) s += V[(long long)j * n + k] * dots[j - c0];
-                        y[k] -= s;
+                    // within the batch, in index order, each member normalised before use
+                    for (int t = 0; t < bn; ++t) {
+                        double* y = V + (long long)(b0 + t) * n;
+                        if (t > 0) {
+                            for (int s0 = tid(); s0 < t; s0 += LSDD_WG) {
+                                const double* q = V + (long long)(b0 + s0) * n;
+                                double s = 0.0;
+                                for (int k = 0; k < n; ++k) s += q[k] * y[k];
+                                dots[s0] = s;
+                            }
+                            __syncthreads();
+                            for (int k = tid(); k < n; k += LSDD_WG) {
+                                double s = 0.0;
+                                for (int s0 = 0; s0 < t; ++s0) s += V[(long long)(b0 + s0) * n + k] * dots[s0];
+                                y[k] -= s;
+                            }
+                            __syncthreads();
+                        }
+                        double nr = 0.0;
+                        for (int k = tid(); k < n; k += LSDD_WG) nr += y[k] * y[k];
+                        nr = wg_sum(nr, red);
+                        const double sc = 1.0 / sqrt(nr);
+                        for (int k = tid(); k < n; k += LSDD_WG) y[k] *= sc;
+                        __syncthreads();
                     }
-                    __syncthreads();
                 }
-                double nr = 0.0;
-                for (int k = tid(); k < n; k += LSDD_WG) nr += y[k] * y[k];
-                nr = wg_sum(nr, red);
-                const double sc = 1.0 / sqrt(nr);
-                for (int k = tid(); k < n; k += LSDD_WG) y[k] *= sc;
-                __syncthreads();
             }
         }
     }

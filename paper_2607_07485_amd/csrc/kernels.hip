@@ -247,11 +247,13 @@ __global__ void __launch_bounds__(WG) k_local_assemble(LocalArgs A) {
 // bisection for all eigenvalues + inverse iteration for the retained vectors
 // only; then the retained-mode count (eq. tau-cut with cluster completion).
 // Writes mu (ascending, clamped at 0), k, and the first k eigenvectors of C into
-// W1 (nw x k, ld nw).
+// W1 (nw x k, ld nw).  Four launches (PHASE 0..3): reduction (or Jacobi),
+// eigenvalues and mode count, inverse iteration, back-transformation; the state
+// between them lives in the aggregate's global scratch.
+template <int PHASE>
 __global__ void __launch_bounds__(WG) k_local_eig(LocalArgs A) {
     __shared__ double s_red[WG / 64];
     __shared__ int s_flag;
-    __shared__ int s_k;
     __shared__ int s_ncl;
     extern __shared__ double s_dyn[];
     const int b = blockIdx.x;
@@ -264,38 +266,43 @@ __global__ void __launch_bounds__(WG) k_local_eig(LocalArgs A) {
     double* mu = A.mu + A.mu_off[ag];
     double* VS = W1;
     const bool small = nw <= 32;
-    if (small) {
-        int* pairs = (int*)s_dyn;
-        double* cs = s_dyn + 32;
-        int* rank = (int*)(s_dyn + 64);
-        double scale = 0.0;
-        for (int i = tid(); i < nw; i += WG) scale = fmax(scale, fabs(S[i + (int64_t)i * nw]));
-        scale = wg_max(scale, s_red);
-        wg_identity(V, nw, nw);
-        wg_jacobi(S, nw, nw, V, nw, 60, 1e-15, 1e-18 * fmax(scale, 1e-300), pairs, cs, &s_flag);
-        wg_sort_eig(S, nw, V, nw, nw, mu, VS, nw, rank);
-    } else {
-        wg_tridiag(S, nw, T, T + nw, T + 2 * nw, s_dyn, s_dyn + nw, s_red);
-        wg_bisect_all(T, T + nw, nw, mu, s_red);
-    }
-    for (int i = tid(); i < nw; i += WG) mu[i] = fmax(mu[i], 0.0);
-    __syncthreads();
-    if (tid() == 0) {
-        int k;
-        if (A.modes_fixed > 0) {
-            k = A.modes_fixed < nw ? A.modes_fixed : nw;
+    if (PHASE == 0) {
+        if (small) {
+            int* pairs = (int*)s_dyn;
+            double* cs = s_dyn + 32;
+            int* rank = (int*)(s_dyn + 64);
+            double scale = 0.0;
+            for (int i = tid(); i < nw; i += WG) scale = fmax(scale, fabs(S[i + (int64_t)i * nw]));
+            scale = wg_max(scale, s_red);
+            wg_identity(V, nw, nw);
+            wg_jacobi(S, nw, nw, V, nw, 60, 1e-15, 1e-18 * fmax(scale, 1e-300), pairs, cs, &s_flag);
+            wg_sort_eig(S, nw, V, nw, nw, mu, VS, nw, rank);
         } else {
-            k = 0;
-            const double thr = A.thr_agg ? A.thr_agg[ag] : A.thr;
-            while (k < nw && mu[k] < thr + A.band_tol) ++k;
+            wg_tridiag(S, nw, T, T + nw, T + 2 * nw, s_dyn, s_dyn + nw, s_red);
         }
-        while (k > 0 && k < nw && mu[k] - mu[k - 1] <= A.cluster_tol) ++k;
-        s_k = k;
-        A.k_out[ag] = k;
+        return;
     }
-    __syncthreads();
-    const int k = s_k;
-    if (!small && k > 0) {
+    if (PHASE == 1) {
+        if (!small) wg_bisect_all(T, T + nw, nw, mu, s_red);
+        for (int i = tid(); i < nw; i += WG) mu[i] = fmax(mu[i], 0.0);
+        __syncthreads();
+        if (tid() == 0) {
+            int k;
+            if (A.modes_fixed > 0) {
+                k = A.modes_fixed < nw ? A.modes_fixed : nw;
+            } else {
+                k = 0;
+                const double thr = A.thr_agg ? A.thr_agg[ag] : A.thr;
+                while (k < nw && mu[k] < thr + A.band_tol) ++k;
+            }
+            while (k > 0 && k < nw && mu[k] - mu[k - 1] <= A.cluster_tol) ++k;
+            A.k_out[ag] = k;
+        }
+        return;
+    }
+    const int k = A.k_out[ag];
+    if (small || k == 0) return;
+    if (PHASE == 2) {
         const double* d = T;
         const double* e = T + nw;
         double tnorm = 0.0;
@@ -304,8 +311,9 @@ __global__ void __launch_bounds__(WG) k_local_eig(LocalArgs A) {
         tnorm = wg_max(tnorm, s_red);
         wg_inverse_iteration(d, e, nw, mu, k, VS, T + 3 * nw, fmax(tnorm, 1e-300), (int*)s_dyn, s_dyn + nw, s_red,
                              &s_ncl);
-        wg_tridiag_backtransform(S, nw, T + 2 * nw, VS, k, s_dyn, s_dyn + nw);
+        return;
     }
+    wg_tridiag_backtransform(S, nw, T + 2 * nw, VS, k, s_dyn, s_dyn + nw);
 }
 
 // Z_i staged row-major (nw x k) from the column-major vectors in W1.
@@ -1049,7 +1057,10 @@ void launch_local_eig(int32_t nbatch, const LocalArgs& a, int32_t max_nw, hipStr
     if (nbatch <= 0) return;
     // dynamic LDS: tridiagonal work vectors, cluster starts and dots, 2 |omega| doubles
     const size_t lds = (size_t)std::max(2 * max_nw, 4096) * sizeof(double);
-    hipLaunchKernelGGL(k_local_eig, dim3(nbatch), dim3(WG), lds, st, a);
+    hipLaunchKernelGGL(k_local_eig<0>, dim3(nbatch), dim3(WG), lds, st, a);
+    hipLaunchKernelGGL(k_local_eig<1>, dim3(nbatch), dim3(WG), lds, st, a);
+    hipLaunchKernelGGL(k_local_eig<2>, dim3(nbatch), dim3(WG), lds, st, a);
+    hipLaunchKernelGGL(k_local_eig<3>, dim3(nbatch), dim3(WG), lds, st, a);
 }
 
 void launch_stage_z(int32_t nbatch, const LocalArgs& a, hipStream_t st) {

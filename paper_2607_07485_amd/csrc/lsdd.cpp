@@ -681,7 +681,7 @@ std::unique_ptr<Level> coarsen(lsdd_hierarchy* h, Level& lv, const int32_t* agg_
         int64_t bytes = 0;
         while (end < n_agg && (end - pos) < 32768) {
             int64_t m = C.sub_ptr[end + 1] - C.sub_ptr[end], nw = C.agg_ptr[end + 1] - C.agg_ptr[end];
-            int64_t tl = 3 * nw + 64 * 5 * nw;
+            int64_t tl = 3 * nw + 64 * 5 * nw + 64 * std::max<int64_t>(nw, 64);
             int64_t need = (2 * m * m + 2 * nw * nw + tl) * 8;
             if (end > pos && bytes + need > budget) break;
             bytes += need;
