@@ -166,6 +166,60 @@ def run_batch(a, torch, P, fegen, dev):
     print(json.dumps(out))
 
 
+def run_h2(a, torch, P, fegen, dev):
+    """Bicubic Hermite anisotropic hyperdiffusion on 256 x 256 (264,196 DOFs), eps = 1e-4 rotated
+    30 degrees, Nitsche clamp; threshold modes with tau_cut = max mult, at most 4 levels."""
+    N = a.N if a.N != 128 else 256
+    prob, b_np = fegen.hyperdiffusion_h2(N=N)
+    b = torch.from_numpy(b_np).to(dev)
+    prm = _params(P, max_levels=4, tau_const=1.0)
+    P.Hierarchy.setup_problem(fegen.hyperdiffusion_h2(N=8)[0], prm).close()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    h = P.Hierarchy.setup_problem(prob, prm)
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+    info = h.info()
+    print(f"[bench] h2 setup {setup_s:.2f} s, levels {info['n']}", file=sys.stderr, flush=True)
+    h.set_cycle_precision(0)
+    tuning = h.autotune(block=False)
+    h.set_graph(True)
+    res = {}
+    for prec in (0, 1):
+        h.set_cycle_precision(prec)
+        try:
+            x, inf = h.solve(b, allow_noconv=True)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(a.steps):
+                x, inf = h.solve(b, allow_noconv=True)
+            torch.cuda.synchronize()
+            dt = (time.perf_counter() - t0) / a.steps
+            res["fp32" if prec else "fp64"] = {"value": prob.n / dt, "ms_per_step": dt * 1e3, "iters": inf[0].iters,
+                                              "converged": bool(inf[0].converged)}
+        except P.LsddError as ex:
+            res["fp32" if prec else "fp64"] = {"converged": False, "error": str(ex)}
+        print(f"[bench] h2 prec {prec}: {res['fp32' if prec else 'fp64']}", file=sys.stderr, flush=True)
+    h.set_cycle_precision(0)
+    h.set_graph(False)
+    kernels, (dname, d) = _trace_dominant(h, torch, lambda: h.solve(b))
+    h.close()
+    ok = [k for k in ("fp64", "fp32") if res[k].get("converged")]
+    best = max(ok, key=lambda k: res[k]["value"])
+    achieved = d["bytes"] / (d["ms"] * 1e-3) / 1e9
+    out = {"metric": METRIC, "value": res[best]["value"], "unit": "DOF/s", "n_gpus": 1, "steps": a.steps,
+           "warmup": 1, "ms_per_step": res[best]["ms_per_step"], "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f32+f64" if best == "fp32" else "f64", "data": "synthetic",
+           "config": {"workload": f"hyperdiffusion_bfs_{N}x{N}", "n_dofs": prob.n, "levels": info["n"],
+                      "oc": round(info["oc"], 3)},
+           "setup_s": setup_s, "tuning": tuning, **res,
+           "roofline": {"bound": "hbm", "kernel": dname, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                        "avg_launch_us": d["ms"] * 1e3 / max(d["launches"], 1)},
+           "kernels": kernels, "cpu_baseline": None}
+    print(json.dumps(out))
+
+
 def run_q2grad(a, torch, P, fegen, dev):
     """Q2 hex elasticity on N^3 (default 24^3), theta ~ lognormal(0, 0.5); compliance J = b^T u and its
     gradient through the autograd Function (adjoint solve on the same hierarchy), checked by central
@@ -248,7 +302,7 @@ def main():
     ap.add_argument("--N", type=int, default=128)
     ap.add_argument("--cpu-sample", type=int, default=16)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", choices=["graddiv", "batch", "q2grad"], default="graddiv")
+    ap.add_argument("--workload", choices=["graddiv", "batch", "q2grad", "h2"], default="graddiv")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a device copy of 1 GiB five times (HBM counter calibration for profiling)")
     a = ap.parse_args()
@@ -280,6 +334,8 @@ def main():
             return run_batch(a, torch, P, fegen, dev)
         if a.workload == "q2grad":
             return run_q2grad(a, torch, P, fegen, dev)
+        if a.workload == "h2":
+            return run_h2(a, torch, P, fegen, dev)
         return run_graddiv(a, torch, P, fegen, dev)
 
 

@@ -9,6 +9,8 @@ mesh sizes, material parameters, element coefficients, right-hand sides):
   div term, beta = 1e-4 mass, 295,680 DOFs.
 * ``elasticity_batch``  64 Q1 instances, N_i ~ U{48..256}, nu_i ~ U(0.3, 0.49), 8 RHS.
 * ``elasticity_q2``     Q2 hexes on 24^3, theta_T ~ lognormal(0, 0.5), nu = 0.3.
+* ``hyperdiffusion_h2`` bicubic Hermite (BFS) anisotropic hyperdiffusion on 256x256, D rotated
+  30 degrees, anisotropy 1e-4, clamped by Nitsche, 264,196 DOFs.
 """
 from __future__ import annotations
 
@@ -51,3 +53,11 @@ def elasticity_q2(N: int = 24, seed: int = 0, nrhs: int = 1):
     theta = np.exp(0.5 * rng.standard_normal(N ** 3))
     prob = elasticity_q2hex(N, nu=0.3, E=1.0, theta=theta)
     return prob, rhs(prob.n, nrhs, rng), theta
+
+
+def hyperdiffusion_h2(N: int = 256, seed: int = 0, nrhs: int = 1, eps: float = 1e-4, theta: float = np.pi / 6):
+    """Clamped anisotropic hyperdiffusion on BFS elements (default 256 x 256 -> 264,196 DOFs); (problem, b)."""
+    from .hermite import hyperdiffusion_bfs
+    rng = np.random.default_rng(seed)
+    prob = hyperdiffusion_bfs(N, eps=eps, theta=theta)
+    return prob, rhs(prob.n, nrhs, rng)

@@ -67,6 +67,10 @@ class Params:
     spsd_tol: float = 1e-12
     rtol: float = 1e-8
     max_iter: int = 1000
+    # generalized inverse of A~_GammaGamma in the Schur complement: "pinv" (the paper's
+    # Moore-Penrose form, reading R4) or "cholesky" (reading R13: Cholesky, and when a
+    # pivot falls to |Gamma| eps max diag, Cholesky of the block shifted by that amount)
+    interface: str = "pinv"
 
 
 # ----------------------------------------------------------------- element factors (Sec. 5.2)
@@ -263,16 +267,46 @@ def local_splitting(omega_dofs: np.ndarray, cl_elems, elem_dofs, blocks, mult) -
     return At
 
 
-def schur_pinv(At: np.ndarray, nw: int) -> np.ndarray:
-    """S~ = A~_ww - A~_wG (A~_GG)^+ A~_Gw (eq. gep_reduced), pseudo-inverse via eigh.
+def cholesky_pivots(M: np.ndarray):
+    """Right-looking Cholesky M = L L^T with its pivots d_j (the diagonal entries
+    before the square root); a pivot <= 0 is recorded and replaced by 1."""
+    n = M.shape[0]
+    W = np.array(M, dtype=np.float64, copy=True)
+    piv = np.empty(n)
+    for j in range(n):
+        d = W[j, j]
+        piv[j] = d
+        s = np.sqrt(d) if d > 0 else 1.0
+        W[j, j] = s
+        W[j + 1:, j] /= s
+        W[j + 1:, j + 1:] -= np.outer(W[j + 1:, j], W[j + 1:, j])
+    return np.tril(W), piv
 
-    Eigenvalues of A~_GG above |Gamma| eps d_max form its range (reading R4).
+
+def schur_pinv(At: np.ndarray, nw: int, interface: str = "pinv") -> np.ndarray:
+    """S~ = A~_ww - A~_wG (A~_GG)^+ A~_Gw (eq. gep_reduced).
+
+    interface = "pinv": pseudo-inverse via eigh; eigenvalues of A~_GG above
+    |Gamma| eps d_max form its range (reading R4).  interface = "cholesky"
+    (reading R13): W = L^{-1} A~_Gw with A~_GG = L L^T; if the smallest pivot is
+    at most |Gamma| eps max diag(A~_GG), the block is factored again with that
+    tolerance added to its diagonal.  For an exactly singular PSD block whose
+    coupling lies in its range both give the same Schur complement.
     """
     Aww = At[:nw, :nw]
     if At.shape[0] == nw:
         return 0.5 * (Aww + Aww.T)
     AwG = At[:nw, nw:]
     AGG = At[nw:, nw:]
+    if interface == "cholesky":
+        ng = AGG.shape[0]
+        tol = ng * EPS * float(np.max(np.diag(AGG)))
+        L, piv = cholesky_pivots(AGG)
+        if not piv.min() > tol:
+            L, piv = cholesky_pivots(AGG + tol * np.eye(ng))
+        W = sla.solve_triangular(L, AwG.T, lower=True)
+        S = Aww - W.T @ W
+        return 0.5 * (S + S.T)
     d, V = np.linalg.eigh(AGG)
     dmax = max(float(d[-1]), 0.0)
     keep = d > AGG.shape[0] * EPS * dmax if dmax > 0 else np.zeros(len(d), bool)
@@ -390,7 +424,7 @@ def coarsen(lev: Level, params: Params, agg_of_dof=None):
         O = omegas[i]
         nw = len(aggs[i])
         At = local_splitting(O, cl[i], lev.elem_dofs, lev.blocks, mult)
-        S = schur_pinv(At, nw)
+        S = schur_pinv(At, nw, params.interface)
         Aww = lev.A[aggs[i]][:, aggs[i]].toarray()
         mu, V, L = local_spectral(S, Aww)
         k = select_modes(mu, params, lev.tau_cut)

@@ -58,3 +58,36 @@ def test_batch_preset_is_seeded():
     b = fegen.elasticity_batch(n_inst=3, nmin=4, nmax=8, nrhs=2)
     for (pa, ba), (pb, bb) in zip(a, b):
         assert pa.n == pb.n and np.array_equal(ba, bb) and ba.shape == (2, pa.n)
+
+
+def test_bfs_hyperdiffusion_blocks():
+    """BFS elements: symmetric SPSD blocks, the DOF count 4 (N+1)^2, and the interior energy of
+    polynomials represented exactly by bicubic Hermite interpolation equals the analytic
+    integral of q(u)^2 with q(u) = D11 u_xx + 2 D12 u_xy + D22 u_yy."""
+    from fegen.hermite import bfs_element_matrices, diffusion_tensor, hyperdiffusion_bfs
+    prob = hyperdiffusion_bfs(4)
+    assert prob.n == 4 * 25 and len(prob.elem_ptr) - 1 == 16
+    B = prob.blocks.reshape(-1, 16, 16)
+    for Be in B:
+        assert np.abs(Be - Be.T).max() <= 1e-12 * np.abs(Be).max()
+        ev = np.linalg.eigvalsh(Be)
+        assert ev[0] >= -1e-12 * ev[-1]
+    D = diffusion_tensor(1e-4, np.pi / 6)
+    h = 0.25
+    K = bfs_element_matrices(D, h)[0]
+    x0, y0 = 0.25, 0.5                                  # element corner; vertices in local order
+    verts = [(x0, y0), (x0 + h, y0), (x0, y0 + h), (x0 + h, y0 + h)]
+    # u, u_x, u_y, u_xy of test polynomials and their constant / affine q(u)
+    polys = {
+        "x2": (lambda x, y: (x * x, 2 * x, 0.0, 0.0), lambda x, y: 2 * D[0, 0]),
+        "xy": (lambda x, y: (x * y, y, x, 1.0), lambda x, y: 2 * D[0, 1]),
+        "y2": (lambda x, y: (y * y, 0.0, 2 * y, 0.0), lambda x, y: 2 * D[1, 1]),
+        "x2y": (lambda x, y: (x * x * y, 2 * x * y, x * x, 2 * x), lambda x, y: 2 * D[0, 0] * y + 4 * D[0, 1] * x),
+    }
+    for name, (f, q) in polys.items():
+        u = np.array([v for (x, y) in verts for v in f(x, y)])
+        # q is at most affine: the midpoint/vertex Simpson-type rule below is exact for q^2 (degree 2)
+        gx, gw = np.polynomial.legendre.leggauss(3)
+        exact = sum(wa * wb * q(x0 + h * (a + 1) / 2, y0 + h * (b + 1) / 2) ** 2
+                    for a, wa in zip(gx, gw) for b, wb in zip(gx, gw)) * h * h / 4
+        assert abs(u @ K @ u - exact) <= 1e-10 * abs(exact), name

@@ -357,3 +357,22 @@ def test_stationary_cycle_converges():
     x0 = np.random.default_rng(0).standard_normal(prob.n)
     x, info = oracle.stationary(h, b, x0, reduction=1e-10)
     assert info.converged and info.iters < 40
+
+
+def test_interface_readings_agree_on_singular_blocks_with_a_gap():
+    """Readings R4 (eigh pseudo-inverse) and R13 (regularised Cholesky) of the interface
+    generalized inverse give the same Schur complement when the singular block's spectrum
+    has a gap at the tolerance and the coupling lies in its range (Sec. 2, eq. gep_reduced)."""
+    rng = np.random.default_rng(5)
+    nw, ng, r = 6, 9, 5
+    H = rng.standard_normal((12, nw + ng))
+    H[:, nw:] = rng.standard_normal((12, r)) @ rng.standard_normal((r, ng))   # rank-r interface columns
+    At = H.T @ H
+    S1 = oracle.schur_pinv(At, nw, "pinv")
+    S2 = oracle.schur_pinv(At, nw, "cholesky")
+    assert np.abs(S1 - S2).max() <= 1e-6 * np.abs(S1).max()
+    # and the Cholesky pivots reproduce numpy's factor on an SPD block
+    M = H.T @ H + np.eye(nw + ng)
+    L, piv = oracle.lsdd.cholesky_pivots(M)
+    assert np.allclose(L, np.linalg.cholesky(M), rtol=1e-12, atol=1e-12)
+    assert np.allclose(piv, np.diag(L) ** 2, rtol=1e-12)
