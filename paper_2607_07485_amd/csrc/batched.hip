@@ -1,6 +1,11 @@
-// Batched tiled FP64 dense kernels (see batched.hpp).  Grid layout of every
+// Batched, tiled FP64 dense kernels (see batched.hpp).  Grid layout of every
 // launch: blockIdx.y = view index, blockIdx.x = tile job inside that view;
 // jobs past a view's own job count exit at once (views have different sizes).
+//
+// The factorisations are blocked with 64 x 64 tiles: the diagonal tile work
+// (unblocked Cholesky, triangular substitution) runs in LDS and registers,
+// every update of the trailing matrix runs on the FP64 matrix cores through
+// the tile contraction of mgemm.hpp.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -10,36 +15,75 @@
 #include <string>
 
 #include "batched.hpp"
+#include "mgemm.hpp"
 
 namespace lsdd {
 
 namespace {
 
-constexpr int TB = 32;
+constexpr int TB = 64;       // tile edge of the blocked algorithms
+constexpr int TT = 32;       // tile edge of the transpose
 constexpr int NT = 256;
 
 __device__ inline int t_id() { return (int)threadIdx.x; }
-
-__device__ inline void ld_tile(double (*t)[TB + 1], const double* a, const View& v, int r0, int c0) {
-    for (int idx = t_id(); idx < TB * TB; idx += NT) {
-        int i = idx % TB, j = idx / TB;
-        int r = r0 + i, c = c0 + j;
-        t[i][j] = (r < v.rows && c < v.cols) ? a[v.off + r + (int64_t)c * v.ld] : 0.0;
-    }
-}
-
-__device__ inline void st_tile(const double (*t)[TB + 1], double* a, const View& v, int r0, int c0) {
-    for (int idx = t_id(); idx < TB * TB; idx += NT) {
-        int i = idx % TB, j = idx / TB;
-        int r = r0 + i, c = c0 + j;
-        if (r < v.rows && c < v.cols) a[v.off + r + (int64_t)c * v.ld] = t[i][j];
-    }
-}
-
 __device__ inline int ntiles(int n) { return (n + TB - 1) / TB; }
+
+// 64 x 64 tile (rows r0.., cols c0..) into LDS, zero outside the view; if
+// `unit_pad`, padded diagonal entries are 1 (a padded triangular factor).
+__device__ inline void ld_tile64(double (*t)[TB + 1], const double* a, const View& v, int r0, int c0,
+                                 bool unit_pad = false) {
+    for (int idx = t_id(); idx < TB * TB; idx += NT) {
+        int i = idx % TB, j = idx / TB;
+        int r = r0 + i, c = c0 + j;
+        double x = (r < v.rows && c < v.cols) ? a[v.off + r + (int64_t)c * v.ld] : 0.0;
+        if (unit_pad && i == j && !(r < v.rows && c < v.cols)) x = 1.0;
+        t[i][j] = x;
+    }
+}
+
+// ---------------------------------------------------------------- substitution in registers
+//
+// 64 right-hand sides at once: thread t works on vector t / 4 and holds its
+// entries sub, sub + 4, ..., sub + 60 (sub = t % 4) in x[16]; the four lanes
+// of a vector are adjacent, so pivots are passed by lane shuffles.
+
+// L x = b (L lower, LDS), first nb rows
+__device__ inline void fwd_subst(const double (*L)[TB + 1], double (&x)[16], int nb) {
+    const int sub = t_id() & 3, base = (t_id() & 63) & ~3;
+#pragma unroll
+    for (int i = 0; i < TB; ++i) {
+        if (i < nb) {
+            double xi = x[i >> 2] / L[i][i];
+            xi = __shfl(xi, base | (i & 3), 64);
+            if (sub == (i & 3)) x[i >> 2] = xi;
+#pragma unroll
+            for (int q = 0; q < 16; ++q)
+                if (4 * q + sub > i) x[q] -= L[4 * q + sub][i] * xi;
+        }
+    }
+}
+
+// L^T x = b (L lower, LDS), first nb rows
+__device__ inline void bwd_subst(const double (*L)[TB + 1], double (&x)[16], int nb) {
+    const int sub = t_id() & 3, base = (t_id() & 63) & ~3;
+#pragma unroll
+    for (int i = TB - 1; i >= 0; --i) {
+        if (i < nb) {
+            double xi = x[i >> 2] / L[i][i];
+            xi = __shfl(xi, base | (i & 3), 64);
+            if (sub == (i & 3)) x[i >> 2] = xi;
+#pragma unroll
+            for (int q = 0; q < 16; ++q)
+                if (4 * q + sub < i) x[q] -= L[i][4 * q + sub] * xi;
+        }
+    }
+}
 
 // ---------------------------------------------------------------- Cholesky
 
+// unblocked Cholesky of diagonal tile kb (LDS); minpiv[view] tracks the
+// smallest pivot (a non-positive or NaN pivot is replaced by 1 so the
+// factorisation runs to the end; the caller reads minpiv)
 __global__ void __launch_bounds__(NT) k_potrf_diag(double* base, const View* views, int kb, double* minpiv) {
     __shared__ double t[TB][TB + 1];
     __shared__ double s_min;
@@ -47,7 +91,7 @@ __global__ void __launch_bounds__(NT) k_potrf_diag(double* base, const View* vie
     const int n = v.rows;
     if (kb * TB >= n) return;
     const int r0 = kb * TB, nb = min(TB, n - r0);
-    ld_tile(t, base, v, r0, r0);
+    ld_tile64(t, base, v, r0, r0);
     if (t_id() == 0) s_min = (kb == 0) ? INFINITY : minpiv[blockIdx.y];
     __syncthreads();
     for (int j = 0; j < nb; ++j) {
@@ -60,9 +104,10 @@ __global__ void __launch_bounds__(NT) k_potrf_diag(double* base, const View* vie
         const double s = t[j][j];
         for (int i = j + 1 + t_id(); i < nb; i += NT) t[i][j] /= s;
         __syncthreads();
-        for (int idx = t_id(); idx < nb * nb; idx += NT) {
-            int i = idx % nb, k = idx / nb;
-            if (i > j && k > j && i >= k) t[i][k] -= t[i][j] * t[k][j];
+        const int m = nb - j - 1;
+        for (int idx = t_id(); idx < m * m; idx += NT) {
+            int i = j + 1 + idx % m, k = j + 1 + idx / m;
+            if (i >= k) t[i][k] -= t[i][j] * t[k][j];
         }
         __syncthreads();
     }
@@ -73,196 +118,205 @@ __global__ void __launch_bounds__(NT) k_potrf_diag(double* base, const View* vie
     if (t_id() == 0) minpiv[blockIdx.y] = s_min;
 }
 
-// L_ib,kb = A_ib,kb L_kk^{-T}, ib = kb + 1 + blockIdx.x
+// L_ib,kb = A_ib,kb L_kk^{-T}, ib = kb + 1 + blockIdx.x: each row solves
+// L_kk x^T = a^T (forward substitution)
 __global__ void __launch_bounds__(NT) k_potrf_panel(double* base, const View* views, int kb) {
     __shared__ double L[TB][TB + 1];
-    __shared__ double X[TB][TB + 1];
     const View v = views[blockIdx.y];
-    const int nt = ntiles(v.rows);
+    const int n = v.rows;
+    const int nt = ntiles(n);
     const int ib = kb + 1 + (int)blockIdx.x;
     if (ib >= nt) return;
-    const int nb = min(TB, v.rows - kb * TB);
-    ld_tile(L, base, v, kb * TB, kb * TB);
-    ld_tile(X, base, v, ib * TB, kb * TB);
+    const int nb = min(TB, n - kb * TB);
+    ld_tile64(L, base, v, kb * TB, kb * TB, true);
     __syncthreads();
-    // x L^T = a per row: 8 threads per row split nothing; rows independent
-    if (t_id() < TB) {
-        const int r = t_id();
-        for (int j = 0; j < nb; ++j) {
-            double s = X[r][j];
-            for (int k = 0; k < j; ++k) s -= X[r][k] * L[j][k];
-            X[r][j] = s / L[j][j];
+    const int r = ib * TB + t_id() / 4, sub = t_id() & 3;
+    double x[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+        const int c = kb * TB + 4 * q + sub;
+        x[q] = (r < n && 4 * q + sub < nb) ? base[v.off + r + (int64_t)c * v.ld] : 0.0;
+    }
+    fwd_subst(L, x, nb);
+    if (r < n) {
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            const int c = kb * TB + 4 * q + sub;
+            if (4 * q + sub < nb) base[v.off + r + (int64_t)c * v.ld] = x[q];
         }
     }
-    __syncthreads();
-    st_tile(X, base, v, ib * TB, kb * TB);
 }
 
-// A_ib,jb -= L_ib,kb L_jb,kb^T for kb < jb <= ib (lower tiles)
+// A_ib,jb -= L_ib,kb L_jb,kb^T for kb < jb <= ib (lower tiles), matrix cores
 __global__ void __launch_bounds__(NT) k_potrf_update(double* base, const View* views, int kb) {
-    __shared__ double Li[TB][TB + 1];
-    __shared__ double Lj[TB][TB + 1];
+    __shared__ mg::Smem sm;
     const View v = views[blockIdx.y];
-    const int nt = ntiles(v.rows);
+    const int n = v.rows;
+    const int nt = ntiles(n);
     const int m = nt - kb - 1;
     int t = (int)blockIdx.x;
     if (m <= 0 || t >= m * (m + 1) / 2) return;
     int jj = 0;
     while (t >= m - jj) { t -= m - jj; ++jj; }
     const int jb = kb + 1 + jj, ib = jb + t;
-    ld_tile(Li, base, v, ib * TB, kb * TB);
-    ld_tile(Lj, base, v, jb * TB, kb * TB);
-    __syncthreads();
-    for (int idx = t_id(); idx < TB * TB; idx += NT) {
-        int i = idx % TB, j = idx / TB;
-        int r = ib * TB + i, c = jb * TB + j;
-        if (r < v.rows && c < v.cols && r >= c) {
-            double s = 0.0;
-#pragma unroll 8
-            for (int k = 0; k < TB; ++k) s += Li[i][k] * Lj[j][k];
-            base[v.off + r + (int64_t)c * v.ld] -= s;
-        }
-    }
+    const int K = min(TB, n - kb * TB);
+    const double* pan = base + v.off + (int64_t)(kb * TB) * v.ld;     // column block kb
+    mg::d4 acc[2][2];
+    mg::zero(acc);
+    mg::tile_mma<mg::IMAJ, mg::IMAJ>(sm, pan, v.ld, ib * TB, n, pan, v.ld, jb * TB, n, 0, K, acc);
+#pragma unroll
+    for (int p = 0; p < 2; ++p)
+#pragma unroll
+        for (int q = 0; q < 2; ++q)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int i = mg::acc_row(p, e), j = mg::acc_col(q);
+                const int r = ib * TB + i, c = jb * TB + j;
+                if (r < n && c < n && (ib != jb || i >= j)) base[v.off + r + (int64_t)c * v.ld] -= acc[p][q][e];
+            }
 }
 
 // ---------------------------------------------------------------- triangular solves
 
 // step s of L X = B (forward, kb = s) or L^T X = B (backward, kb = nt-1-s):
-// solve the diagonal tile for every column tile of B.
+// solve the diagonal tile for column tile jc = blockIdx.x of B.  lower_b: B is
+// lower triangular (forward only), so column tiles jc > kb are still zero.
 __global__ void __launch_bounds__(NT) k_trsm_diag(const double* lbase, const View* lv, double* bbase, const View* bv,
-                                                  int s, int trans) {
+                                                  int s, int trans, int lower_b) {
     __shared__ double L[TB][TB + 1];
-    __shared__ double B[TB][TB + 1];
     const View l = lv[blockIdx.y], b = bv[blockIdx.y];
-    const int nt = ntiles(l.rows);
+    const int n = l.rows;
+    const int nt = ntiles(n);
     if (s >= nt) return;
     const int kb = trans ? nt - 1 - s : s;
     const int jc = (int)blockIdx.x;
-    if (jc * TB >= b.cols) return;
-    const int nb = min(TB, l.rows - kb * TB);
-    ld_tile(L, lbase, l, kb * TB, kb * TB);
-    ld_tile(B, bbase, b, kb * TB, jc * TB);
+    if (jc * TB >= b.cols || (lower_b && jc > kb)) return;
+    const int nb = min(TB, n - kb * TB);
+    ld_tile64(L, lbase, l, kb * TB, kb * TB, true);
     __syncthreads();
-    if (t_id() < TB) {
-        const int c = t_id();
-        if (!trans) {
-            for (int i = 0; i < nb; ++i) {
-                double v = B[i][c];
-                for (int k = 0; k < i; ++k) v -= L[i][k] * B[k][c];
-                B[i][c] = v / L[i][i];
-            }
-        } else {
-            for (int i = nb - 1; i >= 0; --i) {
-                double v = B[i][c];
-                for (int k = i + 1; k < nb; ++k) v -= L[k][i] * B[k][c];
-                B[i][c] = v / L[i][i];
-            }
+    const int c = jc * TB + t_id() / 4, sub = t_id() & 3;
+    double x[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+        const int r = kb * TB + 4 * q + sub;
+        x[q] = (c < b.cols && 4 * q + sub < nb) ? bbase[b.off + r + (int64_t)c * b.ld] : 0.0;
+    }
+    if (!trans) fwd_subst(L, x, nb);
+    else bwd_subst(L, x, nb);
+    if (c < b.cols) {
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            const int r = kb * TB + 4 * q + sub;
+            if (4 * q + sub < nb) bbase[b.off + r + (int64_t)c * b.ld] = x[q];
         }
     }
-    __syncthreads();
-    st_tile(B, bbase, b, kb * TB, jc * TB);
 }
 
-// update: forward B_ib -= L_ib,kb X_kb (ib > kb); backward B_ib -= L_kb,ib^T X_kb (ib < kb)
+// forward B_ib -= L_ib,kb X_kb (ib > kb); backward B_ib -= L_kb,ib^T X_kb (ib < kb)
 __global__ void __launch_bounds__(NT) k_trsm_update(const double* lbase, const View* lv, double* bbase, const View* bv,
-                                                    int s, int trans) {
-    __shared__ double L[TB][TB + 1];
-    __shared__ double X[TB][TB + 1];
+                                                    int s, int trans, int lower_b) {
+    __shared__ mg::Smem sm;
     const View l = lv[blockIdx.y], b = bv[blockIdx.y];
-    const int nt = ntiles(l.rows);
+    const int n = l.rows;
+    const int nt = ntiles(n);
     if (s >= nt) return;
     const int kb = trans ? nt - 1 - s : s;
-    const int nct = ntiles(b.cols);
-    const int nrow = trans ? kb : nt - kb - 1;     // tiles to update
+    int nct = ntiles(b.cols);
+    if (lower_b) nct = min(nct, kb + 1);
+    const int nrow = trans ? kb : nt - kb - 1;
     const int job = (int)blockIdx.x;
     if (job >= nrow * nct) return;
     const int ib = trans ? job % nrow : kb + 1 + job % nrow;
     const int jc = job / nrow;
-    if (!trans) ld_tile(L, lbase, l, ib * TB, kb * TB);
-    else ld_tile(L, lbase, l, kb * TB, ib * TB);
-    ld_tile(X, bbase, b, kb * TB, jc * TB);
-    __syncthreads();
-    for (int idx = t_id(); idx < TB * TB; idx += NT) {
-        int i = idx % TB, j = idx / TB;
-        int r = ib * TB + i, c = jc * TB + j;
-        if (r < b.rows && c < b.cols) {
-            double acc = 0.0;
-            if (!trans) {
-#pragma unroll 8
-                for (int k = 0; k < TB; ++k) acc += L[i][k] * X[k][j];
-            } else {
-#pragma unroll 8
-                for (int k = 0; k < TB; ++k) acc += L[k][i] * X[k][j];
-            }
-            bbase[b.off + r + (int64_t)c * b.ld] -= acc;
-        }
+    const int K = min(TB, n - kb * TB);
+    const double* xk = bbase + b.off + kb * TB;                       // X_kb: element (k, j) at xk[k + j ld]
+    mg::d4 acc[2][2];
+    mg::zero(acc);
+    if (!trans) {
+        const double* lp = lbase + l.off + (int64_t)(kb * TB) * l.ld;  // L[:, kb]: (k, i) at lp[i + k ld]
+        mg::tile_mma<mg::IMAJ, mg::KMAJ>(sm, lp, l.ld, ib * TB, n, xk, b.ld, jc * TB, b.cols, 0, K, acc);
+    } else {
+        const double* lp = lbase + l.off + kb * TB;                    // L[kb, :]: (k, i) at lp[k + i ld]
+        mg::tile_mma<mg::KMAJ, mg::KMAJ>(sm, lp, l.ld, ib * TB, n, xk, b.ld, jc * TB, b.cols, 0, K, acc);
     }
+#pragma unroll
+    for (int p = 0; p < 2; ++p)
+#pragma unroll
+        for (int q = 0; q < 2; ++q)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int r = ib * TB + mg::acc_row(p, e), c = jc * TB + mg::acc_col(q);
+                if (r < b.rows && c < b.cols) bbase[b.off + r + (int64_t)c * b.ld] -= acc[p][q][e];
+            }
 }
 
 // ---------------------------------------------------------------- C = beta C_in - alpha A^T B
 
 __global__ void __launch_bounds__(NT) k_gemm_tn(const double* abase, const View* av, const double* bbase,
                                                 const View* bv, const double* cinbase, const View* civ, double beta,
-                                                double* coutbase, const View* cov, double alpha, int tri_k) {
-    __shared__ double As[TB][TB + 1];
-    __shared__ double Bs[TB][TB + 1];
+                                                double* coutbase, const View* cov, double alpha, int tri_k, int sym) {
+    __shared__ mg::Smem sm;
     const View a = av[blockIdx.y], b = bv[blockIdx.y], co = cov[blockIdx.y];
     const int mt = ntiles(co.rows), ntt = ntiles(co.cols);
-    const int job = (int)blockIdx.x;
-    if (job >= mt * ntt) return;
-    const int it = job % mt, jt = job / mt;
-    const int kt = ntiles(a.rows);
-    double acc[4] = {0.0, 0.0, 0.0, 0.0};
-    for (int kb = tri_k ? max(it, jt) : 0; kb < kt; ++kb) {
-        ld_tile(As, abase, a, kb * TB, it * TB);
-        ld_tile(Bs, bbase, b, kb * TB, jt * TB);
-        __syncthreads();
+    int it, jt;
+    int job = (int)blockIdx.x;
+    if (sym) {
+        if (job >= mt * (mt + 1) / 2) return;
+        jt = 0;
+        while (job >= mt - jt) { job -= mt - jt; ++jt; }
+        it = jt + job;
+    } else {
+        if (job >= mt * ntt) return;
+        it = job % mt;
+        jt = job / mt;
+    }
+    const int kbeg = tri_k ? max(it, jt) * TB : 0;
+    mg::d4 acc[2][2];
+    mg::zero(acc);
+    mg::tile_mma<mg::KMAJ, mg::KMAJ>(sm, abase + a.off, a.ld, it * TB, a.cols, bbase + b.off, b.ld, jt * TB, b.cols,
+                                     kbeg, a.rows, acc);
+    const View ci = civ[blockIdx.y];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            int idx = t_id() + q * NT;
-            int i = idx % TB, j = idx / TB;
-            double s = 0.0;
-#pragma unroll 8
-            for (int k = 0; k < TB; ++k) s += As[k][i] * Bs[k][j];
-            acc[q] += s;
-        }
-        __syncthreads();
-    }
-    for (int q = 0; q < 4; ++q) {
-        int idx = t_id() + q * NT;
-        int i = idx % TB, j = idx / TB;
-        int r = it * TB + i, c = jt * TB + j;
-        if (r < co.rows && c < co.cols) {
-            double v = -alpha * acc[q];
-            if (beta != 0.0) {
-                const View ci = civ[blockIdx.y];
-                v += beta * cinbase[ci.off + r + (int64_t)c * ci.ld];
+    for (int p = 0; p < 2; ++p)
+#pragma unroll
+        for (int q = 0; q < 2; ++q)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int r = it * TB + mg::acc_row(p, e), c = jt * TB + mg::acc_col(q);
+                if (r < co.rows && c < co.cols) {
+                    double x = -alpha * acc[p][q][e];
+                    if (beta != 0.0) x += beta * cinbase[ci.off + r + (int64_t)c * ci.ld];
+                    coutbase[co.off + r + (int64_t)c * co.ld] = x;
+                    if (sym && it != jt) coutbase[co.off + c + (int64_t)r * co.ld] = x;
+                }
             }
-            coutbase[co.off + r + (int64_t)c * co.ld] = v;
-        }
-    }
 }
 
 // ---------------------------------------------------------------- transpose
 
 __global__ void __launch_bounds__(NT) k_transpose(double* base, const View* views) {
-    __shared__ double P[TB][TB + 1];
-    __shared__ double Q[TB][TB + 1];
+    __shared__ double P[TT][TT + 1];
+    __shared__ double Q[TT][TT + 1];
     const View v = views[blockIdx.y];
-    const int nt = ntiles(v.rows);
+    const int nt = (v.rows + TT - 1) / TT;
     int t = (int)blockIdx.x;
     if (t >= nt * (nt + 1) / 2) return;
     int jt = 0;
     while (t > jt) { t -= jt + 1; ++jt; }
     const int it = t;   // it <= jt
-    ld_tile(P, base, v, it * TB, jt * TB);
-    ld_tile(Q, base, v, jt * TB, it * TB);
+    for (int idx = t_id(); idx < TT * TT; idx += NT) {
+        int i = idx % TT, j = idx / TT;
+        int r = it * TT + i, c = jt * TT + j;
+        P[i][j] = (r < v.rows && c < v.cols) ? base[v.off + r + (int64_t)c * v.ld] : 0.0;
+        int r2 = jt * TT + i, c2 = it * TT + j;
+        Q[i][j] = (r2 < v.rows && c2 < v.cols) ? base[v.off + r2 + (int64_t)c2 * v.ld] : 0.0;
+    }
     __syncthreads();
-    for (int idx = t_id(); idx < TB * TB; idx += NT) {
-        int i = idx % TB, j = idx / TB;
-        int r = it * TB + i, c = jt * TB + j;
+    for (int idx = t_id(); idx < TT * TT; idx += NT) {
+        int i = idx % TT, j = idx / TT;
+        int r = it * TT + i, c = jt * TT + j;
         if (r < v.rows && c < v.cols) base[v.off + r + (int64_t)c * v.ld] = Q[j][i];
-        int r2 = jt * TB + i, c2 = it * TB + j;
+        int r2 = jt * TT + i, c2 = it * TT + j;
         if (r2 < v.rows && c2 < v.cols) base[v.off + r2 + (int64_t)c2 * v.ld] = P[j][i];
     }
 }
@@ -294,9 +348,9 @@ void Batched::free_all() {
     slot_cap = 0;
 }
 
-static int max_tiles(const std::vector<View>& v, bool rows) {
+static int max_tiles(const std::vector<View>& v, bool rows, int tb = TB) {
     int m = 0;
-    for (const View& x : v) m = std::max(m, ((rows ? x.rows : x.cols) + TB - 1) / TB);
+    for (const View& x : v) m = std::max(m, ((rows ? x.rows : x.cols) + tb - 1) / tb);
     return m;
 }
 
@@ -317,8 +371,9 @@ void Batched::potrf(double* base, const std::vector<View>& a, double* d_minpiv) 
 }
 
 void Batched::trsm(const double* lbase, const std::vector<View>& l, double* bbase, const std::vector<View>& b,
-                   bool trans) {
+                   bool trans, bool lower_b) {
     if (l.empty()) return;
+    if (trans && lower_b) throw std::runtime_error("batched trsm: lower_b applies to forward solves only");
     View* d1 = put(0, l);
     View* d2 = put(1, b);
     const unsigned nm = (unsigned)l.size();
@@ -326,28 +381,37 @@ void Batched::trsm(const double* lbase, const std::vector<View>& l, double* bbas
     const int nct = max_tiles(b, false);
     if (nct == 0) return;
     for (int s = 0; s < nt; ++s) {
-        hipLaunchKernelGGL(k_trsm_diag, dim3(nct, nm), dim3(NT), 0, st, lbase, d1, bbase, d2, s, trans ? 1 : 0);
-        const int jobs = (nt - 1) * nct;
+        hipLaunchKernelGGL(k_trsm_diag, dim3(nct, nm), dim3(NT), 0, st, lbase, d1, bbase, d2, s, trans ? 1 : 0,
+                           lower_b ? 1 : 0);
+        const int rows = trans ? nt - 1 - s : nt - 1 - s;     // most tiles any view updates at this step
+        const int cols = lower_b ? std::min(nct, s + 1) : nct;
+        const int jobs = rows * cols;
         if (jobs > 0)
-            hipLaunchKernelGGL(k_trsm_update, dim3(jobs, nm), dim3(NT), 0, st, lbase, d1, bbase, d2, s, trans ? 1 : 0);
+            hipLaunchKernelGGL(k_trsm_update, dim3(jobs, nm), dim3(NT), 0, st, lbase, d1, bbase, d2, s,
+                               trans ? 1 : 0, lower_b ? 1 : 0);
     }
     chk(hipGetLastError(), "batched trsm");
 }
 
 void Batched::gemm_tn(const double* abase, const std::vector<View>& a, const double* bbase, const std::vector<View>& b,
                       const double* cinbase, const std::vector<View>& cin, double beta, double* coutbase,
-                      const std::vector<View>& cout, double alpha, bool tri_k) {
+                      const std::vector<View>& cout, double alpha, bool tri_k, bool sym) {
     if (a.empty()) return;
+    if (sym && beta != 0.0) throw std::runtime_error("batched gemm_tn: sym needs beta = 0");
     View* d1 = put(0, a);
     View* d2 = put(1, b);
     View* d3 = put(2, cout);
     View* d4 = beta != 0.0 ? put(3, cin) : d3;
     const unsigned nm = (unsigned)a.size();
-    int mt = 0;
-    for (const View& x : cout) mt = std::max(mt, ((x.rows + TB - 1) / TB) * ((x.cols + TB - 1) / TB));
+    int64_t mt = 0;
+    for (const View& x : cout) {
+        const int64_t r = (x.rows + TB - 1) / TB, c = (x.cols + TB - 1) / TB;
+        mt = std::max(mt, sym ? r * (r + 1) / 2 : r * c);
+    }
     if (mt == 0) return;
-    hipLaunchKernelGGL(k_gemm_tn, dim3(mt, nm), dim3(NT), 0, st, abase, d1, bbase, d2, cinbase, d4, beta, coutbase,
-                       d3, alpha, tri_k ? 1 : 0);
+    if (mt > INT32_MAX) throw std::runtime_error("batched gemm_tn: too many tiles");
+    hipLaunchKernelGGL(k_gemm_tn, dim3((unsigned)mt, nm), dim3(NT), 0, st, abase, d1, bbase, d2, cinbase, d4, beta,
+                       coutbase, d3, alpha, tri_k ? 1 : 0, sym ? 1 : 0);
     chk(hipGetLastError(), "batched gemm_tn");
 }
 
@@ -355,7 +419,7 @@ void Batched::transpose(double* base, const std::vector<View>& a) {
     if (a.empty()) return;
     View* d1 = put(0, a);
     const unsigned nm = (unsigned)a.size();
-    const int nt = max_tiles(a, true);
+    const int nt = max_tiles(a, true, TT);
     hipLaunchKernelGGL(k_transpose, dim3(nt * (nt + 1) / 2, nm), dim3(NT), 0, st, base, d1);
     chk(hipGetLastError(), "batched transpose");
 }

@@ -1,7 +1,8 @@
 // Batched, tiled FP64 dense kernels for the local problems of many
 // aggregates at once (variable sizes).  A matrix "view" is a column-major
 // block at base + off with leading dimension ld; every operation runs tile
-// jobs (32 x 32, staged in LDS) of all views of the batch in the same launch.
+// jobs (64 x 64) of all views of the batch in the same launch, the
+// contractions on the FP64 matrix cores.
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -36,14 +37,18 @@ struct Batched {
     void potrf(double* base, const std::vector<View>& a, double* d_minpiv);
     // B <- L^{-1} B (trans = false) or B <- L^{-T} B (trans = true) with L the
     // lower triangle of the square view l[b] and B the view b[b] (rows = n).
+    // lower_b (forward only): B is lower triangular (e.g. the identity), so
+    // column tiles right of the current diagonal tile are skipped.
     void trsm(const double* lbase, const std::vector<View>& l, double* bbase, const std::vector<View>& b,
-              bool trans);
+              bool trans, bool lower_b = false);
     // C_out = beta * C_in - alpha * A^T B for views (A: K x M, B: K x N,
     // C: M x N).  beta = 0 ignores C_in.  tri_k: A and B are lower triangular,
-    // so the K loop of output tile (i, j) starts at tile max(i, j).
+    // so the K loop of output tile (i, j) starts at tile max(i, j).  sym: the
+    // result is symmetric (A = B, beta = 0): only lower tiles are computed and
+    // each is also stored mirrored.
     void gemm_tn(const double* abase, const std::vector<View>& a, const double* bbase, const std::vector<View>& b,
                  const double* cinbase, const std::vector<View>& cin, double beta, double* coutbase,
-                 const std::vector<View>& cout, double alpha, bool tri_k = false);
+                 const std::vector<View>& cout, double alpha, bool tri_k = false, bool sym = false);
     // In-place transpose of square views.
     void transpose(double* base, const std::vector<View>& a);
 };

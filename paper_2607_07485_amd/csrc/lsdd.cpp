@@ -800,10 +800,10 @@ std::unique_ptr<Level> coarsen(lsdd_hierarchy* h, Level& lv, const int32_t* agg_
         launch_stage_z(nb, B, st);
         // subdomain inverse A_Omega^{-1} = L^{-T} L^{-1}
         launch_views_identity(nb, w1, bt.put(0, vAO), st);
-        bt.trsm(w2, vAO, w1, vAO, false);
+        bt.trsm(w2, vAO, w1, vAO, false, true);                             // X = L^{-1} (lower)
         std::vector<View> vInv(nb);
         for (int32_t b = 0; b < nb; ++b) vInv[b] = View{msq[pos + b], vAO[b].rows, vAO[b].rows, vAO[b].rows, 0};
-        bt.gemm_tn(w1, vAO, w1, vAO, nullptr, vInv, 0.0, lv.d_inv, vInv, -1.0, true);
+        bt.gemm_tn(w1, vAO, w1, vAO, nullptr, vInv, 0.0, lv.d_inv, vInv, -1.0, true, true);   // X^T X
         HIPCHK(hipGetLastError());
         sync(st);
         vlog("  batch of %d aggregates from %d done (%.3f s since start)", nb, pos, now_s() - tc0);
