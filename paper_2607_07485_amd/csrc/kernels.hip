@@ -385,68 +385,30 @@ __global__ void k_z_compact(const int64_t* agg_ptr, const int32_t* k, const int6
 
 // ====================================================================== Galerkin products
 
-// One workgroup per coarse group g: for each member element e build
-// P_e = P[S_e, S_g] (block-structured by aggregate), then accumulate
-// (G_e P_e)^T (G_e P_e) (level 0, Gram factors) or P_e^T A_e P_e.
-__global__ void __launch_bounds__(WG) k_galerkin(GalerkinArgs g) {
-    const int gi = blockIdx.x;
+// Stacked interpolation rows of coarse group g = g0 + blockIdx.x: member e
+// (in member order) contributes the n_e rows P_e = P[S_e, S_g], block
+// structured by aggregate; column-major R_g x c_g with R_g = sum of n_e.
+__global__ void __launch_bounds__(WG) k_build_pst(PstArgs g) {
+    const int gi = g.g0 + (int)blockIdx.x;
     const int c = (int)(g.cptr[gi + 1] - g.cptr[gi]);
-    double* out = g.cblocks + g.cblk_off[gi];
-    double* Pe = g.ws + g.ws_off[gi];
-    wg_zero(out, (int64_t)c * c);
+    const int64_t R = g.rows[blockIdx.x];
+    double* P = g.pst + g.pst_off[blockIdx.x];
+    int64_t row0 = 0;
     for (int64_t mi = g.mem_ptr[gi]; mi < g.mem_ptr[gi + 1]; ++mi) {
         const int32_t e = g.mem_elems[mi];
         const int ne = (int)(g.felem_ptr[e + 1] - g.felem_ptr[e]);
-        double* X = Pe + (int64_t)ne * c;
         const int64_t pm = g.pm_off[mi];
-        // P_e row-major ne x c
         for (int idx = tid(); idx < ne * c; idx += WG) {
-            int a = idx / c, col = idx % c;
+            const int a = idx % ne, col = idx / ne;
             double v = 0.0;
-            int64_t zr = g.pm_zrow[pm + a];
+            const int64_t zr = g.pm_zrow[pm + a];
             if (zr >= 0) {
-                int s = col - g.pm_col[pm + a];
+                const int s = col - g.pm_col[pm + a];
                 if (s >= 0 && s < g.pm_k[pm + a]) v = g.Z[zr + s];
             }
-            Pe[idx] = v;
+            P[row0 + a + (int64_t)col * R] = v;
         }
-        __syncthreads();
-        const double* F = g.fblocks + g.fblk_off[e];   // ne x ne row-major
-        // X = F P_e (ne x c)
-        for (int idx = tid(); idx < ne * c; idx += WG) {
-            int r = idx / c, col = idx % c;
-            double s = 0.0;
-            for (int a = 0; a < ne; ++a) s += F[r * ne + a] * Pe[a * c + col];
-            X[idx] = s;
-        }
-        __syncthreads();
-        if (g.use_gram) {
-            // out += X^T X  (rows of G beyond the rank are zero)
-            for (int idx = tid(); idx < c * c; idx += WG) {
-                int i = idx / c, j = idx % c;
-                double s = 0.0;
-                for (int r = 0; r < ne; ++r) s += X[r * c + i] * X[r * c + j];
-                out[idx] += s;
-            }
-        } else {
-            // out += P_e^T X
-            for (int idx = tid(); idx < c * c; idx += WG) {
-                int i = idx / c, j = idx % c;
-                double s = 0.0;
-                for (int a = 0; a < ne; ++a) s += Pe[a * c + i] * X[a * c + j];
-                out[idx] += s;
-            }
-        }
-        __syncthreads();
-    }
-    // exact symmetry
-    for (int idx = tid(); idx < c * c; idx += WG) {
-        int i = idx / c, j = idx % c;
-        if (i < j) {
-            double s = 0.5 * (out[i * c + j] + out[j * c + i]);
-            out[i * c + j] = s;
-            out[j * c + i] = s;
-        }
+        row0 += ne;
     }
 }
 
@@ -1087,9 +1049,9 @@ void launch_z_compact(int32_t n_agg, const int64_t* agg_ptr, const int32_t* k, c
     hipLaunchKernelGGL(k_z_compact, dim3(n_agg), dim3(WG), 0, st, agg_ptr, k, zst_off, zst, zoff, Z, Zc, Zc32);
 }
 
-void launch_galerkin(const GalerkinArgs& g, hipStream_t st) {
+void launch_build_pst(const PstArgs& g, hipStream_t st) {
     if (g.n_groups <= 0) return;
-    hipLaunchKernelGGL(k_galerkin, dim3(g.n_groups), dim3(WG), 0, st, g);
+    hipLaunchKernelGGL(k_build_pst, dim3(g.n_groups), dim3(WG), 0, st, g);
 }
 
 void launch_dense_from_csr(int64_t off, int64_t n, const int64_t* rowptr, const int32_t* col, const double* val, double* D,

@@ -84,8 +84,13 @@ void launch_views_identity(int32_t nv, double* base, const View* v, hipStream_t 
 void launch_z_compact(int32_t n_agg, const int64_t* agg_ptr, const int32_t* k, const int64_t* zst_off,
                       const double* zst, const int64_t* zoff, double* Z, double* Zc, float* Zc32, hipStream_t st);
 
-struct GalerkinArgs {
-    int32_t n_groups;
+// Galerkin products run as batched matrix-core contractions over stacked
+// interpolation rows: for coarse group g with members e (fine element blocks
+// F_e, n_e x n_e row-major) and stacked P_g = [P_e] (R_g x c_g),
+// Y_e = F_e P_e, then A_g = Y^T Y (level 0, F_e = Gram factor G_e) or
+// A_g = P_g^T Y (F_e = A_e).  This kernel writes P_g.
+struct PstArgs {
+    int32_t g0, n_groups;          // groups g0 .. g0 + n_groups - 1
     const int64_t* cptr;           // coarse group supports (sizes c_g)
     const int64_t* mem_ptr;        // members of group g
     const int32_t* mem_elems;
@@ -95,15 +100,11 @@ struct GalerkinArgs {
     const int32_t* pm_k;           //   modes of its aggregate
     const int32_t* pm_col;         //   column offset of its aggregate in the group support
     const double* Z;
-    int32_t use_gram;              // 1: X = G_e P_e, block += X^T X; 0: block += P_e^T A_e P_e
-    const int64_t* fblk_off;       // fine blocks (G padded n_e x n_e, or A_e), row-major
-    const double* fblocks;
-    const int64_t* ws_off;         // per group scratch offset (2 * n_e_max * c_g)
-    double* ws;
-    const int64_t* cblk_off;       // output coarse blocks c_g x c_g
-    double* cblocks;
+    const int64_t* pst_off;        // per group of the launch: offset of P_g
+    const int64_t* rows;           //   R_g
+    double* pst;
 };
-void launch_galerkin(const GalerkinArgs& g, hipStream_t st);
+void launch_build_pst(const PstArgs& g, hipStream_t st);
 
 // D = A[off:off+n, off:off+n] (column-major n x n; D must be zeroed first)
 void launch_dense_from_csr(int64_t off, int64_t n, const int64_t* rowptr, const int32_t* col, const double* val,

@@ -1001,9 +1001,8 @@ std::unique_ptr<Level> coarsen(lsdd_hierarchy* h, Level& lv, const int32_t* agg_
     cv->n_super = G.n_super;
     const int64_t ng = cv->el.count();
     cv->blk_off.assign(ng + 1, 0);
-    std::vector<int64_t> ws_off(ng, 0), pm_off(G.mem_elems.size() + 1, 0), pm_zrow;
+    std::vector<int64_t> pm_off(G.mem_elems.size() + 1, 0), pm_zrow;
     std::vector<int32_t> pm_k, pm_col;
-    int64_t ws_tot = 0;
     std::vector<int32_t> colof(n_agg, -1);
     for (int64_t g = 0; g < ng; ++g) {
         int64_t c = cv->el.ptr[g + 1] - cv->el.ptr[g];
@@ -1019,10 +1018,8 @@ std::unique_ptr<Level> coarsen(lsdd_hierarchy* h, Level& lv, const int32_t* agg_
             off += lv.k[agg];
             q += lv.k[agg];
         }
-        int64_t ne_max = 0;
         for (int64_t mi = G.mem_ptr[g]; mi < G.mem_ptr[g + 1]; ++mi) {
             int32_t e = G.mem_elems[mi];
-            ne_max = std::max(ne_max, lv.el.ptr[e + 1] - lv.el.ptr[e]);
             for (int64_t r = lv.el.ptr[e]; r < lv.el.ptr[e + 1]; ++r) {
                 int32_t d = lv.el.dofs[r];
                 int32_t agg = lv.agg_of_dof[d];
@@ -1039,38 +1036,104 @@ std::unique_ptr<Level> coarsen(lsdd_hierarchy* h, Level& lv, const int32_t* agg_
             pm_off[mi + 1] = (int64_t)pm_zrow.size();
         }
         for (int32_t agg : touched) colof[agg] = -1;
-        ws_off[g] = ws_tot;
-        ws_tot += 2 * ne_max * c;
     }
     upload_elements(h, *cv);
     cv->d_blocks = ar.alloc<double>(cv->blk_off[ng]);
-    GalerkinArgs ga{};
-    ga.n_groups = (int32_t)ng;
-    ga.cptr = cv->d_elem_ptr;
-    ga.mem_ptr = ar.upload(G.mem_ptr, st);
-    ga.mem_elems = ar.upload(G.mem_elems, st);
-    ga.felem_ptr = lv.d_elem_ptr;
-    ga.pm_off = ar.upload(pm_off, st);
-    ga.pm_zrow = ar.upload(pm_zrow, st);
-    ga.pm_k = ar.upload(pm_k, st);
-    ga.pm_col = ar.upload(pm_col, st);
-    ga.Z = lv.d_Z;
-    ga.use_gram = lv.level == 0 ? 1 : 0;
-    ga.fblk_off = lv.d_blk_off;
-    ga.fblocks = lv.level == 0 ? lv.d_G : lv.d_blocks;
-    ga.ws_off = ar.upload(ws_off, st);
-    ga.ws = ar.alloc<double>(ws_tot);
-    ga.cblk_off = cv->d_blk_off;
-    ga.cblocks = cv->d_blocks;
     double tg0 = now_s();
-    launch_galerkin(ga, st);
-    HIPCHK(hipGetLastError());
-    sync(st);
+    {
+        // stacked interpolation rows P_g per group, Y_e = F_e P_e per member,
+        // then A_g = Y^T Y (Gram factors) or P_g^T Y, both on the matrix cores
+        const bool gram = lv.level == 0;
+        const double* fb = gram ? lv.d_G : lv.d_blocks;
+        std::vector<int64_t> R(ng, 0);
+        for (int64_t g = 0; g < ng; ++g)
+            for (int64_t mi = G.mem_ptr[g]; mi < G.mem_ptr[g + 1]; ++mi) {
+                const int32_t e = G.mem_elems[mi];
+                R[g] += lv.el.ptr[e + 1] - lv.el.ptr[e];
+            }
+        PstArgs pa{};
+        pa.cptr = cv->d_elem_ptr;
+        pa.mem_ptr = ar.upload(G.mem_ptr, st);
+        pa.mem_elems = ar.upload(G.mem_elems, st);
+        pa.felem_ptr = lv.d_elem_ptr;
+        pa.pm_off = ar.upload(pm_off, st);
+        pa.pm_zrow = ar.upload(pm_zrow, st);
+        pa.pm_k = ar.upload(pm_k, st);
+        pa.pm_col = ar.upload(pm_col, st);
+        pa.Z = lv.d_Z;
+        Batched bt;
+        bt.st = st;
+        bt.alloc = [](void* c, size_t b) { return static_cast<Arena*>(c)->get(b); };
+        bt.release = [](void* c, void* p) { static_cast<Arena*>(c)->release(p); };
+        bt.ctx = &ar;
+        const int64_t budget = int64_t(2) << 30;    // bytes of P and Y per launch batch
+        constexpr size_t MAXV = 65535;              // views per launch
+        int64_t g0 = 0;
+        while (g0 < ng) {
+            int64_t g1 = g0, tot = 0;
+            std::vector<int64_t> off, rows;
+            while (g1 < ng) {
+                const int64_t c = cv->el.ptr[g1 + 1] - cv->el.ptr[g1], sz = R[g1] * c;
+                if (g1 > g0 && (tot + sz) * 16 > budget) break;
+                off.push_back(tot);
+                rows.push_back(R[g1]);
+                tot += sz;
+                ++g1;
+            }
+            double* pst = ar.alloc<double>(std::max<int64_t>(tot, 1));
+            double* y = ar.alloc<double>(std::max<int64_t>(tot, 1));
+            pa.g0 = (int32_t)g0;
+            pa.n_groups = (int32_t)(g1 - g0);
+            pa.pst_off = ar.upload(off, st);
+            pa.rows = ar.upload(rows, st);
+            pa.pst = pst;
+            launch_build_pst(pa, st);
+            std::vector<View> va, vb;
+            auto flush_members = [&]() {
+                if (va.empty()) return;
+                bt.gemm_tn(fb, va, pst, vb, nullptr, vb, 0.0, y, vb, -1.0);
+                va.clear();
+                vb.clear();
+            };
+            for (int64_t g = g0; g < g1; ++g) {
+                const int32_t c = (int32_t)(cv->el.ptr[g + 1] - cv->el.ptr[g]);
+                int64_t r0 = 0;
+                for (int64_t mi = G.mem_ptr[g]; mi < G.mem_ptr[g + 1]; ++mi) {
+                    const int32_t e = G.mem_elems[mi];
+                    const int32_t ne = (int32_t)(lv.el.ptr[e + 1] - lv.el.ptr[e]);
+                    va.push_back(View{lv.blk_off[e], ne, ne, ne, 0});
+                    vb.push_back(View{off[g - g0] + r0, (int32_t)R[g], ne, c, 0});
+                    r0 += ne;
+                    if (va.size() == MAXV) flush_members();
+                }
+            }
+            flush_members();
+            std::vector<View> wa, wc;
+            auto flush_groups = [&]() {
+                if (wa.empty()) return;
+                bt.gemm_tn(gram ? y : pst, wa, y, wa, nullptr, wc, 0.0, cv->d_blocks, wc, -1.0, false, true);
+                wa.clear();
+                wc.clear();
+            };
+            for (int64_t g = g0; g < g1; ++g) {
+                const int32_t c = (int32_t)(cv->el.ptr[g + 1] - cv->el.ptr[g]);
+                wa.push_back(View{off[g - g0], (int32_t)R[g], (int32_t)R[g], c, 0});
+                wc.push_back(View{cv->blk_off[g], c, c, c, 0});
+                if (wa.size() == MAXV) flush_groups();
+            }
+            flush_groups();
+            HIPCHK(hipGetLastError());
+            sync(st);
+            for (const void* p : {(const void*)pst, (const void*)y, (const void*)pa.pst_off, (const void*)pa.rows})
+                ar.release(const_cast<void*>(p));
+            g0 = g1;
+        }
+        bt.free_all();
+        for (const void* p : {(const void*)pa.mem_ptr, (const void*)pa.mem_elems, (const void*)pa.pm_off,
+                              (const void*)pa.pm_zrow, (const void*)pa.pm_k, (const void*)pa.pm_col})
+            ar.release(const_cast<void*>(p));
+    }
     vlog("level %d: Galerkin products for %lld coarse elements %.3f s", lv.level, (long long)ng, now_s() - tg0);
-    for (const void* p : {(const void*)ga.mem_ptr, (const void*)ga.mem_elems, (const void*)ga.pm_off,
-                          (const void*)ga.pm_zrow, (const void*)ga.pm_k, (const void*)ga.pm_col,
-                          (const void*)ga.ws_off, (const void*)ga.ws})
-        ar.release(const_cast<void*>(p));
     assemble_operator(h, *cv);
     return cv;
 }
