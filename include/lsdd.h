@@ -59,7 +59,9 @@ typedef struct {
     int32_t min_coarse;         /* a level with fewer DOFs is the coarsest; default 10         */
     int32_t max_iter;           /* PCG iteration cap; default 1000                             */
     int32_t precision;          /* 0 = FP64 cycle, 1 = FP32 cycle inside FP64 PCG              */
-    int32_t reserved0;
+    int32_t blocked_eig_min;    /* local spectral problems with |omega| >= this use the blocked
+                                   multi-workgroup tridiagonal reduction; 0 = library default
+                                   (192), < 0 = never; values below 66 act as 66            */
     double tau_const;           /* tau_cut = tau_const * max mult; default 0.75               */
     double max_density;         /* nnz(A_l)/n_l^2 above this -> coarsest; default 0.25         */
     double rtol;                /* PCG stop: ||r||_2 <= rtol ||b||_2; default 1e-8              */

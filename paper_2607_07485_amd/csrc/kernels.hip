@@ -277,7 +277,7 @@ __global__ void __launch_bounds__(WG) k_local_eig(LocalArgs A) {
             wg_identity(V, nw, nw);
             wg_jacobi(S, nw, nw, V, nw, 60, 1e-15, 1e-18 * fmax(scale, 1e-300), pairs, cs, &s_flag);
             wg_sort_eig(S, nw, V, nw, nw, mu, VS, nw, rank);
-        } else {
+        } else if (!(A.trd_min > 0 && nw >= A.trd_min)) {
             wg_tridiag(S, nw, T, T + nw, T + 2 * nw, s_dyn, s_dyn + nw, s_red);
         }
         return;

@@ -52,7 +52,15 @@ struct LocalArgs {
     double thr;                    // 1 / tau_cut
     const double* thr_agg;         // optional per-aggregate 1 / tau_cut (batched instances)
     double band_tol, cluster_tol;
+    int32_t trd_min;               // > 0: aggregates with nw >= trd_min were reduced by the blocked path
 };
+
+// Blocked multi-workgroup tridiagonalisation (trd.hip) of the batch entries
+// d_big[0 .. sizes.size()) (sizes = their nw, each > 2 TRD_NB + 1); leaves the
+// same d, e, tau and reflectors as the single-workgroup reduction of k_local_eig.
+constexpr int TRD_NB = 32;
+void launch_local_tridiag_blocked(const LocalArgs& a, const int32_t* d_big, const std::vector<int32_t>& sizes,
+                                  hipStream_t st);
 
 void launch_elem_eig(int64_t n_elem, const int64_t* elem_ptr, const int64_t* blk_off, const double* blocks,
                      double* G, int32_t* ranks, int32_t* status, double* scratch, int64_t scratch_stride,

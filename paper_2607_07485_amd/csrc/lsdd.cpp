@@ -55,6 +55,15 @@ bool verbose() {
     return v == 1;
 }
 
+// Local spectral problems with at least this many aggregate DOFs are reduced to
+// tridiagonal form by the blocked multi-workgroup path (0: every reduction in
+// one workgroup).
+int32_t trd_min(int32_t param) {
+    if (param < 0) return 0;
+    if (param == 0) return 192;
+    return std::max<int32_t>(param, 2 * lsdd::TRD_NB + 2);
+}
+
 void vlog(const char* fmt, ...) __attribute__((format(printf, 1, 2)));
 void vlog(const char* fmt, ...) {
     if (!verbose()) return;
@@ -661,6 +670,7 @@ std::unique_ptr<Level> coarsen(lsdd_hierarchy* h, Level& lv, const int32_t* agg_
     double* d_thr = thr_agg.empty() ? nullptr : ar.upload(thr_agg, st);
     A.thr_agg = d_thr;
     A.band_tol = P.band_tol;
+    A.trd_min = trd_min(P.blocked_eig_min);
     A.cluster_tol = P.cluster_tol;
 
     // ---- batched local problems (workspace bounded); every dense step runs as
@@ -786,9 +796,22 @@ std::unique_ptr<Level> coarsen(lsdd_hierarchy* h, Level& lv, const int32_t* agg_
         bt.trsm(w2, vLww, sb, vS, false);
         launch_views_symmetrize(nb, sb, bt.put(0, vS), st);
         // eigenpairs of C and retained modes
+        int32_t* d_big = nullptr;
         {
             int32_t mx = 0;
-            for (int32_t b = 0; b < nb; ++b) mx = std::max(mx, (int32_t)(C.agg_ptr[pos + b + 1] - C.agg_ptr[pos + b]));
+            std::vector<int32_t> big, bigsz;
+            for (int32_t b = 0; b < nb; ++b) {
+                const int32_t nw = (int32_t)(C.agg_ptr[pos + b + 1] - C.agg_ptr[pos + b]);
+                mx = std::max(mx, nw);
+                if (B.trd_min > 0 && nw >= B.trd_min) {
+                    big.push_back(b);
+                    bigsz.push_back(nw);
+                }
+            }
+            if (!big.empty()) {
+                d_big = ar.upload(big, st);
+                launch_local_tridiag_blocked(B, d_big, bigsz, st);
+            }
             launch_local_eig(nb, B, mx, st);
         }
         HIPCHK(hipGetLastError());
@@ -811,6 +834,7 @@ std::unique_ptr<Level> coarsen(lsdd_hierarchy* h, Level& lv, const int32_t* agg_
         for (void* p : {(void*)w1, (void*)w2, (void*)sb, (void*)vb, (void*)tb, (void*)d_ws, (void*)d_sq, (void*)d_t,
                         (void*)d_maxd, (void*)d_minp})
             ar.release(p);
+        if (d_big) ar.release(d_big);
         pos = end;
     }
     vlog("level %d: local problems %.3f s", lv.level, now_s() - tl0);

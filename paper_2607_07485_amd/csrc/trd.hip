@@ -1,0 +1,306 @@
+// Blocked Householder tridiagonalisation of the larger local spectral problems
+// (C = L^{-1} S~ L^{-T} of an aggregate), many matrices per launch and many
+// workgroups per matrix.
+//
+// The reduction T = Q^T C Q is the one the single-workgroup path computes
+// (reflector j from column j below the diagonal, tau_j, d, e), but the
+// rank-2 updates of the trailing matrix are delayed over panels of TRD_NB
+// columns: inside a panel, column j is corrected by the panel's earlier
+// reflectors (V, W) and the matrix-vector product with the trailing block is
+// corrected the same way; after the panel one symmetric rank-2k update
+// C22 -= V W^T + W V^T runs on the FP64 matrix cores.  Per column:
+//   k_trd_col   (one workgroup per matrix): finish the previous W column,
+//               correct column j, form reflector v_j (stored in column j, with
+//               an explicit 1 on the subdiagonal), dots W^T v and V^T v;
+//   k_trd_symv  (many workgroups per matrix): w = tau (C22 v - V (W^T v)
+//               - W (V^T v)), one wave per column of C22.
+// Per panel: k_trd_fin (finish the last W column), k_trd_update.
+//
+// Storage per matrix: C (n x n, both triangles kept exactly symmetric), the
+// tridiagonal d, e, tau in the T scratch, V and W (n x TRD_NB each, row-major)
+// and the dots in the v_buf slot (n^2 doubles, n > 2 TRD_NB).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <stdexcept>
+#include <vector>
+
+#include "dense.hpp"
+#include "kernels.hpp"
+#include "mgemm.hpp"
+
+namespace lsdd {
+
+namespace {
+
+constexpr int WG = LSDD_WG;
+constexpr int NB = TRD_NB;
+constexpr int CPW = 4;               // columns per wave in k_trd_symv
+constexpr int CPG = CPW * WG / 64;   // columns per workgroup
+
+struct Mat {
+    int n;
+    double* a;
+    double* d;
+    double* e;
+    double* tau;
+    double* V;
+    double* W;
+    double* zw;
+    double* zv;
+};
+
+__device__ inline Mat mat_of(const LocalArgs& A, int b) {
+    Mat m;
+    const int ag = A.first + b;
+    m.n = (int)(A.agg_ptr[ag + 1] - A.agg_ptr[ag]);
+    m.a = A.s_buf + A.sq_off[b];
+    double* T = A.t_buf + A.t_off[b];
+    m.d = T;
+    m.e = T + m.n;
+    m.tau = T + 2 * m.n;
+    m.V = A.v_buf + A.sq_off[b];
+    m.W = m.V + (int64_t)NB * m.n;
+    m.zw = m.W + (int64_t)NB * m.n;
+    m.zv = m.zw + NB;
+    return m;
+}
+
+// W(:, q) <- w - (tau_jp / 2) (w . v) v for the raw w of reflector jp
+__device__ inline void finish_w(const Mat& m, int jp, int q, double* red) {
+    double s = 0.0;
+    for (int i = jp + 1 + tid(); i < m.n; i += WG) s += m.W[(int64_t)i * NB + q] * m.V[(int64_t)i * NB + q];
+    s = wg_sum(s, red);
+    const double K = 0.5 * m.tau[jp] * s;
+    for (int i = jp + 1 + tid(); i < m.n; i += WG) m.W[(int64_t)i * NB + q] -= K * m.V[(int64_t)i * NB + q];
+    __syncthreads();
+}
+
+__global__ void __launch_bounds__(WG) k_trd_col(LocalArgs A, const int32_t* big, int j, int j0) {
+    __shared__ double red[WG / 64];
+    __shared__ double rowvw[2 * NB];
+    __shared__ double part[WG / 64][2 * NB];
+    const Mat m = mat_of(A, big[blockIdx.x]);
+    const int n = m.n;
+    if (j + 2 >= n) return;
+    const int p = j - j0;
+    if (p > 0) finish_w(m, j - 1, p - 1, red);
+    // column j (rows j..n-1) with the panel's earlier reflectors applied
+    if (tid() < p) {
+        rowvw[tid()] = m.V[(int64_t)j * NB + tid()];
+        rowvw[NB + tid()] = m.W[(int64_t)j * NB + tid()];
+    }
+    __syncthreads();
+    double* col = m.a + (int64_t)j * n;
+    for (int i = j + tid(); i < n; i += WG) {
+        double s = col[i];
+        const double* vr = m.V + (int64_t)i * NB;
+        const double* wr = m.W + (int64_t)i * NB;
+        for (int q = 0; q < p; ++q) s -= vr[q] * rowvw[NB + q] + wr[q] * rowvw[q];
+        col[i] = s;
+    }
+    __syncthreads();
+    // reflector from x = col[j+1 .. n-1]
+    const int mm = n - j - 1;
+    double* x = col + j + 1;
+    double s2 = 0.0;
+    for (int i = 1 + tid(); i < mm; i += WG) s2 += x[i] * x[i];
+    s2 = wg_sum(s2, red);
+    const double alpha = x[0];
+    double t = 0.0, beta = alpha, sc = 0.0;
+    if (s2 > 0.0) {
+        const double nrm = sqrt(alpha * alpha + s2);
+        beta = alpha >= 0.0 ? -nrm : nrm;
+        t = (beta - alpha) / beta;
+        sc = 1.0 / (alpha - beta);
+    }
+    if (tid() == 0) {
+        m.d[j] = col[j];
+        m.e[j] = beta;
+        m.tau[j] = t;
+    }
+    __syncthreads();
+    for (int i = tid(); i < mm; i += WG) {
+        const double vi = (i == 0) ? 1.0 : (s2 > 0.0 ? x[i] * sc : 0.0);
+        x[i] = vi;
+        m.V[(int64_t)(j + 1 + i) * NB + p] = vi;
+    }
+    for (int i = j0 + tid(); i <= j; i += WG) {
+        m.V[(int64_t)i * NB + p] = 0.0;
+        m.W[(int64_t)i * NB + p] = 0.0;
+    }
+    __syncthreads();
+    // zw_q = W(j+1:, q) . v, zv_q = V(j+1:, q) . v for q < p
+    const int w = tid() >> 6, l = tid() & 63;
+    for (int q0 = 0; q0 < p; q0 += 8) {
+        double aw[8], av[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) aw[u] = av[u] = 0.0;
+        for (int i = j + 1 + tid(); i < n; i += WG) {
+            const double vi = x[i - j - 1];
+            const double* vr = m.V + (int64_t)i * NB + q0;
+            const double* wr = m.W + (int64_t)i * NB + q0;
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+                if (q0 + u < p) {
+                    aw[u] += wr[u] * vi;
+                    av[u] += vr[u] * vi;
+                }
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            aw[u] = wave_sum(aw[u]);
+            av[u] = wave_sum(av[u]);
+        }
+        if (l == 0)
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                part[w][q0 + u] = aw[u];
+                part[w][NB + q0 + u] = av[u];
+            }
+    }
+    __syncthreads();
+    if (tid() < p) {
+        double sw = 0.0, sv = 0.0;
+        for (int r = 0; r < WG / 64; ++r) {
+            sw += part[r][tid()];
+            sv += part[r][NB + tid()];
+        }
+        m.zw[tid()] = sw;
+        m.zv[tid()] = sv;
+    }
+}
+
+__global__ void __launch_bounds__(WG) k_trd_symv(LocalArgs A, const int32_t* big, int j, int j0) {
+    extern __shared__ double s_v[];    // v (n - j - 1), then zw, zv
+    const Mat m = mat_of(A, big[blockIdx.y]);
+    const int n = m.n;
+    if (j + 2 >= n) return;
+    const int mm = n - j - 1;
+    const int c0 = (int)blockIdx.x * CPG;
+    if (c0 >= mm) return;
+    const int p = j - j0;
+    const double* v = m.a + (int64_t)j * n + j + 1;
+    double* zz = s_v + mm;
+    for (int i = tid(); i < mm; i += WG) s_v[i] = v[i];
+    if (tid() < p) {
+        zz[tid()] = m.zw[tid()];
+        zz[NB + tid()] = m.zv[tid()];
+    }
+    __syncthreads();
+    const double t = m.tau[j];
+    const int w = tid() >> 6, l = tid() & 63;
+    for (int cc = 0; cc < CPW; ++cc) {
+        const int c = c0 + w * CPW + cc;
+        if (c >= mm) break;
+        const double* cp = m.a + (int64_t)(j + 1 + c) * n + j + 1;
+        double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+        int i = l;
+        for (; i + 192 < mm; i += 256) {
+            s0 += cp[i] * s_v[i];
+            s1 += cp[i + 64] * s_v[i + 64];
+            s2 += cp[i + 128] * s_v[i + 128];
+            s3 += cp[i + 192] * s_v[i + 192];
+        }
+        for (; i < mm; i += 64) s0 += cp[i] * s_v[i];
+        double s = wave_sum((s0 + s1) + (s2 + s3));
+        if (l == 0) {
+            const int gi = j + 1 + c;
+            const double* vr = m.V + (int64_t)gi * NB;
+            const double* wr = m.W + (int64_t)gi * NB;
+            for (int q = 0; q < p; ++q) s -= vr[q] * zz[q] + wr[q] * zz[NB + q];
+            m.W[(int64_t)gi * NB + p] = t * s;
+        }
+    }
+}
+
+__global__ void __launch_bounds__(WG) k_trd_fin(LocalArgs A, const int32_t* big, int j0) {
+    __shared__ double red[WG / 64];
+    const Mat m = mat_of(A, big[blockIdx.x]);
+    const int pc = min(NB, m.n - 2 - j0);
+    if (pc <= 0) return;
+    finish_w(m, j0 + pc - 1, pc - 1, red);
+}
+
+// C[r0:, r0:] -= V W^T + W V^T over lower tile pairs, stored to both triangles
+__global__ void __launch_bounds__(WG) k_trd_update(LocalArgs A, const int32_t* big, int j0) {
+    __shared__ mg::Smem sm;
+    const Mat m = mat_of(A, big[blockIdx.y]);
+    const int n = m.n;
+    const int pc = min(NB, n - 2 - j0);
+    if (pc <= 0) return;
+    const int r0 = j0 + pc, M = n - r0;
+    const int mt = (M + mg::T - 1) / mg::T;
+    int job = (int)blockIdx.x;
+    if (job >= mt * (mt + 1) / 2) return;
+    int jt = 0;
+    while (job >= mt - jt) {
+        job -= mt - jt;
+        ++jt;
+    }
+    const int it = jt + job;
+    const double* Vr = m.V + (int64_t)r0 * NB;
+    const double* Wr = m.W + (int64_t)r0 * NB;
+    mg::d4 acc[2][2];
+    mg::zero(acc);
+    mg::tile_mma<mg::KMAJ, mg::KMAJ>(sm, Vr, NB, it * mg::T, M, Wr, NB, jt * mg::T, M, 0, pc, acc);
+    mg::tile_mma<mg::KMAJ, mg::KMAJ>(sm, Wr, NB, it * mg::T, M, Vr, NB, jt * mg::T, M, 0, pc, acc);
+#pragma unroll
+    for (int p = 0; p < 2; ++p)
+#pragma unroll
+        for (int q = 0; q < 2; ++q)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int i = it * mg::T + mg::acc_row(p, e), c = jt * mg::T + mg::acc_col(q);
+                if (i < M && c < M && i >= c) {
+                    const int64_t rr = r0 + i, cc = r0 + c;
+                    const double x = m.a[rr + cc * n] - acc[p][q][e];
+                    m.a[rr + cc * n] = x;
+                    if (i != c) m.a[cc + rr * n] = x;
+                }
+            }
+}
+
+__global__ void k_trd_tail(LocalArgs A, const int32_t* big) {
+    const Mat m = mat_of(A, big[blockIdx.x]);
+    const int n = m.n;
+    if (tid() == 0 && n >= 3) {
+        m.d[n - 2] = m.a[(n - 2) + (int64_t)(n - 2) * n];
+        m.e[n - 2] = m.a[(n - 1) + (int64_t)(n - 2) * n];
+        m.d[n - 1] = m.a[(n - 1) + (int64_t)(n - 1) * n];
+    }
+}
+
+}  // namespace
+
+void launch_local_tridiag_blocked(const LocalArgs& a, const int32_t* d_big, const std::vector<int32_t>& sizes,
+                                  hipStream_t st) {
+    const int nbig = (int)sizes.size();
+    if (nbig == 0) return;
+    int max_n = 0;
+    for (int32_t s : sizes) {
+        if (s <= 2 * NB + 1) throw std::runtime_error("blocked tridiagonalisation needs n > 2 * TRD_NB + 1");
+        max_n = std::max(max_n, (int)s);
+    }
+    const size_t lds = (size_t)(max_n + 2 * NB) * sizeof(double);
+    for (int j0 = 0; j0 < max_n - 2; j0 += NB) {
+        const int j1 = std::min(j0 + NB, max_n - 2);
+        for (int j = j0; j < j1; ++j) {
+            hipLaunchKernelGGL(k_trd_col, dim3(nbig), dim3(WG), 0, st, a, d_big, j, j0);
+            const int mm = max_n - j - 1;
+            hipLaunchKernelGGL(k_trd_symv, dim3((mm + CPG - 1) / CPG, nbig), dim3(WG), lds, st, a, d_big, j, j0);
+        }
+        hipLaunchKernelGGL(k_trd_fin, dim3(nbig), dim3(WG), 0, st, a, d_big, j0);
+        int64_t jobs = 0;
+        for (int32_t n : sizes) {
+            const int pc = std::min(NB, (int)n - 2 - j0);
+            if (pc <= 0) continue;
+            const int64_t mt = (n - j0 - pc + mg::T - 1) / mg::T;
+            jobs = std::max(jobs, mt * (mt + 1) / 2);
+        }
+        if (jobs > 0) hipLaunchKernelGGL(k_trd_update, dim3((unsigned)jobs, nbig), dim3(WG), 0, st, a, d_big, j0);
+    }
+    hipLaunchKernelGGL(k_trd_tail, dim3(nbig), dim3(64), 0, st, a, d_big);
+}
+
+}  // namespace lsdd
