@@ -417,8 +417,11 @@ __device__ inline int sturm_count(const double* d, const double* e, int n, doubl
     return c;
 }
 
-// All eigenvalues of the symmetric tridiagonal (d, e), ascending, by bisection.
-__device__ inline void wg_bisect_all(const double* d, const double* e, int n, double* lam, double* red) {
+// Eigenvalues i0 .. i1-1 (ascending order) of the symmetric tridiagonal (d, e)
+// by bisection; the bracket is computed from the whole matrix, so any split of
+// the index range gives the same values.
+__device__ inline void wg_bisect_range(const double* d, const double* e, int n, double* lam, int i0, int i1,
+                                       double* red) {
     double lo = INFINITY, hi = -INFINITY, emax2 = 0.0;
     for (int i = tid(); i < n; i += LSDD_WG) {
         double r = (i > 0 ? fabs(e[i - 1]) : 0.0) + (i + 1 < n ? fabs(e[i]) : 0.0);
@@ -434,7 +437,7 @@ __device__ inline void wg_bisect_all(const double* d, const double* e, int n, do
     const double atol = 2.0 * 2.220446049250313e-16 * tnorm + 1e-300;
     lo -= atol;
     hi += atol;
-    for (int i = tid(); i < n; i += LSDD_WG) {
+    for (int i = i0 + tid(); i < i1; i += LSDD_WG) {
         double a = lo, b = hi;
         for (int it = 0; it < 200; ++it) {
             double mid = 0.5 * (a + b);
@@ -445,6 +448,11 @@ __device__ inline void wg_bisect_all(const double* d, const double* e, int n, do
         lam[i] = 0.5 * (a + b);
     }
     __syncthreads();
+}
+
+// All eigenvalues of the symmetric tridiagonal (d, e), ascending, by bisection.
+__device__ inline void wg_bisect_all(const double* d, const double* e, int n, double* lam, double* red) {
+    wg_bisect_range(d, e, n, lam, 0, n, red);
 }
 
 // Solve (T - lam I) y = b in place for the tridiagonal (d, e) by Gaussian

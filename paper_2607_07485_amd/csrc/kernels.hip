@@ -209,37 +209,62 @@ __global__ void __launch_bounds__(WG) k_elem_bilinear(int64_t n_elem, const int6
 
 // Per aggregate: A~_Omega = sum_{T in cl(omega)} mult(T)^{-1} E_T^T A_T E_T
 // (eq. SPSD_splitting under structural support) and A_Omega = A[Omega, Omega].
+// Grid (column blocks, batch entries): workgroup x owns the Omega columns
+// [x ASM_CW, (x + 1) ASM_CW) of both matrices, zeroes them and adds the closure
+// elements in closure order (every entry is summed in the same order on every
+// run; an element touches an entry at most once).  A_Omega is filled column by
+// column from the CSR rows of the symmetric A_l.
+constexpr int ASM_CW = 32;
+
 __global__ void __launch_bounds__(WG) k_local_assemble(LocalArgs A) {
-    const int b = blockIdx.x;
+    __shared__ int s_cnt;
+    __shared__ int s_j[ASM_CW];
+    const int b = blockIdx.y;
     const int ag = A.agg_list ? A.agg_list[b] : A.first + b;
     const int64_t s0 = A.sub_ptr[ag];
     const int m = (int)(A.sub_ptr[ag + 1] - s0);
+    const int c0 = (int)blockIdx.x * ASM_CW;
+    if (c0 >= m) return;
+    const int c1 = min(m, c0 + ASM_CW);
     const int nw = (int)(A.agg_ptr[ag + 1] - A.agg_ptr[ag]);
     const int32_t* dofs = A.sub_dofs + s0;
     double* W1 = A.w1 + A.ws_off[b];
     double* W2 = A.w2 + A.ws_off[b];
-    wg_zero(W1, (int64_t)m * m);
+    for (int64_t idx = tid(); idx < (int64_t)(c1 - c0) * m; idx += WG) {
+        W1[(int64_t)c0 * m + idx] = 0.0;
+        W2[(int64_t)c0 * m + idx] = 0.0;
+    }
+    __syncthreads();
     for (int64_t c = A.cl_ptr[ag]; c < A.cl_ptr[ag + 1]; ++c) {
         const int32_t e = A.cl_elems[c];
         const int ne = (int)(A.elem_ptr[e + 1] - A.elem_ptr[e]);
         const int32_t* pos = A.clpos + A.clpos_off[c];
-        const double* Be = A.blocks + A.blk_off[e];
-        const double w = 1.0 / (double)A.mult[e];
-        for (int idx = tid(); idx < ne * ne; idx += WG) {
-            int i = idx / ne, j = idx % ne;
-            W1[pos[i] + (int64_t)pos[j] * m] += w * Be[idx];
+        if (tid() == 0) s_cnt = 0;
+        __syncthreads();
+        for (int j = tid(); j < ne; j += WG) {
+            const int pj = pos[j];
+            if (pj >= c0 && pj < c1) s_j[atomicAdd(&s_cnt, 1)] = j;
+        }
+        __syncthreads();
+        const int nj = s_cnt;
+        if (nj > 0) {
+            const double* Be = A.blocks + A.blk_off[e];
+            const double w = 1.0 / (double)A.mult[e];
+            for (int idx = tid(); idx < nj * ne; idx += WG) {
+                const int i = idx % ne, j = s_j[idx / ne];
+                W1[pos[i] + (int64_t)pos[j] * m] += w * Be[(int64_t)i * ne + j];
+            }
         }
         __syncthreads();
     }
-    wg_zero(W2, (int64_t)m * m);
-    for (int a = tid(); a < m; a += WG) {
+    // column a of A_Omega = row dofs[a] of A_l restricted to Omega; 8 threads per column
+    for (int a = c0 + tid() / 8; a < c1; a += WG / 8) {
         const int32_t p = dofs[a];
-        for (int64_t q = A.rowptr[p]; q < A.rowptr[p + 1]; ++q) {
-            int li = local_index(dofs, nw, m, A.col[q]);
-            if (li >= 0) W2[a + (int64_t)li * m] = A.val[q];
+        for (int64_t q = A.rowptr[p] + (tid() & 7); q < A.rowptr[p + 1]; q += 8) {
+            const int li = local_index(dofs, nw, m, A.col[q]);
+            if (li >= 0) W2[li + (int64_t)a * m] = A.val[q];
         }
     }
-    __syncthreads();
 }
 
 // Per aggregate: eigenpairs of C = L^{-1} S~ L^{-T} (held in the S buffer):
@@ -283,7 +308,7 @@ __global__ void __launch_bounds__(WG) k_local_eig(LocalArgs A) {
         return;
     }
     if (PHASE == 1) {
-        if (!small) wg_bisect_all(T, T + nw, nw, mu, s_red);
+        if (!small && !(A.trd_min > 0 && nw >= A.trd_min)) wg_bisect_all(T, T + nw, nw, mu, s_red);
         for (int i = tid(); i < nw; i += WG) mu[i] = fmax(mu[i], 0.0);
         __syncthreads();
         if (tid() == 0) {
@@ -313,6 +338,7 @@ __global__ void __launch_bounds__(WG) k_local_eig(LocalArgs A) {
                              &s_ncl);
         return;
     }
+    if (A.trd_min > 0 && nw >= A.trd_min) return;     // back-transformed by the blocked path
     wg_tridiag_backtransform(S, nw, T + 2 * nw, VS, k, s_dyn, s_dyn + nw);
 }
 
@@ -1010,9 +1036,9 @@ void launch_elem_bilinear(int64_t n_elem, const int64_t* elem_ptr, const int32_t
                        blk_off, blocks, u, v, out);
 }
 
-void launch_local_assemble(int32_t nbatch, const LocalArgs& a, hipStream_t st) {
-    if (nbatch <= 0) return;
-    hipLaunchKernelGGL(k_local_assemble, dim3(nbatch), dim3(WG), 0, st, a);
+void launch_local_assemble(int32_t nbatch, const LocalArgs& a, int32_t max_m, hipStream_t st) {
+    if (nbatch <= 0 || max_m <= 0) return;
+    hipLaunchKernelGGL(k_local_assemble, dim3((max_m + ASM_CW - 1) / ASM_CW, nbatch), dim3(WG), 0, st, a);
 }
 
 void launch_local_eig(int32_t nbatch, const LocalArgs& a, int32_t max_nw, hipStream_t st) {

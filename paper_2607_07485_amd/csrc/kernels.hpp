@@ -61,6 +61,10 @@ struct LocalArgs {
 constexpr int TRD_NB = 32;
 void launch_local_tridiag_blocked(const LocalArgs& a, const int32_t* d_big, const std::vector<int32_t>& sizes,
                                   hipStream_t st);
+// Back-transformation of the retained eigenvectors of the same entries (after
+// the eigenvalue and inverse-iteration phases of k_local_eig).
+void launch_local_backtransform_blocked(const LocalArgs& a, const int32_t* d_big, const std::vector<int32_t>& sizes,
+                                        hipStream_t st);
 
 void launch_elem_eig(int64_t n_elem, const int64_t* elem_ptr, const int64_t* blk_off, const double* blocks,
                      double* G, int32_t* ranks, int32_t* status, double* scratch, int64_t scratch_stride,
@@ -80,7 +84,7 @@ void launch_scale_blocks(int64_t n_elem, const int64_t* blk_off, const double* s
 void launch_elem_bilinear(int64_t n_elem, const int64_t* elem_ptr, const int32_t* elem_dofs, const int64_t* blk_off,
                           const double* blocks, const double* u, const double* v, double* out, hipStream_t st);
 
-void launch_local_assemble(int32_t nbatch, const LocalArgs& a, hipStream_t st);
+void launch_local_assemble(int32_t nbatch, const LocalArgs& a, int32_t max_m, hipStream_t st);
 // max_nw: largest |omega| of the batch (<= 4096)
 void launch_local_eig(int32_t nbatch, const LocalArgs& a, int32_t max_nw, hipStream_t st);
 void launch_stage_z(int32_t nbatch, const LocalArgs& a, hipStream_t st);

@@ -725,7 +725,9 @@ std::unique_ptr<Level> coarsen(lsdd_hierarchy* h, Level& lv, const int32_t* agg_
         B.v_buf = vb;
         B.t_off = d_t;
         B.t_buf = tb;
-        launch_local_assemble(nb, B, st);
+        int32_t max_m = 0;
+        for (int32_t b = 0; b < nb; ++b) max_m = std::max(max_m, (int32_t)(C.sub_ptr[pos + b + 1] - C.sub_ptr[pos + b]));
+        launch_local_assemble(nb, B, max_m, st);
         std::vector<View> vGG, vGw, vww, vS, vAO, vLww;
         std::vector<int64_t> ngs(nb);
         for (int32_t b = 0; b < nb; ++b) {
@@ -771,7 +773,9 @@ std::unique_ptr<Level> coarsen(lsdd_hierarchy* h, Level& lv, const int32_t* agg_
                 LocalArgs R = B;
                 R.agg_list = d_list;
                 R.ws_off = d_sws;
-                launch_local_assemble((int32_t)sing.size(), R, st);
+                int32_t sing_m = 0;
+                for (int32_t i : sing) sing_m = std::max(sing_m, (int32_t)(C.sub_ptr[i + 1] - C.sub_ptr[i]));
+                launch_local_assemble((int32_t)sing.size(), R, sing_m, st);
                 launch_views_add_diag((int32_t)sing.size(), w1, bt.put(0, vs), d_delta, st);
                 double* d_mp2 = ar.alloc<double>(sing.size());
                 bt.potrf(w1, vs, d_mp2);
@@ -813,6 +817,7 @@ std::unique_ptr<Level> coarsen(lsdd_hierarchy* h, Level& lv, const int32_t* agg_
                 launch_local_tridiag_blocked(B, d_big, bigsz, st);
             }
             launch_local_eig(nb, B, mx, st);
+            if (!big.empty()) launch_local_backtransform_blocked(B, d_big, bigsz, st);
         }
         HIPCHK(hipGetLastError());
         std::vector<int32_t> kb = download(lv.d_k + pos, nb, st);

@@ -271,7 +271,56 @@ __global__ void k_trd_tail(LocalArgs A, const int32_t* big) {
     }
 }
 
+// All eigenvalues of the large problems' tridiagonal matrices by bisection,
+// WG of them per workgroup (before the mode-count phase of k_local_eig).
+__global__ void __launch_bounds__(WG) k_trd_bisect(LocalArgs A, const int32_t* big) {
+    __shared__ double red[WG / 64];
+    const int b = big[blockIdx.y];
+    const int ag = A.first + b;
+    const int n = (int)(A.agg_ptr[ag + 1] - A.agg_ptr[ag]);
+    const int i0 = (int)blockIdx.x * WG;
+    if (i0 >= n) return;
+    const double* T = A.t_buf + A.t_off[b];
+    wg_bisect_range(T, T + n, n, A.mu + A.mu_off[ag], i0, min(n, i0 + WG), red);
+}
+
+// Retained eigenvectors x <- Q x (Q = H_0 ... H_{n-3}) for the large
+// problems: one wave per vector (VS = W1, n x k, ld n), reflectors applied
+// from the last to the first.  Lane l owns the rows r = l (mod 64) of its
+// vector, so no lane reads another lane's writes.
+__global__ void __launch_bounds__(WG) k_trd_backtransform(LocalArgs A, const int32_t* big) {
+    const int b = big[blockIdx.y];
+    const int ag = A.first + b;
+    const int n = (int)(A.agg_ptr[ag + 1] - A.agg_ptr[ag]);
+    const int kk = A.k_out[ag];
+    const int c = (int)blockIdx.x * (WG / 64) + (tid() >> 6);
+    if (c >= kk) return;
+    const int l = tid() & 63;
+    const double* a = A.s_buf + A.sq_off[b];
+    const double* tau = A.t_buf + A.t_off[b] + 2 * n;
+    double* x = A.w1 + A.ws_off[b] + (int64_t)c * n;
+    for (int j = n - 3; j >= 0; --j) {
+        const double t = tau[j];
+        if (t == 0.0) continue;
+        const double* v = a + (int64_t)j * n;
+        const int r0 = j + 1 + ((l - (j + 1)) % 64 + 64) % 64;     // first owned row > j
+        double s = 0.0;
+        for (int r = r0; r < n; r += 64) s += (r == j + 1 ? 1.0 : v[r]) * x[r];
+        s = wave_sum(s) * t;
+        for (int r = r0; r < n; r += 64) x[r] -= s * (r == j + 1 ? 1.0 : v[r]);
+    }
+}
+
 }  // namespace
+
+void launch_local_backtransform_blocked(const LocalArgs& a, const int32_t* d_big, const std::vector<int32_t>& sizes,
+                                        hipStream_t st) {
+    const int nbig = (int)sizes.size();
+    if (nbig == 0) return;
+    int max_n = 0;
+    for (int32_t s : sizes) max_n = std::max(max_n, (int)s);
+    hipLaunchKernelGGL(k_trd_backtransform, dim3((max_n + WG / 64 - 1) / (WG / 64), nbig), dim3(WG), 0, st, a, d_big);
+}
 
 void launch_local_tridiag_blocked(const LocalArgs& a, const int32_t* d_big, const std::vector<int32_t>& sizes,
                                   hipStream_t st) {
@@ -301,6 +350,7 @@ void launch_local_tridiag_blocked(const LocalArgs& a, const int32_t* d_big, cons
         if (jobs > 0) hipLaunchKernelGGL(k_trd_update, dim3((unsigned)jobs, nbig), dim3(WG), 0, st, a, d_big, j0);
     }
     hipLaunchKernelGGL(k_trd_tail, dim3(nbig), dim3(64), 0, st, a, d_big);
+    hipLaunchKernelGGL(k_trd_bisect, dim3((max_n + WG - 1) / WG, nbig), dim3(WG), 0, st, a, d_big);
 }
 
 }  // namespace lsdd
