@@ -9,6 +9,8 @@
 
 #include <cmath>
 
+#include "consts.hpp"
+
 #define LSDD_WG 256
 
 namespace lsdd {
@@ -456,9 +458,14 @@ __device__ inline void wg_bisect_all(const double* d, const double* e, int n, do
 }
 
 // Solve (T - lam I) y = b in place for the tridiagonal (d, e) by Gaussian
-// elimination with partial pivoting; scratch u0,u1,u2,l (n each), piv (n).
-__device__ inline void tri_shift_solve(const double* d, const double* e, int n, double lam, double* b, double* u0,
-                                       double* u1, double* u2, double* l, unsigned char* piv, double tiny) {
+// elimination with partial pivoting.  b has stride bs; the factor scratch
+// u0, u1, u2, l, piv (n entries each) has stride S, so the 64 lanes of a wave
+// solving 64 systems at once can keep their scratch interleaved (S = 64,
+// coalesced) without changing the arithmetic.
+template <int S>
+__device__ inline void tri_shift_solve(const double* d, const double* e, int n, double lam, double* b, int bs,
+                                       double* u0, double* u1, double* u2, double* l, unsigned char* piv,
+                                       double tiny) {
     // factor: rows k hold (u0[k], u1[k], u2[k]) on diagonals 0, +1, +2
     double a0 = d[0] - lam, a1 = (n > 1) ? e[0] : 0.0;
     for (int k = 0; k < n - 1; ++k) {
@@ -466,51 +473,62 @@ __device__ inline void tri_shift_solve(const double* d, const double* e, int n, 
         double nd = d[k + 1] - lam;
         double ns = (k + 2 < n) ? e[k + 1] : 0.0;
         if (fabs(a0) >= fabs(sub)) {
-            piv[k] = 0;
+            piv[k * S] = 0;
             if (fabs(a0) < tiny) a0 = (a0 >= 0.0 ? tiny : -tiny);
-            u0[k] = a0; u1[k] = a1; u2[k] = 0.0;
+            u0[k * S] = a0; u1[k * S] = a1; u2[k * S] = 0.0;
             double f = sub / a0;
-            l[k] = f;
+            l[k * S] = f;
             a0 = nd - f * a1;
             a1 = ns;
         } else {
-            piv[k] = 1;
-            u0[k] = sub; u1[k] = nd; u2[k] = ns;
+            piv[k * S] = 1;
+            u0[k * S] = sub; u1[k * S] = nd; u2[k * S] = ns;
             double f = a0 / sub;
-            l[k] = f;
+            l[k * S] = f;
             a0 = a1 - f * nd;
             a1 = -f * ns;
         }
     }
     if (fabs(a0) < tiny) a0 = (a0 >= 0.0 ? tiny : -tiny);
-    u0[n - 1] = a0; u1[n - 1] = 0.0; u2[n - 1] = 0.0;
-    // forward
+    u0[(n - 1) * S] = a0; u1[(n - 1) * S] = 0.0; u2[(n - 1) * S] = 0.0;
+    // forward (b[k] carried in a register)
+    double bk = b[0];
     for (int k = 0; k < n - 1; ++k) {
-        if (piv[k]) { double t = b[k]; b[k] = b[k + 1]; b[k + 1] = t; }
-        b[k + 1] -= l[k] * b[k];
+        double bn = b[(k + 1) * bs];
+        if (piv[k * S]) { double t = bk; bk = bn; bn = t; }
+        b[k * bs] = bk;
+        bk = bn - l[k * S] * bk;
     }
+    b[(n - 1) * bs] = bk;
     // backward
+    double x1 = 0.0, x2 = 0.0;
     for (int k = n - 1; k >= 0; --k) {
-        double s = b[k];
-        if (k + 1 < n) s -= u1[k] * b[k + 1];
-        if (k + 2 < n) s -= u2[k] * b[k + 2];
-        b[k] = s / u0[k];
+        double s = b[k * bs];
+        if (k + 1 < n) s -= u1[k * S] * x1;
+        if (k + 2 < n) s -= u2[k * S] * x2;
+        const double xk = s / u0[k * S];
+        b[k * bs] = xk;
+        x2 = x1;
+        x1 = xk;
     }
 }
 
 // Eigenvectors of the tridiagonal (d, e) for the eigenvalues lam[0..kk) by
 // inverse iteration.  Eigenvalues closer than 1e-4 * tnorm form a cluster.
-// Single-member clusters run one per thread (threads 0..63, each with a
-// scratch slot of 5n doubles in `ws`).  The members of a larger cluster are
-// processed in batches of up to 64: each iteration solves every member's
-// shifted system on its own thread, then orthogonalises the batch by classical
-// Gram-Schmidt applied twice against the earlier members of the cluster and,
-// in index order, within the batch, and normalises it.  Output V (n x kk,
-// column-major, ld n).  `ws` holds 64 * 5n doubles of slots followed by
-// 64 * max(n, 64) doubles of batch dots.  LDS: cl_start (kk+1 ints), dots (64).
-__device__ inline void wg_inverse_iteration(const double* d, const double* e, int n, const double* lam, int kk,
-                                            double* V, double* ws, double tnorm, int* cl_start, double* dots,
-                                            double* red, int* ncl_sh) {
+// This workgroup handles the single-member clusters with index in [r0, r1)
+// and the larger clusters that start there.  Singletons run one per thread
+// (threads 0..63).  `ws` holds INVIT_SLOTS * n doubles: the factor scratch
+// and singleton iterates of the 64 solving lanes, interleaved by lane.  The members of a larger cluster are processed in batches of up
+// to 64: each iteration solves every member's shifted system on its own
+// thread, then orthogonalises the batch by classical Gram-Schmidt applied
+// twice against the earlier members of the cluster and, in index order,
+// within the batch, and normalises it.  Every vector is computed the same way
+// whatever the range split.  Output V (n x kk, column-major, ld n); `dd` holds
+// 64 x 64 batch dots.  LDS: cl_start (kk+1 ints), dots (64).
+__device__ inline void wg_inverse_iteration_range(const double* d, const double* e, int n, const double* lam,
+                                                  int kk, int r0, int r1, double* V, double* ws, double* dd,
+                                                  double tnorm, int* cl_start, double* dots, double* red,
+                                                  int* ncl_sh) {
     const double eps = 2.220446049250313e-16;
     const double gaptol = 1e-4 * tnorm;
     if (tid() == 0) {
@@ -523,59 +541,65 @@ __device__ inline void wg_inverse_iteration(const double* d, const double* e, in
     __syncthreads();
     const int ncl = *ncl_sh;
     const double tiny = eps * fmax(tnorm, 1e-300);
-    auto start_vector = [&](double* y, int i, int k) {
+    auto start_value = [&](int i, int k) {
         unsigned h = (unsigned)(k * 2654435761u) ^ (unsigned)(i * 40503u);
-        y[k] = 1.0 + 0.25 * ((double)(h & 0xffff) / 65536.0 - 0.5);
+        return 1.0 + 0.25 * ((double)(h & 0xffff) / 65536.0 - 0.5);
     };
-    auto slot_solve = [&](int slot, int i, double shift) {
-        double* u0 = ws + (long long)slot * 5 * n;
-        double* u1 = u0 + n;
-        double* u2 = u1 + n;
-        double* l = u2 + n;
-        unsigned char* piv = (unsigned char*)(l + n);
-        tri_shift_solve(d, e, n, shift, V + (long long)i * n, u0, u1, u2, l, piv, tiny);
+    // lane-interleaved scratch of the 64 solving threads (lane t: entry k at [64 k + t])
+    auto slot_solve = [&](int t, double* b, int bs, double shift) {
+        tri_shift_solve<64>(d, e, n, shift, b, bs, ws + t, ws + (long long)64 * n + t, ws + (long long)128 * n + t,
+                            ws + (long long)192 * n + t, (unsigned char*)(ws + (long long)320 * n) + t, tiny);
     };
-    double* dd = ws + (long long)64 * 5 * n;        // batch dots, 64 x 64
     // singletons, one per thread
-    for (int c = tid(); tid() < 64 && c < ncl; c += 64) {
-        const int i = cl_start[c];
-        if (cl_start[c + 1] - i != 1) continue;
-        double* y = V + (long long)i * n;
-        for (int k = 0; k < n; ++k) start_vector(y, i, k);
-        for (int it = 0; it < 4; ++it) {
-            slot_solve(tid(), i, lam[i]);
-            double nr = 0.0;
-            for (int k = 0; k < n; ++k) nr += y[k] * y[k];
-            nr = 1.0 / sqrt(nr);
-            for (int k = 0; k < n; ++k) y[k] *= nr;
+    for (int i = r0 + tid(); tid() < 64 && i < r1; i += 64) {
+        int lo = 0, hi = ncl;                          // cluster of i: last start <= i
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (cl_start[mid] <= i) lo = mid;
+            else hi = mid;
         }
+        if (cl_start[lo] != i || cl_start[lo + 1] != i + 1) continue;
+        double* y = ws + (long long)256 * n + tid();      // interleaved iterate
+        for (int k = 0; k < n; ++k) y[64 * k] = start_value(i, k);
+        for (int it = 0; it < 4; ++it) {
+            slot_solve(tid(), y, 64, lam[i]);
+            double nr = 0.0;
+            for (int k = 0; k < n; ++k) nr += y[64 * k] * y[64 * k];
+            nr = 1.0 / sqrt(nr);
+            for (int k = 0; k < n; ++k) y[64 * k] *= nr;
+        }
+        double* out = V + (long long)i * n;
+        for (int k = 0; k < n; ++k) out[k] = y[64 * k];
     }
     __syncthreads();
     // clusters, in batches of up to 64 members
     for (int c = 0; c < ncl; ++c) {
         const int c0 = cl_start[c], c1 = cl_start[c + 1];
-        if (c1 - c0 == 1) continue;
+        if (c1 - c0 == 1 || c0 < r0 || c0 >= r1) continue;
         for (int b0 = c0; b0 < c1; b0 += 64) {
             const int bn = min(64, c1 - b0), np = b0 - c0;
             for (long long idx = tid(); idx < (long long)bn * n; idx += LSDD_WG) {
                 const int i = b0 + (int)(idx / n), k = (int)(idx % n);
-                start_vector(V + (long long)i * n, i, k);
+                V[(long long)i * n + k] = start_value(i, k);
             }
             __syncthreads();
             for (int it = 0; it < 4; ++it) {
-                if (tid() < bn) slot_solve(tid(), b0 + tid(), lam[b0 + tid()] + (b0 + tid() - c0) * 2.0 * tiny);
+                if (tid() < bn)
+                    slot_solve(tid(), V + (long long)(b0 + tid()) * n, 1, lam[b0 + tid()] + (b0 + tid() - c0) * 2.0 * tiny);
                 __syncthreads();
                 for (int pass = 0; pass < 2; ++pass) {
                     // against the earlier members of the cluster (in chunks of 64 members)
                     for (int q0 = c0; q0 < b0; q0 += 64) {
                         const int qn = min(64, b0 - q0);
-                        for (int pr = tid(); pr < qn * bn; pr += LSDD_WG) {
+                        // one wave per dot product, lanes along the vectors
+                        for (int pr = tid() >> 6; pr < qn * bn; pr += LSDD_WG / 64) {
                             const int j = q0 + pr % qn, t = pr / qn;
                             const double* q = V + (long long)j * n;
                             const double* y = V + (long long)(b0 + t) * n;
                             double s = 0.0;
-                            for (int k = 0; k < n; ++k) s += q[k] * y[k];
-                            dd[pr] = s;
+                            for (int k = tid() & 63; k < n; k += 64) s += q[k] * y[k];
+                            s = wave_sum(s);
+                            if ((tid() & 63) == 0) dd[pr] = s;
                         }
                         __syncthreads();
                         for (long long idx = tid(); idx < (long long)bn * n; idx += LSDD_WG) {
@@ -590,11 +614,12 @@ __device__ inline void wg_inverse_iteration(const double* d, const double* e, in
                     for (int t = 0; t < bn; ++t) {
                         double* y = V + (long long)(b0 + t) * n;
                         if (t > 0) {
-                            for (int s0 = tid(); s0 < t; s0 += LSDD_WG) {
+                            for (int s0 = tid() >> 6; s0 < t; s0 += LSDD_WG / 64) {
                                 const double* q = V + (long long)(b0 + s0) * n;
                                 double s = 0.0;
-                                for (int k = 0; k < n; ++k) s += q[k] * y[k];
-                                dots[s0] = s;
+                                for (int k = tid() & 63; k < n; k += 64) s += q[k] * y[k];
+                                s = wave_sum(s);
+                                if ((tid() & 63) == 0) dots[s0] = s;
                             }
                             __syncthreads();
                             for (int k = tid(); k < n; k += LSDD_WG) {
@@ -615,6 +640,15 @@ __device__ inline void wg_inverse_iteration(const double* d, const double* e, in
             }
         }
     }
+}
+
+// All kk eigenvectors in one workgroup; `ws` holds INVIT_SLOTS * n doubles of
+// interleaved scratch followed by 64 x 64 doubles of batch dots.
+__device__ inline void wg_inverse_iteration(const double* d, const double* e, int n, const double* lam, int kk,
+                                            double* V, double* ws, double tnorm, int* cl_start, double* dots,
+                                            double* red, int* ncl_sh) {
+    wg_inverse_iteration_range(d, e, n, lam, kk, 0, kk, V, ws, ws + (long long)INVIT_SLOTS * n, tnorm, cl_start,
+                               dots, red, ncl_sh);
 }
 
 // V <- Q V with Q = H_0 ... H_{n-3} from wg_tridiag (reflectors in a, tau).

@@ -328,6 +328,7 @@ __global__ void __launch_bounds__(WG) k_local_eig(LocalArgs A) {
     const int k = A.k_out[ag];
     if (small || k == 0) return;
     if (PHASE == 2) {
+        if (A.trd_min > 0 && nw >= A.trd_min) return;     // vectors by the multi-workgroup path
         const double* d = T;
         const double* e = T + nw;
         double tnorm = 0.0;
@@ -450,191 +451,6 @@ __global__ void k_dense_from_csr(int64_t off, int64_t n, const int64_t* rowptr, 
     }
 }
 
-// Single-workgroup Cholesky and explicit inverse of a dense SPD matrix.
-__global__ void __launch_bounds__(WG) k_dense_chol_inv(int n, double* W, double* inv, int32_t* status) {
-    __shared__ double s_sh[2];
-    double dmin = wg_potrf(W, n, n, s_sh);
-    if (!(dmin > 0.0)) {
-        if (tid() == 0) *status = 2;
-        return;
-    }
-    wg_identity(inv, n, n);
-    wg_trsm_lower(W, n, n, inv, n, n);
-    wg_trsm_lower_t(W, n, n, inv, n, n);
-    wg_symmetrize(inv, n, n);
-    if (tid() == 0) *status = 0;
-}
-
-// ---------------------------------------------------------------- blocked dense Cholesky / inverse
-// Column-major n x n matrix, 32 x 32 tiles staged in LDS.  Used for the
-// coarsest level, where one matrix is large enough to fill the device.
-
-constexpr int TB = 32;
-
-__device__ inline void load_tile(double (*t)[TB + 1], const double* A, int n, int r0, int c0) {
-    for (int idx = tid(); idx < TB * TB; idx += WG) {
-        int i = idx % TB, j = idx / TB;
-        int r = r0 + i, c = c0 + j;
-        t[i][j] = (r < n && c < n) ? A[r + (int64_t)c * n] : 0.0;
-    }
-}
-
-// Cholesky of the diagonal tile kb (unblocked, in LDS).
-__global__ void __launch_bounds__(WG) k_potrf_tile(double* A, int n, int kb, int32_t* status) {
-    __shared__ double t[TB][TB + 1];
-    const int r0 = kb * TB;
-    const int nb = min(TB, n - r0);
-    load_tile(t, A, n, r0, r0);
-    __syncthreads();
-    for (int j = 0; j < nb; ++j) {
-        if (tid() == 0) {
-            double d = t[j][j];
-            if (!(d > 0.0)) *status = 2;
-            t[j][j] = d > 0.0 ? sqrt(d) : 1.0;
-        }
-        __syncthreads();
-        const double s = t[j][j];
-        for (int i = j + 1 + tid(); i < nb; i += WG) t[i][j] /= s;
-        __syncthreads();
-        for (int idx = tid(); idx < nb * nb; idx += WG) {
-            int i = idx % nb, k = idx / nb;
-            if (i > j && k > j && i >= k) t[i][k] -= t[i][j] * t[k][j];
-        }
-        __syncthreads();
-    }
-    for (int idx = tid(); idx < nb * nb; idx += WG) {
-        int i = idx % nb, j = idx / nb;
-        if (i >= j) A[(r0 + i) + (int64_t)(r0 + j) * n] = t[i][j];
-    }
-}
-
-// Panel: L_ib,kb = A_ib,kb L_kk^{-T} for ib = kb+1+blockIdx.x.
-__global__ void __launch_bounds__(WG) k_trsm_tile(double* A, int n, int kb) {
-    __shared__ double L[TB][TB + 1];
-    __shared__ double X[TB][TB + 1];
-    const int ib = kb + 1 + blockIdx.x;
-    const int r0 = ib * TB, c0 = kb * TB;
-    const int nb = min(TB, n - c0);
-    load_tile(L, A, n, c0, c0);
-    load_tile(X, A, n, r0, c0);
-    __syncthreads();
-    // rows of X are independent: x L^T = a  (forward over columns)
-    const int r = tid() % TB, part = tid() / TB;     // 8 threads per row cooperate on nothing; row owner = part 0
-    if (part == 0 && r0 + r < n) {
-        for (int j = 0; j < nb; ++j) {
-            double s = X[r][j];
-            for (int t = 0; t < j; ++t) s -= X[r][t] * L[j][t];
-            X[r][j] = s / L[j][j];
-        }
-    }
-    __syncthreads();
-    for (int idx = tid(); idx < TB * TB; idx += WG) {
-        int i = idx % TB, j = idx / TB;
-        if (r0 + i < n && c0 + j < n) A[(r0 + i) + (int64_t)(c0 + j) * n] = X[i][j];
-    }
-}
-
-// Trailing update A_ij -= L_ik L_jk^T over tiles kb < jb <= ib (lower part).
-__global__ void __launch_bounds__(WG) k_syrk_tile(double* A, int n, int kb, int nt) {
-    __shared__ double Li[TB][TB + 1];
-    __shared__ double Lj[TB][TB + 1];
-    // map blockIdx.x to (ib, jb) with kb < jb <= ib < nt
-    int t = blockIdx.x;
-    int m = nt - kb - 1;
-    int jj = 0;
-    while (t >= m - jj) { t -= m - jj; ++jj; }
-    const int jb = kb + 1 + jj, ib = jb + t;
-    load_tile(Li, A, n, ib * TB, kb * TB);
-    load_tile(Lj, A, n, jb * TB, kb * TB);
-    __syncthreads();
-    for (int idx = tid(); idx < TB * TB; idx += WG) {
-        int i = idx % TB, j = idx / TB;
-        int r = ib * TB + i, c = jb * TB + j;
-        if (r < n && c < n && r >= c) {
-            double s = 0.0;
-            for (int k = 0; k < TB; ++k) s += Li[i][k] * Lj[j][k];
-            A[r + (int64_t)c * n] -= s;
-        }
-    }
-}
-
-// W <- L^{-1} W for block row kb of the forward substitution (W starts as I):
-// step 1 solves the diagonal block for every tile column jb <= kb.
-__global__ void __launch_bounds__(WG) k_trinv_diag(const double* Lm, double* W, int n, int kb) {
-    __shared__ double L[TB][TB + 1];
-    __shared__ double B[TB][TB + 1];
-    const int jb = blockIdx.x;          // 0..kb
-    const int r0 = kb * TB, c0 = jb * TB;
-    const int nb = min(TB, n - r0);
-    load_tile(L, Lm, n, r0, r0);
-    load_tile(B, W, n, r0, c0);
-    __syncthreads();
-    const int c = tid() % TB, part = tid() / TB;
-    if (part == 0) {
-        for (int i = 0; i < nb; ++i) {
-            double s = B[i][c];
-            for (int t = 0; t < i; ++t) s -= L[i][t] * B[t][c];
-            B[i][c] = s / L[i][i];
-        }
-    }
-    __syncthreads();
-    for (int idx = tid(); idx < TB * TB; idx += WG) {
-        int i = idx % TB, j = idx / TB;
-        if (r0 + i < n && c0 + j < n) W[(r0 + i) + (int64_t)(c0 + j) * n] = B[i][j];
-    }
-}
-
-// step 2: W_ib,jb -= L_ib,kb W_kb,jb for ib > kb, jb <= kb.
-__global__ void __launch_bounds__(WG) k_trinv_update(const double* Lm, double* W, int n, int kb, int nt) {
-    __shared__ double L[TB][TB + 1];
-    __shared__ double Y[TB][TB + 1];
-    const int ib = kb + 1 + blockIdx.x % (nt - kb - 1);
-    const int jb = blockIdx.x / (nt - kb - 1);
-    load_tile(L, Lm, n, ib * TB, kb * TB);
-    load_tile(Y, W, n, kb * TB, jb * TB);
-    __syncthreads();
-    for (int idx = tid(); idx < TB * TB; idx += WG) {
-        int i = idx % TB, j = idx / TB;
-        int r = ib * TB + i, c = jb * TB + j;
-        if (r < n && c < n) {
-            double s = 0.0;
-            for (int k = 0; k < TB; ++k) s += L[i][k] * Y[k][j];
-            W[r + (int64_t)c * n] -= s;
-        }
-    }
-}
-
-// X = W^T W for W = L^{-1} (lower triangular): tile (ib, jb), ib >= jb, both halves written.
-__global__ void __launch_bounds__(WG) k_wtw(const double* W, double* X, int n, int nt) {
-    __shared__ double Wi[TB][TB + 1];
-    __shared__ double Wj[TB][TB + 1];
-    int t = blockIdx.x, ib = 0;
-    while (t > ib) { t -= ib + 1; ++ib; }
-    const int jb = t;   // jb <= ib
-    double acc[4] = {0.0, 0.0, 0.0, 0.0};
-    for (int kb = ib; kb < nt; ++kb) {
-        load_tile(Wi, W, n, kb * TB, ib * TB);
-        load_tile(Wj, W, n, kb * TB, jb * TB);
-        __syncthreads();
-        for (int q = 0; q < 4; ++q) {
-            int idx = tid() + q * WG;
-            int i = idx % TB, j = idx / TB;
-            double s = 0.0;
-            for (int k = 0; k < TB; ++k) s += Wi[k][i] * Wj[k][j];
-            acc[q] += s;
-        }
-        __syncthreads();
-    }
-    for (int q = 0; q < 4; ++q) {
-        int idx = tid() + q * WG;
-        int i = idx % TB, j = idx / TB;
-        int r = ib * TB + i, c = jb * TB + j;
-        if (r < n && c < n) {
-            X[r + (int64_t)c * n] = acc[q];
-            X[c + (int64_t)r * n] = acc[q];
-        }
-    }
-}
 
 // ====================================================================== conversions
 
@@ -981,10 +797,6 @@ __global__ void k_update_p(int64_t n, const double* s_num, const double* s_den, 
     for (int64_t i = blockIdx.x * (int64_t)WG + tid(); i < n; i += (int64_t)gridDim.x * WG) p[i] = z[i] + beta * p[i];
 }
 
-__global__ void k_set_identity(int64_t n, double* a) {
-    for (int64_t i = blockIdx.x * (int64_t)WG + tid(); i < n; i += (int64_t)gridDim.x * WG) a[i + i * n] = 1.0;
-}
-
 __global__ void k_copy(int64_t n, const double* a, double* b) {
     for (int64_t i = blockIdx.x * (int64_t)WG + tid(); i < n; i += (int64_t)gridDim.x * WG) b[i] = a[i];
 }
@@ -1041,14 +853,15 @@ void launch_local_assemble(int32_t nbatch, const LocalArgs& a, int32_t max_m, hi
     hipLaunchKernelGGL(k_local_assemble, dim3((max_m + ASM_CW - 1) / ASM_CW, nbatch), dim3(WG), 0, st, a);
 }
 
-void launch_local_eig(int32_t nbatch, const LocalArgs& a, int32_t max_nw, hipStream_t st) {
+void launch_local_eig(int32_t nbatch, const LocalArgs& a, int32_t max_nw, int first_phase, int last_phase,
+                      hipStream_t st) {
     if (nbatch <= 0) return;
     // dynamic LDS: tridiagonal work vectors, cluster starts and dots, 2 |omega| doubles
     const size_t lds = (size_t)std::max(2 * max_nw, 4096) * sizeof(double);
-    hipLaunchKernelGGL(k_local_eig<0>, dim3(nbatch), dim3(WG), lds, st, a);
-    hipLaunchKernelGGL(k_local_eig<1>, dim3(nbatch), dim3(WG), lds, st, a);
-    hipLaunchKernelGGL(k_local_eig<2>, dim3(nbatch), dim3(WG), lds, st, a);
-    hipLaunchKernelGGL(k_local_eig<3>, dim3(nbatch), dim3(WG), lds, st, a);
+    if (first_phase <= 0 && last_phase >= 0) hipLaunchKernelGGL(k_local_eig<0>, dim3(nbatch), dim3(WG), lds, st, a);
+    if (first_phase <= 1 && last_phase >= 1) hipLaunchKernelGGL(k_local_eig<1>, dim3(nbatch), dim3(WG), lds, st, a);
+    if (first_phase <= 2 && last_phase >= 2) hipLaunchKernelGGL(k_local_eig<2>, dim3(nbatch), dim3(WG), lds, st, a);
+    if (first_phase <= 3 && last_phase >= 3) hipLaunchKernelGGL(k_local_eig<3>, dim3(nbatch), dim3(WG), lds, st, a);
 }
 
 void launch_stage_z(int32_t nbatch, const LocalArgs& a, hipStream_t st) {
@@ -1083,37 +896,6 @@ void launch_build_pst(const PstArgs& g, hipStream_t st) {
 void launch_dense_from_csr(int64_t off, int64_t n, const int64_t* rowptr, const int32_t* col, const double* val, double* D,
                            hipStream_t st) {
     hipLaunchKernelGGL(k_dense_from_csr, dim3((unsigned)n), dim3(WG), 0, st, off, n, rowptr, col, val, D);
-}
-
-void launch_dense_chol_inv(int64_t n, double* W, double* inv, int32_t* status, hipStream_t st) {
-    if (n <= 256) {
-        hipLaunchKernelGGL(k_dense_chol_inv, dim3(1), dim3(WG), 0, st, (int)n, W, inv, status);
-        return;
-    }
-    // blocked: W <- chol(W) (lower), inv <- L^{-1} (forward substitution on I), then inv^T inv
-    const int nn = (int)n;
-    const int nt = (nn + TB - 1) / TB;
-    hipMemsetAsync(status, 0, sizeof(int32_t), st);
-    for (int kb = 0; kb < nt; ++kb) {
-        hipLaunchKernelGGL(k_potrf_tile, dim3(1), dim3(WG), 0, st, W, nn, kb, status);
-        const int below = nt - kb - 1;
-        if (below > 0) {
-            hipLaunchKernelGGL(k_trsm_tile, dim3(below), dim3(WG), 0, st, W, nn, kb);
-            hipLaunchKernelGGL(k_syrk_tile, dim3(below * (below + 1) / 2), dim3(WG), 0, st, W, nn, kb, nt);
-        }
-    }
-    double* Linv = inv;   // reuse the output as the L^{-1} workspace, then form the product into W
-    hipLaunchKernelGGL(k_zero<double>, dim3(grid_for(n * n)), dim3(WG), 0, st, n * n, Linv);
-    hipLaunchKernelGGL(k_set_identity, dim3(grid_for(n)), dim3(WG), 0, st, n, Linv);
-    for (int kb = 0; kb < nt; ++kb) {
-        hipLaunchKernelGGL(k_trinv_diag, dim3(kb + 1), dim3(WG), 0, st, W, Linv, nn, kb);
-        const int below = nt - kb - 1;
-        if (below > 0)
-            hipLaunchKernelGGL(k_trinv_update, dim3(below * (kb + 1)), dim3(WG), 0, st, W, Linv, nn, kb, nt);
-    }
-    // W (the factor) is no longer needed: X = Linv^T Linv into W, then copy to inv
-    hipLaunchKernelGGL(k_wtw, dim3(nt * (nt + 1) / 2), dim3(WG), 0, st, Linv, W, nn, nt);
-    hipMemcpyAsync(inv, W, (size_t)n * n * sizeof(double), hipMemcpyDeviceToDevice, st);
 }
 
 void launch_to_f32(int64_t n, const double* a, float* b, hipStream_t st) {

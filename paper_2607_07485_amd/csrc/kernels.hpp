@@ -7,6 +7,7 @@
 #include <vector>
 
 #include "batched.hpp"
+#include "consts.hpp"
 #include "symv.hpp"
 
 namespace lsdd {
@@ -61,8 +62,14 @@ struct LocalArgs {
 constexpr int TRD_NB = 32;
 void launch_local_tridiag_blocked(const LocalArgs& a, const int32_t* d_big, const std::vector<int32_t>& sizes,
                                   hipStream_t st);
+// Retained eigenvectors of the tridiagonal matrices of the same entries by
+// inverse iteration, ceil(k / 64) workgroups per entry (after the mode-count
+// phase of k_local_eig); iw + iw_off[i] is entry i's scratch of
+// ceil(k_i / 64) * (INVIT_SLOTS n_i + 4096) doubles.
+void launch_local_invit_blocked(const LocalArgs& a, const int32_t* d_big, const std::vector<int32_t>& sizes,
+                                const std::vector<int32_t>& ks, const int64_t* d_iw_off, double* iw, hipStream_t st);
 // Back-transformation of the retained eigenvectors of the same entries (after
-// the eigenvalue and inverse-iteration phases of k_local_eig).
+// the eigenvalue and inverse-iteration phases).
 void launch_local_backtransform_blocked(const LocalArgs& a, const int32_t* d_big, const std::vector<int32_t>& sizes,
                                         hipStream_t st);
 
@@ -86,7 +93,8 @@ void launch_elem_bilinear(int64_t n_elem, const int64_t* elem_ptr, const int32_t
 
 void launch_local_assemble(int32_t nbatch, const LocalArgs& a, int32_t max_m, hipStream_t st);
 // max_nw: largest |omega| of the batch (<= 4096)
-void launch_local_eig(int32_t nbatch, const LocalArgs& a, int32_t max_nw, hipStream_t st);
+void launch_local_eig(int32_t nbatch, const LocalArgs& a, int32_t max_nw, int first_phase, int last_phase,
+                      hipStream_t st);
 void launch_stage_z(int32_t nbatch, const LocalArgs& a, hipStream_t st);
 void launch_views_max_diag(int32_t nv, const double* base, const View* v, double* out, hipStream_t st);
 void launch_views_add_diag(int32_t nv, double* base, const View* v, const double* delta, hipStream_t st);
@@ -121,7 +129,6 @@ void launch_build_pst(const PstArgs& g, hipStream_t st);
 // D = A[off:off+n, off:off+n] (column-major n x n; D must be zeroed first)
 void launch_dense_from_csr(int64_t off, int64_t n, const int64_t* rowptr, const int32_t* col, const double* val,
                            double* D, hipStream_t st);
-void launch_dense_chol_inv(int64_t n, double* W, double* inv, int32_t* status, hipStream_t st);
 
 void launch_to_f32(int64_t n, const double* a, float* b, hipStream_t st);
 void launch_to_f64(int64_t n, const float* a, double* b, hipStream_t st);

@@ -471,24 +471,37 @@ void make_terminal(lsdd_hierarchy* h, Level& lv, const std::vector<int32_t>& ter
     bool identity = lv.term_len == lv.n;
     for (int64_t t = 0; identity && t < lv.term_len; ++t) identity = dofs[t] == t;
     if (max_ni > 49152) throw Error(LSDD_E_UNSUPPORTED, "terminal block too large: " + std::to_string(max_ni));
-    double* W = ar.alloc<double>((size_t)max_ni * max_ni);
-    double* inv = ar.alloc<double>((size_t)inv_off[nb]);
-    int32_t* d_st = ar.alloc<int32_t>(nb);
-    HIPCHK(hipMemsetAsync(d_st, 0, nb * sizeof(int32_t), h->st));
+    // all blocks at once through the batched tiled engine: W <- chol(A_q),
+    // X <- L^{-1} (forward solve on I), then A_q^{-1} = X^T X back into W
+    double* W = ar.alloc<double>((size_t)inv_off[nb]);
+    double* X = ar.alloc<double>((size_t)inv_off[nb]);
+    double* d_minp = ar.alloc<double>(nb);
     double t0 = now_s();
+    HIPCHK(hipMemsetAsync(W, 0, (size_t)inv_off[nb] * sizeof(double), h->st));
+    std::vector<View> vq(nb);
     for (int32_t q = 0; q < nb; ++q) {
         const int64_t a = lv.inst_off[term[q]], ni = sub_off[q + 1] - sub_off[q];
-        HIPCHK(hipMemsetAsync(W, 0, (size_t)ni * ni * sizeof(double), h->st));
-        launch_dense_from_csr(a, ni, lv.d_rowptr, lv.d_col, lv.d_val, W, h->st);
-        launch_dense_chol_inv(ni, W, inv + inv_off[q], d_st + q, h->st);
+        launch_dense_from_csr(a, ni, lv.d_rowptr, lv.d_col, lv.d_val, W + inv_off[q], h->st);
+        vq[q] = View{inv_off[q], (int32_t)ni, (int32_t)ni, (int32_t)ni, 0};
     }
-    std::vector<int32_t> hs = download(d_st, nb, h->st);
+    Batched bt;
+    bt.st = h->st;
+    bt.alloc = [](void* c, size_t b) { return static_cast<Arena*>(c)->get(b); };
+    bt.release = [](void* c, void* p) { static_cast<Arena*>(c)->release(p); };
+    bt.ctx = &ar;
+    bt.potrf(W, vq, d_minp);
+    launch_views_identity(nb, X, bt.put(0, vq), h->st);
+    bt.trsm(W, vq, X, vq, false, true);
+    bt.gemm_tn(X, vq, X, vq, nullptr, vq, 0.0, W, vq, -1.0, true, true);
+    std::vector<double> minp = download(d_minp, nb, h->st);
+    bt.free_all();
     vlog("level %d: %d terminal block(s), %lld DOFs, dense Cholesky + inverse %.3f s", lv.level, nb,
          (long long)lv.term_len, now_s() - t0);
-    ar.release(W);
-    ar.release(d_st);
+    ar.release(X);
+    ar.release(d_minp);
+    double* inv = W;
     for (int32_t q = 0; q < nb; ++q)
-        if (hs[q] != 0)
+        if (!(minp[q] > 0.0))
             throw Error(LSDD_E_NUMERIC, "dense Cholesky of a terminal block failed (matrix not SPD), instance " +
                                             std::to_string(term[q]) + " on level " + std::to_string(lv.level));
     lv.c_sub_off = ar.upload(sub_off, h->st);
@@ -691,7 +704,7 @@ std::unique_ptr<Level> coarsen(lsdd_hierarchy* h, Level& lv, const int32_t* agg_
         int64_t bytes = 0;
         while (end < n_agg && (end - pos) < 32768) {
             int64_t m = C.sub_ptr[end + 1] - C.sub_ptr[end], nw = C.agg_ptr[end + 1] - C.agg_ptr[end];
-            int64_t tl = 3 * nw + 64 * 5 * nw + 64 * std::max<int64_t>(nw, 64);
+            int64_t tl = 3 * nw + (int64_t)INVIT_SLOTS * nw + 4096;
             int64_t need = (2 * m * m + 2 * nw * nw + tl) * 8;
             if (end > pos && bytes + need > budget) break;
             bytes += need;
@@ -816,8 +829,27 @@ std::unique_ptr<Level> coarsen(lsdd_hierarchy* h, Level& lv, const int32_t* agg_
                 d_big = ar.upload(big, st);
                 launch_local_tridiag_blocked(B, d_big, bigsz, st);
             }
-            launch_local_eig(nb, B, mx, st);
-            if (!big.empty()) launch_local_backtransform_blocked(B, d_big, bigsz, st);
+            launch_local_eig(nb, B, mx, 0, 1, st);
+            if (!big.empty()) {
+                // eigenvectors of the large problems: scratch sized by their mode counts
+                std::vector<int32_t> ks(big.size());
+                std::vector<int64_t> iw_off(big.size() + 1, 0);
+                std::vector<int32_t> kall = download(lv.d_k + pos, nb, st);
+                for (size_t t = 0; t < big.size(); ++t) {
+                    ks[t] = kall[big[t]];
+                    iw_off[t + 1] = iw_off[t] + (int64_t)((ks[t] + 63) / 64) * ((int64_t)INVIT_SLOTS * bigsz[t] + 4096);
+                }
+                double* iw = ar.alloc<double>(std::max<int64_t>(iw_off.back(), 1));
+                int64_t* d_iw_off = ar.upload(iw_off, st);
+                launch_local_invit_blocked(B, d_big, bigsz, ks, d_iw_off, iw, st);
+                launch_local_eig(nb, B, mx, 2, 3, st);
+                launch_local_backtransform_blocked(B, d_big, bigsz, st);
+                sync(st);
+                ar.release(iw);
+                ar.release(d_iw_off);
+            } else {
+                launch_local_eig(nb, B, mx, 2, 3, st);
+            }
         }
         HIPCHK(hipGetLastError());
         std::vector<int32_t> kb = download(lv.d_k + pos, nb, st);

@@ -284,6 +284,33 @@ __global__ void __launch_bounds__(WG) k_trd_bisect(LocalArgs A, const int32_t* b
     wg_bisect_range(T, T + n, n, A.mu + A.mu_off[ag], i0, min(n, i0 + WG), red);
 }
 
+// Retained eigenvectors of the large problems' tridiagonal matrices by
+// inverse iteration: workgroup x takes the eigenvalue indices [64x, 64x + 64)
+// (singletons one per thread, and the clusters that start there).
+__global__ void __launch_bounds__(WG) k_trd_invit(LocalArgs A, const int32_t* big, const int64_t* iw_off,
+                                                  double* iw) {
+    __shared__ double red[WG / 64];
+    __shared__ int s_ncl;
+    extern __shared__ double s_dyn[];
+    const int b = big[blockIdx.y];
+    const int ag = A.first + b;
+    const int n = (int)(A.agg_ptr[ag + 1] - A.agg_ptr[ag]);
+    const int kk = A.k_out[ag];
+    const int r0 = (int)blockIdx.x * 64;
+    if (r0 >= kk) return;
+    const double* T = A.t_buf + A.t_off[b];
+    const double* d = T;
+    const double* e = T + n;
+    double tnorm = 0.0;
+    for (int i = tid(); i < n; i += WG)
+        tnorm = fmax(tnorm, fabs(d[i]) + (i > 0 ? fabs(e[i - 1]) : 0.0) + (i + 1 < n ? fabs(e[i]) : 0.0));
+    tnorm = wg_max(tnorm, red);
+    double* ws = iw + iw_off[blockIdx.y] + (int64_t)blockIdx.x * ((int64_t)INVIT_SLOTS * n + 4096);
+    wg_inverse_iteration_range(d, e, n, A.mu + A.mu_off[ag], kk, r0, min(kk, r0 + 64), A.w1 + A.ws_off[b], ws,
+                               ws + (int64_t)INVIT_SLOTS * n, fmax(tnorm, 1e-300), (int*)s_dyn, s_dyn + n, red,
+                               &s_ncl);
+}
+
 // Retained eigenvectors x <- Q x (Q = H_0 ... H_{n-3}) for the large
 // problems: one wave per vector (VS = W1, n x k, ld n), reflectors applied
 // from the last to the first.  Lane l owns the rows r = l (mod 64) of its
@@ -320,6 +347,19 @@ void launch_local_backtransform_blocked(const LocalArgs& a, const int32_t* d_big
     int max_n = 0;
     for (int32_t s : sizes) max_n = std::max(max_n, (int)s);
     hipLaunchKernelGGL(k_trd_backtransform, dim3((max_n + WG / 64 - 1) / (WG / 64), nbig), dim3(WG), 0, st, a, d_big);
+}
+
+void launch_local_invit_blocked(const LocalArgs& a, const int32_t* d_big, const std::vector<int32_t>& sizes,
+                                const std::vector<int32_t>& ks, const int64_t* d_iw_off, double* iw, hipStream_t st) {
+    const int nbig = (int)sizes.size();
+    int max_n = 0, max_g = 0;
+    for (int i = 0; i < nbig; ++i) {
+        max_n = std::max(max_n, (int)sizes[i]);
+        max_g = std::max(max_g, (ks[i] + 63) / 64);
+    }
+    if (max_g == 0) return;
+    const size_t lds = (size_t)(max_n + 64) * sizeof(double);
+    hipLaunchKernelGGL(k_trd_invit, dim3(max_g, nbig), dim3(WG), lds, st, a, d_big, d_iw_off, iw);
 }
 
 void launch_local_tridiag_blocked(const LocalArgs& a, const int32_t* d_big, const std::vector<int32_t>& sizes,
