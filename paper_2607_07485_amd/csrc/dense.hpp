@@ -10,6 +10,7 @@
 #include <cmath>
 
 #include "consts.hpp"
+#include "mgemm.hpp"
 
 #define LSDD_WG 256
 
@@ -463,31 +464,30 @@ __device__ inline void wg_bisect_all(const double* d, const double* e, int n, do
 // solving 64 systems at once can keep their scratch interleaved (S = 64,
 // coalesced) without changing the arithmetic.
 template <int S>
-__device__ inline void tri_shift_solve(const double* d, const double* e, int n, double lam, double* b, int bs,
-                                       double* u0, double* u1, double* u2, double* l, unsigned char* piv,
-                                       double tiny) {
-    // factor: rows k hold (u0[k], u1[k], u2[k]) on diagonals 0, +1, +2
+__device__ inline void tri_shift_solve(const double* __restrict__ d, const double* __restrict__ e, int n, double lam,
+                                       double* __restrict__ b, int bs, double* __restrict__ u0,
+                                       double* __restrict__ u1, double* __restrict__ u2, double* __restrict__ l,
+                                       unsigned char* __restrict__ piv, double tiny) {
+    // factor: rows k hold (u0[k], u1[k], u2[k]) on diagonals 0, +1, +2; both
+    // pivot cases share one division (the quotient of the smaller by the
+    // larger of a0 and the subdiagonal entry)
     double a0 = d[0] - lam, a1 = (n > 1) ? e[0] : 0.0;
     for (int k = 0; k < n - 1; ++k) {
-        double sub = e[k];
-        double nd = d[k + 1] - lam;
-        double ns = (k + 2 < n) ? e[k + 1] : 0.0;
-        if (fabs(a0) >= fabs(sub)) {
-            piv[k * S] = 0;
-            if (fabs(a0) < tiny) a0 = (a0 >= 0.0 ? tiny : -tiny);
-            u0[k * S] = a0; u1[k * S] = a1; u2[k * S] = 0.0;
-            double f = sub / a0;
-            l[k * S] = f;
-            a0 = nd - f * a1;
-            a1 = ns;
-        } else {
-            piv[k * S] = 1;
-            u0[k * S] = sub; u1[k * S] = nd; u2[k * S] = ns;
-            double f = a0 / sub;
-            l[k * S] = f;
-            a0 = a1 - f * nd;
-            a1 = -f * ns;
-        }
+        const double sub = e[k];
+        const double nd = d[k + 1] - lam;
+        const double ns = (k + 2 < n) ? e[k + 1] : 0.0;
+        const bool sw = !(fabs(a0) >= fabs(sub));
+        if (!sw && fabs(a0) < tiny) a0 = (a0 >= 0.0 ? tiny : -tiny);
+        const double den = sw ? sub : a0;
+        const double f = (sw ? a0 : sub) / den;
+        piv[k * S] = sw ? 1 : 0;
+        u0[k * S] = den;
+        u1[k * S] = sw ? nd : a1;
+        u2[k * S] = sw ? ns : 0.0;
+        l[k * S] = f;
+        const double a0n = sw ? a1 - f * nd : nd - f * a1;
+        a1 = sw ? -f * ns : ns;
+        a0 = a0n;
     }
     if (fabs(a0) < tiny) a0 = (a0 >= 0.0 ? tiny : -tiny);
     u0[(n - 1) * S] = a0; u1[(n - 1) * S] = 0.0; u2[(n - 1) * S] = 0.0;
@@ -513,6 +513,112 @@ __device__ inline void tri_shift_solve(const double* d, const double* e, int n, 
     }
 }
 
+// dd[j + t qn] = Q_j . Y_t for the columns Q_j = V[:, q0 + j] (j < qn <= 64) and
+// Y_t = V[:, b0 + t] (t < bn <= 64) of the column-major V (ld n): each thread
+// accumulates a 4 x 4 block of products over the rows in order.
+__device__ inline void wg_block_dots(const double* V, int n, int q0, int qn, int b0, int bn, double* dd) {
+    const int ib = tid() & 15, jb = tid() >> 4;
+    if (4 * ib >= qn || 4 * jb >= bn) return;
+    const double* qp[4];
+    const double* yp[4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+        qp[a] = V + (long long)(q0 + min(4 * ib + a, qn - 1)) * n;
+        yp[a] = V + (long long)(b0 + min(4 * jb + a, bn - 1)) * n;
+    }
+    double acc[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) acc[a][c] = 0.0;
+    for (int k = 0; k < n; ++k) {
+        double qv[4], yv[4];
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+            qv[a] = qp[a][k];
+            yv[a] = yp[a][k];
+        }
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int c = 0; c < 4; ++c) acc[a][c] += qv[a] * yv[c];
+    }
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+            if (4 * ib + a < qn && 4 * jb + c < bn) dd[(4 * ib + a) + (4 * jb + c) * qn] = acc[a][c];
+}
+
+// Y_t -= sum_j dd[j + t qn] Q_j (same columns as wg_block_dots); each thread
+// takes 4 rows x 4 members, the sum over j in order.
+__device__ inline void wg_block_update(double* V, int n, int q0, int qn, int b0, int bn, const double* dd) {
+    const int nr = (n + 3) / 4, nc = (bn + 3) / 4;
+    for (int w = tid(); w < nr * nc; w += LSDD_WG) {
+        const int r = 4 * (w % nr), c0 = 4 * (w / nr);
+        double acc[4][4];
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int c = 0; c < 4; ++c) acc[a][c] = 0.0;
+        for (int j = 0; j < qn; ++j) {
+            const double* q = V + (long long)(q0 + j) * n + r;
+            double qv[4], dv[4];
+#pragma unroll
+            for (int a = 0; a < 4; ++a) {
+                qv[a] = (r + a < n) ? q[a] : 0.0;
+                dv[a] = (c0 + a < bn) ? dd[j + (c0 + a) * qn] : 0.0;
+            }
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int c = 0; c < 4; ++c) acc[a][c] += qv[a] * dv[c];
+        }
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+                if (r + a < n && c0 + c < bn) V[(long long)(b0 + c0 + c) * n + r + a] -= acc[a][c];
+    }
+}
+
+// The same two steps on the FP64 matrix cores (one 64 x 64 tile of Q^T Y with
+// K = n; then Y -= Q dd tile by tile down the rows).
+__device__ inline void wg_block_dots_mfma(mg::Smem& sm, const double* V, int n, int q0, int qn, int b0, int bn,
+                                          double* dd) {
+    mg::d4 acc[2][2];
+    mg::zero(acc);
+    mg::tile_mma<mg::KMAJ, mg::KMAJ>(sm, V + (long long)q0 * n, n, 0, qn, V + (long long)b0 * n, n, 0, bn, 0, n,
+                                     acc);
+#pragma unroll
+    for (int p = 0; p < 2; ++p)
+#pragma unroll
+        for (int q = 0; q < 2; ++q)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int i = mg::acc_row(p, v), j = mg::acc_col(q);
+                if (i < qn && j < bn) dd[i + j * qn] = acc[p][q][v];
+            }
+}
+
+__device__ inline void wg_block_update_mfma(mg::Smem& sm, double* V, int n, int q0, int qn, int b0, int bn,
+                                            const double* dd) {
+    for (int r0 = 0; r0 < n; r0 += mg::T) {
+        mg::d4 acc[2][2];
+        mg::zero(acc);
+        mg::tile_mma<mg::IMAJ, mg::KMAJ>(sm, V + (long long)q0 * n + r0, n, 0, n - r0, dd, qn, 0, bn, 0, qn, acc);
+#pragma unroll
+        for (int p = 0; p < 2; ++p)
+#pragma unroll
+            for (int q = 0; q < 2; ++q)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int i = r0 + mg::acc_row(p, v), t = mg::acc_col(q);
+                    if (i < n && t < bn) V[(long long)(b0 + t) * n + i] -= acc[p][q][v];
+                }
+    }
+}
+
 // Eigenvectors of the tridiagonal (d, e) for the eigenvalues lam[0..kk) by
 // inverse iteration.  Eigenvalues closer than 1e-4 * tnorm form a cluster.
 // This workgroup handles the single-member clusters with index in [r0, r1)
@@ -525,10 +631,12 @@ __device__ inline void tri_shift_solve(const double* d, const double* e, int n, 
 // within the batch, and normalises it.  Every vector is computed the same way
 // whatever the range split.  Output V (n x kk, column-major, ld n); `dd` holds
 // 64 x 64 batch dots.  LDS: cl_start (kk+1 ints), dots (64).
+// sm: LDS staging of the matrix cores for the block Gram-Schmidt steps of
+// clusters (NULL: the same steps as register-blocked vector loops).
 __device__ inline void wg_inverse_iteration_range(const double* d, const double* e, int n, const double* lam,
                                                   int kk, int r0, int r1, double* V, double* ws, double* dd,
                                                   double tnorm, int* cl_start, double* dots, double* red,
-                                                  int* ncl_sh) {
+                                                  int* ncl_sh, mg::Smem* sm = nullptr) {
     const double eps = 2.220446049250313e-16;
     const double gaptol = 1e-4 * tnorm;
     if (tid() == 0) {
@@ -591,22 +699,14 @@ __device__ inline void wg_inverse_iteration_range(const double* d, const double*
                     // against the earlier members of the cluster (in chunks of 64 members)
                     for (int q0 = c0; q0 < b0; q0 += 64) {
                         const int qn = min(64, b0 - q0);
-                        // one wave per dot product, lanes along the vectors
-                        for (int pr = tid() >> 6; pr < qn * bn; pr += LSDD_WG / 64) {
-                            const int j = q0 + pr % qn, t = pr / qn;
-                            const double* q = V + (long long)j * n;
-                            const double* y = V + (long long)(b0 + t) * n;
-                            double s = 0.0;
-                            for (int k = tid() & 63; k < n; k += 64) s += q[k] * y[k];
-                            s = wave_sum(s);
-                            if ((tid() & 63) == 0) dd[pr] = s;
-                        }
-                        __syncthreads();
-                        for (long long idx = tid(); idx < (long long)bn * n; idx += LSDD_WG) {
-                            const int t = (int)(idx / n), k = (int)(idx % n);
-                            double s = 0.0;
-                            for (int j = 0; j < qn; ++j) s += V[(long long)(q0 + j) * n + k] * dd[j + t * qn];
-                            V[(long long)(b0 + t) * n + k] -= s;
+                        if (sm) {
+                            wg_block_dots_mfma(*sm, V, n, q0, qn, b0, bn, dd);
+                            __syncthreads();
+                            wg_block_update_mfma(*sm, V, n, q0, qn, b0, bn, dd);
+                        } else {
+                            wg_block_dots(V, n, q0, qn, b0, bn, dd);
+                            __syncthreads();
+                            wg_block_update(V, n, q0, qn, b0, bn, dd);
                         }
                         __syncthreads();
                     }

@@ -291,6 +291,7 @@ __global__ void __launch_bounds__(WG) k_trd_invit(LocalArgs A, const int32_t* bi
                                                   double* iw) {
     __shared__ double red[WG / 64];
     __shared__ int s_ncl;
+    __shared__ mg::Smem sm;
     extern __shared__ double s_dyn[];
     const int b = big[blockIdx.y];
     const int ag = A.first + b;
@@ -307,8 +308,8 @@ __global__ void __launch_bounds__(WG) k_trd_invit(LocalArgs A, const int32_t* bi
     tnorm = wg_max(tnorm, red);
     double* ws = iw + iw_off[blockIdx.y] + (int64_t)blockIdx.x * ((int64_t)INVIT_SLOTS * n + 4096);
     wg_inverse_iteration_range(d, e, n, A.mu + A.mu_off[ag], kk, r0, min(kk, r0 + 64), A.w1 + A.ws_off[b], ws,
-                               ws + (int64_t)INVIT_SLOTS * n, fmax(tnorm, 1e-300), (int*)s_dyn, s_dyn + n, red,
-                               &s_ncl);
+                               ws + (int64_t)INVIT_SLOTS * n, fmax(tnorm, 1e-300), (int*)(s_dyn + 64), s_dyn, red,
+                               &s_ncl, &sm);
 }
 
 // Retained eigenvectors x <- Q x (Q = H_0 ... H_{n-3}) for the large
@@ -358,7 +359,7 @@ void launch_local_invit_blocked(const LocalArgs& a, const int32_t* d_big, const 
         max_g = std::max(max_g, (ks[i] + 63) / 64);
     }
     if (max_g == 0) return;
-    const size_t lds = (size_t)(max_n + 64) * sizeof(double);
+    const size_t lds = 64 * sizeof(double) + (size_t)(max_n + 1) * sizeof(int);   // dots, cluster starts
     hipLaunchKernelGGL(k_trd_invit, dim3(max_g, nbig), dim3(WG), lds, st, a, d_big, d_iw_off, iw);
 }
 
