@@ -71,7 +71,8 @@ __global__ void __launch_bounds__(WG) k_csr_spmv_b(int64_t n, const int64_t* row
 // right-hand sides 2w and 2w+1: lane = row for the row part (accumulated over
 // the item's tiles in registers) and lane = column for the column part, so no
 // cross-lane reduction is needed.  The next tile is prefetched into registers
-// while the current one is used.
+// (non-temporal loads: the tiles stream once per application) while the
+// current one is used.
 template <typename T>
 __global__ void __launch_bounds__(WG) k_sub_symv_b(const int32_t* items, const int64_t* sub_off,
                                                    const int64_t* tp_off, const T* tiles, const T* rloc,
@@ -98,7 +99,7 @@ __global__ void __launch_bounds__(WG) k_sub_symv_b(const int32_t* items, const i
     const T* row0 = tiles + tp_off[s] + (int64_t)I * (I + 1) / 2 * 4096;
     T v[16];
 #pragma unroll
-    for (int i = 0; i < 16; ++i) v[i] = row0[(int64_t)J0 * 4096 + i * WG + tid()];
+    for (int i = 0; i < 16; ++i) v[i] = __builtin_nontemporal_load(row0 + (int64_t)J0 * 4096 + i * WG + tid());
     T ar0 = 0, ar1 = 0;
     for (int jj = 0; jj < nJ; ++jj) {
         const int J = J0 + jj;
@@ -115,7 +116,7 @@ __global__ void __launch_bounds__(WG) k_sub_symv_b(const int32_t* items, const i
         __syncthreads();
         if (jj + 1 < nJ) {
 #pragma unroll
-            for (int i = 0; i < 16; ++i) v[i] = row0[(int64_t)(J + 1) * 4096 + i * WG + tid()];
+            for (int i = 0; i < 16; ++i) v[i] = __builtin_nontemporal_load(row0 + (int64_t)(J + 1) * 4096 + i * WG + tid());
         }
         const T* tr = s_t + lane * 65;
 #pragma unroll 8

@@ -459,57 +459,120 @@ __device__ inline void wg_bisect_all(const double* d, const double* e, int n, do
 }
 
 // Solve (T - lam I) y = b in place for the tridiagonal (d, e) by Gaussian
-// elimination with partial pivoting.  b has stride bs; the factor scratch
-// u0, u1, u2, l, piv (n entries each) has stride S, so the 64 lanes of a wave
+// elimination with partial pivoting.  b has stride bs; the upper factor
+// scratch u0, u1, u2 (n entries each) has stride S, so the 64 lanes of a wave
 // solving 64 systems at once can keep their scratch interleaved (S = 64,
-// coalesced) without changing the arithmetic.
+// coalesced) without changing the arithmetic.  The elimination is applied to
+// b as the factor is formed (one pass), then back substitution.  Both passes
+// load the operands of the next block of TRI_PB rows before working on the
+// current block, so a lane's chain of dependent divisions does not wait on
+// memory latency or on the completion of its own stores.
+constexpr int TRI_PB = 8;
+
 template <int S>
 __device__ inline void tri_shift_solve(const double* __restrict__ d, const double* __restrict__ e, int n, double lam,
                                        double* __restrict__ b, int bs, double* __restrict__ u0,
-                                       double* __restrict__ u1, double* __restrict__ u2, double* __restrict__ l,
-                                       unsigned char* __restrict__ piv, double tiny) {
-    // factor: rows k hold (u0[k], u1[k], u2[k]) on diagonals 0, +1, +2; both
-    // pivot cases share one division (the quotient of the smaller by the
-    // larger of a0 and the subdiagonal entry)
+                                       double* __restrict__ u1, double* __restrict__ u2, double tiny) {
+    // rows k hold (u0[k], u1[k], u2[k]) on diagonals 0, +1, +2 of U; both pivot
+    // cases share one division (the quotient of the smaller by the larger of
+    // a0 and the subdiagonal entry)
     double a0 = d[0] - lam, a1 = (n > 1) ? e[0] : 0.0;
-    for (int k = 0; k < n - 1; ++k) {
-        const double sub = e[k];
-        const double nd = d[k + 1] - lam;
-        const double ns = (k + 2 < n) ? e[k + 1] : 0.0;
-        const bool sw = !(fabs(a0) >= fabs(sub));
-        if (!sw && fabs(a0) < tiny) a0 = (a0 >= 0.0 ? tiny : -tiny);
-        const double den = sw ? sub : a0;
-        const double f = (sw ? a0 : sub) / den;
-        piv[k * S] = sw ? 1 : 0;
-        u0[k * S] = den;
-        u1[k * S] = sw ? nd : a1;
-        u2[k * S] = sw ? ns : 0.0;
-        l[k * S] = f;
-        const double a0n = sw ? a1 - f * nd : nd - f * a1;
-        a1 = sw ? -f * ns : ns;
-        a0 = a0n;
+    double bk = b[0];
+    double E[TRI_PB + 1], D[TRI_PB], B[TRI_PB];
+    double En[TRI_PB + 1], Dn[TRI_PB], Bn[TRI_PB];
+    auto fetch_fwd = [&](int k0, double (&e_)[TRI_PB + 1], double (&d_)[TRI_PB], double (&b_)[TRI_PB]) {
+#pragma unroll
+        for (int u = 0; u <= TRI_PB; ++u) e_[u] = (k0 + u < n - 1) ? e[k0 + u] : 0.0;
+#pragma unroll
+        for (int u = 0; u < TRI_PB; ++u) {
+            const bool ok = k0 + u < n - 1;
+            d_[u] = ok ? d[k0 + u + 1] : 0.0;
+            b_[u] = ok ? b[(k0 + u + 1) * bs] : 0.0;
+        }
+    };
+    fetch_fwd(0, E, D, B);
+    for (int k0 = 0; k0 < n - 1; k0 += TRI_PB) {
+        if (k0 + TRI_PB < n - 1) fetch_fwd(k0 + TRI_PB, En, Dn, Bn);
+#pragma unroll
+        for (int u = 0; u < TRI_PB; ++u) {
+            const int k = k0 + u;
+            if (k < n - 1) {
+                const double sub = E[u];
+                const double nd = D[u] - lam;
+                const double ns = E[u + 1];           // e[k + 1], 0 past the end
+                const bool sw = !(fabs(a0) >= fabs(sub));
+                if (!sw && fabs(a0) < tiny) a0 = (a0 >= 0.0 ? tiny : -tiny);
+                const double den = sw ? sub : a0;
+                const double f = (sw ? a0 : sub) / den;
+                u0[k * S] = den;
+                u1[k * S] = sw ? nd : a1;
+                u2[k * S] = sw ? ns : 0.0;
+                const double a0n = sw ? a1 - f * nd : nd - f * a1;
+                a1 = sw ? -f * ns : ns;
+                a0 = a0n;
+                // the same elimination step on b (rows k and k + 1, swapped if pivoted)
+                double bn = B[u];
+                if (sw) {
+                    const double t = bk;
+                    bk = bn;
+                    bn = t;
+                }
+                b[k * bs] = bk;
+                bk = bn - f * bk;
+            }
+        }
+#pragma unroll
+        for (int u = 0; u <= TRI_PB; ++u) E[u] = En[u];
+#pragma unroll
+        for (int u = 0; u < TRI_PB; ++u) {
+            D[u] = Dn[u];
+            B[u] = Bn[u];
+        }
     }
     if (fabs(a0) < tiny) a0 = (a0 >= 0.0 ? tiny : -tiny);
-    u0[(n - 1) * S] = a0; u1[(n - 1) * S] = 0.0; u2[(n - 1) * S] = 0.0;
-    // forward (b[k] carried in a register)
-    double bk = b[0];
-    for (int k = 0; k < n - 1; ++k) {
-        double bn = b[(k + 1) * bs];
-        if (piv[k * S]) { double t = bk; bk = bn; bn = t; }
-        b[k * bs] = bk;
-        bk = bn - l[k * S] * bk;
-    }
+    u0[(n - 1) * S] = a0;
+    u1[(n - 1) * S] = 0.0;
+    u2[(n - 1) * S] = 0.0;
     b[(n - 1) * bs] = bk;
-    // backward
+    // back substitution, rows n-1 .. 0 in blocks of TRI_PB (row k = k1 - u)
+    double Y[TRI_PB], P0[TRI_PB], P1[TRI_PB], P2[TRI_PB];
+    double Yn[TRI_PB], P0n[TRI_PB], P1n[TRI_PB], P2n[TRI_PB];
+    auto fetch_bwd = [&](int k1, double (&y_)[TRI_PB], double (&p0)[TRI_PB], double (&p1)[TRI_PB],
+                         double (&p2)[TRI_PB]) {
+#pragma unroll
+        for (int u = 0; u < TRI_PB; ++u) {
+            const int k = k1 - u;
+            const bool ok = k >= 0;
+            y_[u] = ok ? b[k * bs] : 0.0;
+            p0[u] = ok ? u0[k * S] : 1.0;
+            p1[u] = ok ? u1[k * S] : 0.0;
+            p2[u] = ok ? u2[k * S] : 0.0;
+        }
+    };
     double x1 = 0.0, x2 = 0.0;
-    for (int k = n - 1; k >= 0; --k) {
-        double s = b[k * bs];
-        if (k + 1 < n) s -= u1[k * S] * x1;
-        if (k + 2 < n) s -= u2[k * S] * x2;
-        const double xk = s / u0[k * S];
-        b[k * bs] = xk;
-        x2 = x1;
-        x1 = xk;
+    fetch_bwd(n - 1, Y, P0, P1, P2);
+    for (int k1 = n - 1; k1 >= 0; k1 -= TRI_PB) {
+        if (k1 - TRI_PB >= 0) fetch_bwd(k1 - TRI_PB, Yn, P0n, P1n, P2n);
+#pragma unroll
+        for (int u = 0; u < TRI_PB; ++u) {
+            const int k = k1 - u;
+            if (k >= 0) {
+                double s = Y[u];
+                if (k + 1 < n) s -= P1[u] * x1;
+                if (k + 2 < n) s -= P2[u] * x2;
+                const double xk = s / P0[u];
+                b[k * bs] = xk;
+                x2 = x1;
+                x1 = xk;
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < TRI_PB; ++u) {
+            Y[u] = Yn[u];
+            P0[u] = P0n[u];
+            P1[u] = P1n[u];
+            P2[u] = P2n[u];
+        }
     }
 }
 
@@ -624,7 +687,8 @@ __device__ inline void wg_block_update_mfma(mg::Smem& sm, double* V, int n, int 
 // This workgroup handles the single-member clusters with index in [r0, r1)
 // and the larger clusters that start there.  Singletons run one per thread
 // (threads 0..63).  `ws` holds INVIT_SLOTS * n doubles: the factor scratch
-// and singleton iterates of the 64 solving lanes, interleaved by lane.  The members of a larger cluster are processed in batches of up
+// (u0, u1, u2) and singleton iterates of the 64 solving lanes, interleaved by
+// lane.  The members of a larger cluster are processed in batches of up
 // to 64: each iteration solves every member's shifted system on its own
 // thread, then orthogonalises the batch by classical Gram-Schmidt applied
 // twice against the earlier members of the cluster and, in index order,
@@ -656,7 +720,7 @@ __device__ inline void wg_inverse_iteration_range(const double* d, const double*
     // lane-interleaved scratch of the 64 solving threads (lane t: entry k at [64 k + t])
     auto slot_solve = [&](int t, double* b, int bs, double shift) {
         tri_shift_solve<64>(d, e, n, shift, b, bs, ws + t, ws + (long long)64 * n + t, ws + (long long)128 * n + t,
-                            ws + (long long)192 * n + t, (unsigned char*)(ws + (long long)320 * n) + t, tiny);
+                            tiny);
     };
     // singletons, one per thread
     for (int i = r0 + tid(); tid() < 64 && i < r1; i += 64) {
@@ -667,7 +731,7 @@ __device__ inline void wg_inverse_iteration_range(const double* d, const double*
             else hi = mid;
         }
         if (cl_start[lo] != i || cl_start[lo + 1] != i + 1) continue;
-        double* y = ws + (long long)256 * n + tid();      // interleaved iterate
+        double* y = ws + (long long)192 * n + tid();      // interleaved iterate
         for (int k = 0; k < n; ++k) y[64 * k] = start_value(i, k);
         for (int it = 0; it < 4; ++it) {
             slot_solve(tid(), y, 64, lam[i]);

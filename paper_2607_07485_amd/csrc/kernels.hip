@@ -464,7 +464,9 @@ __global__ void k_to_f64(int64_t n, const float* a, double* b) {
 // ====================================================================== solve kernels
 
 // out[t] = r[rows[t]] - sum_q A[rows[t], q] x[q]; L lanes per row (16 for
-// short rows, a whole wave for the long rows of coarse levels)
+// short rows, a whole wave for the long rows of coarse levels).  The matrix
+// streams (values, column indices) are read non-temporally, the gathered x
+// through the caches.
 template <typename T, int L>
 __global__ void __launch_bounds__(WG) k_csr_resid_rows(int64_t nrows, const int32_t* rows, const int64_t* rowptr,
                                                        const int32_t* col, const T* val, const T* x, const T* r,
@@ -479,10 +481,10 @@ __global__ void __launch_bounds__(WG) k_csr_resid_rows(int64_t nrows, const int3
             int64_t q = rowptr[p] + lane;
             T s1 = 0;
             for (; q + L < q1; q += 2 * L) {
-                s += val[q] * x[col[q]];
-                s1 += val[q + L] * x[col[q + L]];
+                s += __builtin_nontemporal_load(val + q) * x[__builtin_nontemporal_load(col + q)];
+                s1 += __builtin_nontemporal_load(val + q + L) * x[__builtin_nontemporal_load(col + q + L)];
             }
-            if (q < q1) s += val[q] * x[col[q]];
+            if (q < q1) s += __builtin_nontemporal_load(val + q) * x[__builtin_nontemporal_load(col + q)];
             s += s1;
         }
         for (int off = L / 2; off > 0; off >>= 1) s += __shfl_xor(s, off, L);
@@ -501,10 +503,10 @@ __global__ void __launch_bounds__(WG) k_csr_spmv(int64_t n, const int64_t* rowpt
         int64_t q = rowptr[p] + lane;
         T s = 0, s1 = 0;
         for (; q + L < q1; q += 2 * L) {
-            s += val[q] * x[col[q]];
-            s1 += val[q + L] * x[col[q + L]];
+            s += __builtin_nontemporal_load(val + q) * x[__builtin_nontemporal_load(col + q)];
+            s1 += __builtin_nontemporal_load(val + q + L) * x[__builtin_nontemporal_load(col + q + L)];
         }
-        if (q < q1) s += val[q] * x[col[q]];
+        if (q < q1) s += __builtin_nontemporal_load(val + q) * x[__builtin_nontemporal_load(col + q)];
         s += s1;
         for (int off = L / 2; off > 0; off >>= 1) s += __shfl_xor(s, off, L);
         if (lane == 0) y[p] = r_minus ? r_minus[p] - s : s;
@@ -513,21 +515,26 @@ __global__ void __launch_bounds__(WG) k_csr_spmv(int64_t n, const int64_t* rowpt
 
 // Subdomain correction with the packed symmetric inverse: A_Omega^{-1} is stored
 // as its lower 64 x 64 tiles (tile (I, J), I >= J, row-major inside the tile,
-// zero-padded past |Omega|; the diagonal tiles hold both triangles).  Work item
-// = (subdomain, tile row I, chunk of up to `chl` tiles J): waves split the 64
-// rows of the tile row, lanes the 64 columns.  Tile (I, J) is read once and
-// used twice: its rows give y_I += T x_J (per-lane partials, reduced across
-// lanes once per item) and its columns give y_J += T^T x_I (J < I; kept in
-// registers and summed over the waves in LDS once per item).  Partial results
-// go to a per-subdomain scratch -- row parts per (tile row, chunk), column
-// parts per tile -- that k_sub_finalize sums in a fixed order, so the smoother
-// is the same linear map on every application (no order-dependent atomics).
+// zero-padded past |Omega|; the diagonal tiles hold both triangles, of which
+// only the lower one is read).  Work item = (subdomain, tile row I, chunk of up
+// to `chl` tiles J): waves split the 64 rows of the tile row, lanes the 64
+// columns.  Tile (I, J) is read once and used twice: its rows give
+// y_I += T x_J (per-lane partials, reduced across lanes once per item) and its
+// columns give y_J += T^T x_I (J < I; kept in registers and summed over the
+// waves in LDS once per item); on the diagonal tile the columns of the strict
+// lower triangle give the upper part of the product and are added to the
+// item's row part.  Partial results go to a per-subdomain scratch -- row parts
+// per (tile row, chunk), column parts per tile -- that k_sub_finalize sums in a
+// fixed order, so the smoother is the same linear map on every application (no
+// order-dependent atomics).
 template <typename T>
 __global__ void __launch_bounds__(WG) k_sub_symv(const int32_t* items, const int64_t* sub_off, const int64_t* tp_off,
                                                  const T* tiles, const T* rloc, const int64_t* scr_off, T* scr,
                                                  int chl) {
     __shared__ T s_x[SUB_MAX_CHUNK * 64];
+    __shared__ T s_xi[64];
     __shared__ T s_c[4][SUB_MAX_CHUNK][64];
+    __shared__ T s_d[4][64];
     const int s = items[3 * blockIdx.x];
     const int I = items[3 * blockIdx.x + 1];
     const int ch = items[3 * blockIdx.x + 2];
@@ -542,54 +549,53 @@ __global__ void __launch_bounds__(WG) k_sub_symv(const int32_t* items, const int
         s_x[a] = c < m ? rloc[o + c] : (T)0;
     }
     const int lane = tid() & 63, w = tid() >> 6;
-    T xi[16];
-#pragma unroll
-    for (int q = 0; q < 16; ++q) {
-        int r = I * 64 + w + 4 * q;
-        xi[q] = r < m ? rloc[o + r] : (T)0;
+    if (tid() < 64) {
+        const int r = I * 64 + tid();
+        s_xi[tid()] = r < m ? rloc[o + r] : (T)0;
     }
     __syncthreads();
     const T* row0 = tiles + tp_off[s] + (int64_t)I * (I + 1) / 2 * 4096;
     T* part = scr + scr_off[s];
     T* colpart = part + symv_rowpart_off(nt, chl) * 64;
-    T p[16], cv[SUB_MAX_CHUNK];
+    T p[16];
 #pragma unroll
     for (int q = 0; q < 16; ++q) p[q] = 0;
 #pragma unroll
     for (int jj = 0; jj < SUB_MAX_CHUNK; ++jj) {
-        cv[jj] = 0;
         if (jj < nJ) {
+            const bool dg = J0 + jj == I;
             const T* t = row0 + (int64_t)(J0 + jj) * 4096 + lane;
             const T xj = s_x[jj * 64 + lane];
             T v[16];
 #pragma unroll
-            for (int q = 0; q < 16; ++q) v[q] = t[(w + 4 * q) * 64];
+            for (int q = 0; q < 16; ++q)    // streamed once per application: non-temporal
+                v[q] = (!dg || lane <= w + 4 * q) ? __builtin_nontemporal_load(t + (w + 4 * q) * 64) : (T)0;
             T col = 0;
 #pragma unroll
             for (int q = 0; q < 16; ++q) {
                 p[q] += v[q] * xj;
-                col += v[q] * xi[q];
+                if (!dg || lane < w + 4 * q) col += v[q] * s_xi[w + 4 * q];
             }
-            cv[jj] = col;
+            if (dg) s_d[w][lane] = col;
+            else s_c[w][jj][lane] = col;
         }
     }
-#pragma unroll
-    for (int jj = 0; jj < SUB_MAX_CHUNK; ++jj)
-        if (jj < ncol) s_c[w][jj][lane] = cv[jj];
 #pragma unroll
     for (int q = 0; q < 16; ++q) {
         T v = p[q];
         for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
         p[q] = v;
     }
+    __syncthreads();
     if (lane < 16) {
         T y = 0;
 #pragma unroll
         for (int q = 0; q < 16; ++q)
             if (q == lane) y = p[q];
-        part[(symv_rowpart_off(I, chl) + ch) * 64 + w + 4 * lane] = y;
+        const int r = w + 4 * lane;
+        if (ncol < nJ) y += (s_d[0][r] + s_d[1][r]) + (s_d[2][r] + s_d[3][r]);
+        part[(symv_rowpart_off(I, chl) + ch) * 64 + r] = y;
     }
-    __syncthreads();
     for (int a = tid(); a < ncol * 64; a += WG) {
         const int jj = a >> 6, l = a & 63;
         colpart[((int64_t)I * (I - 1) / 2 + J0 + jj) * 64 + l] =
