@@ -263,6 +263,67 @@ Csr assembled_pattern(int64_t n, const ElemList& el) {
     return p;
 }
 
+bool assembled_pattern_blocked(int64_t n, const ElemList& el, const std::vector<int32_t>& node_of_dof,
+                               int32_t n_super, Csr& p) {
+    std::vector<int64_t> first(n_super + 1, -1);
+    for (int64_t d = 0; d < n; ++d) {
+        const int32_t s = node_of_dof[d];
+        if (d > 0 && s < node_of_dof[d - 1]) return false;
+        if (first[s] < 0) first[s] = d;
+    }
+    first[n_super] = n;
+    for (int32_t s = n_super - 1; s >= 0; --s)
+        if (first[s] < 0) first[s] = first[s + 1];
+    // supernodes of every element (each once) and the elements of every supernode
+    ElemList es;
+    es.ptr.assign(1, 0);
+    std::vector<int32_t> last(n_super, -1);
+    for (int64_t e = 0; e < el.count(); ++e) {
+        for (int64_t q = el.ptr[e]; q < el.ptr[e + 1]; ++q) {
+            const int32_t s = node_of_dof[el.dofs[q]];
+            if (last[s] != (int32_t)e) {
+                last[s] = (int32_t)e;
+                es.dofs.push_back(s);
+            }
+        }
+        es.ptr.push_back((int64_t)es.dofs.size());
+    }
+    Csr s2e = transpose(n_super, es.ptr, es.dofs);
+    // supernode neighbourhoods, sorted
+    Csr nb;
+    nb.ptr.assign(n_super + 1, 0);
+    std::vector<int32_t> mark(n_super, -1);
+    for (int32_t s = 0; s < n_super; ++s) {
+        const size_t start = nb.idx.size();
+        for (int64_t q = s2e.ptr[s]; q < s2e.ptr[s + 1]; ++q) {
+            const int32_t e = s2e.idx[q];
+            for (int64_t r = es.ptr[e]; r < es.ptr[e + 1]; ++r) {
+                const int32_t t = es.dofs[r];
+                if (mark[t] != s) {
+                    mark[t] = s;
+                    nb.idx.push_back(t);
+                }
+            }
+        }
+        std::sort(nb.idx.begin() + start, nb.idx.end());
+        nb.ptr[s + 1] = (int64_t)nb.idx.size();
+    }
+    // expand: every DOF of s gets the DOF ranges of its neighbours, ascending
+    std::vector<int64_t> rowlen(n_super, 0);
+    for (int32_t s = 0; s < n_super; ++s)
+        for (int64_t q = nb.ptr[s]; q < nb.ptr[s + 1]; ++q) rowlen[s] += first[nb.idx[q] + 1] - first[nb.idx[q]];
+    p.ptr.assign(n + 1, 0);
+    for (int64_t d = 0; d < n; ++d) p.ptr[d + 1] = p.ptr[d] + rowlen[node_of_dof[d]];
+    p.idx.resize(p.ptr[n]);
+    for (int64_t d = 0; d < n; ++d) {
+        const int32_t s = node_of_dof[d];
+        int64_t o = p.ptr[d];
+        for (int64_t q = nb.ptr[s]; q < nb.ptr[s + 1]; ++q)
+            for (int64_t c = first[nb.idx[q]]; c < first[nb.idx[q] + 1]; ++c) p.idx[o++] = (int32_t)c;
+    }
+    return true;
+}
+
 CoarseGroups group_coarse(const ElemList& el, const std::vector<int32_t>& agg_of_dof,
                           const std::vector<int32_t>& k, const std::vector<int64_t>& coarse_off) {
     CoarseGroups cg;

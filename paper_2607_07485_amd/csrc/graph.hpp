@@ -58,6 +58,14 @@ std::vector<int32_t> color_subdomains(int64_t n, const Closure& c, const ElemLis
 // Structural CSR pattern of sum_e R_e^T 1 R_e (sorted columns).
 Csr assembled_pattern(int64_t n, const ElemList& el);
 
+// The same pattern when the DOFs of every supernode form a contiguous range
+// (node_of_dof non-decreasing) and every element holds whole supernodes, as on
+// the coarse levels: computed on supernodes and expanded by ranges (rows of one
+// supernode share their columns).  Returns false (p untouched) if node_of_dof
+// is not non-decreasing.
+bool assembled_pattern_blocked(int64_t n, const ElemList& el, const std::vector<int32_t>& node_of_dof,
+                               int32_t n_super, Csr& p);
+
 // Coarse element rows: elements touching the same set of aggregates with k > 0
 // share their coarse support and multiplicity; they are grouped into one coarse
 // element whose block is the sum of theirs.

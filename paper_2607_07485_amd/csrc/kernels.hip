@@ -167,6 +167,33 @@ __global__ void k_assemble_rows(int64_t n, const int64_t* d2e_ptr, const int32_t
     }
 }
 
+// The same with one wave per row (for long element rows): lanes take the
+// columns of an element, elements in the same order, so every entry receives
+// its contributions in the same order as above.
+__global__ void __launch_bounds__(WG) k_assemble_rows_wave(int64_t n, const int64_t* d2e_ptr,
+                                                           const int32_t* d2e_elem, const int32_t* d2e_loc,
+                                                           const int64_t* elem_ptr, const int32_t* elem_dofs,
+                                                           const int64_t* blk_off, const double* blocks,
+                                                           const double* factor, const int64_t* rowptr,
+                                                           const int32_t* col, double* val) {
+    const int lane = tid() & 63;
+    const int64_t p = (blockIdx.x * (int64_t)WG + tid()) >> 6;
+    if (p >= n) return;
+    const int64_t lo = rowptr[p], hi = rowptr[p + 1];
+    for (int64_t q = d2e_ptr[p]; q < d2e_ptr[p + 1]; ++q) {
+        const int32_t e = d2e_elem[q];
+        const int a = d2e_loc[q];
+        const int64_t base = elem_ptr[e];
+        const int ne = (int)(elem_ptr[e + 1] - base);
+        const double* B = blocks + blk_off[e] + (int64_t)a * ne;
+        const double f = factor ? factor[e] : 1.0;
+        for (int b = lane; b < ne; b += 64) {
+            const int64_t slot = find_slot(col, lo, hi, elem_dofs[base + b]);
+            val[slot] += f * B[b];
+        }
+    }
+}
+
 // factor[e] = theta[e] / theta0[e] (theta0 NULL: theta[e])
 __global__ void k_theta_factor(int64_t n, const double* theta, const double* theta0, double* factor) {
     for (int64_t e = blockIdx.x * (int64_t)WG + tid(); e < n; e += (int64_t)gridDim.x * WG)
@@ -876,10 +903,14 @@ void launch_elem_eig(int64_t n_elem, const int64_t* elem_ptr, const int64_t* blk
 void launch_assemble_rows(int64_t n, const int64_t* d2e_ptr, const int32_t* d2e_elem, const int32_t* d2e_loc,
                           const int64_t* elem_ptr, const int32_t* elem_dofs, const int64_t* blk_off,
                           const double* blocks, const double* factor, const int64_t* rowptr, const int32_t* col,
-                          double* val, hipStream_t st) {
+                          double* val, hipStream_t st, bool wave_rows) {
     if (n <= 0) return;
-    hipLaunchKernelGGL(k_assemble_rows, dim3(grid_for(n)), dim3(WG), 0, st, n, d2e_ptr, d2e_elem, d2e_loc, elem_ptr,
-                       elem_dofs, blk_off, blocks, factor, rowptr, col, val);
+    if (wave_rows)
+        hipLaunchKernelGGL(k_assemble_rows_wave, dim3(grid_for(n * 64)), dim3(WG), 0, st, n, d2e_ptr, d2e_elem,
+                           d2e_loc, elem_ptr, elem_dofs, blk_off, blocks, factor, rowptr, col, val);
+    else
+        hipLaunchKernelGGL(k_assemble_rows, dim3(grid_for(n)), dim3(WG), 0, st, n, d2e_ptr, d2e_elem, d2e_loc,
+                           elem_ptr, elem_dofs, blk_off, blocks, factor, rowptr, col, val);
 }
 
 void launch_theta_factor(int64_t n, const double* theta, const double* theta0, double* factor, hipStream_t st) {

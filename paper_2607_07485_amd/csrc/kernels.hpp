@@ -78,11 +78,12 @@ void launch_elem_eig(int64_t n_elem, const int64_t* elem_ptr, const int64_t* blk
                      double rank_rtol, double spsd_tol, hipStream_t st);
 
 // CSR values += sum_T f_T R_T^T A_T R_T (f = factor, NULL = 1); d2e lists the
-// (element, local index) pairs of every DOF, elements ascending
+// (element, local index) pairs of every DOF, elements ascending; wave_rows: one
+// wave per row (long element rows of coarse levels), same summation order
 void launch_assemble_rows(int64_t n, const int64_t* d2e_ptr, const int32_t* d2e_elem, const int32_t* d2e_loc,
                           const int64_t* elem_ptr, const int32_t* elem_dofs, const int64_t* blk_off,
                           const double* blocks, const double* factor, const int64_t* rowptr, const int32_t* col,
-                          double* val, hipStream_t st);
+                          double* val, hipStream_t st, bool wave_rows = false);
 // factor[e] = theta[e] / theta0[e] (theta0 NULL: theta[e])
 void launch_theta_factor(int64_t n, const double* theta, const double* theta0, double* factor, hipStream_t st);
 // blocks of element e *= scale[e]

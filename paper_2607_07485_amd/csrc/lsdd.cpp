@@ -357,7 +357,10 @@ void refresh_sweep_rows(Level& lv, hipStream_t st) {
 }
 
 void assemble_operator(lsdd_hierarchy* h, Level& lv) {
-    lv.pat = assembled_pattern(lv.n, lv.el);
+    // coarse levels: element supports are unions of whole aggregates (contiguous
+    // coarse DOF ranges), so the pattern is built on supernodes
+    if (lv.level == 0 || !assembled_pattern_blocked(lv.n, lv.el, lv.node_of_dof, lv.n_super, lv.pat))
+        lv.pat = assembled_pattern(lv.n, lv.el);
     lv.nnz = (int64_t)lv.pat.idx.size();
     lv.lanes = (lv.nnz > 96 * lv.n) ? 64 : 16;
     lv.lanes_b = (lv.nnz > 40 * lv.n) ? 64 : 32;
@@ -381,8 +384,10 @@ void assemble_operator(lsdd_hierarchy* h, Level& lv) {
         int64_t* d_dptr = h->arena.upload(dptr, h->st);
         int32_t* d_de = h->arena.upload(de, h->st);
         int32_t* d_dl = h->arena.upload(dl, h->st);
+        int64_t max_ne = 0;
+        for (int64_t e = 0; e < lv.el.count(); ++e) max_ne = std::max(max_ne, lv.el.ptr[e + 1] - lv.el.ptr[e]);
         launch_assemble_rows(lv.n, d_dptr, d_de, d_dl, lv.d_elem_ptr, lv.d_elem_dofs, lv.d_blk_off, lv.d_blocks,
-                             nullptr, lv.d_rowptr, lv.d_col, lv.d_val, h->st);
+                             nullptr, lv.d_rowptr, lv.d_col, lv.d_val, h->st, max_ne > 48);
         HIPCHK(hipStreamSynchronize(h->st));
         if (lv.level == 0) {
             lv.d_d2e_ptr = d_dptr;
@@ -548,6 +553,7 @@ std::unique_ptr<Level> coarsen(lsdd_hierarchy* h, Level& lv, const int32_t* agg_
     hipStream_t st = h->st;
     Arena& ar = h->arena;
     const int64_t n = lv.n;
+    const double ta0 = now_s();
     // ---- aggregates
     int32_t n_agg = 0;
     if (agg_given) {
@@ -604,6 +610,7 @@ std::unique_ptr<Level> coarsen(lsdd_hierarchy* h, Level& lv, const int32_t* agg_
     lv.cl = build_closure(n, lv.agg_of_dof, n_agg, lv.el);
     const Closure& C = lv.cl;
     double tc0 = now_s();
+    vlog("level %d: aggregation and closures %.3f s", lv.level, tc0 - ta0);
     for (int32_t i = 0; i < n_agg; ++i)
         if (C.agg_ptr[i + 1] == C.agg_ptr[i]) throw Error(LSDD_E_INVAL, "empty aggregate " + std::to_string(i));
     lv.colors = color_subdomains(n, C, lv.el, &lv.n_colors);
@@ -889,6 +896,7 @@ std::unique_ptr<Level> coarsen(lsdd_hierarchy* h, Level& lv, const int32_t* agg_
         pos = end;
     }
     vlog("level %d: local problems %.3f s", lv.level, now_s() - tl0);
+    const double tp0 = now_s();
     for (int32_t i = 0; i < n_agg; ++i) {
         if (status[i] != 0)
             throw Error(LSDD_E_NUMERIC, "local problem of aggregate " + std::to_string(i) + " failed (" +
@@ -1080,7 +1088,9 @@ std::unique_ptr<Level> coarsen(lsdd_hierarchy* h, Level& lv, const int32_t* agg_
     if (n_empty > 0)
         throw Error(LSDD_E_UNSUPPORTED, "an instance of the batch retains no mode on level " +
                                             std::to_string(lv.level) + " while others do");
+    vlog("level %d: modes, transfers, sweep order and packed inverses %.3f s", lv.level, now_s() - tp0);
     // ---- coarse level: grouped element rows and Galerkin products
+    const double tg00 = now_s();
     CoarseGroups G = group_coarse(lv.el, lv.agg_of_dof, lv.k, lv.coff);
     auto cv = std::make_unique<Level>();
     cv->level = lv.level + 1;
@@ -1223,8 +1233,12 @@ std::unique_ptr<Level> coarsen(lsdd_hierarchy* h, Level& lv, const int32_t* agg_
                               (const void*)pa.pm_zrow, (const void*)pa.pm_k, (const void*)pa.pm_col})
             ar.release(const_cast<void*>(p));
     }
-    vlog("level %d: Galerkin products for %lld coarse elements %.3f s", lv.level, (long long)ng, now_s() - tg0);
+    vlog("level %d: Galerkin products for %lld coarse elements %.3f s (grouping %.3f s)", lv.level, (long long)ng,
+         now_s() - tg0, tg0 - tg00);
+    const double tas = now_s();
     assemble_operator(h, *cv);
+    sync(st);
+    vlog("level %d: coarse operator assembly %.3f s", cv->level, now_s() - tas);
     return cv;
 }
 
@@ -1266,9 +1280,8 @@ struct Cyc {
             launch_csr_resid_sw<T>(t0, nrows, lv.d_sw_sub_dofs, lv.d_sw_rowptr, lv.d_sw_col, sw_val, x, r, out, xz,
                                    lv.lanes, st);
         else
-            launch_csr_resid_rows_b<T>(nrows, lv.d_sw_sub_dofs + t0, lv.d_rowptr, lv.d_col,
-                                       std::is_same<T, double>::value ? (const T*)lv.d_val : (const T*)lv.d_val32, x,
-                                       r, out, xz, lv.lanes_b, st);
+            launch_csr_resid_sw_b<T>(t0, nrows, lv.d_sw_sub_dofs, lv.d_sw_rowptr, lv.d_sw_col, sw_val, x, r, out, xz,
+                                     lv.lanes_b, st);
     }
     static void spmv(Level& lv, const T* val, const T* x, T* y, const T* r_minus, hipStream_t st) {
         if constexpr (NR == 1) launch_csr_spmv<T>(lv.n, lv.d_rowptr, lv.d_col, val, x, y, r_minus, lv.lanes, st);
@@ -1759,8 +1772,11 @@ lsdd_hierarchy* build(ElemList el0, const double* blocks, bool blocks_on_device,
         lv->ranks.assign(ne, 1);
         HIPCHK(hipMemcpyAsync(lv->d_G, gram_rows, lv->blk_off[ne] * sizeof(double), hipMemcpyHostToDevice, h->st));
     }
+    const double tas = now_s();
     assemble_operator(h.get(), *lv);
     HIPCHK(hipGetLastError());
+    sync(h->st);
+    vlog("level 0: operator assembly %.3f s (setup so far %.3f s)", now_s() - tas, now_s() - t0);
     h->L.push_back(std::move(lv));
     while (true) {
         Level& cur = *h->L.back();
@@ -1796,6 +1812,7 @@ lsdd_hierarchy* build(ElemList el0, const double* blocks, bool blocks_on_device,
     alloc_pcg(h.get(), 0);
     sync(h->st);
     h->setup_s = now_s() - t0;
+    vlog("setup %.3f s", h->setup_s);
     h->cycle_prec = P.precision;
     return h.release();
 }
