@@ -39,37 +39,16 @@ __global__ void __launch_bounds__(WG) k_csr_resid_rows_b(int64_t nrows, const in
         const int32_t p = rows[t];
         T s = 0;
         if (!x_zero) {
+            // up to 4 nonzeros per lane in flight (indices, then gathers, then products)
             const int64_t q1 = rowptr[p + 1];
-#pragma unroll 4
-            for (int64_t q = rowptr[p] + slot; q < q1; q += NS) s += val[q] * x[(int64_t)col[q] * NB + k];
-        }
-        for (int off = L / 2; off >= NB; off >>= 1) s += __shfl_xor(s, off, L);
-        if (slot == 0) out[t * NB + k] = r[(int64_t)p * NB + k] - s;
-    }
-}
-
-// The same on the sweep-ordered copy of the overlap rows (row t0 + t of the
-// copy is row rows[t0 + t] of A); each lane keeps up to 4 nonzeros in flight.
-template <typename T, int L>
-__global__ void __launch_bounds__(WG) k_csr_resid_sw_b(int64_t t0, int64_t nrows, const int32_t* rows,
-                                                       const int64_t* sw_rowptr, const int32_t* sw_col,
-                                                       const T* sw_val, const T* x, const T* r, T* out, int x_zero) {
-    constexpr int NS = L / NB;
-    const int lane = tid() & (L - 1), k = lane & (NB - 1), slot = lane / NB;
-    const int64_t stride = (int64_t)gridDim.x * (WG / L);
-    for (int64_t t = ((int64_t)blockIdx.x * WG + tid()) / L; t < nrows; t += stride) {
-        const int64_t tt = t0 + t;
-        T s = 0;
-        if (!x_zero) {
-            const int64_t q1 = sw_rowptr[tt + 1];
-            for (int64_t q0 = sw_rowptr[tt] + slot; q0 < q1; q0 += 4 * NS) {
+            for (int64_t q0 = rowptr[p] + slot; q0 < q1; q0 += 4 * NS) {
                 int32_t c[4];
                 T v[4], xv[4];
 #pragma unroll
                 for (int u = 0; u < 4; ++u) {
                     const int64_t q = q0 + u * NS;
-                    c[u] = q < q1 ? __builtin_nontemporal_load(sw_col + q) : 0;
-                    v[u] = q < q1 ? __builtin_nontemporal_load(sw_val + q) : (T)0;
+                    c[u] = q < q1 ? __builtin_nontemporal_load(col + q) : 0;
+                    v[u] = q < q1 ? __builtin_nontemporal_load(val + q) : (T)0;
                 }
 #pragma unroll
                 for (int u = 0; u < 4; ++u) xv[u] = x[(int64_t)c[u] * NB + k];
@@ -78,7 +57,7 @@ __global__ void __launch_bounds__(WG) k_csr_resid_sw_b(int64_t t0, int64_t nrows
             }
         }
         for (int off = L / 2; off >= NB; off >>= 1) s += __shfl_xor(s, off, L);
-        if (slot == 0) out[t * NB + k] = r[(int64_t)rows[tt] * NB + k] - s;
+        if (slot == 0) out[t * NB + k] = r[(int64_t)p * NB + k] - s;
     }
 }
 
@@ -589,21 +568,6 @@ __global__ void k_pcg_start(int64_t len, const double* b, double* r, double* x) 
 // ====================================================================== launchers
 
 template <typename T>
-void launch_csr_resid_sw_b(int64_t t0, int64_t nrows, const int32_t* rows, const int64_t* sw_rowptr,
-                           const int32_t* sw_col, const T* sw_val, const T* x, const T* r, T* out, bool x_zero,
-                           int lanes, hipStream_t st) {
-    if (nrows <= 0) return;
-    if (lanes >= 64)
-        hipLaunchKernelGGL((k_csr_resid_sw_b<T, 64>), dim3(grid_for(nrows * 64)), dim3(WG), 0, st, t0, nrows, rows,
-                           sw_rowptr, sw_col, sw_val, x, r, out, x_zero ? 1 : 0);
-    else if (lanes >= 32)
-        hipLaunchKernelGGL((k_csr_resid_sw_b<T, 32>), dim3(grid_for(nrows * 32)), dim3(WG), 0, st, t0, nrows, rows,
-                           sw_rowptr, sw_col, sw_val, x, r, out, x_zero ? 1 : 0);
-    else
-        hipLaunchKernelGGL((k_csr_resid_sw_b<T, 16>), dim3(grid_for(nrows * 16)), dim3(WG), 0, st, t0, nrows, rows,
-                           sw_rowptr, sw_col, sw_val, x, r, out, x_zero ? 1 : 0);
-}
-template <typename T>
 void launch_csr_resid_rows_b(int64_t nrows, const int32_t* rows, const int64_t* rowptr, const int32_t* col,
                              const T* val, const T* x, const T* r, T* out, bool x_zero, int lanes, hipStream_t st) {
     if (nrows <= 0) return;
@@ -779,8 +743,6 @@ LSDD_SMALL_INST(float, 1)
 LSDD_SMALL_INST(float, NRB)
 
 #define LSDD_BLK_INST(T)                                                                                            \
-    template void launch_csr_resid_sw_b<T>(int64_t, int64_t, const int32_t*, const int64_t*, const int32_t*,         \
-                                           const T*, const T*, const T*, T*, bool, int, hipStream_t);                 \
     template void launch_csr_resid_rows_b<T>(int64_t, const int32_t*, const int64_t*, const int32_t*, const T*,      \
                                              const T*, const T*, T*, bool, int, hipStream_t);                         \
     template void launch_csr_spmv_b<T>(int64_t, const int64_t*, const int32_t*, const T*, const T*, T*, const T*,    \

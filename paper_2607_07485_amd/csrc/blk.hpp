@@ -12,11 +12,6 @@ constexpr int NRB = 8;   // right-hand sides per block
 
 // ---------------------------------------------------------------- cycle, block vectors
 // lanes per row of the CSR kernels: 16, 32 or 64
-// block residual on the sweep-ordered row copy (see launch_csr_resid_sw)
-template <typename T>
-void launch_csr_resid_sw_b(int64_t t0, int64_t nrows, const int32_t* rows, const int64_t* sw_rowptr,
-                           const int32_t* sw_col, const T* sw_val, const T* x, const T* r, T* out, bool x_zero,
-                           int lanes, hipStream_t st);
 template <typename T>
 void launch_csr_resid_rows_b(int64_t nrows, const int32_t* rows, const int64_t* rowptr, const int32_t* col,
                              const T* val, const T* x, const T* r, T* out, bool x_zero, int lanes, hipStream_t st);

@@ -278,13 +278,21 @@ bool assembled_pattern_blocked(int64_t n, const ElemList& el, const std::vector<
     ElemList es;
     es.ptr.assign(1, 0);
     std::vector<int32_t> last(n_super, -1);
+    std::vector<int64_t> cnt(n_super, 0);
     for (int64_t e = 0; e < el.count(); ++e) {
         for (int64_t q = el.ptr[e]; q < el.ptr[e + 1]; ++q) {
             const int32_t s = node_of_dof[el.dofs[q]];
             if (last[s] != (int32_t)e) {
                 last[s] = (int32_t)e;
+                cnt[s] = 0;
                 es.dofs.push_back(s);
             }
+            ++cnt[s];
+        }
+        // every element must hold whole supernodes (distinct DOFs per element)
+        for (int64_t r = es.ptr.back(); r < (int64_t)es.dofs.size(); ++r) {
+            const int32_t s = es.dofs[r];
+            if (cnt[s] != first[s + 1] - first[s]) return false;
         }
         es.ptr.push_back((int64_t)es.dofs.size());
     }

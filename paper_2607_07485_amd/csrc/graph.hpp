@@ -59,10 +59,10 @@ std::vector<int32_t> color_subdomains(int64_t n, const Closure& c, const ElemLis
 Csr assembled_pattern(int64_t n, const ElemList& el);
 
 // The same pattern when the DOFs of every supernode form a contiguous range
-// (node_of_dof non-decreasing) and every element holds whole supernodes, as on
-// the coarse levels: computed on supernodes and expanded by ranges (rows of one
-// supernode share their columns).  Returns false (p untouched) if node_of_dof
-// is not non-decreasing.
+// (node_of_dof non-decreasing) and every element holds whole supernodes (always
+// on the coarse levels, often on level 0): computed on supernodes and expanded
+// by ranges (rows of one supernode share their columns).  Returns false (p
+// untouched) if either property fails.
 bool assembled_pattern_blocked(int64_t n, const ElemList& el, const std::vector<int32_t>& node_of_dof,
                                int32_t n_super, Csr& p);
 

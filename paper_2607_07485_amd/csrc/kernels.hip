@@ -504,45 +504,17 @@ __global__ void __launch_bounds__(WG) k_csr_resid_rows(int64_t nrows, const int3
         const int32_t p = rows[t];
         T s = 0;
         if (!x_zero) {
-            const int64_t q1 = rowptr[p + 1];
-            int64_t q = rowptr[p] + lane;
-            T s1 = 0;
-            for (; q + L < q1; q += 2 * L) {
-                s += __builtin_nontemporal_load(val + q) * x[__builtin_nontemporal_load(col + q)];
-                s1 += __builtin_nontemporal_load(val + q + L) * x[__builtin_nontemporal_load(col + q + L)];
-            }
-            if (q < q1) s += __builtin_nontemporal_load(val + q) * x[__builtin_nontemporal_load(col + q)];
-            s += s1;
-        }
-        for (int off = L / 2; off > 0; off >>= 1) s += __shfl_xor(s, off, L);
-        if (lane == 0) out[t] = r[p] - s;
-    }
-}
-
-// The same residual on rows stored contiguously in sweep order: row t of the
-// copy (sw_rowptr, sw_col, sw_val) is row rows[t0 + t] of A, so the matrix
-// stream of a colour is one contiguous range; rows[] is read only for r.
-template <typename T, int L>
-__global__ void __launch_bounds__(WG) k_csr_resid_sw(int64_t t0, int64_t nrows, const int32_t* rows,
-                                                     const int64_t* sw_rowptr, const int32_t* sw_col,
-                                                     const T* sw_val, const T* x, const T* r, T* out, int x_zero) {
-    const int lane = tid() & (L - 1);
-    const int64_t stride = (int64_t)gridDim.x * (WG / L);
-    for (int64_t t = ((int64_t)blockIdx.x * WG + tid()) / L; t < nrows; t += stride) {
-        const int64_t tt = t0 + t;
-        T s = 0;
-        if (!x_zero) {
             // up to 4 entries per lane in flight: all column indices, then all
             // gathers, then the products (two dependent loads per entry)
-            const int64_t q1 = sw_rowptr[tt + 1];
-            for (int64_t q0 = sw_rowptr[tt] + lane; q0 < q1; q0 += 4 * L) {
+            const int64_t q1 = rowptr[p + 1];
+            for (int64_t q0 = rowptr[p] + lane; q0 < q1; q0 += 4 * L) {
                 int32_t c[4];
                 T v[4], xv[4];
 #pragma unroll
                 for (int u = 0; u < 4; ++u) {
                     const int64_t q = q0 + u * L;
-                    c[u] = q < q1 ? __builtin_nontemporal_load(sw_col + q) : 0;
-                    v[u] = q < q1 ? __builtin_nontemporal_load(sw_val + q) : (T)0;
+                    c[u] = q < q1 ? __builtin_nontemporal_load(col + q) : 0;
+                    v[u] = q < q1 ? __builtin_nontemporal_load(val + q) : (T)0;
                 }
 #pragma unroll
                 for (int u = 0; u < 4; ++u) xv[u] = x[c[u]];
@@ -551,18 +523,7 @@ __global__ void __launch_bounds__(WG) k_csr_resid_sw(int64_t t0, int64_t nrows, 
             }
         }
         for (int off = L / 2; off > 0; off >>= 1) s += __shfl_xor(s, off, L);
-        if (lane == 0) out[t] = r[rows[tt]] - s;
-    }
-}
-
-// sw_val[sw_rowptr[t] ..] = val[rowptr[rows[t]] ..] (one wave per row)
-template <typename T>
-__global__ void __launch_bounds__(WG) k_gather_rows(int64_t nrows, const int32_t* rows, const int64_t* rowptr,
-                                                    const T* val, const int64_t* sw_rowptr, T* sw_val) {
-    const int lane = tid() & 63;
-    for (int64_t t = ((int64_t)blockIdx.x * WG + tid()) / 64; t < nrows; t += (int64_t)gridDim.x * (WG / 64)) {
-        const int64_t src = rowptr[rows[t]], dst = sw_rowptr[t], len = sw_rowptr[t + 1] - dst;
-        for (int64_t q = lane; q < len; q += 64) sw_val[dst + q] = val[src + q];
+        if (lane == 0) out[t] = r[p] - s;
     }
 }
 
@@ -1003,25 +964,6 @@ void launch_csr_resid_rows(int64_t nrows, const int32_t* rows, const int64_t* ro
                            col, val, x, r, out, x_zero ? 1 : 0);
 }
 template <typename T>
-void launch_csr_resid_sw(int64_t t0, int64_t nrows, const int32_t* rows, const int64_t* sw_rowptr,
-                         const int32_t* sw_col, const T* sw_val, const T* x, const T* r, T* out, bool x_zero,
-                         int lanes, hipStream_t st) {
-    if (nrows <= 0) return;
-    if (lanes >= 64)
-        hipLaunchKernelGGL((k_csr_resid_sw<T, 64>), dim3(grid_for(nrows * 64)), dim3(WG), 0, st, t0, nrows, rows,
-                           sw_rowptr, sw_col, sw_val, x, r, out, x_zero ? 1 : 0);
-    else
-        hipLaunchKernelGGL((k_csr_resid_sw<T, 16>), dim3(grid_for(nrows * 16)), dim3(WG), 0, st, t0, nrows, rows,
-                           sw_rowptr, sw_col, sw_val, x, r, out, x_zero ? 1 : 0);
-}
-template <typename T>
-void launch_gather_rows(int64_t nrows, const int32_t* rows, const int64_t* rowptr, const T* val,
-                        const int64_t* sw_rowptr, T* sw_val, hipStream_t st) {
-    if (nrows <= 0) return;
-    hipLaunchKernelGGL(k_gather_rows<T>, dim3(grid_for(nrows * 64)), dim3(WG), 0, st, nrows, rows, rowptr, val,
-                       sw_rowptr, sw_val);
-}
-template <typename T>
 void launch_csr_spmv(int64_t n, const int64_t* rowptr, const int32_t* col, const T* val, const T* x, T* y,
                      const T* r_minus, int lanes, hipStream_t st) {
     if (n <= 0) return;
@@ -1127,10 +1069,6 @@ void launch_check_finite(int64_t n, const double* a, int32_t* flag, hipStream_t 
 }
 
 #define LSDD_INST(T)                                                                                                  \
-    template void launch_csr_resid_sw<T>(int64_t, int64_t, const int32_t*, const int64_t*, const int32_t*, const T*, \
-                                         const T*, const T*, T*, bool, int, hipStream_t);                             \
-    template void launch_gather_rows<T>(int64_t, const int32_t*, const int64_t*, const T*, const int64_t*, T*,       \
-                                        hipStream_t);                                                                \
     template void launch_csr_resid_rows<T>(int64_t, const int32_t*, const int64_t*, const int32_t*, const T*,        \
                                            const T*, const T*, T*, bool, int, hipStream_t);                           \
     template void launch_csr_spmv<T>(int64_t, const int64_t*, const int32_t*, const T*, const T*, T*, const T*, int, \

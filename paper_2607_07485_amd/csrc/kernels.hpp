@@ -139,15 +139,6 @@ void launch_to_f64(int64_t n, const float* a, double* b, hipStream_t st);
 template <typename T>
 void launch_csr_resid_rows(int64_t nrows, const int32_t* rows, const int64_t* rowptr, const int32_t* col,
                            const T* val, const T* x, const T* r, T* out, bool x_zero, int lanes, hipStream_t st);
-// out[t] = r[rows[t0 + t]] - (row t0 + t of the sweep-ordered row copy) . x, t < nrows
-template <typename T>
-void launch_csr_resid_sw(int64_t t0, int64_t nrows, const int32_t* rows, const int64_t* sw_rowptr,
-                         const int32_t* sw_col, const T* sw_val, const T* x, const T* r, T* out, bool x_zero,
-                         int lanes, hipStream_t st);
-// refresh the values of the sweep-ordered row copy from the CSR values
-template <typename T>
-void launch_gather_rows(int64_t nrows, const int32_t* rows, const int64_t* rowptr, const T* val,
-                        const int64_t* sw_rowptr, T* sw_val, hipStream_t st);
 template <typename T>
 void launch_csr_spmv(int64_t n, const int64_t* rowptr, const int32_t* col, const T* val, const T* x, T* y,
                      const T* r_minus, int lanes, hipStream_t st);

@@ -208,12 +208,6 @@ struct Level {
     std::vector<double> color_m2, color_m, color_nnz;   // sums of |Omega|^2, |Omega|, row nnz per colour
     int64_t* d_sw_sub_off = nullptr;
     int32_t* d_sw_sub_dofs = nullptr;
-    // rows of A for the Omega entries in sweep order (contiguous per colour)
-    int64_t* d_sw_rowptr = nullptr;
-    int32_t* d_sw_col = nullptr;
-    double* d_sw_val = nullptr;
-    float* d_sw_val32 = nullptr;
-    int64_t sw_nnz = 0;
     int64_t* d_sw_tp_off = nullptr;   // packed-tile offset of each subdomain (sweep order)
     int32_t* d_items = nullptr;       // (subdomain, tile row), grouped by colour
     int32_t* d_pos_sub = nullptr;     // sweep-order subdomain of every Omega entry
@@ -348,18 +342,10 @@ void upload_elements(lsdd_hierarchy* h, Level& lv) {
     lv.d_blk_off = h->arena.upload(lv.blk_off, h->st);
 }
 
-// values of the sweep-ordered row copy from the current CSR values
-void refresh_sweep_rows(Level& lv, hipStream_t st) {
-    if (!lv.d_sw_val) return;
-    const int64_t nr = (int64_t)lv.sw_sub_off.back();
-    launch_gather_rows<double>(nr, lv.d_sw_sub_dofs, lv.d_rowptr, lv.d_val, lv.d_sw_rowptr, lv.d_sw_val, st);
-    if (lv.d_sw_val32) launch_to_f32(lv.sw_nnz, lv.d_sw_val, lv.d_sw_val32, st);
-}
-
 void assemble_operator(lsdd_hierarchy* h, Level& lv) {
-    // coarse levels: element supports are unions of whole aggregates (contiguous
-    // coarse DOF ranges), so the pattern is built on supernodes
-    if (lv.level == 0 || !assembled_pattern_blocked(lv.n, lv.el, lv.node_of_dof, lv.n_super, lv.pat))
+    // element supports made of whole supernodes with contiguous DOF ranges (the
+    // coarse levels always): the pattern is built on supernodes
+    if (!assembled_pattern_blocked(lv.n, lv.el, lv.node_of_dof, lv.n_super, lv.pat))
         lv.pat = assembled_pattern(lv.n, lv.el);
     lv.nnz = (int64_t)lv.pat.idx.size();
     lv.lanes = (lv.nnz > 96 * lv.n) ? 64 : 16;
@@ -1021,21 +1007,6 @@ std::unique_ptr<Level> coarsen(lsdd_hierarchy* h, Level& lv, const int32_t* agg_
              lv.color_sub0[c + 1] - lv.color_smid[c], lv.color_pk[c] * 8e-6);
     lv.d_sw_sub_off = ar.upload(lv.sw_sub_off, st);
     lv.d_sw_sub_dofs = ar.upload(sw_dofs, st);
-    {
-        std::vector<int64_t> rp(sw_dofs.size() + 1, 0);
-        for (size_t t = 0; t < sw_dofs.size(); ++t)
-            rp[t + 1] = rp[t] + (lv.pat.ptr[sw_dofs[t] + 1] - lv.pat.ptr[sw_dofs[t]]);
-        std::vector<int32_t> cl(rp.back());
-        for (size_t t = 0; t < sw_dofs.size(); ++t)
-            std::copy(lv.pat.idx.begin() + lv.pat.ptr[sw_dofs[t]], lv.pat.idx.begin() + lv.pat.ptr[sw_dofs[t] + 1],
-                      cl.begin() + rp[t]);
-        lv.sw_nnz = rp.back();
-        lv.d_sw_rowptr = ar.upload(rp, st);
-        lv.d_sw_col = ar.upload(cl, st);
-        lv.d_sw_val = ar.alloc<double>(std::max<int64_t>(lv.sw_nnz, 1));
-        if (P.precision == 1) lv.d_sw_val32 = ar.alloc<float>(std::max<int64_t>(lv.sw_nnz, 1));
-        refresh_sweep_rows(lv, st);
-    }
     lv.d_sw_tp_off = ar.upload(sw_tp_off, st);
     lv.d_items = ar.upload(items, st);
     {
@@ -1250,7 +1221,6 @@ template <>
 struct LvOps<double> {
     static VecSet<double>& v(Level& l, int b) { return l.v64[b]; }
     static const double* val(Level& l) { return l.d_val; }
-    static const double* sw_val(Level& l) { return l.d_sw_val; }
     static const double* Z(Level& l) { return l.d_Zc; }
     static const double* inv(Level& l) { return l.d_tiles; }
     static const double* pk(Level& l) { return l.d_pk; }
@@ -1259,7 +1229,6 @@ template <>
 struct LvOps<float> {
     static VecSet<float>& v(Level& l, int b) { return l.v32[b]; }
     static const float* val(Level& l) { return l.d_val32; }
-    static const float* sw_val(Level& l) { return l.d_sw_val32; }
     static const float* Z(Level& l) { return l.d_Zc32; }
     static const float* inv(Level& l) { return l.d_tiles32; }
     static const float* pk(Level& l) { return l.d_pk32; }
@@ -1272,16 +1241,6 @@ struct Cyc {
                            bool xz, hipStream_t st) {
         if constexpr (NR == 1) launch_csr_resid_rows<T>(nrows, rows, lv.d_rowptr, lv.d_col, val, x, r, out, xz, lv.lanes, st);
         else launch_csr_resid_rows_b<T>(nrows, rows, lv.d_rowptr, lv.d_col, val, x, r, out, xz, lv.lanes_b, st);
-    }
-    // residual on the Omega rows of entries [t0, t0 + nrows) of the sweep order
-    static void resid_sw(int64_t t0, int64_t nrows, Level& lv, const T* sw_val, const T* x, const T* r, T* out,
-                         bool xz, hipStream_t st) {
-        if constexpr (NR == 1)
-            launch_csr_resid_sw<T>(t0, nrows, lv.d_sw_sub_dofs, lv.d_sw_rowptr, lv.d_sw_col, sw_val, x, r, out, xz,
-                                   lv.lanes, st);
-        else
-            launch_csr_resid_sw_b<T>(t0, nrows, lv.d_sw_sub_dofs, lv.d_sw_rowptr, lv.d_sw_col, sw_val, x, r, out, xz,
-                                     lv.lanes_b, st);
     }
     static void spmv(Level& lv, const T* val, const T* x, T* y, const T* r_minus, hipStream_t st) {
         if constexpr (NR == 1) launch_csr_spmv<T>(lv.n, lv.d_rowptr, lv.d_col, val, x, y, r_minus, lv.lanes, st);
@@ -1337,7 +1296,7 @@ void sweep(lsdd_hierarchy* h, Level& lv, const T* r, T* x, bool forward, bool x_
         const bool xz = x_zero_first && cc == 0;
         const double rb = lv.color_m[c] * (4 + 8 + 3 * wv) + (xz ? 0.0 : lv.color_nnz[c] * (4 + w));
         traced(h, "csr_resid_rows", rb, [&] {
-            C::resid_sw(r0, r1 - r0, lv, O::sw_val(lv), x, r, v.rloc + r0 * NR, xz, h->st);
+            C::resid_rows(r1 - r0, lv.d_sw_sub_dofs + r0, lv, O::val(lv), x, r, v.rloc + r0 * NR, xz, h->st);
         });
         if (i1 > i0) {
             const double gb = lv.color_m2[c] * w + (double)(rm - r0) * (4 + 3 * wv);
@@ -1647,8 +1606,8 @@ void autotune_levels(lsdd_hierarchy* h) {
             lanes = L;
             const double ms = time_ms(h, [&] {
                 for (int32_t c = 0; c < lv.n_colors; ++c)
-                    C::resid_sw(lv.color_row0[c], lv.color_row0[c + 1] - lv.color_row0[c], lv, O::sw_val(lv), v.x,
-                                v.r, v.rloc + lv.color_row0[c] * NR, false, h->st);
+                    C::resid_rows(lv.color_row0[c + 1] - lv.color_row0[c], lv.d_sw_sub_dofs + lv.color_row0[c], lv,
+                                  O::val(lv), v.x, v.r, v.rloc + lv.color_row0[c] * NR, false, h->st);
             });
             vlog("autotune level %d: CSR lanes %d: %.3f ms", lv.level, L, ms);
             if (ms < best) best = ms, pick = L;
@@ -1941,7 +1900,6 @@ lsdd_status lsdd_update_theta(lsdd_hierarchy* h, const double* theta, void* hip_
     launch_assemble_rows(l0.n, l0.d_d2e_ptr, l0.d_d2e_elem, l0.d_d2e_loc, l0.d_elem_ptr, l0.d_elem_dofs, l0.d_blk_off,
                          l0.d_blocks, h->d_factor, l0.d_rowptr, l0.d_col, l0.d_val, h->st);
     if (l0.d_val32) launch_to_f32(l0.nnz, l0.d_val, l0.d_val32, h->st);
-    refresh_sweep_rows(l0, h->st);
     HIPCHK(hipGetLastError());
     sync(h->st);
     return LSDD_OK;
