@@ -22,6 +22,7 @@ namespace lsdd {
 namespace {
 
 constexpr int TB = 64;       // tile edge of the blocked algorithms
+constexpr int OB = 4;        // tiles per panel of the delayed trailing updates (K = 256)
 constexpr int TT = 32;       // tile edge of the transpose
 constexpr int NT = 256;
 
@@ -147,20 +148,25 @@ __global__ void __launch_bounds__(NT) k_potrf_panel(double* base, const View* vi
     }
 }
 
-// A_ib,jb -= L_ib,kb L_jb,kb^T for kb < jb <= ib (lower tiles), matrix cores
-__global__ void __launch_bounds__(NT) k_potrf_update(double* base, const View* views, int kb) {
+// A_ib,jb -= sum over column tiles k in [kt0, kt1) of L_ib,k L_jb,k^T, for the
+// lower tiles jb in [jt0, jt1), ib >= jb (matrix cores; K up to OB tiles)
+__global__ void __launch_bounds__(NT) k_potrf_update(double* base, const View* views, int kt0, int kt1, int jt0,
+                                                     int jt1) {
     __shared__ mg::Smem sm;
     const View v = views[blockIdx.y];
     const int n = v.rows;
     const int nt = ntiles(n);
-    const int m = nt - kb - 1;
-    int t = (int)blockIdx.x;
-    if (m <= 0 || t >= m * (m + 1) / 2) return;
-    int jj = 0;
-    while (t >= m - jj) { t -= m - jj; ++jj; }
-    const int jb = kb + 1 + jj, ib = jb + t;
-    const int K = min(TB, n - kb * TB);
-    const double* pan = base + v.off + (int64_t)(kb * TB) * v.ld;     // column block kb
+    const int K = min(kt1 * TB, n) - kt0 * TB;
+    if (K <= 0) return;
+    int t = (int)blockIdx.x, jb = jt0;
+    const int jend = min(jt1, nt);
+    while (jb < jend && t >= nt - jb) {
+        t -= nt - jb;
+        ++jb;
+    }
+    if (jb >= jend) return;
+    const int ib = jb + t;
+    const double* pan = base + v.off + (int64_t)(kt0 * TB) * v.ld;    // column tiles kt0 ..
     mg::d4 acc[2][2];
     mg::zero(acc);
     mg::tile_mma<mg::IMAJ, mg::IMAJ>(sm, pan, v.ld, ib * TB, n, pan, v.ld, jb * TB, n, 0, K, acc);
@@ -212,31 +218,44 @@ __global__ void __launch_bounds__(NT) k_trsm_diag(const double* lbase, const Vie
     }
 }
 
-// forward B_ib -= L_ib,kb X_kb (ib > kb); backward B_ib -= L_kb,ib^T X_kb (ib < kb)
+// forward: B_ib -= sum_{k in [kt0, kt1)} L_ib,k X_k for the row tiles ib in
+// [it0, it1) (lower_b: column tiles jc < kt1 only); backward (step s, kb =
+// nt-1-s, it0/it1/kt0/kt1 unused): B_ib -= L_kb,ib^T X_kb for ib < kb
 __global__ void __launch_bounds__(NT) k_trsm_update(const double* lbase, const View* lv, double* bbase, const View* bv,
-                                                    int s, int trans, int lower_b) {
+                                                    int kt0, int kt1, int it0, int it1, int s, int trans,
+                                                    int lower_b) {
     __shared__ mg::Smem sm;
     const View l = lv[blockIdx.y], b = bv[blockIdx.y];
     const int n = l.rows;
     const int nt = ntiles(n);
-    if (s >= nt) return;
-    const int kb = trans ? nt - 1 - s : s;
     int nct = ntiles(b.cols);
-    if (lower_b) nct = min(nct, kb + 1);
-    const int nrow = trans ? kb : nt - kb - 1;
+    int row0, nrow, k0, K;
+    if (!trans) {
+        k0 = kt0;
+        K = min(kt1 * TB, n) - kt0 * TB;
+        row0 = it0;
+        nrow = min(it1, nt) - it0;
+        if (lower_b) nct = min(nct, kt1);
+    } else {
+        if (s >= nt) return;
+        k0 = nt - 1 - s;
+        K = min(TB, n - k0 * TB);
+        row0 = 0;
+        nrow = k0;
+    }
+    if (K <= 0 || nrow <= 0) return;
     const int job = (int)blockIdx.x;
     if (job >= nrow * nct) return;
-    const int ib = trans ? job % nrow : kb + 1 + job % nrow;
+    const int ib = row0 + job % nrow;
     const int jc = job / nrow;
-    const int K = min(TB, n - kb * TB);
-    const double* xk = bbase + b.off + kb * TB;                       // X_kb: element (k, j) at xk[k + j ld]
+    const double* xk = bbase + b.off + k0 * TB;                       // X_k0..: element (k, j) at xk[k + j ld]
     mg::d4 acc[2][2];
     mg::zero(acc);
     if (!trans) {
-        const double* lp = lbase + l.off + (int64_t)(kb * TB) * l.ld;  // L[:, kb]: (k, i) at lp[i + k ld]
+        const double* lp = lbase + l.off + (int64_t)(k0 * TB) * l.ld;  // L[:, k0..]: (k, i) at lp[i + k ld]
         mg::tile_mma<mg::IMAJ, mg::KMAJ>(sm, lp, l.ld, ib * TB, n, xk, b.ld, jc * TB, b.cols, 0, K, acc);
     } else {
-        const double* lp = lbase + l.off + kb * TB;                    // L[kb, :]: (k, i) at lp[k + i ld]
+        const double* lp = lbase + l.off + k0 * TB;                    // L[kb, :]: (k, i) at lp[k + i ld]
         mg::tile_mma<mg::KMAJ, mg::KMAJ>(sm, lp, l.ld, ib * TB, n, xk, b.ld, jc * TB, b.cols, 0, K, acc);
     }
 #pragma unroll
@@ -359,12 +378,26 @@ void Batched::potrf(double* base, const std::vector<View>& a, double* d_minpiv) 
     View* dv = put(0, a);
     const unsigned nm = (unsigned)a.size();
     const int nt = max_tiles(a, true);
-    for (int kb = 0; kb < nt; ++kb) {
-        hipLaunchKernelGGL(k_potrf_diag, dim3(1, nm), dim3(NT), 0, st, base, dv, kb, d_minpiv);
-        const int below = nt - kb - 1;
-        if (below > 0) {
+    // right-looking over panels of OB tile columns: inside a panel the updates
+    // reach the panel's own columns (K = one tile), the rest of the trailing
+    // matrix is updated once per panel with K = OB tiles
+    for (int p0 = 0; p0 < nt; p0 += OB) {
+        const int p1 = std::min(p0 + OB, nt);
+        for (int kb = p0; kb < p1; ++kb) {
+            hipLaunchKernelGGL(k_potrf_diag, dim3(1, nm), dim3(NT), 0, st, base, dv, kb, d_minpiv);
+            const int below = nt - kb - 1;
+            if (below <= 0) continue;
             hipLaunchKernelGGL(k_potrf_panel, dim3(below, nm), dim3(NT), 0, st, base, dv, kb);
-            hipLaunchKernelGGL(k_potrf_update, dim3(below * (below + 1) / 2, nm), dim3(NT), 0, st, base, dv, kb);
+            int64_t jobs = 0;
+            for (int jb = kb + 1; jb < p1; ++jb) jobs += nt - jb;
+            if (jobs > 0)
+                hipLaunchKernelGGL(k_potrf_update, dim3((unsigned)jobs, nm), dim3(NT), 0, st, base, dv, kb, kb + 1,
+                                   kb + 1, p1);
+        }
+        if (p1 < nt) {
+            const int64_t m = nt - p1;
+            hipLaunchKernelGGL(k_potrf_update, dim3((unsigned)(m * (m + 1) / 2), nm), dim3(NT), 0, st, base, dv, p0,
+                               p1, p1, nt);
         }
     }
     chk(hipGetLastError(), "batched potrf");
@@ -380,15 +413,36 @@ void Batched::trsm(const double* lbase, const std::vector<View>& l, double* bbas
     const int nt = max_tiles(l, true);
     const int nct = max_tiles(b, false);
     if (nct == 0) return;
-    for (int s = 0; s < nt; ++s) {
-        hipLaunchKernelGGL(k_trsm_diag, dim3(nct, nm), dim3(NT), 0, st, lbase, d1, bbase, d2, s, trans ? 1 : 0,
-                           lower_b ? 1 : 0);
-        const int rows = trans ? nt - 1 - s : nt - 1 - s;     // most tiles any view updates at this step
-        const int cols = lower_b ? std::min(nct, s + 1) : nct;
-        const int jobs = rows * cols;
-        if (jobs > 0)
-            hipLaunchKernelGGL(k_trsm_update, dim3(jobs, nm), dim3(NT), 0, st, lbase, d1, bbase, d2, s,
-                               trans ? 1 : 0, lower_b ? 1 : 0);
+    if (trans) {
+        // backward solves (few right-hand sides here): one tile step at a time
+        for (int s = 0; s < nt; ++s) {
+            hipLaunchKernelGGL(k_trsm_diag, dim3(nct, nm), dim3(NT), 0, st, lbase, d1, bbase, d2, s, 1, 0);
+            const int jobs = (nt - 1 - s) * nct;
+            if (jobs > 0)
+                hipLaunchKernelGGL(k_trsm_update, dim3(jobs, nm), dim3(NT), 0, st, lbase, d1, bbase, d2, 0, 0, 0, 0,
+                                   s, 1, 0);
+        }
+    } else {
+        // forward over panels of OB tile rows: updates inside the panel with K =
+        // one tile, the rows below once per panel with K = OB tiles
+        for (int p0 = 0; p0 < nt; p0 += OB) {
+            const int p1 = std::min(p0 + OB, nt);
+            for (int kb = p0; kb < p1; ++kb) {
+                hipLaunchKernelGGL(k_trsm_diag, dim3(nct, nm), dim3(NT), 0, st, lbase, d1, bbase, d2, kb, 0,
+                                   lower_b ? 1 : 0);
+                const int cols = lower_b ? std::min(nct, kb + 1) : nct;
+                const int jobs = (p1 - kb - 1) * cols;
+                if (jobs > 0)
+                    hipLaunchKernelGGL(k_trsm_update, dim3(jobs, nm), dim3(NT), 0, st, lbase, d1, bbase, d2, kb,
+                                       kb + 1, kb + 1, p1, 0, 0, lower_b ? 1 : 0);
+            }
+            if (p1 < nt) {
+                const int cols = lower_b ? std::min(nct, p1) : nct;
+                const int64_t jobs = (int64_t)(nt - p1) * cols;
+                hipLaunchKernelGGL(k_trsm_update, dim3((unsigned)jobs, nm), dim3(NT), 0, st, lbase, d1, bbase, d2, p0,
+                                   p1, p1, nt, 0, 0, lower_b ? 1 : 0);
+            }
+        }
     }
     chk(hipGetLastError(), "batched trsm");
 }
