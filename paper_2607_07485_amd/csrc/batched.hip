@@ -27,6 +27,10 @@ constexpr int TT = 32;       // tile edge of the transpose
 constexpr int NT = 256;
 
 __device__ inline int t_id() { return (int)threadIdx.x; }
+__device__ inline double wave_min(double v) {
+    for (int off = 32; off > 0; off >>= 1) v = fmin(v, __shfl_xor(v, off, 64));
+    return v;
+}
 __device__ inline int ntiles(int n) { return (n + TB - 1) / TB; }
 
 // 64 x 64 tile (rows r0.., cols c0..) into LDS, zero outside the view; if
@@ -82,41 +86,50 @@ __device__ inline void bwd_subst(const double (*L)[TB + 1], double (&x)[16], int
 
 // ---------------------------------------------------------------- Cholesky
 
-// unblocked Cholesky of diagonal tile kb (LDS); minpiv[view] tracks the
-// smallest pivot (a non-positive or NaN pivot is replaced by 1 so the
-// factorisation runs to the end; the caller reads minpiv)
-__global__ void __launch_bounds__(NT) k_potrf_diag(double* base, const View* views, int kb, double* minpiv) {
-    __shared__ double t[TB][TB + 1];
-    __shared__ double s_min;
+// unblocked Cholesky of diagonal tile kb by one wave: lane i holds row i of the
+// tile in registers; at column j the pivot is broadcast by a lane shuffle and
+// the new column L[:, j] through LDS.  minpiv[view] tracks the smallest pivot
+// (a non-positive or NaN pivot is replaced by 1 so the factorisation runs to
+// the end; the caller reads minpiv)
+__global__ void __launch_bounds__(64) k_potrf_diag(double* base, const View* views, int kb, double* minpiv) {
+    __shared__ double col[TB];
     const View v = views[blockIdx.y];
     const int n = v.rows;
     if (kb * TB >= n) return;
     const int r0 = kb * TB, nb = min(TB, n - r0);
-    ld_tile64(t, base, v, r0, r0);
-    if (t_id() == 0) s_min = (kb == 0) ? INFINITY : minpiv[blockIdx.y];
-    __syncthreads();
-    for (int j = 0; j < nb; ++j) {
-        if (t_id() == 0) {
-            double d = t[j][j];
-            s_min = fmin(s_min, (d == d) ? d : -1.0);
-            t[j][j] = d > 0.0 ? sqrt(d) : 1.0;
+    const int i = t_id();
+    double x[TB];
+#pragma unroll
+    for (int k = 0; k < TB; ++k)
+        x[k] = (i < nb && k <= i) ? base[v.off + (r0 + i) + (int64_t)(r0 + k) * v.ld] : (k == i ? 1.0 : 0.0);
+    double dmin = INFINITY;
+#pragma unroll
+    for (int j = 0; j < TB; ++j) {
+        if (j < nb) {
+            double dj = 1.0;
+            if (i == j) {
+                const double d = x[j];
+                dmin = (d == d) ? d : -1.0;
+                dj = d > 0.0 ? sqrt(d) : 1.0;
+                x[j] = dj;
+            }
+            dj = __shfl(dj, j, 64);
+            if (i > j) x[j] /= dj;
+            col[i] = i > j ? x[j] : 0.0;
+            __builtin_amdgcn_wave_barrier();
+#pragma unroll
+            for (int k = j + 1; k < TB; ++k)
+                if (i >= k) x[k] -= x[j] * col[k];
+            __builtin_amdgcn_wave_barrier();
         }
-        __syncthreads();
-        const double s = t[j][j];
-        for (int i = j + 1 + t_id(); i < nb; i += NT) t[i][j] /= s;
-        __syncthreads();
-        const int m = nb - j - 1;
-        for (int idx = t_id(); idx < m * m; idx += NT) {
-            int i = j + 1 + idx % m, k = j + 1 + idx / m;
-            if (i >= k) t[i][k] -= t[i][j] * t[k][j];
-        }
-        __syncthreads();
     }
-    for (int idx = t_id(); idx < nb * nb; idx += NT) {
-        int i = idx % nb, j = idx / nb;
-        if (i >= j) base[v.off + (r0 + i) + (int64_t)(r0 + j) * v.ld] = t[i][j];
+    dmin = wave_min(dmin);
+    if (i < nb) {
+#pragma unroll
+        for (int k = 0; k < TB; ++k)
+            if (k <= i) base[v.off + (r0 + i) + (int64_t)(r0 + k) * v.ld] = x[k];
     }
-    if (t_id() == 0) minpiv[blockIdx.y] = s_min;
+    if (i == 0) minpiv[blockIdx.y] = (kb == 0) ? dmin : fmin(minpiv[blockIdx.y], dmin);
 }
 
 // L_ib,kb = A_ib,kb L_kk^{-T}, ib = kb + 1 + blockIdx.x: each row solves
@@ -384,7 +397,7 @@ void Batched::potrf(double* base, const std::vector<View>& a, double* d_minpiv) 
     for (int p0 = 0; p0 < nt; p0 += OB) {
         const int p1 = std::min(p0 + OB, nt);
         for (int kb = p0; kb < p1; ++kb) {
-            hipLaunchKernelGGL(k_potrf_diag, dim3(1, nm), dim3(NT), 0, st, base, dv, kb, d_minpiv);
+            hipLaunchKernelGGL(k_potrf_diag, dim3(1, nm), dim3(64), 0, st, base, dv, kb, d_minpiv);
             const int below = nt - kb - 1;
             if (below <= 0) continue;
             hipLaunchKernelGGL(k_potrf_panel, dim3(below, nm), dim3(NT), 0, st, base, dv, kb);
