@@ -39,10 +39,10 @@ METRIC = "solve DOF/s to 1e-8 rel residual + setup s; FP32-cycle vs FP64, 1 MI35
 HBM_PEAK_GBS = 8000.0
 
 # HBM bytes per launch of the dominant solve kernel, from rocprofv3 FETCH_SIZE and WRITE_SIZE
-# runs of this bench (FP64 cycle, 128 x 128; average over the 22 launches of one solve) scaled by
-# a 1 GiB device-copy calibration (read factor 2.0, write factor 1.0).  Valid only for the kernel
-# source these counters were taken on.
-TRAFFIC = {("sub_symv", "graddiv_rtcf3_128x128", "f64"): ("64882a4d6c4c5b4a", 2.610e8)}
+# runs of this bench (FP64 cycle, 128 x 128; average over the 220 launches of one traced solve)
+# scaled by a 1 GiB device-copy calibration (read factor 2.0, write factor 1.0).  Valid only for
+# the kernel source these counters were taken on.
+TRAFFIC = {("sub_symv", "graddiv_rtcf3_128x128", "f64"): ("9968a8970904d0ba", 2.501e8)}
 
 
 def _kernels_hash():
