@@ -17,8 +17,9 @@
 // Per panel: k_trd_fin (finish the last W column), k_trd_update.
 //
 // Storage per matrix: C (n x n, both triangles kept exactly symmetric), the
-// tridiagonal d, e, tau in the T scratch, V and W (n x TRD_NB each, row-major)
-// and the dots in the v_buf slot (n^2 doubles, n > 2 TRD_NB).
+// tridiagonal d, e, tau in the T scratch, V and W (n x TRD_NB each,
+// column-major, so row sweeps over one column are coalesced) and the dots in
+// the v_buf slot (n^2 doubles, n > 2 TRD_NB).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -69,10 +70,12 @@ __device__ inline Mat mat_of(const LocalArgs& A, int b) {
 // W(:, q) <- w - (tau_jp / 2) (w . v) v for the raw w of reflector jp
 __device__ inline void finish_w(const Mat& m, int jp, int q, double* red) {
     double s = 0.0;
-    for (int i = jp + 1 + tid(); i < m.n; i += WG) s += m.W[(int64_t)i * NB + q] * m.V[(int64_t)i * NB + q];
+    const double* vq = m.V + (int64_t)q * m.n;
+    double* wq = m.W + (int64_t)q * m.n;
+    for (int i = jp + 1 + tid(); i < m.n; i += WG) s += wq[i] * vq[i];
     s = wg_sum(s, red);
     const double K = 0.5 * m.tau[jp] * s;
-    for (int i = jp + 1 + tid(); i < m.n; i += WG) m.W[(int64_t)i * NB + q] -= K * m.V[(int64_t)i * NB + q];
+    for (int i = jp + 1 + tid(); i < m.n; i += WG) wq[i] -= K * vq[i];
     __syncthreads();
 }
 
@@ -87,16 +90,14 @@ __global__ void __launch_bounds__(WG) k_trd_col(LocalArgs A, const int32_t* big,
     if (p > 0) finish_w(m, j - 1, p - 1, red);
     // column j (rows j..n-1) with the panel's earlier reflectors applied
     if (tid() < p) {
-        rowvw[tid()] = m.V[(int64_t)j * NB + tid()];
-        rowvw[NB + tid()] = m.W[(int64_t)j * NB + tid()];
+        rowvw[tid()] = m.V[j + (int64_t)tid() * n];
+        rowvw[NB + tid()] = m.W[j + (int64_t)tid() * n];
     }
     __syncthreads();
     double* col = m.a + (int64_t)j * n;
     for (int i = j + tid(); i < n; i += WG) {
         double s = col[i];
-        const double* vr = m.V + (int64_t)i * NB;
-        const double* wr = m.W + (int64_t)i * NB;
-        for (int q = 0; q < p; ++q) s -= vr[q] * rowvw[NB + q] + wr[q] * rowvw[q];
+        for (int q = 0; q < p; ++q) s -= m.V[i + (int64_t)q * n] * rowvw[NB + q] + m.W[i + (int64_t)q * n] * rowvw[q];
         col[i] = s;
     }
     __syncthreads();
@@ -120,14 +121,15 @@ __global__ void __launch_bounds__(WG) k_trd_col(LocalArgs A, const int32_t* big,
         m.tau[j] = t;
     }
     __syncthreads();
+    double* vp = m.V + (int64_t)p * n;
     for (int i = tid(); i < mm; i += WG) {
         const double vi = (i == 0) ? 1.0 : (s2 > 0.0 ? x[i] * sc : 0.0);
         x[i] = vi;
-        m.V[(int64_t)(j + 1 + i) * NB + p] = vi;
+        vp[j + 1 + i] = vi;
     }
     for (int i = j0 + tid(); i <= j; i += WG) {
-        m.V[(int64_t)i * NB + p] = 0.0;
-        m.W[(int64_t)i * NB + p] = 0.0;
+        vp[i] = 0.0;
+        m.W[i + (int64_t)p * n] = 0.0;
     }
     __syncthreads();
     // zw_q = W(j+1:, q) . v, zv_q = V(j+1:, q) . v for q < p
@@ -138,13 +140,11 @@ __global__ void __launch_bounds__(WG) k_trd_col(LocalArgs A, const int32_t* big,
         for (int u = 0; u < 8; ++u) aw[u] = av[u] = 0.0;
         for (int i = j + 1 + tid(); i < n; i += WG) {
             const double vi = x[i - j - 1];
-            const double* vr = m.V + (int64_t)i * NB + q0;
-            const double* wr = m.W + (int64_t)i * NB + q0;
 #pragma unroll
             for (int u = 0; u < 8; ++u)
                 if (q0 + u < p) {
-                    aw[u] += wr[u] * vi;
-                    av[u] += vr[u] * vi;
+                    aw[u] += m.W[i + (int64_t)(q0 + u) * n] * vi;
+                    av[u] += m.V[i + (int64_t)(q0 + u) * n] * vi;
                 }
         }
 #pragma unroll
@@ -206,10 +206,8 @@ __global__ void __launch_bounds__(WG) k_trd_symv(LocalArgs A, const int32_t* big
         double s = wave_sum((s0 + s1) + (s2 + s3));
         if (l == 0) {
             const int gi = j + 1 + c;
-            const double* vr = m.V + (int64_t)gi * NB;
-            const double* wr = m.W + (int64_t)gi * NB;
-            for (int q = 0; q < p; ++q) s -= vr[q] * zz[q] + wr[q] * zz[NB + q];
-            m.W[(int64_t)gi * NB + p] = t * s;
+            for (int q = 0; q < p; ++q) s -= m.V[gi + (int64_t)q * n] * zz[q] + m.W[gi + (int64_t)q * n] * zz[NB + q];
+            m.W[gi + (int64_t)p * n] = t * s;
         }
     }
 }
@@ -239,12 +237,12 @@ __global__ void __launch_bounds__(WG) k_trd_update(LocalArgs A, const int32_t* b
         ++jt;
     }
     const int it = jt + job;
-    const double* Vr = m.V + (int64_t)r0 * NB;
-    const double* Wr = m.W + (int64_t)r0 * NB;
+    const double* Vr = m.V + r0;                 // (k = reflector, i = row) at Vr[i + k n]
+    const double* Wr = m.W + r0;
     mg::d4 acc[2][2];
     mg::zero(acc);
-    mg::tile_mma<mg::KMAJ, mg::KMAJ>(sm, Vr, NB, it * mg::T, M, Wr, NB, jt * mg::T, M, 0, pc, acc);
-    mg::tile_mma<mg::KMAJ, mg::KMAJ>(sm, Wr, NB, it * mg::T, M, Vr, NB, jt * mg::T, M, 0, pc, acc);
+    mg::tile_mma<mg::IMAJ, mg::IMAJ>(sm, Vr, n, it * mg::T, M, Wr, n, jt * mg::T, M, 0, pc, acc);
+    mg::tile_mma<mg::IMAJ, mg::IMAJ>(sm, Wr, n, it * mg::T, M, Vr, n, jt * mg::T, M, 0, pc, acc);
 #pragma unroll
     for (int p = 0; p < 2; ++p)
 #pragma unroll
