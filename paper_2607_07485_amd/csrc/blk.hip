@@ -39,22 +39,9 @@ __global__ void __launch_bounds__(WG) k_csr_resid_rows_b(int64_t nrows, const in
         const int32_t p = rows[t];
         T s = 0;
         if (!x_zero) {
-            // up to 4 nonzeros per lane in flight (indices, then gathers, then products)
             const int64_t q1 = rowptr[p + 1];
-            for (int64_t q0 = rowptr[p] + slot; q0 < q1; q0 += 4 * NS) {
-                int32_t c[4];
-                T v[4], xv[4];
-#pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    const int64_t q = q0 + u * NS;
-                    c[u] = q < q1 ? __builtin_nontemporal_load(col + q) : 0;
-                    v[u] = q < q1 ? __builtin_nontemporal_load(val + q) : (T)0;
-                }
-#pragma unroll
-                for (int u = 0; u < 4; ++u) xv[u] = x[(int64_t)c[u] * NB + k];
-#pragma unroll
-                for (int u = 0; u < 4; ++u) s += v[u] * xv[u];
-            }
+#pragma unroll 4
+            for (int64_t q = rowptr[p] + slot; q < q1; q += NS) s += val[q] * x[(int64_t)col[q] * NB + k];
         }
         for (int off = L / 2; off >= NB; off >>= 1) s += __shfl_xor(s, off, L);
         if (slot == 0) out[t * NB + k] = r[(int64_t)p * NB + k] - s;
