@@ -11,6 +11,8 @@ mesh sizes, material parameters, element coefficients, right-hand sides):
 * ``elasticity_q2``     Q2 hexes on 24^3, theta_T ~ lognormal(0, 0.5), nu = 0.3.
 * ``hyperdiffusion_h2`` bicubic Hermite (BFS) anisotropic hyperdiffusion on 256x256, D rotated
   30 degrees, anisotropy 1e-4, clamped by Nitsche, 264,196 DOFs.
+* ``closure_comparison`` CG1 triangles, kappa = 1 + x + y, u = 0 by Nitsche, b = 0 and a
+  N(0, 1) initial iterate; N = 32 ... 1024 give 1,089 ... 1,050,625 DOFs.
 """
 from __future__ import annotations
 
@@ -19,6 +21,7 @@ import numpy as np
 from .common import Problem, rhs  # noqa: F401
 from .elasticity import elasticity_q1, elasticity_q2hex  # noqa: F401
 from .hdiv import graddiv_rtcf3  # noqa: F401
+from .p1 import diffusion_p1_triangles  # noqa: F401
 
 
 def elasticity_small(N: int = 32, seed: int = 0, nrhs: int = 1):
@@ -61,3 +64,10 @@ def hyperdiffusion_h2(N: int = 256, seed: int = 0, nrhs: int = 1, eps: float = 1
     rng = np.random.default_rng(seed)
     prob = hyperdiffusion_bfs(N, eps=eps, theta=theta)
     return prob, rhs(prob.n, nrhs, rng)
+
+
+def closure_comparison(N: int = 32, seed: int = 0):
+    """Scalar diffusion on CG1 triangles with zero data and a random start; (problem, b, x0)."""
+    rng = np.random.default_rng(seed)
+    prob = diffusion_p1_triangles(N)
+    return prob, np.zeros(prob.n), rng.standard_normal(prob.n)

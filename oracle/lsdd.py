@@ -35,7 +35,8 @@ supernode graph, R4 pseudo-inverse tolerance |Gamma| eps d_max, R5 the reduced
 problem solved as S~ u = mu A_ww u with mu = 1/lambda, R6 tau_cut uses the
 level-wide maximum multiplicity, R7/R8 cluster completion and threshold band,
 R9 A_ww-orthonormal Z, R11 colour-major sweep order, R12 coarse elements grouped
-by the set of aggregates they touch.
+by the set of aggregates they touch, R14 the local matrix on an A-closure is the
+principal submatrix of the G-row closure's local matrix.
 """
 from __future__ import annotations
 
@@ -71,6 +72,11 @@ class Params:
     # Moore-Penrose form, reading R4) or "cholesky" (reading R13: Cholesky, and when a
     # pivot falls to |Gamma| eps max diag, Cholesky of the block shifted by that amount)
     interface: str = "pinv"
+    # overlaps: "G" = G-row closure (Def. "G-row closure", the method's choice) or
+    # "A" = algebraic A-closure (Def. "algebraic A-closure", the comparison of Sec. 5.3);
+    # with "A" an entry counts as nonzero when |A(p,q)| > closure_tol sqrt(A(p,p) A(q,q))
+    closure: str = "G"
+    closure_tol: float = 1e-12
 
 
 # ----------------------------------------------------------------- element factors (Sec. 5.2)
@@ -256,6 +262,19 @@ def closures(n_agg: int, agg_of_dof: np.ndarray, elem_dofs):
     return aggs, omegas, [np.array(c, dtype=np.int64) for c in cl], mult
 
 
+def a_closure(A: sp.csr_matrix, omega: np.ndarray, tol: float) -> np.ndarray:
+    """Algebraic A-closure (Def. "algebraic A-closure"): omega_i, then the DOFs p
+    outside omega_i whose row block A(p, omega_i) holds an entry with
+    |A(p,q)| > tol sqrt(A(p,p) A(q,q)) (ascending).  A is symmetric, so the rows
+    of omega_i are scanned."""
+    d = A.diagonal()
+    R = A[omega].tocoo()
+    q = omega[R.row]
+    keep = np.abs(R.data) > tol * np.sqrt(np.abs(d[q] * d[R.col]))
+    gamma = np.setdiff1d(np.unique(R.col[keep]), omega)
+    return np.concatenate([omega, gamma]).astype(np.int64)
+
+
 def local_splitting(omega_dofs: np.ndarray, cl_elems, elem_dofs, blocks, mult) -> np.ndarray:
     """A~_Omega = sum_{T in cl} mult(T)^{-1} E_T^T A_T E_T (eq. SPSD_splitting under R1)."""
     pos = {int(d): a for a, d in enumerate(omega_dofs)}
@@ -419,11 +438,27 @@ def coarsen(lev: Level, params: Params, agg_of_dof=None):
     aggs, omegas, cl, mult = closures(n_agg, agg_of_dof, lev.elem_dofs)
     lev.agg_of_dof, lev.aggs, lev.omegas, lev.closure, lev.mult = agg_of_dof, aggs, omegas, cl, mult
     lev.tau_cut = params.tau_const * float(mult.max())
+    if params.closure == "A":
+        # A-closure overlaps (subsets of the G-row closures, since the pattern of A
+        # is the union of the element supports); the local matrix of each is the
+        # principal submatrix of the G-row closure's A~_Omega on them, i.e. the rows
+        # touching omega_i cut down to the A-closure (reading R14)
+        omegas_g = omegas
+        omegas = [a_closure(lev.A, aggs[i], params.closure_tol) for i in range(n_agg)]
+        assert all(np.isin(a, g).all() for a, g in zip(omegas, omegas_g))
+        lev.omegas = omegas
+    elif params.closure != "G":
+        raise ValueError("closure must be 'G' or 'A'")
     lev.mu, lev.Z, ks = [], [], []
     for i in range(n_agg):
         O = omegas[i]
         nw = len(aggs[i])
-        At = local_splitting(O, cl[i], lev.elem_dofs, lev.blocks, mult)
+        if params.closure == "A":
+            At = local_splitting(omegas_g[i], cl[i], lev.elem_dofs, lev.blocks, mult)
+            keep = np.isin(omegas_g[i], O)
+            At = At[np.ix_(keep, keep)]
+        else:
+            At = local_splitting(O, cl[i], lev.elem_dofs, lev.blocks, mult)
         S = schur_pinv(At, nw, params.interface)
         Aww = lev.A[aggs[i]][:, aggs[i]].toarray()
         mu, V, L = local_spectral(S, Aww)

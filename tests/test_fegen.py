@@ -91,3 +91,67 @@ def test_bfs_hyperdiffusion_blocks():
         exact = sum(wa * wb * q(x0 + h * (a + 1) / 2, y0 + h * (b + 1) / 2) ** 2
                     for a, wa in zip(gx, gw) for b, wb in zip(gx, gw)) * h * h / 4
         assert abs(u @ K @ u - exact) <= 1e-10 * abs(exact), name
+
+
+def _assembled(prob):
+    import scipy.sparse as sp
+    ne = np.diff(prob.elem_ptr)
+    rows, cols, vals = [], [], []
+    for e in range(prob.n_elem):
+        d, B = prob.element(e)
+        rows.append(np.repeat(d, len(d)))
+        cols.append(np.tile(d, len(d)))
+        vals.append(B.ravel())
+    assert ne.min() == ne.max() == 3
+    return sp.csr_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
+                         shape=(prob.n, prob.n))
+
+
+def test_p1_triangles_counts_and_five_point_stencil():
+    """With kappa = 1, CG1 on right isosceles triangles is the 5-point Laplacian away
+    from the boundary (4 on the diagonal, -1 to the axis neighbours, exactly 0 to the
+    diagonal neighbour that shares two triangles)."""
+    for N, n in ((32, 1089), (64, 4225)):
+        assert (N + 1) ** 2 == n
+    N = 8
+    prob = fegen.diffusion_p1_triangles(N, kappa=lambda x, y: np.ones_like(np.asarray(x, dtype=float)))
+    assert prob.n == 81 and prob.n_elem == 128
+    _check_blocks(prob)
+    A = _assembled(prob).toarray()
+    nx = N + 1
+    for j in range(2, N - 1):
+        for i in range(2, N - 1):
+            p = j * nx + i
+            assert A[p, p] == pytest.approx(4.0, abs=1e-13)
+            for q in (p - 1, p + 1, p - nx, p + nx):
+                assert A[p, q] == pytest.approx(-1.0, abs=1e-13)
+            assert A[p, p + nx + 1] == 0.0 and A[p, p - nx - 1] == 0.0
+            assert np.count_nonzero(np.abs(A[p]) > 1e-14) == 5
+
+
+def test_p1_nitsche_form_closed_values():
+    """a_h(1, 1) = 24/h int_{bd} kappa ds = 192 N and a_h(x, x) = 96 N - 3 for
+    kappa = 1 + x + y (cell term int kappa = 2, penalty 24/h * 4, and the two
+    consistency terms -2 int_{x=1} kappa = -5); both functions lie in CG1."""
+    for N in (4, 16):
+        prob = fegen.diffusion_p1_triangles(N)
+        A = _assembled(prob)
+        one = np.ones(prob.n)
+        x = np.tile(np.arange(N + 1) / N, N + 1)
+        assert one @ (A @ one) == pytest.approx(192.0 * N, rel=1e-13)
+        assert x @ (A @ x) == pytest.approx(96.0 * N - 3.0, rel=1e-13)
+        _check_blocks(prob)
+
+
+def test_p1_interior_diagonal_entries_cancel_with_variable_kappa():
+    """Each triangle contributes exactly 0 to its hypotenuse pair, so the assembled
+    entry vanishes away from the boundary although two elements hold both DOFs."""
+    N = 16
+    prob = fegen.diffusion_p1_triangles(N)
+    A = _assembled(prob)
+    nx = N + 1
+    zero = [A[j * nx + i, (j + 1) * nx + i + 1] for j in range(1, N - 1) for i in range(1, N - 1)]
+    assert max(abs(z) for z in zero) == 0.0
+    # rows of interior DOFs sum to zero (constants are in the kernel of the cell term)
+    rs = np.asarray(A.sum(axis=1)).ravel().reshape(nx, nx)[2:-2, 2:-2]
+    assert np.abs(rs).max() <= 1e-12
