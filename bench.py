@@ -20,7 +20,11 @@ as setup_s.
 Other workloads (not the default line): --workload batch (64 uneven Q1 elasticity
 instances, 8 right-hand sides each, one batched hierarchy) and --workload q2grad
 (Q2 hexahedral elasticity on 24^3 with per-element coefficients: solve, adjoint
-gradient of the compliance and central differences on 32 elements).
+gradient of the compliance and central differences on 32 elements), --workload h2
+(bicubic Hermite hyperdiffusion on 256 x 256) and --workload closure_table (the
+closure comparison of Sec. 5.3: standalone V-cycles from a random start to a 1e-10
+residual reduction on CG1 triangles, 1,089 ... 1,050,625 DOFs, A-closure against
+G-row closure).
 """
 from __future__ import annotations
 
@@ -220,6 +224,50 @@ def run_h2(a, torch, P, fegen, dev):
     print(json.dumps(out))
 
 
+def run_closure_table(a, torch, P, fegen, dev):
+    """Sec. 5.3 closure comparison: -div((1 + x + y) grad u) = 0 on CG1 triangles of the
+    uniformly refined unit square, u = 0 by Nitsche, standalone V-cycles from a N(0, 1)
+    start until the residual falls by 1e-10; tau_cut = max mult, two aggregation passes,
+    at most 3 levels; A-closure (closure = 1) against G-row closure (closure = 0)."""
+    sizes = [32, 64, 128, 256, 512, 1024]
+    P.Hierarchy.setup_problem(fegen.closure_comparison(8)[0], _params(P, tau_const=1.0)).close()
+    rows = []
+    for N in sizes:
+        prob, b_np, x0_np = fegen.closure_comparison(N)
+        b = torch.from_numpy(b_np).to(dev)
+        for cl in (1, 0):
+            prm = _params(P, tau_const=1.0, closure=cl, rtol=1e-10, max_iter=3000, precision=0)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            h = P.Hierarchy.setup_problem(prob, prm)
+            torch.cuda.synchronize()
+            setup_s = time.perf_counter() - t0
+            info = h.info()
+            x = torch.from_numpy(x0_np).to(dev)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, inf = h.solve_stationary(b, x, allow_noconv=True)
+            torch.cuda.synchronize()
+            solve_s = time.perf_counter() - t0
+            h.close()
+            row = {"n": prob.n, "closure": "A" if cl else "G", "cycles": inf[0].iters,
+                   "converged": bool(inf[0].converged), "rel_res": inf[0].rel_res, "levels": info["n"],
+                   "oc": round(info["oc"], 3), "setup_s": round(setup_s, 3), "solve_s": round(solve_s, 4),
+                   "ms_per_cycle": round(solve_s * 1e3 / max(inf[0].iters, 1), 3)}
+            rows.append(row)
+            print(f"[bench] closure table {row}", file=sys.stderr, flush=True)
+    big = [r for r in rows if r["n"] == max(r2["n"] for r2 in rows) and r["closure"] == "G"][0]
+    out = {"metric": "standalone_cycle_solve_dofs_per_s", "value": big["n"] / big["solve_s"], "unit": "DOF/s",
+           "n_gpus": 1, "steps": 1, "warmup": 1, "ms_per_step": big["solve_s"] * 1e3, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": "closure_comparison_cg1_triangles", "sizes": [(n + 1) ** 2 for n in sizes],
+                      "reduction": 1e-10, "tau_const": 1.0},
+           "table": rows,
+           "paper_cycles": {"A": [10, 12, 13, 28, 72, 158], "G": [10, 10, 11, 11, 11, 11]},
+           "roofline": None, "cpu_baseline": None}
+    print(json.dumps(out))
+
+
 def run_q2grad(a, torch, P, fegen, dev):
     """Q2 hex elasticity on N^3 (default 24^3), theta ~ lognormal(0, 0.5); compliance J = b^T u and its
     gradient through the autograd Function (adjoint solve on the same hierarchy), checked by central
@@ -302,7 +350,7 @@ def main():
     ap.add_argument("--N", type=int, default=128)
     ap.add_argument("--cpu-sample", type=int, default=16)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", choices=["graddiv", "batch", "q2grad", "h2"], default="graddiv")
+    ap.add_argument("--workload", choices=["graddiv", "batch", "q2grad", "h2", "closure_table"], default="graddiv")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a device copy of 1 GiB five times (HBM counter calibration for profiling)")
     a = ap.parse_args()
@@ -336,6 +384,8 @@ def main():
             return run_q2grad(a, torch, P, fegen, dev)
         if a.workload == "h2":
             return run_h2(a, torch, P, fegen, dev)
+        if a.workload == "closure_table":
+            return run_closure_table(a, torch, P, fegen, dev)
         return run_graddiv(a, torch, P, fegen, dev)
 
 

@@ -62,6 +62,13 @@ typedef struct {
     int32_t blocked_eig_min;    /* local spectral problems with |omega| >= this use the blocked
                                    multi-workgroup tridiagonal reduction; 0 = library default
                                    (192), < 0 = never; values below 66 act as 66            */
+    int32_t closure;            /* overlaps: 0 = G-row closure (Def. "G-row closure", default);
+                                   1 = algebraic A-closure (Def. "algebraic A-closure"), the
+                                   comparison of Sec. 5.3: Omega_i = omega_i plus the DOFs p
+                                   with an entry |A(p,q)| > closure_tol sqrt(A(p,p) A(q,q)),
+                                   q in omega_i; the local matrix is the G-row closure's
+                                   A~_Omega cut down to those DOFs                          */
+    int32_t reserved0;          /* ignored                                                    */
     double tau_const;           /* tau_cut = tau_const * max mult; default 0.75               */
     double max_density;         /* nnz(A_l)/n_l^2 above this -> coarsest; default 0.25         */
     double rtol;                /* PCG stop: ||r||_2 <= rtol ||b||_2; default 1e-8              */
@@ -69,6 +76,8 @@ typedef struct {
     double band_tol;            /* mu within band_tol above 1/tau_cut is retained; 1e-9        */
     double rank_rtol;           /* element rank tolerance / lambda_max; 0 = n_T * eps          */
     double spsd_tol;            /* lambda_min < -spsd_tol lambda_max -> LSDD_E_NOT_SPSD; 1e-12 */
+    double closure_tol;         /* relative size below which an entry of A counts as zero for
+                                   the A-closure; default 1e-12                               */
 } lsdd_params;
 
 /* Per-solve report (one per right-hand side). */
@@ -186,6 +195,25 @@ lsdd_status lsdd_setup_gram_csr(int64_t m, int64_t n, const int64_t* rowptr, con
  * NaN/Inf in b -> LSDD_E_INVAL.  LSDD_E_NOCONV leaves the last iterates in x. */
 lsdd_status lsdd_solve(lsdd_hierarchy* h, const double* b, double* x, int32_t nrhs,
                        void* hip_stream, lsdd_info* info);
+
+/* Standalone V-cycle iteration, the solver mode of the paper's experiments (Sec. 6):
+ * x_{k+1} = x_k + V(b - A x_k), where V is one symmetric V-cycle (forward
+ * multiplicative Schwarz pre-smoothing, coarse correction, reverse-order
+ * post-smoothing), until ||b - A x_k||_2 <= rtol ||b - A x_0||_2 (rtol and the
+ * iteration cap max_iter from the parameters or lsdd_set_solve_params; the
+ * paper uses rtol = 1e-10).  Runs in the hierarchy's cycle precision.
+ *   b      device, float64[nrhs * n] (b = 0 is allowed: the iteration then
+ *          drives x_0 to zero, as in the closure comparison of Sec. 5.3)
+ *   x      device, float64[nrhs * n]: the initial iterates x_0 on entry (NOT
+ *          zeroed), the last iterates on return
+ *   info   host, lsdd_info[nrhs] or NULL: iters = cycles applied, rel_res =
+ *          ||b - A x||_2 / ||b - A x_0||_2 (0 and converged when r_0 = 0)
+ * Only hierarchies with one segment (not lsdd_setup_batched) -> else
+ * LSDD_E_UNSUPPORTED; NaN/Inf in b or x_0 -> LSDD_E_INVAL; the cap reached ->
+ * LSDD_E_NOCONV with the last iterates in x; a non-finite residual ->
+ * LSDD_E_BREAKDOWN. */
+lsdd_status lsdd_solve_stationary(lsdd_hierarchy* h, const double* b, double* x, int32_t nrhs,
+                                  void* hip_stream, lsdd_info* info);
 
 /* Switch the cycle precision of an existing hierarchy: 0 = FP64 cycle,
  * 1 = FP32 cycle (the hierarchy must have been set up with precision = 1, which

@@ -4,6 +4,7 @@
 #include "graph.hpp"
 
 #include <algorithm>
+#include <cmath>
 #include <map>
 #include <stdexcept>
 
@@ -200,6 +201,39 @@ Closure build_closure(int64_t n, const std::vector<int32_t>& agg_of_dof, int32_t
         c.sub_ptr[i + 1] = (int64_t)c.sub_dofs.size();
     }
     return c;
+}
+
+void a_closure_overlaps(const Csr& pat, const std::vector<double>& val, double tol, Closure& c) {
+    const int64_t n = pat.rows();
+    std::vector<double> diag(n, 0.0);
+    for (int64_t p = 0; p < n; ++p)
+        for (int64_t q = pat.ptr[p]; q < pat.ptr[p + 1]; ++q)
+            if (pat.idx[q] == p) diag[p] = val[q];
+    std::vector<int64_t> ptr(c.n_agg + 1, 0);
+    std::vector<int32_t> dofs;
+    dofs.reserve(c.sub_dofs.size());
+    std::vector<int32_t> mark(n, -1), gam;
+    for (int32_t i = 0; i < c.n_agg; ++i) {
+        for (int64_t q = c.agg_ptr[i]; q < c.agg_ptr[i + 1]; ++q) mark[c.agg_dofs[q]] = i;
+        gam.clear();
+        for (int64_t q = c.agg_ptr[i]; q < c.agg_ptr[i + 1]; ++q) {
+            const int32_t r = c.agg_dofs[q];
+            dofs.push_back(r);
+            for (int64_t t = pat.ptr[r]; t < pat.ptr[r + 1]; ++t) {
+                const int32_t p = pat.idx[t];
+                if (mark[p] == i) continue;
+                if (std::fabs(val[t]) > tol * std::sqrt(std::fabs(diag[p] * diag[r]))) {
+                    mark[p] = i;
+                    gam.push_back(p);
+                }
+            }
+        }
+        std::sort(gam.begin(), gam.end());
+        dofs.insert(dofs.end(), gam.begin(), gam.end());
+        ptr[i + 1] = (int64_t)dofs.size();
+    }
+    c.sub_ptr = std::move(ptr);
+    c.sub_dofs = std::move(dofs);
 }
 
 std::vector<int32_t> color_subdomains(int64_t n, const Closure& c, const ElemList& el, int32_t* n_colors) {

@@ -51,6 +51,13 @@ struct Closure {
 // hierarchy ended on this level); elements made of such DOFs touch no aggregate.
 Closure build_closure(int64_t n, const std::vector<int32_t>& agg_of_dof, int32_t n_agg, const ElemList& el);
 
+// Replace the overlaps of c by algebraic A-closures (Def. "algebraic A-closure"):
+// Omega_i = omega_i, then the DOFs p outside omega_i with
+// |A(p,q)| > tol sqrt(|A(p,p) A(q,q)|) for some q in omega_i, ascending.  A is the
+// level's symmetric operator (CSR with pattern pat, values val).  Every such p
+// shares an element with omega_i, so the new overlap is a subset of the G-row one.
+void a_closure_overlaps(const Csr& pat, const std::vector<double>& val, double tol, Closure& c);
+
 // Greedy colouring of subdomains: i and k conflict iff an element meets both
 // Omega_i and Omega_k.  Ascending index, smallest free colour.
 std::vector<int32_t> color_subdomains(int64_t n, const Closure& c, const ElemList& el, int32_t* n_colors);

@@ -279,7 +279,8 @@ __global__ void __launch_bounds__(WG) k_local_assemble(LocalArgs A) {
             const double w = 1.0 / (double)A.mult[e];
             for (int idx = tid(); idx < nj * ne; idx += WG) {
                 const int i = idx % ne, j = s_j[idx / ne];
-                W1[pos[i] + (int64_t)pos[j] * m] += w * Be[(int64_t)i * ne + j];
+                const int pi = pos[i];   // < 0: outside an A-closure overlap
+                if (pi >= 0) W1[pi + (int64_t)pos[j] * m] += w * Be[(int64_t)i * ne + j];
             }
         }
         __syncthreads();
@@ -842,6 +843,10 @@ __global__ void k_copy(int64_t n, const double* a, double* b) {
     for (int64_t i = blockIdx.x * (int64_t)WG + tid(); i < n; i += (int64_t)gridDim.x * WG) b[i] = a[i];
 }
 
+__global__ void k_axpy(int64_t n, double a, const double* x, double* y) {
+    for (int64_t i = blockIdx.x * (int64_t)WG + tid(); i < n; i += (int64_t)gridDim.x * WG) y[i] += a * x[i];
+}
+
 __global__ void k_check_finite(int64_t n, const double* a, int32_t* flag) {
     for (int64_t i = blockIdx.x * (int64_t)WG + tid(); i < n; i += (int64_t)gridDim.x * WG)
         if (!isfinite(a[i])) *flag = 1;
@@ -1062,6 +1067,10 @@ void launch_update_p(int64_t n, const double* s_num, const double* s_den, const 
 
 void launch_copy(int64_t n, const double* a, double* b, hipStream_t st) {
     hipLaunchKernelGGL(k_copy, dim3(grid_for(n)), dim3(WG), 0, st, n, a, b);
+}
+
+void launch_axpy(int64_t n, double a, const double* x, double* y, hipStream_t st) {
+    hipLaunchKernelGGL(k_axpy, dim3(grid_for(n)), dim3(WG), 0, st, n, a, x, y);
 }
 
 void launch_check_finite(int64_t n, const double* a, int32_t* flag, hipStream_t st) {

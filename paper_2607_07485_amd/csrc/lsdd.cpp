@@ -594,6 +594,13 @@ std::unique_ptr<Level> coarsen(lsdd_hierarchy* h, Level& lv, const int32_t* agg_
         for (int32_t i = 0; i < n_inst; ++i) agg_first[i + 1] += agg_first[i];
     }
     lv.cl = build_closure(n, lv.agg_of_dof, n_agg, lv.el);
+    if (P.closure == 1) {
+        // algebraic A-closures from the numerical entries of A_l; the closure
+        // elements and multiplicities stay those of the G-row closure, and the
+        // local assembly drops element DOFs outside the smaller overlap
+        const std::vector<double> val = download(lv.d_val, (size_t)lv.nnz, st);
+        a_closure_overlaps(lv.pat, val, P.closure_tol, lv.cl);
+    }
     const Closure& C = lv.cl;
     double tc0 = now_s();
     vlog("level %d: aggregation and closures %.3f s", lv.level, tc0 - ta0);
@@ -1655,7 +1662,8 @@ lsdd_hierarchy* build(ElemList el0, const double* blocks, bool blocks_on_device,
     lsdd_params_default(&h->prm);
     if (prm) h->prm = *prm;
     const lsdd_params& P = h->prm;
-    if (P.max_levels < 1 || P.precision < 0 || P.precision > 1 || P.tau_const <= 0 || P.rtol <= 0 || P.max_iter < 1)
+    if (P.max_levels < 1 || P.precision < 0 || P.precision > 1 || P.tau_const <= 0 || P.rtol <= 0 || P.max_iter < 1 ||
+        P.closure < 0 || P.closure > 1 || !(P.closure_tol >= 0))
         throw Error(LSDD_E_INVAL, "invalid parameters");
     h->st = (hipStream_t)stream;
     double t0 = now_s();
@@ -1802,6 +1810,8 @@ void lsdd_params_default(lsdd_params* p) {
     p->band_tol = 1e-9;
     p->rank_rtol = 0.0;
     p->spsd_tol = 1e-12;
+    p->closure = 0;
+    p->closure_tol = 1e-12;
 }
 
 const char* lsdd_last_error(void) { return g_err.c_str(); }
@@ -2132,6 +2142,84 @@ lsdd_status lsdd_solve(lsdd_hierarchy* h, const double* b, double* x, int32_t nr
     if (breakdown) throw Error(LSDD_E_BREAKDOWN, "PCG breakdown (p^T A p <= 0 or non-finite)");
     if (!allconv) {
         g_err = "PCG did not reach rtol within max_iter";
+        return LSDD_E_NOCONV;
+    }
+    return LSDD_OK;
+    ABI_END
+}
+
+lsdd_status lsdd_solve_stationary(lsdd_hierarchy* h, const double* b, double* x, int32_t nrhs, void* hip_stream,
+                                  lsdd_info* info) {
+    ABI_BEGIN
+    if (!h || !b || !x || nrhs < 1) throw Error(LSDD_E_INVAL, "bad argument");
+    if (h->seg.n_seg != 1)
+        throw Error(LSDD_E_UNSUPPORTED, "the standalone cycle iteration needs a single-problem hierarchy");
+    h->st = (hipStream_t)hip_stream;
+    hipStream_t st = h->st;
+    Level& l0 = *h->L[0];
+    const int64_t n = l0.n;
+    const double t0 = now_s();
+    int32_t* fin = h->ic + 2 * h->nsm + 3;
+    HIPCHK(hipMemsetAsync(fin, 0, sizeof(int32_t), st));
+    launch_check_finite(n * nrhs, b, fin, st);
+    launch_check_finite(n * nrhs, x, fin, st);
+    if (download(fin, 1, st)[0]) throw Error(LSDD_E_INVAL, "right-hand side or initial iterate has NaN/Inf");
+    auto& B = h->pb[0];
+    double* rr = h->sc;
+    std::vector<lsdd_info> out((size_t)nrhs);
+    bool breakdown = false;
+    for (int32_t k = 0; k < nrhs && !breakdown; ++k) {
+        const double* bk = b + (int64_t)k * n;
+        double* xk = x + (int64_t)k * n;
+        lsdd_info& f = out[k];
+        f.setup_s = h->setup_s;
+        // r = b - A x and its norm
+        auto resid = [&] {
+            traced(h, "pcg_spmv", (double)l0.nnz * 12.0 + (double)n * 8.0 * 3,
+                   [&] { Cyc<double, 1>::spmv(l0, l0.d_val, xk, B.r, bk, st); });
+            launch_seg_dot(h->seg, 1, B.r, B.r, nullptr, nullptr, h->part, rr, nullptr, st);
+            const double v = std::sqrt(download(rr, 1, st)[0]);
+            if (h->tr.on) h->tr.flush();
+            return v;
+        };
+        const double r0 = resid();
+        if (!std::isfinite(r0)) {
+            breakdown = true;
+            break;
+        }
+        if (r0 == 0.0) {
+            f.converged = 1;
+            continue;
+        }
+        double rel = 1.0;
+        int32_t it = 0;
+        while (it < h->prm.max_iter) {
+            precond<1>(h, B.r, B.z);
+            launch_axpy(n, 1.0, B.z, xk, st);
+            ++it;
+            rel = resid() / r0;
+            if (!std::isfinite(rel)) {
+                breakdown = true;
+                break;
+            }
+            if (rel <= h->prm.rtol) break;
+        }
+        f.iters = it;
+        f.rel_res = rel;
+        f.converged = (!breakdown && rel <= h->prm.rtol) ? 1 : 0;
+    }
+    HIPCHK(hipGetLastError());
+    sync(st);
+    const double ts = now_s() - t0;
+    bool allconv = true;
+    for (auto& f : out) {
+        f.solve_s = ts;
+        allconv = allconv && f.converged;
+    }
+    if (info) std::copy(out.begin(), out.end(), info);
+    if (breakdown) throw Error(LSDD_E_BREAKDOWN, "non-finite residual in the standalone cycle iteration");
+    if (!allconv) {
+        g_err = "the standalone cycle iteration did not reach rtol within max_iter";
         return LSDD_E_NOCONV;
     }
     return LSDD_OK;

@@ -29,9 +29,10 @@ class Params(C.Structure):
     _fields_ = [("max_levels", C.c_int32), ("agg_passes", C.c_int32), ("agg_passes_coarse", C.c_int32),
                 ("modes_fixed", C.c_int32), ("min_coarse", C.c_int32), ("max_iter", C.c_int32),
                 ("precision", C.c_int32), ("blocked_eig_min", C.c_int32),
+                ("closure", C.c_int32), ("reserved0", C.c_int32),
                 ("tau_const", C.c_double), ("max_density", C.c_double), ("rtol", C.c_double),
                 ("cluster_tol", C.c_double), ("band_tol", C.c_double), ("rank_rtol", C.c_double),
-                ("spsd_tol", C.c_double)]
+                ("spsd_tol", C.c_double), ("closure_tol", C.c_double)]
 
     @classmethod
     def default(cls, **kw) -> "Params":
@@ -68,6 +69,7 @@ def lib():
         L.lsdd_setup_gram_csr.argtypes = [C.c_int64, C.c_int64, i64p, i32p, f64p, i32p, i32p,
                                           C.POINTER(Params), _P, C.POINTER(_P)]
         L.lsdd_solve.argtypes = [_P, _P, _P, C.c_int32, _P, C.POINTER(Info)]
+        L.lsdd_solve_stationary.argtypes = [_P, _P, _P, C.c_int32, _P, C.POINTER(Info)]
         L.lsdd_vcycle.argtypes = [_P, _P, _P, _P]
         L.lsdd_apply.argtypes = [_P, C.c_int32, _P, _P, _P]
         L.lsdd_hierarchy_info.argtypes = [_P, i32p, i64p, i64p, f64p, f64p]
@@ -92,7 +94,8 @@ def lib():
         L.lsdd_elem_bilinear.argtypes = [C.c_int64, i64p, _P, _P, _P, _P, _P, _P]
         L.lsdd_level_tuning.argtypes = [_P, C.c_int32, i32p]
         L.lsdd_set_allocator.restype = None
-        for name in ("lsdd_setup_elements", "lsdd_setup_gram_csr", "lsdd_solve", "lsdd_vcycle", "lsdd_apply",
+        for name in ("lsdd_setup_elements", "lsdd_setup_gram_csr", "lsdd_solve", "lsdd_solve_stationary",
+                     "lsdd_vcycle", "lsdd_apply",
                      "lsdd_hierarchy_info", "lsdd_level_sizes", "lsdd_export_level", "lsdd_export_gram",
                      "lsdd_destroy", "lsdd_set_cycle_precision", "lsdd_trace", "lsdd_trace_get",
                      "lsdd_set_solve_params", "lsdd_set_graph", "lsdd_segments", "lsdd_setup_batched",
@@ -259,6 +262,15 @@ class Hierarchy:
         _check(lib().lsdd_solve(self._h, _dev_ptr(b), _dev_ptr(x), nrhs, _stream(), infos),
                allow=(5,) if allow_noconv else ())
         return x, [infos[i] for i in range(nrhs * nseg)]
+
+    def solve_stationary(self, b, x0, allow_noconv=False):
+        """lsdd_solve_stationary: x <- x + V(b - A x) from x0 (shape [n] or [nrhs, n],
+        overwritten with the last iterates); returns (x, [Info]) per right-hand side."""
+        nrhs = 1 if b.dim() == 1 else b.shape[0]
+        infos = (Info * nrhs)()
+        _check(lib().lsdd_solve_stationary(self._h, _dev_ptr(b), _dev_ptr(x0), nrhs, _stream(), infos),
+               allow=(5,) if allow_noconv else ())
+        return x0, [infos[i] for i in range(nrhs)]
 
     def set_graph(self, on: bool):
         _check(lib().lsdd_set_graph(self._h, 1 if on else 0))

@@ -79,3 +79,20 @@ def test_batched_setup_validates_instance_local_indices():
     bad2.agg_of_dof = agg
     with pytest.raises(P.LsddError, match="aggregate ids of an instance"):
         P.Hierarchy.setup_batched([a, bad2])
+
+
+def test_params_struct_layout_matches_the_header(tmp_path):
+    """The binding's Params mirrors lsdd_params field by field (offsets and size)."""
+    import ctypes
+
+    import paper_2607_07485_amd as P
+    fields = [f for f, _ in P.Params._fields_]
+    src = tmp_path / "layout.c"
+    src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "lsdd.h"\nint main(void) {\n'
+                   + "".join(f'printf("%zu\\n", offsetof(lsdd_params, {f}));\n' for f in fields)
+                   + 'printf("%zu\\n", sizeof(lsdd_params));\nreturn 0;\n}\n')
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    got = [int(v) for v in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()]
+    want = [getattr(P.Params, f).offset for f in fields] + [ctypes.sizeof(P.Params)]
+    assert got == want
