@@ -24,7 +24,9 @@ algebraic preconditioning framework for conforming finite elements"):
   G_c = G P; direct solve on the coarsest level.
 * Sec. 2 (two-level cycle) and Sec. 6 (solver settings): forward multiplicative
   Schwarz pre-smoothing on the overlaps, reverse-order post-smoothing, stop rule
-  (fewer than 10 DOFs, density above 25 %, level cap).
+  (fewer than 10 DOFs, density above 25 %, level cap); the other block Schwarz
+  smoothers Sec. 2 names (restricted additive Schwarz, block Jacobi) with the
+  post-smoother M^{-T}.
 * Outer iteration: preconditioned CG (Hestenes-Stiefel) from x0 = 0 to a relative
   residual tolerance; the paper's own standalone-cycle mode is ``stationary``.
 
@@ -77,6 +79,12 @@ class Params:
     # with "A" an entry counts as nonzero when |A(p,q)| > closure_tol sqrt(A(p,p) A(q,q))
     closure: str = "G"
     closure_tol: float = 1e-12
+    # block Schwarz smoother M^{-1} of the cycle (Sec. 2, two-level propagator with
+    # pre-smoother M^{-1} and post-smoother M^{-T}): "ms" forward multiplicative Schwarz
+    # on the overlaps (post: reverse order; Sec. 6), "ras" restricted additive Schwarz
+    # (local solves on the overlaps, corrections kept on the aggregates), "bj" block
+    # Jacobi on the aggregates
+    smoother: str = "ms"
 
 
 # ----------------------------------------------------------------- element factors (Sec. 5.2)
@@ -223,7 +231,8 @@ class Level:
     coarse_off: np.ndarray = None
     colors: np.ndarray = None
     order: np.ndarray = None            # sweep order: (colour, index) ascending
-    chol: list = field(default_factory=list)      # Cholesky factors of A_Omega_i
+    chol: list = field(default_factory=list)      # Cholesky factors of A_Omega_i (A_ww for "bj")
+    smoother: str = "ms"
     coarsest_chol: tuple = None
 
 
@@ -481,9 +490,16 @@ def coarsen(lev: Level, params: Params, agg_of_dof=None):
         vals.append(lev.Z[i].ravel())
     lev.P = sp.csr_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))), shape=(n, nc))
     # smoother data
-    lev.colors = coloring(omegas, lev.elem_dofs, n)
+    if params.smoother not in ("ms", "ras", "bj"):
+        raise ValueError("smoother must be 'ms', 'ras' or 'bj'")
+    if params.smoother == "bj":
+        lev.colors = np.zeros(n_agg, dtype=np.int64)          # disjoint blocks: one class
+        lev.chol = [sla.cho_factor(lev.A[w][:, w].toarray(), lower=True) for w in aggs]
+    else:
+        lev.colors = coloring(omegas, lev.elem_dofs, n)
+        lev.chol = [sla.cho_factor(lev.A[O][:, O].toarray(), lower=True) for O in omegas]
     lev.order = np.lexsort((np.arange(n_agg), lev.colors))
-    lev.chol = [sla.cho_factor(lev.A[O][:, O].toarray(), lower=True) for O in omegas]
+    lev.smoother = params.smoother
     # coarse level (Sec. 2, Galerkin recursion; Remark "finer-scale Grams induce
     # coarser-scale Grams"): the rows of element T give G_T P_T with structural
     # support on the coarse DOFs of the aggregates T touches.  Elements touching
@@ -525,17 +541,50 @@ def smooth(lev: Level, x: np.ndarray, r: np.ndarray, order) -> None:
         x[O] += sla.cho_solve(lev.chol[i], res)
 
 
+def smooth_additive(lev: Level, x: np.ndarray, r: np.ndarray, post: bool) -> None:
+    """One additive step x += M^{-1} (r - A x) (post: M^{-T}).
+
+    Block Jacobi: M^{-1} = sum_i R_w^T A_ww^{-1} R_w (symmetric).  RAS:
+    M^{-1} = sum_i R_Omega^T D_i A_Omega^{-1} R_Omega with D_i the 0/1 diagonal of
+    omega_i inside Omega_i (corrections kept on the aggregate, a partition of
+    unity); its transpose M^{-T} = sum_i R_Omega^T A_Omega^{-1} D_i R_Omega solves
+    with the residual restricted to the aggregate and keeps the whole correction."""
+    res = r - lev.A @ x
+    dx = np.zeros_like(x)
+    for i, w in enumerate(lev.aggs):
+        if lev.smoother == "bj":
+            dx[w] += sla.cho_solve(lev.chol[i], res[w])
+            continue
+        O = lev.omegas[i]
+        nw = len(w)
+        if not post:
+            dx[O[:nw]] += sla.cho_solve(lev.chol[i], res[O])[:nw]
+        else:
+            rr = np.zeros(len(O))
+            rr[:nw] = res[O[:nw]]
+            dx[O] += sla.cho_solve(lev.chol[i], rr)
+    x += dx
+
+
 def vcycle(h: Hierarchy, r: np.ndarray, l: int = 0) -> np.ndarray:
-    """Symmetric V-cycle: forward sweep, coarse correction, reverse sweep (Sec. 2, Sec. 6)."""
+    """Symmetric V-cycle: pre-smoother M^{-1}, coarse correction, post-smoother M^{-T}
+    (Sec. 2); for multiplicative Schwarz the post-sweep runs the overlaps in reverse
+    order (Sec. 6)."""
     lev = h.levels[l]
     if l == len(h.levels) - 1:
         return sla.cho_solve(lev.coarsest_chol, r)
     x = np.zeros_like(r)
-    smooth(lev, x, r, lev.order)
+    if lev.smoother == "ms":
+        smooth(lev, x, r, lev.order)
+    else:
+        smooth_additive(lev, x, r, post=False)
     t = r - lev.A @ x
     e = vcycle(h, lev.P.T @ t, l + 1)
     x += lev.P @ e
-    smooth(lev, x, r, lev.order[::-1])
+    if lev.smoother == "ms":
+        smooth(lev, x, r, lev.order[::-1])
+    else:
+        smooth_additive(lev, x, r, post=True)
     return x
 
 
