@@ -68,7 +68,13 @@ typedef struct {
                                    with an entry |A(p,q)| > closure_tol sqrt(A(p,p) A(q,q)),
                                    q in omega_i; the local matrix is the G-row closure's
                                    A~_Omega cut down to those DOFs                          */
-    int32_t reserved0;          /* ignored                                                    */
+    int32_t smoother;           /* block Schwarz smoother M^{-1} of the cycle (Sec. 2; the
+                                   post-smoother is M^{-T}): 0 = multiplicative Schwarz on the
+                                   overlaps, colour-major forward, reverse after the coarse
+                                   correction (default, Sec. 6); 1 = restricted additive
+                                   Schwarz (local solves on the overlaps, corrections kept on
+                                   the aggregates; M^{-T} restricts the residual instead);
+                                   2 = block Jacobi on the aggregates (A_ww^{-1})            */
     double tau_const;           /* tau_cut = tau_const * max mult; default 0.75               */
     double max_density;         /* nnz(A_l)/n_l^2 above this -> coarsest; default 0.25         */
     double rtol;                /* PCG stop: ||r||_2 <= rtol ||b||_2; default 1e-8              */

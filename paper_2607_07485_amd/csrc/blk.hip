@@ -36,15 +36,15 @@ __global__ void __launch_bounds__(WG) k_csr_resid_rows_b(int64_t nrows, const in
     const int lane = tid() & (L - 1), k = lane & (NB - 1), slot = lane / NB;
     const int64_t stride = (int64_t)gridDim.x * (WG / L);
     for (int64_t t = ((int64_t)blockIdx.x * WG + tid()) / L; t < nrows; t += stride) {
-        const int32_t p = rows[t];
+        const int32_t p = rows[t];   // < 0: masked entry, out = 0
         T s = 0;
-        if (!x_zero) {
+        if (!x_zero && p >= 0) {
             const int64_t q1 = rowptr[p + 1];
 #pragma unroll 4
             for (int64_t q = rowptr[p] + slot; q < q1; q += NS) s += val[q] * x[(int64_t)col[q] * NB + k];
         }
         for (int off = L / 2; off >= NB; off >>= 1) s += __shfl_xor(s, off, L);
-        if (slot == 0) out[t * NB + k] = r[(int64_t)p * NB + k] - s;
+        if (slot == 0) out[t * NB + k] = p >= 0 ? r[(int64_t)p * NB + k] - s : (T)0;
     }
 }
 
@@ -184,8 +184,8 @@ __global__ void __launch_bounds__(WG) k_sub_finalize_b(int64_t r0, int64_t r1, c
     if (j < NB && t < r1) {
         T v = s_y[0][dl][j];
         for (int q = 1; q < FL; ++q) v += s_y[q][dl][j];
-        const int64_t d = sub_dofs ? (int64_t)sub_dofs[t] : t;
-        x[d * NB + j] = accumulate ? x[d * NB + j] + v : v;
+        const int64_t d = sub_dofs ? (int64_t)sub_dofs[t] : t;   // < 0: masked entry
+        if (d >= 0) x[d * NB + j] = accumulate ? x[d * NB + j] + v : v;
     }
 }
 
@@ -285,8 +285,9 @@ __global__ void __launch_bounds__(WG) k_prolong_b(const int32_t* items, const in
 // Overlaps with |Omega| <= SMALL_M: the inverse is stored as its packed lower
 // triangle (entry (i, j), j <= i, at i (i + 1) / 2 + j), staged in LDS by one
 // wave per subdomain; lane i forms y_i = sum_j (A_Omega^{-1})_{ij} r_j over all j in
-// ascending order (fixed order) and adds it to x: subdomains of one colour are
-// disjoint, so the update needs no partial sums.
+// ascending order (fixed order) and adds it to x (entries with a negative DOF are
+// skipped): subdomains of one colour are disjoint, so the update needs no partial
+// sums.
 template <typename T, int NR>
 __global__ void __launch_bounds__(64) k_small_sub(int32_t s0, const int64_t* sub_off, const int32_t* sub_dofs,
                                                   const int64_t* pk_off, const T* pk, const T* rloc, T* x) {
@@ -312,9 +313,12 @@ __global__ void __launch_bounds__(64) k_small_sub(int32_t s0, const int64_t* sub
 #pragma unroll
             for (int k = 0; k < NR; ++k) y[k] += a * s_x[j * NR + k];
         }
-        T* dst = x + (int64_t)sub_dofs[o + i] * NR;
+        const int32_t d = sub_dofs[o + i];   // < 0: masked entry
+        if (d >= 0) {
+            T* dst = x + (int64_t)d * NR;
 #pragma unroll
-        for (int k = 0; k < NR; ++k) dst[k] += y[k];
+            for (int k = 0; k < NR; ++k) dst[k] += y[k];
+        }
     }
 }
 

@@ -502,9 +502,9 @@ __global__ void __launch_bounds__(WG) k_csr_resid_rows(int64_t nrows, const int3
     const int lane = tid() & (L - 1);
     const int64_t stride = (int64_t)gridDim.x * (WG / L);
     for (int64_t t = ((int64_t)blockIdx.x * WG + tid()) / L; t < nrows; t += stride) {
-        const int32_t p = rows[t];
+        const int32_t p = rows[t];   // < 0: masked entry, out = 0
         T s = 0;
-        if (!x_zero) {
+        if (!x_zero && p >= 0) {
             // up to 4 entries per lane in flight: all column indices, then all
             // gathers, then the products (two dependent loads per entry)
             const int64_t q1 = rowptr[p + 1];
@@ -524,7 +524,7 @@ __global__ void __launch_bounds__(WG) k_csr_resid_rows(int64_t nrows, const int3
             }
         }
         for (int off = L / 2; off > 0; off >>= 1) s += __shfl_xor(s, off, L);
-        if (lane == 0) out[t] = r[p] - s;
+        if (lane == 0) out[t] = p >= 0 ? r[p] - s : (T)0;
     }
 }
 
@@ -676,8 +676,8 @@ __global__ void __launch_bounds__(WG) k_sub_finalize(int64_t r0, int64_t r1, con
         T v = s_y[0][dl];
 #pragma unroll
         for (int q = 1; q < FL; ++q) v += s_y[q][dl];
-        const int32_t d = sub_dofs ? sub_dofs[t] : (int32_t)t;
-        x[d] = accumulate ? x[d] + v : v;
+        const int32_t d = sub_dofs ? sub_dofs[t] : (int32_t)t;   // < 0: masked entry
+        if (d >= 0) x[d] = accumulate ? x[d] + v : v;
     }
 }
 

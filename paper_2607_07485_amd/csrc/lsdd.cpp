@@ -208,6 +208,8 @@ struct Level {
     std::vector<double> color_m2, color_m, color_nnz;   // sums of |Omega|^2, |Omega|, row nnz per colour
     int64_t* d_sw_sub_off = nullptr;
     int32_t* d_sw_sub_dofs = nullptr;
+    int32_t* d_sw_sub_dofs_w = nullptr;   // RAS: the same with interface entries = -1
+    int32_t smoother = 0;                 // 0 multiplicative Schwarz, 1 RAS, 2 block Jacobi
     int64_t* d_sw_tp_off = nullptr;   // packed-tile offset of each subdomain (sweep order)
     int32_t* d_items = nullptr;       // (subdomain, tile row), grouped by colour
     int32_t* d_pos_sub = nullptr;     // sweep-order subdomain of every Omega entry
@@ -606,7 +608,18 @@ std::unique_ptr<Level> coarsen(lsdd_hierarchy* h, Level& lv, const int32_t* agg_
     vlog("level %d: aggregation and closures %.3f s", lv.level, tc0 - ta0);
     for (int32_t i = 0; i < n_agg; ++i)
         if (C.agg_ptr[i + 1] == C.agg_ptr[i]) throw Error(LSDD_E_INVAL, "empty aggregate " + std::to_string(i));
-    lv.colors = color_subdomains(n, C, lv.el, &lv.n_colors);
+    // smoother subdomains: the overlaps (multiplicative Schwarz, restricted additive
+    // Schwarz) or the aggregates themselves (block Jacobi: disjoint, one class)
+    const bool bj = P.smoother == 2;
+    const std::vector<int64_t>& sp_ptr = bj ? C.agg_ptr : C.sub_ptr;
+    const std::vector<int32_t>& sp_dofs = bj ? C.agg_dofs : C.sub_dofs;
+    if (bj) {
+        lv.colors.assign(n_agg, 0);
+        lv.n_colors = n_agg > 0 ? 1 : 0;
+    } else {
+        lv.colors = color_subdomains(n, C, lv.el, &lv.n_colors);
+    }
+    lv.smoother = P.smoother;
     const double tau_cut = P.tau_const * (double)C.max_mult;
     // tau_cut of every aggregate from the largest multiplicity of its own instance
     std::vector<double> thr_agg;
@@ -629,7 +642,7 @@ std::unique_ptr<Level> coarsen(lsdd_hierarchy* h, Level& lv, const int32_t* agg_
         max_m = std::max(max_m, m);
         max_nw = std::max(max_nw, nw);
         sq[i + 1] = sq[i] + nw * nw;
-        msq[i + 1] = msq[i] + m * m;
+        msq[i + 1] = msq[i] + (bj ? nw * nw : m * m);   // smoother inverse
     }
     vlog("level %d: n=%lld aggregates=%d colours=%d max|omega|=%lld max|Omega|=%lld max mult=%d",
          lv.level, (long long)n, n_agg, lv.n_colors, (long long)max_nw, (long long)max_m, C.max_mult);
@@ -872,12 +885,20 @@ std::unique_ptr<Level> coarsen(lsdd_hierarchy* h, Level& lv, const int32_t* agg_
         for (int32_t b = 0; b < nb; ++b) vZ[b] = View{ws_off[b], vS[b].rows, vS[b].rows, kb[b], 0};
         bt.trsm(w2, vLww, w1, vZ, true);
         launch_stage_z(nb, B, st);
-        // subdomain inverse A_Omega^{-1} = L^{-T} L^{-1}
-        launch_views_identity(nb, w1, bt.put(0, vAO), st);
-        bt.trsm(w2, vAO, w1, vAO, false, true);                             // X = L^{-1} (lower)
-        std::vector<View> vInv(nb);
-        for (int32_t b = 0; b < nb; ++b) vInv[b] = View{msq[pos + b], vAO[b].rows, vAO[b].rows, vAO[b].rows, 0};
-        bt.gemm_tn(w1, vAO, w1, vAO, nullptr, vInv, 0.0, lv.d_inv, vInv, -1.0, true, true);   // X^T X
+        // smoother inverse A_Omega^{-1} = L^{-T} L^{-1}, or for block Jacobi
+        // A_ww^{-1} from the leading block L_ww of the same factor
+        {
+            std::vector<View> vL(nb), vX(nb), vInv(nb);
+            for (int32_t b = 0; b < nb; ++b) {
+                const int32_t ms = bj ? vLww[b].rows : vAO[b].rows;
+                vL[b] = bj ? vLww[b] : vAO[b];
+                vX[b] = View{vAO[b].off, ms, ms, ms, 0};
+                vInv[b] = View{msq[pos + b], ms, ms, ms, 0};
+            }
+            launch_views_identity(nb, w1, bt.put(0, vX), st);
+            bt.trsm(w2, vL, w1, vX, false, true);                           // X = L^{-1} (lower)
+            bt.gemm_tn(w1, vX, w1, vX, nullptr, vInv, 0.0, lv.d_inv, vInv, -1.0, true, true);   // X^T X
+        }
         HIPCHK(hipGetLastError());
         sync(st);
         vlog("  batch of %d aggregates from %d done (%.3f s since start)", nb, pos, now_s() - tc0);
@@ -938,18 +959,18 @@ std::unique_ptr<Level> coarsen(lsdd_hierarchy* h, Level& lv, const int32_t* agg_
     // ---- smoother arrays in sweep order: colour-major; inside a colour the large
     // overlaps (tiled product) come first, then the small ones (|Omega| <= SMALL_M);
     // subdomains of one colour commute, so this order gives the same smoother
-    auto is_small = [&](int32_t i) { return C.sub_ptr[i + 1] - C.sub_ptr[i] <= SMALL_M; };
+    auto is_small = [&](int32_t i) { return sp_ptr[i + 1] - sp_ptr[i] <= SMALL_M; };
     lv.sweep.resize(n_agg);
     for (int32_t i = 0; i < n_agg; ++i) lv.sweep[i] = i;
     std::stable_sort(lv.sweep.begin(), lv.sweep.end(), [&](int32_t a, int32_t b) {
         if (lv.colors[a] != lv.colors[b]) return lv.colors[a] < lv.colors[b];
         return (int)is_small(a) < (int)is_small(b);
     });
-    std::vector<int32_t> sw_dofs;
+    std::vector<int32_t> sw_dofs, sw_dofs_w;
     std::vector<int64_t> tp_agg(n_agg, -1), pk_agg(n_agg, -1), sw_tp_off(n_agg, -1), sw_pk_off(n_agg, -1);
     int64_t tiles = 0, pks = 0;
     for (int32_t i = 0; i < n_agg; ++i) {
-        const int64_t m = C.sub_ptr[i + 1] - C.sub_ptr[i];
+        const int64_t m = sp_ptr[i + 1] - sp_ptr[i];
         if (is_small(i)) {
             pk_agg[i] = pks;
             pks += m * (m + 1) / 2;
@@ -975,7 +996,11 @@ std::unique_ptr<Level> coarsen(lsdd_hierarchy* h, Level& lv, const int32_t* agg_
             lv.color_smid[c] = s;
             lv.color_rmid[c] = (int64_t)sw_dofs.size();
         }
-        sw_dofs.insert(sw_dofs.end(), C.sub_dofs.begin() + C.sub_ptr[i], C.sub_dofs.begin() + C.sub_ptr[i + 1]);
+        sw_dofs.insert(sw_dofs.end(), sp_dofs.begin() + sp_ptr[i], sp_dofs.begin() + sp_ptr[i + 1]);
+        // the same list with the interface entries masked (-1): the aggregate part
+        // of the overlap, for the restricted updates of RAS
+        const int64_t nw_i = C.agg_ptr[i + 1] - C.agg_ptr[i];
+        for (int64_t q = sp_ptr[i]; q < sp_ptr[i + 1]; ++q) sw_dofs_w.push_back(q - sp_ptr[i] < nw_i ? sp_dofs[q] : -1);
         lv.sw_sub_off.push_back((int64_t)sw_dofs.size());
         sw_tp_off[s] = tp_agg[i];
         sw_pk_off[s] = pk_agg[i];
@@ -999,11 +1024,11 @@ std::unique_ptr<Level> coarsen(lsdd_hierarchy* h, Level& lv, const int32_t* agg_
     lv.color_nnz.assign(lv.n_colors, 0.0);
     lv.color_pk.assign(lv.n_colors, 0.0);
     for (int32_t i = 0; i < n_agg; ++i) {
-        double m = (double)(C.sub_ptr[i + 1] - C.sub_ptr[i]);
+        double m = (double)(sp_ptr[i + 1] - sp_ptr[i]);
         (is_small(i) ? lv.color_pk : lv.color_m2)[lv.colors[i]] += m * (m + 1.0) / 2.0;   // inverse entries
         lv.color_m[lv.colors[i]] += m;
-        for (int64_t q = C.sub_ptr[i]; q < C.sub_ptr[i + 1]; ++q) {
-            int32_t d = C.sub_dofs[q];
+        for (int64_t q = sp_ptr[i]; q < sp_ptr[i + 1]; ++q) {
+            int32_t d = sp_dofs[q];
             lv.color_nnz[lv.colors[i]] += (double)(lv.pat.ptr[d + 1] - lv.pat.ptr[d]);
         }
     }
@@ -1014,6 +1039,7 @@ std::unique_ptr<Level> coarsen(lsdd_hierarchy* h, Level& lv, const int32_t* agg_
              lv.color_sub0[c + 1] - lv.color_smid[c], lv.color_pk[c] * 8e-6);
     lv.d_sw_sub_off = ar.upload(lv.sw_sub_off, st);
     lv.d_sw_sub_dofs = ar.upload(sw_dofs, st);
+    if (P.smoother == 1) lv.d_sw_sub_dofs_w = ar.upload(sw_dofs_w, st);
     lv.d_sw_tp_off = ar.upload(sw_tp_off, st);
     lv.d_items = ar.upload(items, st);
     {
@@ -1038,8 +1064,9 @@ std::unique_ptr<Level> coarsen(lsdd_hierarchy* h, Level& lv, const int32_t* agg_
         if (P.precision == 1) lv.d_tiles32 = ar.alloc<float>(std::max<int64_t>(lv.tiles_len, 1));
         lv.d_pk = ar.alloc<double>(std::max<int64_t>(pks, 1));
         if (P.precision == 1) lv.d_pk32 = ar.alloc<float>(std::max<int64_t>(pks, 1));
-        launch_pack_tiles(n_agg, d_sub_ptr, d_inv_off, lv.d_inv, d_tp_agg, lv.d_tiles, lv.d_tiles32, st);
-        launch_pack_small(n_agg, d_sub_ptr, d_inv_off, lv.d_inv, d_pk_agg, lv.d_pk, lv.d_pk32, st);
+        const int64_t* d_sp_ptr = bj ? lv.d_agg_ptr : d_sub_ptr;
+        launch_pack_tiles(n_agg, d_sp_ptr, d_inv_off, lv.d_inv, d_tp_agg, lv.d_tiles, lv.d_tiles32, st);
+        launch_pack_small(n_agg, d_sp_ptr, d_inv_off, lv.d_inv, d_pk_agg, lv.d_pk, lv.d_pk32, st);
         HIPCHK(hipGetLastError());
         sync(st);
         ar.release(d_tp_agg);
@@ -1263,8 +1290,9 @@ struct Cyc {
         if constexpr (NR == 1) launch_sub_finalize<T>(r0, r1, pos, sub_off, scr_off, scr, dofs, x, acc, chl, fl, st);
         else launch_sub_finalize_b<T>(r0, r1, pos, sub_off, scr_off, scr, dofs, x, acc, chl, fl, st);
     }
-    static void small(Level& lv, int64_t s0, int64_t n_sub, const T* pk, const T* rloc, T* x, hipStream_t st) {
-        launch_small_sub<T, NR>(s0, n_sub, lv.d_sw_sub_off, lv.d_sw_sub_dofs, lv.d_sw_pk_off, pk, rloc, x, st);
+    static void small(Level& lv, int64_t s0, int64_t n_sub, const T* pk, const T* rloc, T* x, const int32_t* dofs,
+                      hipStream_t st) {
+        launch_small_sub<T, NR>(s0, n_sub, lv.d_sw_sub_off, dofs, lv.d_sw_pk_off, pk, rloc, x, st);
     }
     static void restrict_(Level& lv, const T* Z, const T* t, T* rc, hipStream_t st) {
         launch_restrict_small<T, NR>(lv.coff.back(), lv.d_agg_of_c, lv.d_agg_ptr, lv.d_agg_dofs, lv.d_zoff, lv.d_coff,
@@ -1288,10 +1316,61 @@ struct Cyc {
     }
 };
 
+// Restricted additive Schwarz step (Sec. 2, block Schwarz smoothers): all local
+// residuals from the same x, then the local solves.  Pre-smoother M^{-1}: full
+// local residuals, corrections kept on the aggregates (interface entries of the
+// scatter list masked); post-smoother M^{-T}: residuals restricted to the
+// aggregates (masked gather), full corrections.  The corrections of one colour
+// are disjoint, so the colours are applied one after the other.
+template <typename T, int NR>
+void sweep_ras(lsdd_hierarchy* h, Level& lv, const T* r, T* x, bool post, bool x_zero_first) {
+    using O = LvOps<T>;
+    using C = Cyc<T, NR>;
+    VecSet<T>& v = O::v(lv, NR > 1);
+    const double w = (double)sizeof(T), wv = w * NR;
+    const int64_t rows = lv.color_row0[lv.n_colors];
+    double m_all = 0.0, nnz_all = 0.0;
+    for (int32_t c = 0; c < lv.n_colors; ++c) {
+        m_all += lv.color_m[c];
+        nnz_all += lv.color_nnz[c];
+    }
+    const int32_t* gather = post ? lv.d_sw_sub_dofs_w : lv.d_sw_sub_dofs;
+    const int32_t* scatter = post ? lv.d_sw_sub_dofs : lv.d_sw_sub_dofs_w;
+    traced(h, "csr_resid_rows", m_all * (4 + 8 + 3 * wv) + (x_zero_first ? 0.0 : nnz_all * (4 + w)), [&] {
+        C::resid_rows(rows, gather, lv, O::val(lv), x, r, v.rloc, x_zero_first, h->st);
+    });
+    for (int32_t c = 0; c < lv.n_colors; ++c) {
+        const int64_t r0 = lv.color_row0[c], r1 = lv.color_row0[c + 1], rm = lv.color_rmid[c];
+        const int64_t i0 = lv.color_item0[c], i1 = lv.color_item0[c + 1];
+        const int64_t s0 = lv.color_smid[c], ns = lv.color_sub0[c + 1] - lv.color_smid[c];
+        if (r1 == r0) continue;
+        if (i1 > i0) {
+            const double gb = lv.color_m2[c] * w + (double)(rm - r0) * (4 + 3 * wv);
+            traced(h, "sub_symv", gb, [&] {
+                C::symv(i1 - i0, lv.d_items + 3 * i0, lv.d_sw_sub_off, lv.d_sw_tp_off, O::inv(lv), v.rloc,
+                        lv.d_scr_off, v.scr, lv.chl, h->st);
+            });
+            const double fb = lv.color_scr[c] * wv + (double)(rm - r0) * (8 + 2 * wv);
+            traced(h, "sub_finalize", fb, [&] {
+                C::finalize(r0, rm, lv.d_pos_sub, lv.d_sw_sub_off, lv.d_scr_off, v.scr, scatter, x, true, lv.chl,
+                            lv.fl, h->st);
+            });
+        }
+        if (ns > 0) {
+            const double sb = lv.color_pk[c] * w + (double)(r1 - rm) * (4 + 3 * wv);
+            traced(h, "small_sub", sb, [&] { C::small(lv, s0, ns, O::pk(lv), v.rloc, x, scatter, h->st); });
+        }
+    }
+}
+
 template <typename T, int NR>
 void sweep(lsdd_hierarchy* h, Level& lv, const T* r, T* x, bool forward, bool x_zero_first) {
     using O = LvOps<T>;
     using C = Cyc<T, NR>;
+    if (lv.smoother == 1) {
+        sweep_ras<T, NR>(h, lv, r, x, !forward, x_zero_first);
+        return;
+    }
     VecSet<T>& v = O::v(lv, NR > 1);
     const double w = (double)sizeof(T), wv = w * NR;
     for (int32_t cc = 0; cc < lv.n_colors; ++cc) {
@@ -1319,7 +1398,7 @@ void sweep(lsdd_hierarchy* h, Level& lv, const T* r, T* x, bool forward, bool x_
         }
         if (ns > 0) {
             const double sb = lv.color_pk[c] * w + (double)(r1 - rm) * (4 + 3 * wv);
-            traced(h, "small_sub", sb, [&] { C::small(lv, s0, ns, O::pk(lv), v.rloc, x, h->st); });
+            traced(h, "small_sub", sb, [&] { C::small(lv, s0, ns, O::pk(lv), v.rloc, x, lv.d_sw_sub_dofs, h->st); });
         }
     }
 }
@@ -1663,7 +1742,7 @@ lsdd_hierarchy* build(ElemList el0, const double* blocks, bool blocks_on_device,
     if (prm) h->prm = *prm;
     const lsdd_params& P = h->prm;
     if (P.max_levels < 1 || P.precision < 0 || P.precision > 1 || P.tau_const <= 0 || P.rtol <= 0 || P.max_iter < 1 ||
-        P.closure < 0 || P.closure > 1 || !(P.closure_tol >= 0))
+        P.closure < 0 || P.closure > 1 || !(P.closure_tol >= 0) || P.smoother < 0 || P.smoother > 2)
         throw Error(LSDD_E_INVAL, "invalid parameters");
     h->st = (hipStream_t)stream;
     double t0 = now_s();
