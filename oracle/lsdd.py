@@ -85,6 +85,8 @@ class Params:
     # (local solves on the overlaps, corrections kept on the aggregates), "bj" block
     # Jacobi on the aggregates
     smoother: str = "ms"
+    # element Gram factor (Sec. 5.2): "eig" = Lambda_+^{1/2} Q_+^T, "chol" = pivoted Cholesky
+    elem_factor: str = "eig"
 
 
 # ----------------------------------------------------------------- element factors (Sec. 5.2)
@@ -104,6 +106,49 @@ def element_gram_factor(Ae: np.ndarray, rank_rtol: float = 0.0, spsd_tol: float 
     tol = (rank_rtol if rank_rtol > 0 else ne * EPS) * lmax
     keep = w > tol
     return np.sqrt(w[keep])[:, None] * Q[:, keep].T
+
+
+def element_gram_factor_pchol(Ae: np.ndarray, rank_rtol: float = 0.0, spsd_tol: float = 1e-12) -> np.ndarray:
+    """Pivoted Cholesky factor (Sec. 5.2): G_T with rows g_1 .. g_r, A_T = G_T^T G_T up to
+    the truncated remainder.
+
+    Step k takes the largest remaining diagonal entry of the Schur complement S
+    (lowest index among equal ones) as pivot p, forms g_k = S[:, p] / sqrt(S[p, p])
+    (zero on the DOFs already eliminated) and subtracts g_k g_k^T.  The
+    factorisation stops when the largest remaining diagonal entry is at most
+    tol = (rank_rtol or n_T eps) * max diag(A_T); the rank is the number of steps.
+    For an SPSD block the remainder is then bounded by tol entrywise (|S_ij| <=
+    sqrt(S_ii S_jj)); a remainder entry above 2 max(tol, spsd_tol max diag), or a
+    diagonal entry below -spsd_tol max diag, means the block is not SPSD.  For an
+    SPD block the rows are the transposed Cholesky factor of the block with rows
+    and columns in pivot order, so G_T is a square factor L_T^T up to that
+    symmetric permutation.
+    """
+    ne = Ae.shape[0]
+    S = np.array(Ae, dtype=np.float64, copy=True)
+    dmax0 = float(np.max(np.diag(S))) if ne else 0.0
+    if ne == 0 or dmax0 <= 0.0:
+        if ne and np.abs(S).max() > 0.0:
+            raise NotSPSD("non-positive diagonal with nonzero entries")
+        return np.zeros((0, ne))
+    tol = (rank_rtol if rank_rtol > 0 else ne * EPS) * dmax0
+    live = np.ones(ne, dtype=bool)
+    rows = []
+    for _ in range(ne):
+        d = np.where(live, np.diag(S), -np.inf)
+        p = int(np.argmax(d))                    # first index of the maximum
+        if not d[p] > tol:
+            break
+        g = np.where(live, S[:, p], 0.0) / np.sqrt(d[p])
+        rows.append(g)
+        S -= np.outer(g, g)
+        live[p] = False
+    if live.any():
+        R = S[np.ix_(live, live)]
+        chk = max(tol, spsd_tol * dmax0)
+        if np.diag(R).min() < -spsd_tol * dmax0 or np.abs(R).max() > 2.0 * chk:
+            raise NotSPSD(f"pivoted Cholesky remainder {np.abs(R).max():.3e} above {chk:.3e}")
+    return np.array(rows).reshape(len(rows), ne)
 
 
 # ----------------------------------------------------------------- assembly (Sec. 4, Sec. 5.1)
@@ -411,7 +456,10 @@ def setup(prob, params: Params | None = None) -> Hierarchy:
                  for e in range(nE)]
     offs = np.concatenate([[0], np.cumsum(np.diff(prob.elem_ptr) ** 2)])
     blocks = [np.asarray(prob.blocks[offs[e]:offs[e + 1]]).reshape(len(elem_dofs[e]), -1) for e in range(nE)]
-    G0 = [element_gram_factor(B, params.rank_rtol, params.spsd_tol) for B in blocks]
+    if params.elem_factor not in ("eig", "chol"):
+        raise ValueError("elem_factor must be 'eig' or 'chol'")
+    factor = element_gram_factor if params.elem_factor == "eig" else element_gram_factor_pchol
+    G0 = [factor(B, params.rank_rtol, params.spsd_tol) for B in blocks]
     lev = Level(n=prob.n, level=0, elem_dofs=elem_dofs, blocks=blocks, node_of_dof=np.asarray(prob.node_of_dof, np.int64))
     levels = []
     agg_given = None if prob.agg_of_dof is None else np.asarray(prob.agg_of_dof, np.int64)
