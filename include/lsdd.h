@@ -75,6 +75,14 @@ typedef struct {
                                    Schwarz (local solves on the overlaps, corrections kept on
                                    the aggregates; M^{-T} restricts the residual instead);
                                    2 = block Jacobi on the aggregates (A_ww^{-1})            */
+    int32_t elem_factor;        /* element Gram factor (Sec. 5.2): 0 = Lambda_+^{1/2} Q_+^T from
+                                   the eigendecomposition (default); 1 = pivoted Cholesky
+                                   (largest remaining diagonal pivot, stop at rank_rtol or
+                                   n_T eps times max diag; a remainder above that bound ->
+                                   LSDD_E_NOT_SPSD).  Under full-support rows the hierarchy
+                                   does not depend on the choice (Galerkin products up to
+                                   rounding)                                                */
+    int32_t reserved1;          /* ignored                                                    */
     double tau_const;           /* tau_cut = tau_const * max mult; default 0.75               */
     double max_density;         /* nnz(A_l)/n_l^2 above this -> coarsest; default 0.25         */
     double rtol;                /* PCG stop: ||r||_2 <= rtol ||b||_2; default 1e-8              */

@@ -141,6 +141,103 @@ __global__ void __launch_bounds__(WG) k_elem_eig(const int64_t* elem_ptr, const 
     }
 }
 
+// One workgroup per element: pivoted Cholesky of the symmetric block A_T (Sec. 5.2,
+// the direct alternative to the eigendecomposition).  Step k pivots on the largest
+// remaining diagonal entry of the Schur complement S (lowest index among equal
+// ones); row k of G_T is the pivot column of S scaled by 1/sqrt(pivot), zero on the
+// DOFs already eliminated, and S loses its outer product.  The factorisation stops
+// when the largest remaining diagonal entry is at most
+// tol = (rank_rtol or n_T eps) max diag(A_T); the rank is the number of steps.  For
+// an SPSD block the remainder is then bounded by tol entrywise, so a remainder
+// entry above 2 max(tol, spsd_tol max diag), or a diagonal entry below
+// -spsd_tol max diag, marks the block as not SPSD.  G_T is stored as by k_elem_eig.
+__global__ void __launch_bounds__(WG) k_elem_pchol(const int64_t* elem_ptr, const int64_t* blk_off,
+                                                   const double* blocks, double* G, int32_t* ranks,
+                                                   int32_t* status, double* scratch, int64_t scratch_stride,
+                                                   double rank_rtol, double spsd_tol) {
+    __shared__ double s_a[NE_LDS * NE_LDS];
+    __shared__ double s_g[128];
+    __shared__ int s_live[128];
+    __shared__ double s_red[WG / 64];
+    const int64_t e = blockIdx.x;
+    const int n = (int)(elem_ptr[e + 1] - elem_ptr[e]);
+    const double* B = blocks + blk_off[e];
+    double* a = n <= NE_LDS ? s_a : scratch + e * scratch_stride;
+    double asym = 0.0, amax = 0.0, dmax = -DBL_MAX;
+    for (int idx = tid(); idx < n * n; idx += WG) {
+        int i = idx % n, j = idx / n;
+        double x = B[(int64_t)i * n + j], y = B[(int64_t)j * n + i];
+        a[i + j * n] = 0.5 * (x + y);
+        asym = fmax(asym, fabs(x - y));
+        amax = fmax(amax, fabs(x));
+        if (i == j) dmax = fmax(dmax, x);
+    }
+    for (int i = tid(); i < n; i += WG) s_live[i] = 1;
+    __syncthreads();
+    asym = wg_max(asym, s_red);
+    amax = wg_max(amax, s_red);
+    dmax = wg_max(dmax, s_red);
+    if (!(asym <= 1e-12 * amax) || !(amax == amax) || amax > DBL_MAX) {
+        if (tid() == 0) status[e] = 1;   // asymmetric or non-finite
+        return;
+    }
+    double* g = G + blk_off[e];
+    if (!(dmax > 0.0)) {                 // zero block: rank 0; otherwise not SPSD
+        for (int idx = tid(); idx < n * n; idx += WG) g[idx] = 0.0;
+        if (tid() == 0) {
+            ranks[e] = 0;
+            status[e] = amax > 0.0 ? 2 : 0;
+        }
+        return;
+    }
+    const double tol = (rank_rtol > 0.0 ? rank_rtol : n * DBL_EPSILON) * dmax;
+    int k = 0;
+    for (; k < n; ++k) {
+        double bv = -DBL_MAX;
+        int bi = n;
+        for (int i = tid(); i < n; i += WG) {
+            const double d = a[i + (int64_t)i * n];
+            if (s_live[i] && d > bv) {
+                bv = d;
+                bi = i;
+            }
+        }
+        const double best = wg_max(bv, s_red);
+        const int piv = (int)(-wg_max(-(double)(bv == best ? bi : n), s_red));   // lowest index of the maximum
+        if (!(best > tol)) break;
+        const double rs = 1.0 / sqrt(best);
+        for (int i = tid(); i < n; i += WG) {
+            const double v = s_live[i] ? a[i + (int64_t)piv * n] * rs : 0.0;
+            s_g[i] = v;
+            g[(int64_t)k * n + i] = v;
+        }
+        __syncthreads();
+        for (int idx = tid(); idx < n * n; idx += WG) {
+            const int i = idx % n, j = idx / n;
+            if (s_live[i] && s_live[j]) a[idx] -= s_g[i] * s_g[j];
+        }
+        __syncthreads();
+        if (tid() == 0) s_live[piv] = 0;
+        __syncthreads();
+    }
+    for (int64_t idx = (int64_t)k * n + tid(); idx < (int64_t)n * n; idx += WG) g[idx] = 0.0;
+    double rmax = 0.0, dneg = 0.0;
+    for (int idx = tid(); idx < n * n; idx += WG) {
+        const int i = idx % n, j = idx / n;
+        if (s_live[i] && s_live[j]) {
+            rmax = fmax(rmax, fabs(a[idx]));
+            if (i == j) dneg = fmax(dneg, -a[idx]);
+        }
+    }
+    rmax = wg_max(rmax, s_red);
+    dneg = wg_max(dneg, s_red);
+    const double chk = fmax(tol, spsd_tol * dmax);
+    if (tid() == 0) {
+        ranks[e] = k;
+        status[e] = (dneg > spsd_tol * dmax || rmax > 2.0 * chk) ? 2 : 0;
+    }
+}
+
 // ====================================================================== assembly into CSR
 
 // Assembly A = sum_T R_T^T A_T R_T into a CSR pattern that contains every
@@ -864,6 +961,14 @@ void launch_elem_eig(int64_t n_elem, const int64_t* elem_ptr, const int64_t* blk
     if (n_elem <= 0) return;
     hipLaunchKernelGGL(k_elem_eig, dim3((unsigned)n_elem), dim3(WG), 0, st, elem_ptr, blk_off, blocks, G, ranks, status,
                        scratch, scratch_stride, rank_rtol, spsd_tol);
+}
+
+void launch_elem_pchol(int64_t n_elem, const int64_t* elem_ptr, const int64_t* blk_off, const double* blocks,
+                       double* G, int32_t* ranks, int32_t* status, double* scratch, int64_t scratch_stride,
+                       double rank_rtol, double spsd_tol, hipStream_t st) {
+    if (n_elem <= 0) return;
+    hipLaunchKernelGGL(k_elem_pchol, dim3((unsigned)n_elem), dim3(WG), 0, st, elem_ptr, blk_off, blocks, G, ranks,
+                       status, scratch, scratch_stride, rank_rtol, spsd_tol);
 }
 
 void launch_assemble_rows(int64_t n, const int64_t* d2e_ptr, const int32_t* d2e_elem, const int32_t* d2e_loc,

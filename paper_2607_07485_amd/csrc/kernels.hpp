@@ -80,6 +80,9 @@ void launch_elem_eig(int64_t n_elem, const int64_t* elem_ptr, const int64_t* blk
 // CSR values += sum_T f_T R_T^T A_T R_T (f = factor, NULL = 1); d2e lists the
 // (element, local index) pairs of every DOF, elements ascending; wave_rows: one
 // wave per row (long element rows of coarse levels), same summation order
+void launch_elem_pchol(int64_t n_elem, const int64_t* elem_ptr, const int64_t* blk_off, const double* blocks,
+                       double* G, int32_t* ranks, int32_t* status, double* scratch, int64_t scratch_stride,
+                       double rank_rtol, double spsd_tol, hipStream_t st);
 void launch_assemble_rows(int64_t n, const int64_t* d2e_ptr, const int32_t* d2e_elem, const int32_t* d2e_loc,
                           const int64_t* elem_ptr, const int32_t* elem_dofs, const int64_t* blk_off,
                           const double* blocks, const double* factor, const int64_t* rowptr, const int32_t* col,

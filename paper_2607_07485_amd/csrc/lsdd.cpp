@@ -1742,7 +1742,8 @@ lsdd_hierarchy* build(ElemList el0, const double* blocks, bool blocks_on_device,
     if (prm) h->prm = *prm;
     const lsdd_params& P = h->prm;
     if (P.max_levels < 1 || P.precision < 0 || P.precision > 1 || P.tau_const <= 0 || P.rtol <= 0 || P.max_iter < 1 ||
-        P.closure < 0 || P.closure > 1 || !(P.closure_tol >= 0) || P.smoother < 0 || P.smoother > 2)
+        P.closure < 0 || P.closure > 1 || !(P.closure_tol >= 0) || P.smoother < 0 || P.smoother > 2 ||
+        P.elem_factor < 0 || P.elem_factor > 1)
         throw Error(LSDD_E_INVAL, "invalid parameters");
     h->st = (hipStream_t)stream;
     double t0 = now_s();
@@ -1799,8 +1800,12 @@ lsdd_hierarchy* build(ElemList el0, const double* blocks, bool blocks_on_device,
         double* scratch = ar.alloc<double>(chunk * stride);
         for (int64_t e0 = 0; e0 < ne; e0 += chunk) {
             int64_t cnt = std::min(chunk, ne - e0);
-            launch_elem_eig(cnt, lv->d_elem_ptr + e0, lv->d_blk_off + e0, lv->d_blocks, lv->d_G, d_ranks + e0,
-                            d_status + e0, scratch, stride, P.rank_rtol, P.spsd_tol, h->st);
+            if (P.elem_factor == 1)
+                launch_elem_pchol(cnt, lv->d_elem_ptr + e0, lv->d_blk_off + e0, lv->d_blocks, lv->d_G,
+                                  d_ranks + e0, d_status + e0, scratch, stride, P.rank_rtol, P.spsd_tol, h->st);
+            else
+                launch_elem_eig(cnt, lv->d_elem_ptr + e0, lv->d_blk_off + e0, lv->d_blocks, lv->d_G, d_ranks + e0,
+                                d_status + e0, scratch, stride, P.rank_rtol, P.spsd_tol, h->st);
         }
         HIPCHK(hipGetLastError());
         std::vector<int32_t> status = download(d_status, ne, h->st);
