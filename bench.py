@@ -47,14 +47,18 @@ SMOOTHER = 0          # set from --smoother
 # HBM bytes per launch of the dominant solve kernel, from rocprofv3 FETCH_SIZE and WRITE_SIZE
 # runs of this bench (FP64 cycle, 128 x 128; average over the 220 launches of one traced solve)
 # scaled by a 1 GiB device-copy calibration (read factor 2.0, write factor 1.0).  Valid only for
-# the kernel source these counters were taken on.
-TRAFFIC = {("sub_symv", "graddiv_rtcf3_128x128", "f64"): ("9968a8970904d0ba", 2.501e8)}
+# the kernel source these counters were taken on: the hash covers the text of the k_sub_symv
+# template in kernels.hip and the partial-sum layout header symv.hpp.
+TRAFFIC = {("sub_symv", "graddiv_rtcf3_128x128", "f64"): ("4c9bdb898bf5b4ea", 2.501e8)}
 
 
 def _kernels_hash():
     import hashlib
-    path = os.path.join(ROOT, "paper_2607_07485_amd", "csrc", "kernels.hip")
-    return hashlib.sha256(open(path, "rb").read()).hexdigest()[:16]
+    csrc = os.path.join(ROOT, "paper_2607_07485_amd", "csrc")
+    src = open(os.path.join(csrc, "kernels.hip")).read()
+    i = src.index("__global__ void __launch_bounds__(WG) k_sub_symv(")
+    text = src[src.rindex("template", 0, i):src.index("\n}\n", i) + 3]
+    return hashlib.sha256((text + open(os.path.join(csrc, "symv.hpp")).read()).encode()).hexdigest()[:16]
 
 
 def _params(P, **kw):
