@@ -291,6 +291,35 @@ def run_closure_table(a, torch, P, fegen, dev):
     print(json.dumps(out))
 
 
+def run_setup_only(a, torch, P, fegen, dev):
+    """One hierarchy build of the grad-div or Q2-hex workload (after a small warm-up build
+    that loads the code objects), for profiling the setup kernels."""
+    if a.workload == "q2grad":
+        N = a.N if a.N != 128 else 24
+        theta = np.exp(0.5 * np.random.default_rng(0).standard_normal(N ** 3))
+        prob = fegen.elasticity_q2hex(N, nu=0.3, theta=theta)
+        prm = _params(P, max_levels=3, agg_passes=1, agg_passes_coarse=1)
+        warm = fegen.elasticity_q2hex(2, nu=0.3)
+        name = f"elasticity_q2hex_{N}cubed"
+    elif a.workload == "graddiv":
+        prob, _ = fegen.graddiv_hdiv(N=a.N)
+        prm = _params(P)
+        warm = fegen.graddiv_hdiv(N=4)[0]
+        name = f"graddiv_rtcf3_{a.N}x{a.N}"
+    else:
+        raise SystemExit("--setup-only supports --workload graddiv and q2grad")
+    P.Hierarchy.setup_problem(warm, prm).close()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    h = P.Hierarchy.setup_problem(prob, prm)
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+    info = h.info()
+    h.close()
+    print(json.dumps({"metric": "setup_s", "value": setup_s, "unit": "s", "higher_is_better": False,
+                      "config": {"workload": name, "n_dofs": prob.n, "levels": info["n"]}}))
+
+
 def run_q2grad(a, torch, P, fegen, dev):
     """Q2 hex elasticity on N^3 (default 24^3), theta ~ lognormal(0, 0.5); compliance J = b^T u and its
     gradient through the autograd Function (adjoint solve on the same hierarchy), checked by central
@@ -376,6 +405,9 @@ def main():
     ap.add_argument("--workload", choices=["graddiv", "batch", "q2grad", "h2", "closure_table"], default="graddiv")
     ap.add_argument("--smoother", choices=list(SMOOTHERS), default="ms",
                     help="block Schwarz smoother: multiplicative (default), restricted additive, block Jacobi")
+    ap.add_argument("--setup-only", action="store_true",
+                    help="only build the hierarchy of the workload (graddiv or q2grad) once and report setup_s "
+                         "(for profiling the setup kernels)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a device copy of 1 GiB five times (HBM counter calibration for profiling)")
     a = ap.parse_args()
@@ -405,6 +437,8 @@ def main():
     # a stream of our own (default priority), so the PCG iteration can run as captured HIP graphs
     stream = torch.cuda.Stream()
     with torch.cuda.stream(stream):
+        if a.setup_only:
+            return run_setup_only(a, torch, P, fegen, dev)
         if a.workload == "batch":
             return run_batch(a, torch, P, fegen, dev)
         if a.workload == "q2grad":
