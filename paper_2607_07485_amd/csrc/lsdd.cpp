@@ -715,14 +715,14 @@ std::unique_ptr<Level> coarsen(lsdd_hierarchy* h, Level& lv, const int32_t* agg_
 
     // ---- batched local problems (workspace bounded); every dense step runs as
     // tiled jobs of all aggregates of the batch at once
-    // bytes of workspace per batch: half of the free device memory, at most 32 GiB and
+    // bytes of workspace per batch: half of the free device memory, at most 96 GiB and
     // at least 2 GiB.  The arithmetic of an aggregate does not depend on its batch;
     // larger batches share the per-column launches of the blocked eigensolver
     int64_t budget = int64_t(2) << 30;
     {
         size_t free_b = 0, total_b = 0;
         if (hipMemGetInfo(&free_b, &total_b) == hipSuccess)
-            budget = std::max<int64_t>(budget, std::min<int64_t>(int64_t(32) << 30, (int64_t)(free_b / 2)));
+            budget = std::max<int64_t>(budget, std::min<int64_t>(int64_t(96) << 30, (int64_t)(free_b / 2)));
     }
     vlog("level %d: host graph work %.3f s", lv.level, now_s() - tc0);
     double tl0 = now_s();
