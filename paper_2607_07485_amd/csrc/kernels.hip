@@ -603,21 +603,24 @@ __global__ void __launch_bounds__(WG) k_csr_resid_rows(int64_t nrows, const int3
         T s = 0;
         if (!x_zero && p >= 0) {
             // up to 4 entries per lane in flight: all column indices, then all
-            // gathers, then the products (two dependent loads per entry)
-            const int64_t q1 = rowptr[p + 1];
+            // gathers, then the products (two dependent loads per entry).  The
+            // loads carry no lane condition (a slot past the row's end re-reads its
+            // last entry, same cache line, and contributes zero), so they are all
+            // issued before the first wait.
+            const int64_t q1 = rowptr[p + 1], qlast = q1 - 1;
             for (int64_t q0 = rowptr[p] + lane; q0 < q1; q0 += 4 * L) {
                 int32_t c[4];
                 T v[4], xv[4];
 #pragma unroll
                 for (int u = 0; u < 4; ++u) {
-                    const int64_t q = q0 + u * L;
-                    c[u] = q < q1 ? __builtin_nontemporal_load(col + q) : 0;
-                    v[u] = q < q1 ? __builtin_nontemporal_load(val + q) : (T)0;
+                    const int64_t q = min(q0 + u * L, qlast);
+                    c[u] = __builtin_nontemporal_load(col + q);
+                    v[u] = __builtin_nontemporal_load(val + q);
                 }
 #pragma unroll
                 for (int u = 0; u < 4; ++u) xv[u] = x[c[u]];
 #pragma unroll
-                for (int u = 0; u < 4; ++u) s += v[u] * xv[u];
+                for (int u = 0; u < 4; ++u) s += (q0 + u * L < q1 ? v[u] : (T)0) * xv[u];
             }
         }
         for (int off = L / 2; off > 0; off >>= 1) s += __shfl_xor(s, off, L);
@@ -632,15 +635,24 @@ __global__ void __launch_bounds__(WG) k_csr_spmv(int64_t n, const int64_t* rowpt
     const int lane = tid() & (L - 1);
     const int64_t stride = (int64_t)gridDim.x * (WG / L);
     for (int64_t p = ((int64_t)blockIdx.x * WG + tid()) / L; p < n; p += stride) {
-        const int64_t q1 = rowptr[p + 1];
-        int64_t q = rowptr[p] + lane;
-        T s = 0, s1 = 0;
-        for (; q + L < q1; q += 2 * L) {
-            s += __builtin_nontemporal_load(val + q) * x[__builtin_nontemporal_load(col + q)];
-            s1 += __builtin_nontemporal_load(val + q + L) * x[__builtin_nontemporal_load(col + q + L)];
+        // as in k_csr_resid_rows: 4 entries per lane in flight, loads without lane
+        // conditions (slots past the row's end re-read its last entry and add zero)
+        const int64_t q1 = rowptr[p + 1], qlast = q1 - 1;
+        T s = 0;
+        for (int64_t q0 = rowptr[p] + lane; q0 < q1; q0 += 4 * L) {
+            int32_t c[4];
+            T v[4], xv[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int64_t q = min(q0 + u * L, qlast);
+                c[u] = __builtin_nontemporal_load(col + q);
+                v[u] = __builtin_nontemporal_load(val + q);
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) xv[u] = x[c[u]];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) s += (q0 + u * L < q1 ? v[u] : (T)0) * xv[u];
         }
-        if (q < q1) s += __builtin_nontemporal_load(val + q) * x[__builtin_nontemporal_load(col + q)];
-        s += s1;
         for (int off = L / 2; off > 0; off >>= 1) s += __shfl_xor(s, off, L);
         if (lane == 0) y[p] = r_minus ? r_minus[p] - s : s;
     }
@@ -779,13 +791,12 @@ __global__ void __launch_bounds__(WG) k_sub_finalize(int64_t r0, int64_t r1, con
         const T* colpart = scr + scr_off[s] + symv_rowpart_off(nt, chl) * 64 + l;
         const int nch = (J + chl) / chl;
         const int K = nch + (nt - 1 - J);
+        // one load per partial, its address chosen without a branch so that the
+        // unrolled loads are all in flight before the first wait
+#pragma unroll 4
         for (int k = j; k < K; k += FL) {
-            if (k < nch) {
-                y += part[(int64_t)k * 64];
-            } else {
-                const int64_t I = J + 1 + (k - nch);
-                y += colpart[(I * (I - 1) / 2 + J) * 64];
-            }
+            const int64_t I = J + 1 + (k - nch);
+            y += *(k < nch ? part + (int64_t)k * 64 : colpart + (I * (I - 1) / 2 + J) * 64);
         }
     }
     s_y[j][dl] = y;
