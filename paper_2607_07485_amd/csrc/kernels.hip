@@ -875,13 +875,24 @@ __global__ void __launch_bounds__(WG) k_restrict(const int32_t* items, const int
         __syncthreads();
         for (int a = tid(); a < cn; a += WG) s_t[a] = t[agg_dofs[a0 + c0 + a]];
         __syncthreads();
+        // the wave's 4 columns x 4 rows per lane in flight at once; out-of-range
+        // columns and rows re-read an in-range entry and contribute zero
+        const T* col[4];
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int s = s0 + w + 4 * i;
-            if (s < kk) {
-                const T* col = z + (int64_t)s * nw + c0;
-                for (int a = lane; a < cn; a += 64) acc[i] += col[a] * s_t[a];
+        for (int i = 0; i < 4; ++i) col[i] = z + (int64_t)min(s0 + w + 4 * i, kk - 1) * nw + c0;
+        for (int a = lane; a < cn; a += 256) {
+            T zv[4][4], tv[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int aa = min(a + 64 * u, cn - 1);
+                tv[u] = (a + 64 * u < cn) ? s_t[aa] : (T)0;
+#pragma unroll
+                for (int i = 0; i < 4; ++i) zv[i][u] = col[i][aa];
             }
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int u = 0; u < 4; ++u) acc[i] += zv[i][u] * tv[u];
         }
     }
 #pragma unroll
@@ -914,12 +925,15 @@ __global__ void __launch_bounds__(WG) k_prolong(const int32_t* items, const int6
         for (int s = tid(); s < cn; s += WG) s_e[s] = ec[coff[ag] + c0 + s];
         __syncthreads();
         if (a < nw) {
-            int s = 0;
-            for (; s + 1 < cn; s += 2) {
-                acc0 += z[(int64_t)(c0 + s) * nw] * s_e[s];
-                acc1 += z[(int64_t)(c0 + s + 1) * nw] * s_e[s + 1];
+            // 4 modes per step in flight; modes past the end re-read the last one
+            // and contribute zero
+            for (int s = 0; s < cn; s += 4) {
+                T zv[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) zv[u] = z[(int64_t)(c0 + min(s + u, cn - 1)) * nw];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) (u & 1 ? acc1 : acc0) += (s + u < cn ? zv[u] : (T)0) * s_e[min(s + u, cn - 1)];
             }
-            if (s < cn) acc0 += z[(int64_t)(c0 + s) * nw] * s_e[s];
         }
     }
     if (a < nw) x[agg_dofs[a0 + a]] += acc0 + acc1;
