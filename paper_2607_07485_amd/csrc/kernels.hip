@@ -1112,12 +1112,19 @@ template <typename T>
 void launch_csr_resid_rows(int64_t nrows, const int32_t* rows, const int64_t* rowptr, const int32_t* col, const T* val,
                            const T* x, const T* r, T* out, bool x_zero, int lanes, hipStream_t st) {
     if (nrows <= 0) return;
+    const int xz = x_zero ? 1 : 0;
     if (lanes >= 64)
         hipLaunchKernelGGL((k_csr_resid_rows<T, 64>), dim3(grid_for(nrows * 64)), dim3(WG), 0, st, nrows, rows, rowptr,
-                           col, val, x, r, out, x_zero ? 1 : 0);
-    else
+                           col, val, x, r, out, xz);
+    else if (lanes >= 32)
+        hipLaunchKernelGGL((k_csr_resid_rows<T, 32>), dim3(grid_for(nrows * 32)), dim3(WG), 0, st, nrows, rows, rowptr,
+                           col, val, x, r, out, xz);
+    else if (lanes >= 16)
         hipLaunchKernelGGL((k_csr_resid_rows<T, 16>), dim3(grid_for(nrows * 16)), dim3(WG), 0, st, nrows, rows, rowptr,
-                           col, val, x, r, out, x_zero ? 1 : 0);
+                           col, val, x, r, out, xz);
+    else
+        hipLaunchKernelGGL((k_csr_resid_rows<T, 8>), dim3(grid_for(nrows * 8)), dim3(WG), 0, st, nrows, rows, rowptr,
+                           col, val, x, r, out, xz);
 }
 template <typename T>
 void launch_csr_spmv(int64_t n, const int64_t* rowptr, const int32_t* col, const T* val, const T* x, T* y,
@@ -1126,8 +1133,14 @@ void launch_csr_spmv(int64_t n, const int64_t* rowptr, const int32_t* col, const
     if (lanes >= 64)
         hipLaunchKernelGGL((k_csr_spmv<T, 64>), dim3(grid_for(n * 64)), dim3(WG), 0, st, n, rowptr, col, val, x, y,
                            r_minus);
-    else
+    else if (lanes >= 32)
+        hipLaunchKernelGGL((k_csr_spmv<T, 32>), dim3(grid_for(n * 32)), dim3(WG), 0, st, n, rowptr, col, val, x, y,
+                           r_minus);
+    else if (lanes >= 16)
         hipLaunchKernelGGL((k_csr_spmv<T, 16>), dim3(grid_for(n * 16)), dim3(WG), 0, st, n, rowptr, col, val, x, y,
+                           r_minus);
+    else
+        hipLaunchKernelGGL((k_csr_spmv<T, 8>), dim3(grid_for(n * 8)), dim3(WG), 0, st, n, rowptr, col, val, x, y,
                            r_minus);
 }
 template <typename T>

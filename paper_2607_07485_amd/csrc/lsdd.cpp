@@ -153,7 +153,7 @@ struct Level {
     double* d_blocks = nullptr;
     // assembled operator
     Csr pat;
-    int lanes = 16;                    // CSR lanes per row, single vectors (16 or 64)
+    int lanes = 16;                    // CSR lanes per row, single vectors (8, 16, 32 or 64)
     int lanes_b = 32;                  // CSR lanes per row, blocks of NRB vectors (16, 32 or 64)
     int chl = SUB_MAX_CHUNK;           // tiles per subdomain-kernel work item
     int fl = 8;                        // threads per DOF in the subdomain finalize
@@ -1693,7 +1693,7 @@ void autotune_levels(lsdd_hierarchy* h) {
         launch_zero<T>(lv.n * NR, v.r, h->st);
         launch_zero<T>(lv.n * NR, v.x, h->st);
         int& lanes = NR > 1 ? lv.lanes_b : lv.lanes;
-        const std::vector<int> lane_c = NR > 1 ? std::vector<int>{16, 32, 64} : std::vector<int>{16, 64};
+        const std::vector<int> lane_c = NR > 1 ? std::vector<int>{16, 32, 64} : std::vector<int>{8, 16, 32, 64};
         double best = 1e300;
         int pick = lanes;
         for (int L : lane_c) {
