@@ -400,7 +400,7 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--N", type=int, default=128)
-    ap.add_argument("--cpu-sample", type=int, default=32)
+    ap.add_argument("--cpu-sample", type=int, default=48)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--workload", choices=["graddiv", "batch", "q2grad", "h2", "closure_table"], default="graddiv")
     ap.add_argument("--smoother", choices=list(SMOOTHERS), default="ms",
