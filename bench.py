@@ -89,6 +89,31 @@ def _anorm_err(h, x, x_ref):
     return float(np.sqrt(abs(float((e * Ae).sum())) / float((x_ref * Ax).sum())))
 
 
+def _anorm_err_max(h, X, X_ref, seg_off):
+    """Largest relative A-norm error over the (instance, right-hand side) pairs: A is
+    block diagonal over the instances, so each segment's error is measured alone."""
+    worst = 0.0
+    Xs = X if X.dim() == 2 else X[None]
+    Rs = X_ref if X_ref.dim() == 2 else X_ref[None]
+    for x, xr in zip(Xs, Rs):
+        e = (x - xr).contiguous()
+        Ae, Ar = h.apply(e), h.apply(xr.contiguous())
+        for a, b in zip(seg_off[:-1], seg_off[1:]):
+            num = float((e[a:b] * Ae[a:b]).sum())
+            den = float((xr[a:b] * Ar[a:b]).sum())
+            worst = max(worst, float(np.sqrt(abs(num) / den)) if den > 0 else 0.0)
+    return worst
+
+
+def _reference_solution(h, b):
+    """FP64-cycle PCG to 1e-12 on the same hierarchy (the reference of the A-norm errors)."""
+    h.set_cycle_precision(0)
+    h.set_solve_params(1e-12, 3000)
+    x_ref, _ = h.solve(b, allow_noconv=True)
+    h.set_solve_params(1e-8, 1000)
+    return x_ref
+
+
 def cpu_baseline(N_sample: int):
     """The oracle, as it stands, on the same workload at a bounded size."""
     import fegen
@@ -140,7 +165,7 @@ def run_batch(a, torch, P, fegen, dev):
     setup_s = time.perf_counter() - t0
     info = h.info()
     print(f"[bench] batch setup {setup_s:.2f} s, levels {info['n']}", file=sys.stderr, flush=True)
-    res = {}
+    res, sols = {}, {}
     for prec in (0, 1):
         h.set_cycle_precision(prec)
         h.set_graph(False)
@@ -161,6 +186,7 @@ def run_batch(a, torch, P, fegen, dev):
         torch.cuda.synchronize()
         dt = (time.perf_counter() - t0) / a.steps
         its = [f.iters for f in infs]
+        sols["fp32" if prec else "fp64"] = X.clone()
         res["fp32" if prec else "fp64"] = {"value": n_tot * nrhs / dt, "ms_per_step": dt * 1e3,
                                           "iters_min": min(its), "iters_max": max(its),
                                           "converged": all(f.converged for f in infs), "tuning": tuning}
@@ -168,6 +194,11 @@ def run_batch(a, torch, P, fegen, dev):
               flush=True)
     h.set_graph(False)
     ok = [k for k in ("fp64", "fp32") if res[k].get("converged")]
+    if ok:
+        X_ref = _reference_solution(h, B)
+        seg = h.segments()[1]
+        for k_ in ok:
+            res[k_]["anorm_err_max"] = _anorm_err_max(h, sols[k_], X_ref, seg)
     if not ok:
         h.close()
         print(json.dumps({"metric": METRIC, "value": None, "unit": "DOF/s", "n_gpus": 1, "steps": a.steps,
@@ -211,7 +242,7 @@ def run_h2(a, torch, P, fegen, dev):
     h.set_cycle_precision(0)
     tuning = h.autotune(block=False)
     h.set_graph(True)
-    res = {}
+    res, sols = {}, {}
     for prec in (0, 1):
         h.set_cycle_precision(prec)
         try:
@@ -222,6 +253,7 @@ def run_h2(a, torch, P, fegen, dev):
                 x, inf = h.solve(b, allow_noconv=True)
             torch.cuda.synchronize()
             dt = (time.perf_counter() - t0) / a.steps
+            sols["fp32" if prec else "fp64"] = x.clone()
             res["fp32" if prec else "fp64"] = {"value": prob.n / dt, "ms_per_step": dt * 1e3, "iters": inf[0].iters,
                                               "converged": bool(inf[0].converged)}
         except P.LsddError as ex:
@@ -229,6 +261,10 @@ def run_h2(a, torch, P, fegen, dev):
         print(f"[bench] h2 prec {prec}: {res['fp32' if prec else 'fp64']}", file=sys.stderr, flush=True)
     h.set_cycle_precision(0)
     h.set_graph(False)
+    x_ref = _reference_solution(h, b)
+    for k_ in ("fp64", "fp32"):
+        if res[k_].get("converged"):
+            res[k_]["anorm_err"] = _anorm_err(h, sols[k_], x_ref)
     kernels, (dname, d) = _trace_dominant(h, torch, lambda: h.solve(b))
     h.close()
     ok = [k for k in ("fp64", "fp32") if res[k].get("converged")]
@@ -349,7 +385,7 @@ def run_q2grad(a, torch, P, fegen, dev):
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t0
     info = h.info()
-    res = {}
+    res, sols = {}, {}
     for prec in (0, 1):
         h.set_cycle_precision(prec)
         x, inf = h.solve(b)
@@ -359,7 +395,11 @@ def run_q2grad(a, torch, P, fegen, dev):
             x, inf = h.solve(b)
         torch.cuda.synchronize()
         dt = (time.perf_counter() - t0) / a.steps
+        sols["fp32" if prec else "fp64"] = x.clone()
         res["fp32" if prec else "fp64"] = {"value": prob.n / dt, "ms_per_step": dt * 1e3, "iters": inf[0].iters}
+    x_ref = _reference_solution(h, b)
+    for k_ in ("fp64", "fp32"):
+        res[k_]["anorm_err"] = _anorm_err(h, sols[k_], x_ref)
     h.set_cycle_precision(0)
     h.set_solve_params(1e-11, 1000)
     errs = []
