@@ -257,7 +257,7 @@ lsdd_status lsdd_segments(const lsdd_hierarchy* h, int32_t* n_seg, int64_t* seg_
 lsdd_status lsdd_level_segments(const lsdd_hierarchy* h, int32_t level, int64_t* inst_off, int32_t* terminal);
 
 /* Autotuner: on this hierarchy, time every candidate of the per-level launch
- * shapes with HIP events (three runs after a warm-up, on the level's own
+ * shapes with HIP events (the fastest of five runs after a warm-up, on the level's own
  * operators) and keep the fastest: CSR lanes per row of the residual kernel (8, 16,
  * 32 or 64 for single vectors; 16, 32 or 64 for blocks), tiles per work item of the
  * tiled subdomain product of the large overlaps (2, 4 or 8) and threads per DOF of

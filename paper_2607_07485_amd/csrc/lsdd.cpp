@@ -1663,20 +1663,26 @@ void set_chunk(lsdd_hierarchy* h, Level& lv, int chl) {
 }
 
 template <class F>
-double time_ms(lsdd_hierarchy* h, F&& fn, int reps = 3) {
+double time_ms(lsdd_hierarchy* h, F&& fn, int reps = 5) {
+    // fastest of `reps` separately timed runs after a warm-up: the minimum is the
+    // least noisy estimate of a candidate's own cost
     fn();
     hipEvent_t a, b;
     HIPCHK(hipEventCreate(&a));
     HIPCHK(hipEventCreate(&b));
-    HIPCHK(hipEventRecord(a, h->st));
-    for (int r = 0; r < reps; ++r) fn();
-    HIPCHK(hipEventRecord(b, h->st));
-    HIPCHK(hipEventSynchronize(b));
-    float ms = 0.0f;
-    HIPCHK(hipEventElapsedTime(&ms, a, b));
+    float best = 3.0e38f;
+    for (int r = 0; r < reps; ++r) {
+        HIPCHK(hipEventRecord(a, h->st));
+        fn();
+        HIPCHK(hipEventRecord(b, h->st));
+        HIPCHK(hipEventSynchronize(b));
+        float ms = 0.0f;
+        HIPCHK(hipEventElapsedTime(&ms, a, b));
+        best = std::min(best, ms);
+    }
     (void)hipEventDestroy(a);
     (void)hipEventDestroy(b);
-    return ms / reps;
+    return best;
 }
 
 // Time the candidates of every per-level launch shape on the level's own data
