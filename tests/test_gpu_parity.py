@@ -444,3 +444,77 @@ def test_pivoted_cholesky_rejects_an_indefinite_block(dev):
         P.Hierarchy.setup_elements(prob.n, prob.elem_ptr, prob.elem_dofs, bad.ravel(), prob.node_of_dof,
                                    prob.agg_of_dof, P.Params.default(elem_factor=1, **ELAST_KW))
     assert ei.value.code == 2 and "element 4" in str(ei.value)
+
+
+def _rows_problem(prob, G0):
+    """The cover of a stacked Gram factor: one member per row of G, supported on its
+    element's DOFs, with block g g^T."""
+    from fegen.common import Problem
+    dofs, blocks, ptr = [], [], [0]
+    rp, cols, vals = [0], [], []
+    for e in range(prob.n_elem):
+        S, _ = prob.element(e)
+        for g in G0[e]:
+            dofs.append(np.asarray(S, dtype=np.int32))
+            blocks.append(np.outer(g, g).ravel())
+            ptr.append(ptr[-1] + len(S))
+            cols.append(np.asarray(S, dtype=np.int32))
+            vals.append(g)
+            rp.append(rp[-1] + len(S))
+    P = Problem(n=prob.n, elem_ptr=np.array(ptr, dtype=np.int64), elem_dofs=np.concatenate(dofs),
+                blocks=np.concatenate(blocks), node_of_dof=prob.node_of_dof, agg_of_dof=prob.agg_of_dof)
+    return P, np.array(rp, dtype=np.int64), np.concatenate(cols), np.concatenate(vals)
+
+
+def test_black_box_csr_gram_factor_parity(dev):
+    """lsdd_setup_gram_csr (Sec. 2: A = G^T G from a sparse G, every row its own cover
+    member): the hierarchy built from the stacked element factors of the small elasticity
+    problem matches the oracle run on the same row cover (aggregates, k_i bit-exact;
+    spectra, V-cycle and PCG solution 1e-10, iterations +-1)."""
+    P = _lsdd()
+    prob, b = fegen.elasticity_small(N=16)
+    G0 = oracle.setup(prob, oracle.Params(max_levels=1)).G0
+    rows, rp, col, val = _rows_problem(prob, G0)
+    kw = dict(max_levels=2, modes_fixed=4)
+    h_or = oracle.setup(rows, oracle.Params(**kw))
+    h = P.Hierarchy.setup_gram_csr(len(rp) - 1, prob.n, rp, col, val, prob.node_of_dof, prob.agg_of_dof,
+                                   P.Params.default(**kw))
+    try:
+        assert h.info()["n"] == [lv.n for lv in h_or.levels]
+        ex, lv = h.export_level(0), h_or.levels[0]
+        assert np.array_equal(ex["agg_of_dof"], lv.agg_of_dof)
+        assert np.array_equal(ex["k"], lv.k)
+        assert np.array_equal(ex["omega_sizes"], [len(o) for o in lv.omegas])
+        assert np.abs(ex["mu"] - np.concatenate(lv.mu)).max() <= 1e-10
+        A_gpu = _csr(ex)
+        assert abs(A_gpu - lv.A).max() <= 1e-13 * abs(lv.A).max()
+        r = np.random.default_rng(11).standard_normal(prob.n)
+        z_or = oracle.vcycle(h_or, r)
+        z = h.vcycle(torch.from_numpy(r).to(dev)).cpu().numpy()
+        assert np.linalg.norm(z - z_or) <= 1e-10 * np.linalg.norm(z_or)
+        x_or, inf_or = oracle.pcg(h_or, b)
+        x, infos = h.solve(torch.from_numpy(b).to(dev))
+        assert abs(infos[0].iters - inf_or.iters) <= 1
+        assert np.linalg.norm(x.cpu().numpy() - x_or) <= 1e-10 * np.linalg.norm(x_or)
+    finally:
+        h.close()
+
+
+@pytest.mark.parametrize("case", ["one_level", "no_modes"])
+def test_single_level_hierarchies(dev, case):
+    """Degenerate hierarchies: max_levels = 1, and a cut so strict that no aggregate
+    keeps a mode (the level becomes the coarsest).  Either way the cycle is the dense
+    direct solve: PCG converges in one iteration to the oracle's solution."""
+    P = _lsdd()
+    rng = np.random.default_rng(2)
+    prob = fegen.graddiv_rtcf3(6, kappa=np.exp(rng.standard_normal(36)), beta=1.0)
+    b = rng.standard_normal(prob.n)
+    kw = dict(max_levels=1) if case == "one_level" else dict(max_levels=3, tau_const=1e12, agg_passes=1)
+    h_or = oracle.setup(prob, oracle.Params(**kw))
+    assert len(h_or.levels) == 1
+    with P.Hierarchy.setup_problem(prob, P.Params.default(**kw)) as h:
+        assert h.info()["levels"] == 1
+        x, infos = h.solve(torch.from_numpy(b).to(dev))
+        x_or, inf_or = oracle.pcg(h_or, b)
+        assert infos[0].iters == inf_or.iters == 1
+        assert np.linalg.norm(x.cpu().numpy() - x_or) <= 1e-10 * np.linalg.norm(x_or)
