@@ -5,10 +5,12 @@
 // inverse or interpolation entry read from HBM is used for all of them: the
 // cycle's bytes per right-hand side drop by up to 8x against separate solves.
 #include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
 
 #include <cmath>
 
 #include "blk.hpp"
+#include "kernels.hpp"
 #include "dense.hpp"
 #include "symv.hpp"
 
@@ -592,8 +594,13 @@ template <typename T>
 void launch_sub_symv_b(int64_t n_items, const int32_t* items, const int64_t* sub_off, const int64_t* tp_off,
                        const T* tiles, const T* rloc, const int64_t* scr_off, T* scr, int chl, hipStream_t st) {
     if (n_items <= 0) return;
-    hipLaunchKernelGGL(k_sub_symv_b<T>, dim3((unsigned)n_items), dim3(WG), 0, st, items, sub_off, tp_off, tiles, rloc,
-                       scr_off, scr, chl);
+    hipEvent_t e0, e1;
+    if (take_launch_events(&e0, &e1))
+        hipExtLaunchKernelGGL(k_sub_symv_b<T>, dim3((unsigned)n_items), dim3(WG), 0, st, e0, e1, 0, items, sub_off,
+                              tp_off, tiles, rloc, scr_off, scr, chl);
+    else
+        hipLaunchKernelGGL(k_sub_symv_b<T>, dim3((unsigned)n_items), dim3(WG), 0, st, items, sub_off, tp_off, tiles,
+                           rloc, scr_off, scr, chl);
 }
 
 template <typename T>

@@ -8,6 +8,7 @@
 // explicit subdomain inverses, block-diagonal transfer, dense coarsest solve,
 // PCG vector kernels.
 #include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
 
 #include <algorithm>
 #include <cfloat>
@@ -20,6 +21,23 @@
 #include "symv.hpp"
 
 namespace lsdd {
+
+// Kernel-bracketing timing events for the next subdomain-product launch (per host
+// thread): the launch records them at the kernel's own start and end.
+namespace {
+thread_local hipEvent_t t_ev_start = nullptr, t_ev_stop = nullptr;
+}
+void set_launch_events(hipEvent_t start, hipEvent_t stop) {
+    t_ev_start = start;
+    t_ev_stop = stop;
+}
+bool take_launch_events(hipEvent_t* start, hipEvent_t* stop) {
+    if (!t_ev_start) return false;
+    *start = t_ev_start;
+    *stop = t_ev_stop;
+    t_ev_start = t_ev_stop = nullptr;
+    return true;
+}
 
 namespace {
 
@@ -1147,8 +1165,13 @@ template <typename T>
 void launch_sub_symv(int64_t n_items, const int32_t* items, const int64_t* sub_off, const int64_t* tp_off,
                      const T* tiles, const T* rloc, const int64_t* scr_off, T* scr, int chl, hipStream_t st) {
     if (n_items <= 0) return;
-    hipLaunchKernelGGL(k_sub_symv<T>, dim3((unsigned)n_items), dim3(WG), 0, st, items, sub_off, tp_off, tiles, rloc,
-                       scr_off, scr, chl);
+    hipEvent_t e0, e1;
+    if (take_launch_events(&e0, &e1))
+        hipExtLaunchKernelGGL(k_sub_symv<T>, dim3((unsigned)n_items), dim3(WG), 0, st, e0, e1, 0, items, sub_off,
+                              tp_off, tiles, rloc, scr_off, scr, chl);
+    else
+        hipLaunchKernelGGL(k_sub_symv<T>, dim3((unsigned)n_items), dim3(WG), 0, st, items, sub_off, tp_off, tiles,
+                           rloc, scr_off, scr, chl);
 }
 template <typename T>
 void launch_sub_finalize(int64_t r0, int64_t r1, const int32_t* pos_sub, const int64_t* sub_off,

@@ -184,6 +184,11 @@ void launch_update_xr(int64_t n, const double* s_num, const double* s_den, const
 void launch_update_p(int64_t n, const double* s_num, const double* s_den, const double* z, double* p,
                      hipStream_t st);
 void launch_copy(int64_t n, const double* a, double* b, hipStream_t st);
+// Timing events the next launch of the subdomain product records at the kernel's own
+// start and end (hipExtLaunchKernel), instead of separate event packets around it;
+// take_launch_events hands them to that launch once.
+void set_launch_events(hipEvent_t start, hipEvent_t stop);
+bool take_launch_events(hipEvent_t* start, hipEvent_t* stop);
 // y += a x
 void launch_axpy(int64_t n, double a, const double* x, double* y, hipStream_t st);
 void launch_check_finite(int64_t n, const double* a, int32_t* flag, hipStream_t st);

@@ -427,9 +427,22 @@ void traced(lsdd_hierarchy* h, const char* name, double bytes, F&& launch) {
         return;
     }
     hipEvent_t a = h->tr.get(), b = h->tr.get();
-    HIPCHK(hipEventRecord(a, h->st));
-    launch();
-    HIPCHK(hipEventRecord(b, h->st));
+    // the subdomain product takes the events into its launch (kernel start and end);
+    // every other class is bracketed by event records on the stream
+    const bool ext = !std::strcmp(name, "sub_symv") || !std::strcmp(name, "coarse_symv");
+    if (ext) {
+        set_launch_events(a, b);
+        launch();
+        hipEvent_t u, v;
+        if (take_launch_events(&u, &v)) {     // nothing was launched: an empty interval
+            HIPCHK(hipEventRecord(a, h->st));
+            HIPCHK(hipEventRecord(b, h->st));
+        }
+    } else {
+        HIPCHK(hipEventRecord(a, h->st));
+        launch();
+        HIPCHK(hipEventRecord(b, h->st));
+    }
     h->tr.pend.push_back(Trace::Pend{h->tr.index(name), a, b, bytes});
 }
 
