@@ -156,7 +156,7 @@ def run_batch(a, torch, P, fegen, dev):
     B_np = np.ascontiguousarray(np.concatenate([bb for _, bb in batch], axis=1))
     n_tot, nrhs = B_np.shape[1], B_np.shape[0]
     B = torch.from_numpy(B_np).to(dev)
-    prm = _params(P, max_levels=3)
+    prm = _params(P, max_levels=a.max_levels or 3)
     P.Hierarchy.setup_batched([fegen.elasticity_q1(4)], prm).close()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -440,6 +440,8 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--N", type=int, default=128)
+    ap.add_argument("--max-levels", type=int, default=None,
+                    help="hierarchy depth cap (default 3)")
     ap.add_argument("--cpu-sample", type=int, default=48)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--workload", choices=["graddiv", "batch", "q2grad", "h2", "closure_table"], default="graddiv")
@@ -493,13 +495,13 @@ def main():
 def run_graddiv(a, torch, P, fegen, dev):
     # load code objects once on a tiny instance so setup timing excludes module loading
     pw, bw = fegen.graddiv_hdiv(N=4)
-    P.Hierarchy.setup_problem(pw, _params(P)).close()
+    P.Hierarchy.setup_problem(pw, _params(P, max_levels=a.max_levels or 3)).close()
 
     prob, b_np = fegen.graddiv_hdiv(N=a.N)
     b = torch.from_numpy(b_np).to(dev)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    h = P.Hierarchy.setup_problem(prob, _params(P))
+    h = P.Hierarchy.setup_problem(prob, _params(P, max_levels=a.max_levels or 3))
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t0
     info = h.info()

@@ -259,7 +259,9 @@ lsdd_status lsdd_level_segments(const lsdd_hierarchy* h, int32_t level, int64_t*
 /* Autotuner: on this hierarchy, time every candidate of the per-level launch
  * shapes with HIP events (the fastest of five runs after a warm-up, on the level's own
  * operators) and keep the fastest: CSR lanes per row of the residual kernel (8, 16,
- * 32 or 64 for single vectors; 16, 32 or 64 for blocks), tiles per work item of the
+ * 32 or 64 for single vectors; for blocks 4, 8 or 16 lanes that each hold all 8
+ * right-hand sides of one nonzero slot, or 32 or 64 lanes split over (slot,
+ * right-hand side)), tiles per work item of the
  * tiled subdomain product of the large overlaps (2, 4 or 8) and threads per DOF of
  * its finalize (8 or 32).  block != 0 tunes the shapes of the 8-right-hand-side
  * blocks, 0 those of single vectors, for the current cycle precision.  The choice

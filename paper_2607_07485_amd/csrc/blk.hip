@@ -50,6 +50,126 @@ __global__ void __launch_bounds__(WG) k_csr_resid_rows_b(int64_t nrows, const in
     }
 }
 
+// L lanes per row (4, 8 or 16); lane = nonzero slot holding all NB right-hand
+// sides: it reads its entries' values and columns once and each gathered row of
+// x with 16-byte loads (two entries in flight; past the row end the index is
+// clamped to the last entry and the value zeroed, so the loads need no branch).
+// The NB sums are reduced over the L lanes by a transposing butterfly (4 + 2 + 1
+// exchanges over 8 lanes leave lane l with right-hand side l; 4 + 2 over 4 lanes
+// leave it with 2l and 2l + 1), then by plain exchanges over the remaining lane
+// bits; the order is fixed.
+template <typename T>
+struct Row16 {
+    using V = double2;
+};
+template <>
+struct Row16<float> {
+    using V = float4;
+};
+
+template <typename T>
+__device__ inline void load_xrow(const T* p, T (&v)[NB]) {
+    using V = typename Row16<T>::V;
+    constexpr int W = 16 / sizeof(T);
+    const V* pv = reinterpret_cast<const V*>(p);
+#pragma unroll
+    for (int u = 0; u < NB / W; ++u) {
+        const V t = pv[u];
+        const T* tt = reinterpret_cast<const T*>(&t);
+#pragma unroll
+        for (int c = 0; c < W; ++c) v[u * W + c] = tt[c];
+    }
+}
+
+template <typename T, int L>
+__device__ inline void slot_row_sums(int64_t q0, int64_t q1, int lane, const int32_t* col, const T* val,
+                                     const T* x, T (&s)[NB]) {
+    const int nit = (int)((q1 - q0 + L - 1) / L);
+    for (int it = 0; it < nit; it += 2) {
+        const int64_t qa = q0 + lane + (int64_t)it * L, qb = qa + L;
+        const int64_t qac = qa < q1 ? qa : q1 - 1, qbc = qb < q1 ? qb : q1 - 1;
+        const T va = val[qac], vb = val[qbc];
+        const int32_t ca = col[qac], cb = col[qbc];
+        T xa[NB], xb[NB];
+        load_xrow(x + (int64_t)ca * NB, xa);
+        load_xrow(x + (int64_t)cb * NB, xb);
+        const T wa = qa < q1 ? va : (T)0, wb = qb < q1 ? vb : (T)0;
+#pragma unroll
+        for (int k = 0; k < NB; ++k) s[k] += wa * xa[k];
+#pragma unroll
+        for (int k = 0; k < NB; ++k) s[k] += wb * xb[k];
+    }
+}
+
+// one butterfly step: lanes paired across lane bit `o` swap halves of their
+// first 2 C values and keep the half selected by that bit
+template <typename T, int L, int C>
+__device__ inline void slot_fold(T (&s)[NB], int lane, int o) {
+    const bool hi = (lane & o) != 0;
+#pragma unroll
+    for (int i = 0; i < C; ++i) {
+        const T send = hi ? s[i] : s[i + C], keep = hi ? s[i + C] : s[i];
+        s[i] = keep + __shfl_xor(send, o, L);
+    }
+}
+
+// B = min(L, NB) lanes split the NB sums: afterwards lane l < B holds right-hand
+// sides (NB / B) l + i in s[i], i < NB / B, summed over all L lanes of the row
+template <typename T, int L>
+__device__ inline void slot_reduce(T (&s)[NB], int lane) {
+    static_assert(NB == 8 && L >= 4 && L <= 64, "butterfly laid out for 8 right-hand sides");
+    constexpr int B = L < NB ? L : NB;
+    slot_fold<T, L, 4>(s, lane, B / 2);
+    slot_fold<T, L, 2>(s, lane, B / 4);
+    if constexpr (B == 8) slot_fold<T, L, 1>(s, lane, 1);
+#pragma unroll
+    for (int off = 8; off < L; off <<= 1) s[0] += __shfl_xor(s[0], off, L);
+}
+
+template <typename T, int L>
+__global__ void __launch_bounds__(WG) k_csr_resid_rows_s(int64_t nrows, const int32_t* rows, const int64_t* rowptr,
+                                                         const int32_t* col, const T* val, const T* x, const T* r,
+                                                         T* out, int x_zero) {
+    const int lane = tid() & (L - 1);
+    const int64_t stride = (int64_t)gridDim.x * (WG / L);
+    for (int64_t t = ((int64_t)blockIdx.x * WG + tid()) / L; t < nrows; t += stride) {
+        const int32_t p = rows[t];   // < 0: masked entry, out = 0
+        T s[NB];
+#pragma unroll
+        for (int k = 0; k < NB; ++k) s[k] = 0;
+        if (!x_zero && p >= 0) slot_row_sums<T, L>(rowptr[p], rowptr[p + 1], lane, col, val, x, s);
+        slot_reduce<T, L>(s, lane);
+        constexpr int PL = L < NB ? NB / L : 1;   // right-hand sides per writing lane
+        if (lane * PL < NB)
+#pragma unroll
+            for (int i = 0; i < PL; ++i) {
+                const int k = lane * PL + i;
+                out[t * NB + k] = p >= 0 ? r[(int64_t)p * NB + k] - s[i] : (T)0;
+            }
+    }
+}
+
+template <typename T, int L>
+__global__ void __launch_bounds__(WG) k_csr_spmv_s(int64_t n, const int64_t* rowptr, const int32_t* col,
+                                                   const T* val, const T* x, T* y, const T* r_minus) {
+    const int lane = tid() & (L - 1);
+    const int64_t stride = (int64_t)gridDim.x * (WG / L);
+    for (int64_t p = ((int64_t)blockIdx.x * WG + tid()) / L; p < n; p += stride) {
+        T s[NB];
+#pragma unroll
+        for (int k = 0; k < NB; ++k) s[k] = 0;
+        slot_row_sums<T, L>(rowptr[p], rowptr[p + 1], lane, col, val, x, s);
+        slot_reduce<T, L>(s, lane);
+        constexpr int PL = L < NB ? NB / L : 1;
+        if (lane * PL < NB)
+#pragma unroll
+            for (int i = 0; i < PL; ++i) {
+                const int k = lane * PL + i;
+                y[p * NB + k] = r_minus ? r_minus[p * NB + k] - s[i] : s[i];
+            }
+    }
+}
+
 template <typename T, int L>
 __global__ void __launch_bounds__(WG) k_csr_spmv_b(int64_t n, const int64_t* rowptr, const int32_t* col,
                                                    const T* val, const T* x, T* y, const T* r_minus) {
@@ -564,14 +684,20 @@ template <typename T>
 void launch_csr_resid_rows_b(int64_t nrows, const int32_t* rows, const int64_t* rowptr, const int32_t* col,
                              const T* val, const T* x, const T* r, T* out, bool x_zero, int lanes, hipStream_t st) {
     if (nrows <= 0) return;
-    if (lanes >= 64)
+    if (lanes <= 4)
+        hipLaunchKernelGGL((k_csr_resid_rows_s<T, 4>), dim3(grid_for(nrows * 4)), dim3(WG), 0, st, nrows, rows,
+                           rowptr, col, val, x, r, out, x_zero ? 1 : 0);
+    else if (lanes <= 8)
+        hipLaunchKernelGGL((k_csr_resid_rows_s<T, 8>), dim3(grid_for(nrows * 8)), dim3(WG), 0, st, nrows, rows,
+                           rowptr, col, val, x, r, out, x_zero ? 1 : 0);
+    else if (lanes <= 16)
+        hipLaunchKernelGGL((k_csr_resid_rows_s<T, 16>), dim3(grid_for(nrows * 16)), dim3(WG), 0, st, nrows, rows,
+                           rowptr, col, val, x, r, out, x_zero ? 1 : 0);
+    else if (lanes >= 64)
         hipLaunchKernelGGL((k_csr_resid_rows_b<T, 64>), dim3(grid_for(nrows * 64)), dim3(WG), 0, st, nrows, rows,
                            rowptr, col, val, x, r, out, x_zero ? 1 : 0);
-    else if (lanes >= 32)
-        hipLaunchKernelGGL((k_csr_resid_rows_b<T, 32>), dim3(grid_for(nrows * 32)), dim3(WG), 0, st, nrows, rows,
-                           rowptr, col, val, x, r, out, x_zero ? 1 : 0);
     else
-        hipLaunchKernelGGL((k_csr_resid_rows_b<T, 16>), dim3(grid_for(nrows * 16)), dim3(WG), 0, st, nrows, rows,
+        hipLaunchKernelGGL((k_csr_resid_rows_b<T, 32>), dim3(grid_for(nrows * 32)), dim3(WG), 0, st, nrows, rows,
                            rowptr, col, val, x, r, out, x_zero ? 1 : 0);
 }
 
@@ -579,14 +705,20 @@ template <typename T>
 void launch_csr_spmv_b(int64_t n, const int64_t* rowptr, const int32_t* col, const T* val, const T* x, T* y,
                        const T* r_minus, int lanes, hipStream_t st) {
     if (n <= 0) return;
-    if (lanes >= 64)
+    if (lanes <= 4)
+        hipLaunchKernelGGL((k_csr_spmv_s<T, 4>), dim3(grid_for(n * 4)), dim3(WG), 0, st, n, rowptr, col, val, x, y,
+                           r_minus);
+    else if (lanes <= 8)
+        hipLaunchKernelGGL((k_csr_spmv_s<T, 8>), dim3(grid_for(n * 8)), dim3(WG), 0, st, n, rowptr, col, val, x, y,
+                           r_minus);
+    else if (lanes <= 16)
+        hipLaunchKernelGGL((k_csr_spmv_s<T, 16>), dim3(grid_for(n * 16)), dim3(WG), 0, st, n, rowptr, col, val, x, y,
+                           r_minus);
+    else if (lanes >= 64)
         hipLaunchKernelGGL((k_csr_spmv_b<T, 64>), dim3(grid_for(n * 64)), dim3(WG), 0, st, n, rowptr, col, val, x, y,
                            r_minus);
-    else if (lanes >= 32)
-        hipLaunchKernelGGL((k_csr_spmv_b<T, 32>), dim3(grid_for(n * 32)), dim3(WG), 0, st, n, rowptr, col, val, x, y,
-                           r_minus);
     else
-        hipLaunchKernelGGL((k_csr_spmv_b<T, 16>), dim3(grid_for(n * 16)), dim3(WG), 0, st, n, rowptr, col, val, x, y,
+        hipLaunchKernelGGL((k_csr_spmv_b<T, 32>), dim3(grid_for(n * 32)), dim3(WG), 0, st, n, rowptr, col, val, x, y,
                            r_minus);
 }
 

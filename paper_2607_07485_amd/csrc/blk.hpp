@@ -11,7 +11,8 @@ namespace lsdd {
 constexpr int NRB = 8;   // right-hand sides per block
 
 // ---------------------------------------------------------------- cycle, block vectors
-// lanes per row of the CSR kernels: 16, 32 or 64
+// lanes per row of the CSR kernels: 4, 8 or 16 (lane = nonzero slot, all NRB
+// right-hand sides per lane) or 32 or 64 (lane = (nonzero slot, right-hand side))
 template <typename T>
 void launch_csr_resid_rows_b(int64_t nrows, const int32_t* rows, const int64_t* rowptr, const int32_t* col,
                              const T* val, const T* x, const T* r, T* out, bool x_zero, int lanes, hipStream_t st);

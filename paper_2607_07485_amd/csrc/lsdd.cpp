@@ -153,8 +153,8 @@ struct Level {
     double* d_blocks = nullptr;
     // assembled operator
     Csr pat;
-    int lanes = 16;                    // CSR lanes per row, single vectors (8, 16, 32 or 64)
-    int lanes_b = 32;                  // CSR lanes per row, blocks of NRB vectors (16, 32 or 64)
+    int lanes = 16;                    // CSR lanes per row, single vectors (4, 8, 16, 32 or 64)
+    int lanes_b = 8;                   // CSR lanes per row, blocks of NRB vectors (4, 8, 16, 32 or 64)
     int chl = SUB_MAX_CHUNK;           // tiles per subdomain-kernel work item
     int fl = 8;                        // threads per DOF in the subdomain finalize
     int64_t* d_rowptr = nullptr;
@@ -351,7 +351,7 @@ void assemble_operator(lsdd_hierarchy* h, Level& lv) {
         lv.pat = assembled_pattern(lv.n, lv.el);
     lv.nnz = (int64_t)lv.pat.idx.size();
     lv.lanes = (lv.nnz > 96 * lv.n) ? 64 : 16;
-    lv.lanes_b = (lv.nnz > 40 * lv.n) ? 64 : 32;
+    lv.lanes_b = (lv.nnz > 40 * lv.n) ? 16 : 8;
     lv.d_rowptr = h->arena.upload(lv.pat.ptr, h->st);
     lv.d_col = h->arena.upload(lv.pat.idx, h->st);
     lv.d_val = h->arena.alloc<double>(lv.nnz);
@@ -1712,7 +1712,7 @@ void autotune_levels(lsdd_hierarchy* h) {
         launch_zero<T>(lv.n * NR, v.r, h->st);
         launch_zero<T>(lv.n * NR, v.x, h->st);
         int& lanes = NR > 1 ? lv.lanes_b : lv.lanes;
-        const std::vector<int> lane_c = NR > 1 ? std::vector<int>{16, 32, 64} : std::vector<int>{8, 16, 32, 64};
+        const std::vector<int> lane_c = NR > 1 ? std::vector<int>{4, 8, 16, 32, 64} : std::vector<int>{8, 16, 32, 64};
         double best = 1e300;
         int pick = lanes;
         for (int L : lane_c) {

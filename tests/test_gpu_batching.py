@@ -188,7 +188,7 @@ def test_autotuned_shapes_keep_parity(dev):
         t1 = h.autotune(block=False)
         t8 = h.autotune(block=True)
         for t in t1 + t8:
-            assert t["lanes"] in (16, 64) and t["lanes_block"] in (16, 32, 64)
+            assert t["lanes"] in (8, 16, 32, 64) and t["lanes_block"] in (4, 8, 16, 32, 64)
             assert t["tiles_per_item"] in (2, 4, 8) and t["finalize_threads"] in (8, 32)
         x, inf = h.solve(torch.from_numpy(b).to(dev))
         x_or, inf_or = oracle.pcg(h_or, b)
