@@ -8,6 +8,7 @@
 #include <hip/hip_ext.h>
 
 #include <cmath>
+#include <stdexcept>
 
 #include "blk.hpp"
 #include "kernels.hpp"
@@ -409,12 +410,15 @@ __global__ void __launch_bounds__(WG) k_prolong_b(const int32_t* items, const in
 // wave per subdomain; lane i forms y_i = sum_j (A_Omega^{-1})_{ij} r_j over all j in
 // ascending order (fixed order) and adds it to x (entries with a negative DOF are
 // skipped): subdomains of one colour are disjoint, so the update needs no partial
-// sums.
+// sums.  The LDS is sized by the launch's largest overlap (max_m), so small
+// overlaps leave room for more waves per CU.
 template <typename T, int NR>
 __global__ void __launch_bounds__(64) k_small_sub(int32_t s0, const int64_t* sub_off, const int32_t* sub_dofs,
-                                                  const int64_t* pk_off, const T* pk, const T* rloc, T* x) {
-    __shared__ T s_a[SMALL_M * (SMALL_M + 1) / 2];
-    __shared__ T s_x[SMALL_M * NR];
+                                                  const int64_t* pk_off, const T* pk, const T* rloc, T* x,
+                                                  int max_m) {
+    extern __shared__ __align__(16) unsigned char s_small[];
+    T* s_a = reinterpret_cast<T*>(s_small);
+    T* s_x = s_a + max_m * (max_m + 1) / 2;
     const int s = s0 + blockIdx.x;
     const int lane = tid();
     const int64_t o = sub_off[s];
@@ -836,10 +840,12 @@ void launch_pcg_start(int64_t len, const double* b, double* r, double* x, hipStr
 
 template <typename T, int NR>
 void launch_small_sub(int64_t s0, int64_t n_sub, const int64_t* sub_off, const int32_t* sub_dofs,
-                      const int64_t* pk_off, const T* pk, const T* rloc, T* x, hipStream_t st) {
+                      const int64_t* pk_off, const T* pk, const T* rloc, T* x, int max_m, hipStream_t st) {
     if (n_sub <= 0) return;
-    hipLaunchKernelGGL((k_small_sub<T, NR>), dim3((unsigned)n_sub), dim3(64), 0, st, (int32_t)s0, sub_off, sub_dofs,
-                       pk_off, pk, rloc, x);
+    if (max_m < 1 || max_m > SMALL_M) throw std::runtime_error("launch_small_sub: max_m outside 1 .. SMALL_M");
+    const size_t lds = ((size_t)max_m * (max_m + 1) / 2 + (size_t)max_m * NR) * sizeof(T);
+    hipLaunchKernelGGL((k_small_sub<T, NR>), dim3((unsigned)n_sub), dim3(64), lds, st, (int32_t)s0, sub_off, sub_dofs,
+                       pk_off, pk, rloc, x, max_m);
 }
 
 template <typename T, int NR>
@@ -861,7 +867,7 @@ void launch_prolong_small(int64_t na, const int32_t* agg_of_p, const int64_t* ag
 
 #define LSDD_SMALL_INST(T, NR)                                                                                     \
     template void launch_small_sub<T, NR>(int64_t, int64_t, const int64_t*, const int32_t*, const int64_t*,        \
-                                          const T*, const T*, T*, hipStream_t);                                     \
+                                          const T*, const T*, T*, int, hipStream_t);                                \
     template void launch_restrict_small<T, NR>(int64_t, const int32_t*, const int64_t*, const int32_t*,            \
                                                const int64_t*, const int64_t*, const T*, const T*, T*, hipStream_t); \
     template void launch_prolong_small<T, NR>(int64_t, const int32_t*, const int64_t*, const int32_t*,             \

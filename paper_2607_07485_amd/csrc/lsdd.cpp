@@ -198,6 +198,7 @@ struct Level {
     std::vector<int64_t> color_rmid;  // first row of the colour's small overlaps
     std::vector<int32_t> color_sub0;  // first sweep position of the colour
     std::vector<int32_t> color_smid;  // first small sweep position of the colour
+    int32_t small_m = 1;                  // largest small overlap (sizes the small kernel's LDS)
     std::vector<double> color_pk;     // packed entries of the colour's small overlaps
     int64_t* d_sw_pk_off = nullptr;   // packed-inverse offset of each small subdomain (sweep order)
     double* d_pk = nullptr;
@@ -1017,6 +1018,7 @@ std::unique_ptr<Level> coarsen(lsdd_hierarchy* h, Level& lv, const int32_t* agg_
             lv.color_smid[c] = s;
             lv.color_rmid[c] = (int64_t)sw_dofs.size();
         }
+        if (is_small(i)) lv.small_m = std::max<int32_t>(lv.small_m, (int32_t)(sp_ptr[i + 1] - sp_ptr[i]));
         sw_dofs.insert(sw_dofs.end(), sp_dofs.begin() + sp_ptr[i], sp_dofs.begin() + sp_ptr[i + 1]);
         // the same list with the interface entries masked (-1): the aggregate part
         // of the overlap, for the restricted updates of RAS
@@ -1313,7 +1315,7 @@ struct Cyc {
     }
     static void small(Level& lv, int64_t s0, int64_t n_sub, const T* pk, const T* rloc, T* x, const int32_t* dofs,
                       hipStream_t st) {
-        launch_small_sub<T, NR>(s0, n_sub, lv.d_sw_sub_off, dofs, lv.d_sw_pk_off, pk, rloc, x, st);
+        launch_small_sub<T, NR>(s0, n_sub, lv.d_sw_sub_off, dofs, lv.d_sw_pk_off, pk, rloc, x, lv.small_m, st);
     }
     static void restrict_(Level& lv, const T* Z, const T* t, T* rc, hipStream_t st) {
         launch_restrict_small<T, NR>(lv.coff.back(), lv.d_agg_of_c, lv.d_agg_ptr, lv.d_agg_dofs, lv.d_zoff, lv.d_coff,
