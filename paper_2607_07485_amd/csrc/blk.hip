@@ -450,7 +450,8 @@ __global__ void __launch_bounds__(64) k_small_sub(int32_t s0, const int64_t* sub
 
 // Transfers for aggregates with |omega| <= SMALL_M, one thread per (coarse DOF,
 // right-hand side) for the restriction and per (aggregate entry, right-hand side)
-// for the prolongation.
+// for the prolongation; four independent entries (modes) per step, summed in four
+// partial sums added in a fixed order.
 template <typename T, int NR>
 __global__ void __launch_bounds__(WG) k_restrict_small(int64_t nc, const int32_t* agg_of_c, const int64_t* agg_ptr,
                                                        const int32_t* agg_dofs, const int64_t* zoff,
@@ -463,9 +464,20 @@ __global__ void __launch_bounds__(WG) k_restrict_small(int64_t nc, const int32_t
         const int64_t a0 = agg_ptr[ag];
         const int nw = (int)(agg_ptr[ag + 1] - a0);
         const T* z = Zc + zoff[ag] + (c - coff[ag]) * nw;
-        T acc = 0;
-        for (int a = 0; a < nw; ++a) acc += z[a] * t[(int64_t)agg_dofs[a0 + a] * NR + k];
-        rc[e] = acc;
+        const int32_t* dd = agg_dofs + a0;
+        // four independent entries per step: their indices, then their gathers
+        T acc0 = 0, acc1 = 0, acc2 = 0, acc3 = 0;
+        int a = 0;
+        for (; a + 4 <= nw; a += 4) {
+            const int32_t d0 = dd[a], d1 = dd[a + 1], d2 = dd[a + 2], d3 = dd[a + 3];
+            const T z0 = z[a], z1 = z[a + 1], z2 = z[a + 2], z3 = z[a + 3];
+            acc0 += z0 * t[(int64_t)d0 * NR + k];
+            acc1 += z1 * t[(int64_t)d1 * NR + k];
+            acc2 += z2 * t[(int64_t)d2 * NR + k];
+            acc3 += z3 * t[(int64_t)d3 * NR + k];
+        }
+        for (; a < nw; ++a) acc0 += z[a] * t[(int64_t)dd[a] * NR + k];
+        rc[e] = (acc0 + acc1) + (acc2 + acc3);
     }
 }
 
@@ -484,9 +496,16 @@ __global__ void __launch_bounds__(WG) k_prolong_small(int64_t na, const int32_t*
         const int kk = k[ag];
         const T* z = Zc + zoff[ag] + (p - a0);
         const T* ev = ec + coff[ag] * NR + q;
-        T acc = 0;
-        for (int s = 0; s < kk; ++s) acc += z[(int64_t)s * nw] * ev[(int64_t)s * NR];
-        x[(int64_t)agg_dofs[p] * NR + q] += acc;
+        T acc0 = 0, acc1 = 0, acc2 = 0, acc3 = 0;
+        int s = 0;
+        for (; s + 4 <= kk; s += 4) {
+            acc0 += z[(int64_t)s * nw] * ev[(int64_t)s * NR];
+            acc1 += z[(int64_t)(s + 1) * nw] * ev[(int64_t)(s + 1) * NR];
+            acc2 += z[(int64_t)(s + 2) * nw] * ev[(int64_t)(s + 2) * NR];
+            acc3 += z[(int64_t)(s + 3) * nw] * ev[(int64_t)(s + 3) * NR];
+        }
+        for (; s < kk; ++s) acc0 += z[(int64_t)s * nw] * ev[(int64_t)s * NR];
+        x[(int64_t)agg_dofs[p] * NR + q] += (acc0 + acc1) + (acc2 + acc3);
     }
 }
 
