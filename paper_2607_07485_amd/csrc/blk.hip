@@ -190,12 +190,14 @@ __global__ void __launch_bounds__(WG) k_csr_spmv_b(int64_t n, const int64_t* row
 // ---------------------------------------------------------------- subdomain product
 // Same work items and partial layout as the single-vector kernel, with NB-wide
 // entries.  Each tile is staged once in LDS (rows padded to 65 entries, so both
-// row-wise and column-wise reads are free of bank conflicts); wave w owns
-// right-hand sides 2w and 2w+1: lane = row for the row part (accumulated over
-// the item's tiles in registers) and lane = column for the column part, so no
-// cross-lane reduction is needed.  The next tile is prefetched into registers
-// (non-temporal loads: the tiles stream once per application) while the
-// current one is used.
+// row-wise and column-wise reads are free of bank conflicts).  Every lane works on
+// all NB right-hand sides, so one LDS read of a tile entry feeds NB products: for
+// the row part wave w takes the tile's columns 16w .. 16w + 15 with lane = row
+// (accumulated over the item's tiles in registers), for the column part its rows
+// 16w .. 16w + 15 with lane = column; the four waves' partial sums are added in
+// wave order through LDS (per tile for the column part, once per item for the
+// row part).  The next tile is prefetched into registers (non-temporal loads: the
+// tiles stream once per application) while the current one is used.
 template <typename T>
 __global__ void __launch_bounds__(WG) k_sub_symv_b(const int32_t* items, const int64_t* sub_off,
                                                    const int64_t* tp_off, const T* tiles, const T* rloc,
@@ -212,7 +214,6 @@ __global__ void __launch_bounds__(WG) k_sub_symv_b(const int32_t* items, const i
     const int J0 = ch * chl;
     const int nJ = min(chl, I + 1 - J0);
     const int lane = tid() & 63, w = tid() >> 6;
-    const int k0 = 2 * w;
     for (int a = tid(); a < 64 * NB; a += WG) {
         const int r = I * 64 + a / NB;
         s_xi[a] = r < m ? rloc[(o + r) * NB + (a & (NB - 1))] : (T)0;
@@ -223,7 +224,11 @@ __global__ void __launch_bounds__(WG) k_sub_symv_b(const int32_t* items, const i
     T v[16];
 #pragma unroll
     for (int i = 0; i < 16; ++i) v[i] = __builtin_nontemporal_load(row0 + (int64_t)J0 * 4096 + i * WG + tid());
-    T ar0 = 0, ar1 = 0;
+    static_assert(WG == 256, "four waves split a tile's columns (row part) and rows (column part)");
+    const int q0 = 16 * w;
+    T ar[NB];
+#pragma unroll
+    for (int k = 0; k < NB; ++k) ar[k] = 0;
     for (int jj = 0; jj < nJ; ++jj) {
         const int J = J0 + jj;
         __syncthreads();
@@ -241,29 +246,61 @@ __global__ void __launch_bounds__(WG) k_sub_symv_b(const int32_t* items, const i
 #pragma unroll
             for (int i = 0; i < 16; ++i) v[i] = __builtin_nontemporal_load(row0 + (int64_t)(J + 1) * 4096 + i * WG + tid());
         }
-        const T* tr = s_t + lane * 65;
-#pragma unroll 8
-        for (int c = 0; c < 64; ++c) {
-            const T a = tr[c];
-            ar0 += a * s_xj[c * NB + k0];
-            ar1 += a * s_xj[c * NB + k0 + 1];
+        // row part: lane = row, this wave's 16 columns, all NB right-hand sides
+        {
+            const T* tr = s_t + lane * 65 + q0;
+#pragma unroll 4
+            for (int cc = 0; cc < 16; ++cc) {
+                const T a = tr[cc];
+                const T* xc = s_xj + (q0 + cc) * NB;
+#pragma unroll
+                for (int k = 0; k < NB; ++k) ar[k] += a * xc[k];
+            }
         }
         if (J < I) {
-            T ac0 = 0, ac1 = 0;
-#pragma unroll 8
-            for (int r = 0; r < 64; ++r) {
-                const T a = s_t[r * 65 + lane];
-                ac0 += a * s_xi[r * NB + k0];
-                ac1 += a * s_xi[r * NB + k0 + 1];
+            // column part: lane = column, this wave's 16 rows; the four row quarters
+            // are summed in order through the (then free) tile buffer
+            T ac[NB];
+#pragma unroll
+            for (int k = 0; k < NB; ++k) ac[k] = 0;
+#pragma unroll 4
+            for (int rr = 0; rr < 16; ++rr) {
+                const T a = s_t[(q0 + rr) * 65 + lane];
+                const T* xr = s_xi + (q0 + rr) * NB;
+#pragma unroll
+                for (int k = 0; k < NB; ++k) ac[k] += a * xr[k];
             }
-            T* cp = colpart + (((int64_t)I * (I - 1) / 2 + J) * 64 + lane) * NB + k0;
-            cp[0] = ac0;
-            cp[1] = ac1;
+            __syncthreads();
+#pragma unroll
+            for (int k = 0; k < NB; ++k) s_t[(w * 64 + lane) * NB + k] = ac[k];
+            __syncthreads();
+            const int c = tid() >> 2, k0 = 2 * (tid() & 3);
+            T s0 = 0, s1 = 0;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                s0 += s_t[(q * 64 + c) * NB + k0];
+                s1 += s_t[(q * 64 + c) * NB + k0 + 1];
+            }
+            T* cp = colpart + (((int64_t)I * (I - 1) / 2 + J) * 64 + c) * NB + k0;
+            cp[0] = s0;
+            cp[1] = s1;
         }
     }
-    T* rp = part + ((symv_rowpart_off(I, chl) + ch) * 64 + lane) * NB + k0;
-    rp[0] = ar0;
-    rp[1] = ar1;
+    // row part: the four column quarters summed in order
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < NB; ++k) s_t[(w * 64 + lane) * NB + k] = ar[k];
+    __syncthreads();
+    const int r = tid() >> 2, k0 = 2 * (tid() & 3);
+    T s0 = 0, s1 = 0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        s0 += s_t[(q * 64 + r) * NB + k0];
+        s1 += s_t[(q * 64 + r) * NB + k0 + 1];
+    }
+    T* rp = part + ((symv_rowpart_off(I, chl) + ch) * 64 + r) * NB + k0;
+    rp[0] = s0;
+    rp[1] = s1;
 }
 
 // FL threads per DOF sum fixed strided subsets of its partials (all NB
