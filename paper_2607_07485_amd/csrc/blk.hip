@@ -190,7 +190,8 @@ __global__ void __launch_bounds__(WG) k_csr_spmv_b(int64_t n, const int64_t* row
 // ---------------------------------------------------------------- subdomain product
 // Same work items and partial layout as the single-vector kernel, with NB-wide
 // entries.  Each tile is staged once in LDS (rows padded to 65 entries, so both
-// row-wise and column-wise reads are free of bank conflicts).  Every lane works on
+// row-wise and column-wise reads are free of bank conflicts); the right-hand-side
+// entries are wave-uniform and come through the scalar cache.  Every lane works on
 // all NB right-hand sides, so one LDS read of a tile entry feeds NB products: for
 // the row part wave w takes the tile's columns 16w .. 16w + 15 with lane = row
 // (accumulated over the item's tiles in registers), for the column part its rows
@@ -200,11 +201,10 @@ __global__ void __launch_bounds__(WG) k_csr_spmv_b(int64_t n, const int64_t* row
 // tiles stream once per application) while the current one is used.
 template <typename T>
 __global__ void __launch_bounds__(WG) k_sub_symv_b(const int32_t* items, const int64_t* sub_off,
-                                                   const int64_t* tp_off, const T* tiles, const T* rloc,
-                                                   const int64_t* scr_off, T* scr, int chl) {
+                                                   const int64_t* tp_off, const T* __restrict__ tiles,
+                                                   const T* __restrict__ rloc, const int64_t* scr_off,
+                                                   T* __restrict__ scr, int chl) {
     __shared__ T s_t[64 * 65];
-    __shared__ T s_xi[64 * NB];
-    __shared__ T s_xj[64 * NB];
     const int s = items[3 * blockIdx.x];
     const int I = items[3 * blockIdx.x + 1];
     const int ch = items[3 * blockIdx.x + 2];
@@ -214,10 +214,10 @@ __global__ void __launch_bounds__(WG) k_sub_symv_b(const int32_t* items, const i
     const int J0 = ch * chl;
     const int nJ = min(chl, I + 1 - J0);
     const int lane = tid() & 63, w = tid() >> 6;
-    for (int a = tid(); a < 64 * NB; a += WG) {
-        const int r = I * 64 + a / NB;
-        s_xi[a] = r < m ? rloc[(o + r) * NB + (a & (NB - 1))] : (T)0;
-    }
+    // wave-uniform quarter of the tile; the right-hand-side entries it multiplies are
+    // read at wave-uniform addresses (scalar loads), clamped to the subdomain's last
+    // row: the tiles are zero past |Omega|, so a clamped entry adds nothing
+    const int wu = __builtin_amdgcn_readfirstlane(w);
     T* part = scr + scr_off[s] * NB;
     T* colpart = part + symv_rowpart_off(nt, chl) * 64 * NB;
     const T* row0 = tiles + tp_off[s] + (int64_t)I * (I + 1) / 2 * 4096;
@@ -225,7 +225,8 @@ __global__ void __launch_bounds__(WG) k_sub_symv_b(const int32_t* items, const i
 #pragma unroll
     for (int i = 0; i < 16; ++i) v[i] = __builtin_nontemporal_load(row0 + (int64_t)J0 * 4096 + i * WG + tid());
     static_assert(WG == 256, "four waves split a tile's columns (row part) and rows (column part)");
-    const int q0 = 16 * w;
+    const int q0 = 16 * wu;
+    const T* xI = rloc + o * NB;
     T ar[NB];
 #pragma unroll
     for (int k = 0; k < NB; ++k) ar[k] = 0;
@@ -236,10 +237,6 @@ __global__ void __launch_bounds__(WG) k_sub_symv_b(const int32_t* items, const i
         for (int i = 0; i < 16; ++i) {
             const int e = i * WG + tid();
             s_t[(e >> 6) * 65 + (e & 63)] = v[i];
-        }
-        for (int a = tid(); a < 64 * NB; a += WG) {
-            const int c = J * 64 + a / NB;
-            s_xj[a] = c < m ? rloc[(o + c) * NB + (a & (NB - 1))] : (T)0;
         }
         __syncthreads();
         if (jj + 1 < nJ) {
@@ -252,7 +249,7 @@ __global__ void __launch_bounds__(WG) k_sub_symv_b(const int32_t* items, const i
 #pragma unroll 4
             for (int cc = 0; cc < 16; ++cc) {
                 const T a = tr[cc];
-                const T* xc = s_xj + (q0 + cc) * NB;
+                const T* xc = xI + (int64_t)min(J * 64 + q0 + cc, m - 1) * NB;
 #pragma unroll
                 for (int k = 0; k < NB; ++k) ar[k] += a * xc[k];
             }
@@ -266,7 +263,7 @@ __global__ void __launch_bounds__(WG) k_sub_symv_b(const int32_t* items, const i
 #pragma unroll 4
             for (int rr = 0; rr < 16; ++rr) {
                 const T a = s_t[(q0 + rr) * 65 + lane];
-                const T* xr = s_xi + (q0 + rr) * NB;
+                const T* xr = xI + (int64_t)min(I * 64 + q0 + rr, m - 1) * NB;
 #pragma unroll
                 for (int k = 0; k < NB; ++k) ac[k] += a * xr[k];
             }
