@@ -33,7 +33,8 @@ algebraic preconditioning framework for conforming finite elements"):
 Readings taken where the paper is silent (each is listed in the design notes):
 R1 structural support of element rows (every row of G_T spans all DOFs of T),
 R2 rank tolerance n_T eps lambda_max, R3 aggregation phases/passes and the
-supernode graph, R4 pseudo-inverse tolerance |Gamma| eps d_max, R5 the reduced
+supernode graph, R4 pseudo-inverse tolerance |Gamma| eps d_max (and the equivalent
+projector form on the weighted Gram rows as a second route), R5 the reduced
 problem solved as S~ u = mu A_ww u with mu = 1/lambda, R6 tau_cut uses the
 level-wide maximum multiplicity, R7/R8 cluster completion and threshold band,
 R9 A_ww-orthonormal Z, R11 colour-major sweep order, R12 coarse elements grouped
@@ -70,9 +71,12 @@ class Params:
     spsd_tol: float = 1e-12
     rtol: float = 1e-8
     max_iter: int = 1000
-    # generalized inverse of A~_GammaGamma in the Schur complement: "pinv" (the paper's
-    # Moore-Penrose form, reading R4) or "cholesky" (reading R13: Cholesky, and when a
-    # pivot falls to |Gamma| eps max diag, Cholesky of the block shifted by that amount)
+    # route to the Schur complement of eq. (gep_reduced): "pinv" (the Moore-Penrose
+    # pseudo-inverse of A~_GammaGamma by its eigendecomposition, reading R4; the method's
+    # definition and the default) or "projector" (the same quantity in its equivalent
+    # form H_w^T (I - Pi_range(H_Gamma)) H_w on the weighted Gram rows, with the R4 rule
+    # applied to the squared singular values of H_Gamma; a second FP64 route whose
+    # distance from "pinv" measures how far rounding alone moves the result)
     interface: str = "pinv"
     # overlaps: "G" = G-row closure (Def. "G-row closure", the method's choice) or
     # "A" = algebraic A-closure (Def. "algebraic A-closure", the comparison of Sec. 5.3);
@@ -279,6 +283,7 @@ class Level:
     chol: list = field(default_factory=list)      # Cholesky factors of A_Omega_i (A_ww for "bj")
     smoother: str = "ms"
     coarsest_chol: tuple = None
+    gram: list = None                   # element Gram factors (level 0; "projector" route)
 
 
 @dataclass
@@ -340,46 +345,18 @@ def local_splitting(omega_dofs: np.ndarray, cl_elems, elem_dofs, blocks, mult) -
     return At
 
 
-def cholesky_pivots(M: np.ndarray):
-    """Right-looking Cholesky M = L L^T with its pivots d_j (the diagonal entries
-    before the square root); a pivot <= 0 is recorded and replaced by 1."""
-    n = M.shape[0]
-    W = np.array(M, dtype=np.float64, copy=True)
-    piv = np.empty(n)
-    for j in range(n):
-        d = W[j, j]
-        piv[j] = d
-        s = np.sqrt(d) if d > 0 else 1.0
-        W[j, j] = s
-        W[j + 1:, j] /= s
-        W[j + 1:, j + 1:] -= np.outer(W[j + 1:, j], W[j + 1:, j])
-    return np.tril(W), piv
-
-
-def schur_pinv(At: np.ndarray, nw: int, interface: str = "pinv") -> np.ndarray:
+def schur_pinv(At: np.ndarray, nw: int) -> np.ndarray:
     """S~ = A~_ww - A~_wG (A~_GG)^+ A~_Gw (eq. gep_reduced).
 
-    interface = "pinv": pseudo-inverse via eigh; eigenvalues of A~_GG above
-    |Gamma| eps d_max form its range (reading R4).  interface = "cholesky"
-    (reading R13): W = L^{-1} A~_Gw with A~_GG = L L^T; if the smallest pivot is
-    at most |Gamma| eps max diag(A~_GG), the block is factored again with that
-    tolerance added to its diagonal.  For an exactly singular PSD block whose
-    coupling lies in its range both give the same Schur complement.
+    The pseudo-inverse comes from the eigendecomposition of A~_GG: eigenvalues
+    above |Gamma| eps d_max form its range (reading R4).  With Gamma empty,
+    S~ = A~_ww.
     """
     Aww = At[:nw, :nw]
     if At.shape[0] == nw:
         return 0.5 * (Aww + Aww.T)
     AwG = At[:nw, nw:]
     AGG = At[nw:, nw:]
-    if interface == "cholesky":
-        ng = AGG.shape[0]
-        tol = ng * EPS * float(np.max(np.diag(AGG)))
-        L, piv = cholesky_pivots(AGG)
-        if not piv.min() > tol:
-            L, piv = cholesky_pivots(AGG + tol * np.eye(ng))
-        W = sla.solve_triangular(L, AwG.T, lower=True)
-        S = Aww - W.T @ W
-        return 0.5 * (S + S.T)
     d, V = np.linalg.eigh(AGG)
     dmax = max(float(d[-1]), 0.0)
     keep = d > AGG.shape[0] * EPS * dmax if dmax > 0 else np.zeros(len(d), bool)
@@ -387,6 +364,41 @@ def schur_pinv(At: np.ndarray, nw: int, interface: str = "pinv") -> np.ndarray:
     W = AwG @ Vk
     S = Aww - (W / d[keep]) @ W.T
     return 0.5 * (S + S.T)
+
+
+def schur_projector(H: np.ndarray, nw: int) -> np.ndarray:
+    """The same Schur complement from the weighted Gram rows H of the overlap
+    (A~_Omega = H^T H, eq. SPSD_splitting): S~ = H_w^T (I - U_r U_r^T) H_w with U_r
+    the left singular vectors of H_Gamma whose squared singular values exceed
+    |Gamma| eps s_max^2 (the R4 rule on the eigenvalues of A~_GG = H_G^T H_G).
+    For A~_GG = V D V^T this is the pseudo-inverse expression term by term,
+    A~_wG V_r D_r^{-1} V_r^T A~_Gw = H_w^T U_r U_r^T H_w, without forming A~_GG."""
+    Hw = H[:, :nw]
+    if H.shape[1] == nw:
+        S = Hw.T @ Hw
+        return 0.5 * (S + S.T)
+    HG = H[:, nw:]
+    U, sv, _ = np.linalg.svd(HG, full_matrices=False)
+    smax = float(sv[0]) if len(sv) else 0.0
+    keep = sv ** 2 > HG.shape[1] * EPS * smax ** 2 if smax > 0 else np.zeros(len(sv), bool)
+    Y = U[:, keep].T @ Hw
+    S = Hw.T @ Hw - Y.T @ Y
+    return 0.5 * (S + S.T)
+
+
+def local_gram_rows(omega_dofs: np.ndarray, cl_elems, elem_dofs, factors, mult) -> np.ndarray:
+    """H_Omega: the rows mult(T)^{-1/2} G_T of the closure elements embedded in
+    Omega (eq. Wmatrix-def), so that H^T H = A~_Omega."""
+    pos = {int(d): a for a, d in enumerate(omega_dofs)}
+    rows = []
+    for e in cl_elems:
+        F = factors[e]
+        R = np.zeros((F.shape[0], len(omega_dofs)))
+        idx = np.array([pos.get(int(d), -1) for d in elem_dofs[e]])
+        ok = idx >= 0
+        R[:, idx[ok]] = F[:, ok] / np.sqrt(mult[e])
+        rows.append(R)
+    return np.vstack(rows) if rows else np.zeros((0, len(omega_dofs)))
 
 
 def local_spectral(S: np.ndarray, Aww: np.ndarray):
@@ -460,7 +472,8 @@ def setup(prob, params: Params | None = None) -> Hierarchy:
         raise ValueError("elem_factor must be 'eig' or 'chol'")
     factor = element_gram_factor if params.elem_factor == "eig" else element_gram_factor_pchol
     G0 = [factor(B, params.rank_rtol, params.spsd_tol) for B in blocks]
-    lev = Level(n=prob.n, level=0, elem_dofs=elem_dofs, blocks=blocks, node_of_dof=np.asarray(prob.node_of_dof, np.int64))
+    lev = Level(n=prob.n, level=0, elem_dofs=elem_dofs, blocks=blocks, node_of_dof=np.asarray(prob.node_of_dof, np.int64),
+                gram=G0)
     levels = []
     agg_given = None if prob.agg_of_dof is None else np.asarray(prob.agg_of_dof, np.int64)
     while True:
@@ -506,6 +519,12 @@ def coarsen(lev: Level, params: Params, agg_of_dof=None):
         lev.omegas = omegas
     elif params.closure != "G":
         raise ValueError("closure must be 'G' or 'A'")
+    factors = None
+    if params.interface == "projector":
+        # Gram rows per element: the level-0 factors, and above them range factors of
+        # the grouped coarse blocks (SPSD up to the rounding of the Galerkin products)
+        factors = lev.gram if lev.gram is not None else \
+            [element_gram_factor(B, params.rank_rtol, np.inf) for B in lev.blocks]
     lev.mu, lev.Z, ks = [], [], []
     for i in range(n_agg):
         O = omegas[i]
@@ -516,7 +535,15 @@ def coarsen(lev: Level, params: Params, agg_of_dof=None):
             At = At[np.ix_(keep, keep)]
         else:
             At = local_splitting(O, cl[i], lev.elem_dofs, lev.blocks, mult)
-        S = schur_pinv(At, nw, params.interface)
+        if params.interface == "projector":
+            H = local_gram_rows(omegas_g[i] if params.closure == "A" else O, cl[i], lev.elem_dofs, factors, mult)
+            if params.closure == "A":
+                H = H[:, np.isin(omegas_g[i], O)]
+            S = schur_projector(H, nw)
+        elif params.interface == "pinv":
+            S = schur_pinv(At, nw)
+        else:
+            raise ValueError("interface must be 'pinv' or 'projector'")
         Aww = lev.A[aggs[i]][:, aggs[i]].toarray()
         mu, V, L = local_spectral(S, Aww)
         k = select_modes(mu, params, lev.tau_cut)

@@ -210,6 +210,9 @@ def test_schur_complement_matches_projection_route():
         S = O.schur_pinv(At, len(lv.aggs[i]))
         S2 = _schur_by_projection(lv, i, h.G0)
         assert np.abs(S - S2).max() <= 1e-10 * np.abs(At).max()
+        H = O.local_gram_rows(lv.omegas[i], lv.closure[i], lv.elem_dofs, h.G0, lv.mult)
+        assert np.abs(H.T @ H - At).max() <= 1e-13 * np.abs(At).max()
+        assert np.abs(O.schur_projector(H, len(lv.aggs[i])) - S2).max() <= 1e-10 * np.abs(At).max()
 
 
 def test_schur_pinv_on_singular_interface_block():
@@ -359,20 +362,54 @@ def test_stationary_cycle_converges():
     assert info.converged and info.iters < 40
 
 
-def test_interface_readings_agree_on_singular_blocks_with_a_gap():
-    """Readings R4 (eigh pseudo-inverse) and R13 (regularised Cholesky) of the interface
-    generalized inverse give the same Schur complement when the singular block's spectrum
-    has a gap at the tolerance and the coupling lies in its range (Sec. 2, eq. gep_reduced)."""
+def test_interface_routes_agree_on_singular_blocks_with_a_gap():
+    """The pseudo-inverse route (eigendecomposition of A~_GG, reading R4) and the projector
+    route on the weighted Gram rows give the same Schur complement on a singular interface
+    block, equal to the minimum energy over interface extensions; moving one interface
+    column out of the range changes it (Sec. 2, eq. gep_reduced)."""
     rng = np.random.default_rng(5)
     nw, ng, r = 6, 9, 5
     H = rng.standard_normal((12, nw + ng))
     H[:, nw:] = rng.standard_normal((12, r)) @ rng.standard_normal((r, ng))   # rank-r interface columns
     At = H.T @ H
-    S1 = oracle.schur_pinv(At, nw, "pinv")
-    S2 = oracle.schur_pinv(At, nw, "cholesky")
-    assert np.abs(S1 - S2).max() <= 1e-6 * np.abs(S1).max()
-    # and the Cholesky pivots reproduce numpy's factor on an SPD block
-    M = H.T @ H + np.eye(nw + ng)
-    L, piv = oracle.lsdd.cholesky_pivots(M)
-    assert np.allclose(L, np.linalg.cholesky(M), rtol=1e-12, atol=1e-12)
-    assert np.allclose(piv, np.diag(L) ** 2, rtol=1e-12)
+    S1 = oracle.schur_pinv(At, nw)
+    S2 = oracle.lsdd.schur_projector(H, nw)
+    assert np.abs(S1 - S2).max() <= 1e-10 * np.abs(S1).max()
+    # minimum-energy characterisation: S~ = min over interface extensions of the energy
+    for _ in range(3):
+        v = rng.standard_normal(nw)
+        ext = -np.linalg.lstsq(H[:, nw:], H[:, :nw] @ v, rcond=None)[0]
+        full = np.concatenate([v, ext])
+        assert abs(v @ S1 @ v - full @ At @ full) <= 1e-9 * abs(v @ S1 @ v)
+    Hc = H.copy()
+    Hc[:, nw] = rng.standard_normal(12)                  # an interface column leaving the range: different S~
+    assert np.abs(oracle.lsdd.schur_projector(Hc, nw) - S2).max() > 1e-3 * np.abs(S2).max()
+
+
+def test_schur_complement_does_not_depend_on_the_generalized_inverse():
+    """For a PSD A~_Omega the coupling A~_Gw lies in the range of A~_GG, so every generalized
+    inverse gives the Moore-Penrose Schur complement; here one from eliminating a maximal
+    set of pivots with the largest remaining diagonal (a truncated pivoted Cholesky) on a
+    block with a 3-dimensional null space."""
+    rng = np.random.default_rng(11)
+    nw, ng = 5, 10
+    H = rng.standard_normal((14, nw + ng))
+    H[:, nw + 7:] = H[:, nw:nw + 3] @ rng.standard_normal((3, 3))   # 3 dependent interface columns
+    At = H.T @ H
+    M = At[nw:, nw:].copy()
+    tol = ng * np.finfo(float).eps * M.diagonal().max()
+    live = np.ones(ng, bool)
+    piv = []
+    while live.any():
+        idx = np.flatnonzero(live)
+        j = idx[np.argmax(M[idx, idx])]
+        if not M[j, j] > tol:
+            break
+        c = np.where(live, M[:, j], 0.0) / np.sqrt(M[j, j])
+        M -= np.outer(c, c)
+        live[j] = False
+        piv.append(j)
+    assert len(piv) == ng - 3
+    P = nw + np.array(piv)
+    S_elim = At[:nw, :nw] - At[:nw, P] @ np.linalg.solve(At[np.ix_(P, P)], At[P, :nw])
+    assert np.abs(S_elim - oracle.schur_pinv(At, nw)).max() <= 1e-9 * np.abs(At).max()
