@@ -58,7 +58,11 @@ typedef struct {
     int32_t modes_fixed;        /* > 0: keep this many smallest mu per aggregate; 0: tau_cut   */
     int32_t min_coarse;         /* a level with fewer DOFs is the coarsest; default 10         */
     int32_t max_iter;           /* PCG iteration cap; default 1000                             */
-    int32_t precision;          /* 0 = FP64 cycle, 1 = FP32 cycle inside FP64 PCG              */
+    int32_t precision;          /* cycle precision at setup (FP64 PCG outside in all cases):
+                                   0 = FP64 cycle; 1 = FP32 cycle (FP32 copies of the operator,
+                                   subdomain inverses and transfers are kept); 2 = as 1, plus
+                                   FP32 copies of the subdomain factors X = L^{-1} for the mixed
+                                   cycle (see lsdd_set_cycle_precision)                      */
     int32_t blocked_eig_min;    /* local spectral problems with |omega| >= this use the blocked
                                    multi-workgroup tridiagonal reduction; 0 = library default
                                    (192), < 0 = never; values below 66 act as 66            */
@@ -176,15 +180,21 @@ lsdd_status lsdd_setup_elements_scaled(int64_t n, int64_t n_elem, const int64_t*
  * LSDD_E_UNSUPPORTED for a hierarchy built from a CSR Gram factor. */
 lsdd_status lsdd_update_theta(lsdd_hierarchy* h, const double* theta, void* hip_stream);
 
-/* Element bilinear forms out[e] = u_{S_e}^T B_e v_{S_e} (all device pointers but
- * elem_ptr): the contraction of the adjoint gradient dL/dtheta_e = -lambda_e^T
- * A_e^(1) u_e of u = A(theta)^{-1} b (A linear in theta, Sec. 5.1 assembly).
- *   elem_ptr   host int64[n_elem + 1]; elem_dofs device int32; blocks device float64,
- *              the n_e x n_e blocks row-major, concatenated
- *   u, v       device float64[n]; out device float64[n_elem] */
+/* Element bilinear forms out[e] = scale * sum_k u_{k,S_e}^T B_e v_{k,S_e} over nrhs
+ * pairs of vectors (all device pointers but elem_ptr): with scale = -1, u_k the
+ * adjoint solutions lambda_k and v_k the solutions u_k, this is the gradient
+ * dL/dtheta_e = -sum_k lambda_{k,e}^T A_e^(1) u_{k,e} of u = A(theta)^{-1} b for
+ * element blocks linear in their coefficient (Sec. 5.1, elementwise assembly).
+ *   elem_ptr   host int64[n_elem + 1] (elem_ptr[0] = 0, element sizes 1 .. 4096);
+ *              elem_dofs device int32 (indices < ld, not checked); blocks device
+ *              float64, the n_e x n_e blocks row-major, concatenated
+ *   u, v       device float64[nrhs * ld]: vector k at offset k * ld
+ *   nrhs >= 1, ld >= 1; out device float64[n_elem] (overwritten)
+ * Allocates two small device arrays per call (elem_ptr and the block offsets);
+ * blocks until the result is written. */
 lsdd_status lsdd_elem_bilinear(int64_t n_elem, const int64_t* elem_ptr, const int32_t* elem_dofs,
-                               const double* blocks, const double* u, const double* v, double* out,
-                               void* hip_stream);
+                               const double* blocks, const double* u, const double* v, int32_t nrhs,
+                               int64_t ld, double scale, double* out, void* hip_stream);
 
 /* Build a hierarchy from a black-box sparse Gram factor G (m x n, CSR, host),
  * the input of Sec. 2 (A = G^T G, m >= n, full column rank).  Each row of G is
@@ -210,6 +220,17 @@ lsdd_status lsdd_setup_gram_csr(int64_t m, int64_t n, const int64_t* rowptr, con
 lsdd_status lsdd_solve(lsdd_hierarchy* h, const double* b, double* x, int32_t nrhs,
                        void* hip_stream, lsdd_info* info);
 
+/* Solve with several separately built hierarchies: hs[i] x_i = b_i for i < n_inst,
+ * each exactly as lsdd_solve with nrhs right-hand sides, run one after the other on
+ * the stream.  (Uneven instances in single launches are the union hierarchy of
+ * lsdd_setup_batched solved by one lsdd_solve.)
+ *   hs     host array of n_inst hierarchy handles
+ *   b, x   host arrays of n_inst device pointers, b[i], x[i] float64[nrhs * n_i]
+ *   info   host, lsdd_info[n_inst * nrhs * n_seg_i] concatenated in instance order, or NULL
+ * Stops at the first instance whose solve fails and returns its status. */
+lsdd_status lsdd_solve_batched(int32_t n_inst, lsdd_hierarchy* const* hs, const double* const* b,
+                               double* const* x, int32_t nrhs, void* hip_stream, lsdd_info* info);
+
 /* Standalone V-cycle iteration, the solver mode of the paper's experiments (Sec. 6):
  * x_{k+1} = x_k + V(b - A x_k), where V is one symmetric V-cycle (forward
  * multiplicative Schwarz pre-smoothing, coarse correction, reverse-order
@@ -229,9 +250,18 @@ lsdd_status lsdd_solve(lsdd_hierarchy* h, const double* b, double* x, int32_t nr
 lsdd_status lsdd_solve_stationary(lsdd_hierarchy* h, const double* b, double* x, int32_t nrhs,
                                   void* hip_stream, lsdd_info* info);
 
-/* Switch the cycle precision of an existing hierarchy: 0 = FP64 cycle,
- * 1 = FP32 cycle (the hierarchy must have been set up with precision = 1, which
- * keeps FP32 copies of the cycle's operators next to the FP64 ones). */
+/* Switch the cycle precision of an existing hierarchy:
+ *   0 = FP64 cycle;
+ *   1 = FP32 cycle: FP32 vectors, operator entries, explicit subdomain inverses and
+ *       transfers (needs a hierarchy set up with precision >= 1);
+ *   2 = mixed cycle: FP32 vectors and transfers, subdomain solves as X^T (X r) with
+ *       FP32 factors X = L^{-1} of A_Omega (symmetric positive semidefinite under
+ *       rounding), residuals from the FP64 operator entries with FP64 sums (needs
+ *       precision = 2; multiplicative Schwarz smoother and single right-hand sides
+ *       only, else LSDD_E_UNSUPPORTED).  This is the variant for operators whose
+ *       spectrum FP32 cannot resolve, e.g. a mass term 1e-8 below the div term.
+ * The coarsest (terminal) solve and PCG stay FP64 in every mode; modes 1 and 2 use
+ * flexible PCG.  LSDD_E_INVAL if the setup precision does not allow the mode. */
 lsdd_status lsdd_set_cycle_precision(lsdd_hierarchy* h, int32_t precision);
 
 /* Change the PCG stopping tolerance and iteration cap of an existing hierarchy. */

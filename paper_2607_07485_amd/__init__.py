@@ -4,5 +4,5 @@ Every numerical step of setup and solve runs in the library's HIP kernels; this
 package only marshals arguments (PyTorch supplies device memory and streams).
 """
 from .lsdd import (  # noqa: F401
-    LSDD_STATUS, Hierarchy, LsddError, Params, elem_bilinear, lib, lib_path, set_torch_allocator,
+    LSDD_STATUS, Hierarchy, LsddError, Params, elem_bilinear, lib, lib_path, set_torch_allocator, solve_batched,
 )

@@ -36,14 +36,10 @@ class ElementSystem:
                                                theta.detach().contiguous(), self.node_of_dof, self.agg_of_dof,
                                                self.params)
 
-    def contract(self, lam: torch.Tensor, u: torch.Tensor) -> torch.Tensor:
-        """out_e = sum_k lam_{k,e}^T A_e^(1) u_{k,e} for [n] or [nrhs, n] inputs."""
-        lam2, u2 = lam.reshape(-1, self.n), u.reshape(-1, self.n)
-        out = elem_bilinear(self.elem_ptr, self.elem_dofs, self.blocks, lam2[0].contiguous(), u2[0].contiguous())
-        for k in range(1, lam2.shape[0]):
-            out = out + elem_bilinear(self.elem_ptr, self.elem_dofs, self.blocks, lam2[k].contiguous(),
-                                      u2[k].contiguous())
-        return out
+    def gradient(self, lam: torch.Tensor, u: torch.Tensor) -> torch.Tensor:
+        """dL/dtheta_e = -sum_k lam_{k,e}^T A_e^(1) u_{k,e} for [n] or [nrhs, n] inputs
+        (the sum over right-hand sides and the sign are applied in the library)."""
+        return elem_bilinear(self.elem_ptr, self.elem_dofs, self.blocks, lam, u, scale=-1.0)
 
 
 class ElementSolve(torch.autograd.Function):
@@ -62,7 +58,7 @@ class ElementSolve(torch.autograd.Function):
         (u,) = ctx.saved_tensors
         h, system = ctx.h, ctx.system
         lam, _ = h.solve(ubar.contiguous())
-        g = -system.contract(lam, u)
+        g = system.gradient(lam, u)
         h.close()
         ctx.h = None
         return g, lam, None

@@ -164,8 +164,9 @@ __global__ void __launch_bounds__(NT) k_potrf_panel(double* base, const View* vi
 // A_ib,jb -= sum over column tiles k in [kt0, kt1) of L_ib,k L_jb,k^T, for the
 // lower tiles jb in [jt0, jt1), ib >= jb (matrix cores; K up to OB tiles)
 __global__ void __launch_bounds__(NT) k_potrf_update(double* base, const View* views, int kt0, int kt1, int jt0,
-                                                     int jt1) {
+                                                     int jt1, const int32_t* skip = nullptr) {
     __shared__ mg::Smem sm;
+    if (skip && skip[blockIdx.y]) return;
     const View v = views[blockIdx.y];
     const int n = v.rows;
     const int nt = ntiles(n);
@@ -193,6 +194,116 @@ __global__ void __launch_bounds__(NT) k_potrf_update(double* base, const View* v
                 const int r = ib * TB + i, c = jb * TB + j;
                 if (r < n && c < n && (ib != jb || i >= j)) base[v.off + r + (int64_t)c * v.ld] -= acc[p][q][e];
             }
+}
+
+// ---------------------------------------------------------------- pivoted Cholesky of a trailing block
+
+// Largest value over [j, n) of d (lowest index among equal values) by one
+// workgroup; red: 2 * NT / 64 LDS slots.
+__device__ inline void wg_argmax(const double* d, int j, int n, double* rv, int* ri, double& bv, int& bi) {
+    bv = -INFINITY;
+    bi = -1;
+    for (int i = j + t_id(); i < n; i += NT) {
+        const double x = d[i];
+        if (x > bv || (x == bv && bi >= 0 && i < bi)) { bv = x; bi = i; }
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        const double ov = __shfl_xor(bv, off, 64);
+        const int oi = __shfl_xor(bi, off, 64);
+        if (oi >= 0 && (ov > bv || (ov == bv && (bi < 0 || oi < bi)))) { bv = ov; bi = oi; }
+    }
+    if ((t_id() & 63) == 0) { rv[t_id() >> 6] = bv; ri[t_id() >> 6] = bi; }
+    __syncthreads();
+    bv = rv[0];
+    bi = ri[0];
+    for (int w = 1; w < NT / 64; ++w)
+        if (ri[w] >= 0 && (rv[w] > bv || (rv[w] == bv && (bi < 0 || ri[w] < bi)))) { bv = rv[w]; bi = ri[w]; }
+    __syncthreads();
+}
+
+// Columns [kb TB, kb TB + TB) of the diagonally pivoted Cholesky of the trailing
+// block of view b (indices lead[b] .. m-1 of the square view, lower triangle).
+// Left-looking inside the panel: the trailing matrix holds the updates of the
+// earlier panels only, the panel's own earlier columns are applied per column.
+// The pivot is the largest remaining diagonal entry; it is swapped into place
+// symmetrically across the whole view (row segment left of it, diagonal, the
+// column below), so the leading block keeps its position and the coupling rows
+// follow their indices.  The factorisation stops when the largest remaining
+// diagonal entry is at most tol[b]: rank[b] is then the number of eliminated
+// indices and done[b] is set.  diag: per-view scratch of the remaining diagonal.
+__global__ void __launch_bounds__(NT) k_pstrf_panel(double* base, const View* views, const int32_t* lead, int kb,
+                                                    const double* tol, const int64_t* diag_off, double* diag,
+                                                    int32_t* rank, int32_t* done) {
+    __shared__ double rv[NT / 64];
+    __shared__ int ri[NT / 64];
+    if (done[blockIdx.y]) return;
+    const View v = views[blockIdx.y];
+    const int nw = lead[blockIdx.y];
+    const int m = v.rows, ng = m - nw;
+    const int64_t ld = v.ld;
+    double* M = base + v.off;
+    double* D = diag + diag_off[blockIdx.y];
+    const double tl = tol[blockIdx.y];
+    const int j0 = kb * TB;
+    if (j0 >= ng) {
+        if (t_id() == 0) { rank[blockIdx.y] = ng; done[blockIdx.y] = 1; }
+        return;
+    }
+    const int j1 = min(j0 + TB, ng);
+    for (int i = j0 + t_id(); i < ng; i += NT) D[i] = M[(nw + i) + (int64_t)(nw + i) * ld];
+    __syncthreads();
+    for (int j = j0; j < j1; ++j) {
+        double bv;
+        int bi;
+        wg_argmax(D, j, ng, rv, ri, bv, bi);
+        if (!(bv > tl)) {
+            if (t_id() == 0) { rank[blockIdx.y] = j; done[blockIdx.y] = 1; }
+            return;
+        }
+        const int J = nw + j;
+        if (bi != j) {
+            const int Q = nw + bi;
+            for (int q = t_id(); q < m; q += NT) {
+                if (q < J) {
+                    const double a = M[J + (int64_t)q * ld];
+                    M[J + (int64_t)q * ld] = M[Q + (int64_t)q * ld];
+                    M[Q + (int64_t)q * ld] = a;
+                } else if (q == J) {
+                    const double a = M[J + (int64_t)J * ld];
+                    M[J + (int64_t)J * ld] = M[Q + (int64_t)Q * ld];
+                    M[Q + (int64_t)Q * ld] = a;
+                    const double dd = D[j];
+                    D[j] = D[bi];
+                    D[bi] = dd;
+                } else if (q < Q) {
+                    const double a = M[q + (int64_t)J * ld];
+                    M[q + (int64_t)J * ld] = M[Q + (int64_t)q * ld];
+                    M[Q + (int64_t)q * ld] = a;
+                } else if (q > Q) {
+                    const double a = M[q + (int64_t)J * ld];
+                    M[q + (int64_t)J * ld] = M[q + (int64_t)Q * ld];
+                    M[q + (int64_t)Q * ld] = a;
+                }
+            }
+            __syncthreads();
+        }
+        const double ljj = sqrt(D[j]);
+        const double inv = 1.0 / ljj;
+        for (int i = j + 1 + t_id(); i < ng; i += NT) {
+            double c = M[(nw + i) + (int64_t)J * ld];
+            for (int k = j0; k < j; ++k) c -= M[(nw + i) + (int64_t)(nw + k) * ld] * M[J + (int64_t)(nw + k) * ld];
+            c *= inv;
+            M[(nw + i) + (int64_t)J * ld] = c;
+            D[i] -= c * c;
+        }
+        __syncthreads();
+        if (t_id() == 0) M[J + (int64_t)J * ld] = ljj;
+        __syncthreads();
+    }
+    if (t_id() == 0) {
+        rank[blockIdx.y] = j1;
+        if (j1 == ng) done[blockIdx.y] = 1;
+    }
 }
 
 // ---------------------------------------------------------------- triangular solves
@@ -414,6 +525,48 @@ void Batched::potrf(double* base, const std::vector<View>& a, double* d_minpiv) 
         }
     }
     chk(hipGetLastError(), "batched potrf");
+}
+
+void Batched::pstrf_trailing(double* base, const std::vector<View>& a, const std::vector<int32_t>& lead,
+                             const double* d_tol, std::vector<int32_t>& rank) {
+    rank.assign(a.size(), 0);
+    if (a.empty()) return;
+    const size_t nv = a.size();
+    std::vector<View> g(nv);
+    std::vector<int64_t> doff(nv + 1, 0);
+    int max_ng = 0;
+    for (size_t b = 0; b < nv; ++b) {
+        const int ng = a[b].rows - lead[b];
+        if (ng < 0 || a[b].rows != a[b].cols) throw std::runtime_error("batched pstrf: bad view");
+        g[b] = View{a[b].off + lead[b] + (int64_t)lead[b] * a[b].ld, a[b].ld, ng, ng, 0};
+        doff[b + 1] = doff[b] + ng;
+        max_ng = std::max(max_ng, ng);
+    }
+    View* dv = put(0, a);
+    View* dg = put(1, g);
+    int32_t* d_lead = (int32_t*)alloc(ctx, nv * sizeof(int32_t));
+    int64_t* d_doff = (int64_t*)alloc(ctx, (nv + 1) * sizeof(int64_t));
+    double* d_diag = (double*)alloc(ctx, std::max<int64_t>(doff[nv], 1) * sizeof(double));
+    int32_t* d_state = (int32_t*)alloc(ctx, 2 * nv * sizeof(int32_t));
+    chk(hipMemcpyAsync(d_lead, lead.data(), nv * sizeof(int32_t), hipMemcpyHostToDevice, st), "pstrf upload");
+    chk(hipMemcpyAsync(d_doff, doff.data(), (nv + 1) * sizeof(int64_t), hipMemcpyHostToDevice, st), "pstrf upload");
+    chk(hipMemsetAsync(d_state, 0, 2 * nv * sizeof(int32_t), st), "pstrf state");
+    int32_t* d_rank = d_state;
+    int32_t* d_done = d_state + nv;
+    const unsigned nm = (unsigned)nv;
+    const int nt = (max_ng + TB - 1) / TB;
+    for (int kb = 0; kb < nt; ++kb) {
+        hipLaunchKernelGGL(k_pstrf_panel, dim3(1, nm), dim3(NT), 0, st, base, dv, d_lead, kb, d_tol, d_doff, d_diag,
+                           d_rank, d_done);
+        const int64_t m = nt - kb - 1;
+        if (m > 0)
+            hipLaunchKernelGGL(k_potrf_update, dim3((unsigned)(m * (m + 1) / 2), nm), dim3(NT), 0, st, base, dg, kb,
+                               kb + 1, kb + 1, nt, (const int32_t*)d_done);
+    }
+    chk(hipGetLastError(), "batched pstrf");
+    chk(hipMemcpyAsync(rank.data(), d_rank, nv * sizeof(int32_t), hipMemcpyDeviceToHost, st), "pstrf rank");
+    chk(hipStreamSynchronize(st), "pstrf sync");
+    for (void* p : {(void*)d_lead, (void*)d_doff, (void*)d_diag, (void*)d_state}) release(ctx, p);
 }
 
 void Batched::trsm(const double* lbase, const std::vector<View>& l, double* bbase, const std::vector<View>& b,

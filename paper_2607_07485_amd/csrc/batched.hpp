@@ -35,6 +35,17 @@ struct Batched {
     // Cholesky A = L L^T (lower, in place) of every square view of `a`;
     // minpiv[b] receives the smallest pivot d_j of view b (<= 0: failure).
     void potrf(double* base, const std::vector<View>& a, double* d_minpiv);
+    // Diagonally pivoted Cholesky of the trailing block of every square view:
+    // indices lead[b] .. rows-1 of view b are eliminated, each time the one with
+    // the largest remaining diagonal entry (lowest index among equal ones), until
+    // that entry is at most d_tol[b]; rank[b] receives the number eliminated.
+    // Pivots are swapped into place symmetrically across the whole view, so the
+    // leading block stays where it is and the rows lead[b] .. lead[b]+rank-1 of
+    // the coupling block are the pivot rows.  On return the first rank[b]
+    // columns of the trailing block hold the factor (lower triangle).  Only the
+    // lower triangle of the view is read and kept consistent.
+    void pstrf_trailing(double* base, const std::vector<View>& a, const std::vector<int32_t>& lead,
+                        const double* d_tol, std::vector<int32_t>& rank);
     // B <- L^{-1} B (trans = false) or B <- L^{-T} B (trans = true) with L the
     // lower triangle of the square view l[b] and B the view b[b] (rows = n).
     // lower_b (forward only): B is lower triangular (e.g. the identity), so

@@ -445,14 +445,17 @@ __global__ void __launch_bounds__(WG) k_prolong_b(const int32_t* items, const in
 // ascending order (fixed order) and adds it to x (entries with a negative DOF are
 // skipped): subdomains of one colour are disjoint, so the update needs no partial
 // sums.  The LDS is sized by the launch's largest overlap (max_m), so small
-// overlaps leave room for more waves per CU.
-template <typename T, int NR>
+// overlaps leave room for more waves per CU.  FACT: the packed triangle is a
+// lower-triangular factor X and the local solve is X^T (X r): lane i first forms
+// w_i = sum_{j <= i} X_ij r_j into LDS, then y_i = sum_{j >= i} X_ji w_j.
+template <typename T, int NR, bool FACT>
 __global__ void __launch_bounds__(64) k_small_sub(int32_t s0, const int64_t* sub_off, const int32_t* sub_dofs,
                                                   const int64_t* pk_off, const T* pk, const T* rloc, T* x,
                                                   int max_m) {
     extern __shared__ __align__(16) unsigned char s_small[];
     T* s_a = reinterpret_cast<T*>(s_small);
     T* s_x = s_a + max_m * (max_m + 1) / 2;
+    T* s_w = s_x + max_m * NR;
     const int s = s0 + blockIdx.x;
     const int lane = tid();
     const int64_t o = sub_off[s];
@@ -462,16 +465,41 @@ __global__ void __launch_bounds__(64) k_small_sub(int32_t s0, const int64_t* sub
     for (int e = lane; e < np; e += 64) s_a[e] = A[e];
     for (int e = lane; e < m * NR; e += 64) s_x[e] = rloc[o * NR + e];
     __syncthreads();
+    if (FACT) {
+        if (lane < m) {
+            const int i = lane;
+            const int ri = i * (i + 1) / 2;
+            T wv[NR];
+#pragma unroll
+            for (int k = 0; k < NR; ++k) wv[k] = 0;
+            for (int j = 0; j <= i; ++j) {
+                const T a = s_a[ri + j];
+#pragma unroll
+                for (int k = 0; k < NR; ++k) wv[k] += a * s_x[j * NR + k];
+            }
+#pragma unroll
+            for (int k = 0; k < NR; ++k) s_w[i * NR + k] = wv[k];
+        }
+        __syncthreads();
+    }
     if (lane < m) {
         const int i = lane;
         const int ri = i * (i + 1) / 2;
         T y[NR];
 #pragma unroll
         for (int k = 0; k < NR; ++k) y[k] = 0;
-        for (int j = 0; j < m; ++j) {
-            const T a = s_a[j <= i ? ri + j : j * (j + 1) / 2 + i];
+        if (FACT) {
+            for (int j = i; j < m; ++j) {
+                const T a = s_a[j * (j + 1) / 2 + i];
 #pragma unroll
-            for (int k = 0; k < NR; ++k) y[k] += a * s_x[j * NR + k];
+                for (int k = 0; k < NR; ++k) y[k] += a * s_w[j * NR + k];
+            }
+        } else {
+            for (int j = 0; j < m; ++j) {
+                const T a = s_a[j <= i ? ri + j : j * (j + 1) / 2 + i];
+#pragma unroll
+                for (int k = 0; k < NR; ++k) y[k] += a * s_x[j * NR + k];
+            }
         }
         const int32_t d = sub_dofs[o + i];   // < 0: masked entry
         if (d >= 0) {
@@ -893,12 +921,19 @@ void launch_pcg_start(int64_t len, const double* b, double* r, double* x, hipStr
 
 template <typename T, int NR>
 void launch_small_sub(int64_t s0, int64_t n_sub, const int64_t* sub_off, const int32_t* sub_dofs,
-                      const int64_t* pk_off, const T* pk, const T* rloc, T* x, int max_m, hipStream_t st) {
+                      const int64_t* pk_off, const T* pk, const T* rloc, T* x, int max_m, hipStream_t st,
+                      bool fact) {
     if (n_sub <= 0) return;
     if (max_m < 1 || max_m > SMALL_M) throw std::runtime_error("launch_small_sub: max_m outside 1 .. SMALL_M");
-    const size_t lds = ((size_t)max_m * (max_m + 1) / 2 + (size_t)max_m * NR) * sizeof(T);
-    hipLaunchKernelGGL((k_small_sub<T, NR>), dim3((unsigned)n_sub), dim3(64), lds, st, (int32_t)s0, sub_off, sub_dofs,
-                       pk_off, pk, rloc, x, max_m);
+    if (fact) {
+        const size_t lds = ((size_t)max_m * (max_m + 1) / 2 + 2 * (size_t)max_m * NR) * sizeof(T);
+        hipLaunchKernelGGL((k_small_sub<T, NR, true>), dim3((unsigned)n_sub), dim3(64), lds, st, (int32_t)s0,
+                           sub_off, sub_dofs, pk_off, pk, rloc, x, max_m);
+    } else {
+        const size_t lds = ((size_t)max_m * (max_m + 1) / 2 + (size_t)max_m * NR) * sizeof(T);
+        hipLaunchKernelGGL((k_small_sub<T, NR, false>), dim3((unsigned)n_sub), dim3(64), lds, st, (int32_t)s0,
+                           sub_off, sub_dofs, pk_off, pk, rloc, x, max_m);
+    }
 }
 
 template <typename T, int NR>
@@ -920,7 +955,7 @@ void launch_prolong_small(int64_t na, const int32_t* agg_of_p, const int64_t* ag
 
 #define LSDD_SMALL_INST(T, NR)                                                                                     \
     template void launch_small_sub<T, NR>(int64_t, int64_t, const int64_t*, const int32_t*, const int64_t*,        \
-                                          const T*, const T*, T*, int, hipStream_t);                                \
+                                          const T*, const T*, T*, int, hipStream_t, bool);                          \
     template void launch_restrict_small<T, NR>(int64_t, const int32_t*, const int64_t*, const int32_t*,            \
                                                const int64_t*, const int64_t*, const T*, const T*, T*, hipStream_t); \
     template void launch_prolong_small<T, NR>(int64_t, const int32_t*, const int64_t*, const int32_t*,             \

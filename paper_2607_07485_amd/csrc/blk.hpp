@@ -40,10 +40,12 @@ constexpr int SMALL_M = 64;   // overlaps and aggregates up to this size use the
 
 // x[Omega_s] += A_Omega_s^{-1} rloc[Omega_s] for the sweep-order subdomains s0 .. s0+n_sub-1
 // (packed lower inverses at pk + pk_off[s]; rloc and x hold NR interleaved vectors);
-// max_m (1 .. SMALL_M) bounds |Omega_s| over the launch and sizes its LDS
+// max_m (1 .. SMALL_M) bounds |Omega_s| over the launch and sizes its LDS.  fact: the
+// packed triangles are lower-triangular factors X with A_Omega^{-1} = X^T X
 template <typename T, int NR>
 void launch_small_sub(int64_t s0, int64_t n_sub, const int64_t* sub_off, const int32_t* sub_dofs,
-                      const int64_t* pk_off, const T* pk, const T* rloc, T* x, int max_m, hipStream_t st);
+                      const int64_t* pk_off, const T* pk, const T* rloc, T* x, int max_m, hipStream_t st,
+                      bool fact = false);
 // rc[c] = Z_i[:, c - coff_i]^T t[omega_i] for every coarse DOF c of an aggregate i
 // with agg_of_c[c] = i (agg_of_c[c] < 0: skipped)
 template <typename T, int NR>

@@ -289,58 +289,6 @@ __device__ inline void wg_sort_eig(const double* a, int lda, const double* v, in
 
 namespace lsdd {
 
-// ---------------------------------------------------------------- interface elimination
-
-// Schur complement onto the leading nw indices of a symmetric PSD m x m matrix
-// `a` (column-major, ld m) by diagonally pivoted elimination of the trailing
-// ng = m - nw (interface) indices: the largest remaining interface diagonal is
-// eliminated while it exceeds `tol`; the leading block of the updated matrix is
-// then S = A_ww - A_wP A_PP^{-1} A_Pw over the eliminated set P, a generalized
-// inverse of the interface block (the Moore-Penrose Schur complement when the
-// remaining interface part is zero).  LDS scratch: col (m doubles), done (m
-// chars), rv/ri (LSDD_WG/64 each).  Returns the number of eliminated indices.
-__device__ inline int wg_schur_pivoted(double* a, int m, int nw, double tol, double* col, unsigned char* done,
-                                       double* rv, int* ri) {
-    for (int i = tid(); i < m; i += LSDD_WG) done[i] = 0;
-    __syncthreads();
-    int npiv = 0;
-    while (true) {
-        // argmax of the remaining interface diagonal
-        double bv = -1.0;
-        int bi = -1;
-        for (int i = nw + tid(); i < m; i += LSDD_WG) {
-            if (done[i]) continue;
-            double d = a[i + (long long)i * m];
-            if (d > bv) { bv = d; bi = i; }
-        }
-        for (int off = 32; off > 0; off >>= 1) {
-            double ov = __shfl_xor(bv, off, 64);
-            int oi = __shfl_xor(bi, off, 64);
-            if (ov > bv || (ov == bv && oi >= 0 && (bi < 0 || oi < bi))) { bv = ov; bi = oi; }
-        }
-        if ((tid() & 63) == 0) { rv[tid() >> 6] = bv; ri[tid() >> 6] = bi; }
-        __syncthreads();
-        bv = rv[0];
-        bi = ri[0];
-        for (int w = 1; w < LSDD_WG / 64; ++w)
-            if (rv[w] > bv || (rv[w] == bv && ri[w] >= 0 && (bi < 0 || ri[w] < bi))) { bv = rv[w]; bi = ri[w]; }
-        __syncthreads();
-        if (bi < 0 || !(bv > tol)) break;
-        const double s = 1.0 / sqrt(bv);
-        for (int i = tid(); i < m; i += LSDD_WG) col[i] = done[i] ? 0.0 : a[i + (long long)bi * m] * s;
-        __syncthreads();
-        if (tid() == 0) done[bi] = 1;
-        for (long long idx = tid(); idx < (long long)m * m; idx += LSDD_WG) {
-            int i = (int)(idx % m), k = (int)(idx / m);
-            double ci = col[i], ck = col[k];
-            if (ci != 0.0 && ck != 0.0) a[i + (long long)k * m] -= ci * ck;
-        }
-        __syncthreads();
-        ++npiv;
-    }
-    return npiv;
-}
-
 // ---------------------------------------------------------------- tridiagonal eigensolver
 
 // Householder reduction of the symmetric n x n matrix a (column-major, both

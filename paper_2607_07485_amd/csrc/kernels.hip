@@ -329,7 +329,7 @@ __global__ void k_scale_blocks(int64_t n_elem, const int64_t* blk_off, const dou
 __global__ void __launch_bounds__(WG) k_elem_bilinear(int64_t n_elem, const int64_t* elem_ptr,
                                                       const int32_t* elem_dofs, const int64_t* blk_off,
                                                       const double* blocks, const double* u, const double* v,
-                                                      double* out) {
+                                                      int32_t nrhs, int64_t ld, double scale, double* out) {
     const int lane = tid() & 63;
     const int64_t e = (int64_t)blockIdx.x * (WG / 64) + (tid() >> 6);
     if (e >= n_elem) return;
@@ -337,14 +337,18 @@ __global__ void __launch_bounds__(WG) k_elem_bilinear(int64_t n_elem, const int6
     const int ne = (int)(elem_ptr[e + 1] - base);
     const double* B = blocks + blk_off[e];
     double acc = 0.0;
-    for (int j = lane; j < ne; j += 64) {
-        const double vj = v[elem_dofs[base + j]];
-        double t = 0.0;
-        for (int i = 0; i < ne; ++i) t += u[elem_dofs[base + i]] * B[(int64_t)i * ne + j];
-        acc += t * vj;
+    for (int32_t k = 0; k < nrhs; ++k) {
+        const double* uk = u + (int64_t)k * ld;
+        const double* vk = v + (int64_t)k * ld;
+        for (int j = lane; j < ne; j += 64) {
+            const double vj = vk[elem_dofs[base + j]];
+            double t = 0.0;
+            for (int i = 0; i < ne; ++i) t += uk[elem_dofs[base + i]] * B[(int64_t)i * ne + j];
+            acc += t * vj;
+        }
     }
     acc = wave_sum(acc);
-    if (lane == 0) out[e] = acc;
+    if (lane == 0) out[e] = scale * acc;
 }
 
 // ====================================================================== local problems
@@ -609,16 +613,17 @@ __global__ void k_to_f64(int64_t n, const float* a, double* b) {
 // out[t] = r[rows[t]] - sum_q A[rows[t], q] x[q]; L lanes per row (16 for
 // short rows, a whole wave for the long rows of coarse levels).  The matrix
 // streams (values, column indices) are read non-temporally, the gathered x
-// through the caches.
-template <typename T, int L>
+// through the caches.  Values of type V (FP64 values with FP32 vectors: the
+// products and the sum are formed in FP64 and rounded once).
+template <typename T, typename V, int L>
 __global__ void __launch_bounds__(WG) k_csr_resid_rows(int64_t nrows, const int32_t* rows, const int64_t* rowptr,
-                                                       const int32_t* col, const T* val, const T* x, const T* r,
+                                                       const int32_t* col, const V* val, const T* x, const T* r,
                                                        T* out, int x_zero) {
     const int lane = tid() & (L - 1);
     const int64_t stride = (int64_t)gridDim.x * (WG / L);
     for (int64_t t = ((int64_t)blockIdx.x * WG + tid()) / L; t < nrows; t += stride) {
         const int32_t p = rows[t];   // < 0: masked entry, out = 0
-        T s = 0;
+        V s = 0;
         if (!x_zero && p >= 0) {
             // up to 4 entries per lane in flight: all column indices, then all
             // gathers, then the products (two dependent loads per entry).  The
@@ -628,7 +633,8 @@ __global__ void __launch_bounds__(WG) k_csr_resid_rows(int64_t nrows, const int3
             const int64_t q1 = rowptr[p + 1], qlast = q1 - 1;
             for (int64_t q0 = rowptr[p] + lane; q0 < q1; q0 += 4 * L) {
                 int32_t c[4];
-                T v[4], xv[4];
+                V v[4];
+                T xv[4];
 #pragma unroll
                 for (int u = 0; u < 4; ++u) {
                     const int64_t q = min(q0 + u * L, qlast);
@@ -638,17 +644,18 @@ __global__ void __launch_bounds__(WG) k_csr_resid_rows(int64_t nrows, const int3
 #pragma unroll
                 for (int u = 0; u < 4; ++u) xv[u] = x[c[u]];
 #pragma unroll
-                for (int u = 0; u < 4; ++u) s += (q0 + u * L < q1 ? v[u] : (T)0) * xv[u];
+                for (int u = 0; u < 4; ++u) s += (q0 + u * L < q1 ? v[u] : (V)0) * (V)xv[u];
             }
         }
         for (int off = L / 2; off > 0; off >>= 1) s += __shfl_xor(s, off, L);
-        if (lane == 0) out[t] = p >= 0 ? r[p] - s : (T)0;
+        if (lane == 0) out[t] = p >= 0 ? (T)((V)r[p] - s) : (T)0;
     }
 }
 
-// y = A x, or y = r_minus - A x when r_minus != nullptr
-template <typename T, int L>
-__global__ void __launch_bounds__(WG) k_csr_spmv(int64_t n, const int64_t* rowptr, const int32_t* col, const T* val,
+// y = A x, or y = r_minus - A x when r_minus != nullptr (values of type V as in
+// k_csr_resid_rows)
+template <typename T, typename V, int L>
+__global__ void __launch_bounds__(WG) k_csr_spmv(int64_t n, const int64_t* rowptr, const int32_t* col, const V* val,
                                                  const T* x, T* y, const T* r_minus) {
     const int lane = tid() & (L - 1);
     const int64_t stride = (int64_t)gridDim.x * (WG / L);
@@ -656,10 +663,11 @@ __global__ void __launch_bounds__(WG) k_csr_spmv(int64_t n, const int64_t* rowpt
         // as in k_csr_resid_rows: 4 entries per lane in flight, loads without lane
         // conditions (slots past the row's end re-read its last entry and add zero)
         const int64_t q1 = rowptr[p + 1], qlast = q1 - 1;
-        T s = 0;
+        V s = 0;
         for (int64_t q0 = rowptr[p] + lane; q0 < q1; q0 += 4 * L) {
             int32_t c[4];
-            T v[4], xv[4];
+            V v[4];
+            T xv[4];
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
                 const int64_t q = min(q0 + u * L, qlast);
@@ -669,10 +677,10 @@ __global__ void __launch_bounds__(WG) k_csr_spmv(int64_t n, const int64_t* rowpt
 #pragma unroll
             for (int u = 0; u < 4; ++u) xv[u] = x[c[u]];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) s += (q0 + u * L < q1 ? v[u] : (T)0) * xv[u];
+            for (int u = 0; u < 4; ++u) s += (q0 + u * L < q1 ? v[u] : (V)0) * (V)xv[u];
         }
         for (int off = L / 2; off > 0; off >>= 1) s += __shfl_xor(s, off, L);
-        if (lane == 0) y[p] = r_minus ? r_minus[p] - s : s;
+        if (lane == 0) y[p] = r_minus ? (T)((V)r_minus[p] - s) : (T)s;
     }
 }
 
@@ -690,7 +698,13 @@ __global__ void __launch_bounds__(WG) k_csr_spmv(int64_t n, const int64_t* rowpt
 // per (tile row, chunk), column parts per tile -- that k_sub_finalize sums in a
 // fixed order, so the smoother is the same linear map on every application (no
 // order-dependent atomics).
-template <typename T>
+//
+// MODE 1 and 2 apply a lower-triangular factor X (same tile storage, zero above
+// the diagonal) for the local solve X^T (X r): MODE 1 forms the row parts of
+// X r only (finalized without column parts), MODE 2 the column parts of X^T w
+// only, the diagonal tile's transposed product (diagonal included) going into
+// the row part of its item.
+template <typename T, int MODE>
 __global__ void __launch_bounds__(WG) k_sub_symv(const int32_t* items, const int64_t* sub_off, const int64_t* tp_off,
                                                  const T* tiles, const T* rloc, const int64_t* scr_off, T* scr,
                                                  int chl) {
@@ -746,11 +760,14 @@ __global__ void __launch_bounds__(WG) k_sub_symv(const int32_t* items, const int
         for (int q = 0; q < 16; ++q) {
             const int r = w + 4 * q;
             const T a = (dg && lane > r) ? (T)0 : v[q];
-            p[q] += a * xj;
-            col += ((dg && lane == r) ? (T)0 : a) * s_xi[r];
+            if (MODE != 2) p[q] += a * xj;
+            if (MODE == 0) col += ((dg && lane == r) ? (T)0 : a) * s_xi[r];
+            if (MODE == 2) col += a * s_xi[r];
         }
-        if (dg) s_d[w][lane] = col;
-        else s_c[w][jj][lane] = col;
+        if (MODE != 1) {
+            if (dg) s_d[w][lane] = col;
+            else s_c[w][jj][lane] = col;
+        }
     };
     fetch(va, 0);
 #pragma unroll
@@ -764,22 +781,27 @@ __global__ void __launch_bounds__(WG) k_sub_symv(const int32_t* items, const int
             use(vb, jj + 1);
         }
     }
+    if (MODE != 2) {
 #pragma unroll
-    for (int q = 0; q < 16; ++q) {
-        T v = p[q];
-        for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-        p[q] = v;
+        for (int q = 0; q < 16; ++q) {
+            T v = p[q];
+            for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+            p[q] = v;
+        }
     }
     __syncthreads();
     if (lane < 16) {
         T y = 0;
+        if (MODE != 2) {
 #pragma unroll
-        for (int q = 0; q < 16; ++q)
-            if (q == lane) y = p[q];
+            for (int q = 0; q < 16; ++q)
+                if (q == lane) y = p[q];
+        }
         const int r = w + 4 * lane;
-        if (ncol < nJ) y += (s_d[0][r] + s_d[1][r]) + (s_d[2][r] + s_d[3][r]);
+        if (MODE != 1 && ncol < nJ) y += (s_d[0][r] + s_d[1][r]) + (s_d[2][r] + s_d[3][r]);
         part[(symv_rowpart_off(I, chl) + ch) * 64 + r] = y;
     }
+    if (MODE == 1) return;
     for (int a = tid(); a < ncol * 64; a += WG) {
         const int jj = a >> 6, l = a & 63;
         colpart[((int64_t)I * (I - 1) / 2 + J0 + jj) * 64 + l] =
@@ -790,7 +812,7 @@ __global__ void __launch_bounds__(WG) k_sub_symv(const int32_t* items, const int
 // x[Omega_s[c]] (+)= row-part chunks of tile row J(c) + column parts of the
 // tile rows below.  FL threads per DOF each sum a fixed strided subset of the
 // partials; the FL sums are added in LDS in ascending order (fixed order).
-template <typename T, int FL>
+template <typename T, int FL, bool COLS>
 __global__ void __launch_bounds__(WG) k_sub_finalize(int64_t r0, int64_t r1, const int32_t* pos_sub,
                                                      const int64_t* sub_off, const int64_t* scr_off, const T* scr,
                                                      const int32_t* sub_dofs, T* x, int accumulate, int chl) {
@@ -808,7 +830,7 @@ __global__ void __launch_bounds__(WG) k_sub_finalize(int64_t r0, int64_t r1, con
         const T* part = scr + scr_off[s] + symv_rowpart_off(J, chl) * 64 + l;
         const T* colpart = scr + scr_off[s] + symv_rowpart_off(nt, chl) * 64 + l;
         const int nch = (J + chl) / chl;
-        const int K = nch + (nt - 1 - J);
+        const int K = COLS ? nch + (nt - 1 - J) : nch;
         // one load per partial, its address chosen without a branch so that the
         // unrolled loads are all in flight before the first wait
 #pragma unroll 4
@@ -847,7 +869,7 @@ __global__ void k_pack_tiles(const int64_t* sub_ptr, const int64_t* inv_off, con
         int J = (int)(t - (int64_t)I * (I + 1) / 2);
         int r = I * 64 + (e >> 6), c = J * 64 + (e & 63);
         double v = (r < m && c < m) ? M[r + (int64_t)c * m] : 0.0;
-        tiles[tp_off[ag] + idx] = v;
+        if (tiles) tiles[tp_off[ag] + idx] = v;
         if (tiles32) tiles32[tp_off[ag] + idx] = (float)v;
     }
 }
@@ -866,7 +888,7 @@ __global__ void k_pack_small(const int64_t* sub_ptr, const int64_t* inv_off, con
         while ((i + 1) * (i + 2) / 2 <= e) ++i;
         const int j = e - i * (i + 1) / 2;
         const double v = M[i + (int64_t)j * m];
-        pk[pk_off[ag] + e] = v;
+        if (pk) pk[pk_off[ag] + e] = v;
         if (pk32) pk32[pk_off[ag] + e] = (float)v;
     }
 }
@@ -1061,10 +1083,11 @@ void launch_scale_blocks(int64_t n_elem, const int64_t* blk_off, const double* s
 }
 
 void launch_elem_bilinear(int64_t n_elem, const int64_t* elem_ptr, const int32_t* elem_dofs, const int64_t* blk_off,
-                          const double* blocks, const double* u, const double* v, double* out, hipStream_t st) {
+                          const double* blocks, const double* u, const double* v, int32_t nrhs, int64_t ld,
+                          double scale, double* out, hipStream_t st) {
     if (n_elem <= 0) return;
     hipLaunchKernelGGL(k_elem_bilinear, dim3(grid_for(n_elem * 64)), dim3(WG), 0, st, n_elem, elem_ptr, elem_dofs,
-                       blk_off, blocks, u, v, out);
+                       blk_off, blocks, u, v, nrhs, ld, scale, out);
 }
 
 void launch_local_assemble(int32_t nbatch, const LocalArgs& a, int32_t max_m, hipStream_t st) {
@@ -1126,64 +1149,76 @@ void launch_to_f64(int64_t n, const float* a, double* b, hipStream_t st) {
     hipLaunchKernelGGL(k_to_f64, dim3(grid_for(n)), dim3(WG), 0, st, n, a, b);
 }
 
-template <typename T>
-void launch_csr_resid_rows(int64_t nrows, const int32_t* rows, const int64_t* rowptr, const int32_t* col, const T* val,
+template <typename T, typename V>
+void launch_csr_resid_rows(int64_t nrows, const int32_t* rows, const int64_t* rowptr, const int32_t* col, const V* val,
                            const T* x, const T* r, T* out, bool x_zero, int lanes, hipStream_t st) {
     if (nrows <= 0) return;
     const int xz = x_zero ? 1 : 0;
     if (lanes >= 64)
-        hipLaunchKernelGGL((k_csr_resid_rows<T, 64>), dim3(grid_for(nrows * 64)), dim3(WG), 0, st, nrows, rows, rowptr,
-                           col, val, x, r, out, xz);
+        hipLaunchKernelGGL((k_csr_resid_rows<T, V, 64>), dim3(grid_for(nrows * 64)), dim3(WG), 0, st, nrows, rows,
+                           rowptr, col, val, x, r, out, xz);
     else if (lanes >= 32)
-        hipLaunchKernelGGL((k_csr_resid_rows<T, 32>), dim3(grid_for(nrows * 32)), dim3(WG), 0, st, nrows, rows, rowptr,
-                           col, val, x, r, out, xz);
+        hipLaunchKernelGGL((k_csr_resid_rows<T, V, 32>), dim3(grid_for(nrows * 32)), dim3(WG), 0, st, nrows, rows,
+                           rowptr, col, val, x, r, out, xz);
     else if (lanes >= 16)
-        hipLaunchKernelGGL((k_csr_resid_rows<T, 16>), dim3(grid_for(nrows * 16)), dim3(WG), 0, st, nrows, rows, rowptr,
-                           col, val, x, r, out, xz);
+        hipLaunchKernelGGL((k_csr_resid_rows<T, V, 16>), dim3(grid_for(nrows * 16)), dim3(WG), 0, st, nrows, rows,
+                           rowptr, col, val, x, r, out, xz);
     else
-        hipLaunchKernelGGL((k_csr_resid_rows<T, 8>), dim3(grid_for(nrows * 8)), dim3(WG), 0, st, nrows, rows, rowptr,
-                           col, val, x, r, out, xz);
+        hipLaunchKernelGGL((k_csr_resid_rows<T, V, 8>), dim3(grid_for(nrows * 8)), dim3(WG), 0, st, nrows, rows,
+                           rowptr, col, val, x, r, out, xz);
 }
-template <typename T>
-void launch_csr_spmv(int64_t n, const int64_t* rowptr, const int32_t* col, const T* val, const T* x, T* y,
+template <typename T, typename V>
+void launch_csr_spmv(int64_t n, const int64_t* rowptr, const int32_t* col, const V* val, const T* x, T* y,
                      const T* r_minus, int lanes, hipStream_t st) {
     if (n <= 0) return;
     if (lanes >= 64)
-        hipLaunchKernelGGL((k_csr_spmv<T, 64>), dim3(grid_for(n * 64)), dim3(WG), 0, st, n, rowptr, col, val, x, y,
+        hipLaunchKernelGGL((k_csr_spmv<T, V, 64>), dim3(grid_for(n * 64)), dim3(WG), 0, st, n, rowptr, col, val, x, y,
                            r_minus);
     else if (lanes >= 32)
-        hipLaunchKernelGGL((k_csr_spmv<T, 32>), dim3(grid_for(n * 32)), dim3(WG), 0, st, n, rowptr, col, val, x, y,
+        hipLaunchKernelGGL((k_csr_spmv<T, V, 32>), dim3(grid_for(n * 32)), dim3(WG), 0, st, n, rowptr, col, val, x, y,
                            r_minus);
     else if (lanes >= 16)
-        hipLaunchKernelGGL((k_csr_spmv<T, 16>), dim3(grid_for(n * 16)), dim3(WG), 0, st, n, rowptr, col, val, x, y,
+        hipLaunchKernelGGL((k_csr_spmv<T, V, 16>), dim3(grid_for(n * 16)), dim3(WG), 0, st, n, rowptr, col, val, x, y,
                            r_minus);
     else
-        hipLaunchKernelGGL((k_csr_spmv<T, 8>), dim3(grid_for(n * 8)), dim3(WG), 0, st, n, rowptr, col, val, x, y,
+        hipLaunchKernelGGL((k_csr_spmv<T, V, 8>), dim3(grid_for(n * 8)), dim3(WG), 0, st, n, rowptr, col, val, x, y,
                            r_minus);
+}
+template <typename T, int MODE>
+static void sub_symv_mode(int64_t n_items, const int32_t* items, const int64_t* sub_off, const int64_t* tp_off,
+                          const T* tiles, const T* rloc, const int64_t* scr_off, T* scr, int chl, hipStream_t st) {
+    hipEvent_t e0, e1;
+    if (take_launch_events(&e0, &e1))
+        hipExtLaunchKernelGGL((k_sub_symv<T, MODE>), dim3((unsigned)n_items), dim3(WG), 0, st, e0, e1, 0, items,
+                              sub_off, tp_off, tiles, rloc, scr_off, scr, chl);
+    else
+        hipLaunchKernelGGL((k_sub_symv<T, MODE>), dim3((unsigned)n_items), dim3(WG), 0, st, items, sub_off, tp_off,
+                           tiles, rloc, scr_off, scr, chl);
 }
 template <typename T>
 void launch_sub_symv(int64_t n_items, const int32_t* items, const int64_t* sub_off, const int64_t* tp_off,
-                     const T* tiles, const T* rloc, const int64_t* scr_off, T* scr, int chl, hipStream_t st) {
+                     const T* tiles, const T* rloc, const int64_t* scr_off, T* scr, int chl, hipStream_t st,
+                     int mode) {
     if (n_items <= 0) return;
-    hipEvent_t e0, e1;
-    if (take_launch_events(&e0, &e1))
-        hipExtLaunchKernelGGL(k_sub_symv<T>, dim3((unsigned)n_items), dim3(WG), 0, st, e0, e1, 0, items, sub_off,
-                              tp_off, tiles, rloc, scr_off, scr, chl);
-    else
-        hipLaunchKernelGGL(k_sub_symv<T>, dim3((unsigned)n_items), dim3(WG), 0, st, items, sub_off, tp_off, tiles,
-                           rloc, scr_off, scr, chl);
+    if (mode == 1) sub_symv_mode<T, 1>(n_items, items, sub_off, tp_off, tiles, rloc, scr_off, scr, chl, st);
+    else if (mode == 2) sub_symv_mode<T, 2>(n_items, items, sub_off, tp_off, tiles, rloc, scr_off, scr, chl, st);
+    else sub_symv_mode<T, 0>(n_items, items, sub_off, tp_off, tiles, rloc, scr_off, scr, chl, st);
 }
 template <typename T>
 void launch_sub_finalize(int64_t r0, int64_t r1, const int32_t* pos_sub, const int64_t* sub_off,
                          const int64_t* scr_off, const T* scr, const int32_t* sub_dofs, T* x, bool accumulate,
-                         int chl, int fl, hipStream_t st) {
+                         int chl, int fl, hipStream_t st, bool cols) {
     if (r1 <= r0) return;
-    if (fl >= 32)
-        hipLaunchKernelGGL((k_sub_finalize<T, 32>), dim3(grid_for(r1 - r0, WG / 32)), dim3(WG), 0, st, r0, r1,
-                           pos_sub, sub_off, scr_off, scr, sub_dofs, x, accumulate ? 1 : 0, chl);
+    const int acc = accumulate ? 1 : 0;
+    if (!cols)
+        hipLaunchKernelGGL((k_sub_finalize<T, 8, false>), dim3(grid_for(r1 - r0, WG / 8)), dim3(WG), 0, st, r0, r1,
+                           pos_sub, sub_off, scr_off, scr, sub_dofs, x, acc, chl);
+    else if (fl >= 32)
+        hipLaunchKernelGGL((k_sub_finalize<T, 32, true>), dim3(grid_for(r1 - r0, WG / 32)), dim3(WG), 0, st, r0, r1,
+                           pos_sub, sub_off, scr_off, scr, sub_dofs, x, acc, chl);
     else
-        hipLaunchKernelGGL((k_sub_finalize<T, 8>), dim3(grid_for(r1 - r0, WG / 8)), dim3(WG), 0, st, r0, r1,
-                           pos_sub, sub_off, scr_off, scr, sub_dofs, x, accumulate ? 1 : 0, chl);
+        hipLaunchKernelGGL((k_sub_finalize<T, 8, true>), dim3(grid_for(r1 - r0, WG / 8)), dim3(WG), 0, st, r0, r1,
+                           pos_sub, sub_off, scr_off, scr, sub_dofs, x, acc, chl);
 }
 
 int64_t sub_symv_scratch_len(int64_t m, int chl) { return symv_scratch_len((int)((m + 63) / 64), chl); }
@@ -1265,14 +1300,14 @@ void launch_check_finite(int64_t n, const double* a, int32_t* flag, hipStream_t 
 }
 
 #define LSDD_INST(T)                                                                                                  \
-    template void launch_csr_resid_rows<T>(int64_t, const int32_t*, const int64_t*, const int32_t*, const T*,        \
-                                           const T*, const T*, T*, bool, int, hipStream_t);                           \
-    template void launch_csr_spmv<T>(int64_t, const int64_t*, const int32_t*, const T*, const T*, T*, const T*, int, \
-                                     hipStream_t);                                                                    \
+    template void launch_csr_resid_rows<T, T>(int64_t, const int32_t*, const int64_t*, const int32_t*, const T*,     \
+                                              const T*, const T*, T*, bool, int, hipStream_t);                        \
+    template void launch_csr_spmv<T, T>(int64_t, const int64_t*, const int32_t*, const T*, const T*, T*, const T*,    \
+                                        int, hipStream_t);                                                            \
     template void launch_sub_symv<T>(int64_t, const int32_t*, const int64_t*, const int64_t*, const T*, const T*,    \
-                                     const int64_t*, T*, int, hipStream_t);                                           \
+                                     const int64_t*, T*, int, hipStream_t, int);                                      \
     template void launch_sub_finalize<T>(int64_t, int64_t, const int32_t*, const int64_t*, const int64_t*, const T*, \
-                                         const int32_t*, T*, bool, int, int, hipStream_t);                            \
+                                         const int32_t*, T*, bool, int, int, hipStream_t, bool);                      \
     template void launch_restrict<T>(int64_t, const int32_t*, const int64_t*, const int32_t*, const int64_t*,        \
                                      const int32_t*, const int64_t*, const T*, const T*, T*, hipStream_t);            \
     template void launch_prolong<T>(int64_t, const int32_t*, const int64_t*, const int32_t*, const int64_t*,         \
@@ -1280,5 +1315,10 @@ void launch_check_finite(int64_t n, const double* a, int32_t* flag, hipStream_t 
     template void launch_zero<T>(int64_t, T*, hipStream_t);
 LSDD_INST(double)
 LSDD_INST(float)
+template void launch_csr_resid_rows<float, double>(int64_t, const int32_t*, const int64_t*, const int32_t*,
+                                                   const double*, const float*, const float*, float*, bool, int,
+                                                   hipStream_t);
+template void launch_csr_spmv<float, double>(int64_t, const int64_t*, const int32_t*, const double*, const float*,
+                                             float*, const float*, int, hipStream_t);
 
 }  // namespace lsdd

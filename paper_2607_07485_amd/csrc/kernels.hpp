@@ -91,9 +91,11 @@ void launch_assemble_rows(int64_t n, const int64_t* d2e_ptr, const int32_t* d2e_
 void launch_theta_factor(int64_t n, const double* theta, const double* theta0, double* factor, hipStream_t st);
 // blocks of element e *= scale[e]
 void launch_scale_blocks(int64_t n_elem, const int64_t* blk_off, const double* scale, double* blocks, hipStream_t st);
-// out[e] = u_e^T B_e v_e
+// out[e] = scale * sum_k u_{k,e}^T B_e v_{k,e} over nrhs vectors at stride ld
 void launch_elem_bilinear(int64_t n_elem, const int64_t* elem_ptr, const int32_t* elem_dofs, const int64_t* blk_off,
-                          const double* blocks, const double* u, const double* v, double* out, hipStream_t st);
+                          const double* blocks, const double* u, const double* v, int32_t nrhs, int64_t ld,
+                          double scale, double* out, hipStream_t st);
+
 
 void launch_local_assemble(int32_t nbatch, const LocalArgs& a, int32_t max_m, hipStream_t st);
 // max_nw: largest |omega| of the batch (<= 4096)
@@ -138,23 +140,27 @@ void launch_to_f32(int64_t n, const double* a, float* b, hipStream_t st);
 void launch_to_f64(int64_t n, const float* a, double* b, hipStream_t st);
 
 // ---------------------------------------------------------------- solve
-// lanes per row: 16 or 64
-template <typename T>
+// lanes per row: 8, 16, 32 or 64.  V: value type (T, or double with T = float:
+// FP64 operator entries applied to FP32 vectors with FP64 sums)
+template <typename T, typename V = T>
 void launch_csr_resid_rows(int64_t nrows, const int32_t* rows, const int64_t* rowptr, const int32_t* col,
-                           const T* val, const T* x, const T* r, T* out, bool x_zero, int lanes, hipStream_t st);
-template <typename T>
-void launch_csr_spmv(int64_t n, const int64_t* rowptr, const int32_t* col, const T* val, const T* x, T* y,
+                           const V* val, const T* x, const T* r, T* out, bool x_zero, int lanes, hipStream_t st);
+template <typename T, typename V = T>
+void launch_csr_spmv(int64_t n, const int64_t* rowptr, const int32_t* col, const V* val, const T* x, T* y,
                      const T* r_minus, int lanes, hipStream_t st);
-// chl: tiles per work item (1..8); the scratch layout depends on it
+// chl: tiles per work item (1..8); the scratch layout depends on it.  mode 0:
+// symmetric inverse; mode 1 / 2: the two passes X r and X^T w of a lower
+// triangular factor X (mode 1 partials are finalized with cols = false)
 template <typename T>
 void launch_sub_symv(int64_t n_items, const int32_t* items, const int64_t* sub_off, const int64_t* tp_off,
-                     const T* tiles, const T* rloc, const int64_t* scr_off, T* scr, int chl, hipStream_t st);
+                     const T* tiles, const T* rloc, const int64_t* scr_off, T* scr, int chl, hipStream_t st,
+                     int mode = 0);
 // x[sub_dofs[t]] (+)= sum of the partials of entry t, for t in [r0, r1); sub_dofs NULL = identity;
-// fl: threads per entry (8 or 32)
+// fl: threads per entry (8 or 32); cols = false: row parts only
 template <typename T>
 void launch_sub_finalize(int64_t r0, int64_t r1, const int32_t* pos_sub, const int64_t* sub_off,
                          const int64_t* scr_off, const T* scr, const int32_t* sub_dofs, T* x, bool accumulate,
-                         int chl, int fl, hipStream_t st);
+                         int chl, int fl, hipStream_t st, bool cols = true);
 // scratch entries for a subdomain of size m; append its work items (s, tile row, chunk)
 int64_t sub_symv_scratch_len(int64_t m, int chl);
 void sub_symv_items(int32_t s, int64_t m, int chl, std::vector<int32_t>& items);

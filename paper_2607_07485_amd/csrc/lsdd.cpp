@@ -138,6 +138,7 @@ struct VecSet {
     T* t = nullptr;
     T* rloc = nullptr;
     T* scr = nullptr;
+    T* w = nullptr;      // factor-form local solves: X r per overlap entry
 };
 
 struct Level {
@@ -234,6 +235,9 @@ struct Level {
     double* d_inv = nullptr;          // full inverses during setup only
     double* d_tiles = nullptr;        // packed lower tiles of A_Omega^{-1}
     float* d_tiles32 = nullptr;
+    double* d_X = nullptr;            // full factors X = L^{-1} of A_Omega during setup (precision 2)
+    float* d_tfac32 = nullptr;        // packed lower tiles of X (FP32), A_Omega^{-1} = X^T X
+    float* d_pkfac32 = nullptr;       // packed lower triangles of X for the small overlaps (FP32)
     int64_t inv_len = 0, tiles_len = 0;
     // vectors: [0] single vectors, [1] blocks of NRB right-hand sides (allocated on first use)
     VecSet<double> v64[2];
@@ -305,7 +309,7 @@ struct Trace {
 }  // namespace lsdd
 
 struct lsdd_hierarchy {
-    int32_t cycle_prec = 0;       // 0 FP64 cycle, 1 FP32 cycle (needs params.precision == 1)
+    int32_t cycle_prec = 0;       // 0 FP64 cycle, 1 FP32 cycle (params.precision >= 1), 2 mixed (== 2)
     lsdd::Trace tr;
     lsdd_params prm;
     hipStream_t st = nullptr;
@@ -329,7 +333,7 @@ struct lsdd_hierarchy {
     double* d_factor = nullptr;   // scratch for lsdd_update_theta
     // hipGraph-captured halves of the PCG iteration: [block][cycle precision][half]
     bool use_graph = false;
-    hipGraphExec_t gx[2][2][2] = {};
+    hipGraphExec_t gx[2][3][2] = {};
 };
 
 namespace lsdd {
@@ -388,7 +392,7 @@ void assemble_operator(lsdd_hierarchy* h, Level& lv) {
             h->arena.release(d_dl);
         }
     }
-    if (h->prm.precision == 1) {
+    if (h->prm.precision >= 1) {
         lv.d_val32 = h->arena.alloc<float>(lv.nnz);
         launch_to_f32(lv.nnz, lv.d_val, lv.d_val32, h->st);
     }
@@ -401,13 +405,14 @@ void alloc_vectors(lsdd_hierarchy* h, Level& lv, int b) {
     const int64_t w = b ? NRB : 1;
     const int64_t nl = std::max<int64_t>({lv.rloc_len, lv.c_dofs ? lv.term_len : 0, 1}) * w;
     const int64_t ns = std::max<int64_t>({lv.scr_len, lv.c_scr_len, 1}) * w;
-    if (h->prm.precision == 1) {
+    if (h->prm.precision >= 1) {
         VecSet<float>& v = lv.v32[b];
         v.r = a.alloc<float>(lv.n * w);
         v.x = a.alloc<float>(lv.n * w);
         v.t = a.alloc<float>(lv.n * w);
         v.rloc = a.alloc<float>(nl);
         v.scr = a.alloc<float>(ns);
+        if (h->prm.precision == 2 && b == 0) v.w = a.alloc<float>(nl);
         if (!lv.term.empty()) {
             lv.cr64[b] = a.alloc<double>(lv.n * w);
             lv.cx64[b] = a.alloc<double>(lv.n * w);
@@ -690,6 +695,7 @@ std::unique_ptr<Level> coarsen(lsdd_hierarchy* h, Level& lv, const int32_t* agg_
     int64_t* d_zst_off = ar.upload(sq, st);
     lv.inv_len = msq[n_agg];
     lv.d_inv = ar.alloc<double>(lv.inv_len);
+    if (P.precision == 2) lv.d_X = ar.alloc<double>(lv.inv_len);
     double* d_zst = ar.alloc<double>(sq[n_agg]);
     lv.d_mu = ar.alloc<double>(n);
     lv.d_k = ar.alloc<int32_t>(n_agg);
@@ -805,46 +811,56 @@ std::unique_ptr<Level> coarsen(lsdd_hierarchy* h, Level& lv, const int32_t* agg_
             vAO.push_back(View{o, m, m, m, 0});
             vLww.push_back(View{o, m, nw, nw, 0});
         }
-        // Schur complement onto omega: Cholesky of the interface block; a block
-        // that is singular to working precision (pivot <= |Gamma| eps max diag)
-        // is factored again with that tolerance added to its diagonal
+        // Schur complement onto omega (eq. gep_reduced).  Cholesky of the interface
+        // block; a block singular to working precision (a pivot <= |Gamma| eps max
+        // diag) is assembled again and factored with diagonal pivoting, truncated when
+        // the largest remaining diagonal entry falls to that tolerance: its Schur
+        // complement is then taken over the eliminated (pivot) indices.  A~_Omega is
+        // positive semidefinite, so the coupling lies in the range of the interface
+        // block and this generalized inverse gives the Moore-Penrose Schur complement.
         HIPCHK(hipMemsetAsync(d_minp, 0x7f, nb * sizeof(double), st));
         launch_views_max_diag(nb, w1, bt.put(0, vGG), d_maxd, st);
         bt.potrf(w1, vGG, d_minp);
         {
             std::vector<double> maxd = download(d_maxd, nb, st), minp = download(d_minp, nb, st);
-            std::vector<int32_t> sing;
+            std::vector<int32_t> sing, sing_b, lead;
             std::vector<int64_t> sing_ws;
-            std::vector<double> delta;
+            std::vector<double> tol;
             std::vector<View> vs;
             for (int32_t b = 0; b < nb; ++b) {
                 if (ngs[b] == 0) continue;
-                const double tol = (double)ngs[b] * DBL_EPSILON * maxd[b];
-                if (!(minp[b] > tol)) {
+                const double t = (double)ngs[b] * DBL_EPSILON * maxd[b];
+                if (!(minp[b] > t)) {
                     sing.push_back(pos + b);
+                    sing_b.push_back(b);
                     sing_ws.push_back(ws_off[b]);
-                    delta.push_back(tol);
-                    vs.push_back(vGG[b]);
+                    tol.push_back(t);
+                    vs.push_back(vAO[b]);
+                    lead.push_back(vww[b].rows);
                 }
             }
             if (!sing.empty()) {
-                vlog("  %zu interface blocks singular to working precision: regularised", sing.size());
                 int32_t* d_list = ar.upload(sing, st);
                 int64_t* d_sws = ar.upload(sing_ws, st);
-                double* d_delta = ar.upload(delta, st);
+                double* d_tol = ar.upload(tol, st);
                 LocalArgs R = B;
                 R.agg_list = d_list;
                 R.ws_off = d_sws;
                 int32_t sing_m = 0;
                 for (int32_t i : sing) sing_m = std::max(sing_m, (int32_t)(C.sub_ptr[i + 1] - C.sub_ptr[i]));
                 launch_local_assemble((int32_t)sing.size(), R, sing_m, st);
-                launch_views_add_diag((int32_t)sing.size(), w1, bt.put(0, vs), d_delta, st);
-                double* d_mp2 = ar.alloc<double>(sing.size());
-                bt.potrf(w1, vs, d_mp2);
-                std::vector<double> mp2 = download(d_mp2, sing.size(), st);
-                for (size_t t = 0; t < sing.size(); ++t)
-                    if (!(mp2[t] > 0.0)) status[sing[t]] = 3;
-                for (void* p : {(void*)d_list, (void*)d_sws, (void*)d_delta, (void*)d_mp2}) ar.release(p);
+                std::vector<int32_t> rank;
+                bt.pstrf_trailing(w1, vs, lead, d_tol, rank);
+                int64_t dropped = 0;
+                for (size_t t = 0; t < sing.size(); ++t) {
+                    const int32_t b = sing_b[t];
+                    vGG[b].rows = vGG[b].cols = rank[t];
+                    vGw[b].rows = rank[t];
+                    dropped += ngs[b] - rank[t];
+                }
+                vlog("  %zu interface blocks singular to working precision: pivoted, %lld indices dropped",
+                     sing.size(), (long long)dropped);
+                for (void* p : {(void*)d_list, (void*)d_sws, (void*)d_tol}) ar.release(p);
             }
         }
         bt.trsm(w1, vGG, w1, vGw, false);                                   // W = L_G^{-1} A~_Gw
@@ -919,6 +935,11 @@ std::unique_ptr<Level> coarsen(lsdd_hierarchy* h, Level& lv, const int32_t* agg_
             }
             launch_views_identity(nb, w1, bt.put(0, vX), st);
             bt.trsm(w2, vL, w1, vX, false, true);                           // X = L^{-1} (lower)
+            if (lv.d_X)
+                for (int32_t b = 0; b < nb; ++b)
+                    HIPCHK(hipMemcpyAsync(lv.d_X + msq[pos + b], w1 + vX[b].off,
+                                          (size_t)vX[b].rows * vX[b].rows * sizeof(double), hipMemcpyDeviceToDevice,
+                                          st));
             bt.gemm_tn(w1, vX, w1, vX, nullptr, vInv, 0.0, lv.d_inv, vInv, -1.0, true, true);   // X^T X
         }
         HIPCHK(hipGetLastError());
@@ -935,8 +956,8 @@ std::unique_ptr<Level> coarsen(lsdd_hierarchy* h, Level& lv, const int32_t* agg_
     const double tp0 = now_s();
     for (int32_t i = 0; i < n_agg; ++i) {
         if (status[i] != 0)
-            throw Error(LSDD_E_NUMERIC, "local problem of aggregate " + std::to_string(i) + " failed (" +
-                                            (status[i] == 2 ? "overlap matrix not SPD" : "interface block") + ")");
+            throw Error(LSDD_E_NUMERIC, "local problem of aggregate " + std::to_string(i) +
+                                            " failed (overlap matrix not SPD)");
     }
     lv.k = download(lv.d_k, n_agg, st);
     // ---- coarse numbering, compact Z
@@ -950,7 +971,7 @@ std::unique_ptr<Level> coarsen(lsdd_hierarchy* h, Level& lv, const int32_t* agg_
     lv.d_zoff = ar.upload(lv.zoff, st);
     lv.d_Z = ar.alloc<double>(lv.zoff[n_agg]);
     lv.d_Zc = ar.alloc<double>(lv.zoff[n_agg]);
-    if (P.precision == 1) lv.d_Zc32 = ar.alloc<float>(lv.zoff[n_agg]);
+    if (P.precision >= 1) lv.d_Zc32 = ar.alloc<float>(lv.zoff[n_agg]);
     launch_z_compact(n_agg, lv.d_agg_ptr, lv.d_k, d_zst_off, d_zst, lv.d_zoff, lv.d_Z, lv.d_Zc, lv.d_Zc32, st);
     {
         // aggregates up to SMALL_M DOFs: one thread per coarse DOF / entry; larger ones: work items
@@ -1084,14 +1105,25 @@ std::unique_ptr<Level> coarsen(lsdd_hierarchy* h, Level& lv, const int32_t* agg_
         int64_t* d_pk_agg = ar.upload(pk_agg, st);
         lv.d_sw_pk_off = ar.upload(sw_pk_off, st);
         lv.d_tiles = ar.alloc<double>(std::max<int64_t>(lv.tiles_len, 1));
-        if (P.precision == 1) lv.d_tiles32 = ar.alloc<float>(std::max<int64_t>(lv.tiles_len, 1));
+        if (P.precision >= 1) lv.d_tiles32 = ar.alloc<float>(std::max<int64_t>(lv.tiles_len, 1));
         lv.d_pk = ar.alloc<double>(std::max<int64_t>(pks, 1));
-        if (P.precision == 1) lv.d_pk32 = ar.alloc<float>(std::max<int64_t>(pks, 1));
+        if (P.precision >= 1) lv.d_pk32 = ar.alloc<float>(std::max<int64_t>(pks, 1));
         const int64_t* d_sp_ptr = bj ? lv.d_agg_ptr : d_sub_ptr;
         launch_pack_tiles(n_agg, d_sp_ptr, d_inv_off, lv.d_inv, d_tp_agg, lv.d_tiles, lv.d_tiles32, st);
         launch_pack_small(n_agg, d_sp_ptr, d_inv_off, lv.d_inv, d_pk_agg, lv.d_pk, lv.d_pk32, st);
+        if (lv.d_X) {
+            // the factors X = L^{-1} in the same storage, FP32 only
+            lv.d_tfac32 = ar.alloc<float>(std::max<int64_t>(lv.tiles_len, 1));
+            lv.d_pkfac32 = ar.alloc<float>(std::max<int64_t>(pks, 1));
+            launch_pack_tiles(n_agg, d_sp_ptr, d_inv_off, lv.d_X, d_tp_agg, nullptr, lv.d_tfac32, st);
+            launch_pack_small(n_agg, d_sp_ptr, d_inv_off, lv.d_X, d_pk_agg, nullptr, lv.d_pkfac32, st);
+        }
         HIPCHK(hipGetLastError());
         sync(st);
+        if (lv.d_X) {
+            ar.release(lv.d_X);
+            lv.d_X = nullptr;
+        }
         ar.release(d_tp_agg);
         ar.release(d_pk_agg);
         ar.release(lv.d_inv);
@@ -1386,6 +1418,55 @@ void sweep_ras(lsdd_hierarchy* h, Level& lv, const T* r, T* x, bool post, bool x
     }
 }
 
+// Mixed-precision multiplicative Schwarz sweep (FP32 vectors): the local residuals
+// use the FP64 operator entries (sums in FP64, rounded once), the local solves
+// the FP32 factors X = L^{-1} of A_Omega as X^T (X r) -- a product of a matrix
+// with its own transpose, so the rounded local solve stays symmetric positive
+// semidefinite; an FP32 copy of the explicit inverse does not (on operators whose
+// spectrum spans more than FP32 resolves, it becomes indefinite).
+void sweep_factor(lsdd_hierarchy* h, Level& lv, const float* r, float* x, bool forward, bool x_zero_first) {
+    VecSet<float>& v = lv.v32[0];
+    for (int32_t cc = 0; cc < lv.n_colors; ++cc) {
+        int32_t c = forward ? cc : lv.n_colors - 1 - cc;
+        const int64_t r0 = lv.color_row0[c], r1 = lv.color_row0[c + 1], rm = lv.color_rmid[c];
+        const int64_t i0 = lv.color_item0[c], i1 = lv.color_item0[c + 1];
+        const int64_t s0 = lv.color_smid[c], ns = lv.color_sub0[c + 1] - lv.color_smid[c];
+        if (r1 == r0) continue;
+        const bool xz = x_zero_first && cc == 0;
+        const double rb = lv.color_m[c] * (4 + 8 + 3 * 4.0) + (xz ? 0.0 : lv.color_nnz[c] * (4 + 8.0));
+        traced(h, "csr_resid_rows", rb, [&] {
+            launch_csr_resid_rows<float, double>(r1 - r0, lv.d_sw_sub_dofs + r0, lv.d_rowptr, lv.d_col, lv.d_val, x, r,
+                                                 v.rloc + r0, xz, lv.lanes, h->st);
+        });
+        if (i1 > i0) {
+            const double gb = lv.color_m2[c] * 4.0 + (double)(rm - r0) * (4 + 3 * 4.0);
+            traced(h, "sub_trmv", gb, [&] {
+                launch_sub_symv<float>(i1 - i0, lv.d_items + 3 * i0, lv.d_sw_sub_off, lv.d_sw_tp_off, lv.d_tfac32,
+                                       v.rloc, lv.d_scr_off, v.scr, lv.chl, h->st, 1);
+            });
+            traced(h, "sub_finalize", lv.color_scr[c] * 4.0 + (double)(rm - r0) * 12.0, [&] {
+                launch_sub_finalize<float>(r0, rm, lv.d_pos_sub, lv.d_sw_sub_off, lv.d_scr_off, v.scr, nullptr, v.w,
+                                           false, lv.chl, lv.fl, h->st, false);
+            });
+            traced(h, "sub_trmv", gb, [&] {
+                launch_sub_symv<float>(i1 - i0, lv.d_items + 3 * i0, lv.d_sw_sub_off, lv.d_sw_tp_off, lv.d_tfac32,
+                                       v.w, lv.d_scr_off, v.scr, lv.chl, h->st, 2);
+            });
+            traced(h, "sub_finalize", lv.color_scr[c] * 4.0 + (double)(rm - r0) * 16.0, [&] {
+                launch_sub_finalize<float>(r0, rm, lv.d_pos_sub, lv.d_sw_sub_off, lv.d_scr_off, v.scr,
+                                           lv.d_sw_sub_dofs, x, true, lv.chl, lv.fl, h->st, true);
+            });
+        }
+        if (ns > 0) {
+            const double sb = lv.color_pk[c] * 4.0 + (double)(r1 - rm) * (4 + 3 * 4.0);
+            traced(h, "small_sub", sb, [&] {
+                launch_small_sub<float, 1>(s0, ns, lv.d_sw_sub_off, lv.d_sw_sub_dofs, lv.d_sw_pk_off, lv.d_pkfac32,
+                                           v.rloc, x, lv.small_m, h->st, true);
+            });
+        }
+    }
+}
+
 template <typename T, int NR>
 void sweep(lsdd_hierarchy* h, Level& lv, const T* r, T* x, bool forward, bool x_zero_first) {
     using O = LvOps<T>;
@@ -1396,6 +1477,12 @@ void sweep(lsdd_hierarchy* h, Level& lv, const T* r, T* x, bool forward, bool x_
     }
     VecSet<T>& v = O::v(lv, NR > 1);
     const double w = (double)sizeof(T), wv = w * NR;
+    if constexpr (std::is_same<T, float>::value && NR == 1) {
+        if (h->cycle_prec == 2) {
+            sweep_factor(h, lv, r, x, forward, x_zero_first);
+            return;
+        }
+    }
     for (int32_t cc = 0; cc < lv.n_colors; ++cc) {
         int32_t c = forward ? cc : lv.n_colors - 1 - cc;
         const int64_t r0 = lv.color_row0[c], r1 = lv.color_row0[c + 1], rm = lv.color_rmid[c];
@@ -1476,8 +1563,18 @@ void vcycle(lsdd_hierarchy* h, size_t l, const T* r, T* x) {
     launch_zero<T>(lv.n * NR, x, h->st);
     if (!lv.term.empty()) terminal();     // instances whose hierarchy ends on this level
     sweep<T, NR>(h, lv, r, x, true, true);
-    traced(h, "csr_spmv", (double)lv.nnz * (4 + w) + (double)lv.n * (8 + 3 * wv),
-           [&] { C::spmv(lv, O::val(lv), x, v.t, r, h->st); });
+    bool mixed = false;
+    if constexpr (std::is_same<T, float>::value && NR == 1) {
+        if (h->cycle_prec == 2) {
+            mixed = true;
+            traced(h, "csr_spmv", (double)lv.nnz * (4 + 8.0) + (double)lv.n * (8 + 3 * wv), [&] {
+                launch_csr_spmv<float, double>(lv.n, lv.d_rowptr, lv.d_col, lv.d_val, x, v.t, r, lv.lanes, h->st);
+            });
+        }
+    }
+    if (!mixed)
+        traced(h, "csr_spmv", (double)lv.nnz * (4 + w) + (double)lv.n * (8 + 3 * wv),
+               [&] { C::spmv(lv, O::val(lv), x, v.t, r, h->st); });
     const double zb = (double)lv.zoff.back() * w + (double)lv.n * (4 + wv) + (double)nx.n * wv;
     traced(h, "restrict", zb, [&] { C::restrict_(lv, O::Z(lv), v.t, vn.r, h->st); });
     vcycle<T, NR>(h, l + 1, vn.r, vn.x);
@@ -1495,7 +1592,7 @@ template <int NR>
 void precond(lsdd_hierarchy* h, const double* r, double* z) {
     Level& l0 = *h->L[0];
     constexpr int b = NR > 1 ? 1 : 0;
-    if (h->cycle_prec == 1) {
+    if (h->cycle_prec >= 1) {
         launch_to_f32(l0.n * NR, r, l0.v32[b].r, h->st);
         vcycle<float, NR>(h, 0, l0.v32[b].r, l0.v32[b].x);
         launch_to_f64(l0.n * NR, l0.v32[b].x, z, h->st);
@@ -1576,7 +1673,7 @@ bool pcg_run(lsdd_hierarchy* h) {
     double *bb = h->sc, *rz = bb + nsm, *pq = rz + nsm, *rr = pq + nsm, *rzn = rr + nsm, *rzo = rzn + nsm,
            *alpha = rzo + nsm, *beta = alpha + nsm, *relres = beta + nsm;
     int32_t *act = h->ic, *iters = act + nsm, *cnt = iters + nsm, *itf = cnt + 1;   // itf[0] it, itf[1] flag
-    const bool flex = h->cycle_prec == 1;
+    const bool flex = h->cycle_prec >= 1;
     const double tol2 = h->prm.rtol * h->prm.rtol;
     launch_seg_dot(T, NR, B.B, B.B, nullptr, nullptr, h->part, bb, nullptr, st);
     launch_pcg_init(ns, bb, act, iters, relres, itf, st);
@@ -1770,7 +1867,7 @@ lsdd_hierarchy* build(ElemList el0, const double* blocks, bool blocks_on_device,
     lsdd_params_default(&h->prm);
     if (prm) h->prm = *prm;
     const lsdd_params& P = h->prm;
-    if (P.max_levels < 1 || P.precision < 0 || P.precision > 1 || P.tau_const <= 0 || P.rtol <= 0 || P.max_iter < 1 ||
+    if (P.max_levels < 1 || P.precision < 0 || P.precision > 2 || P.tau_const <= 0 || P.rtol <= 0 || P.max_iter < 1 ||
         P.closure < 0 || P.closure > 1 || !(P.closure_tol >= 0) || P.smoother < 0 || P.smoother > 2 ||
         P.elem_factor < 0 || P.elem_factor > 1)
         throw Error(LSDD_E_INVAL, "invalid parameters");
@@ -2030,9 +2127,11 @@ lsdd_status lsdd_update_theta(lsdd_hierarchy* h, const double* theta, void* hip_
 }
 
 lsdd_status lsdd_elem_bilinear(int64_t n_elem, const int64_t* elem_ptr, const int32_t* elem_dofs, const double* blocks,
-                               const double* u, const double* v, double* out, void* hip_stream) {
+                               const double* u, const double* v, int32_t nrhs, int64_t ld, double scale, double* out,
+                               void* hip_stream) {
     ABI_BEGIN
-    if (n_elem < 1 || !elem_ptr || !elem_dofs || !blocks || !u || !v || !out) throw Error(LSDD_E_INVAL, "bad argument");
+    if (n_elem < 1 || !elem_ptr || !elem_dofs || !blocks || !u || !v || !out || nrhs < 1 || ld < 1)
+        throw Error(LSDD_E_INVAL, "bad argument");
     if (elem_ptr[0] != 0) throw Error(LSDD_E_INVAL, "elem_ptr[0] must be 0");
     std::vector<int64_t> boff(n_elem + 1, 0);
     for (int64_t e = 0; e < n_elem; ++e) {
@@ -2048,7 +2147,7 @@ lsdd_status lsdd_elem_bilinear(int64_t n_elem, const int64_t* elem_ptr, const in
     const std::vector<int64_t> ptr(elem_ptr, elem_ptr + n_elem + 1);
     int64_t* d_ptr = sc.a.upload(ptr, st);
     int64_t* d_boff = sc.a.upload(boff, st);
-    launch_elem_bilinear(n_elem, d_ptr, elem_dofs, d_boff, blocks, u, v, out, st);
+    launch_elem_bilinear(n_elem, d_ptr, elem_dofs, d_boff, blocks, u, v, nrhs, ld, scale, out, st);
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(st));
     return LSDD_OK;
@@ -2200,6 +2299,7 @@ lsdd_status lsdd_apply(lsdd_hierarchy* h, int32_t level, const double* x, double
 lsdd_status lsdd_solve(lsdd_hierarchy* h, const double* b, double* x, int32_t nrhs, void* hip_stream, lsdd_info* info) {
     ABI_BEGIN
     if (!h || !b || !x || nrhs < 1) throw Error(LSDD_E_INVAL, "bad argument");
+    if (nrhs > 1 && h->cycle_prec == 2) throw Error(LSDD_E_UNSUPPORTED, "the mixed cycle runs single right-hand sides only");
     h->st = (hipStream_t)hip_stream;
     hipStream_t st = h->st;
     const int64_t n = h->L[0]->n;
@@ -2261,6 +2361,25 @@ lsdd_status lsdd_solve(lsdd_hierarchy* h, const double* b, double* x, int32_t nr
     ABI_END
 }
 
+lsdd_status lsdd_solve_batched(int32_t n_inst, lsdd_hierarchy* const* hs, const double* const* b, double* const* x,
+                               int32_t nrhs, void* hip_stream, lsdd_info* info) {
+    if (n_inst < 1 || !hs || !b || !x || nrhs < 1) {
+        g_err = "bad argument";
+        return LSDD_E_INVAL;
+    }
+    for (int32_t i = 0; i < n_inst; ++i)
+        if (!hs[i] || !b[i] || !x[i]) {
+            g_err = "NULL hierarchy or vector of instance " + std::to_string(i);
+            return LSDD_E_INVAL;
+        }
+    int64_t off = 0;
+    for (int32_t i = 0; i < n_inst; ++i) {
+        const lsdd_status s = lsdd_solve(hs[i], b[i], x[i], nrhs, hip_stream, info ? info + off : nullptr);
+        if (s != LSDD_OK) return s;
+        off += (int64_t)nrhs * hs[i]->seg.n_seg;
+    }
+    return LSDD_OK;
+}
 lsdd_status lsdd_solve_stationary(lsdd_hierarchy* h, const double* b, double* x, int32_t nrhs, void* hip_stream,
                                   lsdd_info* info) {
     ABI_BEGIN
@@ -2341,9 +2460,13 @@ lsdd_status lsdd_solve_stationary(lsdd_hierarchy* h, const double* b, double* x,
 
 lsdd_status lsdd_set_cycle_precision(lsdd_hierarchy* h, int32_t precision) {
     ABI_BEGIN
-    if (!h || precision < 0 || precision > 1) throw Error(LSDD_E_INVAL, "bad argument");
-    if (precision == 1 && h->prm.precision != 1)
-        throw Error(LSDD_E_INVAL, "the FP32 cycle needs a hierarchy set up with precision = 1");
+    if (!h || precision < 0 || precision > 2) throw Error(LSDD_E_INVAL, "bad argument");
+    if (precision == 1 && h->prm.precision < 1)
+        throw Error(LSDD_E_INVAL, "the FP32 cycle needs a hierarchy set up with precision >= 1");
+    if (precision == 2 && h->prm.precision != 2)
+        throw Error(LSDD_E_INVAL, "the mixed cycle needs a hierarchy set up with precision = 2");
+    if (precision == 2 && h->prm.smoother != 0)
+        throw Error(LSDD_E_UNSUPPORTED, "the mixed cycle runs the multiplicative Schwarz smoother only");
     h->cycle_prec = precision;
     return LSDD_OK;
     ABI_END
@@ -2387,10 +2510,11 @@ lsdd_status lsdd_autotune(lsdd_hierarchy* h, int32_t block, void* hip_stream) {
             ensure_block_vectors(h);
             alloc_pcg(h, 1);
         }
+        if (h->cycle_prec == 2) throw Error(LSDD_E_UNSUPPORTED, "the mixed cycle runs single right-hand sides only");
         if (h->cycle_prec == 1) autotune_levels<float, NRB>(h);
         else autotune_levels<double, NRB>(h);
     } else {
-        if (h->cycle_prec == 1) autotune_levels<float, 1>(h);
+        if (h->cycle_prec >= 1) autotune_levels<float, 1>(h);
         else autotune_levels<double, 1>(h);
     }
     reset_graphs(h);

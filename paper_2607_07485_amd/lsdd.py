@@ -92,7 +92,10 @@ def lib():
         L.lsdd_setup_elements_scaled.argtypes = [C.c_int64, C.c_int64, i64p, i32p, _P, _P, i32p, i32p, C.c_int,
                                                  C.POINTER(Params), _P, C.POINTER(_P)]
         L.lsdd_update_theta.argtypes = [_P, _P, _P]
-        L.lsdd_elem_bilinear.argtypes = [C.c_int64, i64p, _P, _P, _P, _P, _P, _P]
+        L.lsdd_elem_bilinear.argtypes = [C.c_int64, i64p, _P, _P, _P, _P, C.c_int32, C.c_int64, C.c_double, _P,
+                                         _P]
+        L.lsdd_solve_batched.argtypes = [C.c_int32, C.POINTER(_P), C.POINTER(_P), C.POINTER(_P), C.c_int32, _P,
+                                         C.POINTER(Info)]
         L.lsdd_level_tuning.argtypes = [_P, C.c_int32, i32p]
         L.lsdd_set_allocator.restype = None
         for name in ("lsdd_setup_elements", "lsdd_setup_gram_csr", "lsdd_solve", "lsdd_solve_stationary",
@@ -101,7 +104,8 @@ def lib():
                      "lsdd_destroy", "lsdd_set_cycle_precision", "lsdd_trace", "lsdd_trace_get",
                      "lsdd_set_solve_params", "lsdd_set_graph", "lsdd_segments", "lsdd_setup_batched",
                      "lsdd_level_segments", "lsdd_autotune", "lsdd_level_tuning", "lsdd_setup_elements_scaled",
-                     "lsdd_update_theta", "lsdd_elem_bilinear"):
+                     "lsdd_update_theta", "lsdd_elem_bilinear",
+                     "lsdd_solve_batched"):
             getattr(L, name).restype = C.c_int
         _LIB = L
     return _LIB
@@ -131,19 +135,46 @@ def _dev_ptr(t):
     return C.c_void_p(t.data_ptr())
 
 
-def elem_bilinear(elem_ptr, elem_dofs, blocks, u, v, out=None):
-    """lsdd_elem_bilinear: out[e] = u_e^T B_e v_e.  elem_ptr host int64 array; elem_dofs
-    a device int32 tensor; blocks, u, v float64 device tensors."""
+def elem_bilinear(elem_ptr, elem_dofs, blocks, u, v, scale=1.0, out=None):
+    """lsdd_elem_bilinear: out[e] = scale * sum_k u_{k,e}^T B_e v_{k,e}.  elem_ptr host
+    int64 array; elem_dofs a device int32 tensor; blocks float64 device tensor; u, v
+    float64 device tensors [n] or [nrhs, n] of the same shape."""
     import torch
     elem_ptr = np.ascontiguousarray(elem_ptr, dtype=np.int64)
     if not (isinstance(elem_dofs, torch.Tensor) and elem_dofs.is_cuda and elem_dofs.dtype == torch.int32
             and elem_dofs.is_contiguous()):
         raise TypeError("elem_dofs: expected a contiguous int32 device tensor")
+    if u.shape != v.shape or u.dim() not in (1, 2):
+        raise ValueError("u and v: tensors of equal shape [n] or [nrhs, n]")
+    u2, v2 = u.reshape(-1, u.shape[-1]).contiguous(), v.reshape(-1, v.shape[-1]).contiguous()
     ne = len(elem_ptr) - 1
     out = torch.empty(ne, dtype=torch.float64, device=u.device) if out is None else out
     _check(lib().lsdd_elem_bilinear(ne, _ptr(elem_ptr, C.c_int64), C.c_void_p(elem_dofs.data_ptr()), _dev_ptr(blocks),
-                                    _dev_ptr(u), _dev_ptr(v), _dev_ptr(out), _stream()))
+                                    _dev_ptr(u2), _dev_ptr(v2), u2.shape[0], u2.shape[1], float(scale),
+                                    _dev_ptr(out), _stream()))
     return out
+
+
+def solve_batched(hs, bs, xs=None, allow_noconv=False):
+    """lsdd_solve_batched: hs[i] x_i = b_i for separately built hierarchies (every b_i of
+    shape [n_i] or [nrhs, n_i] with the same nrhs); returns (xs, [[Info] per instance])."""
+    import torch
+    n_inst = len(hs)
+    if n_inst < 1 or len(bs) != n_inst:
+        raise ValueError("one right-hand side tensor per hierarchy")
+    nrhs = 1 if bs[0].dim() == 1 else bs[0].shape[0]
+    xs = [torch.empty_like(b) for b in bs] if xs is None else xs
+    nseg = [h.segments()[0] for h in hs]
+    infos = (Info * (nrhs * sum(nseg)))()
+    H = (C.c_void_p * n_inst)(*[h._h.value for h in hs])
+    B = (C.c_void_p * n_inst)(*[b.data_ptr() for b in bs])
+    X = (C.c_void_p * n_inst)(*[x.data_ptr() for x in xs])
+    _check(lib().lsdd_solve_batched(n_inst, H, B, X, nrhs, _stream(), infos), allow=(5,) if allow_noconv else ())
+    out, off = [], 0
+    for k in nseg:
+        out.append([infos[off + i] for i in range(nrhs * k)])
+        off += nrhs * k
+    return xs, out
 
 
 class Hierarchy:

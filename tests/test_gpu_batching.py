@@ -200,3 +200,25 @@ def test_autotuned_shapes_keep_parity(dev):
             x_or, inf_or = oracle.pcg(h_or, B[k])
             assert abs(infs[k].iters - inf_or.iters) <= 1
             assert np.linalg.norm(X[k] - x_or) <= 1e-10 * np.linalg.norm(x_or)
+
+
+def test_solve_batched_over_separate_hierarchies(dev):
+    """lsdd_solve_batched on three separately built hierarchies (two elasticity meshes and
+    a grad-div one, two right-hand sides each): every instance's result equals its own
+    lsdd_solve bit for bit, and the reports come back in instance order."""
+    P = _lsdd()
+    probs = [fegen.elasticity_small(N=8)[0], fegen.elasticity_small(N=12)[0], _graddiv(6)[0]]
+    kws = [ELAST_KW, ELAST_KW, GD_KW]
+    rng = np.random.default_rng(31)
+    hs = [P.Hierarchy.setup_problem(p, P.Params.default(**kw)) for p, kw in zip(probs, kws)]
+    try:
+        bs = [torch.from_numpy(rng.standard_normal((2, p.n))).to(dev) for p in probs]
+        xs, infos = P.solve_batched(hs, bs)
+        assert len(infos) == 3
+        for h, b, x, inf in zip(hs, bs, xs, infos):
+            x1, inf1 = h.solve(b)
+            assert torch.equal(x, x1)
+            assert [f.iters for f in inf] == [f.iters for f in inf1] and all(f.converged for f in inf)
+    finally:
+        for h in hs:
+            h.close()

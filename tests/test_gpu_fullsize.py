@@ -18,11 +18,16 @@ what it can compute one piece at a time, from the problem data alone:
   for the exported P within the rounding bound of the double sum, the symmetry
   and positivity of the V-cycle, and the normwise backward error of the PCG
   result against the oracle's A.
+* the four-level grad-div hierarchy against the values of the oracle's own run at
+  this size (tests/golden/): aggregates, retained-mode counts, level sizes, PCG
+  iterations and the A-norm error against the oracle's reference solution.
 * the 64-instance Q1 batch with 8 right-hand sides, FP32 cycle in FP64 PCG
   (blocks, autotuned shapes, captured iterations): on sampled instances the true
   residuals against the oracle's A and the A-norm errors against a sparse
-  direct solve of that A, beside those of the FP64 cycle.
+  direct solve of that A, beside those of the FP64 cycle, both at the 1e-8 gate.
 """
+import os
+
 import numpy as np
 import pytest
 import scipy.linalg as sla
@@ -31,6 +36,7 @@ import scipy.sparse.linalg as spla
 
 import fegen
 import oracle
+from refsol import anorm_rel, extended_reference
 from oracle import lsdd as O
 
 torch = pytest.importorskip("torch")
@@ -124,17 +130,21 @@ def test_graddiv_aggregates_and_sampled_local_problems(graddiv):
     sample = list(rng.choice(n_agg, 24, replace=False)) + [int(np.argmax([len(o) for o in omegas]))]
     for i in sample:
         At = O.local_splitting(omegas[i], cl[i], dofs, blocks, mult)
-        S = O.schur_pinv(At, nw[i], "cholesky")
+        S = O.schur_pinv(At, nw[i])
         Aww = A[aggs[i]][:, aggs[i]].toarray()
         mu, V, L = O.local_spectral(S, Aww)
         k = O.select_modes(mu, prm, tau_cut)
         # the oracle's own rounding spread on this pencil: the Cholesky reduction
-        # against LAPACK's generalized eigensolver, both FP64.  On the finest
-        # grad-div level A_ww has condition numbers near 1e10, so two correct FP64
-        # routes differ by far more than 1e-10; the tolerance is ten times that
-        # spread, never below 1e-10
+        # against LAPACK's generalized eigensolver, and the pseudo-inverse Schur
+        # complement against its projector form on the weighted Gram rows, all FP64.
+        # On the finest grad-div level A_ww has condition numbers near 1e10, so two
+        # correct FP64 routes differ by far more than 1e-10; the tolerance is ten
+        # times the larger spread, never below 1e-10
         mu2, Z2 = sla.eigh(S, Aww)
-        mu_tol = max(MU_TOL, 10 * float(np.abs(np.maximum(mu2, 0.0) - mu).max()))
+        H = O.local_gram_rows(omegas[i], cl[i], dofs, {e: O.element_gram_factor(blocks[e]) for e in cl[i]}, mult)
+        mu3, _, _ = O.local_spectral(O.schur_projector(H, nw[i]), Aww)
+        spread = max(float(np.abs(np.maximum(mu2, 0.0) - mu).max()), float(np.abs(mu3 - mu).max()))
+        mu_tol = max(MU_TOL, 10 * spread)
         k_g = int(l0["k"][i])
         mu_g = l0["mu"][mu_off[i]:mu_off[i + 1]]
         assert np.abs(mu_g - mu).max() <= mu_tol, (i, np.abs(mu_g - mu).max(), mu_tol)
@@ -230,12 +240,77 @@ def test_graddiv_galerkin_cycle_and_solution_properties(graddiv, dev):
     assert eta <= 1e-8, eta
 
 
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "graddiv128_oracle.npz")
+GOLDEN_KW = dict(max_levels=4, tau_const=0.75, agg_passes=2, agg_passes_coarse=1)
+# local spectra at this size: two correct FP64 routes through the same pencil differ
+# by up to 1e-6 in mu (the Cholesky reduction against LAPACK's generalized solver,
+# measured on sampled aggregates); ten times that
+GOLDEN_MU_TOL = 1e-5
+
+
+def test_graddiv_four_levels_against_the_oracle_run(dev):
+    """The whole four-level grad-div hierarchy at 128 x 128 against the oracle's own run
+    (tests/golden/make_graddiv128.py, the oracle only): level-0 aggregates bit-exact;
+    retained-mode counts per level-0 aggregate bit-exact except where every mode in
+    between lies within GOLDEN_MU_TOL of the cut 1/tau_cut or of a cluster-completion
+    gap; the level-1 size equal to the sum of the counts; the coarser sizes within 1 %
+    (their aggregates follow the level-1 numbering); PCG iterations +-1; and the A-norm
+    error of the GPU solution against a reference accurate beyond FP64 within twice
+    that of the oracle's own FP64 solution (PCG to 1e-12).
+
+    The cut 1/tau_cut = 1/(0.75 * 4) = 1/3 falls on the eigenvalue 1/mult of modes
+    that live inside elements touching three aggregates, a cluster that every
+    aggregate's spectrum holds; the oracle's own rounding puts members of it up to
+    1e-8 on either side of the cut (its first dropped mode lies within 1e-8 of the cut
+    on 237 of 493 aggregates), so the counts there are decided by rounding."""
+    P = _lsdd()
+    g = dict(np.load(GOLDEN))
+    prob, b = fegen.graddiv_hdiv(N=128)
+    with P.Hierarchy.setup_problem(prob, P.Params.default(**GOLDEN_KW, rtol=1e-8)) as h:
+        n = h.info()["n"]
+        assert len(n) == 4 and n[0] == int(g["n"][0])
+        l0 = h.export_level(0)
+        assert np.array_equal(l0["agg_of_dof"], g["agg0"])
+        k_g, k_o = np.asarray(l0["k"]), g["k0"]
+        thr = 1.0 / float(g["tau_cut0"])
+        nw = g["nw0"]
+        mu_off = np.concatenate([[0], np.cumsum(nw)])
+        prm = oracle.Params(**GOLDEN_KW)
+        differ = np.flatnonzero(k_g != k_o)
+        for i in differ:
+            mu = l0["mu"][mu_off[i]:mu_off[i + 1]]
+            for j in range(min(k_g[i], k_o[i]), max(k_g[i], k_o[i])):
+                near_cut = abs(mu[j] - thr) <= GOLDEN_MU_TOL
+                near_gap = j > 0 and abs((mu[j] - mu[j - 1]) - prm.cluster_tol) <= 2 * GOLDEN_MU_TOL
+                assert near_cut or near_gap, (i, j, k_g[i], k_o[i], mu[j] - thr)
+        assert n[1] == int(k_g.sum())
+        for l in (2, 3):
+            assert abs(n[l] - int(g["n"][l])) <= 0.01 * int(g["n"][l]), (n, g["n"])
+        x, infos = h.solve(torch.from_numpy(b).to(dev))
+        assert infos[0].converged == 1 and abs(infos[0].iters - int(g["iters"])) <= 1
+        dofs, blocks = _elem_lists(prob)
+        A = O.assemble(prob.n, dofs, blocks)
+        # both solutions against one accurate beyond FP64 (LU + extended-precision
+        # refinement): FP64 itself stops near eps cond(A) ~ 2e-6 from it here, so the
+        # GPU solution is held to the accuracy of the oracle's own FP64 solution
+        x_true = extended_reference(A, b)
+        err = anorm_rel(A, x.cpu().numpy(), x_true)
+        err_or = anorm_rel(A, g["x_ref"], x_true)
+        assert err <= 2.0 * err_or + 1e-9, (err, err_or)
+        print(f"four-level grad-div: GPU levels {n}, oracle {g['n'].tolist()}, "
+              f"{len(differ)} aggregates with other counts ({int(k_g.sum()) - int(k_o.sum()):+d} modes), "
+              f"its {infos[0].iters} / {int(g['iters'])}, A-norm error {err:.2e} (oracle {err_or:.2e})")
+
+
 def test_q1_batch_sampled_instances(dev):
     P = _lsdd()
     batch = fegen.elasticity_batch(64, 48, 256, seed=0, nrhs=8)
     probs = [p for p, _ in batch]
     B_np = np.ascontiguousarray(np.concatenate([bb for _, bb in batch], axis=1))
-    prm = P.Params.default(**BENCH_KW, precision=1, rtol=1e-8)
+    # the stiffest instances (nu near 0.49) stop at an A-norm error near 2e-8 with a
+    # 1e-8 residual for either cycle: both are tightened by the same factor (to 2.5e-9)
+    # so that every sampled (instance, right-hand side) pair meets the 1e-8 gate
+    prm = P.Params.default(**BENCH_KW, precision=1, rtol=2.5e-9)
     h = P.Hierarchy.setup_batched(probs, prm)
     try:
         seg = h.segments()[1]
@@ -264,11 +339,12 @@ def test_q1_batch_sampled_instances(dev):
                 err = {}
                 for prec in (0, 1):
                     xq = sols[prec][q, a:e]
-                    assert np.linalg.norm(bq - A @ xq) <= 1.5e-8 * np.linalg.norm(bq), (i, q, prec)
+                    assert np.linalg.norm(bq - A @ xq) <= 1.5 * 2.5e-9 * np.linalg.norm(bq), (i, q, prec)
                     d = xq - xs
                     err[prec] = np.sqrt(d @ (A @ d)) / nA
-                # the FP32 cycle reaches the accuracy of the FP64 cycle at the same stopping test
+                # the FP32 cycle reaches the accuracy of the FP64 cycle at the same stopping
+                # test, and both meet the 1e-8 A-norm gate
                 assert err[1] <= 1.1 * err[0] + 1e-10, (i, q, err)
-                assert err[1] <= 5e-8, (i, q, err)
+                assert err[0] <= 1e-8 and err[1] <= 1e-8, (i, q, err)
     finally:
         h.close()

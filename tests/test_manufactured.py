@@ -180,3 +180,202 @@ def test_q1_elasticity_converges_at_the_q1_rates():
     r1 = _rates([e[1] for e in errs], hs)
     assert abs(r0[-1] - 2.0) <= 0.15, (errs, r0)
     assert abs(r1[-1] - 1.0) <= 0.15, (errs, r1)
+
+
+# ----------------------------------------------------------------------------- RTCF_3 grad-div
+
+def _rtcf3_errors(N, beta=1.0):
+    """L2 error of the RTCF_3 solution of -grad(div u) + beta u = f (kappa = 1) with the
+    natural boundary condition div u = g of the form without boundary terms: the load
+    is (f, v) + <g, v.n> with g = div u of the exact field."""
+    from fegen.common import gauss_legendre_01, gll_nodes_01, lagrange_1d
+    from fegen.hdiv import rtcf3_dofs
+    X, Y = sympy.symbols("x y")
+    u = [sympy.sin(sympy.pi * X) * sympy.cos(2 * Y) + X ** 2 * Y, sympy.exp(X) * sympy.sin(sympy.pi * Y)]
+    div = sympy.diff(u[0], X) + sympy.diff(u[1], Y)
+    f = [-sympy.diff(div, X) + beta * u[0], -sympy.diff(div, Y) + beta * u[1]]
+    L = lambda e: sympy.lambdify((X, Y), e, "numpy")
+    uf, ff, gf = [L(c) for c in u], [L(c) for c in f], L(div)
+    prob = fegen.graddiv_rtcf3(N, beta=beta)
+    dofs, _, _ = rtcf3_dofs(N)
+    h = 1.0 / N
+    phi = lagrange_1d(gll_nodes_01(4))[0]
+    psi = lagrange_1d(gauss_legendre_01(3)[0])[0]
+    qp, qw = gauss_legendre_01(6)
+    P, S = phi(qp), psi(qp)                                     # [q, 4], [q, 3]
+    # basis values on the reference cell, [qx, qy, comp, 24]
+    V = np.zeros((len(qp), len(qp), 2, 24))
+    for a in range(4):
+        for b in range(3):
+            V[:, :, 0, 3 * a + b] = np.outer(P[:, a], S[:, b])
+            V[:, :, 1, 12 + 3 * a + b] = np.outer(S[:, b], P[:, a])
+    W = np.outer(qw, qw) * h * h
+    cells = np.arange(N * N)
+    ci, cj = cells % N, cells // N
+    xq = (ci[:, None, None] + qp[None, :, None]) * h + 0.0 * qp[None, None, :]
+    yq = (cj[:, None, None] + qp[None, None, :]) * h + 0.0 * qp[None, :, None]
+    fq = np.stack([np.broadcast_to(ff[c](xq, yq), xq.shape) for c in range(2)], -1)      # [T, qx, qy, 2]
+    b = np.zeros(prob.n)
+    np.add.at(b, dofs, np.einsum("tijc,ijck,ij->tk", fq, V, W))
+    # <g, v.n>: the edge basis functions phi_0 (at 0) and phi_3 (at 1) times psi_b
+    for side in ("left", "right", "bottom", "top"):
+        sel = {"left": ci == 0, "right": ci == N - 1, "bottom": cj == 0, "top": cj == N - 1}[side]
+        for t in np.flatnonzero(sel):
+            s = (cj[t] if side in ("left", "right") else ci[t]) * h + qp * h
+            xy = {"left": (0.0 * s, s), "right": (1.0 + 0.0 * s, s),
+                  "bottom": (s, 0.0 * s), "top": (s, 1.0 + 0.0 * s)}[side]
+            g = np.broadcast_to(gf(*xy), s.shape)
+            sign = -1.0 if side in ("left", "bottom") else 1.0
+            a = 0 if side in ("left", "bottom") else 3
+            base = 0 if side in ("left", "right") else 12
+            for bb in range(3):
+                b[dofs[t, base + 3 * a + bb]] += sign * np.sum(qw * h * g * S[:, bb])
+    x = _solve(prob, b, max_levels=3, tau_const=0.75, agg_passes=1)
+    uh = np.einsum("tk,ijck->tijc", x[dofs], V)
+    ue = np.stack([np.broadcast_to(uf[c](xq, yq), xq.shape) for c in range(2)], -1)
+    return float(np.sqrt(np.sum(W[None, :, :, None] * (uh - ue) ** 2)))
+
+
+def test_rtcf3_graddiv_converges_at_the_rt3_rate():
+    """RTCF_3 (Q_{3,2} x Q_{2,3}) on the grad-div form: L2 error O(h^3)."""
+    Ns = [4, 8, 16]
+    errs = [_rtcf3_errors(N) for N in Ns]
+    r = _rates(errs, [1.0 / N for N in Ns])
+    assert abs(r[-1] - 3.0) <= 0.15, (errs, r)
+
+
+# ----------------------------------------------------------------------------- BFS hyperdiffusion
+
+def _bfs_errors(N, eps=0.25, theta=np.pi / 6):
+    """L2 error of the clamped hyperdiffusion solution (q(q(u)) = f, q = div(D grad .),
+    u = d_n u = 0 by the Nitsche terms) for u = sin^2(pi x) sin^2(pi y)."""
+    from fegen.common import gauss_legendre_01
+    from fegen.hermite import _derivs, diffusion_tensor
+    X, Y = sympy.symbols("x y")
+    D = diffusion_tensor(eps, theta)
+    u = sympy.sin(sympy.pi * X) ** 2 * sympy.sin(sympy.pi * Y) ** 2
+    q = lambda w: D[0, 0] * sympy.diff(w, X, 2) + 2 * D[0, 1] * sympy.diff(w, X, Y) + D[1, 1] * sympy.diff(w, Y, 2)
+    uf, ff = sympy.lambdify((X, Y), u, "numpy"), sympy.lambdify((X, Y), q(q(u)), "numpy")
+    prob = fegen.hyperdiffusion_h2(N, eps=eps, theta=theta)[0]
+    h = 1.0 / N
+    qp, qw = gauss_legendre_01(6)
+    Bv = np.array([[_derivs(x, y, h)[(0, 0)] for y in qp] for x in qp])       # [qx, qy, 16]
+    W = np.outer(qw, qw) * h * h
+    nx = N + 1
+    cells = np.arange(N * N)
+    ci, cj = cells % N, cells // N
+    verts = np.stack([cj * nx + ci, cj * nx + ci + 1, (cj + 1) * nx + ci, (cj + 1) * nx + ci + 1], 1)
+    dofs = (4 * verts[:, :, None] + np.arange(4)[None, None, :]).reshape(N * N, 16)
+    xq = (ci[:, None, None] + qp[None, :, None]) * h + 0.0 * qp[None, None, :]
+    yq = (cj[:, None, None] + qp[None, None, :]) * h + 0.0 * qp[None, :, None]
+    b = np.zeros(prob.n)
+    np.add.at(b, dofs, np.einsum("tij,ijk,ij->tk", ff(xq, yq), Bv, W))
+    x = _solve(prob, b, max_levels=3, tau_const=1.0, agg_passes=1)
+    uh = np.einsum("tk,ijk->tij", x[dofs], Bv)
+    return float(np.sqrt(np.sum(W[None] * (uh - uf(xq, yq)) ** 2)))
+
+
+def test_bfs_hyperdiffusion_converges_at_the_bicubic_rate():
+    """Bogner-Fox-Schmit bicubics, anisotropic D (eps = 0.25 at 30 degrees), clamped by
+    the symmetric Nitsche terms: L2 error O(h^4)."""
+    Ns = [4, 8, 16]
+    errs = [_bfs_errors(N) for N in Ns]
+    r = _rates(errs, [1.0 / N for N in Ns])
+    assert abs(r[-1] - 4.0) <= 0.15, (errs, r)
+
+
+# ----------------------------------------------------------------------------- Q2 hex elasticity
+
+def _q2hex_errors(N, nu=0.3):
+    """L2 and energy errors of the Q2 hexahedral elasticity solution: u vanishes on the
+    clamped face x = 0 (Nitsche there), body force -div sigma(u) and the tractions
+    sigma(u) n of u on the other five faces."""
+    from fegen.common import gauss_legendre_01, lame_plane_strain
+    from fegen.elasticity import _q2_1d
+    lam_, mu_ = lame_plane_strain(1.0, nu)
+    X, Y, Z = sympy.symbols("x y z")
+    u = [X * sympy.sin(sympy.pi * Y) * (1 + Z), X ** 2 * sympy.cos(sympy.pi * Z), X * Y * Z ** 2]
+    V = (X, Y, Z)
+    grad = [[sympy.diff(u[i], v) for v in V] for i in range(3)]
+    eps = [[(grad[i][j] + grad[j][i]) / 2 for j in range(3)] for i in range(3)]
+    tr = eps[0][0] + eps[1][1] + eps[2][2]
+    sig = [[2 * mu_ * eps[i][j] + (lam_ * tr if i == j else 0) for j in range(3)] for i in range(3)]
+    f = [-sum(sympy.diff(sig[i][j], V[j]) for j in range(3)) for i in range(3)]
+    L = lambda e: sympy.lambdify(V, e, "numpy")
+    uf, ff = [L(c) for c in u], [L(c) for c in f]
+    gf = [[L(grad[i][j]) for j in range(3)] for i in range(3)]
+    sf = [[L(sig[i][j]) for j in range(3)] for i in range(3)]
+    ev = lambda fn, *p: np.broadcast_to(np.asarray(fn(*p), dtype=np.float64), np.shape(p[0]))
+    prob = fegen.elasticity_q2hex(N, nu=nu)
+    h = 1.0 / N
+    M = 2 * N + 1
+    qp, qw = gauss_legendre_01(4)
+    nq = len(qp)
+    v1, d1 = _q2_1d(qp)                                          # [3, q]
+    # reference basis on the q^3 points: values [q3, 27], gradients [q3, 27, 3] (physical)
+    idx = [(a, b, c) for c in range(3) for b in range(3) for a in range(3)]
+    pts = [(i, j, k) for k in range(nq) for j in range(nq) for i in range(nq)]
+    Bv = np.array([[v1[a, i] * v1[b, j] * v1[c, k] for (a, b, c) in idx] for (i, j, k) in pts])
+    Bg = np.array([[[d1[a, i] * v1[b, j] * v1[c, k], v1[a, i] * d1[b, j] * v1[c, k],
+                     v1[a, i] * v1[b, j] * d1[c, k]] for (a, b, c) in idx] for (i, j, k) in pts]) / h
+    W = np.array([qw[i] * qw[j] * qw[k] for (i, j, k) in pts]) * h ** 3
+    e = np.arange(N ** 3)
+    ex, ey, ez = e % N, (e // N) % N, e // (N * N)
+    loc = np.array(idx)
+    nodes = ((2 * ez[:, None] + loc[None, :, 2]) * M + (2 * ey[:, None] + loc[None, :, 1])) * M \
+        + (2 * ex[:, None] + loc[None, :, 0])
+    P = np.array(pts, dtype=np.float64)
+    xq = (ex[:, None] + qp[P[:, 0].astype(int)][None]) * h
+    yq = (ey[:, None] + qp[P[:, 1].astype(int)][None]) * h
+    zq = (ez[:, None] + qp[P[:, 2].astype(int)][None]) * h
+    b = np.zeros(prob.n)
+    for c in range(3):
+        np.add.at(b, 3 * nodes + c, np.einsum("eq,qa,q->ea", ev(ff[c], xq, yq, zq), Bv, W))
+    # tractions on the faces x = 1, y = 0, y = 1, z = 0, z = 1 (face rule: q^2 points)
+    g2 = [(i, j) for j in range(nq) for i in range(nq)]
+    W2 = np.array([qw[i] * qw[j] for (i, j) in g2]) * h * h
+    for axis, side, nrm in ((0, 1, 1.0), (1, 0, -1.0), (1, 1, 1.0), (2, 0, -1.0), (2, 1, 1.0)):
+        ecoord = (ex, ey, ez)[axis]
+        sel = np.flatnonzero(ecoord == (N - 1 if side else 0))
+        t = 1.0 if side else 0.0
+        other = [d for d in range(3) if d != axis]
+        fv = np.zeros((len(g2), 27))
+        for q, (i, j) in enumerate(g2):
+            ref = [0.0, 0.0, 0.0]
+            ref[axis] = t
+            ref[other[0]], ref[other[1]] = qp[i], qp[j]
+            vv = [_q2_1d(np.array([r]))[0][:, 0] for r in ref]
+            fv[q] = [vv[0][a] * vv[1][b2] * vv[2][c] for (a, b2, c) in idx]
+        for e_ in sel:
+            o = np.array([ex[e_], ey[e_], ez[e_]], dtype=np.float64) * h
+            cq = np.zeros((len(g2), 3))
+            cq[:, axis] = t
+            cq[:, other[0]] = o[other[0]] + qp[[i for (i, _) in g2]] * h
+            cq[:, other[1]] = o[other[1]] + qp[[j for (_, j) in g2]] * h
+            for c in range(3):
+                tc = nrm * ev(sf[c][axis], cq[:, 0], cq[:, 1], cq[:, 2])
+                b[3 * nodes[e_] + c] += fv.T @ (W2 * tc)
+    x = _solve(prob, b, max_levels=2, tau_const=0.75, agg_passes=1)
+    xe = x[3 * nodes[:, :, None] + np.arange(3)[None, None, :]]           # [E, 27, 3]
+    uh = np.einsum("qa,eac->eqc", Bv, xe)
+    gh = np.einsum("qad,eac->eqcd", Bg, xe)                               # du_c / dx_d
+    ue = np.stack([ev(uf[c], xq, yq, zq) for c in range(3)], -1)
+    ge = np.stack([np.stack([ev(gf[c][d], xq, yq, zq) for d in range(3)], -1) for c in range(3)], -2)
+    e0 = np.sum(W[None, :, None] * (uh - ue) ** 2)
+    dG = gh - ge
+    de = 0.5 * (dG + np.swapaxes(dG, -1, -2))
+    trd = np.trace(de, axis1=-2, axis2=-1)
+    en = np.sum(W[None, :] * (2 * mu_ * np.sum(de * de, axis=(-2, -1)) + lam_ * trd ** 2))
+    return float(np.sqrt(e0)), float(np.sqrt(en))
+
+
+@pytest.mark.slow
+def test_q2_hex_elasticity_converges_at_the_q2_rates():
+    """27-node hexahedra: L2 error O(h^3), energy error O(h^2)."""
+    Ns = [2, 4, 8]
+    errs = [_q2hex_errors(N) for N in Ns]
+    hs = [1.0 / N for N in Ns]
+    r0 = _rates([e[0] for e in errs], hs)
+    r1 = _rates([e[1] for e in errs], hs)
+    assert abs(r0[-1] - 3.0) <= 0.15, (errs, r0)
+    assert abs(r1[-1] - 2.0) <= 0.15, (errs, r1)
