@@ -196,6 +196,20 @@ lsdd_status lsdd_elem_bilinear(int64_t n_elem, const int64_t* elem_ptr, const in
                                const double* blocks, const double* u, const double* v, int32_t nrhs,
                                int64_t ld, double scale, double* out, void* hip_stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): the same contraction as
+ * lsdd_elem_bilinear, same arguments and result (identical kernels), with its
+ * staging (elem_ptr and the block offsets) in a static device array of the library
+ * instead of per-call allocations.  That array holds 2 (n_elem + 1) int64 entries
+ * for at most 1,048,576 elements (16 MiB per GPU, held until the process ends);
+ * n_elem above that -> LSDD_E_UNSUPPORTED before any device work.  Every call on
+ * one GPU uses that GPU's copy of the array: calls that overlap on one GPU (other
+ * threads, other streams) race.  Calls no hipMalloc/hipFree; blocks until the
+ * result is written. */
+lsdd_status lsdd_elem_bilinear_noalloc(int64_t n_elem, const int64_t* elem_ptr, const int32_t* elem_dofs,
+                                       const double* blocks, const double* u, const double* v, int32_t nrhs,
+                                       int64_t ld, double scale, double* out, void* hip_stream);
+
 /* Build a hierarchy from a black-box sparse Gram factor G (m x n, CSR, host),
  * the input of Sec. 2 (A = G^T G, m >= n, full column rank).  Each row of G is
  * its own cover member: row j contributes g_j g_j^T with support = its stored

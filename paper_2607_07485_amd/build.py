@@ -47,6 +47,7 @@ def build(jobs: int = 4, verbose: bool = False) -> str:
         [hipcc, *HIP_FLAGS, "-c", os.path.join(CSRC, "batched.hip"), "-o", os.path.join(BUILD, "batched.o")],
         [hipcc, *HIP_FLAGS, "-c", os.path.join(CSRC, "blk.hip"), "-o", os.path.join(BUILD, "blk.o")],
         [hipcc, *HIP_FLAGS, "-c", os.path.join(CSRC, "trd.hip"), "-o", os.path.join(BUILD, "trd.o")],
+        [hipcc, *HIP_FLAGS, "-c", os.path.join(CSRC, "noalloc.hip"), "-o", os.path.join(BUILD, "noalloc.o")],
         ["g++", *CXX_FLAGS, "-c", os.path.join(CSRC, "lsdd.cpp"), "-o", os.path.join(BUILD, "lsdd.o")],
         ["g++", *CXX_FLAGS, "-c", os.path.join(CSRC, "graph.cpp"), "-o", os.path.join(BUILD, "graph.o")],
     ]
@@ -54,7 +55,8 @@ def build(jobs: int = 4, verbose: bool = False) -> str:
         for r in ex.map(_run, steps):
             if verbose and (r.stdout or r.stderr):
                 print(r.stdout + r.stderr)
-    objs = [os.path.join(BUILD, f) for f in ("kernels.o", "batched.o", "blk.o", "trd.o", "lsdd.o", "graph.o")]
+    objs = [os.path.join(BUILD, f) for f in ("kernels.o", "batched.o", "blk.o", "trd.o", "noalloc.o", "lsdd.o",
+                                             "graph.o")]
     tmp = LIB + ".tmp"
     _run([hipcc, "-shared", "-fPIC", f"--offload-arch={ARCH}", *objs, "-o", tmp,
           f"-L{os.path.join(ROCM, 'lib')}", "-lamdhip64", f"-Wl,-rpath,{os.path.join(ROCM, 'lib')}",

@@ -1090,6 +1090,40 @@ void launch_elem_bilinear(int64_t n_elem, const int64_t* elem_ptr, const int32_t
                        blk_off, blocks, u, v, nrhs, ld, scale, out);
 }
 
+// blk_off[e] = sum_{f < e} n_f^2 for n_f = elem_ptr[f + 1] - elem_ptr[f], e = 0 .. n_elem:
+// one workgroup, each thread sums a contiguous chunk, the chunk totals are scanned
+// in LDS, then every thread writes its chunk's prefix sums.
+__global__ void __launch_bounds__(1024) k_block_offsets(int64_t n_elem, const int64_t* elem_ptr, int64_t* blk_off) {
+    __shared__ int64_t s[1024];
+    const int t = (int)threadIdx.x;
+    const int64_t chunk = (n_elem + 1023) / 1024;
+    const int64_t a = min(n_elem, (int64_t)t * chunk), b = min(n_elem, a + chunk);
+    int64_t sum = 0;
+    for (int64_t e = a; e < b; ++e) {
+        const int64_t m = elem_ptr[e + 1] - elem_ptr[e];
+        sum += m * m;
+    }
+    s[t] = sum;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+        const int64_t add = t >= off ? s[t - off] : 0;
+        __syncthreads();
+        s[t] += add;
+        __syncthreads();
+    }
+    int64_t run = s[t] - sum;             // exclusive prefix of this chunk
+    for (int64_t e = a; e < b; ++e) {
+        blk_off[e] = run;
+        const int64_t m = elem_ptr[e + 1] - elem_ptr[e];
+        run += m * m;
+    }
+    if (t == 1023) blk_off[n_elem] = s[1023];
+}
+
+void launch_block_offsets(int64_t n_elem, const int64_t* elem_ptr, int64_t* blk_off, hipStream_t st) {
+    hipLaunchKernelGGL(k_block_offsets, dim3(1), dim3(1024), 0, st, n_elem, elem_ptr, blk_off);
+}
+
 void launch_local_assemble(int32_t nbatch, const LocalArgs& a, int32_t max_m, hipStream_t st) {
     if (nbatch <= 0 || max_m <= 0) return;
     hipLaunchKernelGGL(k_local_assemble, dim3((max_m + ASM_CW - 1) / ASM_CW, nbatch), dim3(WG), 0, st, a);

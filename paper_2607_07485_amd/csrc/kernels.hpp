@@ -95,7 +95,14 @@ void launch_scale_blocks(int64_t n_elem, const int64_t* blk_off, const double* s
 void launch_elem_bilinear(int64_t n_elem, const int64_t* elem_ptr, const int32_t* elem_dofs, const int64_t* blk_off,
                           const double* blocks, const double* u, const double* v, int32_t nrhs, int64_t ld,
                           double scale, double* out, hipStream_t st);
+// blk_off[0 .. n_elem] = prefix sums of the squared element sizes (device elem_ptr)
+void launch_block_offsets(int64_t n_elem, const int64_t* elem_ptr, int64_t* blk_off, hipStream_t st);
 
+// Allocation-free entry points (noalloc.hip): the device address, on the current
+// device, of a static scratch array of 2 (NOALLOC_MAX_ELEM + 1) int64 entries
+// (16 MiB), looked up once per device and shared by every call on that device.
+constexpr int64_t NOALLOC_MAX_ELEM = int64_t(1) << 20;
+hipError_t noalloc_scratch(int64_t** out);
 
 void launch_local_assemble(int32_t nbatch, const LocalArgs& a, int32_t max_m, hipStream_t st);
 // max_nw: largest |omega| of the batch (<= 4096)

@@ -2284,6 +2284,32 @@ lsdd_status lsdd_vcycle(lsdd_hierarchy* h, const double* r, double* z, void* hip
     ABI_END
 }
 
+lsdd_status lsdd_elem_bilinear_noalloc(int64_t n_elem, const int64_t* elem_ptr, const int32_t* elem_dofs,
+                                       const double* blocks, const double* u, const double* v, int32_t nrhs,
+                                       int64_t ld, double scale, double* out, void* hip_stream) {
+    ABI_BEGIN
+    if (n_elem < 1 || !elem_ptr || !elem_dofs || !blocks || !u || !v || !out || nrhs < 1 || ld < 1)
+        throw Error(LSDD_E_INVAL, "bad argument");
+    if (n_elem > NOALLOC_MAX_ELEM)
+        throw Error(LSDD_E_UNSUPPORTED, "lsdd_elem_bilinear_noalloc: more than 1048576 elements");
+    if (elem_ptr[0] != 0) throw Error(LSDD_E_INVAL, "elem_ptr[0] must be 0");
+    for (int64_t e = 0; e < n_elem; ++e) {
+        const int64_t m = elem_ptr[e + 1] - elem_ptr[e];
+        if (m < 1 || m > 4096) throw Error(LSDD_E_INVAL, "bad element size");
+    }
+    int64_t* scr = nullptr;
+    HIPCHK(noalloc_scratch(&scr));
+    hipStream_t st = (hipStream_t)hip_stream;
+    int64_t* d_ptr = scr;
+    int64_t* d_boff = scr + (n_elem + 1);
+    HIPCHK(hipMemcpyAsync(d_ptr, elem_ptr, (size_t)(n_elem + 1) * sizeof(int64_t), hipMemcpyHostToDevice, st));
+    launch_block_offsets(n_elem, d_ptr, d_boff, st);
+    launch_elem_bilinear(n_elem, d_ptr, elem_dofs, d_boff, blocks, u, v, nrhs, ld, scale, out, st);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(st));
+    return LSDD_OK;
+    ABI_END
+}
 lsdd_status lsdd_apply(lsdd_hierarchy* h, int32_t level, const double* x, double* y, void* hip_stream) {
     ABI_BEGIN
     if (!h || !x || !y || level < 0 || level >= (int32_t)h->L.size()) throw Error(LSDD_E_INVAL, "bad argument");

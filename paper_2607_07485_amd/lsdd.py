@@ -94,6 +94,8 @@ def lib():
         L.lsdd_update_theta.argtypes = [_P, _P, _P]
         L.lsdd_elem_bilinear.argtypes = [C.c_int64, i64p, _P, _P, _P, _P, C.c_int32, C.c_int64, C.c_double, _P,
                                          _P]
+        L.lsdd_elem_bilinear_noalloc.argtypes = [C.c_int64, i64p, _P, _P, _P, _P, C.c_int32, C.c_int64,
+                                                 C.c_double, _P, _P]
         L.lsdd_solve_batched.argtypes = [C.c_int32, C.POINTER(_P), C.POINTER(_P), C.POINTER(_P), C.c_int32, _P,
                                          C.POINTER(Info)]
         L.lsdd_level_tuning.argtypes = [_P, C.c_int32, i32p]
@@ -104,7 +106,7 @@ def lib():
                      "lsdd_destroy", "lsdd_set_cycle_precision", "lsdd_trace", "lsdd_trace_get",
                      "lsdd_set_solve_params", "lsdd_set_graph", "lsdd_segments", "lsdd_setup_batched",
                      "lsdd_level_segments", "lsdd_autotune", "lsdd_level_tuning", "lsdd_setup_elements_scaled",
-                     "lsdd_update_theta", "lsdd_elem_bilinear",
+                     "lsdd_update_theta", "lsdd_elem_bilinear", "lsdd_elem_bilinear_noalloc",
                      "lsdd_solve_batched"):
             getattr(L, name).restype = C.c_int
         _LIB = L
