@@ -635,6 +635,22 @@ def run_graddiv(a, torch, P, fegen, dev):
     dt = times[best]
     h.set_cycle_precision(prec)
 
+    # per-kernel timing of one more solve of each other converged leg (HIP events), for the record
+    for name in times:
+        if name == best:
+            continue
+        h.set_cycle_precision({"fp64": 0, "fp32": 1, "mixed": 2}[name])
+        h.trace(True)
+        h.solve(b)
+        h.trace(False)
+        trl = h.trace_read()
+        legs[name]["kernels"] = {k: dict(launches=v["launches"], ms=round(v["ms"], 4),
+                                         gbs=round(v["bytes"] / max(v["ms"], 1e-9) / 1e6, 1)) for k, v in trl.items()}
+        lb = sum(v["bytes"] for v in trl.values())
+        legs[name]["cycle_roofline"] = {"achieved": lb / times[name] / 1e9, "frac": lb / times[name] / 1e9 / HBM_PEAK_GBS,
+                                        "bytes_per_solve": lb}
+        print(f"[bench] {name} kernels {json.dumps(legs[name]['kernels'])}", file=sys.stderr, flush=True)
+    h.set_cycle_precision(prec)
     # live per-kernel timing of one more solve of the reported variant (HIP events on the solve stream)
     h.trace(True)
     h.solve(b)

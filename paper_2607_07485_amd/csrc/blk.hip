@@ -9,6 +9,7 @@
 
 #include <cmath>
 #include <stdexcept>
+#include <type_traits>
 
 #include "blk.hpp"
 #include "kernels.hpp"
@@ -465,34 +466,37 @@ __global__ void __launch_bounds__(64) k_small_sub(int32_t s0, const int64_t* sub
     for (int e = lane; e < np; e += 64) s_a[e] = A[e];
     for (int e = lane; e < m * NR; e += 64) s_x[e] = rloc[o * NR + e];
     __syncthreads();
+    // the factor form keeps its sums in FP64 (FP32 storage): its two products
+    // would otherwise each add FP32 rounding to an ill-conditioned local solve
+    using Acc = typename std::conditional<FACT, double, T>::type;
     if (FACT) {
         if (lane < m) {
             const int i = lane;
             const int ri = i * (i + 1) / 2;
-            T wv[NR];
+            Acc wv[NR];
 #pragma unroll
             for (int k = 0; k < NR; ++k) wv[k] = 0;
             for (int j = 0; j <= i; ++j) {
-                const T a = s_a[ri + j];
+                const Acc a = s_a[ri + j];
 #pragma unroll
-                for (int k = 0; k < NR; ++k) wv[k] += a * s_x[j * NR + k];
+                for (int k = 0; k < NR; ++k) wv[k] += a * (Acc)s_x[j * NR + k];
             }
 #pragma unroll
-            for (int k = 0; k < NR; ++k) s_w[i * NR + k] = wv[k];
+            for (int k = 0; k < NR; ++k) s_w[i * NR + k] = (T)wv[k];
         }
         __syncthreads();
     }
     if (lane < m) {
         const int i = lane;
         const int ri = i * (i + 1) / 2;
-        T y[NR];
+        Acc y[NR];
 #pragma unroll
         for (int k = 0; k < NR; ++k) y[k] = 0;
         if (FACT) {
             for (int j = i; j < m; ++j) {
-                const T a = s_a[j * (j + 1) / 2 + i];
+                const Acc a = s_a[j * (j + 1) / 2 + i];
 #pragma unroll
-                for (int k = 0; k < NR; ++k) y[k] += a * s_w[j * NR + k];
+                for (int k = 0; k < NR; ++k) y[k] += a * (Acc)s_w[j * NR + k];
             }
         } else {
             for (int j = 0; j < m; ++j) {
@@ -621,18 +625,27 @@ __global__ void __launch_bounds__(WG) k_seg_dot(const int64_t* blk_lo, const int
 }
 
 // out[s * NR + k] = sum over the blocks of segment s, in block order
+// One wave per (segment, right-hand side): lane l sums the blocks l, l + 64, ... of
+// the segment in order, then a butterfly over the lanes -- a fixed order, so the
+// same partials always give the same sum.
 __global__ void k_seg_sum(int n_seg, int nr, const int32_t* seg_blk, const double* part, int n_blk, double* out0,
                           double* out1) {
-    const int i = blockIdx.x * WG + tid();
+    const int i = (int)((blockIdx.x * WG + tid()) >> 6), lane = tid() & 63;
     if (i >= n_seg * nr) return;
     const int s = i / nr, k = i % nr;
     double u = 0.0, v = 0.0;
-    for (int b = seg_blk[s]; b < seg_blk[s + 1]; ++b) {
+    for (int b = seg_blk[s] + lane; b < seg_blk[s + 1]; b += 64) {
         u += part[(int64_t)b * nr + k];
         v += part[((int64_t)n_blk + b) * nr + k];
     }
-    out0[i] = u;
-    if (out1) out1[i] = v;
+    for (int off = 32; off > 0; off >>= 1) {
+        u += __shfl_xor(u, off, 64);
+        v += __shfl_xor(v, off, 64);
+    }
+    if (lane == 0) {
+        out0[i] = u;
+        if (out1) out1[i] = v;
+    }
 }
 
 __global__ void k_pcg_init(int n_s, const double* bb, int32_t* act, int32_t* iters, double* relres,
@@ -655,7 +668,9 @@ __global__ void k_pcg_alpha(int n_s, const int32_t* act, const double* rz, const
     double a = 0.0;
     if (act[i]) {
         const double d = pq[i];
-        if (!(d > 0.0) || !isfinite(d) || !isfinite(rz[i])) flag[0] = 1;
+        // breakdown cause bits: 1 p^T A p <= 0, 2 p^T A p or r^T z not finite
+        if (!isfinite(d) || !isfinite(rz[i])) atomicOr(flag, 2);
+        else if (!(d > 0.0)) atomicOr(flag, 1);
         else a = rz[i] / d;
     }
     alpha[i] = a;
@@ -704,7 +719,7 @@ __global__ void __launch_bounds__(WG) k_pcg_check(int n_s, int32_t* it_dev, doub
         if (!act[i]) continue;
         const double v = rr[i];
         if (!isfinite(v)) {
-            flag[0] = 1;
+            atomicOr(flag, 4);          // residual norm not finite
             continue;
         }
         relres[i] = sqrt(v / bb[i]);
@@ -732,7 +747,7 @@ __global__ void k_pcg_beta(int n_s, const int32_t* act, const double* rz_new, co
     if (act[i]) {
         const double num = rz_old_dot ? rz_new[i] - rz_old_dot[i] : rz_new[i];
         bt = num / rz[i];
-        if (!isfinite(bt)) flag[0] = 1;
+        if (!isfinite(bt)) atomicOr(flag, 8);   // beta not finite
         rz[i] = rz_new[i];
     }
     beta[i] = bt;
@@ -867,7 +882,7 @@ void launch_seg_dot(const SegTable& t, int nr, const double* a0, const double* b
     else
         hipLaunchKernelGGL(k_seg_dot<1>, dim3((unsigned)t.n_blk), dim3(WG), 0, st, t.blk_lo, t.blk_hi, a0, b0, a1, b1,
                            part, t.n_blk);
-    hipLaunchKernelGGL(k_seg_sum, dim3(grid_for((int64_t)t.n_seg * nr)), dim3(WG), 0, st, t.n_seg, nr, t.seg_blk,
+    hipLaunchKernelGGL(k_seg_sum, dim3(grid_for((int64_t)t.n_seg * nr * 64)), dim3(WG), 0, st, t.n_seg, nr, t.seg_blk,
                        part, t.n_blk, out0, a1 ? out1 : nullptr);
 }
 
@@ -889,7 +904,7 @@ void launch_pcg_update_xr(const SegTable& t, int nr, const int32_t* act, const d
     else
         hipLaunchKernelGGL(k_pcg_update_xr<1>, dim3((unsigned)t.n_blk), dim3(WG), 0, st, t.blk_seg, t.blk_lo,
                            t.blk_hi, act, alpha, p, q, x, r, part);
-    hipLaunchKernelGGL(k_seg_sum, dim3(grid_for((int64_t)t.n_seg * nr)), dim3(WG), 0, st, t.n_seg, nr, t.seg_blk,
+    hipLaunchKernelGGL(k_seg_sum, dim3(grid_for((int64_t)t.n_seg * nr * 64)), dim3(WG), 0, st, t.n_seg, nr, t.seg_blk,
                        part, 0, rr, nullptr);
 }
 

@@ -698,13 +698,7 @@ __global__ void __launch_bounds__(WG) k_csr_spmv(int64_t n, const int64_t* rowpt
 // per (tile row, chunk), column parts per tile -- that k_sub_finalize sums in a
 // fixed order, so the smoother is the same linear map on every application (no
 // order-dependent atomics).
-//
-// MODE 1 and 2 apply a lower-triangular factor X (same tile storage, zero above
-// the diagonal) for the local solve X^T (X r): MODE 1 forms the row parts of
-// X r only (finalized without column parts), MODE 2 the column parts of X^T w
-// only, the diagonal tile's transposed product (diagonal included) going into
-// the row part of its item.
-template <typename T, int MODE>
+template <typename T>
 __global__ void __launch_bounds__(WG) k_sub_symv(const int32_t* items, const int64_t* sub_off, const int64_t* tp_off,
                                                  const T* tiles, const T* rloc, const int64_t* scr_off, T* scr,
                                                  int chl) {
@@ -760,14 +754,11 @@ __global__ void __launch_bounds__(WG) k_sub_symv(const int32_t* items, const int
         for (int q = 0; q < 16; ++q) {
             const int r = w + 4 * q;
             const T a = (dg && lane > r) ? (T)0 : v[q];
-            if (MODE != 2) p[q] += a * xj;
-            if (MODE == 0) col += ((dg && lane == r) ? (T)0 : a) * s_xi[r];
-            if (MODE == 2) col += a * s_xi[r];
+            p[q] += a * xj;
+            col += ((dg && lane == r) ? (T)0 : a) * s_xi[r];
         }
-        if (MODE != 1) {
-            if (dg) s_d[w][lane] = col;
-            else s_c[w][jj][lane] = col;
-        }
+        if (dg) s_d[w][lane] = col;
+        else s_c[w][jj][lane] = col;
     };
     fetch(va, 0);
 #pragma unroll
@@ -781,27 +772,22 @@ __global__ void __launch_bounds__(WG) k_sub_symv(const int32_t* items, const int
             use(vb, jj + 1);
         }
     }
-    if (MODE != 2) {
 #pragma unroll
-        for (int q = 0; q < 16; ++q) {
-            T v = p[q];
-            for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-            p[q] = v;
-        }
+    for (int q = 0; q < 16; ++q) {
+        T v = p[q];
+        for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+        p[q] = v;
     }
     __syncthreads();
     if (lane < 16) {
         T y = 0;
-        if (MODE != 2) {
 #pragma unroll
-            for (int q = 0; q < 16; ++q)
-                if (q == lane) y = p[q];
-        }
+        for (int q = 0; q < 16; ++q)
+            if (q == lane) y = p[q];
         const int r = w + 4 * lane;
-        if (MODE != 1 && ncol < nJ) y += (s_d[0][r] + s_d[1][r]) + (s_d[2][r] + s_d[3][r]);
+        if (ncol < nJ) y += (s_d[0][r] + s_d[1][r]) + (s_d[2][r] + s_d[3][r]);
         part[(symv_rowpart_off(I, chl) + ch) * 64 + r] = y;
     }
-    if (MODE == 1) return;
     for (int a = tid(); a < ncol * 64; a += WG) {
         const int jj = a >> 6, l = a & 63;
         colpart[((int64_t)I * (I - 1) / 2 + J0 + jj) * 64 + l] =
@@ -809,10 +795,105 @@ __global__ void __launch_bounds__(WG) k_sub_symv(const int32_t* items, const int
     }
 }
 
+// Factor-form local solve y = X^T (X r) of the mixed cycle in one pass over the
+// FP32 factor tiles (the lower tiles of X = L^{-1} in the storage of k_sub_symv,
+// zero above the diagonal), FP64 sums.  Work item = (subdomain, whole tile row
+// I).  Phase 1 streams the row's tiles through the caches and forms
+// w_I = sum_{J <= I} X_IJ r_J (waves split the 64 rows, lanes the 64 columns,
+// per-lane partial sums reduced across the lanes once per item).  Phase 2 reads
+// the same tiles again, now from the caches, with the same lane mapping: each
+// wave forms the products of its 16 rows of w_I with the tile's columns and the
+// four waves' partials are added in LDS: X_IJ^T w_I is the column part of tile (I, J);
+// the diagonal tile's goes to the row-part slot of the chunk that holds it and
+// the row's other chunk slots get zero, so k_sub_finalize sums the same layout as
+// for the symmetric product.  HBM reads one pass of X (half the bytes of the FP64
+// inverse) instead of two.
+__global__ void __launch_bounds__(WG) k_sub_fact(const int32_t* items, const int64_t* sub_off, const int64_t* tp_off,
+                                                 const float* tiles, const float* rloc, const int64_t* scr_off,
+                                                 float* scr, int chl) {
+    constexpr int CH = 8;                                   // tiles per phase-2 LDS round
+    __shared__ double s_w[64];
+    __shared__ double s_c[4][CH][64];
+    const int s = items[2 * blockIdx.x];
+    const int I = items[2 * blockIdx.x + 1];
+    const int64_t o = sub_off[s];
+    const int m = (int)(sub_off[s + 1] - o);
+    const int nt = (m + 63) >> 6;
+    const int lane = tid() & 63, w = tid() >> 6;
+    const float* row0 = tiles + tp_off[s] + (int64_t)I * (I + 1) / 2 * 4096;
+    float* part = scr + scr_off[s];
+    float* colpart = part + symv_rowpart_off(nt, chl) * 64;
+    double p[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) p[q] = 0.0;
+    float va[16], vb[16];
+    // waves split the tile's 64 rows (row w + 4 q), lanes its columns
+    auto fetch = [&](float(&v)[16], int J) {
+        const float* t = row0 + (int64_t)J * 4096;
+#pragma unroll
+        for (int q = 0; q < 16; ++q) v[q] = t[(w + 4 * q) * 64 + lane];
+    };
+    // phase 1: per-lane partials of w_I = sum_J X_IJ r_J
+    auto use1 = [&](const float(&v)[16], int J) {
+        const int c = J * 64 + lane;
+        const double xj = c < m ? (double)rloc[o + c] : 0.0;
+#pragma unroll
+        for (int q = 0; q < 16; ++q) p[q] += (double)v[q] * xj;
+    };
+    fetch(va, 0);
+    for (int J = 0; J <= I; J += 2) {
+        if (J + 1 <= I) fetch(vb, J + 1);
+        use1(va, J);
+        if (J + 1 <= I) {
+            if (J + 2 <= I) fetch(va, J + 2);
+            use1(vb, J + 1);
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+        double v = p[q];
+        for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+        p[q] = v;                                           // w_I[w + 4 q], on every lane
+    }
+    // phase 2: column parts X_IJ^T w_I, the row's tiles read again (now from the
+    // caches) in rounds of CH tiles; per-wave partials summed over the waves in LDS
+    auto use2 = [&](const float(&v)[16], int jj) {
+        double col = 0.0;
+#pragma unroll
+        for (int q = 0; q < 16; ++q) col += (double)v[q] * p[q];
+        s_c[w][jj][lane] = col;
+    };
+    for (int J0 = 0; J0 <= I; J0 += CH) {
+        const int nJ = min(CH, I + 1 - J0);
+        fetch(va, J0);
+#pragma unroll
+        for (int jj = 0; jj < CH; jj += 2) {
+            if (jj < nJ) {
+                if (jj + 1 < nJ) fetch(vb, J0 + jj + 1);
+                use2(va, jj);
+            }
+            if (jj + 1 < nJ) {
+                if (jj + 2 < nJ) fetch(va, J0 + jj + 2);
+                use2(vb, jj + 1);
+            }
+        }
+        __syncthreads();
+        for (int a = tid(); a < nJ * 64; a += WG) {
+            const int jj = a >> 6, l = a & 63, J = J0 + jj;
+            const float v = (float)((s_c[0][jj][l] + s_c[1][jj][l]) + (s_c[2][jj][l] + s_c[3][jj][l]));
+            if (J < I) colpart[((int64_t)I * (I - 1) / 2 + J) * 64 + l] = v;
+            else part[(symv_rowpart_off(I, chl) + I / chl) * 64 + l] = v;
+        }
+        __syncthreads();
+    }
+    if (w == 0)
+        for (int ch = 0; ch < I / chl; ++ch) part[(symv_rowpart_off(I, chl) + ch) * 64 + lane] = 0.0f;
+}
+
 // x[Omega_s[c]] (+)= row-part chunks of tile row J(c) + column parts of the
 // tile rows below.  FL threads per DOF each sum a fixed strided subset of the
 // partials; the FL sums are added in LDS in ascending order (fixed order).
-template <typename T, int FL, bool COLS>
+template <typename T, int FL>
 __global__ void __launch_bounds__(WG) k_sub_finalize(int64_t r0, int64_t r1, const int32_t* pos_sub,
                                                      const int64_t* sub_off, const int64_t* scr_off, const T* scr,
                                                      const int32_t* sub_dofs, T* x, int accumulate, int chl) {
@@ -830,7 +911,7 @@ __global__ void __launch_bounds__(WG) k_sub_finalize(int64_t r0, int64_t r1, con
         const T* part = scr + scr_off[s] + symv_rowpart_off(J, chl) * 64 + l;
         const T* colpart = scr + scr_off[s] + symv_rowpart_off(nt, chl) * 64 + l;
         const int nch = (J + chl) / chl;
-        const int K = COLS ? nch + (nt - 1 - J) : nch;
+        const int K = nch + (nt - 1 - J);
         // one load per partial, its address chosen without a branch so that the
         // unrolled loads are all in flight before the first wait
 #pragma unroll 4
@@ -1218,41 +1299,38 @@ void launch_csr_spmv(int64_t n, const int64_t* rowptr, const int32_t* col, const
         hipLaunchKernelGGL((k_csr_spmv<T, V, 8>), dim3(grid_for(n * 8)), dim3(WG), 0, st, n, rowptr, col, val, x, y,
                            r_minus);
 }
-template <typename T, int MODE>
-static void sub_symv_mode(int64_t n_items, const int32_t* items, const int64_t* sub_off, const int64_t* tp_off,
-                          const T* tiles, const T* rloc, const int64_t* scr_off, T* scr, int chl, hipStream_t st) {
-    hipEvent_t e0, e1;
-    if (take_launch_events(&e0, &e1))
-        hipExtLaunchKernelGGL((k_sub_symv<T, MODE>), dim3((unsigned)n_items), dim3(WG), 0, st, e0, e1, 0, items,
-                              sub_off, tp_off, tiles, rloc, scr_off, scr, chl);
-    else
-        hipLaunchKernelGGL((k_sub_symv<T, MODE>), dim3((unsigned)n_items), dim3(WG), 0, st, items, sub_off, tp_off,
-                           tiles, rloc, scr_off, scr, chl);
-}
 template <typename T>
 void launch_sub_symv(int64_t n_items, const int32_t* items, const int64_t* sub_off, const int64_t* tp_off,
-                     const T* tiles, const T* rloc, const int64_t* scr_off, T* scr, int chl, hipStream_t st,
-                     int mode) {
+                     const T* tiles, const T* rloc, const int64_t* scr_off, T* scr, int chl, hipStream_t st) {
     if (n_items <= 0) return;
-    if (mode == 1) sub_symv_mode<T, 1>(n_items, items, sub_off, tp_off, tiles, rloc, scr_off, scr, chl, st);
-    else if (mode == 2) sub_symv_mode<T, 2>(n_items, items, sub_off, tp_off, tiles, rloc, scr_off, scr, chl, st);
-    else sub_symv_mode<T, 0>(n_items, items, sub_off, tp_off, tiles, rloc, scr_off, scr, chl, st);
+    hipEvent_t e0, e1;
+    if (take_launch_events(&e0, &e1))
+        hipExtLaunchKernelGGL(k_sub_symv<T>, dim3((unsigned)n_items), dim3(WG), 0, st, e0, e1, 0, items, sub_off,
+                              tp_off, tiles, rloc, scr_off, scr, chl);
+    else
+        hipLaunchKernelGGL(k_sub_symv<T>, dim3((unsigned)n_items), dim3(WG), 0, st, items, sub_off, tp_off, tiles,
+                           rloc, scr_off, scr, chl);
 }
 template <typename T>
 void launch_sub_finalize(int64_t r0, int64_t r1, const int32_t* pos_sub, const int64_t* sub_off,
                          const int64_t* scr_off, const T* scr, const int32_t* sub_dofs, T* x, bool accumulate,
-                         int chl, int fl, hipStream_t st, bool cols) {
+                         int chl, int fl, hipStream_t st) {
     if (r1 <= r0) return;
     const int acc = accumulate ? 1 : 0;
-    if (!cols)
-        hipLaunchKernelGGL((k_sub_finalize<T, 8, false>), dim3(grid_for(r1 - r0, WG / 8)), dim3(WG), 0, st, r0, r1,
-                           pos_sub, sub_off, scr_off, scr, sub_dofs, x, acc, chl);
-    else if (fl >= 32)
-        hipLaunchKernelGGL((k_sub_finalize<T, 32, true>), dim3(grid_for(r1 - r0, WG / 32)), dim3(WG), 0, st, r0, r1,
+    if (fl >= 32)
+        hipLaunchKernelGGL((k_sub_finalize<T, 32>), dim3(grid_for(r1 - r0, WG / 32)), dim3(WG), 0, st, r0, r1,
                            pos_sub, sub_off, scr_off, scr, sub_dofs, x, acc, chl);
     else
-        hipLaunchKernelGGL((k_sub_finalize<T, 8, true>), dim3(grid_for(r1 - r0, WG / 8)), dim3(WG), 0, st, r0, r1,
+        hipLaunchKernelGGL((k_sub_finalize<T, 8>), dim3(grid_for(r1 - r0, WG / 8)), dim3(WG), 0, st, r0, r1,
                            pos_sub, sub_off, scr_off, scr, sub_dofs, x, acc, chl);
+}
+
+void launch_sub_fact(int64_t n_items, const int32_t* items, const int64_t* sub_off, const int64_t* tp_off,
+                     const float* tiles, const float* rloc, const int64_t* scr_off, float* scr, int chl,
+                     hipStream_t st) {
+    if (n_items <= 0) return;
+    hipLaunchKernelGGL(k_sub_fact, dim3((unsigned)n_items), dim3(WG), 0, st, items, sub_off, tp_off, tiles, rloc,
+                       scr_off, scr, chl);
 }
 
 int64_t sub_symv_scratch_len(int64_t m, int chl) { return symv_scratch_len((int)((m + 63) / 64), chl); }
@@ -1339,9 +1417,9 @@ void launch_check_finite(int64_t n, const double* a, int32_t* flag, hipStream_t 
     template void launch_csr_spmv<T, T>(int64_t, const int64_t*, const int32_t*, const T*, const T*, T*, const T*,    \
                                         int, hipStream_t);                                                            \
     template void launch_sub_symv<T>(int64_t, const int32_t*, const int64_t*, const int64_t*, const T*, const T*,    \
-                                     const int64_t*, T*, int, hipStream_t, int);                                      \
+                                     const int64_t*, T*, int, hipStream_t);                                           \
     template void launch_sub_finalize<T>(int64_t, int64_t, const int32_t*, const int64_t*, const int64_t*, const T*, \
-                                         const int32_t*, T*, bool, int, int, hipStream_t, bool);                      \
+                                         const int32_t*, T*, bool, int, int, hipStream_t);                            \
     template void launch_restrict<T>(int64_t, const int32_t*, const int64_t*, const int32_t*, const int64_t*,        \
                                      const int32_t*, const int64_t*, const T*, const T*, T*, hipStream_t);            \
     template void launch_prolong<T>(int64_t, const int32_t*, const int64_t*, const int32_t*, const int64_t*,         \

@@ -155,19 +155,21 @@ void launch_csr_resid_rows(int64_t nrows, const int32_t* rows, const int64_t* ro
 template <typename T, typename V = T>
 void launch_csr_spmv(int64_t n, const int64_t* rowptr, const int32_t* col, const V* val, const T* x, T* y,
                      const T* r_minus, int lanes, hipStream_t st);
-// chl: tiles per work item (1..8); the scratch layout depends on it.  mode 0:
-// symmetric inverse; mode 1 / 2: the two passes X r and X^T w of a lower
-// triangular factor X (mode 1 partials are finalized with cols = false)
+// chl: tiles per work item (1..8); the scratch layout depends on it
 template <typename T>
 void launch_sub_symv(int64_t n_items, const int32_t* items, const int64_t* sub_off, const int64_t* tp_off,
-                     const T* tiles, const T* rloc, const int64_t* scr_off, T* scr, int chl, hipStream_t st,
-                     int mode = 0);
+                     const T* tiles, const T* rloc, const int64_t* scr_off, T* scr, int chl, hipStream_t st);
 // x[sub_dofs[t]] (+)= sum of the partials of entry t, for t in [r0, r1); sub_dofs NULL = identity;
-// fl: threads per entry (8 or 32); cols = false: row parts only
+// fl: threads per entry (8 or 32)
 template <typename T>
 void launch_sub_finalize(int64_t r0, int64_t r1, const int32_t* pos_sub, const int64_t* sub_off,
                          const int64_t* scr_off, const T* scr, const int32_t* sub_dofs, T* x, bool accumulate,
-                         int chl, int fl, hipStream_t st, bool cols = true);
+                         int chl, int fl, hipStream_t st);
+// mixed cycle: y = X^T (X r) with FP32 factor tiles in one pass, FP64 sums; items =
+// (subdomain, whole tile row) pairs; partials in the layout of launch_sub_symv for chl
+void launch_sub_fact(int64_t n_items, const int32_t* items, const int64_t* sub_off, const int64_t* tp_off,
+                     const float* tiles, const float* rloc, const int64_t* scr_off, float* scr, int chl,
+                     hipStream_t st);
 // scratch entries for a subdomain of size m; append its work items (s, tile row, chunk)
 int64_t sub_symv_scratch_len(int64_t m, int chl);
 void sub_symv_items(int32_t s, int64_t m, int chl, std::vector<int32_t>& items);

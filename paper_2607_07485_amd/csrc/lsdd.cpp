@@ -138,7 +138,6 @@ struct VecSet {
     T* t = nullptr;
     T* rloc = nullptr;
     T* scr = nullptr;
-    T* w = nullptr;      // factor-form local solves: X r per overlap entry
 };
 
 struct Level {
@@ -214,6 +213,8 @@ struct Level {
     int32_t smoother = 0;                 // 0 multiplicative Schwarz, 1 RAS, 2 block Jacobi
     int64_t* d_sw_tp_off = nullptr;   // packed-tile offset of each subdomain (sweep order)
     int32_t* d_items = nullptr;       // (subdomain, tile row), grouped by colour
+    int32_t* d_row_items = nullptr;   // mixed cycle: (subdomain, whole tile row), grouped by colour
+    std::vector<int64_t> color_ritem0;
     int32_t* d_pos_sub = nullptr;     // sweep-order subdomain of every Omega entry
     int64_t* d_scr_off = nullptr;     // per subdomain: offset of its partial-sum scratch
     // coarsest level as one packed symmetric "subdomain"
@@ -331,6 +332,7 @@ struct lsdd_hierarchy {
     // element coefficients the level-0 blocks were scaled with at setup (NULL: none)
     double* d_scale0 = nullptr;
     double* d_factor = nullptr;   // scratch for lsdd_update_theta
+    int32_t breakdown_bits = 0;   // cause of the last PCG breakdown (k_pcg_alpha/check/beta bits)
     // hipGraph-captured halves of the PCG iteration: [block][cycle precision][half]
     bool use_graph = false;
     hipGraphExec_t gx[2][3][2] = {};
@@ -341,6 +343,16 @@ namespace lsdd {
 namespace {
 
 void sync(hipStream_t st) { HIPCHK(hipStreamSynchronize(st)); }
+
+std::string breakdown_cause(int32_t bits) {
+    std::string s;
+    auto add = [&](const char* t) { s += (s.empty() ? "" : ", ") + std::string(t); };
+    if (bits & 1) add("p^T A p <= 0 (preconditioner or operator not positive definite)");
+    if (bits & 2) add("p^T A p or r^T z not finite");
+    if (bits & 4) add("residual norm not finite");
+    if (bits & 8) add("beta not finite");
+    return s.empty() ? "unknown" : s;
+}
 
 // Device copies of a level's element supports and blocks.
 void upload_elements(lsdd_hierarchy* h, Level& lv) {
@@ -412,7 +424,6 @@ void alloc_vectors(lsdd_hierarchy* h, Level& lv, int b) {
         v.t = a.alloc<float>(lv.n * w);
         v.rloc = a.alloc<float>(nl);
         v.scr = a.alloc<float>(ns);
-        if (h->prm.precision == 2 && b == 0) v.w = a.alloc<float>(nl);
         if (!lv.term.empty()) {
             lv.cr64[b] = a.alloc<double>(lv.n * w);
             lv.cx64[b] = a.alloc<double>(lv.n * w);
@@ -1086,6 +1097,25 @@ std::unique_ptr<Level> coarsen(lsdd_hierarchy* h, Level& lv, const int32_t* agg_
     if (P.smoother == 1) lv.d_sw_sub_dofs_w = ar.upload(sw_dofs_w, st);
     lv.d_sw_tp_off = ar.upload(sw_tp_off, st);
     lv.d_items = ar.upload(items, st);
+    if (P.precision == 2) {
+        // whole-tile-row items of the one-pass factor product, longest rows first per colour
+        std::vector<int32_t> ritems;
+        lv.color_ritem0.assign(lv.n_colors + 1, 0);
+        for (int32_t c = 0; c < lv.n_colors; ++c) {
+            std::vector<std::pair<int32_t, int32_t>> rows;
+            for (int32_t q = lv.color_sub0[c]; q < lv.color_smid[c]; ++q) {
+                const int32_t nt = (int32_t)((lv.sw_sub_off[q + 1] - lv.sw_sub_off[q] + 63) / 64);
+                for (int32_t I = 0; I < nt; ++I) rows.emplace_back(q, I);
+            }
+            std::stable_sort(rows.begin(), rows.end(),
+                             [](const std::pair<int32_t, int32_t>& a, const std::pair<int32_t, int32_t>& b) {
+                                 return a.second > b.second;
+                             });
+            for (auto& r : rows) ritems.insert(ritems.end(), {r.first, r.second});
+            lv.color_ritem0[c + 1] = (int64_t)ritems.size() / 2;
+        }
+        lv.d_row_items = ar.upload(ritems, st);
+    }
     {
         std::vector<int32_t> pos_sub(sw_dofs.size());
         std::vector<int64_t> scr_off(n_agg + 1, 0);
@@ -1420,10 +1450,11 @@ void sweep_ras(lsdd_hierarchy* h, Level& lv, const T* r, T* x, bool post, bool x
 
 // Mixed-precision multiplicative Schwarz sweep (FP32 vectors): the local residuals
 // use the FP64 operator entries (sums in FP64, rounded once), the local solves
-// the FP32 factors X = L^{-1} of A_Omega as X^T (X r) -- a product of a matrix
-// with its own transpose, so the rounded local solve stays symmetric positive
-// semidefinite; an FP32 copy of the explicit inverse does not (on operators whose
-// spectrum spans more than FP32 resolves, it becomes indefinite).
+// the FP32 factors X = L^{-1} of A_Omega as X^T (X r) with FP64 sums, in one pass
+// over the factor tiles -- a product of a matrix with its own transpose, so the
+// rounded local solve stays symmetric positive semidefinite; an FP32 copy of the
+// explicit inverse does not (on operators whose spectrum spans more than FP32
+// resolves, it becomes indefinite).
 void sweep_factor(lsdd_hierarchy* h, Level& lv, const float* r, float* x, bool forward, bool x_zero_first) {
     VecSet<float>& v = lv.v32[0];
     for (int32_t cc = 0; cc < lv.n_colors; ++cc) {
@@ -1438,23 +1469,16 @@ void sweep_factor(lsdd_hierarchy* h, Level& lv, const float* r, float* x, bool f
             launch_csr_resid_rows<float, double>(r1 - r0, lv.d_sw_sub_dofs + r0, lv.d_rowptr, lv.d_col, lv.d_val, x, r,
                                                  v.rloc + r0, xz, lv.lanes, h->st);
         });
-        if (i1 > i0) {
+        const int64_t j0 = lv.color_ritem0[c], j1 = lv.color_ritem0[c + 1];
+        if (j1 > j0) {
             const double gb = lv.color_m2[c] * 4.0 + (double)(rm - r0) * (4 + 3 * 4.0);
-            traced(h, "sub_trmv", gb, [&] {
-                launch_sub_symv<float>(i1 - i0, lv.d_items + 3 * i0, lv.d_sw_sub_off, lv.d_sw_tp_off, lv.d_tfac32,
-                                       v.rloc, lv.d_scr_off, v.scr, lv.chl, h->st, 1);
-            });
-            traced(h, "sub_finalize", lv.color_scr[c] * 4.0 + (double)(rm - r0) * 12.0, [&] {
-                launch_sub_finalize<float>(r0, rm, lv.d_pos_sub, lv.d_sw_sub_off, lv.d_scr_off, v.scr, nullptr, v.w,
-                                           false, lv.chl, lv.fl, h->st, false);
-            });
-            traced(h, "sub_trmv", gb, [&] {
-                launch_sub_symv<float>(i1 - i0, lv.d_items + 3 * i0, lv.d_sw_sub_off, lv.d_sw_tp_off, lv.d_tfac32,
-                                       v.w, lv.d_scr_off, v.scr, lv.chl, h->st, 2);
+            traced(h, "sub_fact", gb, [&] {
+                launch_sub_fact(j1 - j0, lv.d_row_items + 2 * j0, lv.d_sw_sub_off, lv.d_sw_tp_off, lv.d_tfac32,
+                                v.rloc, lv.d_scr_off, v.scr, lv.chl, h->st);
             });
             traced(h, "sub_finalize", lv.color_scr[c] * 4.0 + (double)(rm - r0) * 16.0, [&] {
                 launch_sub_finalize<float>(r0, rm, lv.d_pos_sub, lv.d_sw_sub_off, lv.d_scr_off, v.scr,
-                                           lv.d_sw_sub_dofs, x, true, lv.chl, lv.fl, h->st, true);
+                                           lv.d_sw_sub_dofs, x, true, lv.chl, lv.fl, h->st);
             });
         }
         if (ns > 0) {
@@ -1720,6 +1744,7 @@ bool pcg_run(lsdd_hierarchy* h) {
         if (h->tr.on) h->tr.flush();
         if (h->h_ic[2]) {
             breakdown = true;
+            h->breakdown_bits = h->h_ic[2];
             break;
         }
         if (h->h_ic[0] == 0) break;
@@ -2378,7 +2403,7 @@ lsdd_status lsdd_solve(lsdd_hierarchy* h, const double* b, double* x, int32_t nr
         allconv = allconv && f.converged;
     }
     if (info) std::copy(out.begin(), out.end(), info);
-    if (breakdown) throw Error(LSDD_E_BREAKDOWN, "PCG breakdown (p^T A p <= 0 or non-finite)");
+    if (breakdown) throw Error(LSDD_E_BREAKDOWN, "PCG breakdown: " + breakdown_cause(h->breakdown_bits));
     if (!allconv) {
         g_err = "PCG did not reach rtol within max_iter";
         return LSDD_E_NOCONV;
