@@ -4,7 +4,7 @@ Test infrastructure only: imported by the tests, by the smoke entry point and by
 the benchmark's CPU-baseline leg, never by the library or its Python binding.
 """
 from .lsdd import (  # noqa: F401
-    EPS, Hierarchy, Level, NotSPSD, Params, SolveInfo, assemble, closures, coloring,
+    EPS, Hierarchy, Level, NotSPSD, Params, SolveInfo, assemble, closures, coarse_gram_factors, coloring,
     element_gram_factor, hierarchy_stats, local_spectral, local_splitting, pcg,
     schur_pinv, select_modes, setup, standard_aggregation, stationary, structural_pattern,
     supernode_graph, vcycle,

@@ -606,6 +606,23 @@ def coarsen(lev: Level, params: Params, agg_of_dof=None):
     return coarse
 
 
+# ----------------------------------------------------------------- coarse Gram rows (Remark "coarse_gram")
+
+def coarse_gram_factors(lev: Level, rank_rtol: float = 0.0):
+    """Gram factors of the grouped coarse element blocks of a coarse level: the
+    rows G_g with G_g^T G_g = A_g for every coarse element g (elements of the finer
+    level summed over the set of aggregates they touch, reading R12), from the
+    pivoted Cholesky factorization of Sec. 5.2 truncated at n_g eps max diag.
+
+    Remark "finer-scale Grams induce coarser-scale Grams" (Sec. 5.1): a sum of SPSD
+    element blocks is SPSD and has a Gram factor, so the literal coarse factor
+    G_c = G P (one row per fine row) may be replaced by these re-factored rows,
+    which number rank(A_g) per group.  The coarse operator is unchanged up to the
+    truncation, A_c = sum_g R_g^T G_g^T G_g R_g.  The blocks are SPSD only up to
+    the rounding of the Galerkin products, so no SPSD test is applied."""
+    return [element_gram_factor_pchol(B, rank_rtol, np.inf) for B in lev.blocks]
+
+
 # ----------------------------------------------------------------- cycle and outer iteration
 
 def smooth(lev: Level, x: np.ndarray, r: np.ndarray, order) -> None:
