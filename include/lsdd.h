@@ -365,6 +365,25 @@ lsdd_status lsdd_export_level(const lsdd_hierarchy* h, int32_t level, int32_t* a
  * first r_T rows hold Lambda_+^{1/2} Q_+^T (remaining rows zero). */
 lsdd_status lsdd_export_gram(const lsdd_hierarchy* h, int32_t* ranks, double* G);
 
+/* Element Gram factors of level l (host outputs, any may be NULL).  Level 0: the
+ * factors lsdd_export_gram returns.  Level l >= 1: the elements are the coarse
+ * element groups (finer-level elements summed over the set of aggregates they
+ * touch), and the factors are Gram rows of their summed blocks A_g (Sec. 5.1,
+ * the remark that sums of element Grams are Grams of the coarser scale), from a
+ * diagonally pivoted Cholesky factorization of each block (Sec. 5.2; pivot = the
+ * largest remaining diagonal entry, lowest index among equal ones), truncated
+ * when that entry is at most n_g eps max diag(A_g).  They replace the rows G P
+ * (one per level-0 row) by rank(A_g) rows per group, and A_l = sum_g R_g^T
+ * G_g^T G_g R_g up to the truncation.  The first call on a coarse level factors
+ * its blocks on the device and keeps the result in the hierarchy.
+ *   elem_ptr int64[n_e + 1], elem_dofs int32[elem_ptr[n_e]] (level-l DOFs of every
+ *   element; n_e from lsdd_level_sizes); ranks int32[n_e]; G float64[sum n_g^2]
+ *   with G_g stored row-major as an n_g x n_g array whose first r_g rows hold the
+ *   factor rows (remaining rows zero).
+ * Errors: LSDD_E_INVAL for a NULL hierarchy or a level out of range; device errors. */
+lsdd_status lsdd_export_gram_level(lsdd_hierarchy* h, int32_t level, int64_t* elem_ptr, int32_t* elem_dofs,
+                                   int32_t* ranks, double* G);
+
 /* Library allocator hook (e.g. a framework's caching allocator).  alloc returns a
  * device pointer of at least `bytes` bytes on the current device or NULL; free
  * releases it.  NULL functions restore hipMalloc/hipFree.  Call before setup. */

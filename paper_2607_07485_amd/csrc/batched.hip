@@ -198,26 +198,31 @@ __global__ void __launch_bounds__(NT) k_potrf_update(double* base, const View* v
 
 // ---------------------------------------------------------------- pivoted Cholesky of a trailing block
 
-// Largest value over [j, n) of d (lowest index among equal values) by one
-// workgroup; red: 2 * NT / 64 LDS slots.
-__device__ inline void wg_argmax(const double* d, int j, int n, double* rv, int* ri, double& bv, int& bi) {
+// Largest value over [j, n) of d by one workgroup; among equal values the one
+// with the lowest key (key[i], or i without keys).  red: 2 * NT / 64 LDS slots.
+__device__ inline void wg_argmax(const double* d, const int32_t* key, int j, int n, double* rv, int* ri, double& bv,
+                                 int& bi) {
+    auto kf = [key](int i) { return key ? key[i] : i; };
+    auto better = [&](double xv, int xi, double yv, int yi) {   // (xv, xi) before (yv, yi)
+        return xi >= 0 && (yi < 0 || xv > yv || (xv == yv && kf(xi) < kf(yi)));
+    };
     bv = -INFINITY;
     bi = -1;
     for (int i = j + t_id(); i < n; i += NT) {
         const double x = d[i];
-        if (x > bv || (x == bv && bi >= 0 && i < bi)) { bv = x; bi = i; }
+        if (better(x, i, bv, bi)) { bv = x; bi = i; }
     }
     for (int off = 32; off > 0; off >>= 1) {
         const double ov = __shfl_xor(bv, off, 64);
         const int oi = __shfl_xor(bi, off, 64);
-        if (oi >= 0 && (ov > bv || (ov == bv && (bi < 0 || oi < bi)))) { bv = ov; bi = oi; }
+        if (better(ov, oi, bv, bi)) { bv = ov; bi = oi; }
     }
     if ((t_id() & 63) == 0) { rv[t_id() >> 6] = bv; ri[t_id() >> 6] = bi; }
     __syncthreads();
     bv = rv[0];
     bi = ri[0];
     for (int w = 1; w < NT / 64; ++w)
-        if (ri[w] >= 0 && (rv[w] > bv || (rv[w] == bv && (bi < 0 || ri[w] < bi)))) { bv = rv[w]; bi = ri[w]; }
+        if (better(rv[w], ri[w], bv, bi)) { bv = rv[w]; bi = ri[w]; }
     __syncthreads();
 }
 
@@ -231,9 +236,12 @@ __device__ inline void wg_argmax(const double* d, int j, int n, double* rv, int*
 // follow their indices.  The factorisation stops when the largest remaining
 // diagonal entry is at most tol[b]: rank[b] is then the number of eliminated
 // indices and done[b] is set.  diag: per-view scratch of the remaining diagonal.
+// perm (optional, at diag_off like diag): perm[i] is the trailing index whose
+// row and column sit at trailing position i; among equal diagonal entries the
+// pivot is then the lowest original index (without perm: the lowest position).
 __global__ void __launch_bounds__(NT) k_pstrf_panel(double* base, const View* views, const int32_t* lead, int kb,
                                                     const double* tol, const int64_t* diag_off, double* diag,
-                                                    int32_t* rank, int32_t* done) {
+                                                    int32_t* perm, int32_t* rank, int32_t* done) {
     __shared__ double rv[NT / 64];
     __shared__ int ri[NT / 64];
     if (done[blockIdx.y]) return;
@@ -250,12 +258,15 @@ __global__ void __launch_bounds__(NT) k_pstrf_panel(double* base, const View* vi
         return;
     }
     const int j1 = min(j0 + TB, ng);
+    int32_t* Pm = perm ? perm + diag_off[blockIdx.y] : nullptr;
     for (int i = j0 + t_id(); i < ng; i += NT) D[i] = M[(nw + i) + (int64_t)(nw + i) * ld];
+    if (Pm && kb == 0)
+        for (int i = t_id(); i < ng; i += NT) Pm[i] = i;
     __syncthreads();
     for (int j = j0; j < j1; ++j) {
         double bv;
         int bi;
-        wg_argmax(D, j, ng, rv, ri, bv, bi);
+        wg_argmax(D, Pm, j, ng, rv, ri, bv, bi);
         if (!(bv > tl)) {
             if (t_id() == 0) { rank[blockIdx.y] = j; done[blockIdx.y] = 1; }
             return;
@@ -275,6 +286,11 @@ __global__ void __launch_bounds__(NT) k_pstrf_panel(double* base, const View* vi
                     const double dd = D[j];
                     D[j] = D[bi];
                     D[bi] = dd;
+                    if (Pm) {
+                        const int32_t pp = Pm[j];
+                        Pm[j] = Pm[bi];
+                        Pm[bi] = pp;
+                    }
                 } else if (q < Q) {
                     const double a = M[q + (int64_t)J * ld];
                     M[q + (int64_t)J * ld] = M[Q + (int64_t)q * ld];
@@ -528,7 +544,7 @@ void Batched::potrf(double* base, const std::vector<View>& a, double* d_minpiv) 
 }
 
 void Batched::pstrf_trailing(double* base, const std::vector<View>& a, const std::vector<int32_t>& lead,
-                             const double* d_tol, std::vector<int32_t>& rank) {
+                             const double* d_tol, std::vector<int32_t>& rank, int32_t* d_perm) {
     rank.assign(a.size(), 0);
     if (a.empty()) return;
     const size_t nv = a.size();
@@ -557,7 +573,7 @@ void Batched::pstrf_trailing(double* base, const std::vector<View>& a, const std
     const int nt = (max_ng + TB - 1) / TB;
     for (int kb = 0; kb < nt; ++kb) {
         hipLaunchKernelGGL(k_pstrf_panel, dim3(1, nm), dim3(NT), 0, st, base, dv, d_lead, kb, d_tol, d_doff, d_diag,
-                           d_rank, d_done);
+                           d_perm, d_rank, d_done);
         const int64_t m = nt - kb - 1;
         if (m > 0)
             hipLaunchKernelGGL(k_potrf_update, dim3((unsigned)(m * (m + 1) / 2), nm), dim3(NT), 0, st, base, dg, kb,

@@ -43,9 +43,12 @@ struct Batched {
     // leading block stays where it is and the rows lead[b] .. lead[b]+rank-1 of
     // the coupling block are the pivot rows.  On return the first rank[b]
     // columns of the trailing block hold the factor (lower triangle).  Only the
-    // lower triangle of the view is read and kept consistent.
+    // lower triangle of the view is read and kept consistent.  d_perm (optional,
+    // device, sum of rows - lead entries in view order): the trailing index at each
+    // trailing position on return; with it, ties between equal diagonal entries go
+    // to the lowest original index.
     void pstrf_trailing(double* base, const std::vector<View>& a, const std::vector<int32_t>& lead,
-                        const double* d_tol, std::vector<int32_t>& rank);
+                        const double* d_tol, std::vector<int32_t>& rank, int32_t* d_perm = nullptr);
     // B <- L^{-1} B (trans = false) or B <- L^{-T} B (trans = true) with L the
     // lower triangle of the square view l[b] and B the view b[b] (rows = n).
     // lower_b (forward only): B is lower triangular (e.g. the identity), so

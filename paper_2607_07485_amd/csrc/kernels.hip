@@ -323,6 +323,27 @@ __global__ void k_scale_blocks(int64_t n_elem, const int64_t* blk_off, const dou
     }
 }
 
+// Gram rows from diagonally pivoted Cholesky factors (Sec. 5.2).  Element e
+// (n x n at blk_off[e]) holds in L the factor in pivot order (column-major, lower
+// triangle: L(i, k) at i + k n), perm[i] (at perm_off[e] - perm_off[0]) is the
+// index at pivot position i and rank[e] the number of pivots r.  Writes G_e
+// row-major n x n with G_e(k, perm[i]) = L(i, k) for k < r, i >= k, zero
+// elsewhere, so that G_e^T G_e = A_e up to the truncated remainder.
+__global__ void k_gram_rows(int64_t n_elem, const int64_t* perm_off, const int64_t* blk_off, const double* L,
+                            const int32_t* perm, const int32_t* rank, double* G) {
+    for (int64_t e = blockIdx.x; e < n_elem; e += gridDim.x) {
+        const int n = (int)(perm_off[e + 1] - perm_off[e]);
+        const int r = rank[e];
+        const double* l = L + blk_off[e];
+        const int32_t* pm = perm + (perm_off[e] - perm_off[0]);
+        double* g = G + blk_off[e];
+        for (int idx = tid(); idx < n * n; idx += WG) {
+            const int k = idx / n, i = idx % n;
+            g[(int64_t)k * n + pm[i]] = (k < r && i >= k) ? l[i + (int64_t)k * n] : 0.0;
+        }
+    }
+}
+
 // out[e] = u_e^T B_e v_e (B_e row-major n_e x n_e at blk_off[e]); one wave per
 // element: lane j sums u_i B_ij v_j over the rows i (coalesced row reads), then
 // a fixed-order wave reduction.
@@ -1161,6 +1182,13 @@ void launch_scale_blocks(int64_t n_elem, const int64_t* blk_off, const double* s
     if (n_elem <= 0) return;
     hipLaunchKernelGGL(k_scale_blocks, dim3((unsigned)std::min<int64_t>(n_elem, 65535 * 16)), dim3(WG), 0, st, n_elem,
                        blk_off, scale, blocks);
+}
+
+void launch_gram_rows(int64_t n_elem, const int64_t* perm_off, const int64_t* blk_off, const double* L,
+                      const int32_t* perm, const int32_t* rank, double* G, hipStream_t st) {
+    if (n_elem <= 0) return;
+    hipLaunchKernelGGL(k_gram_rows, dim3((unsigned)std::min<int64_t>(n_elem, 65535 * 16)), dim3(WG), 0, st, n_elem,
+                       perm_off, blk_off, L, perm, rank, G);
 }
 
 void launch_elem_bilinear(int64_t n_elem, const int64_t* elem_ptr, const int32_t* elem_dofs, const int64_t* blk_off,

@@ -89,6 +89,11 @@ void launch_assemble_rows(int64_t n, const int64_t* d2e_ptr, const int32_t* d2e_
                           double* val, hipStream_t st, bool wave_rows = false);
 // factor[e] = theta[e] / theta0[e] (theta0 NULL: theta[e])
 void launch_theta_factor(int64_t n, const double* theta, const double* theta0, double* factor, hipStream_t st);
+// Gram rows G_e (row-major n_e x n_e at blk_off[e]) from pivoted Cholesky factors
+// in pivot order: G_e(k, perm[i]) = L_e(i, k) for k < rank[e], zero elsewhere.
+// perm_off: elem_ptr of the elements (perm of element e at perm_off[e] - perm_off[0]).
+void launch_gram_rows(int64_t n_elem, const int64_t* perm_off, const int64_t* blk_off, const double* L,
+                      const int32_t* perm, const int32_t* rank, double* G, hipStream_t st);
 // blocks of element e *= scale[e]
 void launch_scale_blocks(int64_t n_elem, const int64_t* blk_off, const double* scale, double* blocks, hipStream_t st);
 // out[e] = scale * sum_k u_{k,e}^T B_e v_{k,e} over nrhs vectors at stride ld

@@ -2698,6 +2698,79 @@ lsdd_status lsdd_export_level(const lsdd_hierarchy* h, int32_t level, int32_t* a
     ABI_END
 }
 
+namespace lsdd {
+// Gram factors of the grouped element blocks of a coarse level (Sec. 5.1: a sum
+// of SPSD element blocks is SPSD and so has a Gram factor of its own, which may
+// replace the rows G P inherited from the finer level; factorisation of
+// Sec. 5.2).  Every block is factored with diagonal pivoting (largest remaining
+// diagonal entry, lowest index among equal ones), truncated when that entry is
+// at most n_g eps max diag; the rows come out in the original index order.  The
+// blocks are SPSD only up to the rounding of the Galerkin products, so no SPSD
+// test is applied.  Runs once per level, on the first request.
+void coarse_gram(lsdd_hierarchy* h, Level& lv) {
+    Arena& ar = h->arena;
+    hipStream_t st = h->st;
+    const int64_t ne = lv.el.count();
+    const int64_t tot = lv.blk_off[ne];
+    constexpr int64_t CH = 65535;                       // views per batched launch
+    double* W = ar.alloc<double>(std::max<int64_t>(tot, 1));
+    int32_t* d_perm = ar.alloc<int32_t>(std::max<int64_t>(lv.el.ptr[ne], 1));
+    int32_t* d_rank = ar.alloc<int32_t>(std::max<int64_t>(ne, 1));
+    double* d_maxd = ar.alloc<double>(CH);
+    double* d_tol = ar.alloc<double>(CH);
+    double* G = ar.alloc<double>(std::max<int64_t>(tot, 1));
+    if (tot) HIPCHK(hipMemcpyAsync(W, lv.d_blocks, tot * sizeof(double), hipMemcpyDeviceToDevice, st));
+    Batched bt;
+    bt.st = st;
+    bt.alloc = [](void* c, size_t b) { return static_cast<Arena*>(c)->get(b); };
+    bt.release = [](void* c, void* p) { static_cast<Arena*>(c)->release(p); };
+    bt.ctx = &ar;
+    std::vector<int32_t> ranks(ne, 0);
+    for (int64_t e0 = 0; e0 < ne; e0 += CH) {
+        const int64_t cnt = std::min(CH, ne - e0);
+        std::vector<View> v(cnt);
+        std::vector<int32_t> lead(cnt, 0), rank;
+        for (int64_t i = 0; i < cnt; ++i) {
+            const int32_t n = (int32_t)(lv.el.ptr[e0 + i + 1] - lv.el.ptr[e0 + i]);
+            v[i] = View{lv.blk_off[e0 + i], n, n, n, 0};
+        }
+        launch_views_max_diag((int32_t)cnt, W, bt.put(0, v), d_maxd, st);
+        std::vector<double> maxd = download(d_maxd, cnt, st), tol(cnt);
+        for (int64_t i = 0; i < cnt; ++i) tol[i] = v[i].rows * DBL_EPSILON * std::max(maxd[i], 0.0);
+        HIPCHK(hipMemcpyAsync(d_tol, tol.data(), cnt * sizeof(double), hipMemcpyHostToDevice, st));
+        bt.pstrf_trailing(W, v, lead, d_tol, rank, d_perm + lv.el.ptr[e0]);      // synchronises
+        std::copy(rank.begin(), rank.end(), ranks.begin() + e0);
+        HIPCHK(hipMemcpyAsync(d_rank + e0, rank.data(), cnt * sizeof(int32_t), hipMemcpyHostToDevice, st));
+        launch_gram_rows(cnt, lv.d_elem_ptr + e0, lv.d_blk_off + e0, W, d_perm + lv.el.ptr[e0], d_rank + e0, G, st);
+        HIPCHK(hipGetLastError());
+        sync(st);
+    }
+    bt.free_all();
+    for (void* p : {(void*)W, (void*)d_perm, (void*)d_rank, (void*)d_maxd, (void*)d_tol}) ar.release(p);
+    lv.d_G = G;
+    lv.ranks = std::move(ranks);
+}
+}  // namespace lsdd
+
+lsdd_status lsdd_export_gram_level(lsdd_hierarchy* h, int32_t level, int64_t* elem_ptr, int32_t* elem_dofs,
+                                   int32_t* ranks, double* G) {
+    ABI_BEGIN
+    if (!h || level < 0 || level >= (int32_t)h->L.size()) throw Error(LSDD_E_INVAL, "bad argument");
+    Level& lv = *h->L[level];
+    if (elem_ptr) std::copy(lv.el.ptr.begin(), lv.el.ptr.end(), elem_ptr);
+    if (elem_dofs) std::copy(lv.el.dofs.begin(), lv.el.dofs.end(), elem_dofs);
+    if (ranks || G) {
+        if (!lv.d_G) coarse_gram(h, lv);
+        if (ranks) std::copy(lv.ranks.begin(), lv.ranks.end(), ranks);
+        if (G) {
+            HIPCHK(hipMemcpyAsync(G, lv.d_G, lv.blk_off.back() * sizeof(double), hipMemcpyDeviceToHost, h->st));
+            sync(h->st);
+        }
+    }
+    return LSDD_OK;
+    ABI_END
+}
+
 lsdd_status lsdd_export_gram(const lsdd_hierarchy* h, int32_t* ranks, double* G) {
     ABI_BEGIN
     if (!h) throw Error(LSDD_E_INVAL, "NULL hierarchy");

@@ -77,6 +77,7 @@ def lib():
         L.lsdd_level_sizes.argtypes = [_P, C.c_int32, i64p]
         L.lsdd_export_level.argtypes = [_P, C.c_int32, i32p, i32p, f64p, f64p, i32p, i64p, i32p, f64p, i32p]
         L.lsdd_export_gram.argtypes = [_P, i32p, f64p]
+        L.lsdd_export_gram_level.argtypes = [_P, C.c_int32, i64p, i32p, i32p, f64p]
         L.lsdd_destroy.argtypes = [_P]
         L.lsdd_set_cycle_precision.argtypes = [_P, C.c_int32]
         L.lsdd_trace.argtypes = [_P, C.c_int32]
@@ -107,7 +108,7 @@ def lib():
                      "lsdd_set_solve_params", "lsdd_set_graph", "lsdd_segments", "lsdd_setup_batched",
                      "lsdd_level_segments", "lsdd_autotune", "lsdd_level_tuning", "lsdd_setup_elements_scaled",
                      "lsdd_update_theta", "lsdd_elem_bilinear", "lsdd_elem_bilinear_noalloc",
-                     "lsdd_solve_batched"):
+                     "lsdd_solve_batched", "lsdd_export_gram_level"):
             getattr(L, name).restype = C.c_int
         _LIB = L
     return _LIB
@@ -415,6 +416,23 @@ class Hierarchy:
         G = np.zeros(int(np.sum(sizes * sizes)), np.float64)
         _check(lib().lsdd_export_gram(self._h, _ptr(ranks, C.c_int32), _ptr(G, C.c_double)))
         return ranks, G
+
+    def export_gram_level(self, level, rows=True):
+        """Element Gram factors of a level (level 0: as export_gram; coarse levels:
+        re-factored rows of the grouped element blocks).  Returns a dict with
+        elem_ptr, elem_dofs, ranks and G (each G_g row-major n_g x n_g, first
+        ranks[g] rows the factor; None with rows=False)."""
+        s = np.zeros(8, np.int64)
+        _check(lib().lsdd_level_sizes(self._h, int(level), _ptr(s, C.c_int64)))
+        ptr = np.zeros(int(s[7]) + 1, np.int64)
+        _check(lib().lsdd_export_gram_level(self._h, int(level), _ptr(ptr, C.c_int64), None, None, None))
+        sizes = np.diff(ptr)
+        dofs = np.zeros(int(ptr[-1]), np.int32)
+        ranks = np.zeros(len(sizes), np.int32)
+        G = np.zeros(int(np.sum(sizes * sizes)), np.float64) if rows else None
+        _check(lib().lsdd_export_gram_level(self._h, int(level), None, _ptr(dofs, C.c_int32),
+                                            _ptr(ranks, C.c_int32), _ptr(G, C.c_double)))
+        return dict(elem_ptr=ptr, elem_dofs=dofs, ranks=ranks, G=G)
 
     def close(self):
         if self._h is not None and self._h.value:
