@@ -235,6 +235,8 @@ def run_batch(a, torch, P, fegen, dev):
         return
     h.set_cycle_precision(1 if "fp32" in ok else 0)
     kernels, (dname, d) = _trace_dominant(h, torch, lambda: h.solve(B, allow_noconv=True))
+    if ok and not a.no_galerkin32:
+        res["fp32_galerkin32"] = _batch_galerkin32(a, torch, P, probs, B, X_ref, h.segments()[1], n_tot * nrhs)
     h.close()
     best = max(ok, key=lambda k: res[k]["value"])
     achieved = d["bytes"] / (d["ms"] * 1e-3) / 1e9
@@ -249,6 +251,42 @@ def run_batch(a, torch, P, fegen, dev):
                         "avg_launch_us": d["ms"] * 1e3 / max(d["launches"], 1)},
            "kernels": kernels, "cpu_baseline": None}
     print(json.dumps(out))
+
+
+def _batch_galerkin32(a, torch, P, probs, B, X_ref, seg, n_work):
+    """The batch again with its Galerkin products on the FP32 matrix cores (operands rounded
+    to FP32, FP32 accumulation) and the FP32 cycle: setup time, solve rate, iterations and
+    the A-norm error against the FP64 hierarchy's reference solution (same A_0)."""
+    prm = _params(P, max_levels=a.max_levels or 3, rtol=2.5e-9, galerkin_precision=1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    try:
+        g = P.Hierarchy.setup_batched(probs, prm)
+    except P.LsddError as ex:
+        return {"setup_error": str(ex)}
+    torch.cuda.synchronize()
+    out = {"setup_s": time.perf_counter() - t0}
+    g.set_cycle_precision(1)
+    g.set_graph(False)
+    g.autotune(block=True)
+    g.set_graph(True)
+    X, infs = g.solve(B, allow_noconv=True)
+    if all(f.converged for f in infs):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(a.steps):
+            X, infs = g.solve(B)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / a.steps
+        its = [f.iters for f in infs]
+        g.set_graph(False)
+        out.update(value=n_work / dt, ms_per_step=dt * 1e3, iters_min=min(its), iters_max=max(its), converged=True,
+                   anorm_err_max=_anorm_err_max(g, X, X_ref, seg))
+    else:
+        out.update(converged=False, not_converged_pairs=sum(1 for f in infs if not f.converged))
+    g.close()
+    print(f"[bench] batch with FP32 Galerkin products: {out}", file=sys.stderr, flush=True)
+    return out
 
 
 def run_h2(a, torch, P, fegen, dev):
@@ -473,6 +511,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch-leg", action="store_true",
                     help="skip the FP32/FP64 legs on the 64-instance Q1 batch in the default line")
+    ap.add_argument("--no-galerkin32", action="store_true",
+                    help="skip the hierarchies with FP32 matrix-core Galerkin products")
     ap.add_argument("--workload", choices=["graddiv", "batch", "q2grad", "h2", "closure_table"], default="graddiv")
     ap.add_argument("--smoother", choices=list(SMOOTHERS), default="ms",
                     help="block Schwarz smoother: multiplicative (default), restricted additive, block Jacobi")
@@ -530,8 +570,13 @@ def _batch_legs(a, torch, P, fegen, dev):
     n_tot, nrhs = B_np.shape[1], B_np.shape[0]
     B = torch.from_numpy(B_np).to(dev)
     rtol = 2.5e-9
+    P.Hierarchy.setup_batched([fegen.elasticity_q1(4)], _params(P, max_levels=3, rtol=rtol)).close()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
     h = P.Hierarchy.setup_batched(probs, _params(P, max_levels=3, rtol=rtol))
-    out = {"workload": f"elasticity_q1_batch64_{nrhs}rhs", "n_dofs": n_tot, "rtol": rtol}
+    torch.cuda.synchronize()
+    out = {"workload": f"elasticity_q1_batch64_{nrhs}rhs", "n_dofs": n_tot, "rtol": rtol,
+           "setup_s": time.perf_counter() - t0}
     sols = {}
     for name, prec in (("fp64", 0), ("fp32", 1)):
         h.set_cycle_precision(prec)
@@ -555,6 +600,8 @@ def _batch_legs(a, torch, P, fegen, dev):
     for name in ("fp64", "fp32"):
         out[name]["anorm_err_max"] = _anorm_err_max(h, sols[name], X_ref, seg)
     out["fp32_vs_fp64"] = out["fp32"]["value"] / out["fp64"]["value"]
+    if not a.no_galerkin32:
+        out["fp32_galerkin32"] = _batch_galerkin32(a, torch, P, probs, B, X_ref, seg, n_tot * nrhs)
     h.close()
     return out
 
@@ -668,6 +715,24 @@ def run_graddiv(a, torch, P, fegen, dev):
     cycle_gbs = solve_bytes / dt / 1e9
     h.close()
 
+    g32 = None
+    if not a.no_galerkin32:
+        # the same hierarchy with its Galerkin products on the FP32 matrix cores: the coarse
+        # operators lose the mass term (about 1e-8 of the div term) to FP32 cancellation
+        try:
+            t0 = time.perf_counter()
+            g = P.Hierarchy.setup_problem(prob, _params(P, max_levels=a.max_levels or 3, precision=2,
+                                                        galerkin_precision=1))
+            g32 = {"setup_s": time.perf_counter() - t0}
+            g.set_cycle_precision(0)
+            x, inf = g.solve(b, allow_noconv=True)
+            g32.update(converged=bool(inf[0].converged), iters=inf[0].iters,
+                       anorm_err=_anorm_rel(A0, x.cpu().numpy(), x_true))
+            g.close()
+        except P.LsddError as ex:
+            g32 = {"setup_error": str(ex)}
+        print(f"[bench] FP32 Galerkin products: {g32}", file=sys.stderr, flush=True)
+
     batch = None
     if not a.no_batch_leg:
         batch = _batch_legs(a, torch, P, fegen, dev)
@@ -705,6 +770,7 @@ def run_graddiv(a, torch, P, fegen, dev):
                            "frac": cycle_gbs / HBM_PEAK_GBS, "bytes_per_solve": solve_bytes,
                            "what": "sum of the algorithmic bytes of every launch of one solve / solve time"},
         "kernels": kernels,
+        "galerkin32": g32,
         "batch": batch,
         "cpu_baseline": None if cb is None else {k: cb[k] for k in ("value", "unit", "cores", "kind", "sample")},
     }

@@ -86,7 +86,12 @@ typedef struct {
                                    LSDD_E_NOT_SPSD).  Under full-support rows the hierarchy
                                    does not depend on the choice (Galerkin products up to
                                    rounding)                                                */
-    int32_t reserved1;          /* ignored                                                    */
+    int32_t galerkin_precision; /* Galerkin products G_T P_T and A_g = Y^T Y of levels >= 1
+                                   (Sec. 2, Galerkin Gram recursion): 0 = FP64 matrix cores
+                                   (default); 1 = FP32 matrix cores, operands rounded to FP32,
+                                   FP32 accumulation (the coarse operators then carry FP32
+                                   rounding; local spectral problems, coarsest factorisation
+                                   and PCG stay FP64)                                        */
     double tau_const;           /* tau_cut = tau_const * max mult; default 0.75               */
     double max_density;         /* nnz(A_l)/n_l^2 above this -> coarsest; default 0.25         */
     double rtol;                /* PCG stop: ||r||_2 <= rtol ||b||_2; default 1e-8              */

@@ -13,6 +13,7 @@
 #include <cmath>
 #include <stdexcept>
 #include <string>
+#include <type_traits>
 
 #include "batched.hpp"
 #include "mgemm.hpp"
@@ -411,10 +412,11 @@ __global__ void __launch_bounds__(NT) k_trsm_update(const double* lbase, const V
 
 // ---------------------------------------------------------------- C = beta C_in - alpha A^T B
 
+template <bool F32>
 __global__ void __launch_bounds__(NT) k_gemm_tn(const double* abase, const View* av, const double* bbase,
                                                 const View* bv, const double* cinbase, const View* civ, double beta,
                                                 double* coutbase, const View* cov, double alpha, int tri_k, int sym) {
-    __shared__ mg::Smem sm;
+    __shared__ typename std::conditional<F32, mg::Smem32, mg::Smem>::type sm;
     const View a = av[blockIdx.y], b = bv[blockIdx.y], co = cov[blockIdx.y];
     const int mt = ntiles(co.rows), ntt = ntiles(co.cols);
     int it, jt;
@@ -430,25 +432,40 @@ __global__ void __launch_bounds__(NT) k_gemm_tn(const double* abase, const View*
         jt = job / mt;
     }
     const int kbeg = tri_k ? max(it, jt) * TB : 0;
-    mg::d4 acc[2][2];
-    mg::zero(acc);
-    mg::tile_mma<mg::KMAJ, mg::KMAJ>(sm, abase + a.off, a.ld, it * TB, a.cols, bbase + b.off, b.ld, jt * TB, b.cols,
-                                     kbeg, a.rows, acc);
     const View ci = civ[blockIdx.y];
+    auto put = [&](int r, int c, double s) {
+        if (r < co.rows && c < co.cols) {
+            double x = -alpha * s;
+            if (beta != 0.0) x += beta * cinbase[ci.off + r + (int64_t)c * ci.ld];
+            coutbase[co.off + r + (int64_t)c * co.ld] = x;
+            if (sym && it != jt) coutbase[co.off + c + (int64_t)r * co.ld] = x;
+        }
+    };
+    if constexpr (F32) {
+        mg::f4 acc[2][2];
+        mg::zero32(acc);
+        mg::tile_mma32<mg::KMAJ, mg::KMAJ>(sm, abase + a.off, a.ld, it * TB, a.cols, bbase + b.off, b.ld, jt * TB,
+                                           b.cols, kbeg, a.rows, acc);
 #pragma unroll
-    for (int p = 0; p < 2; ++p)
+        for (int p = 0; p < 2; ++p)
 #pragma unroll
-        for (int q = 0; q < 2; ++q)
+            for (int q = 0; q < 2; ++q)
 #pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const int r = it * TB + mg::acc_row(p, e), c = jt * TB + mg::acc_col(q);
-                if (r < co.rows && c < co.cols) {
-                    double x = -alpha * acc[p][q][e];
-                    if (beta != 0.0) x += beta * cinbase[ci.off + r + (int64_t)c * ci.ld];
-                    coutbase[co.off + r + (int64_t)c * co.ld] = x;
-                    if (sym && it != jt) coutbase[co.off + c + (int64_t)r * co.ld] = x;
-                }
-            }
+                for (int e = 0; e < 4; ++e)
+                    put(it * TB + mg::acc_row32(p, e), jt * TB + mg::acc_col(q), (double)acc[p][q][e]);
+    } else {
+        mg::d4 acc[2][2];
+        mg::zero(acc);
+        mg::tile_mma<mg::KMAJ, mg::KMAJ>(sm, abase + a.off, a.ld, it * TB, a.cols, bbase + b.off, b.ld, jt * TB,
+                                         b.cols, kbeg, a.rows, acc);
+#pragma unroll
+        for (int p = 0; p < 2; ++p)
+#pragma unroll
+            for (int q = 0; q < 2; ++q)
+#pragma unroll
+                for (int e = 0; e < 4; ++e)
+                    put(it * TB + mg::acc_row(p, e), jt * TB + mg::acc_col(q), acc[p][q][e]);
+    }
 }
 
 // ---------------------------------------------------------------- transpose
@@ -631,7 +648,7 @@ void Batched::trsm(const double* lbase, const std::vector<View>& l, double* bbas
 
 void Batched::gemm_tn(const double* abase, const std::vector<View>& a, const double* bbase, const std::vector<View>& b,
                       const double* cinbase, const std::vector<View>& cin, double beta, double* coutbase,
-                      const std::vector<View>& cout, double alpha, bool tri_k, bool sym) {
+                      const std::vector<View>& cout, double alpha, bool tri_k, bool sym, bool f32) {
     if (a.empty()) return;
     if (sym && beta != 0.0) throw std::runtime_error("batched gemm_tn: sym needs beta = 0");
     View* d1 = put(0, a);
@@ -646,8 +663,12 @@ void Batched::gemm_tn(const double* abase, const std::vector<View>& a, const dou
     }
     if (mt == 0) return;
     if (mt > INT32_MAX) throw std::runtime_error("batched gemm_tn: too many tiles");
-    hipLaunchKernelGGL(k_gemm_tn, dim3((unsigned)mt, nm), dim3(NT), 0, st, abase, d1, bbase, d2, cinbase, d4, beta,
-                       coutbase, d3, alpha, tri_k ? 1 : 0, sym ? 1 : 0);
+    if (f32)
+        hipLaunchKernelGGL(k_gemm_tn<true>, dim3((unsigned)mt, nm), dim3(NT), 0, st, abase, d1, bbase, d2, cinbase, d4,
+                           beta, coutbase, d3, alpha, tri_k ? 1 : 0, sym ? 1 : 0);
+    else
+        hipLaunchKernelGGL(k_gemm_tn<false>, dim3((unsigned)mt, nm), dim3(NT), 0, st, abase, d1, bbase, d2, cinbase,
+                           d4, beta, coutbase, d3, alpha, tri_k ? 1 : 0, sym ? 1 : 0);
     chk(hipGetLastError(), "batched gemm_tn");
 }
 

@@ -59,10 +59,12 @@ struct Batched {
     // C: M x N).  beta = 0 ignores C_in.  tri_k: A and B are lower triangular,
     // so the K loop of output tile (i, j) starts at tile max(i, j).  sym: the
     // result is symmetric (A = B, beta = 0): only lower tiles are computed and
-    // each is also stored mirrored.
+    // each is also stored mirrored.  f32: the product runs on the FP32 matrix
+    // cores (operands rounded to FP32, FP32 accumulation), C stays FP64.
     void gemm_tn(const double* abase, const std::vector<View>& a, const double* bbase, const std::vector<View>& b,
                  const double* cinbase, const std::vector<View>& cin, double beta, double* coutbase,
-                 const std::vector<View>& cout, double alpha, bool tri_k = false, bool sym = false);
+                 const std::vector<View>& cout, double alpha, bool tri_k = false, bool sym = false,
+                 bool f32 = false);
     // In-place transpose of square views.
     void transpose(double* base, const std::vector<View>& a);
 };

@@ -1234,6 +1234,7 @@ std::unique_ptr<Level> coarsen(lsdd_hierarchy* h, Level& lv, const int32_t* agg_
         // stacked interpolation rows P_g per group, Y_e = F_e P_e per member,
         // then A_g = Y^T Y (Gram factors) or P_g^T Y, both on the matrix cores
         const bool gram = lv.level == 0;
+        const bool g32 = h->prm.galerkin_precision == 1;
         const double* fb = gram ? lv.d_G : lv.d_blocks;
         std::vector<int64_t> R(ng, 0);
         for (int64_t g = 0; g < ng; ++g)
@@ -1281,7 +1282,7 @@ std::unique_ptr<Level> coarsen(lsdd_hierarchy* h, Level& lv, const int32_t* agg_
             std::vector<View> va, vb;
             auto flush_members = [&]() {
                 if (va.empty()) return;
-                bt.gemm_tn(fb, va, pst, vb, nullptr, vb, 0.0, y, vb, -1.0);
+                bt.gemm_tn(fb, va, pst, vb, nullptr, vb, 0.0, y, vb, -1.0, false, false, g32);
                 va.clear();
                 vb.clear();
             };
@@ -1301,7 +1302,7 @@ std::unique_ptr<Level> coarsen(lsdd_hierarchy* h, Level& lv, const int32_t* agg_
             std::vector<View> wa, wc;
             auto flush_groups = [&]() {
                 if (wa.empty()) return;
-                bt.gemm_tn(gram ? y : pst, wa, y, wa, nullptr, wc, 0.0, cv->d_blocks, wc, -1.0, false, true);
+                bt.gemm_tn(gram ? y : pst, wa, y, wa, nullptr, wc, 0.0, cv->d_blocks, wc, -1.0, false, true, g32);
                 wa.clear();
                 wc.clear();
             };
@@ -1894,7 +1895,7 @@ lsdd_hierarchy* build(ElemList el0, const double* blocks, bool blocks_on_device,
     const lsdd_params& P = h->prm;
     if (P.max_levels < 1 || P.precision < 0 || P.precision > 2 || P.tau_const <= 0 || P.rtol <= 0 || P.max_iter < 1 ||
         P.closure < 0 || P.closure > 1 || !(P.closure_tol >= 0) || P.smoother < 0 || P.smoother > 2 ||
-        P.elem_factor < 0 || P.elem_factor > 1)
+        P.elem_factor < 0 || P.elem_factor > 1 || P.galerkin_precision < 0 || P.galerkin_precision > 1)
         throw Error(LSDD_E_INVAL, "invalid parameters");
     h->st = (hipStream_t)stream;
     double t0 = now_s();

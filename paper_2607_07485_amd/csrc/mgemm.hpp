@@ -1,4 +1,5 @@
-// FP64 matrix-core tile contraction for gfx950 (v_mfma_f64_16x16x4f64).
+// FP64 matrix-core tile contraction for gfx950 (v_mfma_f64_16x16x4f64), and an
+// FP32 variant (v_mfma_f32_16x16x4f32) at the end.
 //
 // One workgroup of 256 threads (4 waves) accumulates a 64 x 64 output tile
 //     acc[i][j] = sum_k a(k, i) * b(k, j),   i in [m0, m0+64), j in [n0, n0+64)
@@ -125,6 +126,76 @@ __device__ inline int acc_row(int p, int v) {
 __device__ inline int acc_col(int q) {
     const int w = (int)threadIdx.x >> 6, l = (int)threadIdx.x & 63;
     return (w >> 1) * 32 + 16 * q + (l & 15);
+}
+
+// ---------------------------------------------------------------- FP32 variant
+// The same 64 x 64 tile contraction on v_mfma_f32_16x16x4f32: the FP64
+// operands are rounded to FP32 as they are staged in LDS and the products are
+// accumulated in FP32.  The FP32 instruction takes its operands like the FP64
+// one (lane l: A[l % 16][l / 16], B[l / 16][l % 16]) but returns register v of
+// lane l as D[4 (l / 16) + v][l % 16] (acc_row32).
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+constexpr int LS32 = KC + 1;  // LDS row stride in floats
+
+struct Smem32 {
+    float a[T][LS32];
+    float b[T][LS32];
+};
+
+template <int LAY>
+__device__ inline void stash32(float (*s)[LS32], const double (&r)[8]) {
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        int i, k;
+        chunk_idx<LAY>(q, i, k);
+        s[i][k] = (float)r[q];
+    }
+}
+
+__device__ inline void zero32(f4 (&acc)[2][2]) {
+#pragma unroll
+    for (int p = 0; p < 2; ++p)
+#pragma unroll
+        for (int q = 0; q < 2; ++q) acc[p][q] = f4{0.0f, 0.0f, 0.0f, 0.0f};
+}
+
+template <int LA, int LB>
+__device__ inline void tile_mma32(Smem32& sm, const double* __restrict__ a, int64_t lda, int m0, int M,
+                                  const double* __restrict__ b, int64_t ldb, int n0, int N, int kbeg, int kend,
+                                  f4 (&acc)[2][2]) {
+    if (kbeg >= kend) return;
+    const int w = (int)threadIdx.x >> 6, l = (int)threadIdx.x & 63;
+    const int wr = (w & 1) * 32, wc = (w >> 1) * 32;
+    const int lm = l & 15, lk = l >> 4;
+    double ra[8], rb[8];
+    fetch<LA>(a, lda, m0, M, kbeg, kend, ra);
+    fetch<LB>(b, ldb, n0, N, kbeg, kend, rb);
+    for (int k0 = kbeg; k0 < kend; k0 += KC) {
+        __syncthreads();
+        stash32<LA>(sm.a, ra);
+        stash32<LB>(sm.b, rb);
+        __syncthreads();
+        if (k0 + KC < kend) {
+            fetch<LA>(a, lda, m0, M, k0 + KC, kend, ra);
+            fetch<LB>(b, ldb, n0, N, k0 + KC, kend, rb);
+        }
+#pragma unroll
+        for (int kk = 0; kk < KC; kk += 4) {
+            const float a0 = sm.a[wr + lm][kk + lk], a1 = sm.a[wr + 16 + lm][kk + lk];
+            const float b0 = sm.b[wc + lm][kk + lk], b1 = sm.b[wc + 16 + lm][kk + lk];
+            acc[0][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b0, acc[0][0], 0, 0, 0);
+            acc[0][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b1, acc[0][1], 0, 0, 0);
+            acc[1][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b0, acc[1][0], 0, 0, 0);
+            acc[1][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b1, acc[1][1], 0, 0, 0);
+        }
+    }
+}
+
+__device__ inline int acc_row32(int p, int v) {
+    const int w = (int)threadIdx.x >> 6, l = (int)threadIdx.x & 63;
+    return (w & 1) * 32 + 16 * p + 4 * (l >> 4) + v;
 }
 
 }  // namespace mg

@@ -30,7 +30,7 @@ class Params(C.Structure):
                 ("modes_fixed", C.c_int32), ("min_coarse", C.c_int32), ("max_iter", C.c_int32),
                 ("precision", C.c_int32), ("blocked_eig_min", C.c_int32),
                 ("closure", C.c_int32), ("smoother", C.c_int32),
-                ("elem_factor", C.c_int32), ("reserved1", C.c_int32),
+                ("elem_factor", C.c_int32), ("galerkin_precision", C.c_int32),
                 ("tau_const", C.c_double), ("max_density", C.c_double), ("rtol", C.c_double),
                 ("cluster_tol", C.c_double), ("band_tol", C.c_double), ("rank_rtol", C.c_double),
                 ("spsd_tol", C.c_double), ("closure_tol", C.c_double)]
