@@ -687,6 +687,7 @@ def run_graddiv(a, torch, P, fegen, dev):
         if name == best:
             continue
         h.set_cycle_precision({"fp64": 0, "fp32": 1, "mixed": 2}[name])
+        h.set_tuning(tunings[name])          # the launch shapes this leg was timed with
         h.trace(True)
         h.solve(b)
         h.trace(False)
@@ -698,6 +699,7 @@ def run_graddiv(a, torch, P, fegen, dev):
                                         "bytes_per_solve": lb}
         print(f"[bench] {name} kernels {json.dumps(legs[name]['kernels'])}", file=sys.stderr, flush=True)
     h.set_cycle_precision(prec)
+    h.set_tuning(tunings[best])
     # live per-kernel timing of one more solve of the reported variant (HIP events on the solve stream)
     h.trace(True)
     h.solve(b)

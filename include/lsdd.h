@@ -321,6 +321,14 @@ lsdd_status lsdd_autotune(lsdd_hierarchy* h, int32_t block, void* hip_stream);
  * for blocks, tiles per work item, finalize threads per DOF. */
 lsdd_status lsdd_level_tuning(const lsdd_hierarchy* h, int32_t level, int32_t* out);
 
+/* Set the launch shapes of level l (host int32[4], the layout of lsdd_level_tuning),
+ * e.g. to restore what lsdd_autotune chose for another cycle precision.  Every value
+ * must be one of the autotuner's candidates (else LSDD_E_INVAL, nothing changed);
+ * tiles per work item is ignored on the coarsest level.  Captured PCG graphs are
+ * dropped and recaptured on the next solve.  Like lsdd_autotune, it changes only the
+ * summation order of the sums involved. */
+lsdd_status lsdd_set_level_tuning(lsdd_hierarchy* h, int32_t level, const int32_t* in);
+
 /* Per-kernel timing: on != 0 clears the counters and records a pair of HIP
  * events on the solve stream around every launch of the traced kernel classes
  * (csr_resid_rows, sub_symv, sub_finalize, small_sub, csr_spmv, restrict,

@@ -27,6 +27,7 @@ constexpr int OB = 4;        // tiles per panel of the delayed trailing updates 
 constexpr int TT = 32;       // tile edge of the transpose
 constexpr int NT = 256;
 
+constexpr int NTP = 1024;   // threads of the pivoted-Cholesky panel kernel (one workgroup per matrix)
 __device__ inline int t_id() { return (int)threadIdx.x; }
 __device__ inline double wave_min(double v) {
     for (int off = 32; off > 0; off >>= 1) v = fmin(v, __shfl_xor(v, off, 64));
@@ -199,8 +200,9 @@ __global__ void __launch_bounds__(NT) k_potrf_update(double* base, const View* v
 
 // ---------------------------------------------------------------- pivoted Cholesky of a trailing block
 
-// Largest value over [j, n) of d by one workgroup; among equal values the one
-// with the lowest key (key[i], or i without keys).  red: 2 * NT / 64 LDS slots.
+// Largest value over [j, n) of d by one workgroup of NTH threads; among equal values
+// the one with the lowest key (key[i], or i without keys).  rv, ri: NTH / 64 LDS slots.
+template <int NTH>
 __device__ inline void wg_argmax(const double* d, const int32_t* key, int j, int n, double* rv, int* ri, double& bv,
                                  int& bi) {
     auto kf = [key](int i) { return key ? key[i] : i; };
@@ -209,7 +211,7 @@ __device__ inline void wg_argmax(const double* d, const int32_t* key, int j, int
     };
     bv = -INFINITY;
     bi = -1;
-    for (int i = j + t_id(); i < n; i += NT) {
+    for (int i = j + t_id(); i < n; i += NTH) {
         const double x = d[i];
         if (better(x, i, bv, bi)) { bv = x; bi = i; }
     }
@@ -222,7 +224,7 @@ __device__ inline void wg_argmax(const double* d, const int32_t* key, int j, int
     __syncthreads();
     bv = rv[0];
     bi = ri[0];
-    for (int w = 1; w < NT / 64; ++w)
+    for (int w = 1; w < NTH / 64; ++w)
         if (better(rv[w], ri[w], bv, bi)) { bv = rv[w]; bi = ri[w]; }
     __syncthreads();
 }
@@ -240,11 +242,12 @@ __device__ inline void wg_argmax(const double* d, const int32_t* key, int j, int
 // perm (optional, at diag_off like diag): perm[i] is the trailing index whose
 // row and column sit at trailing position i; among equal diagonal entries the
 // pivot is then the lowest original index (without perm: the lowest position).
-__global__ void __launch_bounds__(NT) k_pstrf_panel(double* base, const View* views, const int32_t* lead, int kb,
-                                                    const double* tol, const int64_t* diag_off, double* diag,
-                                                    int32_t* perm, int32_t* rank, int32_t* done) {
-    __shared__ double rv[NT / 64];
-    __shared__ int ri[NT / 64];
+__global__ void __launch_bounds__(NTP) k_pstrf_panel(double* base, const View* views, const int32_t* lead, int kb,
+                                                     const double* tol, const int64_t* diag_off, double* diag,
+                                                     int32_t* perm, int32_t* rank, int32_t* done) {
+    __shared__ double rv[NTP / 64];
+    __shared__ int ri[NTP / 64];
+    __shared__ double s_p[TB];
     if (done[blockIdx.y]) return;
     const View v = views[blockIdx.y];
     const int nw = lead[blockIdx.y];
@@ -260,14 +263,14 @@ __global__ void __launch_bounds__(NT) k_pstrf_panel(double* base, const View* vi
     }
     const int j1 = min(j0 + TB, ng);
     int32_t* Pm = perm ? perm + diag_off[blockIdx.y] : nullptr;
-    for (int i = j0 + t_id(); i < ng; i += NT) D[i] = M[(nw + i) + (int64_t)(nw + i) * ld];
+    for (int i = j0 + t_id(); i < ng; i += NTP) D[i] = M[(nw + i) + (int64_t)(nw + i) * ld];
     if (Pm && kb == 0)
-        for (int i = t_id(); i < ng; i += NT) Pm[i] = i;
+        for (int i = t_id(); i < ng; i += NTP) Pm[i] = i;
     __syncthreads();
     for (int j = j0; j < j1; ++j) {
         double bv;
         int bi;
-        wg_argmax(D, Pm, j, ng, rv, ri, bv, bi);
+        wg_argmax<NTP>(D, Pm, j, ng, rv, ri, bv, bi);
         if (!(bv > tl)) {
             if (t_id() == 0) { rank[blockIdx.y] = j; done[blockIdx.y] = 1; }
             return;
@@ -275,7 +278,7 @@ __global__ void __launch_bounds__(NT) k_pstrf_panel(double* base, const View* vi
         const int J = nw + j;
         if (bi != j) {
             const int Q = nw + bi;
-            for (int q = t_id(); q < m; q += NT) {
+            for (int q = t_id(); q < m; q += NTP) {
                 if (q < J) {
                     const double a = M[J + (int64_t)q * ld];
                     M[J + (int64_t)q * ld] = M[Q + (int64_t)q * ld];
@@ -304,12 +307,25 @@ __global__ void __launch_bounds__(NT) k_pstrf_panel(double* base, const View* vi
             }
             __syncthreads();
         }
+        // the pivot row's entries in the panel's earlier columns, staged once
+        for (int k = j0 + t_id(); k < j; k += NTP) s_p[k - j0] = M[J + (int64_t)(nw + k) * ld];
+        __syncthreads();
         const double ljj = sqrt(D[j]);
         const double inv = 1.0 / ljj;
-        for (int i = j + 1 + t_id(); i < ng; i += NT) {
-            double c = M[(nw + i) + (int64_t)J * ld];
-            for (int k = j0; k < j; ++k) c -= M[(nw + i) + (int64_t)(nw + k) * ld] * M[J + (int64_t)(nw + k) * ld];
-            c *= inv;
+        // column j below the pivot, left-looking over the panel's earlier columns in
+        // four independent partial sums
+        for (int i = j + 1 + t_id(); i < ng; i += NTP) {
+            const double* mi = M + (nw + i);
+            double c0 = mi[(int64_t)J * ld], c1 = 0.0, c2 = 0.0, c3 = 0.0;
+            int k = j0;
+            for (; k + 4 <= j; k += 4) {
+                c0 -= mi[(int64_t)(nw + k) * ld] * s_p[k - j0];
+                c1 -= mi[(int64_t)(nw + k + 1) * ld] * s_p[k + 1 - j0];
+                c2 -= mi[(int64_t)(nw + k + 2) * ld] * s_p[k + 2 - j0];
+                c3 -= mi[(int64_t)(nw + k + 3) * ld] * s_p[k + 3 - j0];
+            }
+            for (; k < j; ++k) c0 -= mi[(int64_t)(nw + k) * ld] * s_p[k - j0];
+            const double c = ((c0 + c1) + (c2 + c3)) * inv;
             M[(nw + i) + (int64_t)J * ld] = c;
             D[i] -= c * c;
         }
@@ -589,7 +605,7 @@ void Batched::pstrf_trailing(double* base, const std::vector<View>& a, const std
     const unsigned nm = (unsigned)nv;
     const int nt = (max_ng + TB - 1) / TB;
     for (int kb = 0; kb < nt; ++kb) {
-        hipLaunchKernelGGL(k_pstrf_panel, dim3(1, nm), dim3(NT), 0, st, base, dv, d_lead, kb, d_tol, d_doff, d_diag,
+        hipLaunchKernelGGL(k_pstrf_panel, dim3(1, nm), dim3(NTP), 0, st, base, dv, d_lead, kb, d_tol, d_doff, d_diag,
                            d_perm, d_rank, d_done);
         const int64_t m = nt - kb - 1;
         if (m > 0)

@@ -2575,6 +2575,28 @@ lsdd_status lsdd_autotune(lsdd_hierarchy* h, int32_t block, void* hip_stream) {
     ABI_END
 }
 
+lsdd_status lsdd_set_level_tuning(lsdd_hierarchy* h, int32_t level, const int32_t* in) {
+    ABI_BEGIN
+    if (!h || !in || level < 0 || level >= (int32_t)h->L.size()) throw Error(LSDD_E_INVAL, "bad argument");
+    auto one_of = [](int32_t v, std::initializer_list<int32_t> ok) {
+        return std::find(ok.begin(), ok.end(), v) != ok.end();
+    };
+    if (!one_of(in[0], {8, 16, 32, 64}) || !one_of(in[1], {4, 8, 16, 32, 64}) || !one_of(in[2], {2, 4, 8}) ||
+        !one_of(in[3], {8, 32}))
+        throw Error(LSDD_E_INVAL, "launch shape outside the autotuner's candidates");
+    Level& lv = *h->L[level];
+    lv.lanes = in[0];
+    lv.lanes_b = in[1];
+    lv.fl = in[3];
+    if (!lv.coarsest && in[2] != lv.chl) {
+        set_chunk(h, lv, in[2]);
+        sync(h->st);
+    }
+    reset_graphs(h);
+    return LSDD_OK;
+    ABI_END
+}
+
 lsdd_status lsdd_level_tuning(const lsdd_hierarchy* h, int32_t level, int32_t* out) {
     ABI_BEGIN
     if (!h || !out || level < 0 || level >= (int32_t)h->L.size()) throw Error(LSDD_E_INVAL, "bad argument");

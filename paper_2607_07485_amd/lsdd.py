@@ -100,6 +100,7 @@ def lib():
         L.lsdd_solve_batched.argtypes = [C.c_int32, C.POINTER(_P), C.POINTER(_P), C.POINTER(_P), C.c_int32, _P,
                                          C.POINTER(Info)]
         L.lsdd_level_tuning.argtypes = [_P, C.c_int32, i32p]
+        L.lsdd_set_level_tuning.argtypes = [_P, C.c_int32, i32p]
         L.lsdd_set_allocator.restype = None
         for name in ("lsdd_setup_elements", "lsdd_setup_gram_csr", "lsdd_solve", "lsdd_solve_stationary",
                      "lsdd_vcycle", "lsdd_apply",
@@ -108,7 +109,7 @@ def lib():
                      "lsdd_set_solve_params", "lsdd_set_graph", "lsdd_segments", "lsdd_setup_batched",
                      "lsdd_level_segments", "lsdd_autotune", "lsdd_level_tuning", "lsdd_setup_elements_scaled",
                      "lsdd_update_theta", "lsdd_elem_bilinear", "lsdd_elem_bilinear_noalloc",
-                     "lsdd_solve_batched", "lsdd_export_gram_level"):
+                     "lsdd_solve_batched", "lsdd_export_gram_level", "lsdd_set_level_tuning"):
             getattr(L, name).restype = C.c_int
         _LIB = L
     return _LIB
@@ -328,6 +329,16 @@ class Hierarchy:
         out = np.zeros(4, dtype=np.int32)
         _check(lib().lsdd_level_tuning(self._h, int(level), out.ctypes.data_as(C.POINTER(C.c_int32))))
         return dict(lanes=int(out[0]), lanes_block=int(out[1]), tiles_per_item=int(out[2]), finalize_threads=int(out[3]))
+
+    def set_level_tuning(self, level: int, t: dict):
+        """lsdd_set_level_tuning with a dict as returned by level_tuning."""
+        a = np.array([t["lanes"], t["lanes_block"], t["tiles_per_item"], t["finalize_threads"]], dtype=np.int32)
+        _check(lib().lsdd_set_level_tuning(self._h, int(level), a.ctypes.data_as(C.POINTER(C.c_int32))))
+
+    def set_tuning(self, tuning):
+        """Apply a list of per-level shapes (the return value of autotune)."""
+        for l, t in enumerate(tuning):
+            self.set_level_tuning(l, t)
 
     def segments(self):
         """(n_seg, seg_off as a list)."""

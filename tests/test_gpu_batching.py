@@ -202,6 +202,40 @@ def test_autotuned_shapes_keep_parity(dev):
             assert np.linalg.norm(X[k] - x_or) <= 1e-10 * np.linalg.norm(x_or)
 
 
+def test_set_level_tuning_round_trip_and_checks(dev):
+    """lsdd_set_level_tuning applies any candidate shape (read back by lsdd_level_tuning),
+    the solve then matches the oracle as with the autotuner's shapes, and values outside
+    the candidates are refused without changing anything."""
+    P = _lsdd()
+    prob, rng = _graddiv(seed=9)
+    h_or = oracle.setup(prob, oracle.Params(**GD_KW))
+    b = rng.standard_normal(prob.n)
+    x_or, inf_or = oracle.pcg(h_or, b)
+    with P.Hierarchy.setup_problem(prob, P.Params.default(**GD_KW)) as h:
+        tuned = h.autotune(block=False)
+        other = [dict(lanes=8 if t["lanes"] != 8 else 32, lanes_block=4, tiles_per_item=2 if t["tiles_per_item"] != 2 else 8,
+                      finalize_threads=32 if t["finalize_threads"] == 8 else 8) for t in tuned]
+        h.set_tuning(other)
+        levels = len(tuned)
+        for l in range(levels):
+            got = h.level_tuning(l)
+            assert got["lanes"] == other[l]["lanes"] and got["finalize_threads"] == other[l]["finalize_threads"]
+            if l < levels - 1:
+                assert got["tiles_per_item"] == other[l]["tiles_per_item"]
+        x, inf = h.solve(torch.from_numpy(b).to(dev))
+        assert abs(inf[0].iters - inf_or.iters) <= 1
+        assert np.linalg.norm(x.cpu().numpy() - x_or) <= 1e-10 * np.linalg.norm(x_or)
+        before = h.level_tuning(0)
+        for bad in (dict(before, lanes=12), dict(before, tiles_per_item=3), dict(before, finalize_threads=16)):
+            with pytest.raises(P.LsddError) as ei:
+                h.set_level_tuning(0, bad)
+            assert ei.value.code == 1
+        assert h.level_tuning(0) == before
+        h.set_tuning(tuned)
+        x2, _ = h.solve(torch.from_numpy(b).to(dev))
+        assert np.linalg.norm(x2.cpu().numpy() - x_or) <= 1e-10 * np.linalg.norm(x_or)
+
+
 def test_solve_batched_over_separate_hierarchies(dev):
     """lsdd_solve_batched on three separately built hierarchies (two elasticity meshes and
     a grad-div one, two right-hand sides each): every instance's result equals its own
