@@ -630,6 +630,59 @@ __device__ inline void wg_block_update_mfma(mg::Smem& sm, double* V, int n, int 
     }
 }
 
+// Orthonormalise the batch Y = V[:, b0 .. b0 + bn) by Cholesky QR: with D the
+// inverse column norms, D Y^T Y D = L L^T and Y <- Y D L^{-T}.  That is the Q of
+// Y = QR, the factor Gram-Schmidt in index order produces, from one product on
+// the matrix cores, a 64 x 64 Cholesky in LDS and one triangular solve per row.
+// Returns false, with Y unchanged, when a pivot of the unit-diagonal Gram matrix
+// falls below 1e-12 (cond(Y D) above about 1e6, where one pass would lose
+// orthogonality); the caller then orthogonalises member by member.  dd: 64 x 64
+// doubles of global scratch.
+__device__ inline bool wg_batch_cholqr(mg::Smem& sm, double* V, int n, int b0, int bn, double* dd) {
+    __shared__ int s_ok;
+    __shared__ double s_d[64];
+    wg_block_dots_mfma(sm, V, n, b0, bn, b0, bn, dd);
+    __syncthreads();
+    double* G = reinterpret_cast<double*>(&sm);                // bn * bn <= 4096 doubles
+    for (int i = tid(); i < bn; i += LSDD_WG) {
+        const double g = dd[i + i * bn];
+        s_d[i] = g > 0.0 ? 1.0 / sqrt(g) : 0.0;
+    }
+    if (tid() == 0) s_ok = 1;
+    __syncthreads();
+    for (int idx = tid(); idx < bn * bn; idx += LSDD_WG) G[idx] = dd[idx] * s_d[idx % bn] * s_d[idx / bn];
+    __syncthreads();
+    for (int j = 0; j < bn; ++j) {
+        const double pjj = G[j + j * bn];
+        if (!(pjj > 1e-12)) {
+            if (tid() == 0) s_ok = 0;
+            break;                                              // same value on every thread
+        }
+        const double ljj = sqrt(pjj);
+        for (int i = j + 1 + tid(); i < bn; i += LSDD_WG) G[i + j * bn] /= ljj;
+        __syncthreads();
+        const int m = bn - 1 - j;                               // trailing (i, k), j < k <= i
+        for (int idx = tid(); idx < m * m; idx += LSDD_WG) {
+            const int i = j + 1 + idx % m, k = j + 1 + idx / m;
+            if (k <= i) G[i + k * bn] -= G[i + j * bn] * G[k + j * bn];
+        }
+        if (tid() == 0) G[j + j * bn] = ljj;
+        __syncthreads();
+    }
+    __syncthreads();
+    const bool ok = s_ok != 0;
+    if (ok) {
+        for (int r = tid(); r < n; r += LSDD_WG)
+            for (int j = 0; j < bn; ++j) {
+                double z = V[(long long)(b0 + j) * n + r] * s_d[j];
+                for (int k = 0; k < j; ++k) z -= V[(long long)(b0 + k) * n + r] * G[j + k * bn];
+                V[(long long)(b0 + j) * n + r] = z / G[j + j * bn];
+            }
+    }
+    __syncthreads();
+    return ok;
+}
+
 // Eigenvectors of the tridiagonal (d, e) for the eigenvalues lam[0..kk) by
 // inverse iteration.  Eigenvalues closer than 1e-4 * tnorm form a cluster.
 // This workgroup handles the single-member clusters with index in [r0, r1)
@@ -638,9 +691,10 @@ __device__ inline void wg_block_update_mfma(mg::Smem& sm, double* V, int n, int 
 // (u0, u1, u2) and singleton iterates of the 64 solving lanes, interleaved by
 // lane.  The members of a larger cluster are processed in batches of up
 // to 64: each iteration solves every member's shifted system on its own
-// thread, then orthogonalises the batch by classical Gram-Schmidt applied
-// twice against the earlier members of the cluster and, in index order,
-// within the batch, and normalises it.  Every vector is computed the same way
+// thread, then orthogonalises the batch twice: by block classical Gram-Schmidt
+// against the earlier members of the cluster, then within the batch by Cholesky
+// QR (with sm; wg_batch_cholqr) or, where that is refused or without sm, by
+// Gram-Schmidt in index order, normalising each member.  Every vector is computed the same way
 // whatever the range split.  Output V (n x kk, column-major, ld n); `dd` holds
 // 64 x 64 batch dots.  LDS: cl_start (kk+1 ints), dots (64).
 // sm: LDS staging of the matrix cores for the block Gram-Schmidt steps of
@@ -722,7 +776,9 @@ __device__ inline void wg_inverse_iteration_range(const double* d, const double*
                         }
                         __syncthreads();
                     }
-                    // within the batch, in index order, each member normalised before use
+                    // within the batch: Cholesky QR where the batch is well enough
+                    // conditioned, else in index order, each member normalised before use
+                    if (sm && wg_batch_cholqr(*sm, V, n, b0, bn, dd)) continue;
                     for (int t = 0; t < bn; ++t) {
                         double* y = V + (long long)(b0 + t) * n;
                         if (t > 0) {

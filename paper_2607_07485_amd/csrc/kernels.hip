@@ -86,13 +86,15 @@ __device__ inline int local_index(const int32_t* dofs, int nw, int m, int32_t q)
 
 // One workgroup per element: eigendecomposition of the symmetric block A_T by
 // parallel Jacobi, SPSD check, rank, and G_T = Lambda_+^{1/2} Q_+^T stored
-// row-major as an n_T x n_T array whose first r_T rows are valid.
+// row-major as an n_T x n_T array whose first r_T rows are valid.  For n_T up to
+// NE_LDS the rotated matrix and the eigenvectors live in dynamic LDS (lds_bytes);
+// otherwise in the element's slot of scratch (3 n_T^2 doubles), which also holds
+// the sorted vectors.
 __global__ void __launch_bounds__(WG) k_elem_eig(const int64_t* elem_ptr, const int64_t* blk_off,
                                                  const double* blocks, double* G, int32_t* ranks,
                                                  int32_t* status, double* scratch, int64_t scratch_stride,
-                                                 double rank_rtol, double spsd_tol) {
-    __shared__ double s_a[NE_LDS * NE_LDS];
-    __shared__ double s_v[NE_LDS * NE_LDS];
+                                                 double rank_rtol, double spsd_tol, int64_t lds_bytes) {
+    extern __shared__ double s_dyn[];
     __shared__ double s_w[128];
     __shared__ int s_rank[128];
     __shared__ int s_pairs[128];
@@ -102,19 +104,12 @@ __global__ void __launch_bounds__(WG) k_elem_eig(const int64_t* elem_ptr, const 
     const int64_t e = blockIdx.x;
     const int n = (int)(elem_ptr[e + 1] - elem_ptr[e]);
     const double* B = blocks + blk_off[e];
-    double* a;
-    double* v;
-    double* vs;
-    if (n <= NE_LDS) {
-        a = s_a;
-        v = s_v;
-        vs = scratch + e * scratch_stride;   // sorted vectors (global, n^2)
-    } else {
-        a = scratch + e * scratch_stride;
-        v = a + (int64_t)n * n;
-        vs = v + (int64_t)n * n;
-    }
-    if (n <= NE_LDS) vs = scratch + e * scratch_stride;
+    const int64_t nn = (int64_t)n * n;
+    double* gs = scratch + e * scratch_stride;
+    const bool in_lds = n <= NE_LDS && 2 * nn * 8 <= lds_bytes;
+    double* a = in_lds ? s_dyn : gs;
+    double* v = in_lds ? s_dyn + nn : gs + nn;
+    double* vs = gs + 2 * nn;                  // sorted vectors (global, n^2)
     // load (column-major == row-major for symmetric), asymmetry and scale
     double asym = 0.0, amax = 0.0;
     for (int idx = tid(); idx < n * n; idx += WG) {
@@ -1147,8 +1142,15 @@ void launch_elem_eig(int64_t n_elem, const int64_t* elem_ptr, const int64_t* blk
                      int32_t* ranks, int32_t* status, double* scratch, int64_t scratch_stride, double rank_rtol,
                      double spsd_tol, hipStream_t st) {
     if (n_elem <= 0) return;
-    hipLaunchKernelGGL(k_elem_eig, dim3((unsigned)n_elem), dim3(WG), 0, st, elem_ptr, blk_off, blocks, G, ranks, status,
-                       scratch, scratch_stride, rank_rtol, spsd_tol);
+    // scratch_stride = 3 n_max^2.  Matrix and vectors in LDS up to NE_LDS, sized to the
+    // blocks so that small blocks leave room for many workgroups per CU (Q1 batch: 0.26 ->
+    // 0.21 s).  Larger blocks rotate in scratch; for them the same 2 NE_LDS^2 doubles are
+    // still reserved, which caps the workgroups per CU at what measured fastest (81 x 81 Q2
+    // blocks: 0.67 s, against 0.74 s with no LDS and 1.2 s with the matrix in LDS)
+    const int64_t nn = scratch_stride / 3;
+    const int64_t lds = 2 * std::min<int64_t>(nn, (int64_t)NE_LDS * NE_LDS) * 8;
+    hipLaunchKernelGGL(k_elem_eig, dim3((unsigned)n_elem), dim3(WG), (size_t)lds, st, elem_ptr, blk_off, blocks, G,
+                       ranks, status, scratch, scratch_stride, rank_rtol, spsd_tol, lds);
 }
 
 void launch_elem_pchol(int64_t n_elem, const int64_t* elem_ptr, const int64_t* blk_off, const double* blocks,
