@@ -86,10 +86,11 @@ __device__ inline int local_index(const int32_t* dofs, int nw, int m, int32_t q)
 
 // One workgroup per element: eigendecomposition of the symmetric block A_T by
 // parallel Jacobi, SPSD check, rank, and G_T = Lambda_+^{1/2} Q_+^T stored
-// row-major as an n_T x n_T array whose first r_T rows are valid.  For n_T up to
-// NE_LDS the rotated matrix and the eigenvectors live in dynamic LDS (lds_bytes);
-// otherwise in the element's slot of scratch (3 n_T^2 doubles), which also holds
-// the sorted vectors.
+// row-major as an n_T x n_T array whose first r_T rows are valid.  Blocks up to
+// NE_LDS: the rotated matrix and the eigenvectors live in dynamic LDS (lds_bytes,
+// sized to the largest block so small blocks leave room for many workgroups per
+// CU), the sorted vectors in the element's slot of scratch; larger blocks are
+// left to k_elem_eig_trd.
 __global__ void __launch_bounds__(WG) k_elem_eig(const int64_t* elem_ptr, const int64_t* blk_off,
                                                  const double* blocks, double* G, int32_t* ranks,
                                                  int32_t* status, double* scratch, int64_t scratch_stride,
@@ -104,12 +105,11 @@ __global__ void __launch_bounds__(WG) k_elem_eig(const int64_t* elem_ptr, const 
     const int64_t e = blockIdx.x;
     const int n = (int)(elem_ptr[e + 1] - elem_ptr[e]);
     const double* B = blocks + blk_off[e];
+    if (n > NE_LDS) return;                   // k_elem_eig_trd
     const int64_t nn = (int64_t)n * n;
-    double* gs = scratch + e * scratch_stride;
-    const bool in_lds = n <= NE_LDS && 2 * nn * 8 <= lds_bytes;
-    double* a = in_lds ? s_dyn : gs;
-    double* v = in_lds ? s_dyn + nn : gs + nn;
-    double* vs = gs + 2 * nn;                  // sorted vectors (global, n^2)
+    double* a = s_dyn;                         // lds_bytes >= 2 n^2 doubles
+    double* v = s_dyn + nn;
+    double* vs = scratch + e * scratch_stride; // sorted vectors (global, n^2)
     // load (column-major == row-major for symmetric), asymmetry and scale
     double asym = 0.0, amax = 0.0;
     for (int idx = tid(); idx < n * n; idx += WG) {
@@ -151,6 +151,95 @@ __global__ void __launch_bounds__(WG) k_elem_eig(const int64_t* elem_ptr, const 
     if (tid() == 0) {
         ranks[e] = r;
         status[e] = 0;
+    }
+}
+
+// Element blocks larger than NE_LDS, one workgroup per element: the same outputs
+// and rules as k_elem_eig (SPSD check, rank at n_T eps lambda_max, G_T =
+// Lambda_+^{1/2} Q_+^T with rows in ascending eigenvalue order) from a Householder
+// tridiagonalisation, bisection for all eigenvalues, inverse iteration for the
+// retained ones only and back-transformation, instead of Jacobi sweeps.  Four
+// launches (PHASE 0..3: load and reduce; eigenvalues, SPSD check and rank;
+// inverse iteration; back-transformation and G_T), so that the register-heavy
+// inverse iteration does not set the occupancy of the others.  The element's slot
+// of scratch holds S (n^2, reduced in place) | V (n^2, retained vectors) | d, e,
+// tau, w (4n) | inverse-iteration scratch (INVIT_SLOTS n + 4096); status[e] and
+// ranks[e] carry the state between phases.  Dynamic LDS: 2 n_max + 64 doubles.
+// Smaller elements are left to k_elem_eig.
+template <int PHASE>
+__global__ void __launch_bounds__(WG) k_elem_eig_trd(const int64_t* elem_ptr, const int64_t* blk_off,
+                                                     const double* blocks, double* G, int32_t* ranks,
+                                                     int32_t* status, double* scratch, int64_t scratch_stride,
+                                                     double rank_rtol, double spsd_tol) {
+    extern __shared__ double s_dyn[];
+    __shared__ double s_red[WG / 64];
+    __shared__ int s_ncl;
+    const int64_t e = blockIdx.x;
+    const int n = (int)(elem_ptr[e + 1] - elem_ptr[e]);
+    if (n <= NE_LDS) return;
+    if (PHASE > 0 && status[e] != 0) return;
+    const int64_t nn = (int64_t)n * n;
+    double* S = scratch + e * scratch_stride;
+    double* V = S + nn;
+    double* d = V + nn;
+    double* ee = d + n;
+    double* tau = ee + n;
+    double* w = tau + n;
+    double* ws = w + n;
+    if (PHASE == 0) {
+        const double* B = blocks + blk_off[e];
+        double asym = 0.0, amax = 0.0;
+        for (int idx = tid(); idx < n * n; idx += WG) {
+            const int i = idx % n, j = idx / n;
+            const double x = B[(int64_t)i * n + j], y = B[(int64_t)j * n + i];
+            S[i + (int64_t)j * n] = 0.5 * (x + y);
+            asym = fmax(asym, fabs(x - y));
+            amax = fmax(amax, fabs(x));
+        }
+        __syncthreads();
+        asym = wg_max(asym, s_red);
+        amax = wg_max(amax, s_red);
+        if (!(asym <= 1e-12 * amax) || !(amax == amax) || amax > DBL_MAX) {
+            if (tid() == 0) status[e] = 1;   // asymmetric or non-finite
+            return;
+        }
+        wg_tridiag(S, n, d, ee, tau, s_dyn, s_dyn + n, s_red);
+        if (tid() == 0) status[e] = 0;
+        return;
+    }
+    if (PHASE == 1) {
+        wg_bisect_all(d, ee, n, w, s_red);
+        __syncthreads();
+        if (tid() == 0) {
+            const double lmax = fmax(w[n - 1], 0.0);
+            if (w[0] < -spsd_tol * lmax) {
+                status[e] = 2;
+            } else {
+                const double tol = (rank_rtol > 0.0 ? rank_rtol : n * DBL_EPSILON) * lmax;
+                int first = 0;
+                while (first < n && !(w[first] > tol)) ++first;     // eigenvalues ascending
+                ranks[e] = n - first;
+            }
+        }
+        return;
+    }
+    const int r = ranks[e];
+    const int first = n - r;
+    if (PHASE == 2) {
+        if (r == 0) return;
+        double tnorm = 0.0;
+        for (int i = tid(); i < n; i += WG)
+            tnorm = fmax(tnorm, fabs(d[i]) + (i > 0 ? fabs(ee[i - 1]) : 0.0) + (i + 1 < n ? fabs(ee[i]) : 0.0));
+        tnorm = wg_max(tnorm, s_red);
+        wg_inverse_iteration(d, ee, n, w + first, r, V, ws, fmax(tnorm, 1e-300), (int*)s_dyn, s_dyn + n, s_red,
+                             &s_ncl);
+        return;
+    }
+    if (r > 0) wg_tridiag_backtransform(S, n, tau, V, r, s_dyn, s_dyn + n);
+    double* g = G + blk_off[e];
+    for (int idx = tid(); idx < n * n; idx += WG) {
+        const int row = idx / n, c = idx % n;
+        g[idx] = row < r ? sqrt(w[first + row]) * V[c + (int64_t)row * n] : 0.0;
     }
 }
 
@@ -1062,14 +1151,15 @@ __global__ void __launch_bounds__(WG) k_prolong(const int32_t* items, const int6
         for (int s = tid(); s < cn; s += WG) s_e[s] = ec[coff[ag] + c0 + s];
         __syncthreads();
         if (a < nw) {
-            // 4 modes per step in flight; modes past the end re-read the last one
+            // PU modes per step in flight; modes past the end re-read the last one
             // and contribute zero
-            for (int s = 0; s < cn; s += 4) {
-                T zv[4];
+            constexpr int PU = 8;
+            for (int s = 0; s < cn; s += PU) {
+                T zv[PU];
 #pragma unroll
-                for (int u = 0; u < 4; ++u) zv[u] = z[(int64_t)(c0 + min(s + u, cn - 1)) * nw];
+                for (int u = 0; u < PU; ++u) zv[u] = z[(int64_t)(c0 + min(s + u, cn - 1)) * nw];
 #pragma unroll
-                for (int u = 0; u < 4; ++u) (u & 1 ? acc1 : acc0) += (s + u < cn ? zv[u] : (T)0) * s_e[min(s + u, cn - 1)];
+                for (int u = 0; u < PU; ++u) (u & 1 ? acc1 : acc0) += (s + u < cn ? zv[u] : (T)0) * s_e[min(s + u, cn - 1)];
             }
         }
     }
@@ -1140,17 +1230,32 @@ constexpr int NPART = 1024;
 
 void launch_elem_eig(int64_t n_elem, const int64_t* elem_ptr, const int64_t* blk_off, const double* blocks, double* G,
                      int32_t* ranks, int32_t* status, double* scratch, int64_t scratch_stride, double rank_rtol,
-                     double spsd_tol, hipStream_t st) {
+                     double spsd_tol, int64_t n_max, hipStream_t st) {
     if (n_elem <= 0) return;
-    // scratch_stride = 3 n_max^2.  Matrix and vectors in LDS up to NE_LDS, sized to the
-    // blocks so that small blocks leave room for many workgroups per CU (Q1 batch: 0.26 ->
-    // 0.21 s).  Larger blocks rotate in scratch; for them the same 2 NE_LDS^2 doubles are
-    // still reserved, which caps the workgroups per CU at what measured fastest (81 x 81 Q2
-    // blocks: 0.67 s, against 0.74 s with no LDS and 1.2 s with the matrix in LDS)
-    const int64_t nn = scratch_stride / 3;
-    const int64_t lds = 2 * std::min<int64_t>(nn, (int64_t)NE_LDS * NE_LDS) * 8;
+    // blocks up to NE_LDS: Jacobi with matrix and vectors in LDS; larger blocks: the
+    // tridiagonal route (k_elem_eig_trd; 81 x 81 Q2 blocks: Jacobi took 0.67 s)
+    const int64_t nl = std::min<int64_t>(n_max, NE_LDS);
+    const int64_t lds = 2 * nl * nl * 8;
     hipLaunchKernelGGL(k_elem_eig, dim3((unsigned)n_elem), dim3(WG), (size_t)lds, st, elem_ptr, blk_off, blocks, G,
                        ranks, status, scratch, scratch_stride, rank_rtol, spsd_tol, lds);
+    if (n_max > NE_LDS) {
+        const size_t ld = (size_t)(2 * n_max + 64) * 8;
+        const dim3 g((unsigned)n_elem);
+        hipLaunchKernelGGL(k_elem_eig_trd<0>, g, dim3(WG), ld, st, elem_ptr, blk_off, blocks, G, ranks, status,
+                           scratch, scratch_stride, rank_rtol, spsd_tol);
+        hipLaunchKernelGGL(k_elem_eig_trd<1>, g, dim3(WG), ld, st, elem_ptr, blk_off, blocks, G, ranks, status,
+                           scratch, scratch_stride, rank_rtol, spsd_tol);
+        hipLaunchKernelGGL(k_elem_eig_trd<2>, g, dim3(WG), ld, st, elem_ptr, blk_off, blocks, G, ranks, status,
+                           scratch, scratch_stride, rank_rtol, spsd_tol);
+        hipLaunchKernelGGL(k_elem_eig_trd<3>, g, dim3(WG), ld, st, elem_ptr, blk_off, blocks, G, ranks, status,
+                           scratch, scratch_stride, rank_rtol, spsd_tol);
+    }
+}
+
+int64_t elem_eig_scratch_stride(int64_t n_max) {
+    const int64_t jac = 3 * n_max * n_max;
+    const int64_t trd = n_max > NE_LDS ? 2 * n_max * n_max + 4 * n_max + (int64_t)INVIT_SLOTS * n_max + 4096 : 0;
+    return std::max(jac, trd);
 }
 
 void launch_elem_pchol(int64_t n_elem, const int64_t* elem_ptr, const int64_t* blk_off, const double* blocks,

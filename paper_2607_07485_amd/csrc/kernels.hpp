@@ -73,9 +73,13 @@ void launch_local_invit_blocked(const LocalArgs& a, const int32_t* d_big, const 
 void launch_local_backtransform_blocked(const LocalArgs& a, const int32_t* d_big, const std::vector<int32_t>& sizes,
                                         hipStream_t st);
 
+// Element Gram factors from eigendecompositions: Jacobi in LDS for blocks up to 48,
+// the tridiagonal route above; n_max = largest block, scratch of
+// elem_eig_scratch_stride(n_max) doubles per element.
 void launch_elem_eig(int64_t n_elem, const int64_t* elem_ptr, const int64_t* blk_off, const double* blocks,
                      double* G, int32_t* ranks, int32_t* status, double* scratch, int64_t scratch_stride,
-                     double rank_rtol, double spsd_tol, hipStream_t st);
+                     double rank_rtol, double spsd_tol, int64_t n_max, hipStream_t st);
+int64_t elem_eig_scratch_stride(int64_t n_max);
 
 // CSR values += sum_T f_T R_T^T A_T R_T (f = factor, NULL = 1); d2e lists the
 // (element, local index) pairs of every DOF, elements ascending; wave_rows: one

@@ -1946,7 +1946,7 @@ lsdd_hierarchy* build(ElemList el0, const double* blocks, bool blocks_on_device,
         int32_t* d_status = ar.alloc<int32_t>(ne);
         int64_t max_ne = 0;
         for (int64_t e = 0; e < ne; ++e) max_ne = std::max(max_ne, lv->el.ptr[e + 1] - lv->el.ptr[e]);
-        const int64_t stride = 3 * max_ne * max_ne;
+        const int64_t stride = std::max<int64_t>(3 * max_ne * max_ne, elem_eig_scratch_stride(max_ne));
         // process elements in chunks so the eigen scratch stays bounded
         const int64_t chunk = std::max<int64_t>(1, std::min<int64_t>(ne, (int64_t(1) << 30) / (stride * 8)));
         double* scratch = ar.alloc<double>(chunk * stride);
@@ -1957,7 +1957,7 @@ lsdd_hierarchy* build(ElemList el0, const double* blocks, bool blocks_on_device,
                                   d_ranks + e0, d_status + e0, scratch, stride, P.rank_rtol, P.spsd_tol, h->st);
             else
                 launch_elem_eig(cnt, lv->d_elem_ptr + e0, lv->d_blk_off + e0, lv->d_blocks, lv->d_G, d_ranks + e0,
-                                d_status + e0, scratch, stride, P.rank_rtol, P.spsd_tol, h->st);
+                                d_status + e0, scratch, stride, P.rank_rtol, P.spsd_tol, max_ne, h->st);
         }
         HIPCHK(hipGetLastError());
         std::vector<int32_t> status = download(d_status, ne, h->st);

@@ -434,6 +434,39 @@ def test_pivoted_cholesky_element_factors(dev, name):
         h.close()
 
 
+def test_eigen_element_factors_of_large_blocks(dev):
+    """81 x 81 Q2 blocks (above the Jacobi size) go through the tridiagonal route
+    (Householder reduction, bisection, inverse iteration, back-transformation):
+    ranks bit-exact against the oracle's eigendecomposition, G^T G = A_T and
+    G G^T = diag(positive eigenvalues, ascending) to 1e-12 of the block's scale (a few
+    n eps for the backward-stable reduction and the inverse-iteration residuals), and
+    the hierarchy's V-cycle as with the oracle's factor."""
+    P = _lsdd()
+    prob = fegen.elasticity_q2hex(3, nu=0.3)
+    kw = dict(max_levels=2, tau_const=0.75, agg_passes=1)
+    h_or, h_pr = oracle_routes(prob, **kw)
+    h = P.Hierarchy.setup_problem(prob, P.Params.default(**kw))
+    try:
+        ranks, G = h.export_gram(prob.elem_ptr)
+        assert ranks.tolist() == [g.shape[0] for g in h_or.G0]
+        offs = prob.block_offsets()
+        for e in range(prob.n_elem):
+            ne = int(prob.elem_ptr[e + 1] - prob.elem_ptr[e])
+            assert ne == 81
+            Ge = G[offs[e]:offs[e + 1]].reshape(ne, ne)[:ranks[e]]
+            _, Ae = prob.element(e)
+            scale = np.abs(Ae).max()
+            assert np.abs(Ge.T @ Ge - Ae).max() <= 1e-12 * scale
+            lam = np.linalg.eigvalsh(Ae)[ne - ranks[e]:]
+            assert np.abs(Ge @ Ge.T - np.diag(lam)).max() <= 1e-12 * scale
+        r = np.random.default_rng(7).standard_normal(prob.n)
+        z_or = oracle.vcycle(h_or, r)
+        z = h.vcycle(torch.from_numpy(r).to(dev)).cpu().numpy()
+        assert rel(z, z_or) <= tol_from(z_or, oracle.vcycle(h_pr, r))
+    finally:
+        h.close()
+
+
 def test_pivoted_cholesky_rejects_an_indefinite_block(dev):
     P = _lsdd()
     prob = fegen.elasticity_q1(3, nu=0.3)
