@@ -5,7 +5,6 @@
 
 #include <algorithm>
 #include <cmath>
-#include <map>
 #include <stdexcept>
 
 namespace lsdd {
@@ -239,7 +238,9 @@ void a_closure_overlaps(const Csr& pat, const std::vector<double>& val, double t
 std::vector<int32_t> color_subdomains(int64_t n, const Closure& c, const ElemList& el, int32_t* n_colors) {
     const int32_t na = c.n_agg;
     Csr d2s = transpose(n, c.sub_ptr, c.sub_dofs);        // DOF -> subdomains containing it
-    std::vector<std::pair<int32_t, int32_t>> pr;
+    // S_e: the subdomains an element meets (sorted, distinct); every pair in one S_e conflicts
+    Csr es;
+    es.ptr.assign(el.count() + 1, 0);
     std::vector<int32_t> subs;
     for (int64_t e = 0; e < el.count(); ++e) {
         subs.clear();
@@ -249,26 +250,29 @@ std::vector<int32_t> color_subdomains(int64_t n, const Closure& c, const ElemLis
         }
         std::sort(subs.begin(), subs.end());
         subs.erase(std::unique(subs.begin(), subs.end()), subs.end());
-        for (size_t a = 0; a < subs.size(); ++a)
-            for (size_t b = 0; b < subs.size(); ++b)
-                if (a != b) pr.emplace_back(subs[a], subs[b]);
+        es.idx.insert(es.idx.end(), subs.begin(), subs.end());
+        es.ptr[e + 1] = (int64_t)es.idx.size();
     }
-    Csr conf = pairs_to_csr(na, pr);
-    std::vector<int32_t> color(na, -1);
-    std::vector<int32_t> seen;
+    Csr se = transpose(na, es.ptr, es.idx);              // subdomain -> elements meeting it
+    // greedy in ascending index: the smallest colour that no already coloured
+    // conflicting subdomain holds (stamped per subdomain, no conflict list stored)
+    std::vector<int32_t> color(na, -1), stamp;
     int32_t nc = 0;
     for (int32_t i = 0; i < na; ++i) {
-        seen.clear();
-        for (int64_t q = conf.ptr[i]; q < conf.ptr[i + 1]; ++q)
-            if (color[conf.idx[q]] >= 0) seen.push_back(color[conf.idx[q]]);
-        std::sort(seen.begin(), seen.end());
-        int32_t col = 0;
-        for (int32_t s : seen) {
-            if (s == col) ++col;
-            else if (s > col) break;
+        for (int64_t q = se.ptr[i]; q < se.ptr[i + 1]; ++q) {
+            const int32_t e = se.idx[q];
+            for (int64_t r = es.ptr[e]; r < es.ptr[e + 1]; ++r) {
+                const int32_t k = es.idx[r];
+                if (k < i) stamp[color[k]] = i;
+            }
         }
+        int32_t col = 0;
+        while (col < nc && stamp[col] == i) ++col;
         color[i] = col;
-        nc = std::max(nc, col + 1);
+        if (col == nc) {
+            ++nc;
+            stamp.push_back(-1);
+        }
     }
     *n_colors = nc;
     return color;
@@ -378,11 +382,25 @@ CoarseGroups group_coarse(const ElemList& el, const std::vector<int32_t>& agg_of
     cg.node_of_cdof.resize(coarse_off[na]);
     for (int32_t i = 0; i < na; ++i)
         for (int64_t d = coarse_off[i]; d < coarse_off[i + 1]; ++d) cg.node_of_cdof[d] = compact[i];
-    std::map<std::vector<int32_t>, int32_t> key2g;
-    std::vector<std::vector<int32_t>> members;
-    std::vector<int32_t> t;
-    cg.coarse.ptr.assign(1, 0);
-    for (int64_t e = 0; e < el.count(); ++e) {
+    // Groups keyed by the sorted set of aggregates (with k > 0) an element touches, numbered
+    // in order of first occurrence.  Open-addressing table of group ids; the keys live
+    // once per group in a flat array.
+    const int64_t ne = el.count();
+    int64_t cap = 64;
+    while (cap < 2 * ne + 64) cap <<= 1;
+    std::vector<int32_t> table(cap, -1);
+    std::vector<uint64_t> ghash;
+    std::vector<int64_t> kptr(1, 0);
+    std::vector<int32_t> kval, gid(ne, -1), t;
+    auto hash_of = [](const std::vector<int32_t>& v) {
+        uint64_t h = 1469598103934665603ull;                   // FNV-1a over the entries
+        for (int32_t x : v) {
+            h ^= (uint64_t)(uint32_t)x;
+            h *= 1099511628211ull;
+        }
+        return h;
+    };
+    for (int64_t e = 0; e < ne; ++e) {
         t.clear();
         for (int64_t q = el.ptr[e]; q < el.ptr[e + 1]; ++q) {
             int32_t a = agg_of_dof[el.dofs[q]];
@@ -391,25 +409,43 @@ CoarseGroups group_coarse(const ElemList& el, const std::vector<int32_t>& agg_of
         std::sort(t.begin(), t.end());
         t.erase(std::unique(t.begin(), t.end()), t.end());
         if (t.empty()) continue;
-        auto it = key2g.find(t);
-        int32_t g;
-        if (it == key2g.end()) {
-            g = (int32_t)members.size();
-            key2g.emplace(t, g);
-            members.emplace_back();
-            for (int32_t a : t)
-                for (int64_t d = coarse_off[a]; d < coarse_off[a + 1]; ++d) cg.coarse.dofs.push_back((int32_t)d);
-            cg.coarse.ptr.push_back((int64_t)cg.coarse.dofs.size());
-        } else {
-            g = it->second;
+        const uint64_t h = hash_of(t);
+        int64_t slot = (int64_t)(h & (uint64_t)(cap - 1));
+        int32_t g = -1;
+        while (table[slot] >= 0) {
+            const int32_t c = table[slot];
+            if (ghash[c] == h && kptr[c + 1] - kptr[c] == (int64_t)t.size() &&
+                std::equal(t.begin(), t.end(), kval.begin() + kptr[c])) {
+                g = c;
+                break;
+            }
+            slot = (slot + 1) & (cap - 1);
         }
-        members[g].push_back((int32_t)e);
+        if (g < 0) {
+            g = (int32_t)ghash.size();
+            table[slot] = g;
+            ghash.push_back(h);
+            kval.insert(kval.end(), t.begin(), t.end());
+            kptr.push_back((int64_t)kval.size());
+        }
+        gid[e] = g;
     }
-    cg.mem_ptr.assign(members.size() + 1, 0);
-    for (size_t g = 0; g < members.size(); ++g) {
-        cg.mem_elems.insert(cg.mem_elems.end(), members[g].begin(), members[g].end());
-        cg.mem_ptr[g + 1] = (int64_t)cg.mem_elems.size();
+    const int32_t ng = (int32_t)ghash.size();
+    cg.coarse.ptr.assign(ng + 1, 0);
+    for (int32_t g = 0; g < ng; ++g) {
+        for (int64_t q = kptr[g]; q < kptr[g + 1]; ++q)
+            for (int64_t d = coarse_off[kval[q]]; d < coarse_off[kval[q] + 1]; ++d)
+                cg.coarse.dofs.push_back((int32_t)d);
+        cg.coarse.ptr[g + 1] = (int64_t)cg.coarse.dofs.size();
     }
+    cg.mem_ptr.assign(ng + 1, 0);
+    for (int64_t e = 0; e < ne; ++e)
+        if (gid[e] >= 0) ++cg.mem_ptr[gid[e] + 1];
+    for (int32_t g = 0; g < ng; ++g) cg.mem_ptr[g + 1] += cg.mem_ptr[g];
+    cg.mem_elems.resize(cg.mem_ptr[ng]);
+    std::vector<int64_t> fill(cg.mem_ptr.begin(), cg.mem_ptr.end() - 1);
+    for (int64_t e = 0; e < ne; ++e)
+        if (gid[e] >= 0) cg.mem_elems[fill[gid[e]]++] = (int32_t)e;
     return cg;
 }
 

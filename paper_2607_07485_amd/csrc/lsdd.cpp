@@ -649,6 +649,7 @@ std::unique_ptr<Level> coarsen(lsdd_hierarchy* h, Level& lv, const int32_t* agg_
     } else {
         lv.colors = color_subdomains(n, C, lv.el, &lv.n_colors);
     }
+    vlog("level %d: colouring %.3f s", lv.level, now_s() - tc0);
     lv.smoother = P.smoother;
     const double tau_cut = P.tau_const * (double)C.max_mult;
     // tau_cut of every aggregate from the largest multiplicity of its own instance
@@ -692,6 +693,7 @@ std::unique_ptr<Level> coarsen(lsdd_hierarchy* h, Level& lv, const int32_t* agg_
             for (int64_t q = C.sub_ptr[i]; q < C.sub_ptr[i + 1]; ++q) loc[C.sub_dofs[q]] = -1;
         }
     }
+    vlog("level %d: closure positions %.3f s", lv.level, now_s() - tc0);
     // ---- device inputs
     int64_t* d_sub_ptr = ar.upload(C.sub_ptr, st);
     int32_t* d_sub_dofs = ar.upload(C.sub_dofs, st);
