@@ -1195,16 +1195,22 @@ std::unique_ptr<Level> coarsen(lsdd_hierarchy* h, Level& lv, const int32_t* agg_
     cv->blk_off.assign(ng + 1, 0);
     std::vector<int64_t> pm_off(G.mem_elems.size() + 1, 0), pm_zrow;
     std::vector<int32_t> pm_k, pm_col;
-    std::vector<int32_t> colof(n_agg, -1);
+    pm_zrow.reserve(lv.el.dofs.size());
+    pm_k.reserve(lv.el.dofs.size());
+    pm_col.reserve(lv.el.dofs.size());
+    std::vector<int32_t> colof(n_agg, -1), agg_of_c(nc);
+    for (int32_t a = 0; a < n_agg; ++a)
+        for (int64_t d = lv.coff[a]; d < lv.coff[a + 1]; ++d) agg_of_c[d] = a;
+    std::vector<int32_t> touched;
     for (int64_t g = 0; g < ng; ++g) {
         int64_t c = cv->el.ptr[g + 1] - cv->el.ptr[g];
         cv->blk_off[g + 1] = cv->blk_off[g] + c * c;
         // column offset of each aggregate inside the group support
         int64_t off = 0;
-        std::vector<int32_t> touched;
+        touched.clear();
         for (int64_t q = cv->el.ptr[g]; q < cv->el.ptr[g + 1];) {
             int32_t d = cv->el.dofs[q];
-            int32_t agg = (int32_t)(std::upper_bound(lv.coff.begin(), lv.coff.end(), (int64_t)d) - lv.coff.begin() - 1);
+            int32_t agg = agg_of_c[d];
             colof[agg] = (int32_t)off;
             touched.push_back(agg);
             off += lv.k[agg];
