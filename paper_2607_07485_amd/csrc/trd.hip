@@ -203,12 +203,13 @@ __global__ void __launch_bounds__(WG) k_trd_symv(LocalArgs A, const int32_t* big
             s3 += cp[i + 192] * s_v[i + 192];
         }
         for (; i < mm; i += 64) s0 += cp[i] * s_v[i];
-        double s = wave_sum((s0 + s1) + (s2 + s3));
-        if (l == 0) {
-            const int gi = j + 1 + c;
-            for (int q = 0; q < p; ++q) s -= m.V[gi + (int64_t)q * n] * zz[q] + m.W[gi + (int64_t)q * n] * zz[NB + q];
-            m.W[gi + (int64_t)p * n] = t * s;
-        }
+        // the panel's correction V (W^T v) + W (V^T v) of row gi, one term per lane
+        // (p <= NB < 64), folded into the same wave reduction
+        const int gi = j + 1 + c;
+        double corr = 0.0;
+        if (l < p) corr = m.V[gi + (int64_t)l * n] * zz[l] + m.W[gi + (int64_t)l * n] * zz[NB + l];
+        const double s = wave_sum(((s0 + s1) + (s2 + s3)) - corr);
+        if (l == 0) m.W[gi + (int64_t)p * n] = t * s;
     }
 }
 
