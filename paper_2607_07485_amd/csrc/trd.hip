@@ -313,8 +313,12 @@ __global__ void __launch_bounds__(WG) k_trd_invit(LocalArgs A, const int32_t* bi
 
 // Retained eigenvectors x <- Q x (Q = H_0 ... H_{n-3}) for the large
 // problems: one wave per vector (VS = W1, n x k, ld n), reflectors applied
-// from the last to the first.  Lane l owns the rows r = l (mod 64) of its
-// vector, so no lane reads another lane's writes.
+// from the last to the first, four per round: with the dots d_k = v_k^T x and
+// the cross products c_kl = v_k^T v_l of reflectors j, j-1, j-2, j-3 (k = 0..3)
+// gathered in one pass, s_k = tau_k (d_k - sum_{l<k} s_l c_kl) are the
+// multipliers of applying them one after the other, and x -= sum_k s_k v_k.
+// Lane l owns the rows r = l (mod 64) of its vector, so no lane reads another
+// lane's writes.
 __global__ void __launch_bounds__(WG) k_trd_backtransform(LocalArgs A, const int32_t* big) {
     const int b = big[blockIdx.y];
     const int ag = A.first + b;
@@ -326,7 +330,43 @@ __global__ void __launch_bounds__(WG) k_trd_backtransform(LocalArgs A, const int
     const double* a = A.s_buf + A.sq_off[b];
     const double* tau = A.t_buf + A.t_off[b] + 2 * n;
     double* x = A.w1 + A.ws_off[b] + (int64_t)c * n;
-    for (int j = n - 3; j >= 0; --j) {
+    // entry r of reflector jj: 1 at jj + 1, stored below it, 0 above
+    auto vr = [&](int jj, int r) { return r == jj + 1 ? 1.0 : (r > jj + 1 ? a[r + (int64_t)jj * n] : 0.0); };
+    int j = n - 3;
+    for (; j >= 3; j -= 4) {
+        const int r0 = j - 2 + ((l - (j - 2)) % 64 + 64) % 64;     // first owned row >= j - 2
+        double d[4] = {0.0, 0.0, 0.0, 0.0}, cc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+        for (int r = r0; r < n; r += 64) {
+            const double xr = x[r];
+            double v[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) v[k] = vr(j - k, r);
+#pragma unroll
+            for (int k = 0; k < 4; ++k) d[k] += v[k] * xr;
+            cc[0] += v[1] * v[0];
+            cc[1] += v[2] * v[0];
+            cc[2] += v[2] * v[1];
+            cc[3] += v[3] * v[0];
+            cc[4] += v[3] * v[1];
+            cc[5] += v[3] * v[2];
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) d[k] = wave_sum(d[k]);
+#pragma unroll
+        for (int q = 0; q < 6; ++q) cc[q] = wave_sum(cc[q]);
+        double sk[4];
+        sk[0] = tau[j] * d[0];
+        sk[1] = tau[j - 1] * (d[1] - sk[0] * cc[0]);
+        sk[2] = tau[j - 2] * (d[2] - sk[0] * cc[1] - sk[1] * cc[2]);
+        sk[3] = tau[j - 3] * (d[3] - sk[0] * cc[3] - sk[1] * cc[4] - sk[2] * cc[5]);
+        for (int r = r0; r < n; r += 64) {
+            double y = x[r];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) y -= sk[k] * vr(j - k, r);
+            x[r] = y;
+        }
+    }
+    for (; j >= 0; --j) {
         const double t = tau[j];
         if (t == 0.0) continue;
         const double* v = a + (int64_t)j * n;
