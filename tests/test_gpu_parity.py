@@ -203,6 +203,22 @@ def test_error_paths_on_device(dev):
         h.close()
 
 
+def test_size_limits_are_reported(dev):
+    """A caller cover with one aggregate of 4,802 DOFs (above the 4,096 the local
+    spectral problems take) is refused with LSDD_E_UNSUPPORTED and a message naming
+    the limit, before any local problem runs; the same mesh with its vertex-patch
+    cover builds."""
+    P = _lsdd()
+    prob = fegen.elasticity_q1(48, nu=0.3)
+    one = np.zeros(prob.n, np.int32)
+    with pytest.raises(P.LsddError) as ei:
+        P.Hierarchy.setup_elements(prob.n, prob.elem_ptr, prob.elem_dofs, prob.blocks, prob.node_of_dof, one,
+                                   P.Params.default(**ELAST_KW))
+    assert ei.value.code == 7 and "4096" in str(ei.value)
+    with P.Hierarchy.setup_problem(prob, P.Params.default(**ELAST_KW)) as h:
+        assert h.info()["levels"] == 2
+
+
 def test_setup_and_solve_are_bitwise_reproducible(dev):
     """Every reduction has a fixed order: two setups and solves give identical bits."""
     P = _lsdd()
