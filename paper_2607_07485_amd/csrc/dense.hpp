@@ -715,6 +715,13 @@ __device__ inline void wg_inverse_iteration_range(const double* d, const double*
     __syncthreads();
     const int ncl = *ncl_sh;
     const double tiny = eps * fmax(tnorm, 1e-300);
+    // convergence: from the second solve on, the iterate entering a solve has unit norm,
+    // so the norm of the result is the solve's growth 1 / |lambda - shift| along the
+    // eigenvector; once it exceeds 1 / (1e-10 ||T||) (shift within 1e-10 ||T|| of an
+    // eigenvalue, at least 1e-4 ||T|| from every other cluster) each further solve would
+    // shrink the error by at least 1e6, and the iteration stops (at most 4 solves)
+    const double grow2 = 1.0 / ((1e-10 * fmax(tnorm, 1e-300)) * (1e-10 * fmax(tnorm, 1e-300)));
+    __shared__ int s_conv;
     auto start_value = [&](int i, int k) {
         unsigned h = (unsigned)(k * 2654435761u) ^ (unsigned)(i * 40503u);
         return 1.0 + 0.25 * ((double)(h & 0xffff) / 65536.0 - 0.5);
@@ -739,8 +746,10 @@ __device__ inline void wg_inverse_iteration_range(const double* d, const double*
             slot_solve(tid(), y, 64, lam[i]);
             double nr = 0.0;
             for (int k = 0; k < n; ++k) nr += y[64 * k] * y[64 * k];
+            const bool conv = it >= 1 && nr >= grow2;
             nr = 1.0 / sqrt(nr);
             for (int k = 0; k < n; ++k) y[64 * k] *= nr;
+            if (conv) break;
         }
         double* out = V + (long long)i * n;
         for (int k = 0; k < n; ++k) out[k] = y[64 * k];
@@ -758,8 +767,17 @@ __device__ inline void wg_inverse_iteration_range(const double* d, const double*
             }
             __syncthreads();
             for (int it = 0; it < 4; ++it) {
-                if (tid() < bn)
-                    slot_solve(tid(), V + (long long)(b0 + tid()) * n, 1, lam[b0 + tid()] + (b0 + tid() - c0) * 2.0 * tiny);
+                if (tid() == 0) s_conv = 1;
+                __syncthreads();
+                if (tid() < bn) {
+                    double* y = V + (long long)(b0 + tid()) * n;
+                    slot_solve(tid(), y, 1, lam[b0 + tid()] + (b0 + tid() - c0) * 2.0 * tiny);
+                    if (it >= 1) {
+                        double nr = 0.0;
+                        for (int k = 0; k < n; ++k) nr += y[k] * y[k];
+                        if (!(nr >= grow2)) s_conv = 0;
+                    }
+                }
                 __syncthreads();
                 for (int pass = 0; pass < 2; ++pass) {
                     // against the earlier members of the cluster (in chunks of 64 members)
@@ -805,6 +823,9 @@ __device__ inline void wg_inverse_iteration_range(const double* d, const double*
                         __syncthreads();
                     }
                 }
+                const int conv = s_conv;
+                __syncthreads();                  // every thread has read the flag before it is reset
+                if (it >= 1 && conv) break;
             }
         }
     }
