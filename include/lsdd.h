@@ -215,14 +215,23 @@ lsdd_status lsdd_elem_bilinear_noalloc(int64_t n_elem, const int64_t* elem_ptr, 
                                        const double* blocks, const double* u, const double* v, int32_t nrhs,
                                        int64_t ld, double scale, double* out, void* hip_stream);
 
-/* Build a hierarchy from a black-box sparse Gram factor G (m x n, CSR, host),
- * the input of Sec. 2 (A = G^T G, m >= n, full column rank).  Each row of G is
- * its own cover member: row j contributes g_j g_j^T with support = its stored
- * pattern (all stored entries count as support, zero values included).
- * Rows with no stored entries are dropped (Sec. 2, after eq. row_multiplicity). */
+/* Build a hierarchy from a black-box sparse Gram factor G (m x n, CSR), the input
+ * of Sec. 2 (A = G^T G, m >= n, full column rank).  Each row of G is its own cover
+ * member: row j contributes g_j g_j^T with support = its stored pattern (all
+ * stored entries count as support, zero values included).  Rows with no stored
+ * entries are dropped (Sec. 2, after eq. row_multiplicity).
+ *   rowptr  int64[m + 1], rowptr[0] = 0, non-decreasing; col int32[rowptr[m]] in
+ *           [0, n); val float64[rowptr[m]]; a row holds at most 128 entries
+ *   mem_is_device  0: rowptr, col, val are host arrays; 1: device arrays (the
+ *           pattern is copied to the host once to build the cover; the values
+ *           stay on the device, where the element factors and blocks are formed)
+ *   node_of_dof, agg_of_dof  host, as in lsdd_setup_elements
+ * The caller keeps ownership of every array.  A column with no entry (A
+ * singular), a bad index or a non-finite value -> LSDD_E_INVAL; a row above 128
+ * entries -> LSDD_E_UNSUPPORTED. */
 lsdd_status lsdd_setup_gram_csr(int64_t m, int64_t n, const int64_t* rowptr, const int32_t* col,
                                 const double* val, const int32_t* node_of_dof,
-                                const int32_t* agg_of_dof, const lsdd_params* params,
+                                const int32_t* agg_of_dof, int mem_is_device, const lsdd_params* params,
                                 void* hip_stream, lsdd_hierarchy** out);
 
 /* Solve A x = b for nrhs right-hand sides with PCG (x0 = 0) preconditioned by

@@ -428,6 +428,24 @@ __global__ void k_gram_rows(int64_t n_elem, const int64_t* perm_off, const int64
     }
 }
 
+// Element e of a black-box Gram factor is one row g of G with s stored entries
+// (values at val + src_off[e]): G_e (s x s, row-major) holds g in its first row
+// and zeros below, and the element block is A_e = g^T g.
+__global__ void k_gram_csr_rows(int64_t n_elem, const int64_t* elem_ptr, const int64_t* src_off,
+                                const int64_t* blk_off, const double* val, double* G, double* blocks) {
+    for (int64_t e = blockIdx.x; e < n_elem; e += gridDim.x) {
+        const int s = (int)(elem_ptr[e + 1] - elem_ptr[e]);
+        const double* g = val + src_off[e];
+        double* ge = G + blk_off[e];
+        double* be = blocks + blk_off[e];
+        for (int idx = tid(); idx < s * s; idx += WG) {
+            const int u = idx / s, v = idx % s;
+            ge[idx] = u == 0 ? g[v] : 0.0;
+            be[idx] = g[u] * g[v];
+        }
+    }
+}
+
 // out[e] = u_e^T B_e v_e (B_e row-major n_e x n_e at blk_off[e]); one wave per
 // element: lane j sums u_i B_ij v_j over the rows i (coalesced row reads), then
 // a fixed-order wave reduction.
@@ -1296,6 +1314,13 @@ void launch_gram_rows(int64_t n_elem, const int64_t* perm_off, const int64_t* bl
     if (n_elem <= 0) return;
     hipLaunchKernelGGL(k_gram_rows, dim3((unsigned)std::min<int64_t>(n_elem, 65535 * 16)), dim3(WG), 0, st, n_elem,
                        perm_off, blk_off, L, perm, rank, G);
+}
+
+void launch_gram_csr_rows(int64_t n_elem, const int64_t* elem_ptr, const int64_t* src_off, const int64_t* blk_off,
+                          const double* val, double* G, double* blocks, hipStream_t st) {
+    if (n_elem <= 0) return;
+    hipLaunchKernelGGL(k_gram_csr_rows, dim3((unsigned)std::min<int64_t>(n_elem, 65535 * 16)), dim3(WG), 0, st, n_elem,
+                       elem_ptr, src_off, blk_off, val, G, blocks);
 }
 
 void launch_elem_bilinear(int64_t n_elem, const int64_t* elem_ptr, const int32_t* elem_dofs, const int64_t* blk_off,

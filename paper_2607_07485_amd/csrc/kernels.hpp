@@ -93,6 +93,10 @@ void launch_assemble_rows(int64_t n, const int64_t* d2e_ptr, const int32_t* d2e_
                           double* val, hipStream_t st, bool wave_rows = false);
 // factor[e] = theta[e] / theta0[e] (theta0 NULL: theta[e])
 void launch_theta_factor(int64_t n, const double* theta, const double* theta0, double* factor, hipStream_t st);
+// Black-box Gram factor rows as elements: G_e = [g; 0] and A_e = g^T g for the row g
+// of element e (values at val + src_off[e], elem_ptr giving its length).
+void launch_gram_csr_rows(int64_t n_elem, const int64_t* elem_ptr, const int64_t* src_off, const int64_t* blk_off,
+                          const double* val, double* G, double* blocks, hipStream_t st);
 // Gram rows G_e (row-major n_e x n_e at blk_off[e]) from pivoted Cholesky factors
 // in pivot order: G_e(k, perm[i]) = L_e(i, k) for k < rank[e], zero elsewhere.
 // perm_off: elem_ptr of the elements (perm of element e at perm_off[e] - perm_off[0]).

@@ -1894,9 +1894,18 @@ void autotune_levels(lsdd_hierarchy* h) {
 
 // ---------------------------------------------------------------- setup driver
 
-lsdd_hierarchy* build(ElemList el0, const double* blocks, bool blocks_on_device, const double* gram_rows, int64_t n,
-                      const int32_t* node_of_dof, const int32_t* agg_of_dof, const lsdd_params* prm, void* stream,
-                      std::vector<int64_t> inst_off = {}, const double* elem_scale = nullptr) {
+// Rows of a black-box CSR Gram factor as level-0 elements: element e is the row whose
+// values start at val + src_off[e] (val on the host or the device).
+struct GramCsrRows {
+    std::vector<int64_t> src_off;
+    const double* val = nullptr;
+    bool on_device = false;
+    int64_t nnz = 0;
+};
+
+lsdd_hierarchy* build(ElemList el0, const double* blocks, bool blocks_on_device, const GramCsrRows* gram_rows,
+                      int64_t n, const int32_t* node_of_dof, const int32_t* agg_of_dof, const lsdd_params* prm,
+                      void* stream, std::vector<int64_t> inst_off = {}, const double* elem_scale = nullptr) {
     auto h = std::make_unique<lsdd_hierarchy>();
     lsdd_params_default(&h->prm);
     if (prm) h->prm = *prm;
@@ -1938,8 +1947,9 @@ lsdd_hierarchy* build(ElemList el0, const double* blocks, bool blocks_on_device,
     Arena& ar = h->arena;
     upload_elements(h.get(), *lv);
     lv->d_blocks = ar.alloc<double>(lv->blk_off[ne]);
-    HIPCHK(hipMemcpyAsync(lv->d_blocks, blocks, lv->blk_off[ne] * sizeof(double),
-                          blocks_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, h->st));
+    if (!gram_rows)
+        HIPCHK(hipMemcpyAsync(lv->d_blocks, blocks, lv->blk_off[ne] * sizeof(double),
+                              blocks_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, h->st));
     if (elem_scale) {
         // A_e = theta_e A_e^(1): scale the blocks on the device, keep theta for lsdd_update_theta
         h->d_scale0 = ar.alloc<double>(ne);
@@ -1979,9 +1989,27 @@ lsdd_hierarchy* build(ElemList el0, const double* blocks, bool blocks_on_device,
         ar.release(d_ranks);
         ar.release(d_status);
     } else {
-        // CSR G input: the level-0 blocks are g g^T and the Gram row is the factor
+        // CSR G input: the Gram row is the element factor and the block is g^T g, both
+        // formed on the device from the row values
         lv->ranks.assign(ne, 1);
-        HIPCHK(hipMemcpyAsync(lv->d_G, gram_rows, lv->blk_off[ne] * sizeof(double), hipMemcpyHostToDevice, h->st));
+        int64_t* d_src = ar.upload(gram_rows->src_off, h->st);
+        const double* d_val = gram_rows->val;
+        double* d_copy = nullptr;
+        if (!gram_rows->on_device) {
+            d_copy = ar.alloc<double>(std::max<int64_t>(gram_rows->nnz, 1));
+            HIPCHK(hipMemcpyAsync(d_copy, gram_rows->val, gram_rows->nnz * sizeof(double), hipMemcpyHostToDevice,
+                                  h->st));
+            d_val = d_copy;
+        }
+        int32_t* d_fin = ar.alloc<int32_t>(1);
+        HIPCHK(hipMemsetAsync(d_fin, 0, sizeof(int32_t), h->st));
+        launch_check_finite(gram_rows->nnz, d_val, d_fin, h->st);
+        if (download(d_fin, 1, h->st)[0]) throw Error(LSDD_E_INVAL, "non-finite value in G");
+        launch_gram_csr_rows(ne, lv->d_elem_ptr, d_src, lv->d_blk_off, d_val, lv->d_G, lv->d_blocks, h->st);
+        HIPCHK(hipGetLastError());
+        sync(h->st);
+        for (void* q : {(void*)d_src, (void*)d_copy, (void*)d_fin})
+            if (q) ar.release(q);
     }
     const double tas = now_s();
     assemble_operator(h.get(), *lv);
@@ -2258,37 +2286,51 @@ lsdd_status lsdd_setup_batched(int32_t n_inst, const int64_t* inst_n, const int6
 }
 
 lsdd_status lsdd_setup_gram_csr(int64_t m, int64_t n, const int64_t* rowptr, const int32_t* col, const double* val,
-                                const int32_t* node_of_dof, const int32_t* agg_of_dof, const lsdd_params* params,
-                                void* hip_stream, lsdd_hierarchy** out) {
+                                const int32_t* node_of_dof, const int32_t* agg_of_dof, int mem_is_device,
+                                const lsdd_params* params, void* hip_stream, lsdd_hierarchy** out) {
     ABI_BEGIN
     if (!out) throw Error(LSDD_E_INVAL, "out is NULL");
     *out = nullptr;
     if (m < 1 || n < 1 || n >= (int64_t(1) << 31) || !rowptr || !col || !val) throw Error(LSDD_E_INVAL, "bad arguments");
+    // the integer structure is read on the host (copied back once for device input)
+    std::vector<int64_t> rp_h;
+    std::vector<int32_t> col_h;
+    const int64_t* rp = rowptr;
+    const int32_t* cl = col;
+    if (mem_is_device) {
+        rp_h.resize(m + 1);
+        HIPCHK(hipMemcpy(rp_h.data(), rowptr, (m + 1) * sizeof(int64_t), hipMemcpyDeviceToHost));
+        if (rp_h[0] != 0 || rp_h[m] < 0) throw Error(LSDD_E_INVAL, "rowptr must start at 0 and end at nnz >= 0");
+        col_h.resize(rp_h[m]);
+        if (rp_h[m] > 0)
+            HIPCHK(hipMemcpy(col_h.data(), col, rp_h[m] * sizeof(int32_t), hipMemcpyDeviceToHost));
+        rp = rp_h.data();
+        cl = col_h.data();
+    }
+    if (rp[0] != 0) throw Error(LSDD_E_INVAL, "rowptr must start at 0");
     ElemList el;
     el.ptr.assign(1, 0);
-    std::vector<double> blocks, grows;
+    GramCsrRows gr;
     std::vector<char> covered(n, 0);
     for (int64_t j = 0; j < m; ++j) {
-        int64_t a = rowptr[j], b = rowptr[j + 1];
+        int64_t a = rp[j], b = rp[j + 1];
         if (b < a) throw Error(LSDD_E_INVAL, "rowptr not monotone");
         if (b == a) continue;                               // zero rows are dropped
         if (b - a > 128) throw Error(LSDD_E_UNSUPPORTED, "a row of G has more than 128 entries");
         for (int64_t q = a; q < b; ++q) {
-            if (col[q] < 0 || col[q] >= n) throw Error(LSDD_E_INVAL, "column index out of range");
-            if (!std::isfinite(val[q])) throw Error(LSDD_E_INVAL, "non-finite value in G");
-            covered[col[q]] = 1;
-            el.dofs.push_back(col[q]);
+            if (cl[q] < 0 || cl[q] >= n) throw Error(LSDD_E_INVAL, "column index out of range");
+            covered[cl[q]] = 1;
+            el.dofs.push_back(cl[q]);
         }
-        const int64_t s = b - a;
-        for (int64_t u = 0; u < s; ++u)
-            for (int64_t v = 0; v < s; ++v) blocks.push_back(val[a + u] * val[a + v]);
-        for (int64_t u = 0; u < s; ++u)
-            for (int64_t v = 0; v < s; ++v) grows.push_back(u == 0 ? val[a + v] : 0.0);
+        gr.src_off.push_back(a);
         el.ptr.push_back((int64_t)el.dofs.size());
     }
     for (int64_t d = 0; d < n; ++d)
         if (!covered[d]) throw Error(LSDD_E_INVAL, "column " + std::to_string(d) + " of G is empty (A singular)");
-    *out = build(std::move(el), blocks.data(), false, grows.data(), n, node_of_dof, agg_of_dof, params, hip_stream);
+    gr.val = val;
+    gr.on_device = mem_is_device != 0;
+    gr.nnz = rp[m];
+    *out = build(std::move(el), nullptr, false, &gr, n, node_of_dof, agg_of_dof, params, hip_stream);
     return LSDD_OK;
     ABI_END
 }

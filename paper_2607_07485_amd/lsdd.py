@@ -67,7 +67,7 @@ def lib():
         L.lsdd_last_error.restype = C.c_char_p
         L.lsdd_setup_elements.argtypes = [C.c_int64, C.c_int64, i64p, i32p, _P, i32p, i32p, C.c_int,
                                           C.POINTER(Params), _P, C.POINTER(_P)]
-        L.lsdd_setup_gram_csr.argtypes = [C.c_int64, C.c_int64, i64p, i32p, f64p, i32p, i32p,
+        L.lsdd_setup_gram_csr.argtypes = [C.c_int64, C.c_int64, _P, _P, _P, i32p, i32p, C.c_int,
                                           C.POINTER(Params), _P, C.POINTER(_P)]
         L.lsdd_solve.argtypes = [_P, _P, _P, C.c_int32, _P, C.POINTER(Info)]
         L.lsdd_solve_stationary.argtypes = [_P, _P, _P, C.c_int32, _P, C.POINTER(Info)]
@@ -273,16 +273,28 @@ class Hierarchy:
 
     @classmethod
     def setup_gram_csr(cls, m, n, rowptr, col, val, node_of_dof=None, agg_of_dof=None, params=None):
-        rowptr = np.ascontiguousarray(rowptr, dtype=np.int64)
-        col = np.ascontiguousarray(col, dtype=np.int32)
-        val = np.ascontiguousarray(val, dtype=np.float64)
+        """lsdd_setup_gram_csr.  rowptr/col/val are either host arrays or contiguous
+        device tensors (int64, int32, float64), all three on the same side."""
+        import torch
+        dev = [isinstance(a, torch.Tensor) and a.is_cuda for a in (rowptr, col, val)]
+        if any(dev) and not all(dev):
+            raise TypeError("rowptr, col and val must all be host arrays or all device tensors")
+        keep = []
+        if all(dev):
+            for a, dt in ((rowptr, torch.int64), (col, torch.int32), (val, torch.float64)):
+                if a.dtype != dt or not a.is_contiguous():
+                    raise TypeError("device CSR arrays: contiguous int64 rowptr, int32 col, float64 val")
+            ptrs = [C.c_void_p(a.data_ptr()) for a in (rowptr, col, val)]
+        else:
+            keep = [np.ascontiguousarray(rowptr, dtype=np.int64), np.ascontiguousarray(col, dtype=np.int32),
+                    np.ascontiguousarray(val, dtype=np.float64)]
+            ptrs = [C.c_void_p(a.ctypes.data) for a in keep]
         nod = None if node_of_dof is None else np.ascontiguousarray(node_of_dof, dtype=np.int32)
         agg = None if agg_of_dof is None else np.ascontiguousarray(agg_of_dof, dtype=np.int32)
         params = params or Params.default()
         h = C.c_void_p()
-        _check(lib().lsdd_setup_gram_csr(int(m), int(n), _ptr(rowptr, C.c_int64), _ptr(col, C.c_int32),
-                                         _ptr(val, C.c_double), _ptr(nod, C.c_int32), _ptr(agg, C.c_int32),
-                                         C.byref(params), _stream(), C.byref(h)))
+        _check(lib().lsdd_setup_gram_csr(int(m), int(n), *ptrs, _ptr(nod, C.c_int32), _ptr(agg, C.c_int32),
+                                         int(all(dev)), C.byref(params), _stream(), C.byref(h)))
         return cls(h)
 
     # ---------------------------------------------------------------- solve

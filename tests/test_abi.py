@@ -81,6 +81,28 @@ def test_batched_setup_validates_instance_local_indices():
         P.Hierarchy.setup_batched([a, bad2])
 
 
+def test_gram_csr_setup_validates_the_pattern_on_the_host():
+    """Black-box CSR G: rowptr not starting at 0, a column index out of range, an
+    empty column (A singular) and a row above 128 entries are refused before any
+    device call."""
+    import paper_2607_07485_amd as P
+    n = 4
+    rp = np.array([0, 2, 4], np.int64)
+    col = np.array([0, 1, 2, 3], np.int32)
+    val = np.ones(4)
+    with pytest.raises(P.LsddError, match="start at 0"):
+        P.Hierarchy.setup_gram_csr(2, n, rp + 1, col, np.ones(5))
+    with pytest.raises(P.LsddError, match="out of range"):
+        P.Hierarchy.setup_gram_csr(2, n, rp, np.array([0, 1, 2, 9], np.int32), val)
+    with pytest.raises(P.LsddError, match="column 3 of G is empty") as ei:
+        P.Hierarchy.setup_gram_csr(2, n, np.array([0, 2, 3], np.int64), col[:3], val[:3])
+    assert ei.value.code == 1
+    with pytest.raises(P.LsddError, match="more than 128") as ei:
+        P.Hierarchy.setup_gram_csr(1, 129, np.array([0, 129], np.int64), np.arange(129, dtype=np.int32),
+                                   np.ones(129))
+    assert ei.value.code == 7
+
+
 def test_params_struct_layout_matches_the_header(tmp_path):
     """The binding's Params mirrors lsdd_params field by field (offsets and size)."""
     import ctypes

@@ -548,6 +548,37 @@ def test_black_box_csr_gram_factor_parity(dev):
         h.close()
 
 
+def test_black_box_csr_gram_factor_device_input(dev):
+    """The same CSR factor handed over as device arrays (mem_is_device = 1) builds the
+    identical hierarchy: level-0 Gram rows, operators and solve bit-for-bit equal."""
+    P = _lsdd()
+    prob, b = fegen.elasticity_small(N=8)
+    G0 = oracle.setup(prob, oracle.Params(max_levels=1)).G0
+    _, rp, col, val = _rows_problem(prob, G0)
+    kw = dict(max_levels=2, modes_fixed=4)
+    args = (prob.node_of_dof, prob.agg_of_dof, P.Params.default(**kw))
+    m = len(rp) - 1
+    dv = [torch.from_numpy(a).to(dev) for a in (rp, col, val)]
+    with P.Hierarchy.setup_gram_csr(m, prob.n, rp, col, val, *args) as hh, \
+            P.Hierarchy.setup_gram_csr(m, prob.n, *dv, *args) as hd:
+        assert hh.info()["n"] == hd.info()["n"]
+        for l in range(len(hh.info()["n"])):
+            eh, ed = hh.export_level(l), hd.export_level(l)
+            for key in eh:
+                assert np.array_equal(eh[key], ed[key]), (l, key)
+        gh, gd = hh.export_gram_level(0), hd.export_gram_level(0)
+        assert np.array_equal(gh["ranks"], gd["ranks"]) and np.array_equal(gh["G"], gd["G"])
+        assert (gh["ranks"] == 1).all()
+        bd = torch.from_numpy(b).to(dev)
+        xh, ih = hh.solve(bd)
+        xd, idd = hd.solve(bd)
+        assert ih[0].iters == idd[0].iters and torch.equal(xh, xd)
+    bad = dv[2].clone()
+    bad[3] = float("nan")
+    with pytest.raises(P.LsddError, match="non-finite"):
+        P.Hierarchy.setup_gram_csr(m, prob.n, dv[0], dv[1], bad, *args)
+
+
 @pytest.mark.parametrize("case", ["one_level", "no_modes"])
 def test_single_level_hierarchies(dev, case):
     """Degenerate hierarchies: max_levels = 1, and a cut so strict that no aggregate
