@@ -321,19 +321,28 @@ lsdd_status lsdd_level_segments(const lsdd_hierarchy* h, int32_t level, int64_t*
  * right-hand sides of one nonzero slot, or 32 or 64 lanes split over (slot,
  * right-hand side)), tiles per work item of the
  * tiled subdomain product of the large overlaps (2, 4 or 8) and threads per DOF of
- * its finalize (8 or 32).  block != 0 tunes the shapes of the 8-right-hand-side
- * blocks, 0 those of single vectors, for the current cycle precision.  The choice
- * changes only the summation order of the sums involved. */
+ * its finalize (8 or 32).  For single vectors on level 0 of a hierarchy built from
+ * element blocks (at most 128 DOFs each) it also times the full products A x (the
+ * residual before restriction and the PCG product) from the CSR against the
+ * element-batch form A x = sum_e R_e^T (A_e x_e) (Sec. 2) with the packed lower
+ * triangles of the A_e, built on the first call (one FP64 triangle per element, plus
+ * an FP32 copy when the hierarchy has an FP32 cycle), and keeps the faster.  block
+ * != 0 tunes the shapes of the 8-right-hand-side blocks, 0 those of single vectors,
+ * for the current cycle precision.  The choice changes only the summation order of
+ * the sums involved. */
 lsdd_status lsdd_autotune(lsdd_hierarchy* h, int32_t block, void* hip_stream);
 
-/* Launch shapes of level l (host int32[4]): CSR lanes per row for single vectors,
- * for blocks, tiles per work item, finalize threads per DOF. */
+/* Launch shapes of level l (host int32[5]): CSR lanes per row for single vectors,
+ * for blocks, tiles per work item, finalize threads per DOF, full products of single
+ * vectors from the element triangles (1) or the CSR (0). */
 lsdd_status lsdd_level_tuning(const lsdd_hierarchy* h, int32_t level, int32_t* out);
 
-/* Set the launch shapes of level l (host int32[4], the layout of lsdd_level_tuning),
+/* Set the launch shapes of level l (host int32[5], the layout of lsdd_level_tuning),
  * e.g. to restore what lsdd_autotune chose for another cycle precision.  Every value
  * must be one of the autotuner's candidates (else LSDD_E_INVAL, nothing changed);
- * tiles per work item is ignored on the coarsest level.  Captured PCG graphs are
+ * tiles per work item is ignored on the coarsest level; element products on a level
+ * other than 0, on a hierarchy without element blocks or with an element above 128
+ * DOFs -> LSDD_E_UNSUPPORTED (the triangles are built on first use).  Captured PCG graphs are
  * dropped and recaptured on the next solve.  Like lsdd_autotune, it changes only the
  * summation order of the sums involved. */
 lsdd_status lsdd_set_level_tuning(lsdd_hierarchy* h, int32_t level, const int32_t* in);
@@ -355,7 +364,8 @@ lsdd_status lsdd_trace_get(lsdd_hierarchy* h, int32_t idx, char* name, int32_t n
  *   r, z   device, float64[n] */
 lsdd_status lsdd_vcycle(lsdd_hierarchy* h, const double* r, double* z, void* hip_stream);
 
-/* y = A_l x on level l (A_0 = A, A_{l+1} = P_l^T A_l P_l).  x, y device float64[n_l]. */
+/* y = A_l x on level l (A_0 = A, A_{l+1} = P_l^T A_l P_l), from the CSR or, where the
+ * level's tuning selects them, the element triangles.  x, y device float64[n_l]. */
 lsdd_status lsdd_apply(lsdd_hierarchy* h, int32_t level, const double* x, double* y,
                        void* hip_stream);
 

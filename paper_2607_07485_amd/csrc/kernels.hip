@@ -807,6 +807,96 @@ __global__ void __launch_bounds__(WG) k_csr_spmv(int64_t n, const int64_t* rowpt
     }
 }
 
+// Element-batch operator apply (Sec. 2, A = sum_T R_T^T A_T R_T with A_T = G_T^T G_T):
+// ybuf[elem_ptr[e] + j] = (A_e x_e)_j from the packed lower triangle of A_e (row i
+// at tri_off[e] + i (i + 1) / 2, entries A_e(i, 0 .. i)).  S lanes per element
+// (S = 32: two elements per wave), C columns per lane (n_e <= S C).  Lane j forms
+// y_j = sum_{i >= j} A_e(i, j) x_i by streaming the triangle row by row (row i is
+// contiguous and read by lanes 0 .. i, coalesced), then adds sum_{k < j} A_e(j, k)
+// x_k from its own row, which the first pass has just brought into the caches.
+// Fixed order: ascending i, then ascending k.  Values of type V, vectors of type T
+// (FP64 entries with FP32 vectors: FP64 sums, ybuf in FP64).
+template <typename T, typename V, int S, int C>
+__global__ void __launch_bounds__(WG) k_elem_tri_apply(int64_t n_elem, const int64_t* elem_ptr,
+                                                       const int32_t* elem_dofs, const int64_t* tri_off,
+                                                       const V* tri, const T* x, V* ybuf) {
+    constexpr int SL = WG / S;
+    __shared__ V s_x[SL][S * C];
+    const int slot = tid() / S, lane = tid() % S;
+    for (int64_t e0 = (int64_t)blockIdx.x * SL; e0 < n_elem; e0 += (int64_t)gridDim.x * SL) {
+        const int64_t e = e0 + slot;
+        const bool on = e < n_elem;
+        const int64_t a0 = on ? elem_ptr[e] : 0;
+        const int n = on ? (int)(elem_ptr[e + 1] - a0) : 0;
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            const int j = lane + S * c;
+            if (j < n) s_x[slot][j] = (V)x[elem_dofs[a0 + j]];
+        }
+        __syncthreads();
+        V y[C];
+#pragma unroll
+        for (int c = 0; c < C; ++c) y[c] = 0;
+        if (on) {
+            const V* t0 = tri + tri_off[e];
+#pragma unroll 4
+            for (int i = 0; i < n; ++i) {
+                const V xi = s_x[slot][i];
+                const V* row = t0 + (int64_t)i * (i + 1) / 2;
+#pragma unroll
+                for (int c = 0; c < C; ++c) {
+                    const int j = lane + S * c;
+                    if (j <= i) y[c] += row[j] * xi;
+                }
+            }
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+                const int j = lane + S * c;
+                if (j < n) {
+                    const V* row = t0 + (int64_t)j * (j + 1) / 2;
+                    V u = y[c];
+                    for (int k = 0; k < j; ++k) u += row[k] * s_x[slot][k];
+                    ybuf[a0 + j] = u;
+                }
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// y[d] = sum over the elements holding DOF d (ascending) of their ybuf entries, or
+// r_minus[d] minus that sum.
+template <typename T, typename V>
+__global__ void k_elem_gather(int64_t n, const int64_t* d2e_ptr, const int32_t* e2y, const V* ybuf,
+                              const T* r_minus, T* y) {
+    for (int64_t d = blockIdx.x * (int64_t)WG + tid(); d < n; d += (int64_t)gridDim.x * WG) {
+        const int64_t q0 = d2e_ptr[d], q1 = d2e_ptr[d + 1];
+        V s = 0;
+        for (int64_t q = q0; q < q1; ++q) s += ybuf[e2y[q]];
+        y[d] = r_minus ? (T)((V)r_minus[d] - s) : (T)s;
+    }
+}
+
+// Packed lower triangles of factor[e] * A_e (factor NULL: 1) from the row-major
+// blocks, in FP64 and (tri32 != NULL) FP32.
+__global__ void k_pack_elem_tri(int64_t n_elem, const int64_t* elem_ptr, const int64_t* blk_off, const double* blocks,
+                                const double* factor, const int64_t* tri_off, double* tri, float* tri32) {
+    for (int64_t e = blockIdx.x; e < n_elem; e += gridDim.x) {
+        const int n = (int)(elem_ptr[e + 1] - elem_ptr[e]);
+        const double f = factor ? factor[e] : 1.0;
+        const double* B = blocks + blk_off[e];
+        for (int idx = tid(); idx < n * (n + 1) / 2; idx += WG) {
+            int i = (int)((sqrt(8.0 * idx + 1.0) - 1.0) * 0.5);
+            while (i * (i + 1) / 2 > idx) --i;
+            while ((i + 1) * (i + 2) / 2 <= idx) ++i;
+            const int j = idx - i * (i + 1) / 2;
+            const double v = f * B[(int64_t)i * n + j];
+            tri[tri_off[e] + idx] = v;
+            if (tri32) tri32[tri_off[e] + idx] = (float)v;
+        }
+    }
+}
+
 // Subdomain correction with the packed symmetric inverse: A_Omega^{-1} is stored
 // as its lower 64 x 64 tiles (tile (I, J), I >= J, row-major inside the tile,
 // zero-padded past |Omega|; the diagonal tiles hold both triangles, of which
@@ -1321,6 +1411,42 @@ void launch_gram_csr_rows(int64_t n_elem, const int64_t* elem_ptr, const int64_t
     if (n_elem <= 0) return;
     hipLaunchKernelGGL(k_gram_csr_rows, dim3((unsigned)std::min<int64_t>(n_elem, 65535 * 16)), dim3(WG), 0, st, n_elem,
                        elem_ptr, src_off, blk_off, val, G, blocks);
+}
+
+template <typename T, typename V>
+void launch_elem_apply(int64_t n_elem, const int64_t* elem_ptr, const int32_t* elem_dofs, const int64_t* tri_off,
+                       const V* tri, int n_max, const T* x, V* ybuf, int64_t n, const int64_t* d2e_ptr,
+                       const int32_t* e2y, const T* r_minus, T* y, hipStream_t st) {
+    if (n_elem > 0) {
+        if (n_max <= 32)
+            hipLaunchKernelGGL((k_elem_tri_apply<T, V, 32, 1>), dim3(grid_for(n_elem, WG / 32)), dim3(WG), 0, st,
+                               n_elem, elem_ptr, elem_dofs, tri_off, tri, x, ybuf);
+        else if (n_max <= 64)
+            hipLaunchKernelGGL((k_elem_tri_apply<T, V, 64, 1>), dim3(grid_for(n_elem, WG / 64)), dim3(WG), 0, st,
+                               n_elem, elem_ptr, elem_dofs, tri_off, tri, x, ybuf);
+        else
+            hipLaunchKernelGGL((k_elem_tri_apply<T, V, 64, 2>), dim3(grid_for(n_elem, WG / 64)), dim3(WG), 0, st,
+                               n_elem, elem_ptr, elem_dofs, tri_off, tri, x, ybuf);
+    }
+    if (n > 0)
+        hipLaunchKernelGGL((k_elem_gather<T, V>), dim3(grid_for(n)), dim3(WG), 0, st, n, d2e_ptr, e2y, ybuf, r_minus,
+                           y);
+}
+template void launch_elem_apply<double, double>(int64_t, const int64_t*, const int32_t*, const int64_t*,
+                                                const double*, int, const double*, double*, int64_t, const int64_t*,
+                                                const int32_t*, const double*, double*, hipStream_t);
+template void launch_elem_apply<float, float>(int64_t, const int64_t*, const int32_t*, const int64_t*, const float*,
+                                              int, const float*, float*, int64_t, const int64_t*, const int32_t*,
+                                              const float*, float*, hipStream_t);
+template void launch_elem_apply<float, double>(int64_t, const int64_t*, const int32_t*, const int64_t*,
+                                               const double*, int, const float*, double*, int64_t, const int64_t*,
+                                               const int32_t*, const float*, float*, hipStream_t);
+
+void launch_pack_elem_tri(int64_t n_elem, const int64_t* elem_ptr, const int64_t* blk_off, const double* blocks,
+                          const double* factor, const int64_t* tri_off, double* tri, float* tri32, hipStream_t st) {
+    if (n_elem <= 0) return;
+    hipLaunchKernelGGL(k_pack_elem_tri, dim3((unsigned)std::min<int64_t>(n_elem, 65535 * 16)), dim3(WG), 0, st,
+                       n_elem, elem_ptr, blk_off, blocks, factor, tri_off, tri, tri32);
 }
 
 void launch_elem_bilinear(int64_t n_elem, const int64_t* elem_ptr, const int32_t* elem_dofs, const int64_t* blk_off,

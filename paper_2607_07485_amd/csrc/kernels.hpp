@@ -93,6 +93,18 @@ void launch_assemble_rows(int64_t n, const int64_t* d2e_ptr, const int32_t* d2e_
                           double* val, hipStream_t st, bool wave_rows = false);
 // factor[e] = theta[e] / theta0[e] (theta0 NULL: theta[e])
 void launch_theta_factor(int64_t n, const double* theta, const double* theta0, double* factor, hipStream_t st);
+// Element-batch operator apply: y = A x (r_minus NULL) or y = r_minus - A x with
+// A = sum_e R_e^T A_e R_e from the packed lower triangles of the A_e (tri at
+// tri_off[e]; n_max the largest element, <= 128), through a per-element buffer ybuf
+// (one entry per elem_dofs entry) summed per DOF in ascending element order
+// (d2e_ptr over the DOFs, e2y the elem_dofs position of each (DOF, element) pair).
+template <typename T, typename V>
+void launch_elem_apply(int64_t n_elem, const int64_t* elem_ptr, const int32_t* elem_dofs, const int64_t* tri_off,
+                       const V* tri, int n_max, const T* x, V* ybuf, int64_t n, const int64_t* d2e_ptr,
+                       const int32_t* e2y, const T* r_minus, T* y, hipStream_t st);
+// packed lower triangles of factor[e] * A_e (factor NULL: 1), FP64 and optionally FP32
+void launch_pack_elem_tri(int64_t n_elem, const int64_t* elem_ptr, const int64_t* blk_off, const double* blocks,
+                          const double* factor, const int64_t* tri_off, double* tri, float* tri32, hipStream_t st);
 // Black-box Gram factor rows as elements: G_e = [g; 0] and A_e = g^T g for the row g
 // of element e (values at val + src_off[e], elem_ptr giving its length).
 void launch_gram_csr_rows(int64_t n_elem, const int64_t* elem_ptr, const int64_t* src_off, const int64_t* blk_off,

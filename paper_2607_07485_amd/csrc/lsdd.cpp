@@ -163,6 +163,17 @@ struct Level {
     int64_t* d_d2e_ptr = nullptr;     // level 0: DOF -> (element, local index), kept for re-assembly
     int32_t* d_d2e_elem = nullptr;
     int32_t* d_d2e_loc = nullptr;
+    // level 0: element-batch operator apply from the packed lower triangles of the
+    // element blocks (built when the autotuner first times it)
+    double* d_etri = nullptr;
+    float* d_etri32 = nullptr;
+    int64_t* d_etri_off = nullptr;
+    int32_t* d_e2y = nullptr;         // per (DOF, element) pair: its elem_dofs position
+    double* d_ebuf = nullptr;         // per elem_dofs entry: (A_e x_e)_j
+    float* d_ebuf32 = nullptr;
+    int64_t etri_len = 0;
+    int e_nmax = 0;
+    int eapply = 0;                   // 1: full products of the level from the element triangles
     float* d_val32 = nullptr;
     // level-0 Gram factors
     double* d_G = nullptr;
@@ -408,6 +419,63 @@ void assemble_operator(lsdd_hierarchy* h, Level& lv) {
         lv.d_val32 = h->arena.alloc<float>(lv.nnz);
         launch_to_f32(lv.nnz, lv.d_val, lv.d_val32, h->st);
     }
+}
+
+// Element-batch apply of level 0 (packed lower triangles of factor[e] A_e, factor =
+// the theta update's ratio when one was applied).  Returns false where the level
+// has no element blocks or an element above 128 DOFs.
+bool build_elem_apply(lsdd_hierarchy* h, Level& lv);
+
+void pack_elem_tri(lsdd_hierarchy* h, Level& lv) {
+    launch_pack_elem_tri(lv.el.count(), lv.d_elem_ptr, lv.d_blk_off, lv.d_blocks, h->d_factor, lv.d_etri_off,
+                         lv.d_etri, lv.d_etri32, h->st);
+}
+
+bool build_elem_apply(lsdd_hierarchy* h, Level& lv) {
+    if (lv.d_etri) return true;
+    if (lv.level != 0 || !lv.d_d2e_ptr || !lv.d_blocks) return false;
+    const int64_t ne = lv.el.count();
+    int64_t n_max = 0;
+    std::vector<int64_t> toff(ne + 1, 0);
+    for (int64_t e = 0; e < ne; ++e) {
+        const int64_t m = lv.el.ptr[e + 1] - lv.el.ptr[e];
+        n_max = std::max(n_max, m);
+        toff[e + 1] = toff[e] + m * (m + 1) / 2;
+    }
+    if (n_max > 128 || n_max < 1) return false;
+    // (DOF, element) pairs in DOF order, elements ascending: their elem_dofs positions
+    std::vector<int64_t> dptr(lv.n + 1, 0);
+    for (int32_t d : lv.el.dofs) dptr[d + 1]++;
+    for (int64_t i = 0; i < lv.n; ++i) dptr[i + 1] += dptr[i];
+    std::vector<int32_t> e2y(lv.el.dofs.size());
+    std::vector<int64_t> fill(dptr.begin(), dptr.end() - 1);
+    for (int64_t q = 0; q < (int64_t)lv.el.dofs.size(); ++q) e2y[fill[lv.el.dofs[q]]++] = (int32_t)q;
+    Arena& ar = h->arena;
+    lv.e_nmax = (int)n_max;
+    lv.etri_len = toff[ne];
+    lv.d_etri_off = ar.upload(toff, h->st);
+    lv.d_e2y = ar.upload(e2y, h->st);
+    lv.d_etri = ar.alloc<double>(lv.etri_len);
+    lv.d_ebuf = ar.alloc<double>(std::max<int64_t>((int64_t)lv.el.dofs.size(), 1));
+    if (h->prm.precision >= 1) {
+        lv.d_etri32 = ar.alloc<float>(lv.etri_len);
+        lv.d_ebuf32 = ar.alloc<float>(std::max<int64_t>((int64_t)lv.el.dofs.size(), 1));
+    }
+    pack_elem_tri(h, lv);
+    HIPCHK(hipGetLastError());
+    sync(h->st);
+    vlog("level %d: element triangles, %lld entries (CSR %lld)", lv.level, (long long)lv.etri_len,
+         (long long)lv.nnz);
+    return true;
+}
+
+// algorithmic bytes of one full product y = A x (or r - A x): CSR rows, or element
+// triangles + per-element buffer + per-DOF sums
+double full_apply_bytes(const Level& lv, double wval, double wvec, bool r_minus) {
+    const double nv = r_minus ? 3.0 : 2.0;
+    if (!lv.eapply) return (double)lv.nnz * (4 + wval) + (double)lv.n * (8 + nv * wvec);
+    const double nd = (double)lv.el.dofs.size();
+    return (double)lv.etri_len * wval + nd * (4 + 8 + wvec + 2 * wval) + (double)lv.n * (8 + (nv - 1) * wvec);
 }
 
 // Cycle vectors of one level: set b = 0 holds single vectors, b = 1 blocks of
@@ -1352,6 +1420,8 @@ struct LvOps<double> {
     static const double* Z(Level& l) { return l.d_Zc; }
     static const double* inv(Level& l) { return l.d_tiles; }
     static const double* pk(Level& l) { return l.d_pk; }
+    static const double* etri(Level& l) { return l.d_etri; }
+    static double* ebuf(Level& l) { return l.d_ebuf; }
 };
 template <>
 struct LvOps<float> {
@@ -1360,6 +1430,8 @@ struct LvOps<float> {
     static const float* Z(Level& l) { return l.d_Zc32; }
     static const float* inv(Level& l) { return l.d_tiles32; }
     static const float* pk(Level& l) { return l.d_pk32; }
+    static const float* etri(Level& l) { return l.d_etri32; }
+    static float* ebuf(Level& l) { return l.d_ebuf32; }
 };
 
 // Cycle kernels for NR = 1 (single vectors) or NR = NRB (interleaved blocks).
@@ -1370,9 +1442,19 @@ struct Cyc {
         if constexpr (NR == 1) launch_csr_resid_rows<T>(nrows, rows, lv.d_rowptr, lv.d_col, val, x, r, out, xz, lv.lanes, st);
         else launch_csr_resid_rows_b<T>(nrows, rows, lv.d_rowptr, lv.d_col, val, x, r, out, xz, lv.lanes_b, st);
     }
+    // y = A x or r_minus - A x with the level's entries of type T (val), or from its
+    // element triangles of the same precision when the autotuner chose them
     static void spmv(Level& lv, const T* val, const T* x, T* y, const T* r_minus, hipStream_t st) {
-        if constexpr (NR == 1) launch_csr_spmv<T>(lv.n, lv.d_rowptr, lv.d_col, val, x, y, r_minus, lv.lanes, st);
-        else launch_csr_spmv_b<T>(lv.n, lv.d_rowptr, lv.d_col, val, x, y, r_minus, lv.lanes_b, st);
+        if constexpr (NR == 1) {
+            if (lv.eapply && LvOps<T>::etri(lv)) {
+                launch_elem_apply<T, T>(lv.el.count(), lv.d_elem_ptr, lv.d_elem_dofs, lv.d_etri_off, LvOps<T>::etri(lv),
+                                        lv.e_nmax, x, LvOps<T>::ebuf(lv), lv.n, lv.d_d2e_ptr, lv.d_e2y, r_minus, y, st);
+                return;
+            }
+            launch_csr_spmv<T>(lv.n, lv.d_rowptr, lv.d_col, val, x, y, r_minus, lv.lanes, st);
+        } else {
+            launch_csr_spmv_b<T>(lv.n, lv.d_rowptr, lv.d_col, val, x, y, r_minus, lv.lanes_b, st);
+        }
     }
     static void symv(int64_t n_items, const int32_t* items, const int64_t* sub_off, const int64_t* tp_off,
                      const T* tiles, const T* rloc, const int64_t* scr_off, T* scr, int chl, hipStream_t st) {
@@ -1600,13 +1682,18 @@ void vcycle(lsdd_hierarchy* h, size_t l, const T* r, T* x) {
     if constexpr (std::is_same<T, float>::value && NR == 1) {
         if (h->cycle_prec == 2) {
             mixed = true;
-            traced(h, "csr_spmv", (double)lv.nnz * (4 + 8.0) + (double)lv.n * (8 + 3 * wv), [&] {
-                launch_csr_spmv<float, double>(lv.n, lv.d_rowptr, lv.d_col, lv.d_val, x, v.t, r, lv.lanes, h->st);
+            traced(h, "csr_spmv", full_apply_bytes(lv, 8.0, wv, true), [&] {
+                if (lv.eapply && lv.d_etri)
+                    launch_elem_apply<float, double>(lv.el.count(), lv.d_elem_ptr, lv.d_elem_dofs, lv.d_etri_off,
+                                                     lv.d_etri, lv.e_nmax, x, lv.d_ebuf, lv.n, lv.d_d2e_ptr, lv.d_e2y,
+                                                     r, v.t, h->st);
+                else
+                    launch_csr_spmv<float, double>(lv.n, lv.d_rowptr, lv.d_col, lv.d_val, x, v.t, r, lv.lanes, h->st);
             });
         }
     }
     if (!mixed)
-        traced(h, "csr_spmv", (double)lv.nnz * (4 + w) + (double)lv.n * (8 + 3 * wv),
+        traced(h, "csr_spmv", NR == 1 ? full_apply_bytes(lv, w, wv, true) : (double)lv.nnz * (4 + w) + (double)lv.n * (8 + 3 * wv),
                [&] { C::spmv(lv, O::val(lv), x, v.t, r, h->st); });
     const double zb = (double)lv.zoff.back() * w + (double)lv.n * (4 + wv) + (double)nx.n * wv;
     traced(h, "restrict", zb, [&] { C::restrict_(lv, O::Z(lv), v.t, vn.r, h->st); });
@@ -1715,7 +1802,7 @@ bool pcg_run(lsdd_hierarchy* h) {
     launch_copy(n * NR, B.z, B.p, st);
     launch_seg_dot(T, NR, B.r, B.z, nullptr, nullptr, h->part, rz, nullptr, st);
     auto half_a = [&] {
-        traced(h, "pcg_spmv", (double)l0.nnz * 12.0 + (double)n * 8.0 * (1 + 2 * NR),
+        traced(h, "pcg_spmv", NR == 1 ? full_apply_bytes(l0, 8.0, 8.0, false) : (double)l0.nnz * 12.0 + (double)n * 8.0 * (1 + 2 * NR),
                [&] { Cyc<double, NR>::spmv(l0, l0.d_val, B.p, B.q, nullptr, st); });
         launch_seg_dot(T, NR, B.p, B.q, nullptr, nullptr, h->part, pq, nullptr, st);
         launch_pcg_alpha(ns, act, rz, pq, alpha, itf + 1, st);
@@ -1859,6 +1946,18 @@ void autotune_levels(lsdd_hierarchy* h) {
             if (ms < best) best = ms, pick = L;
         }
         lanes = pick;
+        if (NR == 1 && build_elem_apply(h, lv)) {
+            // the full product (pre-restriction residual, PCG) from the CSR or the element triangles
+            best = 1e300;
+            int pick_e = 0;
+            for (int ea : {0, 1}) {
+                lv.eapply = ea;
+                const double ms = time_ms(h, [&] { C::spmv(lv, O::val(lv), v.x, v.t, v.r, h->st); });
+                vlog("autotune level %d: full product from %s: %.3f ms", lv.level, ea ? "element triangles" : "CSR", ms);
+                if (ms < best) best = ms, pick_e = ea;
+            }
+            lv.eapply = pick_e;
+        }
         if (lv.color_item0.back() == 0) continue;   // no large overlap on this level
         auto run_large = [&] {
             for (int32_t c = 0; c < lv.n_colors; ++c) {
@@ -2182,6 +2281,7 @@ lsdd_status lsdd_update_theta(lsdd_hierarchy* h, const double* theta, void* hip_
     launch_assemble_rows(l0.n, l0.d_d2e_ptr, l0.d_d2e_elem, l0.d_d2e_loc, l0.d_elem_ptr, l0.d_elem_dofs, l0.d_blk_off,
                          l0.d_blocks, h->d_factor, l0.d_rowptr, l0.d_col, l0.d_val, h->st);
     if (l0.d_val32) launch_to_f32(l0.nnz, l0.d_val, l0.d_val32, h->st);
+    if (l0.d_etri) pack_elem_tri(h, l0);
     HIPCHK(hipGetLastError());
     sync(h->st);
     return LSDD_OK;
@@ -2391,7 +2491,7 @@ lsdd_status lsdd_apply(lsdd_hierarchy* h, int32_t level, const double* x, double
     if (!h || !x || !y || level < 0 || level >= (int32_t)h->L.size()) throw Error(LSDD_E_INVAL, "bad argument");
     h->st = (hipStream_t)hip_stream;
     Level& lv = *h->L[level];
-    launch_csr_spmv<double>(lv.n, lv.d_rowptr, lv.d_col, lv.d_val, x, y, nullptr, lv.lanes, h->st);
+    Cyc<double, 1>::spmv(lv, lv.d_val, x, y, nullptr, h->st);
     HIPCHK(hipGetLastError());
     sync(h->st);
     return LSDD_OK;
@@ -2509,7 +2609,7 @@ lsdd_status lsdd_solve_stationary(lsdd_hierarchy* h, const double* b, double* x,
         f.setup_s = h->setup_s;
         // r = b - A x and its norm
         auto resid = [&] {
-            traced(h, "pcg_spmv", (double)l0.nnz * 12.0 + (double)n * 8.0 * 3,
+            traced(h, "pcg_spmv", full_apply_bytes(l0, 8.0, 8.0, true),
                    [&] { Cyc<double, 1>::spmv(l0, l0.d_val, xk, B.r, bk, st); });
             launch_seg_dot(h->seg, 1, B.r, B.r, nullptr, nullptr, h->part, rr, nullptr, st);
             const double v = std::sqrt(download(rr, 1, st)[0]);
@@ -2632,9 +2732,13 @@ lsdd_status lsdd_set_level_tuning(lsdd_hierarchy* h, int32_t level, const int32_
         return std::find(ok.begin(), ok.end(), v) != ok.end();
     };
     if (!one_of(in[0], {8, 16, 32, 64}) || !one_of(in[1], {4, 8, 16, 32, 64}) || !one_of(in[2], {2, 4, 8}) ||
-        !one_of(in[3], {8, 32}))
+        !one_of(in[3], {8, 32}) || !one_of(in[4], {0, 1}))
         throw Error(LSDD_E_INVAL, "launch shape outside the autotuner's candidates");
     Level& lv = *h->L[level];
+    if (in[4] && !build_elem_apply(h, lv))
+        throw Error(LSDD_E_UNSUPPORTED, "element apply: only on level 0 of a hierarchy built from element blocks "
+                                        "of at most 128 DOFs");
+    lv.eapply = in[4];
     lv.lanes = in[0];
     lv.lanes_b = in[1];
     lv.fl = in[3];
@@ -2655,6 +2759,7 @@ lsdd_status lsdd_level_tuning(const lsdd_hierarchy* h, int32_t level, int32_t* o
     out[1] = lv.lanes_b;
     out[2] = lv.chl;
     out[3] = lv.fl;
+    out[4] = lv.eapply;
     return LSDD_OK;
     ABI_END
 }

@@ -190,6 +190,7 @@ def test_autotuned_shapes_keep_parity(dev):
         for t in t1 + t8:
             assert t["lanes"] in (8, 16, 32, 64) and t["lanes_block"] in (4, 8, 16, 32, 64)
             assert t["tiles_per_item"] in (2, 4, 8) and t["finalize_threads"] in (8, 32)
+            assert t["elem_apply"] in (0, 1)
         x, inf = h.solve(torch.from_numpy(b).to(dev))
         x_or, inf_or = oracle.pcg(h_or, b)
         assert abs(inf[0].iters - inf_or.iters) <= 1
@@ -214,26 +215,93 @@ def test_set_level_tuning_round_trip_and_checks(dev):
     with P.Hierarchy.setup_problem(prob, P.Params.default(**GD_KW)) as h:
         tuned = h.autotune(block=False)
         other = [dict(lanes=8 if t["lanes"] != 8 else 32, lanes_block=4, tiles_per_item=2 if t["tiles_per_item"] != 2 else 8,
-                      finalize_threads=32 if t["finalize_threads"] == 8 else 8) for t in tuned]
+                      finalize_threads=32 if t["finalize_threads"] == 8 else 8,
+                      elem_apply=(1 - t["elem_apply"]) if l == 0 else 0) for l, t in enumerate(tuned)]
         h.set_tuning(other)
         levels = len(tuned)
         for l in range(levels):
             got = h.level_tuning(l)
             assert got["lanes"] == other[l]["lanes"] and got["finalize_threads"] == other[l]["finalize_threads"]
+            assert got["elem_apply"] == other[l]["elem_apply"]
             if l < levels - 1:
                 assert got["tiles_per_item"] == other[l]["tiles_per_item"]
         x, inf = h.solve(torch.from_numpy(b).to(dev))
         assert abs(inf[0].iters - inf_or.iters) <= 1
         assert np.linalg.norm(x.cpu().numpy() - x_or) <= 1e-10 * np.linalg.norm(x_or)
         before = h.level_tuning(0)
-        for bad in (dict(before, lanes=12), dict(before, tiles_per_item=3), dict(before, finalize_threads=16)):
+        for bad in (dict(before, lanes=12), dict(before, tiles_per_item=3), dict(before, finalize_threads=16),
+                    dict(before, elem_apply=2)):
             with pytest.raises(P.LsddError) as ei:
                 h.set_level_tuning(0, bad)
             assert ei.value.code == 1
         assert h.level_tuning(0) == before
+        with pytest.raises(P.LsddError) as ei:                # element products exist on level 0 only
+            h.set_level_tuning(1, dict(h.level_tuning(1), elem_apply=1))
+        assert ei.value.code == 7
         h.set_tuning(tuned)
         x2, _ = h.solve(torch.from_numpy(b).to(dev))
         assert np.linalg.norm(x2.cpu().numpy() - x_or) <= 1e-10 * np.linalg.norm(x_or)
+
+
+@pytest.mark.parametrize("case", ["graddiv", "elasticity_q2hex"])
+def test_element_triangle_products_match_the_csr_products(dev, case):
+    """Full products of level 0 from the packed element triangles (elem_apply = 1):
+    A x agrees with the CSR product to the rounding bound of the two summation orders
+    (both sum the same products: 2 k u sum |A||x| per entry, k the longest CSR row plus
+    the largest element), also after lsdd_update_theta; the FP64 PCG solve matches the
+    oracle (1e-10, iterations +-1), and the FP32 and mixed cycles reach the tolerance
+    in the CSR path's iteration count +-1."""
+    P = _lsdd()
+    rng = np.random.default_rng(17)
+    if case == "graddiv":
+        prob, _ = _graddiv(seed=9)
+        kw = GD_KW
+    else:
+        prob = fegen.elasticity_q2hex(3, nu=0.3)
+        kw = dict(max_levels=3, agg_passes=1, agg_passes_coarse=1, tau_const=0.75)
+    theta = np.ones(prob.n_elem)
+    with P.Hierarchy.setup_elements_scaled(prob.n, prob.elem_ptr, prob.elem_dofs, prob.blocks, theta,
+                                           prob.node_of_dof, prob.agg_of_dof,
+                                           P.Params.default(precision=2, **kw)) as h:
+        t0 = h.level_tuning(0)
+        x = torch.from_numpy(rng.standard_normal(prob.n)).to(dev)
+        offs = prob.block_offsets()
+        dofs = [prob.elem_dofs[prob.elem_ptr[e]:prob.elem_ptr[e + 1]] for e in range(prob.n_elem)]
+        absA = oracle.assemble(prob.n, dofs, [np.abs(prob.blocks[offs[e]:offs[e + 1]]).reshape(len(S), len(S))
+                                              for e, S in enumerate(dofs)])
+        k = int(np.diff(absA.indptr).max()) + max(len(S) for S in dofs)
+
+        def products(th):
+            ys = []
+            for ea in (0, 1):
+                h.set_level_tuning(0, dict(t0, elem_apply=ea))
+                ys.append(h.apply(x, level=0).cpu().numpy())
+            bound = 2 * k * np.finfo(float).eps * (absA @ np.abs(x.cpu().numpy())) * th.max()
+            assert (np.abs(ys[0] - ys[1]) <= bound).all()
+            assert np.abs(ys[0] - ys[1]).max() > 0                 # the element path is taken
+
+        products(theta)
+        theta2 = np.exp(0.3 * rng.standard_normal(prob.n_elem))
+        h.update_theta(torch.from_numpy(theta2).to(dev))
+        products(theta2)
+        h.update_theta(torch.from_numpy(theta).to(dev))
+        b = rng.standard_normal(prob.n)
+        h_or = oracle.setup(prob, oracle.Params(**kw))
+        x_or, inf_or = oracle.pcg(h_or, b)
+        bd = torch.from_numpy(b).to(dev)
+        its = {}
+        for ea in (0, 1):
+            h.set_level_tuning(0, dict(t0, elem_apply=ea))
+            for prec in (0, 1, 2):
+                h.set_cycle_precision(prec)
+                xs, inf = h.solve(bd)
+                assert inf[0].converged == 1
+                its[ea, prec] = inf[0].iters
+                if prec == 0:
+                    assert abs(inf[0].iters - inf_or.iters) <= 1
+                    assert np.linalg.norm(xs.cpu().numpy() - x_or) <= 1e-10 * np.linalg.norm(x_or)
+        for prec in (0, 1, 2):
+            assert abs(its[1, prec] - its[0, prec]) <= 1, its
 
 
 def test_solve_batched_over_separate_hierarchies(dev):
