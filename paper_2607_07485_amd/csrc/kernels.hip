@@ -838,15 +838,28 @@ __global__ void __launch_bounds__(WG) k_elem_tri_apply(int64_t n_elem, const int
 #pragma unroll
         for (int c = 0; c < C; ++c) y[c] = 0;
         if (on) {
+            // eight rows (pass 1) or entries (pass 2) per step, all loads issued before
+            // the first use: the indices are clamped into the triangle instead of the
+            // loads being conditional, and the clamped slots contribute nothing
             const V* t0 = tri + tri_off[e];
-#pragma unroll 4
-            for (int i = 0; i < n; ++i) {
-                const V xi = s_x[slot][i];
-                const V* row = t0 + (int64_t)i * (i + 1) / 2;
+            for (int i0 = 0; i0 < n; i0 += 8) {
+                V a[8][C];
 #pragma unroll
-                for (int c = 0; c < C; ++c) {
-                    const int j = lane + S * c;
-                    if (j <= i) y[c] += row[j] * xi;
+                for (int q = 0; q < 8; ++q) {
+                    const int i = min(i0 + q, n - 1);
+                    const V* row = t0 + (int64_t)i * (i + 1) / 2;
+#pragma unroll
+                    for (int c = 0; c < C; ++c) a[q][c] = row[min(lane + S * c, i)];
+                }
+#pragma unroll
+                for (int q = 0; q < 8; ++q) {
+                    const int i = i0 + q;
+                    if (i < n) {
+                        const V xi = s_x[slot][i];
+#pragma unroll
+                        for (int c = 0; c < C; ++c)
+                            if (lane + S * c <= i) y[c] += a[q][c] * xi;
+                    }
                 }
             }
 #pragma unroll
@@ -855,7 +868,14 @@ __global__ void __launch_bounds__(WG) k_elem_tri_apply(int64_t n_elem, const int
                 if (j < n) {
                     const V* row = t0 + (int64_t)j * (j + 1) / 2;
                     V u = y[c];
-                    for (int k = 0; k < j; ++k) u += row[k] * s_x[slot][k];
+                    for (int k0 = 0; k0 < j; k0 += 8) {
+                        V a[8];
+#pragma unroll
+                        for (int q = 0; q < 8; ++q) a[q] = row[min(k0 + q, j - 1)];
+#pragma unroll
+                        for (int q = 0; q < 8; ++q)
+                            if (k0 + q < j) u += a[q] * s_x[slot][k0 + q];
+                    }
                     ybuf[a0 + j] = u;
                 }
             }
