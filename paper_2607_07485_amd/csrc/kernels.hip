@@ -1164,6 +1164,42 @@ __global__ void __launch_bounds__(WG) k_sub_finalize(int64_t r0, int64_t r1, con
     }
 }
 
+// k_sub_finalize with the scratch addresses of every overlap entry precomputed
+// (tab[t] = {row-part address of its first chunk, column-part address of tile row
+// J's entry minus the tile-row offset, J, nch | nt << 16}, in scratch entries): the
+// partial sums are one dependent load away from the table instead of three (entry ->
+// subdomain -> offsets -> partials).  Same sums in the same order, accumulating.
+template <typename T, int FL>
+__global__ void __launch_bounds__(WG) k_sub_finalize_tab(int64_t r0, int64_t r1, const int4* tab, const T* scr,
+                                                         const int32_t* sub_dofs, T* x) {
+    constexpr int ND = WG / FL;
+    __shared__ T s_y[FL][ND];
+    const int dl = tid() % ND, j = tid() / ND;
+    const int64_t t = r0 + (int64_t)blockIdx.x * ND + dl;
+    T y = 0;
+    if (t < r1) {
+        const int4 e = tab[t];
+        const T* part = scr + (uint32_t)e.x;
+        const T* colpart = scr + (uint32_t)e.y;
+        const int J = e.z, nch = e.w & 0xffff, nt = e.w >> 16;
+        const int K = nch + (nt - 1 - J);
+#pragma unroll 4
+        for (int k = j; k < K; k += FL) {
+            const int64_t I = J + 1 + (k - nch);
+            y += *(k < nch ? part + (int64_t)k * 64 : colpart + I * (I - 1) / 2 * 64);
+        }
+    }
+    s_y[j][dl] = y;
+    __syncthreads();
+    if (j == 0 && t < r1) {
+        T v = s_y[0][dl];
+#pragma unroll
+        for (int q = 1; q < FL; ++q) v += s_y[q][dl];
+        const int32_t d = sub_dofs[t];   // < 0: masked entry
+        if (d >= 0) x[d] = x[d] + v;
+    }
+}
+
 // Pack full m x m symmetric inverses (aggregate order, column-major) into the
 // tiled lower storage of k_sub_symv (FP64 and, optionally, FP32).
 __global__ void k_pack_tiles(const int64_t* sub_ptr, const int64_t* inv_off, const double* inv, const int64_t* tp_off,
@@ -1630,6 +1666,23 @@ void launch_sub_finalize(int64_t r0, int64_t r1, const int32_t* pos_sub, const i
         hipLaunchKernelGGL((k_sub_finalize<T, 8>), dim3(grid_for(r1 - r0, WG / 8)), dim3(WG), 0, st, r0, r1,
                            pos_sub, sub_off, scr_off, scr, sub_dofs, x, acc, chl);
 }
+
+template <typename T>
+void launch_sub_finalize_tab(int64_t r0, int64_t r1, const int32_t* tab, const T* scr, const int32_t* sub_dofs, T* x,
+                             int fl, hipStream_t st) {
+    if (r1 <= r0) return;
+    const int4* tb = reinterpret_cast<const int4*>(tab);
+    if (fl >= 32)
+        hipLaunchKernelGGL((k_sub_finalize_tab<T, 32>), dim3(grid_for(r1 - r0, WG / 32)), dim3(WG), 0, st, r0, r1, tb,
+                           scr, sub_dofs, x);
+    else
+        hipLaunchKernelGGL((k_sub_finalize_tab<T, 8>), dim3(grid_for(r1 - r0, WG / 8)), dim3(WG), 0, st, r0, r1, tb,
+                           scr, sub_dofs, x);
+}
+template void launch_sub_finalize_tab<double>(int64_t, int64_t, const int32_t*, const double*, const int32_t*, double*,
+                                              int, hipStream_t);
+template void launch_sub_finalize_tab<float>(int64_t, int64_t, const int32_t*, const float*, const int32_t*, float*,
+                                             int, hipStream_t);
 
 void launch_sub_fact(int64_t n_items, const int32_t* items, const int64_t* sub_off, const int64_t* tp_off,
                      const float* tiles, const float* rloc, const int64_t* scr_off, float* scr, int chl,

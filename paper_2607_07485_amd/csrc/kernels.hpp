@@ -190,6 +190,11 @@ template <typename T>
 void launch_sub_finalize(int64_t r0, int64_t r1, const int32_t* pos_sub, const int64_t* sub_off,
                          const int64_t* scr_off, const T* scr, const int32_t* sub_dofs, T* x, bool accumulate,
                          int chl, int fl, hipStream_t st);
+// the same (accumulating) from a table of 4 int32 per entry t (16-byte aligned):
+// {row-part address of chunk 0, scr_off + rowpart_off(nt) * 64 + J * 64 + l, J, nch | nt << 16}
+template <typename T>
+void launch_sub_finalize_tab(int64_t r0, int64_t r1, const int32_t* tab, const T* scr, const int32_t* sub_dofs, T* x,
+                             int fl, hipStream_t st);
 // mixed cycle: y = X^T (X r) with FP32 factor tiles in one pass, FP64 sums; items =
 // (subdomain, whole tile row) pairs; partials in the layout of launch_sub_symv for chl
 void launch_sub_fact(int64_t n_items, const int32_t* items, const int64_t* sub_off, const int64_t* tp_off,

@@ -228,6 +228,7 @@ struct Level {
     std::vector<int64_t> color_ritem0;
     int32_t* d_pos_sub = nullptr;     // sweep-order subdomain of every Omega entry
     int64_t* d_scr_off = nullptr;     // per subdomain: offset of its partial-sum scratch
+    int32_t* d_fin_tab = nullptr;     // per overlap entry: its partial-sum addresses (4 int32)
     // coarsest level as one packed symmetric "subdomain"
     // terminal blocks: the instances whose hierarchy ends on this level (every
     // instance present on the coarsest level), each solved with its dense inverse
@@ -476,6 +477,41 @@ double full_apply_bytes(const Level& lv, double wval, double wvec, bool r_minus)
     if (!lv.eapply) return (double)lv.nnz * (4 + wval) + (double)lv.n * (8 + nv * wvec);
     const double nd = (double)lv.el.dofs.size();
     return (double)lv.etri_len * wval + nd * (4 + 8 + wvec + 2 * wval) + (double)lv.n * (8 + (nv - 1) * wvec);
+}
+
+// Finalize table of the large overlaps (launch_sub_finalize_tab): per sweep entry the
+// scratch addresses of its partial sums for the level's chunk length.  Not built when
+// the scratch exceeds int32 offsets (the finalize then looks the addresses up).
+void build_fin_tab(lsdd_hierarchy* h, Level& lv, const std::vector<int64_t>& scr_off) {
+    Arena& ar = h->arena;
+    if (lv.d_fin_tab) {
+        ar.release(lv.d_fin_tab);
+        lv.d_fin_tab = nullptr;
+    }
+    const int32_t n_sub = (int32_t)lv.sw_sub_off.size() - 1;
+    if (n_sub < 1 || scr_off[n_sub] >= (int64_t(1) << 31)) return;
+    const int64_t rows = lv.sw_sub_off[n_sub];
+    std::vector<int32_t> tab(4 * std::max<int64_t>(rows, 1), 0);
+    for (int32_t q = 0; q < n_sub; ++q) {
+        const int64_t o = lv.sw_sub_off[q], m = lv.sw_sub_off[q + 1] - o;
+        if (m <= SMALL_M) continue;
+        const int nt = (int)((m + 63) / 64);
+        for (int64_t c = 0; c < m; ++c) {
+            const int J = (int)(c >> 6), l = (int)(c & 63);
+            int32_t* e = &tab[4 * (o + c)];
+            e[0] = (int32_t)(scr_off[q] + symv_rowpart_off(J, lv.chl) * 64 + l);
+            e[1] = (int32_t)(scr_off[q] + symv_rowpart_off(nt, lv.chl) * 64 + (int64_t)J * 64 + l);
+            e[2] = J;
+            e[3] = (J / lv.chl + 1) | (nt << 16);
+        }
+    }
+    int32_t* d = ar.upload(tab, h->st);
+    sync(h->st);
+    if (reinterpret_cast<uintptr_t>(d) % 16 != 0) {   // a caller allocator without 16-byte alignment
+        ar.release(d);
+        return;
+    }
+    lv.d_fin_tab = d;
 }
 
 // Cycle vectors of one level: set b = 0 holds single vectors, b = 1 blocks of
@@ -1197,6 +1233,7 @@ std::unique_ptr<Level> coarsen(lsdd_hierarchy* h, Level& lv, const int32_t* agg_
         lv.d_pos_sub = ar.upload(pos_sub, st);
         lv.d_scr_off = ar.upload(scr_off, st);
         lv.scr_len = scr_off[n_agg];
+        build_fin_tab(h, lv, scr_off);
         lv.color_scr.assign(lv.n_colors, 0.0);
         for (int32_t q = 0; q < n_agg; ++q) lv.color_scr[lv.colors[lv.sweep[q]]] += (double)(scr_off[q + 1] - scr_off[q]);
     }
@@ -1466,6 +1503,15 @@ struct Cyc {
         if constexpr (NR == 1) launch_sub_finalize<T>(r0, r1, pos, sub_off, scr_off, scr, dofs, x, acc, chl, fl, st);
         else launch_sub_finalize_b<T>(r0, r1, pos, sub_off, scr_off, scr, dofs, x, acc, chl, fl, st);
     }
+    // x += the large-overlap corrections of colour c of a sweep (scatter list dofs)
+    static void finalize_colour(Level& lv, int32_t c, const T* scr, const int32_t* dofs, T* x, hipStream_t st) {
+        const int64_t r0 = lv.color_row0[c], rm = lv.color_rmid[c];
+        if (NR == 1 && lv.d_fin_tab) {
+            if constexpr (NR == 1) launch_sub_finalize_tab<T>(r0, rm, lv.d_fin_tab, scr, dofs, x, lv.fl, st);
+            return;
+        }
+        finalize(r0, rm, lv.d_pos_sub, lv.d_sw_sub_off, lv.d_scr_off, scr, dofs, x, true, lv.chl, lv.fl, st);
+    }
     static void small(Level& lv, int64_t s0, int64_t n_sub, const T* pk, const T* rloc, T* x, const int32_t* dofs,
                       hipStream_t st) {
         launch_small_sub<T, NR>(s0, n_sub, lv.d_sw_sub_off, dofs, lv.d_sw_pk_off, pk, rloc, x, lv.small_m, st);
@@ -1528,8 +1574,7 @@ void sweep_ras(lsdd_hierarchy* h, Level& lv, const T* r, T* x, bool post, bool x
             });
             const double fb = lv.color_scr[c] * wv + (double)(rm - r0) * (8 + 2 * wv);
             traced(h, "sub_finalize", fb, [&] {
-                C::finalize(r0, rm, lv.d_pos_sub, lv.d_sw_sub_off, lv.d_scr_off, v.scr, scatter, x, true, lv.chl,
-                            lv.fl, h->st);
+                C::finalize_colour(lv, c, v.scr, scatter, x, h->st);
             });
         }
         if (ns > 0) {
@@ -1568,8 +1613,7 @@ void sweep_factor(lsdd_hierarchy* h, Level& lv, const float* r, float* x, bool f
                                 v.rloc, lv.d_scr_off, v.scr, lv.chl, h->st);
             });
             traced(h, "sub_finalize", lv.color_scr[c] * 4.0 + (double)(rm - r0) * 16.0, [&] {
-                launch_sub_finalize<float>(r0, rm, lv.d_pos_sub, lv.d_sw_sub_off, lv.d_scr_off, v.scr,
-                                           lv.d_sw_sub_dofs, x, true, lv.chl, lv.fl, h->st);
+                Cyc<float, 1>::finalize_colour(lv, c, v.scr, lv.d_sw_sub_dofs, x, h->st);
             });
         }
         if (ns > 0) {
@@ -1617,8 +1661,7 @@ void sweep(lsdd_hierarchy* h, Level& lv, const T* r, T* x, bool forward, bool x_
             });
             const double fb = lv.color_scr[c] * wv + (double)(rm - r0) * (8 + 2 * wv);
             traced(h, "sub_finalize", fb, [&] {
-                C::finalize(r0, rm, lv.d_pos_sub, lv.d_sw_sub_off, lv.d_scr_off, v.scr, lv.d_sw_sub_dofs, x, true,
-                            lv.chl, lv.fl, h->st);
+                C::finalize_colour(lv, c, v.scr, lv.d_sw_sub_dofs, x, h->st);
             });
         }
         if (ns > 0) {
@@ -1892,6 +1935,7 @@ void set_chunk(lsdd_hierarchy* h, Level& lv, int chl) {
         }
     }
     lv.scr_len = scr_off[n_sub];
+    build_fin_tab(h, lv, scr_off);
     sync(h->st);
 }
 
@@ -1965,8 +2009,7 @@ void autotune_levels(lsdd_hierarchy* h) {
                 if (i1 == i0) continue;
                 C::symv(i1 - i0, lv.d_items + 3 * i0, lv.d_sw_sub_off, lv.d_sw_tp_off, O::inv(lv), v.rloc,
                         lv.d_scr_off, v.scr, lv.chl, h->st);
-                C::finalize(lv.color_row0[c], lv.color_rmid[c], lv.d_pos_sub, lv.d_sw_sub_off, lv.d_scr_off, v.scr,
-                            lv.d_sw_sub_dofs, v.x, true, lv.chl, lv.fl, h->st);
+                C::finalize_colour(lv, c, v.scr, lv.d_sw_sub_dofs, v.x, h->st);
             }
         };
         best = 1e300;
