@@ -738,10 +738,15 @@ __global__ void k_to_f64(int64_t n, const float* a, double* b) {
 // streams (values, column indices) are read non-temporally, the gathered x
 // through the caches.  Values of type V (FP64 values with FP32 vectors: the
 // products and the sum are formed in FP64 and rounded once).
+//
+// scoff != NULL: the rows of a supernode share one column list (coarse levels,
+// whose DOFs come in contiguous per-aggregate groups): row p's columns are
+// col[scoff[p] ..] (read through the caches, reused by the supernode's other
+// rows) and only the values stream, 8 bytes per entry instead of 12.
 template <typename T, typename V, int L>
 __global__ void __launch_bounds__(WG) k_csr_resid_rows(int64_t nrows, const int32_t* rows, const int64_t* rowptr,
                                                        const int32_t* col, const V* val, const T* x, const T* r,
-                                                       T* out, int x_zero) {
+                                                       T* out, int x_zero, const int64_t* scoff) {
     const int lane = tid() & (L - 1);
     const int64_t stride = (int64_t)gridDim.x * (WG / L);
     for (int64_t t = ((int64_t)blockIdx.x * WG + tid()) / L; t < nrows; t += stride) {
@@ -753,15 +758,16 @@ __global__ void __launch_bounds__(WG) k_csr_resid_rows(int64_t nrows, const int3
             // loads carry no lane condition (a slot past the row's end re-reads its
             // last entry, same cache line, and contributes zero), so they are all
             // issued before the first wait.
-            const int64_t q1 = rowptr[p + 1], qlast = q1 - 1;
-            for (int64_t q0 = rowptr[p] + lane; q0 < q1; q0 += 4 * L) {
+            const int64_t qb = rowptr[p], q1 = rowptr[p + 1], qlast = q1 - 1;
+            const int64_t cb = scoff ? scoff[p] - qb : 0;
+            for (int64_t q0 = qb + lane; q0 < q1; q0 += 4 * L) {
                 int32_t c[4];
                 V v[4];
                 T xv[4];
 #pragma unroll
                 for (int u = 0; u < 4; ++u) {
                     const int64_t q = min(q0 + u * L, qlast);
-                    c[u] = __builtin_nontemporal_load(col + q);
+                    c[u] = scoff ? col[cb + q] : __builtin_nontemporal_load(col + q);
                     v[u] = __builtin_nontemporal_load(val + q);
                 }
 #pragma unroll
@@ -779,22 +785,24 @@ __global__ void __launch_bounds__(WG) k_csr_resid_rows(int64_t nrows, const int3
 // k_csr_resid_rows)
 template <typename T, typename V, int L>
 __global__ void __launch_bounds__(WG) k_csr_spmv(int64_t n, const int64_t* rowptr, const int32_t* col, const V* val,
-                                                 const T* x, T* y, const T* r_minus) {
+                                                 const T* x, T* y, const T* r_minus, const int64_t* scoff) {
     const int lane = tid() & (L - 1);
     const int64_t stride = (int64_t)gridDim.x * (WG / L);
     for (int64_t p = ((int64_t)blockIdx.x * WG + tid()) / L; p < n; p += stride) {
         // as in k_csr_resid_rows: 4 entries per lane in flight, loads without lane
-        // conditions (slots past the row's end re-read its last entry and add zero)
-        const int64_t q1 = rowptr[p + 1], qlast = q1 - 1;
+        // conditions (slots past the row's end re-read its last entry and add zero);
+        // scoff != NULL: per-supernode column lists
+        const int64_t qb = rowptr[p], q1 = rowptr[p + 1], qlast = q1 - 1;
+        const int64_t cb = scoff ? scoff[p] - qb : 0;
         V s = 0;
-        for (int64_t q0 = rowptr[p] + lane; q0 < q1; q0 += 4 * L) {
+        for (int64_t q0 = qb + lane; q0 < q1; q0 += 4 * L) {
             int32_t c[4];
             V v[4];
             T xv[4];
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
                 const int64_t q = min(q0 + u * L, qlast);
-                c[u] = __builtin_nontemporal_load(col + q);
+                c[u] = scoff ? col[cb + q] : __builtin_nontemporal_load(col + q);
                 v[u] = __builtin_nontemporal_load(val + q);
             }
 #pragma unroll
@@ -1608,38 +1616,39 @@ void launch_to_f64(int64_t n, const float* a, double* b, hipStream_t st) {
 
 template <typename T, typename V>
 void launch_csr_resid_rows(int64_t nrows, const int32_t* rows, const int64_t* rowptr, const int32_t* col, const V* val,
-                           const T* x, const T* r, T* out, bool x_zero, int lanes, hipStream_t st) {
+                           const T* x, const T* r, T* out, bool x_zero, int lanes, hipStream_t st,
+                           const int64_t* scoff) {
     if (nrows <= 0) return;
     const int xz = x_zero ? 1 : 0;
     if (lanes >= 64)
         hipLaunchKernelGGL((k_csr_resid_rows<T, V, 64>), dim3(grid_for(nrows * 64)), dim3(WG), 0, st, nrows, rows,
-                           rowptr, col, val, x, r, out, xz);
+                           rowptr, col, val, x, r, out, xz, scoff);
     else if (lanes >= 32)
         hipLaunchKernelGGL((k_csr_resid_rows<T, V, 32>), dim3(grid_for(nrows * 32)), dim3(WG), 0, st, nrows, rows,
-                           rowptr, col, val, x, r, out, xz);
+                           rowptr, col, val, x, r, out, xz, scoff);
     else if (lanes >= 16)
         hipLaunchKernelGGL((k_csr_resid_rows<T, V, 16>), dim3(grid_for(nrows * 16)), dim3(WG), 0, st, nrows, rows,
-                           rowptr, col, val, x, r, out, xz);
+                           rowptr, col, val, x, r, out, xz, scoff);
     else
         hipLaunchKernelGGL((k_csr_resid_rows<T, V, 8>), dim3(grid_for(nrows * 8)), dim3(WG), 0, st, nrows, rows,
-                           rowptr, col, val, x, r, out, xz);
+                           rowptr, col, val, x, r, out, xz, scoff);
 }
 template <typename T, typename V>
 void launch_csr_spmv(int64_t n, const int64_t* rowptr, const int32_t* col, const V* val, const T* x, T* y,
-                     const T* r_minus, int lanes, hipStream_t st) {
+                     const T* r_minus, int lanes, hipStream_t st, const int64_t* scoff) {
     if (n <= 0) return;
     if (lanes >= 64)
         hipLaunchKernelGGL((k_csr_spmv<T, V, 64>), dim3(grid_for(n * 64)), dim3(WG), 0, st, n, rowptr, col, val, x, y,
-                           r_minus);
+                           r_minus, scoff);
     else if (lanes >= 32)
         hipLaunchKernelGGL((k_csr_spmv<T, V, 32>), dim3(grid_for(n * 32)), dim3(WG), 0, st, n, rowptr, col, val, x, y,
-                           r_minus);
+                           r_minus, scoff);
     else if (lanes >= 16)
         hipLaunchKernelGGL((k_csr_spmv<T, V, 16>), dim3(grid_for(n * 16)), dim3(WG), 0, st, n, rowptr, col, val, x, y,
-                           r_minus);
+                           r_minus, scoff);
     else
         hipLaunchKernelGGL((k_csr_spmv<T, V, 8>), dim3(grid_for(n * 8)), dim3(WG), 0, st, n, rowptr, col, val, x, y,
-                           r_minus);
+                           r_minus, scoff);
 }
 template <typename T>
 void launch_sub_symv(int64_t n_items, const int32_t* items, const int64_t* sub_off, const int64_t* tp_off,
@@ -1772,9 +1781,9 @@ void launch_check_finite(int64_t n, const double* a, int32_t* flag, hipStream_t 
 
 #define LSDD_INST(T)                                                                                                  \
     template void launch_csr_resid_rows<T, T>(int64_t, const int32_t*, const int64_t*, const int32_t*, const T*,     \
-                                              const T*, const T*, T*, bool, int, hipStream_t);                        \
+                                              const T*, const T*, T*, bool, int, hipStream_t, const int64_t*);        \
     template void launch_csr_spmv<T, T>(int64_t, const int64_t*, const int32_t*, const T*, const T*, T*, const T*,    \
-                                        int, hipStream_t);                                                            \
+                                        int, hipStream_t, const int64_t*);                                            \
     template void launch_sub_symv<T>(int64_t, const int32_t*, const int64_t*, const int64_t*, const T*, const T*,    \
                                      const int64_t*, T*, int, hipStream_t);                                           \
     template void launch_sub_finalize<T>(int64_t, int64_t, const int32_t*, const int64_t*, const int64_t*, const T*, \
@@ -1788,8 +1797,8 @@ LSDD_INST(double)
 LSDD_INST(float)
 template void launch_csr_resid_rows<float, double>(int64_t, const int32_t*, const int64_t*, const int32_t*,
                                                    const double*, const float*, const float*, float*, bool, int,
-                                                   hipStream_t);
+                                                   hipStream_t, const int64_t*);
 template void launch_csr_spmv<float, double>(int64_t, const int64_t*, const int32_t*, const double*, const float*,
-                                             float*, const float*, int, hipStream_t);
+                                             float*, const float*, int, hipStream_t, const int64_t*);
 
 }  // namespace lsdd

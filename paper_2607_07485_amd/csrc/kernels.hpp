@@ -174,12 +174,15 @@ void launch_to_f64(int64_t n, const float* a, double* b, hipStream_t st);
 // ---------------------------------------------------------------- solve
 // lanes per row: 8, 16, 32 or 64.  V: value type (T, or double with T = float:
 // FP64 operator entries applied to FP32 vectors with FP64 sums)
+// scoff != NULL: col holds one column list per supernode and row p's list starts at
+// col[scoff[p]] (rows of a supernode share their columns); else the CSR's own col
 template <typename T, typename V = T>
 void launch_csr_resid_rows(int64_t nrows, const int32_t* rows, const int64_t* rowptr, const int32_t* col,
-                           const V* val, const T* x, const T* r, T* out, bool x_zero, int lanes, hipStream_t st);
+                           const V* val, const T* x, const T* r, T* out, bool x_zero, int lanes, hipStream_t st,
+                           const int64_t* scoff = nullptr);
 template <typename T, typename V = T>
 void launch_csr_spmv(int64_t n, const int64_t* rowptr, const int32_t* col, const V* val, const T* x, T* y,
-                     const T* r_minus, int lanes, hipStream_t st);
+                     const T* r_minus, int lanes, hipStream_t st, const int64_t* scoff = nullptr);
 // chl: tiles per work item (1..8); the scratch layout depends on it
 template <typename T>
 void launch_sub_symv(int64_t n_items, const int32_t* items, const int64_t* sub_off, const int64_t* tp_off,

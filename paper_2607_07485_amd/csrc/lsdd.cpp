@@ -174,6 +174,11 @@ struct Level {
     int64_t etri_len = 0;
     int e_nmax = 0;
     int eapply = 0;                   // 1: full products of the level from the element triangles
+    // supernode-blocked pattern: the rows of a supernode share one column list
+    int32_t* d_scol = nullptr;        // the lists, one per supernode
+    int64_t* d_scoff = nullptr;       // per row: start of its supernode's list
+    double sup_ib = 4.0;              // column-index bytes per entry read from HBM with the lists
+    int sup = 0;                      // 1: single-vector CSR kernels read the shared lists
     float* d_val32 = nullptr;
     // level-0 Gram factors
     double* d_G = nullptr;
@@ -373,11 +378,39 @@ void upload_elements(lsdd_hierarchy* h, Level& lv) {
     lv.d_blk_off = h->arena.upload(lv.blk_off, h->st);
 }
 
+// Shared column lists of a supernode-blocked pattern (every row of a supernode has
+// the same columns): one list per supernode and, per row, where its list starts.
+// Kept only where the lists are at most half the column indices.
+void build_supernode_cols(lsdd_hierarchy* h, Level& lv) {
+    std::vector<int64_t> soff(lv.n_super + 1, -1), scoff(lv.n);
+    std::vector<int32_t> scol;
+    int32_t prev = -1;
+    for (int64_t d = 0; d < lv.n; ++d) {
+        const int32_t sn = lv.node_of_dof[d];
+        const int64_t a = lv.pat.ptr[d], len = lv.pat.ptr[d + 1] - a;
+        if (sn != prev) {
+            soff[sn] = (int64_t)scol.size();
+            scol.insert(scol.end(), lv.pat.idx.begin() + a, lv.pat.idx.begin() + a + len);
+            prev = sn;
+        } else {
+            const int64_t b = lv.pat.ptr[d - 1], lb = a - b;
+            if (lb != len || !std::equal(lv.pat.idx.begin() + a, lv.pat.idx.begin() + a + len, lv.pat.idx.begin() + b))
+                return;                       // not a shared pattern after all
+        }
+        scoff[d] = soff[sn];
+    }
+    if (2 * (int64_t)scol.size() > lv.nnz) return;
+    lv.d_scol = h->arena.upload(scol, h->st);
+    lv.d_scoff = h->arena.upload(scoff, h->st);
+    lv.sup_ib = 4.0 * (double)scol.size() / (double)std::max<int64_t>(lv.nnz, 1);
+    sync(h->st);
+}
+
 void assemble_operator(lsdd_hierarchy* h, Level& lv) {
     // element supports made of whole supernodes with contiguous DOF ranges (the
     // coarse levels always): the pattern is built on supernodes
-    if (!assembled_pattern_blocked(lv.n, lv.el, lv.node_of_dof, lv.n_super, lv.pat))
-        lv.pat = assembled_pattern(lv.n, lv.el);
+    const bool blocked = assembled_pattern_blocked(lv.n, lv.el, lv.node_of_dof, lv.n_super, lv.pat);
+    if (!blocked) lv.pat = assembled_pattern(lv.n, lv.el);
     lv.nnz = (int64_t)lv.pat.idx.size();
     lv.lanes = (lv.nnz > 96 * lv.n) ? 64 : 16;
     lv.lanes_b = (lv.nnz > 40 * lv.n) ? 16 : 8;
@@ -420,6 +453,7 @@ void assemble_operator(lsdd_hierarchy* h, Level& lv) {
         lv.d_val32 = h->arena.alloc<float>(lv.nnz);
         launch_to_f32(lv.nnz, lv.d_val, lv.d_val32, h->st);
     }
+    if (blocked) build_supernode_cols(h, lv);
 }
 
 // Element-batch apply of level 0 (packed lower triangles of factor[e] A_e, factor =
@@ -474,7 +508,7 @@ bool build_elem_apply(lsdd_hierarchy* h, Level& lv) {
 // triangles + per-element buffer + per-DOF sums
 double full_apply_bytes(const Level& lv, double wval, double wvec, bool r_minus) {
     const double nv = r_minus ? 3.0 : 2.0;
-    if (!lv.eapply) return (double)lv.nnz * (4 + wval) + (double)lv.n * (8 + nv * wvec);
+    if (!lv.eapply) return (double)lv.nnz * ((lv.sup ? lv.sup_ib : 4.0) + wval) + (double)lv.n * (8 + nv * wvec);
     const double nd = (double)lv.el.dofs.size();
     return (double)lv.etri_len * wval + nd * (4 + 8 + wvec + 2 * wval) + (double)lv.n * (8 + (nv - 1) * wvec);
 }
@@ -1476,7 +1510,9 @@ template <typename T, int NR>
 struct Cyc {
     static void resid_rows(int64_t nrows, const int32_t* rows, Level& lv, const T* val, const T* x, const T* r, T* out,
                            bool xz, hipStream_t st) {
-        if constexpr (NR == 1) launch_csr_resid_rows<T>(nrows, rows, lv.d_rowptr, lv.d_col, val, x, r, out, xz, lv.lanes, st);
+        if constexpr (NR == 1)
+            launch_csr_resid_rows<T>(nrows, rows, lv.d_rowptr, lv.sup ? lv.d_scol : lv.d_col, val, x, r, out, xz,
+                                     lv.lanes, st, lv.sup ? lv.d_scoff : nullptr);
         else launch_csr_resid_rows_b<T>(nrows, rows, lv.d_rowptr, lv.d_col, val, x, r, out, xz, lv.lanes_b, st);
     }
     // y = A x or r_minus - A x with the level's entries of type T (val), or from its
@@ -1488,7 +1524,8 @@ struct Cyc {
                                         lv.e_nmax, x, LvOps<T>::ebuf(lv), lv.n, lv.d_d2e_ptr, lv.d_e2y, r_minus, y, st);
                 return;
             }
-            launch_csr_spmv<T>(lv.n, lv.d_rowptr, lv.d_col, val, x, y, r_minus, lv.lanes, st);
+            launch_csr_spmv<T>(lv.n, lv.d_rowptr, lv.sup ? lv.d_scol : lv.d_col, val, x, y, r_minus, lv.lanes, st,
+                               lv.sup ? lv.d_scoff : nullptr);
         } else {
             launch_csr_spmv_b<T>(lv.n, lv.d_rowptr, lv.d_col, val, x, y, r_minus, lv.lanes_b, st);
         }
@@ -1558,7 +1595,8 @@ void sweep_ras(lsdd_hierarchy* h, Level& lv, const T* r, T* x, bool post, bool x
     }
     const int32_t* gather = post ? lv.d_sw_sub_dofs_w : lv.d_sw_sub_dofs;
     const int32_t* scatter = post ? lv.d_sw_sub_dofs : lv.d_sw_sub_dofs_w;
-    traced(h, "csr_resid_rows", m_all * (4 + 8 + 3 * wv) + (x_zero_first ? 0.0 : nnz_all * (4 + w)), [&] {
+    const double ib = (NR == 1 && lv.sup) ? lv.sup_ib : 4.0;
+    traced(h, "csr_resid_rows", m_all * (4 + 8 + 3 * wv) + (x_zero_first ? 0.0 : nnz_all * (ib + w)), [&] {
         C::resid_rows(rows, gather, lv, O::val(lv), x, r, v.rloc, x_zero_first, h->st);
     });
     for (int32_t c = 0; c < lv.n_colors; ++c) {
@@ -1600,10 +1638,11 @@ void sweep_factor(lsdd_hierarchy* h, Level& lv, const float* r, float* x, bool f
         const int64_t s0 = lv.color_smid[c], ns = lv.color_sub0[c + 1] - lv.color_smid[c];
         if (r1 == r0) continue;
         const bool xz = x_zero_first && cc == 0;
-        const double rb = lv.color_m[c] * (4 + 8 + 3 * 4.0) + (xz ? 0.0 : lv.color_nnz[c] * (4 + 8.0));
+        const double rb = lv.color_m[c] * (4 + 8 + 3 * 4.0) + (xz ? 0.0 : lv.color_nnz[c] * ((lv.sup ? lv.sup_ib : 4.0) + 8.0));
         traced(h, "csr_resid_rows", rb, [&] {
-            launch_csr_resid_rows<float, double>(r1 - r0, lv.d_sw_sub_dofs + r0, lv.d_rowptr, lv.d_col, lv.d_val, x, r,
-                                                 v.rloc + r0, xz, lv.lanes, h->st);
+            launch_csr_resid_rows<float, double>(r1 - r0, lv.d_sw_sub_dofs + r0, lv.d_rowptr,
+                                                 lv.sup ? lv.d_scol : lv.d_col, lv.d_val, x, r, v.rloc + r0, xz,
+                                                 lv.lanes, h->st, lv.sup ? lv.d_scoff : nullptr);
         });
         const int64_t j0 = lv.color_ritem0[c], j1 = lv.color_ritem0[c + 1];
         if (j1 > j0) {
@@ -1649,7 +1688,8 @@ void sweep(lsdd_hierarchy* h, Level& lv, const T* r, T* x, bool forward, bool x_
         const int64_t s0 = lv.color_smid[c], ns = lv.color_sub0[c + 1] - lv.color_smid[c];
         if (r1 == r0) continue;
         const bool xz = x_zero_first && cc == 0;
-        const double rb = lv.color_m[c] * (4 + 8 + 3 * wv) + (xz ? 0.0 : lv.color_nnz[c] * (4 + w));
+        const double rb = lv.color_m[c] * (4 + 8 + 3 * wv) +
+                          (xz ? 0.0 : lv.color_nnz[c] * ((NR == 1 && lv.sup ? lv.sup_ib : 4.0) + w));
         traced(h, "csr_resid_rows", rb, [&] {
             C::resid_rows(r1 - r0, lv.d_sw_sub_dofs + r0, lv, O::val(lv), x, r, v.rloc + r0 * NR, xz, h->st);
         });
@@ -1731,7 +1771,8 @@ void vcycle(lsdd_hierarchy* h, size_t l, const T* r, T* x) {
                                                      lv.d_etri, lv.e_nmax, x, lv.d_ebuf, lv.n, lv.d_d2e_ptr, lv.d_e2y,
                                                      r, v.t, h->st);
                 else
-                    launch_csr_spmv<float, double>(lv.n, lv.d_rowptr, lv.d_col, lv.d_val, x, v.t, r, lv.lanes, h->st);
+                    launch_csr_spmv<float, double>(lv.n, lv.d_rowptr, lv.sup ? lv.d_scol : lv.d_col, lv.d_val, x, v.t,
+                                                   r, lv.lanes, h->st, lv.sup ? lv.d_scoff : nullptr);
             });
         }
     }
@@ -1978,18 +2019,23 @@ void autotune_levels(lsdd_hierarchy* h) {
         int& lanes = NR > 1 ? lv.lanes_b : lv.lanes;
         const std::vector<int> lane_c = NR > 1 ? std::vector<int>{4, 8, 16, 32, 64} : std::vector<int>{8, 16, 32, 64};
         double best = 1e300;
-        int pick = lanes;
-        for (int L : lane_c) {
-            lanes = L;
-            const double ms = time_ms(h, [&] {
-                for (int32_t c = 0; c < lv.n_colors; ++c)
-                    C::resid_rows(lv.color_row0[c + 1] - lv.color_row0[c], lv.d_sw_sub_dofs + lv.color_row0[c], lv,
-                                  O::val(lv), v.x, v.r, v.rloc + lv.color_row0[c] * NR, false, h->st);
-            });
-            vlog("autotune level %d: CSR lanes %d: %.3f ms", lv.level, L, ms);
-            if (ms < best) best = ms, pick = L;
+        int pick = lanes, pick_sup = 0;
+        // single vectors on a supernode-blocked level: also with the shared column lists
+        for (int sp : (NR == 1 && lv.d_scoff) ? std::vector<int>{0, 1} : std::vector<int>{0}) {
+            if (NR == 1) lv.sup = sp;
+            for (int L : lane_c) {
+                lanes = L;
+                const double ms = time_ms(h, [&] {
+                    for (int32_t c = 0; c < lv.n_colors; ++c)
+                        C::resid_rows(lv.color_row0[c + 1] - lv.color_row0[c], lv.d_sw_sub_dofs + lv.color_row0[c],
+                                      lv, O::val(lv), v.x, v.r, v.rloc + lv.color_row0[c] * NR, false, h->st);
+                });
+                vlog("autotune level %d: CSR lanes %d%s: %.3f ms", lv.level, L, sp ? ", shared column lists" : "", ms);
+                if (ms < best) best = ms, pick = L, pick_sup = sp;
+            }
         }
         lanes = pick;
+        if (NR == 1) lv.sup = pick_sup;
         if (NR == 1 && build_elem_apply(h, lv)) {
             // the full product (pre-restriction residual, PCG) from the CSR or the element triangles
             best = 1e300;
@@ -2775,13 +2821,16 @@ lsdd_status lsdd_set_level_tuning(lsdd_hierarchy* h, int32_t level, const int32_
         return std::find(ok.begin(), ok.end(), v) != ok.end();
     };
     if (!one_of(in[0], {8, 16, 32, 64}) || !one_of(in[1], {4, 8, 16, 32, 64}) || !one_of(in[2], {2, 4, 8}) ||
-        !one_of(in[3], {8, 32}) || !one_of(in[4], {0, 1}))
+        !one_of(in[3], {8, 32}) || !one_of(in[4], {0, 1}) || !one_of(in[5], {0, 1}))
         throw Error(LSDD_E_INVAL, "launch shape outside the autotuner's candidates");
     Level& lv = *h->L[level];
+    if (in[5] && !lv.d_scoff)
+        throw Error(LSDD_E_UNSUPPORTED, "shared column lists: the level's pattern is not supernode-blocked");
     if (in[4] && !build_elem_apply(h, lv))
         throw Error(LSDD_E_UNSUPPORTED, "element apply: only on level 0 of a hierarchy built from element blocks "
                                         "of at most 128 DOFs");
     lv.eapply = in[4];
+    lv.sup = in[5];
     lv.lanes = in[0];
     lv.lanes_b = in[1];
     lv.fl = in[3];
@@ -2803,6 +2852,7 @@ lsdd_status lsdd_level_tuning(const lsdd_hierarchy* h, int32_t level, int32_t* o
     out[2] = lv.chl;
     out[3] = lv.fl;
     out[4] = lv.eapply;
+    out[5] = lv.sup;
     return LSDD_OK;
     ABI_END
 }

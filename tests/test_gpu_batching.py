@@ -190,7 +190,7 @@ def test_autotuned_shapes_keep_parity(dev):
         for t in t1 + t8:
             assert t["lanes"] in (8, 16, 32, 64) and t["lanes_block"] in (4, 8, 16, 32, 64)
             assert t["tiles_per_item"] in (2, 4, 8) and t["finalize_threads"] in (8, 32)
-            assert t["elem_apply"] in (0, 1)
+            assert t["elem_apply"] in (0, 1) and t["shared_cols"] in (0, 1)
         x, inf = h.solve(torch.from_numpy(b).to(dev))
         x_or, inf_or = oracle.pcg(h_or, b)
         assert abs(inf[0].iters - inf_or.iters) <= 1
@@ -230,7 +230,7 @@ def test_set_level_tuning_round_trip_and_checks(dev):
         assert np.linalg.norm(x.cpu().numpy() - x_or) <= 1e-10 * np.linalg.norm(x_or)
         before = h.level_tuning(0)
         for bad in (dict(before, lanes=12), dict(before, tiles_per_item=3), dict(before, finalize_threads=16),
-                    dict(before, elem_apply=2)):
+                    dict(before, elem_apply=2), dict(before, shared_cols=3)):
             with pytest.raises(P.LsddError) as ei:
                 h.set_level_tuning(0, bad)
             assert ei.value.code == 1
@@ -302,6 +302,41 @@ def test_element_triangle_products_match_the_csr_products(dev, case):
                     assert np.linalg.norm(xs.cpu().numpy() - x_or) <= 1e-10 * np.linalg.norm(x_or)
         for prec in (0, 1, 2):
             assert abs(its[1, prec] - its[0, prec]) <= 1, its
+
+
+def test_shared_column_lists_match_per_entry_columns_bit_for_bit(dev):
+    """On supernode-blocked levels the single-vector CSR kernels may read one column
+    list per supernode instead of a column index per entry: V-cycles and PCG solves
+    (FP64, FP32 and mixed cycles) equal the per-entry reads bit for bit; the coarse
+    levels always offer the lists."""
+    P = _lsdd()
+    prob, rng = _graddiv(seed=9)
+    r = torch.from_numpy(rng.standard_normal(prob.n)).to(dev)
+    with P.Hierarchy.setup_problem(prob, P.Params.default(precision=2, **GD_KW)) as h:
+        levels = h.info()["levels"]
+        base = [h.level_tuning(l) for l in range(levels)]
+        avail = []
+        for l in range(levels):
+            try:
+                h.set_level_tuning(l, dict(base[l], shared_cols=1))
+                avail.append(l)
+            except P.LsddError as ex:
+                assert ex.code == 7
+        assert 1 in avail
+        r1 = torch.from_numpy(rng.standard_normal(h.info()["n"][1])).to(dev)
+
+        def run(sc):
+            h.set_tuning([dict(t, shared_cols=sc if l in avail else 0) for l, t in enumerate(base)])
+            out = []
+            for prec in (0, 1, 2):
+                h.set_cycle_precision(prec)
+                x, inf = h.solve(r)
+                assert inf[0].converged == 1
+                out += [h.vcycle(r), x, h.apply(r1, level=1)]
+            return out
+
+        for a, b in zip(run(0), run(1)):
+            assert torch.equal(a, b)
 
 
 def test_solve_batched_over_separate_hierarchies(dev):
