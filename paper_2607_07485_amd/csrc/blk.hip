@@ -35,7 +35,7 @@ inline unsigned grid_for(int64_t n, int per_block = WG) {
 template <typename T, int L>
 __global__ void __launch_bounds__(WG) k_csr_resid_rows_b(int64_t nrows, const int32_t* rows, const int64_t* rowptr,
                                                          const int32_t* col, const T* val, const T* x, const T* r,
-                                                         T* out, int x_zero) {
+                                                         T* out, int x_zero, const int64_t* scoff) {
     constexpr int NS = L / NB;
     const int lane = tid() & (L - 1), k = lane & (NB - 1), slot = lane / NB;
     const int64_t stride = (int64_t)gridDim.x * (WG / L);
@@ -43,9 +43,9 @@ __global__ void __launch_bounds__(WG) k_csr_resid_rows_b(int64_t nrows, const in
         const int32_t p = rows[t];   // < 0: masked entry, out = 0
         T s = 0;
         if (!x_zero && p >= 0) {
-            const int64_t q1 = rowptr[p + 1];
+            const int64_t q1 = rowptr[p + 1], cb = scoff ? scoff[p] - rowptr[p] : 0;
 #pragma unroll 4
-            for (int64_t q = rowptr[p] + slot; q < q1; q += NS) s += val[q] * x[(int64_t)col[q] * NB + k];
+            for (int64_t q = rowptr[p] + slot; q < q1; q += NS) s += val[q] * x[(int64_t)col[cb + q] * NB + k];
         }
         for (int off = L / 2; off >= NB; off >>= 1) s += __shfl_xor(s, off, L);
         if (slot == 0) out[t * NB + k] = p >= 0 ? r[(int64_t)p * NB + k] - s : (T)0;
@@ -84,17 +84,17 @@ __device__ inline void load_xrow(const T* p, T (&v)[NB]) {
 }
 
 template <typename T, int L>
-__device__ inline void slot_row_sums(int64_t q0, int64_t q1, int lane, const int32_t* col, const T* val,
+__device__ inline void slot_row_sums(int64_t q0, int64_t q1, int lane, const int32_t* col, int64_t cb, const T* val,
                                      const T* x, T (&s)[NB]) {
     const int nit = (int)((q1 - q0 + L - 1) / L);
     for (int it = 0; it < nit; it += 2) {
         const int64_t qa = q0 + lane + (int64_t)it * L, qb = qa + L;
         const int64_t qac = qa < q1 ? qa : q1 - 1, qbc = qb < q1 ? qb : q1 - 1;
         const T va = val[qac], vb = val[qbc];
-        const int32_t ca = col[qac], cb = col[qbc];
+        const int32_t ca = col[cb + qac], cc = col[cb + qbc];
         T xa[NB], xb[NB];
         load_xrow(x + (int64_t)ca * NB, xa);
-        load_xrow(x + (int64_t)cb * NB, xb);
+        load_xrow(x + (int64_t)cc * NB, xb);
         const T wa = qa < q1 ? va : (T)0, wb = qb < q1 ? vb : (T)0;
 #pragma unroll
         for (int k = 0; k < NB; ++k) s[k] += wa * xa[k];
@@ -131,7 +131,7 @@ __device__ inline void slot_reduce(T (&s)[NB], int lane) {
 template <typename T, int L>
 __global__ void __launch_bounds__(WG) k_csr_resid_rows_s(int64_t nrows, const int32_t* rows, const int64_t* rowptr,
                                                          const int32_t* col, const T* val, const T* x, const T* r,
-                                                         T* out, int x_zero) {
+                                                         T* out, int x_zero, const int64_t* scoff) {
     const int lane = tid() & (L - 1);
     const int64_t stride = (int64_t)gridDim.x * (WG / L);
     for (int64_t t = ((int64_t)blockIdx.x * WG + tid()) / L; t < nrows; t += stride) {
@@ -139,7 +139,8 @@ __global__ void __launch_bounds__(WG) k_csr_resid_rows_s(int64_t nrows, const in
         T s[NB];
 #pragma unroll
         for (int k = 0; k < NB; ++k) s[k] = 0;
-        if (!x_zero && p >= 0) slot_row_sums<T, L>(rowptr[p], rowptr[p + 1], lane, col, val, x, s);
+        if (!x_zero && p >= 0)
+            slot_row_sums<T, L>(rowptr[p], rowptr[p + 1], lane, col, scoff ? scoff[p] - rowptr[p] : 0, val, x, s);
         slot_reduce<T, L>(s, lane);
         constexpr int PL = L < NB ? NB / L : 1;   // right-hand sides per writing lane
         if (lane * PL < NB)
@@ -153,14 +154,15 @@ __global__ void __launch_bounds__(WG) k_csr_resid_rows_s(int64_t nrows, const in
 
 template <typename T, int L>
 __global__ void __launch_bounds__(WG) k_csr_spmv_s(int64_t n, const int64_t* rowptr, const int32_t* col,
-                                                   const T* val, const T* x, T* y, const T* r_minus) {
+                                                   const T* val, const T* x, T* y, const T* r_minus,
+                                                   const int64_t* scoff) {
     const int lane = tid() & (L - 1);
     const int64_t stride = (int64_t)gridDim.x * (WG / L);
     for (int64_t p = ((int64_t)blockIdx.x * WG + tid()) / L; p < n; p += stride) {
         T s[NB];
 #pragma unroll
         for (int k = 0; k < NB; ++k) s[k] = 0;
-        slot_row_sums<T, L>(rowptr[p], rowptr[p + 1], lane, col, val, x, s);
+        slot_row_sums<T, L>(rowptr[p], rowptr[p + 1], lane, col, scoff ? scoff[p] - rowptr[p] : 0, val, x, s);
         slot_reduce<T, L>(s, lane);
         constexpr int PL = L < NB ? NB / L : 1;
         if (lane * PL < NB)
@@ -174,15 +176,16 @@ __global__ void __launch_bounds__(WG) k_csr_spmv_s(int64_t n, const int64_t* row
 
 template <typename T, int L>
 __global__ void __launch_bounds__(WG) k_csr_spmv_b(int64_t n, const int64_t* rowptr, const int32_t* col,
-                                                   const T* val, const T* x, T* y, const T* r_minus) {
+                                                   const T* val, const T* x, T* y, const T* r_minus,
+                                                   const int64_t* scoff) {
     constexpr int NS = L / NB;
     const int lane = tid() & (L - 1), k = lane & (NB - 1), slot = lane / NB;
     const int64_t stride = (int64_t)gridDim.x * (WG / L);
     for (int64_t p = ((int64_t)blockIdx.x * WG + tid()) / L; p < n; p += stride) {
-        const int64_t q1 = rowptr[p + 1];
+        const int64_t q1 = rowptr[p + 1], cb = scoff ? scoff[p] - rowptr[p] : 0;
         T s = 0;
 #pragma unroll 4
-        for (int64_t q = rowptr[p] + slot; q < q1; q += NS) s += val[q] * x[(int64_t)col[q] * NB + k];
+        for (int64_t q = rowptr[p] + slot; q < q1; q += NS) s += val[q] * x[(int64_t)col[cb + q] * NB + k];
         for (int off = L / 2; off >= NB; off >>= 1) s += __shfl_xor(s, off, L);
         if (slot == 0) y[p * NB + k] = r_minus ? r_minus[p * NB + k] - s : s;
     }
@@ -782,44 +785,45 @@ __global__ void k_pcg_start(int64_t len, const double* b, double* r, double* x) 
 
 template <typename T>
 void launch_csr_resid_rows_b(int64_t nrows, const int32_t* rows, const int64_t* rowptr, const int32_t* col,
-                             const T* val, const T* x, const T* r, T* out, bool x_zero, int lanes, hipStream_t st) {
+                             const T* val, const T* x, const T* r, T* out, bool x_zero, int lanes, hipStream_t st,
+                             const int64_t* scoff) {
     if (nrows <= 0) return;
     if (lanes <= 4)
         hipLaunchKernelGGL((k_csr_resid_rows_s<T, 4>), dim3(grid_for(nrows * 4)), dim3(WG), 0, st, nrows, rows,
-                           rowptr, col, val, x, r, out, x_zero ? 1 : 0);
+                           rowptr, col, val, x, r, out, x_zero ? 1 : 0, scoff);
     else if (lanes <= 8)
         hipLaunchKernelGGL((k_csr_resid_rows_s<T, 8>), dim3(grid_for(nrows * 8)), dim3(WG), 0, st, nrows, rows,
-                           rowptr, col, val, x, r, out, x_zero ? 1 : 0);
+                           rowptr, col, val, x, r, out, x_zero ? 1 : 0, scoff);
     else if (lanes <= 16)
         hipLaunchKernelGGL((k_csr_resid_rows_s<T, 16>), dim3(grid_for(nrows * 16)), dim3(WG), 0, st, nrows, rows,
-                           rowptr, col, val, x, r, out, x_zero ? 1 : 0);
+                           rowptr, col, val, x, r, out, x_zero ? 1 : 0, scoff);
     else if (lanes >= 64)
         hipLaunchKernelGGL((k_csr_resid_rows_b<T, 64>), dim3(grid_for(nrows * 64)), dim3(WG), 0, st, nrows, rows,
-                           rowptr, col, val, x, r, out, x_zero ? 1 : 0);
+                           rowptr, col, val, x, r, out, x_zero ? 1 : 0, scoff);
     else
         hipLaunchKernelGGL((k_csr_resid_rows_b<T, 32>), dim3(grid_for(nrows * 32)), dim3(WG), 0, st, nrows, rows,
-                           rowptr, col, val, x, r, out, x_zero ? 1 : 0);
+                           rowptr, col, val, x, r, out, x_zero ? 1 : 0, scoff);
 }
 
 template <typename T>
 void launch_csr_spmv_b(int64_t n, const int64_t* rowptr, const int32_t* col, const T* val, const T* x, T* y,
-                       const T* r_minus, int lanes, hipStream_t st) {
+                       const T* r_minus, int lanes, hipStream_t st, const int64_t* scoff) {
     if (n <= 0) return;
     if (lanes <= 4)
         hipLaunchKernelGGL((k_csr_spmv_s<T, 4>), dim3(grid_for(n * 4)), dim3(WG), 0, st, n, rowptr, col, val, x, y,
-                           r_minus);
+                           r_minus, scoff);
     else if (lanes <= 8)
         hipLaunchKernelGGL((k_csr_spmv_s<T, 8>), dim3(grid_for(n * 8)), dim3(WG), 0, st, n, rowptr, col, val, x, y,
-                           r_minus);
+                           r_minus, scoff);
     else if (lanes <= 16)
         hipLaunchKernelGGL((k_csr_spmv_s<T, 16>), dim3(grid_for(n * 16)), dim3(WG), 0, st, n, rowptr, col, val, x, y,
-                           r_minus);
+                           r_minus, scoff);
     else if (lanes >= 64)
         hipLaunchKernelGGL((k_csr_spmv_b<T, 64>), dim3(grid_for(n * 64)), dim3(WG), 0, st, n, rowptr, col, val, x, y,
-                           r_minus);
+                           r_minus, scoff);
     else
         hipLaunchKernelGGL((k_csr_spmv_b<T, 32>), dim3(grid_for(n * 32)), dim3(WG), 0, st, n, rowptr, col, val, x, y,
-                           r_minus);
+                           r_minus, scoff);
 }
 
 template <typename T>
@@ -983,9 +987,9 @@ LSDD_SMALL_INST(float, NRB)
 
 #define LSDD_BLK_INST(T)                                                                                            \
     template void launch_csr_resid_rows_b<T>(int64_t, const int32_t*, const int64_t*, const int32_t*, const T*,      \
-                                             const T*, const T*, T*, bool, int, hipStream_t);                         \
+                                             const T*, const T*, T*, bool, int, hipStream_t, const int64_t*);         \
     template void launch_csr_spmv_b<T>(int64_t, const int64_t*, const int32_t*, const T*, const T*, T*, const T*,    \
-                                       int, hipStream_t);                                                             \
+                                       int, hipStream_t, const int64_t*);                                             \
     template void launch_sub_symv_b<T>(int64_t, const int32_t*, const int64_t*, const int64_t*, const T*, const T*,  \
                                        const int64_t*, T*, int, hipStream_t);                                         \
     template void launch_sub_finalize_b<T>(int64_t, int64_t, const int32_t*, const int64_t*, const int64_t*,         \

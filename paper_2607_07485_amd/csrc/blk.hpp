@@ -12,13 +12,15 @@ constexpr int NRB = 8;   // right-hand sides per block
 
 // ---------------------------------------------------------------- cycle, block vectors
 // lanes per row of the CSR kernels: 4, 8 or 16 (lane = nonzero slot, all NRB
-// right-hand sides per lane) or 32 or 64 (lane = (nonzero slot, right-hand side))
+// right-hand sides per lane) or 32 or 64 (lane = (nonzero slot, right-hand side));
+// scoff != NULL: shared per-supernode column lists, as in launch_csr_resid_rows
 template <typename T>
 void launch_csr_resid_rows_b(int64_t nrows, const int32_t* rows, const int64_t* rowptr, const int32_t* col,
-                             const T* val, const T* x, const T* r, T* out, bool x_zero, int lanes, hipStream_t st);
+                             const T* val, const T* x, const T* r, T* out, bool x_zero, int lanes, hipStream_t st,
+                             const int64_t* scoff = nullptr);
 template <typename T>
 void launch_csr_spmv_b(int64_t n, const int64_t* rowptr, const int32_t* col, const T* val, const T* x, T* y,
-                       const T* r_minus, int lanes, hipStream_t st);
+                       const T* r_minus, int lanes, hipStream_t st, const int64_t* scoff = nullptr);
 template <typename T>
 void launch_sub_symv_b(int64_t n_items, const int32_t* items, const int64_t* sub_off, const int64_t* tp_off,
                        const T* tiles, const T* rloc, const int64_t* scr_off, T* scr, int chl, hipStream_t st);

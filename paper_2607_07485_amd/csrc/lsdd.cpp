@@ -1513,7 +1513,9 @@ struct Cyc {
         if constexpr (NR == 1)
             launch_csr_resid_rows<T>(nrows, rows, lv.d_rowptr, lv.sup ? lv.d_scol : lv.d_col, val, x, r, out, xz,
                                      lv.lanes, st, lv.sup ? lv.d_scoff : nullptr);
-        else launch_csr_resid_rows_b<T>(nrows, rows, lv.d_rowptr, lv.d_col, val, x, r, out, xz, lv.lanes_b, st);
+        else
+            launch_csr_resid_rows_b<T>(nrows, rows, lv.d_rowptr, lv.sup ? lv.d_scol : lv.d_col, val, x, r, out, xz,
+                                       lv.lanes_b, st, lv.sup ? lv.d_scoff : nullptr);
     }
     // y = A x or r_minus - A x with the level's entries of type T (val), or from its
     // element triangles of the same precision when the autotuner chose them
@@ -1527,7 +1529,8 @@ struct Cyc {
             launch_csr_spmv<T>(lv.n, lv.d_rowptr, lv.sup ? lv.d_scol : lv.d_col, val, x, y, r_minus, lv.lanes, st,
                                lv.sup ? lv.d_scoff : nullptr);
         } else {
-            launch_csr_spmv_b<T>(lv.n, lv.d_rowptr, lv.d_col, val, x, y, r_minus, lv.lanes_b, st);
+            launch_csr_spmv_b<T>(lv.n, lv.d_rowptr, lv.sup ? lv.d_scol : lv.d_col, val, x, y, r_minus, lv.lanes_b, st,
+                                 lv.sup ? lv.d_scoff : nullptr);
         }
     }
     static void symv(int64_t n_items, const int32_t* items, const int64_t* sub_off, const int64_t* tp_off,
@@ -1595,7 +1598,7 @@ void sweep_ras(lsdd_hierarchy* h, Level& lv, const T* r, T* x, bool post, bool x
     }
     const int32_t* gather = post ? lv.d_sw_sub_dofs_w : lv.d_sw_sub_dofs;
     const int32_t* scatter = post ? lv.d_sw_sub_dofs : lv.d_sw_sub_dofs_w;
-    const double ib = (NR == 1 && lv.sup) ? lv.sup_ib : 4.0;
+    const double ib = lv.sup ? lv.sup_ib : 4.0;
     traced(h, "csr_resid_rows", m_all * (4 + 8 + 3 * wv) + (x_zero_first ? 0.0 : nnz_all * (ib + w)), [&] {
         C::resid_rows(rows, gather, lv, O::val(lv), x, r, v.rloc, x_zero_first, h->st);
     });
@@ -1689,7 +1692,7 @@ void sweep(lsdd_hierarchy* h, Level& lv, const T* r, T* x, bool forward, bool x_
         if (r1 == r0) continue;
         const bool xz = x_zero_first && cc == 0;
         const double rb = lv.color_m[c] * (4 + 8 + 3 * wv) +
-                          (xz ? 0.0 : lv.color_nnz[c] * ((NR == 1 && lv.sup ? lv.sup_ib : 4.0) + w));
+                          (xz ? 0.0 : lv.color_nnz[c] * ((lv.sup ? lv.sup_ib : 4.0) + w));
         traced(h, "csr_resid_rows", rb, [&] {
             C::resid_rows(r1 - r0, lv.d_sw_sub_dofs + r0, lv, O::val(lv), x, r, v.rloc + r0 * NR, xz, h->st);
         });
@@ -1777,7 +1780,9 @@ void vcycle(lsdd_hierarchy* h, size_t l, const T* r, T* x) {
         }
     }
     if (!mixed)
-        traced(h, "csr_spmv", NR == 1 ? full_apply_bytes(lv, w, wv, true) : (double)lv.nnz * (4 + w) + (double)lv.n * (8 + 3 * wv),
+        traced(h, "csr_spmv",
+               NR == 1 ? full_apply_bytes(lv, w, wv, true)
+                       : (double)lv.nnz * ((lv.sup ? lv.sup_ib : 4.0) + w) + (double)lv.n * (8 + 3 * wv),
                [&] { C::spmv(lv, O::val(lv), x, v.t, r, h->st); });
     const double zb = (double)lv.zoff.back() * w + (double)lv.n * (4 + wv) + (double)nx.n * wv;
     traced(h, "restrict", zb, [&] { C::restrict_(lv, O::Z(lv), v.t, vn.r, h->st); });
@@ -1886,7 +1891,9 @@ bool pcg_run(lsdd_hierarchy* h) {
     launch_copy(n * NR, B.z, B.p, st);
     launch_seg_dot(T, NR, B.r, B.z, nullptr, nullptr, h->part, rz, nullptr, st);
     auto half_a = [&] {
-        traced(h, "pcg_spmv", NR == 1 ? full_apply_bytes(l0, 8.0, 8.0, false) : (double)l0.nnz * 12.0 + (double)n * 8.0 * (1 + 2 * NR),
+        traced(h, "pcg_spmv",
+               NR == 1 ? full_apply_bytes(l0, 8.0, 8.0, false)
+                       : (double)l0.nnz * ((l0.sup ? l0.sup_ib : 4.0) + 8.0) + (double)n * 8.0 * (1 + 2 * NR),
                [&] { Cyc<double, NR>::spmv(l0, l0.d_val, B.p, B.q, nullptr, st); });
         launch_seg_dot(T, NR, B.p, B.q, nullptr, nullptr, h->part, pq, nullptr, st);
         launch_pcg_alpha(ns, act, rz, pq, alpha, itf + 1, st);
@@ -2021,8 +2028,8 @@ void autotune_levels(lsdd_hierarchy* h) {
         double best = 1e300;
         int pick = lanes, pick_sup = 0;
         // single vectors on a supernode-blocked level: also with the shared column lists
-        for (int sp : (NR == 1 && lv.d_scoff) ? std::vector<int>{0, 1} : std::vector<int>{0}) {
-            if (NR == 1) lv.sup = sp;
+        for (int sp : lv.d_scoff ? std::vector<int>{0, 1} : std::vector<int>{0}) {
+            lv.sup = sp;
             for (int L : lane_c) {
                 lanes = L;
                 const double ms = time_ms(h, [&] {
@@ -2035,7 +2042,7 @@ void autotune_levels(lsdd_hierarchy* h) {
             }
         }
         lanes = pick;
-        if (NR == 1) lv.sup = pick_sup;
+        lv.sup = pick_sup;
         if (NR == 1 && build_elem_apply(h, lv)) {
             // the full product (pre-restriction residual, PCG) from the CSR or the element triangles
             best = 1e300;

@@ -305,10 +305,10 @@ def test_element_triangle_products_match_the_csr_products(dev, case):
 
 
 def test_shared_column_lists_match_per_entry_columns_bit_for_bit(dev):
-    """On supernode-blocked levels the single-vector CSR kernels may read one column
-    list per supernode instead of a column index per entry: V-cycles and PCG solves
-    (FP64, FP32 and mixed cycles) equal the per-entry reads bit for bit; the coarse
-    levels always offer the lists."""
+    """On supernode-blocked levels the CSR kernels may read one column list per
+    supernode instead of a column index per entry: V-cycles and PCG solves (FP64, FP32
+    and mixed cycles, single vectors and blocks of 8 right-hand sides) equal the
+    per-entry reads bit for bit; the coarse levels always offer the lists."""
     P = _lsdd()
     prob, rng = _graddiv(seed=9)
     r = torch.from_numpy(rng.standard_normal(prob.n)).to(dev)
@@ -337,6 +337,14 @@ def test_shared_column_lists_match_per_entry_columns_bit_for_bit(dev):
 
         for a, b in zip(run(0), run(1)):
             assert torch.equal(a, b)
+        # blocks of 8 right-hand sides (the block CSR kernels) read the same lists
+        R = torch.from_numpy(rng.standard_normal((9, prob.n))).to(dev)
+        h.set_cycle_precision(0)
+        outs = []
+        for sc in (0, 1):
+            h.set_tuning([dict(t, shared_cols=sc if l in avail else 0) for l, t in enumerate(base)])
+            outs.append(h.solve(R)[0])
+        assert torch.equal(outs[0], outs[1])
 
 
 def test_solve_batched_over_separate_hierarchies(dev):
