@@ -328,21 +328,24 @@ lsdd_status lsdd_level_segments(const lsdd_hierarchy* h, int32_t level, int64_t*
  * triangles of the A_e, built on the first call (one FP64 triangle per element, plus
  * an FP32 copy when the hierarchy has an FP32 cycle), and keeps the faster; on levels
  * whose rows share per-supernode column lists it times the CSR kernels with and
- * without them.  block
+ * without them; in the mixed cycle it times the factor product with and without its
+ * tile rows kept in LDS.  block
  * != 0 tunes the shapes of the 8-right-hand-side blocks, 0 those of single vectors,
  * for the current cycle precision.  The choice changes only the summation order of
  * the sums involved. */
 lsdd_status lsdd_autotune(lsdd_hierarchy* h, int32_t block, void* hip_stream);
 
-/* Launch shapes of level l (host int32[6]): CSR lanes per row for single vectors,
+/* Launch shapes of level l (host int32[7]): CSR lanes per row for single vectors,
  * for blocks, tiles per work item, finalize threads per DOF, full products of single
- * vectors from the element triangles (1) or the CSR (0), and whether the
- * single-vector CSR kernels read one shared column list per supernode (1) instead of
- * a column index per entry (0; available where the level's pattern is built on
- * supernodes, i.e. every row of a supernode has the same columns; same results). */
+ * vectors from the element triangles (1) or the CSR (0), whether the CSR kernels
+ * read one shared column list per supernode (1) instead of a column index per entry
+ * (0; available where the level's pattern is built on supernodes, i.e. every row of
+ * a supernode has the same columns; same results), and whether the mixed cycle's
+ * factor product keeps each tile row in LDS between its two passes (1) or reads it
+ * again through the caches (0; same results). */
 lsdd_status lsdd_level_tuning(const lsdd_hierarchy* h, int32_t level, int32_t* out);
 
-/* Set the launch shapes of level l (host int32[6], the layout of lsdd_level_tuning),
+/* Set the launch shapes of level l (host int32[7], the layout of lsdd_level_tuning),
  * e.g. to restore what lsdd_autotune chose for another cycle precision.  Every value
  * must be one of the autotuner's candidates (else LSDD_E_INVAL, nothing changed);
  * tiles per work item is ignored on the coarsest level; element products on a level

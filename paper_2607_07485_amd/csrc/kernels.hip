@@ -1049,11 +1049,16 @@ __global__ void __launch_bounds__(WG) k_sub_symv(const int32_t* items, const int
 // the row's other chunk slots get zero, so k_sub_finalize sums the same layout as
 // for the symmetric product.  HBM reads one pass of X (half the bytes of the FP64
 // inverse) instead of two.
+//
+// stash > 0: the first `stash` tiles of the row also go to LDS (dynamic shared
+// memory, stash * 16 KB) in phase 1, and phase 2 takes them from there; every
+// thread reads back exactly the entries it stored, so no barrier separates the
+// phases.  Tiles past `stash` are read again through the caches.
 __global__ void __launch_bounds__(WG) k_sub_fact(const int32_t* items, const int64_t* sub_off, const int64_t* tp_off,
                                                  const float* tiles, const float* rloc, const int64_t* scr_off,
-                                                 float* scr, int chl) {
+                                                 float* scr, int chl, int stash) {
     constexpr int CH = 8;                                   // tiles per phase-2 LDS round
-    __shared__ double s_w[64];
+    extern __shared__ float s_stash[];
     __shared__ double s_c[4][CH][64];
     const int s = items[2 * blockIdx.x];
     const int I = items[2 * blockIdx.x + 1];
@@ -1080,6 +1085,17 @@ __global__ void __launch_bounds__(WG) k_sub_fact(const int32_t* items, const int
         const double xj = c < m ? (double)rloc[o + c] : 0.0;
 #pragma unroll
         for (int q = 0; q < 16; ++q) p[q] += (double)v[q] * xj;
+        if (J < stash)
+#pragma unroll
+            for (int q = 0; q < 16; ++q) s_stash[J * 4096 + (w + 4 * q) * 64 + lane] = v[q];
+    };
+    auto fetch2 = [&](float(&v)[16], int J) {
+        if (J < stash) {
+#pragma unroll
+            for (int q = 0; q < 16; ++q) v[q] = s_stash[J * 4096 + (w + 4 * q) * 64 + lane];
+        } else {
+            fetch(v, J);
+        }
     };
     fetch(va, 0);
     for (int J = 0; J <= I; J += 2) {
@@ -1106,15 +1122,15 @@ __global__ void __launch_bounds__(WG) k_sub_fact(const int32_t* items, const int
     };
     for (int J0 = 0; J0 <= I; J0 += CH) {
         const int nJ = min(CH, I + 1 - J0);
-        fetch(va, J0);
+        fetch2(va, J0);
 #pragma unroll
         for (int jj = 0; jj < CH; jj += 2) {
             if (jj < nJ) {
-                if (jj + 1 < nJ) fetch(vb, J0 + jj + 1);
+                if (jj + 1 < nJ) fetch2(vb, J0 + jj + 1);
                 use2(va, jj);
             }
             if (jj + 1 < nJ) {
-                if (jj + 2 < nJ) fetch(va, J0 + jj + 2);
+                if (jj + 2 < nJ) fetch2(va, J0 + jj + 2);
                 use2(vb, jj + 1);
             }
         }
@@ -1694,11 +1710,19 @@ template void launch_sub_finalize_tab<float>(int64_t, int64_t, const int32_t*, c
                                              int, hipStream_t);
 
 void launch_sub_fact(int64_t n_items, const int32_t* items, const int64_t* sub_off, const int64_t* tp_off,
-                     const float* tiles, const float* rloc, const int64_t* scr_off, float* scr, int chl,
+                     const float* tiles, const float* rloc, const int64_t* scr_off, float* scr, int chl, int stash,
                      hipStream_t st) {
     if (n_items <= 0) return;
-    hipLaunchKernelGGL(k_sub_fact, dim3((unsigned)n_items), dim3(WG), 0, st, items, sub_off, tp_off, tiles, rloc,
-                       scr_off, scr, chl);
+    stash = std::max(0, std::min(stash, SUB_FACT_MAX_STASH));
+    static bool attr = false;
+    if (!attr) {
+        // allow the largest stash (the static LDS of the kernel comes on top)
+        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_sub_fact),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, SUB_FACT_MAX_STASH * 4096 * 4);
+        attr = true;
+    }
+    hipLaunchKernelGGL(k_sub_fact, dim3((unsigned)n_items), dim3(WG), (size_t)stash * 4096 * 4, st, items, sub_off,
+                       tp_off, tiles, rloc, scr_off, scr, chl, stash);
 }
 
 int64_t sub_symv_scratch_len(int64_t m, int chl) { return symv_scratch_len((int)((m + 63) / 64), chl); }

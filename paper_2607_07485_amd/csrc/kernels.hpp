@@ -199,9 +199,12 @@ template <typename T>
 void launch_sub_finalize_tab(int64_t r0, int64_t r1, const int32_t* tab, const T* scr, const int32_t* sub_dofs, T* x,
                              int fl, hipStream_t st);
 // mixed cycle: y = X^T (X r) with FP32 factor tiles in one pass, FP64 sums; items =
-// (subdomain, whole tile row) pairs; partials in the layout of launch_sub_symv for chl
+// (subdomain, whole tile row) pairs; partials in the layout of launch_sub_symv for chl.
+// stash: tiles of each row kept in LDS between the two products (0 .. SUB_FACT_MAX_STASH;
+// 16 KB each, all work items of the launch get the same allocation)
+constexpr int SUB_FACT_MAX_STASH = 8;
 void launch_sub_fact(int64_t n_items, const int32_t* items, const int64_t* sub_off, const int64_t* tp_off,
-                     const float* tiles, const float* rloc, const int64_t* scr_off, float* scr, int chl,
+                     const float* tiles, const float* rloc, const int64_t* scr_off, float* scr, int chl, int stash,
                      hipStream_t st);
 // scratch entries for a subdomain of size m; append its work items (s, tile row, chunk)
 int64_t sub_symv_scratch_len(int64_t m, int chl);

@@ -231,6 +231,8 @@ struct Level {
     int32_t* d_items = nullptr;       // (subdomain, tile row), grouped by colour
     int32_t* d_row_items = nullptr;   // mixed cycle: (subdomain, whole tile row), grouped by colour
     std::vector<int64_t> color_ritem0;
+    std::vector<int> color_stash;     // mixed cycle: factor tiles per row kept in LDS, per colour
+    int fact_stash = 1;               // 0: the factor product re-reads every tile through the caches
     int32_t* d_pos_sub = nullptr;     // sweep-order subdomain of every Omega entry
     int64_t* d_scr_off = nullptr;     // per subdomain: offset of its partial-sum scratch
     int32_t* d_fin_tab = nullptr;     // per overlap entry: its partial-sum addresses (4 int32)
@@ -1241,6 +1243,7 @@ std::unique_ptr<Level> coarsen(lsdd_hierarchy* h, Level& lv, const int32_t* agg_
         // whole-tile-row items of the one-pass factor product, longest rows first per colour
         std::vector<int32_t> ritems;
         lv.color_ritem0.assign(lv.n_colors + 1, 0);
+        lv.color_stash.assign(lv.n_colors, 0);
         for (int32_t c = 0; c < lv.n_colors; ++c) {
             std::vector<std::pair<int32_t, int32_t>> rows;
             for (int32_t q = lv.color_sub0[c]; q < lv.color_smid[c]; ++q) {
@@ -1253,6 +1256,8 @@ std::unique_ptr<Level> coarsen(lsdd_hierarchy* h, Level& lv, const int32_t* agg_
                              });
             for (auto& r : rows) ritems.insert(ritems.end(), {r.first, r.second});
             lv.color_ritem0[c + 1] = (int64_t)ritems.size() / 2;
+            // the longest tile row of the colour, up to the LDS capacity
+            lv.color_stash[c] = rows.empty() ? 0 : std::min<int>(SUB_FACT_MAX_STASH, rows.front().second + 1);
         }
         lv.d_row_items = ar.upload(ritems, st);
     }
@@ -1652,7 +1657,7 @@ void sweep_factor(lsdd_hierarchy* h, Level& lv, const float* r, float* x, bool f
             const double gb = lv.color_m2[c] * 4.0 + (double)(rm - r0) * (4 + 3 * 4.0);
             traced(h, "sub_fact", gb, [&] {
                 launch_sub_fact(j1 - j0, lv.d_row_items + 2 * j0, lv.d_sw_sub_off, lv.d_sw_tp_off, lv.d_tfac32,
-                                v.rloc, lv.d_scr_off, v.scr, lv.chl, h->st);
+                                v.rloc, lv.d_scr_off, v.scr, lv.chl, lv.fact_stash ? lv.color_stash[c] : 0, h->st);
             });
             traced(h, "sub_finalize", lv.color_scr[c] * 4.0 + (double)(rm - r0) * 16.0, [&] {
                 Cyc<float, 1>::finalize_colour(lv, c, v.scr, lv.d_sw_sub_dofs, x, h->st);
@@ -2083,6 +2088,30 @@ void autotune_levels(lsdd_hierarchy* h) {
             if (ms < best) best = ms, pick_fl = fl;
         }
         lv.fl = pick_fl;
+        if constexpr (std::is_same<T, float>::value && NR == 1) {
+            if (h->cycle_prec == 2 && lv.d_row_items) {
+                // the mixed cycle's factor product, with and without the tile rows kept in LDS
+                auto run_fact = [&] {
+                    for (int32_t c = 0; c < lv.n_colors; ++c) {
+                        const int64_t j0 = lv.color_ritem0[c], j1 = lv.color_ritem0[c + 1];
+                        if (j1 == j0) continue;
+                        launch_sub_fact(j1 - j0, lv.d_row_items + 2 * j0, lv.d_sw_sub_off, lv.d_sw_tp_off,
+                                        lv.d_tfac32, v.rloc, lv.d_scr_off, v.scr, lv.chl,
+                                        lv.fact_stash ? lv.color_stash[c] : 0, h->st);
+                        C::finalize_colour(lv, c, v.scr, lv.d_sw_sub_dofs, v.x, h->st);
+                    }
+                };
+                best = 1e300;
+                int pick_fs = lv.fact_stash;
+                for (int fs : {0, 1}) {
+                    lv.fact_stash = fs;
+                    const double ms = time_ms(h, run_fact);
+                    vlog("autotune level %d: factor product, rows %s: %.3f ms", lv.level, fs ? "kept in LDS" : "re-read", ms);
+                    if (ms < best) best = ms, pick_fs = fs;
+                }
+                lv.fact_stash = pick_fs;
+            }
+        }
     }
     sync(h->st);
 }
@@ -2828,7 +2857,7 @@ lsdd_status lsdd_set_level_tuning(lsdd_hierarchy* h, int32_t level, const int32_
         return std::find(ok.begin(), ok.end(), v) != ok.end();
     };
     if (!one_of(in[0], {8, 16, 32, 64}) || !one_of(in[1], {4, 8, 16, 32, 64}) || !one_of(in[2], {2, 4, 8}) ||
-        !one_of(in[3], {8, 32}) || !one_of(in[4], {0, 1}) || !one_of(in[5], {0, 1}))
+        !one_of(in[3], {8, 32}) || !one_of(in[4], {0, 1}) || !one_of(in[5], {0, 1}) || !one_of(in[6], {0, 1}))
         throw Error(LSDD_E_INVAL, "launch shape outside the autotuner's candidates");
     Level& lv = *h->L[level];
     if (in[5] && !lv.d_scoff)
@@ -2838,6 +2867,7 @@ lsdd_status lsdd_set_level_tuning(lsdd_hierarchy* h, int32_t level, const int32_
                                         "of at most 128 DOFs");
     lv.eapply = in[4];
     lv.sup = in[5];
+    lv.fact_stash = in[6];
     lv.lanes = in[0];
     lv.lanes_b = in[1];
     lv.fl = in[3];
@@ -2860,6 +2890,7 @@ lsdd_status lsdd_level_tuning(const lsdd_hierarchy* h, int32_t level, int32_t* o
     out[3] = lv.fl;
     out[4] = lv.eapply;
     out[5] = lv.sup;
+    out[6] = lv.fact_stash;
     return LSDD_OK;
     ABI_END
 }

@@ -338,15 +338,15 @@ class Hierarchy:
         return [self.level_tuning(l) for l in range(self.info()["levels"])]
 
     def level_tuning(self, level: int):
-        out = np.zeros(6, dtype=np.int32)
+        out = np.zeros(7, dtype=np.int32)
         _check(lib().lsdd_level_tuning(self._h, int(level), out.ctypes.data_as(C.POINTER(C.c_int32))))
         return dict(lanes=int(out[0]), lanes_block=int(out[1]), tiles_per_item=int(out[2]), finalize_threads=int(out[3]),
-                    elem_apply=int(out[4]), shared_cols=int(out[5]))
+                    elem_apply=int(out[4]), shared_cols=int(out[5]), fact_stash=int(out[6]))
 
     def set_level_tuning(self, level: int, t: dict):
         """lsdd_set_level_tuning with a dict as returned by level_tuning."""
         a = np.array([t["lanes"], t["lanes_block"], t["tiles_per_item"], t["finalize_threads"],
-                      t.get("elem_apply", 0), t.get("shared_cols", 0)], dtype=np.int32)
+                      t.get("elem_apply", 0), t.get("shared_cols", 0), t.get("fact_stash", 1)], dtype=np.int32)
         _check(lib().lsdd_set_level_tuning(self._h, int(level), a.ctypes.data_as(C.POINTER(C.c_int32))))
 
     def set_tuning(self, tuning):

@@ -190,7 +190,7 @@ def test_autotuned_shapes_keep_parity(dev):
         for t in t1 + t8:
             assert t["lanes"] in (8, 16, 32, 64) and t["lanes_block"] in (4, 8, 16, 32, 64)
             assert t["tiles_per_item"] in (2, 4, 8) and t["finalize_threads"] in (8, 32)
-            assert t["elem_apply"] in (0, 1) and t["shared_cols"] in (0, 1)
+            assert t["elem_apply"] in (0, 1) and t["shared_cols"] in (0, 1) and t["fact_stash"] in (0, 1)
         x, inf = h.solve(torch.from_numpy(b).to(dev))
         x_or, inf_or = oracle.pcg(h_or, b)
         assert abs(inf[0].iters - inf_or.iters) <= 1
@@ -230,7 +230,7 @@ def test_set_level_tuning_round_trip_and_checks(dev):
         assert np.linalg.norm(x.cpu().numpy() - x_or) <= 1e-10 * np.linalg.norm(x_or)
         before = h.level_tuning(0)
         for bad in (dict(before, lanes=12), dict(before, tiles_per_item=3), dict(before, finalize_threads=16),
-                    dict(before, elem_apply=2), dict(before, shared_cols=3)):
+                    dict(before, elem_apply=2), dict(before, shared_cols=3), dict(before, fact_stash=2)):
             with pytest.raises(P.LsddError) as ei:
                 h.set_level_tuning(0, bad)
             assert ei.value.code == 1

@@ -102,6 +102,34 @@ def test_mixed_cycle_graddiv_vcycle_positive(dev):
             assert r @ z > 0
 
 
+@pytest.mark.parametrize("N", [16, 48])
+def test_factor_rows_kept_in_lds_change_nothing(dev, N):
+    """The mixed cycle's factor product with each tile row kept in LDS between its two
+    passes (fact_stash = 1; rows longer than the LDS capacity keep their first tiles)
+    gives V-cycles and PCG solves equal bit for bit to re-reading the rows (0), with 2
+    and 8 tiles per work item's partial layout, and on repeated application."""
+    import paper_2607_07485_amd as P
+    prob, b = fegen.graddiv_hdiv(N=N)
+    rng = np.random.default_rng(12)
+    r = torch.from_numpy(rng.standard_normal(prob.n)).to(dev)
+    bd = torch.from_numpy(b).to(dev)
+    with P.Hierarchy.setup_problem(prob, P.Params.default(precision=2, **GD_KW)) as h:
+        h.set_cycle_precision(2)
+        base = [h.level_tuning(l) for l in range(h.info()["levels"])]
+        for chl in (2, 8):
+            out = {}
+            for fs in (0, 1):
+                h.set_tuning([dict(t, tiles_per_item=chl, fact_stash=fs) for t in base])
+                z1, z2 = h.vcycle(r), h.vcycle(r)
+                x, inf = h.solve(bd)
+                assert inf[0].converged == 1
+                out[fs] = (z1, z2, x, inf[0].iters)
+            assert out[0][3] == out[1][3]
+            for a, c in zip(out[0][:3], out[1][:3]):
+                assert torch.equal(a, c), chl
+            assert torch.equal(out[1][0], out[1][1])
+
+
 def test_mixed_cycle_argument_checks(dev):
     import paper_2607_07485_amd as P
     prob, b = fegen.elasticity_small(N=8)
