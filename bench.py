@@ -161,6 +161,25 @@ def cpu_baseline(N_sample: int):
             "setup_s": t1 - t0}
 
 
+def _practical_read_gbs(torch):
+    """Measured read ceiling of this GPU: the fastest of five full reductions of a 2 GiB
+    FP64 tensor (torch's own sum, timed with events), in GB/s.  Context for the
+    roofline fractions, which stay against the published 8 TB/s."""
+    x = torch.ones(1 << 28, dtype=torch.float64, device="cuda:0")
+    best = float("inf")
+    for _ in range(6):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        x.sum()
+        e1.record()
+        e1.synchronize()
+        best = min(best, e0.elapsed_time(e1) * 1e-3)
+    n = x.numel() * 8
+    del x
+    torch.cuda.empty_cache()
+    return n / best / 1e9
+
+
 def _trace_dominant(h, torch, run):
     """Per-kernel HIP-event timing of one more run; returns (kernels dict, dominant (name, rec))."""
     h.trace(True)
@@ -754,6 +773,7 @@ def run_graddiv(a, torch, P, fegen, dev):
         cb = cpu_baseline(a.cpu_sample)
         print(f"[bench] cpu baseline {cb['sample']}", file=sys.stderr, flush=True)
 
+    practical = _practical_read_gbs(torch)
     workload = f"graddiv_rtcf3_{a.N}x{a.N}"
     vdt = "f64" if best == "fp64" else "f32+f64"
     rec = TRAFFIC.get((dname, workload, vdt))
@@ -776,9 +796,11 @@ def run_graddiv(a, torch, P, fegen, dev):
         "roofline": {"bound": "hbm", "kernel": dname, "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "algorithmic_bytes_per_launch": d["bytes"] / max(d["launches"], 1),
-                     "avg_launch_us": d["ms"] * 1e3 / max(d["launches"], 1)},
+                     "avg_launch_us": d["ms"] * 1e3 / max(d["launches"], 1),
+                     "practical_read_gbs": practical, "frac_of_practical": achieved / practical},
         "cycle_roofline": {"bound": "hbm", "achieved": cycle_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                            "frac": cycle_gbs / HBM_PEAK_GBS, "bytes_per_solve": solve_bytes,
+                           "practical_read_gbs": practical, "frac_of_practical": cycle_gbs / practical,
                            "what": "sum of the algorithmic bytes of every launch of one solve / solve time"},
         "kernels": kernels,
         "galerkin32": g32,

@@ -101,9 +101,14 @@ __global__ void __launch_bounds__(64) k_potrf_diag(double* base, const View* vie
     const int r0 = kb * TB, nb = min(TB, n - r0);
     const int i = t_id();
     double x[TB];
+    // every lane loads a full row of the block first (row and column clamped into
+    // the block, so the 64 loads are unconditional and in flight together), then
+    // keeps its lower part (identity rows past the block end)
+    const int ic = min(i, nb - 1);
 #pragma unroll
-    for (int k = 0; k < TB; ++k)
-        x[k] = (i < nb && k <= i) ? base[v.off + (r0 + i) + (int64_t)(r0 + k) * v.ld] : (k == i ? 1.0 : 0.0);
+    for (int k = 0; k < TB; ++k) x[k] = base[v.off + (r0 + ic) + (int64_t)(r0 + min(k, nb - 1)) * v.ld];
+#pragma unroll
+    for (int k = 0; k < TB; ++k) x[k] = (i < nb && k <= i) ? x[k] : (k == i ? 1.0 : 0.0);
     double dmin = INFINITY;
 #pragma unroll
     for (int j = 0; j < TB; ++j) {
@@ -186,6 +191,18 @@ __global__ void __launch_bounds__(NT) k_potrf_update(double* base, const View* v
     mg::d4 acc[2][2];
     mg::zero(acc);
     mg::tile_mma<mg::IMAJ, mg::IMAJ>(sm, pan, v.ld, ib * TB, n, pan, v.ld, jb * TB, n, 0, K, acc);
+    // the 16 old entries are loaded before any is used (addresses clamped into the
+    // matrix, so no load is conditional and none waits for the previous one)
+    double old[2][2][4];
+#pragma unroll
+    for (int p = 0; p < 2; ++p)
+#pragma unroll
+        for (int q = 0; q < 2; ++q)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int r = min(ib * TB + mg::acc_row(p, e), n - 1), c = min(jb * TB + mg::acc_col(q), n - 1);
+                old[p][q][e] = base[v.off + r + (int64_t)c * v.ld];
+            }
 #pragma unroll
     for (int p = 0; p < 2; ++p)
 #pragma unroll
@@ -194,7 +211,8 @@ __global__ void __launch_bounds__(NT) k_potrf_update(double* base, const View* v
             for (int e = 0; e < 4; ++e) {
                 const int i = mg::acc_row(p, e), j = mg::acc_col(q);
                 const int r = ib * TB + i, c = jb * TB + j;
-                if (r < n && c < n && (ib != jb || i >= j)) base[v.off + r + (int64_t)c * v.ld] -= acc[p][q][e];
+                if (r < n && c < n && (ib != jb || i >= j))
+                    base[v.off + r + (int64_t)c * v.ld] = old[p][q][e] - acc[p][q][e];
             }
 }
 
@@ -415,6 +433,16 @@ __global__ void __launch_bounds__(NT) k_trsm_update(const double* lbase, const V
         const double* lp = lbase + l.off + k0 * TB;                    // L[kb, :]: (k, i) at lp[k + i ld]
         mg::tile_mma<mg::KMAJ, mg::KMAJ>(sm, lp, l.ld, ib * TB, n, xk, b.ld, jc * TB, b.cols, 0, K, acc);
     }
+    double old[2][2][4];   // loaded before use, addresses clamped (no conditional loads)
+#pragma unroll
+    for (int p = 0; p < 2; ++p)
+#pragma unroll
+        for (int q = 0; q < 2; ++q)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int r = min(ib * TB + mg::acc_row(p, e), b.rows - 1), c = min(jc * TB + mg::acc_col(q), b.cols - 1);
+                old[p][q][e] = bbase[b.off + r + (int64_t)c * b.ld];
+            }
 #pragma unroll
     for (int p = 0; p < 2; ++p)
 #pragma unroll
@@ -422,7 +450,7 @@ __global__ void __launch_bounds__(NT) k_trsm_update(const double* lbase, const V
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
                 const int r = ib * TB + mg::acc_row(p, e), c = jc * TB + mg::acc_col(q);
-                if (r < b.rows && c < b.cols) bbase[b.off + r + (int64_t)c * b.ld] -= acc[p][q][e];
+                if (r < b.rows && c < b.cols) bbase[b.off + r + (int64_t)c * b.ld] = old[p][q][e] - acc[p][q][e];
             }
 }
 
@@ -449,10 +477,24 @@ __global__ void __launch_bounds__(NT) k_gemm_tn(const double* abase, const View*
     }
     const int kbeg = tri_k ? max(it, jt) * TB : 0;
     const View ci = civ[blockIdx.y];
-    auto put = [&](int r, int c, double s) {
+    // C_in entries are loaded for the whole tile before any is used (addresses clamped
+    // into C, so the loads are unconditional and issued back to back)
+    double cin[2][2][4];
+    auto load_cin = [&](auto row_of) {
+#pragma unroll
+        for (int p = 0; p < 2; ++p)
+#pragma unroll
+            for (int q = 0; q < 2; ++q)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int r = min(it * TB + row_of(p, e), co.rows - 1), c = min(jt * TB + mg::acc_col(q), co.cols - 1);
+                    cin[p][q][e] = beta != 0.0 ? cinbase[ci.off + r + (int64_t)c * ci.ld] : 0.0;
+                }
+    };
+    auto put = [&](int r, int c, double s, double old) {
         if (r < co.rows && c < co.cols) {
             double x = -alpha * s;
-            if (beta != 0.0) x += beta * cinbase[ci.off + r + (int64_t)c * ci.ld];
+            if (beta != 0.0) x += beta * old;
             coutbase[co.off + r + (int64_t)c * co.ld] = x;
             if (sym && it != jt) coutbase[co.off + c + (int64_t)r * co.ld] = x;
         }
@@ -462,25 +504,27 @@ __global__ void __launch_bounds__(NT) k_gemm_tn(const double* abase, const View*
         mg::zero32(acc);
         mg::tile_mma32<mg::KMAJ, mg::KMAJ>(sm, abase + a.off, a.ld, it * TB, a.cols, bbase + b.off, b.ld, jt * TB,
                                            b.cols, kbeg, a.rows, acc);
+        if (beta != 0.0) load_cin([](int p, int e) { return mg::acc_row32(p, e); });
 #pragma unroll
         for (int p = 0; p < 2; ++p)
 #pragma unroll
             for (int q = 0; q < 2; ++q)
 #pragma unroll
                 for (int e = 0; e < 4; ++e)
-                    put(it * TB + mg::acc_row32(p, e), jt * TB + mg::acc_col(q), (double)acc[p][q][e]);
+                    put(it * TB + mg::acc_row32(p, e), jt * TB + mg::acc_col(q), (double)acc[p][q][e], cin[p][q][e]);
     } else {
         mg::d4 acc[2][2];
         mg::zero(acc);
         mg::tile_mma<mg::KMAJ, mg::KMAJ>(sm, abase + a.off, a.ld, it * TB, a.cols, bbase + b.off, b.ld, jt * TB,
                                          b.cols, kbeg, a.rows, acc);
+        if (beta != 0.0) load_cin([](int p, int e) { return mg::acc_row(p, e); });
 #pragma unroll
         for (int p = 0; p < 2; ++p)
 #pragma unroll
             for (int q = 0; q < 2; ++q)
 #pragma unroll
                 for (int e = 0; e < 4; ++e)
-                    put(it * TB + mg::acc_row(p, e), jt * TB + mg::acc_col(q), acc[p][q][e]);
+                    put(it * TB + mg::acc_row(p, e), jt * TB + mg::acc_col(q), acc[p][q][e], cin[p][q][e]);
     }
 }
 

@@ -614,10 +614,21 @@ __device__ inline void wg_block_dots_mfma(mg::Smem& sm, const double* V, int n, 
 
 __device__ inline void wg_block_update_mfma(mg::Smem& sm, double* V, int n, int q0, int qn, int b0, int bn,
                                             const double* dd) {
+    if (bn <= 0) return;   // uniform over the workgroup
     for (int r0 = 0; r0 < n; r0 += mg::T) {
         mg::d4 acc[2][2];
         mg::zero(acc);
         mg::tile_mma<mg::IMAJ, mg::KMAJ>(sm, V + (long long)q0 * n + r0, n, 0, n - r0, dd, qn, 0, bn, 0, qn, acc);
+        double old[2][2][4];   // loaded before use, addresses clamped (no conditional loads)
+#pragma unroll
+        for (int p = 0; p < 2; ++p)
+#pragma unroll
+            for (int q = 0; q < 2; ++q)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int i = min(r0 + mg::acc_row(p, v), n - 1), t = min(mg::acc_col(q), bn - 1);
+                    old[p][q][v] = V[(long long)(b0 + t) * n + i];
+                }
 #pragma unroll
         for (int p = 0; p < 2; ++p)
 #pragma unroll
@@ -625,7 +636,7 @@ __device__ inline void wg_block_update_mfma(mg::Smem& sm, double* V, int n, int 
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
                     const int i = r0 + mg::acc_row(p, v), t = mg::acc_col(q);
-                    if (i < n && t < bn) V[(long long)(b0 + t) * n + i] -= acc[p][q][v];
+                    if (i < n && t < bn) V[(long long)(b0 + t) * n + i] = old[p][q][v] - acc[p][q][v];
                 }
     }
 }

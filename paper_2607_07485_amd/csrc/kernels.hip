@@ -1287,7 +1287,20 @@ __global__ void __launch_bounds__(WG) k_restrict(const int32_t* items, const int
     for (int c0 = 0; c0 < nw; c0 += 2048) {
         const int cn = min(2048, nw - c0);
         __syncthreads();
-        for (int a = tid(); a < cn; a += WG) s_t[a] = t[agg_dofs[a0 + c0 + a]];
+        // gather t over the chunk: all index loads, then all value loads (slots past the
+        // chunk re-read its last entry and are not stored), so the two dependent loads
+        // are paid once per four entries instead of once per entry
+        for (int b = tid(); b < cn; b += 4 * WG) {
+            int32_t d[4];
+            T tv[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) d[u] = agg_dofs[a0 + c0 + min(b + u * WG, cn - 1)];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) tv[u] = t[d[u]];
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                if (b + u * WG < cn) s_t[b + u * WG] = tv[u];
+        }
         __syncthreads();
         // the wave's 4 columns x 4 rows per lane in flight at once; out-of-range
         // columns and rows re-read an in-range entry and contribute zero

@@ -140,11 +140,20 @@ __global__ void __launch_bounds__(WG) k_trd_col(LocalArgs A, const int32_t* big,
         for (int u = 0; u < 8; ++u) aw[u] = av[u] = 0.0;
         for (int i = j + 1 + tid(); i < n; i += WG) {
             const double vi = x[i - j - 1];
+            // columns past p re-read column p - 1 (the loads stay unconditional and in
+            // flight together) and are not added
+            double ww[8], vv[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int64_t qc = min(q0 + u, p - 1);
+                ww[u] = m.W[i + qc * n];
+                vv[u] = m.V[i + qc * n];
+            }
 #pragma unroll
             for (int u = 0; u < 8; ++u)
                 if (q0 + u < p) {
-                    aw[u] += m.W[i + (int64_t)(q0 + u) * n] * vi;
-                    av[u] += m.V[i + (int64_t)(q0 + u) * n] * vi;
+                    aw[u] += ww[u] * vi;
+                    av[u] += vv[u] * vi;
                 }
         }
 #pragma unroll
@@ -244,6 +253,17 @@ __global__ void __launch_bounds__(WG) k_trd_update(LocalArgs A, const int32_t* b
     mg::zero(acc);
     mg::tile_mma<mg::IMAJ, mg::IMAJ>(sm, Vr, n, it * mg::T, M, Wr, n, jt * mg::T, M, 0, pc, acc);
     mg::tile_mma<mg::IMAJ, mg::IMAJ>(sm, Wr, n, it * mg::T, M, Vr, n, jt * mg::T, M, 0, pc, acc);
+    double old[2][2][4];   // loaded before use, addresses clamped (no conditional loads)
+#pragma unroll
+    for (int p = 0; p < 2; ++p)
+#pragma unroll
+        for (int q = 0; q < 2; ++q)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int64_t rr = r0 + min(it * mg::T + mg::acc_row(p, e), M - 1);
+                const int64_t cc = r0 + min(jt * mg::T + mg::acc_col(q), M - 1);
+                old[p][q][e] = m.a[rr + cc * n];
+            }
 #pragma unroll
     for (int p = 0; p < 2; ++p)
 #pragma unroll
@@ -253,7 +273,7 @@ __global__ void __launch_bounds__(WG) k_trd_update(LocalArgs A, const int32_t* b
                 const int i = it * mg::T + mg::acc_row(p, e), c = jt * mg::T + mg::acc_col(q);
                 if (i < M && c < M && i >= c) {
                     const int64_t rr = r0 + i, cc = r0 + c;
-                    const double x = m.a[rr + cc * n] - acc[p][q][e];
+                    const double x = old[p][q][e] - acc[p][q][e];
                     m.a[rr + cc * n] = x;
                     if (i != c) m.a[cc + rr * n] = x;
                 }
