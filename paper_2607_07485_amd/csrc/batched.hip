@@ -216,6 +216,51 @@ __global__ void __launch_bounds__(NT) k_potrf_update(double* base, const View* v
             }
 }
 
+// The trailing update of a panel group on 128 x 128 tiles: A[r, c] -= sum over the
+// group's columns k of L[r, k] L[c, k] for r >= c >= jt0 TB (lower triangle only).
+// Used where the trailing block spans several 128-row blocks.
+__global__ void __launch_bounds__(NT, 2) k_potrf_update2(double* base, const View* views, int kt0, int kt1, int jt0) {
+    __shared__ mg::Smem128 sm;
+    const View v = views[blockIdx.y];
+    const int n = v.rows;
+    const int K = min(kt1 * TB, n) - kt0 * TB;
+    const int r00 = jt0 * TB;
+    if (K <= 0 || r00 >= n) return;
+    const int m2 = (n - r00 + mg::T2 - 1) / mg::T2;
+    int job = (int)blockIdx.x;
+    if (job >= m2 * (m2 + 1) / 2) return;
+    int J = 0;
+    while (job >= m2 - J) {
+        job -= m2 - J;
+        ++J;
+    }
+    const int I = J + job;
+    const int rb = r00 + I * mg::T2, cb = r00 + J * mg::T2;
+    const double* pan = base + v.off + (int64_t)(kt0 * TB) * v.ld;
+    mg::d4 acc[4][4];
+    mg::zero(acc);
+    mg::tile_mma128<mg::IMAJ, mg::IMAJ>(sm, pan, v.ld, rb, n, pan, v.ld, cb, n, 0, K, acc);
+    // per block row: its 16 old entries loaded first (addresses clamped), then updated
+#pragma unroll
+    for (int p = 0; p < 4; ++p) {
+        double old[4][4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int r = min(rb + mg::acc_row2(p, e), n - 1), c = min(cb + mg::acc_col2(q), n - 1);
+                old[q][e] = base[v.off + r + (int64_t)c * v.ld];
+            }
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int r = rb + mg::acc_row2(p, e), c = cb + mg::acc_col2(q);
+                if (r < n && c < n && r >= c) base[v.off + r + (int64_t)c * v.ld] = old[q][e] - acc[p][q][e];
+            }
+    }
+}
+
 // ---------------------------------------------------------------- pivoted Cholesky of a trailing block
 
 // Largest value over [j, n) of d by one workgroup of NTH threads; among equal values
@@ -454,6 +499,46 @@ __global__ void __launch_bounds__(NT) k_trsm_update(const double* lbase, const V
             }
 }
 
+// Forward trailing update on 128 x 128 tiles: B[r, c] -= sum_{k in [kt0, kt1) tiles}
+// L[r, k] X[k, c] for rows r >= kt1 TB and columns c < ccap (lower_b: ccap = kt1 TB).
+__global__ void __launch_bounds__(NT, 2) k_trsm_update2(const double* lbase, const View* lv, double* bbase,
+                                                        const View* bv, int kt0, int kt1, int lower_b) {
+    __shared__ mg::Smem128 sm;
+    const View l = lv[blockIdx.y], b = bv[blockIdx.y];
+    const int n = l.rows;
+    const int K = min(kt1 * TB, n) - kt0 * TB;
+    const int r00 = kt1 * TB;
+    const int ccap = lower_b ? min(b.cols, kt1 * TB) : b.cols;
+    if (K <= 0 || r00 >= n || ccap <= 0) return;
+    const int nr2 = (n - r00 + mg::T2 - 1) / mg::T2, nc2 = (ccap + mg::T2 - 1) / mg::T2;
+    const int job = (int)blockIdx.x;
+    if (job >= nr2 * nc2) return;
+    const int rb = r00 + (job % nr2) * mg::T2, cb = (job / nr2) * mg::T2;
+    const double* lp = lbase + l.off + (int64_t)(kt0 * TB) * l.ld;   // L[:, kt0..]: (k, i) at lp[i + k ld]
+    const double* xk = bbase + b.off + kt0 * TB;                      // X rows kt0..: (k, j) at xk[k + j ld]
+    mg::d4 acc[4][4];
+    mg::zero(acc);
+    mg::tile_mma128<mg::IMAJ, mg::KMAJ>(sm, lp, l.ld, rb, n, xk, b.ld, cb, ccap, 0, K, acc);
+#pragma unroll
+    for (int p = 0; p < 4; ++p) {
+        double old[4][4];   // loaded first, addresses clamped (no conditional loads)
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int r = min(rb + mg::acc_row2(p, e), b.rows - 1), c = min(cb + mg::acc_col2(q), ccap - 1);
+                old[q][e] = bbase[b.off + r + (int64_t)c * b.ld];
+            }
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int r = rb + mg::acc_row2(p, e), c = cb + mg::acc_col2(q);
+                if (r < b.rows && c < ccap) bbase[b.off + r + (int64_t)c * b.ld] = old[q][e] - acc[p][q][e];
+            }
+    }
+}
+
 // ---------------------------------------------------------------- C = beta C_in - alpha A^T B
 
 template <bool F32>
@@ -525,6 +610,63 @@ __global__ void __launch_bounds__(NT) k_gemm_tn(const double* abase, const View*
 #pragma unroll
                 for (int e = 0; e < 4; ++e)
                     put(it * TB + mg::acc_row(p, e), jt * TB + mg::acc_col(q), acc[p][q][e], cin[p][q][e]);
+    }
+}
+
+// C = beta C_in - alpha A^T B on 128 x 128 tiles (FP64), as k_gemm_tn<false>
+__global__ void __launch_bounds__(NT, 2) k_gemm_tn2(const double* abase, const View* av, const double* bbase,
+                                                    const View* bv, const double* cinbase, const View* civ,
+                                                    double beta, double* coutbase, const View* cov, double alpha,
+                                                    int tri_k, int sym) {
+    __shared__ mg::Smem128 sm;
+    const View a = av[blockIdx.y], b = bv[blockIdx.y], co = cov[blockIdx.y];
+    const int mt = (co.rows + mg::T2 - 1) / mg::T2, ntt = (co.cols + mg::T2 - 1) / mg::T2;
+    int it, jt;
+    int job = (int)blockIdx.x;
+    if (sym) {
+        if (job >= mt * (mt + 1) / 2) return;
+        jt = 0;
+        while (job >= mt - jt) {
+            job -= mt - jt;
+            ++jt;
+        }
+        it = jt + job;
+    } else {
+        if (job >= mt * ntt) return;
+        it = job % mt;
+        jt = job / mt;
+    }
+    const int kbeg = tri_k ? max(it, jt) * mg::T2 : 0;
+    const View ci = civ[blockIdx.y];
+    mg::d4 acc[4][4];
+    mg::zero(acc);
+    mg::tile_mma128<mg::KMAJ, mg::KMAJ>(sm, abase + a.off, a.ld, it * mg::T2, a.cols, bbase + b.off, b.ld,
+                                        jt * mg::T2, b.cols, kbeg, a.rows, acc);
+#pragma unroll
+    for (int p = 0; p < 4; ++p) {
+        double old[4][4];   // C_in loaded first, addresses clamped (no conditional loads)
+        if (beta != 0.0) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int r = min(it * mg::T2 + mg::acc_row2(p, e), co.rows - 1);
+                    const int c = min(jt * mg::T2 + mg::acc_col2(q), co.cols - 1);
+                    old[q][e] = cinbase[ci.off + r + (int64_t)c * ci.ld];
+                }
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int r = it * mg::T2 + mg::acc_row2(p, e), c = jt * mg::T2 + mg::acc_col2(q);
+                if (r < co.rows && c < co.cols) {
+                    double x = -alpha * acc[p][q][e];
+                    if (beta != 0.0) x += beta * old[q][e];
+                    coutbase[co.off + r + (int64_t)c * co.ld] = x;
+                    if (sym && it != jt) coutbase[co.off + c + (int64_t)r * co.ld] = x;
+                }
+            }
     }
 }
 
@@ -613,8 +755,14 @@ void Batched::potrf(double* base, const std::vector<View>& a, double* d_minpiv) 
         }
         if (p1 < nt) {
             const int64_t m = nt - p1;
-            hipLaunchKernelGGL(k_potrf_update, dim3((unsigned)(m * (m + 1) / 2), nm), dim3(NT), 0, st, base, dv, p0,
-                               p1, p1, nt);
+            if (m >= 4) {      // at least two 128-row blocks: the 128 x 128 tiles
+                const int64_t m2 = (m + 1) / 2;
+                hipLaunchKernelGGL(k_potrf_update2, dim3((unsigned)(m2 * (m2 + 1) / 2), nm), dim3(NT), 0, st, base,
+                                   dv, p0, p1, p1);
+            } else {
+                hipLaunchKernelGGL(k_potrf_update, dim3((unsigned)(m * (m + 1) / 2), nm), dim3(NT), 0, st, base, dv,
+                                   p0, p1, p1, nt);
+            }
         }
     }
     chk(hipGetLastError(), "batched potrf");
@@ -697,9 +845,15 @@ void Batched::trsm(const double* lbase, const std::vector<View>& l, double* bbas
             }
             if (p1 < nt) {
                 const int cols = lower_b ? std::min(nct, p1) : nct;
-                const int64_t jobs = (int64_t)(nt - p1) * cols;
-                hipLaunchKernelGGL(k_trsm_update, dim3((unsigned)jobs, nm), dim3(NT), 0, st, lbase, d1, bbase, d2, p0,
-                                   p1, p1, nt, 0, 0, lower_b ? 1 : 0);
+                if (nt - p1 >= 4 && cols >= 2) {   // 128 x 128 tiles where the block is large enough
+                    const int64_t jobs = (int64_t)((nt - p1 + 1) / 2) * ((cols + 1) / 2);
+                    hipLaunchKernelGGL(k_trsm_update2, dim3((unsigned)jobs, nm), dim3(NT), 0, st, lbase, d1, bbase, d2,
+                                       p0, p1, lower_b ? 1 : 0);
+                } else {
+                    const int64_t jobs = (int64_t)(nt - p1) * cols;
+                    hipLaunchKernelGGL(k_trsm_update, dim3((unsigned)jobs, nm), dim3(NT), 0, st, lbase, d1, bbase, d2,
+                                       p0, p1, p1, nt, 0, 0, lower_b ? 1 : 0);
+                }
             }
         }
     }
@@ -723,6 +877,18 @@ void Batched::gemm_tn(const double* abase, const std::vector<View>& a, const dou
     }
     if (mt == 0) return;
     if (mt > INT32_MAX) throw std::runtime_error("batched gemm_tn: too many tiles");
+    int64_t mt2 = 0, big = 0;
+    for (const View& x : cout) {
+        const int64_t r = (x.rows + 127) / 128, c = (x.cols + 127) / 128;
+        mt2 = std::max(mt2, sym ? r * (r + 1) / 2 : r * c);
+        big = std::max<int64_t>(big, std::min(x.rows, x.cols));
+    }
+    if (!f32 && big >= 256) {   // 128 x 128 tiles once the outputs span several of them
+        hipLaunchKernelGGL(k_gemm_tn2, dim3((unsigned)mt2, nm), dim3(NT), 0, st, abase, d1, bbase, d2, cinbase, d4,
+                           beta, coutbase, d3, alpha, tri_k ? 1 : 0, sym ? 1 : 0);
+        chk(hipGetLastError(), "batched gemm_tn");
+        return;
+    }
     if (f32)
         hipLaunchKernelGGL(k_gemm_tn<true>, dim3((unsigned)mt, nm), dim3(NT), 0, st, abase, d1, bbase, d2, cinbase, d4,
                            beta, coutbase, d3, alpha, tri_k ? 1 : 0, sym ? 1 : 0);

@@ -198,5 +198,112 @@ __device__ inline int acc_row32(int p, int v) {
     return (w & 1) * 32 + 16 * p + 4 * (l >> 4) + v;
 }
 
+// ---------------------------------------------------------------- 128 x 128 tiles
+// The same contraction on a 128 x 128 output tile: each of the four waves owns a
+// 64 x 64 quarter as 4 x 4 blocks of 16 x 16, so every operand entry staged in
+// LDS feeds twice the products of the 64 x 64 tile and the operands cross the
+// memory hierarchy half as often per product.  K is staged in chunks of 16.
+
+constexpr int T2 = 128;
+constexpr int KC2 = 16;
+constexpr int LS2 = KC2 + 2;
+
+struct Smem128 {
+    double a[T2][LS2];
+    double b[T2][LS2];
+};
+
+// 8 elements of the 128 x 16 chunk per thread, reads contiguous along the fast index
+template <int LAY>
+__device__ inline void chunk_idx2(int q, int& i, int& k) {
+    const int t = (int)threadIdx.x;
+    if (LAY == KMAJ) {
+        k = t & 15;
+        i = (t >> 4) + 16 * q;
+    } else {
+        i = t & 127;
+        k = (t >> 7) + 2 * q;
+    }
+}
+
+template <int LAY>
+__device__ inline void fetch2(const double* __restrict__ p, int64_t ld, int i0, int ilim, int k0, int kend,
+                              double (&r)[8]) {
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        int i, k;
+        chunk_idx2<LAY>(q, i, k);
+        const int gi = i0 + i, gk = k0 + k;
+        double v = 0.0;
+        if (gi < ilim && gk < kend) v = (LAY == KMAJ) ? p[gk + (int64_t)gi * ld] : p[gi + (int64_t)gk * ld];
+        r[q] = v;
+    }
+}
+
+template <int LAY>
+__device__ inline void stash2(double (*s)[LS2], const double (&r)[8]) {
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        int i, k;
+        chunk_idx2<LAY>(q, i, k);
+        s[i][k] = r[q];
+    }
+}
+
+__device__ inline void zero(d4 (&acc)[4][4]) {
+#pragma unroll
+    for (int p = 0; p < 4; ++p)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) acc[p][q] = d4{0.0, 0.0, 0.0, 0.0};
+}
+
+// acc += sum over k in [kbeg, kend) of a(k, m0 + .) b(k, n0 + .) on a 128 x 128
+// tile.  Must be called by all 256 threads.
+template <int LA, int LB>
+__device__ inline void tile_mma128(Smem128& sm, const double* __restrict__ a, int64_t lda, int m0, int M,
+                                   const double* __restrict__ b, int64_t ldb, int n0, int N, int kbeg, int kend,
+                                   d4 (&acc)[4][4]) {
+    if (kbeg >= kend) return;
+    const int w = (int)threadIdx.x >> 6, l = (int)threadIdx.x & 63;
+    const int wr = (w & 1) * 64, wc = (w >> 1) * 64;
+    const int lm = l & 15, lk = l >> 4;
+    double ra[8], rb[8];
+    fetch2<LA>(a, lda, m0, M, kbeg, kend, ra);
+    fetch2<LB>(b, ldb, n0, N, kbeg, kend, rb);
+    for (int k0 = kbeg; k0 < kend; k0 += KC2) {
+        __syncthreads();
+        stash2<LA>(sm.a, ra);
+        stash2<LB>(sm.b, rb);
+        __syncthreads();
+        if (k0 + KC2 < kend) {
+            fetch2<LA>(a, lda, m0, M, k0 + KC2, kend, ra);
+            fetch2<LB>(b, ldb, n0, N, k0 + KC2, kend, rb);
+        }
+#pragma unroll
+        for (int kk = 0; kk < KC2; kk += 4) {
+            double fa[4], fb[4];
+#pragma unroll
+            for (int p = 0; p < 4; ++p) fa[p] = sm.a[wr + 16 * p + lm][kk + lk];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) fb[q] = sm.b[wc + 16 * q + lm][kk + lk];
+#pragma unroll
+            for (int p = 0; p < 4; ++p)
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    acc[p][q] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[p], fb[q], acc[p][q], 0, 0, 0);
+        }
+    }
+}
+
+// position inside the 128 x 128 tile of accumulator register v of block (p, q)
+__device__ inline int acc_row2(int p, int v) {
+    const int w = (int)threadIdx.x >> 6, l = (int)threadIdx.x & 63;
+    return (w & 1) * 64 + 16 * p + (l >> 4) + 4 * v;
+}
+__device__ inline int acc_col2(int q) {
+    const int w = (int)threadIdx.x >> 6, l = (int)threadIdx.x & 63;
+    return (w >> 1) * 64 + 16 * q + (l & 15);
+}
+
 }  // namespace mg
 }  // namespace lsdd
