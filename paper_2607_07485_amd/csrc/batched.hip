@@ -219,8 +219,10 @@ __global__ void __launch_bounds__(NT) k_potrf_update(double* base, const View* v
 // The trailing update of a panel group on 128 x 128 tiles: A[r, c] -= sum over the
 // group's columns k of L[r, k] L[c, k] for r >= c >= jt0 TB (lower triangle only).
 // Used where the trailing block spans several 128-row blocks.
-__global__ void __launch_bounds__(NT, 2) k_potrf_update2(double* base, const View* views, int kt0, int kt1, int jt0) {
+__global__ void __launch_bounds__(NT, 2) k_potrf_update2(double* base, const View* views, int kt0, int kt1, int jt0,
+                                                         const int32_t* skip = nullptr) {
     __shared__ mg::Smem128 sm;
+    if (skip && skip[blockIdx.y]) return;
     const View v = views[blockIdx.y];
     const int n = v.rows;
     const int K = min(kt1 * TB, n) - kt0 * TB;
@@ -800,9 +802,14 @@ void Batched::pstrf_trailing(double* base, const std::vector<View>& a, const std
         hipLaunchKernelGGL(k_pstrf_panel, dim3(1, nm), dim3(NTP), 0, st, base, dv, d_lead, kb, d_tol, d_doff, d_diag,
                            d_perm, d_rank, d_done);
         const int64_t m = nt - kb - 1;
-        if (m > 0)
+        if (m >= 4) {
+            const int64_t m2 = (m + 1) / 2;
+            hipLaunchKernelGGL(k_potrf_update2, dim3((unsigned)(m2 * (m2 + 1) / 2), nm), dim3(NT), 0, st, base, dg,
+                               kb, kb + 1, kb + 1, (const int32_t*)d_done);
+        } else if (m > 0) {
             hipLaunchKernelGGL(k_potrf_update, dim3((unsigned)(m * (m + 1) / 2), nm), dim3(NT), 0, st, base, dg, kb,
                                kb + 1, kb + 1, nt, (const int32_t*)d_done);
+        }
     }
     chk(hipGetLastError(), "batched pstrf");
     chk(hipMemcpyAsync(rank.data(), d_rank, nv * sizeof(int32_t), hipMemcpyDeviceToHost, st), "pstrf rank");
