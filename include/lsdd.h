@@ -328,7 +328,9 @@ lsdd_status lsdd_level_segments(const lsdd_hierarchy* h, int32_t level, int64_t*
  * triangles of the A_e, built on the first call (one FP64 triangle per element, plus
  * an FP32 copy when the hierarchy has an FP32 cycle), and keeps the faster; on levels
  * whose rows share per-supernode column lists it times the CSR kernels with and
- * without them; in the mixed cycle it times the factor product with and without its
+ * without them, and for single vectors the sweep residuals by supernode row blocks
+ * (1, 2 or 4 waves per run of up to 8 sweep rows of one supernode, x gathered once
+ * per run and wave; another order of the cross-lane sums); in the mixed cycle it times the factor product with and without its
  * tile rows kept in LDS.  block
  * != 0 tunes the shapes of the 8-right-hand-side blocks, 0 those of single vectors,
  * for the current cycle precision.  The choice changes only the summation order of
@@ -340,7 +342,9 @@ lsdd_status lsdd_autotune(lsdd_hierarchy* h, int32_t block, void* hip_stream);
  * vectors from the element triangles (1) or the CSR (0), whether the CSR kernels
  * read one shared column list per supernode (1) instead of a column index per entry
  * (0; available where the level's pattern is built on supernodes, i.e. every row of
- * a supernode has the same columns; same results), and whether the mixed cycle's
+ * a supernode has the same columns; same results) -- 2, 3, 4: the lists as with 1,
+ * and the single-vector sweep residuals by supernode row blocks of 1, 2 or 4 waves
+ * (where the level has sweeps) --, and whether the mixed cycle's
  * factor product keeps each tile row in LDS between its two passes (1) or reads it
  * again through the caches (0; same results). */
 lsdd_status lsdd_level_tuning(const lsdd_hierarchy* h, int32_t level, int32_t* out);
@@ -350,7 +354,8 @@ lsdd_status lsdd_level_tuning(const lsdd_hierarchy* h, int32_t level, int32_t* o
  * must be one of the autotuner's candidates (else LSDD_E_INVAL, nothing changed);
  * tiles per work item is ignored on the coarsest level; element products on a level
  * other than 0, on a hierarchy without element blocks or with an element above 128
- * DOFs, or shared column lists on a level without them -> LSDD_E_UNSUPPORTED (the
+ * DOFs, or shared column lists (row blocks) on a level without them ->
+ * LSDD_E_UNSUPPORTED (the
  * triangles are built on first use).  Captured PCG graphs are
  * dropped and recaptured on the next solve.  Like lsdd_autotune, it changes only the
  * summation order of the sums involved. */

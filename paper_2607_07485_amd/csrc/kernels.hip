@@ -781,6 +781,98 @@ __global__ void __launch_bounds__(WG) k_csr_resid_rows(int64_t nrows, const int3
     }
 }
 
+// The residual rows of a supernode-blocked level by row blocks.  Block b is the run
+// of list positions blk[2b] .. blk[2b] + blk[2b+1] - 1 (1 to 8 of them) whose rows
+// belong to one supernode and so share one column list.  WPB waves of one workgroup
+// per block split its column list in chunks of 128; per chunk a wave gathers x once
+// and streams the (up to) 8 value rows against it, so the column indices and the
+// gathered x cost one cache read per block instead of one per row.  A block of
+// fewer than 8 rows repeats its last row in the spare slots (same addresses, never
+// stored).  out[t] as in k_csr_resid_rows; every product and the per-lane sums as
+// there, the cross-lane and cross-wave sums in another (fixed) order.
+template <typename T, typename V, int WPB>
+__global__ void __launch_bounds__(WG) k_sup_resid_blocks(int64_t nblk, const int32_t* blk, const int32_t* rows,
+                                                         const int64_t* rowptr, const int32_t* scol,
+                                                         const int64_t* scoff, const V* val, const T* x, const T* r,
+                                                         T* out, int x_zero) {
+    constexpr int RB = 8, U = 2, NW = WG / 64, BPW = NW / WPB;   // blocks per workgroup
+    __shared__ V red[NW][RB];
+    const int lane = tid() & 63, wave = tid() >> 6, wb = wave % WPB;
+    const int j = (lane >> 3) & 7;   // the row whose sum lane j*8 ends with
+    // the loop runs alike in every wave of the workgroup (barriers below)
+    for (int64_t base = (int64_t)blockIdx.x * BPW; base < nblk; base += (int64_t)gridDim.x * BPW) {
+        const int64_t b = base + wave / WPB;
+        const bool act = b < nblk;
+        int32_t t0 = 0, nb = 0;
+        V a1 = 0;
+        if (act) {
+            t0 = blk[2 * b];
+            nb = blk[2 * b + 1];
+            const int32_t p0 = rows[t0];
+            const int64_t qb = rowptr[p0], len = rowptr[p0 + 1] - qb;
+            V s[RB];
+#pragma unroll
+            for (int i = 0; i < RB; ++i) s[i] = 0;
+            if (!x_zero) {
+                const V* vr[RB];
+#pragma unroll
+                for (int i = 0; i < RB; ++i) vr[i] = val + rowptr[rows[t0 + min(i, nb - 1)]];
+                const int32_t* cl = scol + scoff[p0];
+                for (int64_t q0 = lane + wb * U * 64; q0 < len; q0 += WPB * U * 64) {
+                    int64_t qq[U];
+                    int32_t c[U];
+                    V v[RB][U];
+                    T xv[U];
+#pragma unroll
+                    for (int u = 0; u < U; ++u) {
+                        qq[u] = min(q0 + u * 64, len - 1);
+                        c[u] = cl[qq[u]];
+                    }
+#pragma unroll
+                    for (int i = 0; i < RB; ++i)
+#pragma unroll
+                        for (int u = 0; u < U; ++u) v[i][u] = __builtin_nontemporal_load(vr[i] + qq[u]);
+#pragma unroll
+                    for (int u = 0; u < U; ++u) xv[u] = x[c[u]];
+#pragma unroll
+                    for (int u = 0; u < U; ++u) {
+                        const bool in = q0 + u * 64 < len;
+#pragma unroll
+                        for (int i = 0; i < RB; ++i) s[i] += (in ? v[i][u] : (V)0) * (V)xv[u];
+                    }
+                }
+            }
+            // the 8 sums over the wave: exchanges over lane distances 32, 16, 8 halve
+            // the rows each lane carries (lane l ends with row j over 8 lanes), then
+            // distances 4, 2, 1 finish each row's sum
+            const bool h32 = lane & 32, h16 = lane & 16, h8 = lane & 8;
+            V a4[4], a2[2];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) a4[i] = (h32 ? s[i + 4] : s[i]) + __shfl_xor(h32 ? s[i] : s[i + 4], 32);
+#pragma unroll
+            for (int i = 0; i < 2; ++i) a2[i] = (h16 ? a4[i + 2] : a4[i]) + __shfl_xor(h16 ? a4[i] : a4[i + 2], 16);
+            a1 = (h8 ? a2[1] : a2[0]) + __shfl_xor(h8 ? a2[0] : a2[1], 8);
+            a1 += __shfl_xor(a1, 4);
+            a1 += __shfl_xor(a1, 2);
+            a1 += __shfl_xor(a1, 1);
+        }
+        if constexpr (WPB > 1) {
+            // the block's waves in order, summed by its first wave
+            if ((lane & 7) == 0) red[wave][j] = a1;
+            __syncthreads();
+            if (wb == 0) {
+#pragma unroll
+                for (int w = 1; w < WPB; ++w) a1 += red[wave + w][j];
+            }
+            __syncthreads();
+        }
+        if (act && wb == 0 && (lane & 7) == 0 && j < nb) {
+            const int32_t pj = rows[t0 + j];
+            out[t0 + j] = (T)((V)r[pj] - a1);
+        }
+    }
+}
+
 // y = A x, or y = r_minus - A x when r_minus != nullptr (values of type V as in
 // k_csr_resid_rows)
 template <typename T, typename V, int L>
@@ -1663,6 +1755,22 @@ void launch_csr_resid_rows(int64_t nrows, const int32_t* rows, const int64_t* ro
                            rowptr, col, val, x, r, out, xz, scoff);
 }
 template <typename T, typename V>
+void launch_sup_resid_blocks(int64_t nblk, const int32_t* blk, const int32_t* rows, const int64_t* rowptr,
+                             const int32_t* scol, const int64_t* scoff, const V* val, const T* x, const T* r, T* out,
+                             bool x_zero, int waves, hipStream_t st) {
+    if (nblk <= 0) return;
+    const int xz = x_zero ? 1 : 0;
+    if (waves >= 4)
+        hipLaunchKernelGGL((k_sup_resid_blocks<T, V, 4>), dim3(grid_for(nblk * 256)), dim3(WG), 0, st, nblk, blk,
+                           rows, rowptr, scol, scoff, val, x, r, out, xz);
+    else if (waves >= 2)
+        hipLaunchKernelGGL((k_sup_resid_blocks<T, V, 2>), dim3(grid_for(nblk * 128)), dim3(WG), 0, st, nblk, blk,
+                           rows, rowptr, scol, scoff, val, x, r, out, xz);
+    else
+        hipLaunchKernelGGL((k_sup_resid_blocks<T, V, 1>), dim3(grid_for(nblk * 64)), dim3(WG), 0, st, nblk, blk,
+                           rows, rowptr, scol, scoff, val, x, r, out, xz);
+}
+template <typename T, typename V>
 void launch_csr_spmv(int64_t n, const int64_t* rowptr, const int32_t* col, const V* val, const T* x, T* y,
                      const T* r_minus, int lanes, hipStream_t st, const int64_t* scoff) {
     if (n <= 0) return;
@@ -1819,6 +1927,9 @@ void launch_check_finite(int64_t n, const double* a, int32_t* flag, hipStream_t 
 #define LSDD_INST(T)                                                                                                  \
     template void launch_csr_resid_rows<T, T>(int64_t, const int32_t*, const int64_t*, const int32_t*, const T*,     \
                                               const T*, const T*, T*, bool, int, hipStream_t, const int64_t*);        \
+    template void launch_sup_resid_blocks<T, T>(int64_t, const int32_t*, const int32_t*, const int64_t*,              \
+                                                const int32_t*, const int64_t*, const T*, const T*, const T*, T*,    \
+                                                bool, int, hipStream_t);                                              \
     template void launch_csr_spmv<T, T>(int64_t, const int64_t*, const int32_t*, const T*, const T*, T*, const T*,    \
                                         int, hipStream_t, const int64_t*);                                            \
     template void launch_sub_symv<T>(int64_t, const int32_t*, const int64_t*, const int64_t*, const T*, const T*,    \
@@ -1835,6 +1946,9 @@ LSDD_INST(float)
 template void launch_csr_resid_rows<float, double>(int64_t, const int32_t*, const int64_t*, const int32_t*,
                                                    const double*, const float*, const float*, float*, bool, int,
                                                    hipStream_t, const int64_t*);
+template void launch_sup_resid_blocks<float, double>(int64_t, const int32_t*, const int32_t*, const int64_t*,
+                                                     const int32_t*, const int64_t*, const double*, const float*,
+                                                     const float*, float*, bool, int, hipStream_t);
 template void launch_csr_spmv<float, double>(int64_t, const int64_t*, const int32_t*, const double*, const float*,
                                              float*, const float*, int, hipStream_t, const int64_t*);
 

@@ -180,6 +180,14 @@ template <typename T, typename V = T>
 void launch_csr_resid_rows(int64_t nrows, const int32_t* rows, const int64_t* rowptr, const int32_t* col,
                            const V* val, const T* x, const T* r, T* out, bool x_zero, int lanes, hipStream_t st,
                            const int64_t* scoff = nullptr);
+// residual rows of a supernode-blocked level by row blocks of one supernode (blk:
+// per block the first list position and the row count, 1..8; rows, out: the whole
+// list); scol/scoff as the shared column lists of launch_csr_resid_rows; waves (1,
+// 2 or 4) per block
+template <typename T, typename V = T>
+void launch_sup_resid_blocks(int64_t nblk, const int32_t* blk, const int32_t* rows, const int64_t* rowptr,
+                             const int32_t* scol, const int64_t* scoff, const V* val, const T* x, const T* r, T* out,
+                             bool x_zero, int waves, hipStream_t st);
 template <typename T, typename V = T>
 void launch_csr_spmv(int64_t n, const int64_t* rowptr, const int32_t* col, const V* val, const T* x, T* y,
                      const T* r_minus, int lanes, hipStream_t st, const int64_t* scoff = nullptr);

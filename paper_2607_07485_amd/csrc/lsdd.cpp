@@ -178,7 +178,13 @@ struct Level {
     int32_t* d_scol = nullptr;        // the lists, one per supernode
     int64_t* d_scoff = nullptr;       // per row: start of its supernode's list
     double sup_ib = 4.0;              // column-index bytes per entry read from HBM with the lists
-    int sup = 0;                      // 1: single-vector CSR kernels read the shared lists
+    int sup = 0;                      // 1: single-vector CSR kernels read the shared lists; 2, 3, 4: and
+                                      // the sweep residuals run by supernode row blocks, 1, 2 or 4
+                                      // waves per block
+    // row blocks of the sweep lists: (first list position, rows 1..8) per run of
+    // list entries of one supernode, grouped by colour
+    int32_t* d_rblk = nullptr;
+    std::vector<int64_t> color_rblk0;
     float* d_val32 = nullptr;
     // level-0 Gram factors
     double* d_G = nullptr;
@@ -1236,6 +1242,25 @@ std::unique_ptr<Level> coarsen(lsdd_hierarchy* h, Level& lv, const int32_t* agg_
              lv.color_sub0[c + 1] - lv.color_smid[c], lv.color_pk[c] * 8e-6);
     lv.d_sw_sub_off = ar.upload(lv.sw_sub_off, st);
     lv.d_sw_sub_dofs = ar.upload(sw_dofs, st);
+    if (lv.d_scoff && (int64_t)lv.node_of_dof.size() == lv.n && sw_dofs.size() < (size_t)INT32_MAX) {
+        // supernode row blocks of the sweep list: runs of up to 8 entries of one
+        // colour whose rows belong to one supernode (so share one column list)
+        std::vector<int32_t> rb;
+        lv.color_rblk0.assign(lv.n_colors + 1, 0);
+        for (int32_t c = 0; c < lv.n_colors; ++c) {
+            const int64_t t1 = lv.color_row0[c + 1];
+            for (int64_t t = lv.color_row0[c]; t < t1;) {
+                const int32_t sn = lv.node_of_dof[sw_dofs[t]];
+                int64_t e = t + 1;
+                while (e < t1 && e - t < 8 && lv.node_of_dof[sw_dofs[e]] == sn) ++e;
+                rb.push_back((int32_t)t);
+                rb.push_back((int32_t)(e - t));
+                t = e;
+            }
+            lv.color_rblk0[c + 1] = (int64_t)rb.size() / 2;
+        }
+        lv.d_rblk = ar.upload(rb, st);
+    }
     if (P.smoother == 1) lv.d_sw_sub_dofs_w = ar.upload(sw_dofs_w, st);
     lv.d_sw_tp_off = ar.upload(sw_tp_off, st);
     lv.d_items = ar.upload(items, st);
@@ -1522,6 +1547,26 @@ struct Cyc {
             launch_csr_resid_rows_b<T>(nrows, rows, lv.d_rowptr, lv.sup ? lv.d_scol : lv.d_col, val, x, r, out, xz,
                                        lv.lanes_b, st, lv.sup ? lv.d_scoff : nullptr);
     }
+    // the residual rows of colour c of a sweep into rloc (indexed like the whole
+    // sweep list), values of type V; by supernode row blocks where chosen
+    template <typename V>
+    static void resid_colour(Level& lv, int32_t c, const V* val, const T* x, const T* r, T* rloc, bool xz,
+                             hipStream_t st) {
+        const int64_t r0 = lv.color_row0[c], r1 = lv.color_row0[c + 1];
+        if constexpr (NR == 1) {
+            if (lv.sup >= 2 && lv.d_rblk) {
+                const int64_t b0 = lv.color_rblk0[c];
+                launch_sup_resid_blocks<T, V>(lv.color_rblk0[c + 1] - b0, lv.d_rblk + 2 * b0, lv.d_sw_sub_dofs,
+                                              lv.d_rowptr, lv.d_scol, lv.d_scoff, val, x, r, rloc, xz,
+                                              1 << (lv.sup - 2), st);
+                return;
+            }
+            launch_csr_resid_rows<T, V>(r1 - r0, lv.d_sw_sub_dofs + r0, lv.d_rowptr, lv.sup ? lv.d_scol : lv.d_col,
+                                        val, x, r, rloc + r0, xz, lv.lanes, st, lv.sup ? lv.d_scoff : nullptr);
+        } else {
+            resid_rows(r1 - r0, lv.d_sw_sub_dofs + r0, lv, val, x, r, rloc + r0 * NR, xz, st);
+        }
+    }
     // y = A x or r_minus - A x with the level's entries of type T (val), or from its
     // element triangles of the same precision when the autotuner chose them
     static void spmv(Level& lv, const T* val, const T* x, T* y, const T* r_minus, hipStream_t st) {
@@ -1648,9 +1693,7 @@ void sweep_factor(lsdd_hierarchy* h, Level& lv, const float* r, float* x, bool f
         const bool xz = x_zero_first && cc == 0;
         const double rb = lv.color_m[c] * (4 + 8 + 3 * 4.0) + (xz ? 0.0 : lv.color_nnz[c] * ((lv.sup ? lv.sup_ib : 4.0) + 8.0));
         traced(h, "csr_resid_rows", rb, [&] {
-            launch_csr_resid_rows<float, double>(r1 - r0, lv.d_sw_sub_dofs + r0, lv.d_rowptr,
-                                                 lv.sup ? lv.d_scol : lv.d_col, lv.d_val, x, r, v.rloc + r0, xz,
-                                                 lv.lanes, h->st, lv.sup ? lv.d_scoff : nullptr);
+            Cyc<float, 1>::resid_colour<double>(lv, c, lv.d_val, x, r, v.rloc, xz, h->st);
         });
         const int64_t j0 = lv.color_ritem0[c], j1 = lv.color_ritem0[c + 1];
         if (j1 > j0) {
@@ -1699,7 +1742,7 @@ void sweep(lsdd_hierarchy* h, Level& lv, const T* r, T* x, bool forward, bool x_
         const double rb = lv.color_m[c] * (4 + 8 + 3 * wv) +
                           (xz ? 0.0 : lv.color_nnz[c] * ((lv.sup ? lv.sup_ib : 4.0) + w));
         traced(h, "csr_resid_rows", rb, [&] {
-            C::resid_rows(r1 - r0, lv.d_sw_sub_dofs + r0, lv, O::val(lv), x, r, v.rloc + r0 * NR, xz, h->st);
+            C::template resid_colour<T>(lv, c, O::val(lv), x, r, v.rloc, xz, h->st);
         });
         if (i1 > i0) {
             const double gb = lv.color_m2[c] * w + (double)(rm - r0) * (4 + 3 * wv);
@@ -2032,22 +2075,33 @@ void autotune_levels(lsdd_hierarchy* h) {
         const std::vector<int> lane_c = NR > 1 ? std::vector<int>{4, 8, 16, 32, 64} : std::vector<int>{8, 16, 32, 64};
         double best = 1e300;
         int pick = lanes, pick_sup = 0;
-        // single vectors on a supernode-blocked level: also with the shared column lists
-        for (int sp : lv.d_scoff ? std::vector<int>{0, 1} : std::vector<int>{0}) {
+        const int prev_sup = lv.sup;
+        // a supernode-blocked level: also with the shared column lists and, for single
+        // vectors, by supernode row blocks of 1, 2 or 4 waves
+        std::vector<int> sup_c{0};
+        if (lv.d_scoff) sup_c.push_back(1);
+        if (lv.d_scoff && lv.d_rblk && NR == 1) sup_c.insert(sup_c.end(), {2, 3, 4});
+        for (int sp : sup_c) {
             lv.sup = sp;
             for (int L : lane_c) {
                 lanes = L;
                 const double ms = time_ms(h, [&] {
                     for (int32_t c = 0; c < lv.n_colors; ++c)
-                        C::resid_rows(lv.color_row0[c + 1] - lv.color_row0[c], lv.d_sw_sub_dofs + lv.color_row0[c],
-                                      lv, O::val(lv), v.x, v.r, v.rloc + lv.color_row0[c] * NR, false, h->st);
+                        C::template resid_colour<T>(lv, c, O::val(lv), v.x, v.r, v.rloc, false, h->st);
                 });
+                if (sp >= 2) {
+                    vlog("autotune level %d: supernode row blocks, %d wave(s) each: %.3f ms", lv.level,
+                         1 << (sp - 2), ms);
+                    if (ms < best) best = ms, pick = lanes, pick_sup = sp;
+                    break;
+                }
                 vlog("autotune level %d: CSR lanes %d%s: %.3f ms", lv.level, L, sp ? ", shared column lists" : "", ms);
                 if (ms < best) best = ms, pick = L, pick_sup = sp;
             }
         }
         lanes = pick;
-        lv.sup = pick_sup;
+        // blocks of vectors read the lists alike for 1 and 2: keep a single-vector choice of row blocks
+        lv.sup = (NR > 1 && pick_sup == 1 && prev_sup >= 2) ? prev_sup : pick_sup;
         if (NR == 1 && build_elem_apply(h, lv)) {
             // the full product (pre-restriction residual, PCG) from the CSR or the element triangles
             best = 1e300;
@@ -2857,11 +2911,13 @@ lsdd_status lsdd_set_level_tuning(lsdd_hierarchy* h, int32_t level, const int32_
         return std::find(ok.begin(), ok.end(), v) != ok.end();
     };
     if (!one_of(in[0], {8, 16, 32, 64}) || !one_of(in[1], {4, 8, 16, 32, 64}) || !one_of(in[2], {2, 4, 8}) ||
-        !one_of(in[3], {8, 32}) || !one_of(in[4], {0, 1}) || !one_of(in[5], {0, 1}) || !one_of(in[6], {0, 1}))
+        !one_of(in[3], {8, 32}) || !one_of(in[4], {0, 1}) || !one_of(in[5], {0, 1, 2, 3, 4}) || !one_of(in[6], {0, 1}))
         throw Error(LSDD_E_INVAL, "launch shape outside the autotuner's candidates");
     Level& lv = *h->L[level];
     if (in[5] && !lv.d_scoff)
         throw Error(LSDD_E_UNSUPPORTED, "shared column lists: the level's pattern is not supernode-blocked");
+    if (in[5] >= 2 && !lv.d_rblk)
+        throw Error(LSDD_E_UNSUPPORTED, "supernode row blocks: the level has no sweep row blocks");
     if (in[4] && !build_elem_apply(h, lv))
         throw Error(LSDD_E_UNSUPPORTED, "element apply: only on level 0 of a hierarchy built from element blocks "
                                         "of at most 128 DOFs");
