@@ -230,7 +230,7 @@ def test_set_level_tuning_round_trip_and_checks(dev):
         assert np.linalg.norm(x.cpu().numpy() - x_or) <= 1e-10 * np.linalg.norm(x_or)
         before = h.level_tuning(0)
         for bad in (dict(before, lanes=12), dict(before, tiles_per_item=3), dict(before, finalize_threads=16),
-                    dict(before, elem_apply=2), dict(before, shared_cols=3), dict(before, fact_stash=2)):
+                    dict(before, elem_apply=2), dict(before, shared_cols=5), dict(before, fact_stash=2)):
             with pytest.raises(P.LsddError) as ei:
                 h.set_level_tuning(0, bad)
             assert ei.value.code == 1
