@@ -23,6 +23,19 @@ namespace {
 constexpr int WG = LSDD_WG;
 constexpr int NB = NRB;
 
+// compute units of the current device (queried once per device)
+int device_cu_count() {
+    static int count[64] = {};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+    if (!count[dev]) {
+        int n = 0;
+        if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n < 1) n = 256;
+        count[dev] = n;
+    }
+    return count[dev];
+}
+
 inline unsigned grid_for(int64_t n, int per_block = WG) {
     int64_t g = (n + per_block - 1) / per_block;
     if (g < 1) g = 1;
@@ -452,67 +465,114 @@ __global__ void __launch_bounds__(WG) k_prolong_b(const int32_t* items, const in
 // overlaps leave room for more waves per CU.  FACT: the packed triangle is a
 // lower-triangular factor X and the local solve is X^T (X r): lane i first forms
 // w_i = sum_{j <= i} X_ij r_j into LDS, then y_i = sum_{j >= i} X_ji w_j.
+//
+// Persistent waves: wave b takes subdomains b, b + gridDim.x, ...; the triangle and
+// right-hand sides of the next subdomain are loaded into registers while the
+// current one is computed from LDS, so the loads of one subdomain overlap the
+// arithmetic of the previous one.  Loads go in groups of 8 per lane, a group only
+// where the subdomain reaches it; inside a group a slot past the end re-reads the
+// last entry (same cache line) and is never stored.
 template <typename T, int NR, bool FACT>
-__global__ void __launch_bounds__(64) k_small_sub(int32_t s0, const int64_t* sub_off, const int32_t* sub_dofs,
-                                                  const int64_t* pk_off, const T* pk, const T* rloc, T* x,
-                                                  int max_m) {
+__global__ void __launch_bounds__(64) k_small_sub(int32_t s0, int32_t n_sub, const int64_t* sub_off,
+                                                  const int32_t* sub_dofs, const int64_t* pk_off, const T* pk,
+                                                  const T* rloc, T* x, int max_m) {
+    constexpr int PG = 8;
+    constexpr int PMAX = ((SMALL_M * (SMALL_M + 1) / 2 + 63) / 64 + PG - 1) / PG * PG;   // triangle loads per lane
+    constexpr int XMAX = ((SMALL_M * NR + 63) / 64 + PG - 1) / PG * PG;                   // rhs loads per lane
     extern __shared__ __align__(16) unsigned char s_small[];
     T* s_a = reinterpret_cast<T*>(s_small);
     T* s_x = s_a + max_m * (max_m + 1) / 2;
     T* s_w = s_x + max_m * NR;
-    const int s = s0 + blockIdx.x;
     const int lane = tid();
-    const int64_t o = sub_off[s];
-    const int m = (int)(sub_off[s + 1] - o);
-    const T* A = pk + pk_off[s];
-    const int np = m * (m + 1) / 2;
-    for (int e = lane; e < np; e += 64) s_a[e] = A[e];
-    for (int e = lane; e < m * NR; e += 64) s_x[e] = rloc[o * NR + e];
-    __syncthreads();
+    T ra[PMAX], rx[XMAX];
+    int64_t o_n = 0;
+    int m_n = 0;
+    auto fetch = [&](int sb) {
+        o_n = sub_off[s0 + sb];
+        m_n = (int)(sub_off[s0 + sb + 1] - o_n);
+        const T* A = pk + pk_off[s0 + sb];
+        const int np = m_n * (m_n + 1) / 2, nx = m_n * NR;
+        const T* r = rloc + o_n * NR;
+#pragma unroll
+        for (int g = 0; g < PMAX; g += PG)
+            if (g * 64 < np) {
+#pragma unroll
+                for (int u = g; u < g + PG; ++u) ra[u] = A[min(lane + 64 * u, np - 1)];
+            }
+#pragma unroll
+        for (int g = 0; g < XMAX; g += PG)
+            if (g * 64 < nx) {
+#pragma unroll
+                for (int u = g; u < g + PG; ++u) rx[u] = r[min(lane + 64 * u, nx - 1)];
+            }
+    };
     // the factor form keeps its sums in FP64 (FP32 storage): its two products
     // would otherwise each add FP32 rounding to an ill-conditioned local solve
     using Acc = typename std::conditional<FACT, double, T>::type;
-    if (FACT) {
+    int sb = blockIdx.x;
+    if (sb < n_sub) fetch(sb);
+    for (; sb < n_sub; sb += gridDim.x) {
+        const int64_t o = o_n;
+        const int m = m_n;
+        const int np = m * (m + 1) / 2;
+        __syncthreads();                                   // the previous subdomain's reads of LDS are done
+#pragma unroll
+        for (int u = 0; u < PMAX; ++u)
+            if (lane + 64 * u < np) s_a[lane + 64 * u] = ra[u];
+#pragma unroll
+        for (int u = 0; u < XMAX; ++u)
+            if (lane + 64 * u < m * NR) s_x[lane + 64 * u] = rx[u];
+        __syncthreads();
+        // this subdomain's DOFs and their current x, loaded ahead of the prefetch so
+        // that waiting for them does not wait for it (lanes >= m read a valid entry and
+        // store nothing; a masked entry reads x[0]); the colour's subdomains are
+        // disjoint, so no other wave writes these x during the launch
+        const int32_t d = m > 0 ? sub_dofs[o + min(lane, m - 1)] : -1;
+        T xo[NR];
+#pragma unroll
+        for (int k = 0; k < NR; ++k) xo[k] = x[(int64_t)max(d, 0) * NR + k];
+        if (sb + (int)gridDim.x < n_sub) fetch(sb + gridDim.x);   // in flight during the arithmetic below
+        if (FACT) {
+            if (lane < m) {
+                const int i = lane;
+                const int ri = i * (i + 1) / 2;
+                Acc wv[NR];
+#pragma unroll
+                for (int k = 0; k < NR; ++k) wv[k] = 0;
+                for (int j = 0; j <= i; ++j) {
+                    const Acc a = s_a[ri + j];
+#pragma unroll
+                    for (int k = 0; k < NR; ++k) wv[k] += a * (Acc)s_x[j * NR + k];
+                }
+#pragma unroll
+                for (int k = 0; k < NR; ++k) s_w[i * NR + k] = (T)wv[k];
+            }
+            __syncthreads();
+        }
         if (lane < m) {
             const int i = lane;
             const int ri = i * (i + 1) / 2;
-            Acc wv[NR];
+            Acc y[NR];
 #pragma unroll
-            for (int k = 0; k < NR; ++k) wv[k] = 0;
-            for (int j = 0; j <= i; ++j) {
-                const Acc a = s_a[ri + j];
+            for (int k = 0; k < NR; ++k) y[k] = 0;
+            if (FACT) {
+                for (int j = i; j < m; ++j) {
+                    const Acc a = s_a[j * (j + 1) / 2 + i];
 #pragma unroll
-                for (int k = 0; k < NR; ++k) wv[k] += a * (Acc)s_x[j * NR + k];
+                    for (int k = 0; k < NR; ++k) y[k] += a * (Acc)s_w[j * NR + k];
+                }
+            } else {
+                for (int j = 0; j < m; ++j) {
+                    const T a = s_a[j <= i ? ri + j : j * (j + 1) / 2 + i];
+#pragma unroll
+                    for (int k = 0; k < NR; ++k) y[k] += a * s_x[j * NR + k];
+                }
             }
+            if (d >= 0) {                        // < 0: masked entry
+                T* dst = x + (int64_t)d * NR;
 #pragma unroll
-            for (int k = 0; k < NR; ++k) s_w[i * NR + k] = (T)wv[k];
-        }
-        __syncthreads();
-    }
-    if (lane < m) {
-        const int i = lane;
-        const int ri = i * (i + 1) / 2;
-        Acc y[NR];
-#pragma unroll
-        for (int k = 0; k < NR; ++k) y[k] = 0;
-        if (FACT) {
-            for (int j = i; j < m; ++j) {
-                const Acc a = s_a[j * (j + 1) / 2 + i];
-#pragma unroll
-                for (int k = 0; k < NR; ++k) y[k] += a * (Acc)s_w[j * NR + k];
+                for (int k = 0; k < NR; ++k) dst[k] = xo[k] + y[k];
             }
-        } else {
-            for (int j = 0; j < m; ++j) {
-                const T a = s_a[j <= i ? ri + j : j * (j + 1) / 2 + i];
-#pragma unroll
-                for (int k = 0; k < NR; ++k) y[k] += a * s_x[j * NR + k];
-            }
-        }
-        const int32_t d = sub_dofs[o + i];   // < 0: masked entry
-        if (d >= 0) {
-            T* dst = x + (int64_t)d * NR;
-#pragma unroll
-            for (int k = 0; k < NR; ++k) dst[k] += y[k];
         }
     }
 }
@@ -944,15 +1004,18 @@ void launch_small_sub(int64_t s0, int64_t n_sub, const int64_t* sub_off, const i
                       bool fact) {
     if (n_sub <= 0) return;
     if (max_m < 1 || max_m > SMALL_M) throw std::runtime_error("launch_small_sub: max_m outside 1 .. SMALL_M");
-    if (fact) {
-        const size_t lds = ((size_t)max_m * (max_m + 1) / 2 + 2 * (size_t)max_m * NR) * sizeof(T);
-        hipLaunchKernelGGL((k_small_sub<T, NR, true>), dim3((unsigned)n_sub), dim3(64), lds, st, (int32_t)s0,
-                           sub_off, sub_dofs, pk_off, pk, rloc, x, max_m);
-    } else {
-        const size_t lds = ((size_t)max_m * (max_m + 1) / 2 + (size_t)max_m * NR) * sizeof(T);
-        hipLaunchKernelGGL((k_small_sub<T, NR, false>), dim3((unsigned)n_sub), dim3(64), lds, st, (int32_t)s0,
-                           sub_off, sub_dofs, pk_off, pk, rloc, x, max_m);
-    }
+    if (n_sub > INT32_MAX) throw std::runtime_error("launch_small_sub: more than 2^31 - 1 subdomains");
+    const size_t lds = ((size_t)max_m * (max_m + 1) / 2 + (fact ? 2 : 1) * (size_t)max_m * NR) * sizeof(T);
+    // persistent waves: as many as fit on the device at once (LDS or registers bound)
+    auto kern = fact ? &k_small_sub<T, NR, true> : &k_small_sub<T, NR, false>;
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(kern), 64, lds) !=
+            hipSuccess ||
+        per_cu < 1)
+        per_cu = (int)std::max<size_t>(1, std::min<size_t>(8, (size_t)(160 * 1024) / lds));
+    const unsigned grid = (unsigned)std::min<int64_t>(n_sub, (int64_t)per_cu * device_cu_count());
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(64), lds, st, (int32_t)s0, (int32_t)n_sub, sub_off, sub_dofs, pk_off,
+                       pk, rloc, x, max_m);
 }
 
 template <typename T, int NR>
