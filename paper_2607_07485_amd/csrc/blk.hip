@@ -577,17 +577,24 @@ __global__ void __launch_bounds__(64) k_small_sub(int32_t s0, int32_t n_sub, con
     }
 }
 
-// Transfers for aggregates with |omega| <= SMALL_M, one thread per (coarse DOF,
-// right-hand side) for the restriction and per (aggregate entry, right-hand side)
-// for the prolongation; four independent entries (modes) per step, summed in four
-// partial sums added in a fixed order.
-template <typename T, int NR>
+// Transfers for aggregates with |omega| <= SMALL_M, one thread per coarse DOF for
+// the restriction and per aggregate entry for the prolongation, each for all NR
+// right-hand sides (the index and the Z entry are loaded once for the NR products;
+// AL: the NR interleaved values of a DOF are 16-byte aligned and load as 16-byte
+// vectors); four independent entries (modes) per step, summed in four partial sums
+// added in a fixed order.
+template <typename T, int NR, bool AL>
+__device__ inline void load_nr(const T* p, T (&v)[NR]) {
+    const T* q = AL ? static_cast<const T*>(__builtin_assume_aligned(p, 16)) : p;
+#pragma unroll
+    for (int k = 0; k < NR; ++k) v[k] = q[k];
+}
+
+template <typename T, int NR, bool AL>
 __global__ void __launch_bounds__(WG) k_restrict_small(int64_t nc, const int32_t* agg_of_c, const int64_t* agg_ptr,
                                                        const int32_t* agg_dofs, const int64_t* zoff,
                                                        const int64_t* coff, const T* Zc, const T* t, T* rc) {
-    for (int64_t e = blockIdx.x * (int64_t)WG + tid(); e < nc * NR; e += (int64_t)gridDim.x * WG) {
-        const int64_t c = e / NR;
-        const int k = (int)(e % NR);
+    for (int64_t c = blockIdx.x * (int64_t)WG + tid(); c < nc; c += (int64_t)gridDim.x * WG) {
         const int ag = agg_of_c[c];
         if (ag < 0) continue;
         const int64_t a0 = agg_ptr[ag];
@@ -595,46 +602,85 @@ __global__ void __launch_bounds__(WG) k_restrict_small(int64_t nc, const int32_t
         const T* z = Zc + zoff[ag] + (c - coff[ag]) * nw;
         const int32_t* dd = agg_dofs + a0;
         // four independent entries per step: their indices, then their gathers
-        T acc0 = 0, acc1 = 0, acc2 = 0, acc3 = 0;
+        T acc[4][NR];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int k = 0; k < NR; ++k) acc[u][k] = 0;
         int a = 0;
         for (; a + 4 <= nw; a += 4) {
-            const int32_t d0 = dd[a], d1 = dd[a + 1], d2 = dd[a + 2], d3 = dd[a + 3];
-            const T z0 = z[a], z1 = z[a + 1], z2 = z[a + 2], z3 = z[a + 3];
-            acc0 += z0 * t[(int64_t)d0 * NR + k];
-            acc1 += z1 * t[(int64_t)d1 * NR + k];
-            acc2 += z2 * t[(int64_t)d2 * NR + k];
-            acc3 += z3 * t[(int64_t)d3 * NR + k];
+            int32_t d[4];
+            T zz[4], tv[4][NR];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                d[u] = dd[a + u];
+                zz[u] = z[a + u];
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) load_nr<T, NR, AL>(t + (int64_t)d[u] * NR, tv[u]);
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+#pragma unroll
+                for (int k = 0; k < NR; ++k) acc[u][k] += zz[u] * tv[u][k];
         }
-        for (; a < nw; ++a) acc0 += z[a] * t[(int64_t)dd[a] * NR + k];
-        rc[e] = (acc0 + acc1) + (acc2 + acc3);
+        for (; a < nw; ++a) {
+            T tv[NR];
+            const T zz = z[a];
+            load_nr<T, NR, AL>(t + (int64_t)dd[a] * NR, tv);
+#pragma unroll
+            for (int k = 0; k < NR; ++k) acc[0][k] += zz * tv[k];
+        }
+        T* out = AL ? static_cast<T*>(__builtin_assume_aligned(rc + c * NR, 16)) : rc + c * NR;
+#pragma unroll
+        for (int k = 0; k < NR; ++k) out[k] = (acc[0][k] + acc[1][k]) + (acc[2][k] + acc[3][k]);
     }
 }
 
-template <typename T, int NR>
+template <typename T, int NR, bool AL>
 __global__ void __launch_bounds__(WG) k_prolong_small(int64_t na, const int32_t* agg_of_p, const int64_t* agg_ptr,
                                                       const int32_t* agg_dofs, const int64_t* zoff,
                                                       const int32_t* k, const int64_t* coff, const T* Zc,
                                                       const T* ec, T* x) {
-    for (int64_t e = blockIdx.x * (int64_t)WG + tid(); e < na * NR; e += (int64_t)gridDim.x * WG) {
-        const int64_t p = e / NR;
-        const int q = (int)(e % NR);
+    for (int64_t p = blockIdx.x * (int64_t)WG + tid(); p < na; p += (int64_t)gridDim.x * WG) {
         const int ag = agg_of_p[p];
         if (ag < 0) continue;
         const int64_t a0 = agg_ptr[ag];
         const int nw = (int)(agg_ptr[ag + 1] - a0);
         const int kk = k[ag];
         const T* z = Zc + zoff[ag] + (p - a0);
-        const T* ev = ec + coff[ag] * NR + q;
-        T acc0 = 0, acc1 = 0, acc2 = 0, acc3 = 0;
+        const T* ev = ec + coff[ag] * NR;
+        T acc[4][NR];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int q = 0; q < NR; ++q) acc[u][q] = 0;
         int s = 0;
         for (; s + 4 <= kk; s += 4) {
-            acc0 += z[(int64_t)s * nw] * ev[(int64_t)s * NR];
-            acc1 += z[(int64_t)(s + 1) * nw] * ev[(int64_t)(s + 1) * NR];
-            acc2 += z[(int64_t)(s + 2) * nw] * ev[(int64_t)(s + 2) * NR];
-            acc3 += z[(int64_t)(s + 3) * nw] * ev[(int64_t)(s + 3) * NR];
+            T zz[4], e[4][NR];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                zz[u] = z[(int64_t)(s + u) * nw];
+                load_nr<T, NR, AL>(ev + (int64_t)(s + u) * NR, e[u]);
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+#pragma unroll
+                for (int q = 0; q < NR; ++q) acc[u][q] += zz[u] * e[u][q];
         }
-        for (; s < kk; ++s) acc0 += z[(int64_t)s * nw] * ev[(int64_t)s * NR];
-        x[(int64_t)agg_dofs[p] * NR + q] += (acc0 + acc1) + (acc2 + acc3);
+        for (; s < kk; ++s) {
+            T e[NR];
+            const T zz = z[(int64_t)s * nw];
+            load_nr<T, NR, AL>(ev + (int64_t)s * NR, e);
+#pragma unroll
+            for (int q = 0; q < NR; ++q) acc[0][q] += zz * e[q];
+        }
+        T* dst = x + (int64_t)agg_dofs[p] * NR;
+        if (AL) dst = static_cast<T*>(__builtin_assume_aligned(dst, 16));
+        T old[NR];
+#pragma unroll
+        for (int q = 0; q < NR; ++q) old[q] = dst[q];
+#pragma unroll
+        for (int q = 0; q < NR; ++q) dst[q] = old[q] + ((acc[0][q] + acc[1][q]) + (acc[2][q] + acc[3][q]));
     }
 }
 
@@ -1022,8 +1068,12 @@ template <typename T, int NR>
 void launch_restrict_small(int64_t nc, const int32_t* agg_of_c, const int64_t* agg_ptr, const int32_t* agg_dofs,
                            const int64_t* zoff, const int64_t* coff, const T* Zc, const T* t, T* rc, hipStream_t st) {
     if (nc <= 0) return;
-    hipLaunchKernelGGL((k_restrict_small<T, NR>), dim3(grid_for(nc * NR)), dim3(WG), 0, st, nc, agg_of_c, agg_ptr,
-                       agg_dofs, zoff, coff, Zc, t, rc);
+    if ((NR * sizeof(T)) % 16 == 0 && (((uintptr_t)t | (uintptr_t)rc) & 15) == 0)
+        hipLaunchKernelGGL((k_restrict_small<T, NR, true>), dim3(grid_for(nc)), dim3(WG), 0, st, nc, agg_of_c,
+                           agg_ptr, agg_dofs, zoff, coff, Zc, t, rc);
+    else
+        hipLaunchKernelGGL((k_restrict_small<T, NR, false>), dim3(grid_for(nc)), dim3(WG), 0, st, nc, agg_of_c,
+                           agg_ptr, agg_dofs, zoff, coff, Zc, t, rc);
 }
 
 template <typename T, int NR>
@@ -1031,8 +1081,12 @@ void launch_prolong_small(int64_t na, const int32_t* agg_of_p, const int64_t* ag
                           const int64_t* zoff, const int32_t* k, const int64_t* coff, const T* Zc, const T* ec, T* x,
                           hipStream_t st) {
     if (na <= 0) return;
-    hipLaunchKernelGGL((k_prolong_small<T, NR>), dim3(grid_for(na * NR)), dim3(WG), 0, st, na, agg_of_p, agg_ptr,
-                       agg_dofs, zoff, k, coff, Zc, ec, x);
+    if ((NR * sizeof(T)) % 16 == 0 && (((uintptr_t)ec | (uintptr_t)x) & 15) == 0)
+        hipLaunchKernelGGL((k_prolong_small<T, NR, true>), dim3(grid_for(na)), dim3(WG), 0, st, na, agg_of_p,
+                           agg_ptr, agg_dofs, zoff, k, coff, Zc, ec, x);
+    else
+        hipLaunchKernelGGL((k_prolong_small<T, NR, false>), dim3(grid_for(na)), dim3(WG), 0, st, na, agg_of_p,
+                           agg_ptr, agg_dofs, zoff, k, coff, Zc, ec, x);
 }
 
 #define LSDD_SMALL_INST(T, NR)                                                                                     \
