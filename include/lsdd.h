@@ -328,7 +328,7 @@ lsdd_status lsdd_level_segments(const lsdd_hierarchy* h, int32_t level, int64_t*
  * triangles of the A_e, built on the first call (one FP64 triangle per element, plus
  * an FP32 copy when the hierarchy has an FP32 cycle), and keeps the faster; on levels
  * whose rows share per-supernode column lists it times the CSR kernels with and
- * without them, and for single vectors the sweep residuals by supernode row blocks
+ * without them, and the sweep residuals by supernode row blocks
  * (1, 2 or 4 waves per run of up to 8 sweep rows of one supernode, x gathered once
  * per run and wave; another order of the cross-lane sums); in the mixed cycle it times the factor product with and without its
  * tile rows kept in LDS.  block
@@ -344,7 +344,8 @@ lsdd_status lsdd_autotune(lsdd_hierarchy* h, int32_t block, void* hip_stream);
  * (0; available where the level's pattern is built on supernodes, i.e. every row of
  * a supernode has the same columns; same results) -- 2, 3, 4: the lists as with 1,
  * and the single-vector sweep residuals by supernode row blocks of 1, 2 or 4 waves
- * (where the level has sweeps) --, and whether the mixed cycle's
+ * (where the level has sweeps); with 4, 8 or 16 lanes for blocks, the block sweep
+ * residuals by row blocks too, with the same results as per row --, and whether the mixed cycle's
  * factor product keeps each tile row in LDS between its two passes (1) or reads it
  * again through the caches (0; same results). */
 lsdd_status lsdd_level_tuning(const lsdd_hierarchy* h, int32_t level, int32_t* out);

@@ -889,6 +889,96 @@ __global__ void k_pcg_start(int64_t len, const double* b, double* r, double* x) 
 
 // ====================================================================== launchers
 
+// The residual rows of a supernode-blocked level by supernode row blocks, for blocks
+// of NB right-hand sides: L lanes per block (blk as in k_sup_resid_blocks) take its
+// shared column list; per entry a lane gathers the NB interleaved x values once and
+// uses them for up to 4 rows of the block at a time (slots past the block's end
+// repeat its last row and are never stored).  Per row the products, the per-lane
+// sums and the cross-lane sums are those of k_csr_resid_rows_s for the same L: the
+// results are bit-identical to it.
+template <typename T, int L>
+__global__ void __launch_bounds__(WG) k_sup_resid_blocks_s(int64_t nblk, const int32_t* blk, const int32_t* rows,
+                                                           const int64_t* rowptr, const int32_t* scol,
+                                                           const int64_t* scoff, const T* val, const T* x,
+                                                           const T* r, T* out, int x_zero) {
+    constexpr int RB = 4;
+    const int lane = tid() & (L - 1);
+    const int64_t stride = (int64_t)gridDim.x * (WG / L);
+    for (int64_t b = ((int64_t)blockIdx.x * WG + tid()) / L; b < nblk; b += stride) {
+        const int32_t t0 = blk[2 * b], nb = blk[2 * b + 1];
+        const int32_t p0 = rows[t0];
+        const int64_t q0 = rowptr[p0], q1 = rowptr[p0 + 1];
+        const int64_t cb = scoff[p0] - q0;   // the list entry of position q is scol[cb + q]
+        for (int j0 = 0; j0 < nb; j0 += RB) {
+            int32_t p[RB];
+            int64_t vo[RB];   // value offset of row j relative to the first row's
+#pragma unroll
+            for (int j = 0; j < RB; ++j) {
+                p[j] = rows[t0 + min(j0 + j, nb - 1)];
+                vo[j] = rowptr[p[j]] - q0;
+            }
+            T s[RB][NB];
+#pragma unroll
+            for (int j = 0; j < RB; ++j)
+#pragma unroll
+                for (int k = 0; k < NB; ++k) s[j][k] = 0;
+            if (!x_zero) {
+                const int nit = (int)((q1 - q0 + L - 1) / L);
+                for (int it = 0; it < nit; it += 2) {
+                    const int64_t qa = q0 + lane + (int64_t)it * L, qb = qa + L;
+                    const int64_t qac = qa < q1 ? qa : q1 - 1, qbc = qb < q1 ? qb : q1 - 1;
+                    const int32_t ca = scol[cb + qac], cc = scol[cb + qbc];
+                    T va[RB], vb[RB];
+#pragma unroll
+                    for (int j = 0; j < RB; ++j) {
+                        va[j] = val[vo[j] + qac];
+                        vb[j] = val[vo[j] + qbc];
+                    }
+                    T xa[NB], xb[NB];
+                    load_xrow(x + (int64_t)ca * NB, xa);
+                    load_xrow(x + (int64_t)cc * NB, xb);
+#pragma unroll
+                    for (int j = 0; j < RB; ++j) {
+                        const T wa = qa < q1 ? va[j] : (T)0, wb = qb < q1 ? vb[j] : (T)0;
+#pragma unroll
+                        for (int k = 0; k < NB; ++k) s[j][k] += wa * xa[k];
+#pragma unroll
+                        for (int k = 0; k < NB; ++k) s[j][k] += wb * xb[k];
+                    }
+                }
+            }
+            constexpr int PL = L < NB ? NB / L : 1;   // right-hand sides per writing lane
+#pragma unroll
+            for (int j = 0; j < RB; ++j) {
+                slot_reduce<T, L>(s[j], lane);
+                if (j0 + j < nb && lane * PL < NB)
+#pragma unroll
+                    for (int i = 0; i < PL; ++i) {
+                        const int k = lane * PL + i;
+                        out[(int64_t)(t0 + j0 + j) * NB + k] = r[(int64_t)p[j] * NB + k] - s[j][i];
+                    }
+            }
+        }
+    }
+}
+
+template <typename T>
+void launch_sup_resid_blocks_b(int64_t nblk, const int32_t* blk, const int32_t* rows, const int64_t* rowptr,
+                               const int32_t* scol, const int64_t* scoff, const T* val, const T* x, const T* r, T* out,
+                               bool x_zero, int lanes, hipStream_t st) {
+    if (nblk <= 0) return;
+    const int xz = x_zero ? 1 : 0;
+    if (lanes <= 4)
+        hipLaunchKernelGGL((k_sup_resid_blocks_s<T, 4>), dim3(grid_for(nblk * 4)), dim3(WG), 0, st, nblk, blk, rows,
+                           rowptr, scol, scoff, val, x, r, out, xz);
+    else if (lanes <= 8)
+        hipLaunchKernelGGL((k_sup_resid_blocks_s<T, 8>), dim3(grid_for(nblk * 8)), dim3(WG), 0, st, nblk, blk, rows,
+                           rowptr, scol, scoff, val, x, r, out, xz);
+    else
+        hipLaunchKernelGGL((k_sup_resid_blocks_s<T, 16>), dim3(grid_for(nblk * 16)), dim3(WG), 0, st, nblk, blk,
+                           rows, rowptr, scol, scoff, val, x, r, out, xz);
+}
+
 template <typename T>
 void launch_csr_resid_rows_b(int64_t nrows, const int32_t* rows, const int64_t* rowptr, const int32_t* col,
                              const T* val, const T* x, const T* r, T* out, bool x_zero, int lanes, hipStream_t st,
@@ -1103,6 +1193,9 @@ LSDD_SMALL_INST(float, 1)
 LSDD_SMALL_INST(float, NRB)
 
 #define LSDD_BLK_INST(T)                                                                                            \
+    template void launch_sup_resid_blocks_b<T>(int64_t, const int32_t*, const int32_t*, const int64_t*,            \
+                                               const int32_t*, const int64_t*, const T*, const T*, const T*, T*,     \
+                                               bool, int, hipStream_t);                                              \
     template void launch_csr_resid_rows_b<T>(int64_t, const int32_t*, const int64_t*, const int32_t*, const T*,      \
                                              const T*, const T*, T*, bool, int, hipStream_t, const int64_t*);         \
     template void launch_csr_spmv_b<T>(int64_t, const int64_t*, const int32_t*, const T*, const T*, T*, const T*,    \

@@ -13,6 +13,13 @@ constexpr int NRB = 8;   // right-hand sides per block
 // ---------------------------------------------------------------- cycle, block vectors
 // lanes per row of the CSR kernels: 4, 8 or 16 (lane = nonzero slot, all NRB
 // right-hand sides per lane) or 32 or 64 (lane = (nonzero slot, right-hand side));
+// residual rows of a supernode-blocked level by supernode row blocks (blk, rows, out
+// as in launch_sup_resid_blocks; scol/scoff: the shared column lists), blocks of NRB
+// right-hand sides, 4 / 8 / 16 lanes per row block
+template <typename T>
+void launch_sup_resid_blocks_b(int64_t nblk, const int32_t* blk, const int32_t* rows, const int64_t* rowptr,
+                               const int32_t* scol, const int64_t* scoff, const T* val, const T* x, const T* r, T* out,
+                               bool x_zero, int lanes, hipStream_t st);
 // scoff != NULL: shared per-supernode column lists, as in launch_csr_resid_rows
 template <typename T>
 void launch_csr_resid_rows_b(int64_t nrows, const int32_t* rows, const int64_t* rowptr, const int32_t* col,

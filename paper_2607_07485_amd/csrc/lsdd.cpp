@@ -1564,6 +1564,12 @@ struct Cyc {
             launch_csr_resid_rows<T, V>(r1 - r0, lv.d_sw_sub_dofs + r0, lv.d_rowptr, lv.sup ? lv.d_scol : lv.d_col,
                                         val, x, r, rloc + r0, xz, lv.lanes, st, lv.sup ? lv.d_scoff : nullptr);
         } else {
+            if (lv.sup >= 2 && lv.d_rblk && lv.lanes_b <= 16) {
+                const int64_t b0 = lv.color_rblk0[c];
+                launch_sup_resid_blocks_b<T>(lv.color_rblk0[c + 1] - b0, lv.d_rblk + 2 * b0, lv.d_sw_sub_dofs,
+                                             lv.d_rowptr, lv.d_scol, lv.d_scoff, val, x, r, rloc, xz, lv.lanes_b, st);
+                return;
+            }
             resid_rows(r1 - r0, lv.d_sw_sub_dofs + r0, lv, val, x, r, rloc + r0 * NR, xz, st);
         }
     }
@@ -2080,7 +2086,10 @@ void autotune_levels(lsdd_hierarchy* h) {
         // vectors, by supernode row blocks of 1, 2 or 4 waves
         std::vector<int> sup_c{0};
         if (lv.d_scoff) sup_c.push_back(1);
-        if (lv.d_scoff && lv.d_rblk && NR == 1) sup_c.insert(sup_c.end(), {2, 3, 4});
+        if (lv.d_scoff && lv.d_rblk) {
+            if (NR == 1) sup_c.insert(sup_c.end(), {2, 3, 4});
+            else sup_c.push_back(2);   // blocks of right-hand sides: 4, 8 or 16 lanes per row block
+        }
         for (int sp : sup_c) {
             lv.sup = sp;
             for (int L : lane_c) {
@@ -2089,6 +2098,12 @@ void autotune_levels(lsdd_hierarchy* h) {
                     for (int32_t c = 0; c < lv.n_colors; ++c)
                         C::template resid_colour<T>(lv, c, O::val(lv), v.x, v.r, v.rloc, false, h->st);
                 });
+                if (sp >= 2 && NR > 1) {
+                    vlog("autotune level %d: supernode row blocks, %d lanes each: %.3f ms", lv.level, L, ms);
+                    if (ms < best) best = ms, pick = L, pick_sup = sp;
+                    if (L >= 16) break;
+                    continue;
+                }
                 if (sp >= 2) {
                     vlog("autotune level %d: supernode row blocks, %d wave(s) each: %.3f ms", lv.level,
                          1 << (sp - 2), ms);
@@ -2100,8 +2115,9 @@ void autotune_levels(lsdd_hierarchy* h) {
             }
         }
         lanes = pick;
-        // blocks of vectors read the lists alike for 1 and 2: keep a single-vector choice of row blocks
-        lv.sup = (NR > 1 && pick_sup == 1 && prev_sup >= 2) ? prev_sup : pick_sup;
+        // one setting serves both: blocks of right-hand sides that choose row blocks keep
+        // the single vectors' choice of waves per block
+        lv.sup = (NR > 1 && pick_sup >= 2 && prev_sup >= 2) ? prev_sup : pick_sup;
         if (NR == 1 && build_elem_apply(h, lv)) {
             // the full product (pre-restriction residual, PCG) from the CSR or the element triangles
             best = 1e300;

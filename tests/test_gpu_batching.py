@@ -407,6 +407,41 @@ def test_supernode_row_blocks_match_the_oracle(dev, sc):
         assert torch.equal(h.solve(rt)[0], h.solve(rt)[0])
 
 
+@pytest.mark.parametrize("lanes_block", [4, 8, 16])
+def test_supernode_row_blocks_for_blocks_of_rhs_are_bit_identical(dev, lanes_block):
+    """Blocks of right-hand sides (9 = a full block of 8 and a ragged one): the sweep
+    residuals by supernode row blocks (up to 4 rows of one supernode per x gather) use
+    the per-row sums of the same lane count, so the solves equal the per-row kernels'
+    bit for bit, and match the oracle per column."""
+    P = _lsdd()
+    prob, rng = _graddiv(seed=13)
+    h_or = oracle.setup(prob, oracle.Params(**GD_KW))
+    B = rng.standard_normal((9, prob.n))
+    with P.Hierarchy.setup_problem(prob, P.Params.default(**GD_KW)) as h:
+        levels = h.info()["levels"]
+        base = [h.level_tuning(l) for l in range(levels)]
+        avail = []
+        for l in range(levels):
+            try:
+                h.set_level_tuning(l, dict(base[l], shared_cols=2, lanes_block=lanes_block))
+                avail.append(l)
+            except P.LsddError as ex:
+                assert ex.code == 7
+        assert 1 in avail
+        outs = []
+        for sc in (1, 2):
+            h.set_tuning([dict(t, shared_cols=sc if l in avail else 0, lanes_block=lanes_block)
+                          for l, t in enumerate(base)])
+            X, infos = h.solve(torch.from_numpy(B).to(dev))
+            outs.append((X, [f.iters for f in infos]))
+        assert torch.equal(outs[0][0], outs[1][0]) and outs[0][1] == outs[1][1]
+        X = outs[1][0].cpu().numpy()
+        for k in (0, 8):
+            x_or, inf_or = oracle.pcg(h_or, B[k])
+            assert abs(outs[1][1][k] - inf_or.iters) <= 1
+            assert np.linalg.norm(X[k] - x_or) <= 1e-10 * np.linalg.norm(x_or)
+
+
 def test_solve_batched_over_separate_hierarchies(dev):
     """lsdd_solve_batched on three separately built hierarchies (two elasticity meshes and
     a grad-div one, two right-hand sides each): every instance's result equals its own
