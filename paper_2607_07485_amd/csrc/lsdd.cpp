@@ -2081,6 +2081,8 @@ void autotune_levels(lsdd_hierarchy* h) {
         const std::vector<int> lane_c = NR > 1 ? std::vector<int>{4, 8, 16, 32, 64} : std::vector<int>{8, 16, 32, 64};
         double best = 1e300;
         int pick = lanes, pick_sup = 0;
+        double best_row = 1e300;   // the per-row kernels' best lane count: it also serves the
+        int pick_row = lanes;      // full products and the RAS sweep when row blocks win
         const int prev_sup = lv.sup;
         // a supernode-blocked level: also with the shared column lists and, for single
         // vectors, by supernode row blocks of 1, 2 or 4 waves
@@ -2107,14 +2109,15 @@ void autotune_levels(lsdd_hierarchy* h) {
                 if (sp >= 2) {
                     vlog("autotune level %d: supernode row blocks, %d wave(s) each: %.3f ms", lv.level,
                          1 << (sp - 2), ms);
-                    if (ms < best) best = ms, pick = lanes, pick_sup = sp;
+                    if (ms < best) best = ms, pick_sup = sp;
                     break;
                 }
                 vlog("autotune level %d: CSR lanes %d%s: %.3f ms", lv.level, L, sp ? ", shared column lists" : "", ms);
                 if (ms < best) best = ms, pick = L, pick_sup = sp;
+                if (ms < best_row) best_row = ms, pick_row = L;
             }
         }
-        lanes = pick;
+        lanes = (NR == 1 && pick_sup >= 2) ? pick_row : pick;
         // one setting serves both: blocks of right-hand sides that choose row blocks keep
         // the single vectors' choice of waves per block
         lv.sup = (NR > 1 && pick_sup >= 2 && prev_sup >= 2) ? prev_sup : pick_sup;
