@@ -1048,6 +1048,59 @@ void launch_sub_finalize_b(int64_t r0, int64_t r1, const int32_t* pos_sub, const
                            pos_sub, sub_off, scr_off, scr, sub_dofs, x, accumulate ? 1 : 0, chl);
 }
 
+// The same sums from the per-entry address table of the single-vector finalize
+// (int4 per overlap entry: row-part address, column-part address + J * 64 + l, J,
+// row-part chunks | tile rows << 16, in single-vector units; the block layout holds
+// NB consecutive values at NB times that address): one table load replaces the
+// entry's subdomain and offset lookups.  Same per-thread subsets, same order, same
+// results as k_sub_finalize_b with accumulate.
+template <typename T, int FL>
+__global__ void __launch_bounds__(WG) k_sub_finalize_tab_b(int64_t r0, int64_t r1, const int4* tab, const T* scr,
+                                                           const int32_t* sub_dofs, T* x) {
+    constexpr int ND = WG / FL;
+    __shared__ T s_y[FL][ND][NB];
+    const int dl = tid() % ND, j = tid() / ND;
+    const int64_t t = r0 + (int64_t)blockIdx.x * ND + dl;
+    T y[NB];
+#pragma unroll
+    for (int q = 0; q < NB; ++q) y[q] = 0;
+    if (t < r1) {
+        const int4 e = tab[t];
+        const T* part = scr + (int64_t)(uint32_t)e.x * NB;
+        const T* colpart = scr + (int64_t)(uint32_t)e.y * NB;
+        const int J = e.z, nch = e.w & 0xffff, nt = e.w >> 16;
+        const int K = nch + (nt - 1 - J);
+        for (int k = j; k < K; k += FL) {
+            const int64_t I = J + 1 + (k - nch);
+            const T* src = k < nch ? part + (int64_t)k * 64 * NB : colpart + I * (I - 1) / 2 * 64 * NB;
+#pragma unroll
+            for (int q = 0; q < NB; ++q) y[q] += src[q];
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < NB; ++q) s_y[j][dl][q] = y[q];
+    __syncthreads();
+    if (j < NB && t < r1) {
+        T v = s_y[0][dl][j];
+        for (int q = 1; q < FL; ++q) v += s_y[q][dl][j];
+        const int64_t d = sub_dofs[t];   // < 0: masked entry
+        if (d >= 0) x[d * NB + j] = x[d * NB + j] + v;
+    }
+}
+
+template <typename T>
+void launch_sub_finalize_tab_b(int64_t r0, int64_t r1, const int32_t* tab, const T* scr, const int32_t* sub_dofs,
+                               T* x, int fl, hipStream_t st) {
+    if (r1 <= r0) return;
+    const int4* tb = reinterpret_cast<const int4*>(tab);
+    if (fl >= 32)
+        hipLaunchKernelGGL((k_sub_finalize_tab_b<T, 32>), dim3(grid_for(r1 - r0, WG / 32)), dim3(WG), 0, st, r0, r1,
+                           tb, scr, sub_dofs, x);
+    else
+        hipLaunchKernelGGL((k_sub_finalize_tab_b<T, 8>), dim3(grid_for(r1 - r0, WG / 8)), dim3(WG), 0, st, r0, r1,
+                           tb, scr, sub_dofs, x);
+}
+
 template <typename T>
 void launch_restrict_b(int64_t n_items, const int32_t* items, const int64_t* agg_ptr, const int32_t* agg_dofs,
                        const int64_t* zoff, const int32_t* k, const int64_t* coff, const T* Zc, const T* t, T* rc,
@@ -1202,6 +1255,8 @@ LSDD_SMALL_INST(float, NRB)
                                        int, hipStream_t, const int64_t*);                                             \
     template void launch_sub_symv_b<T>(int64_t, const int32_t*, const int64_t*, const int64_t*, const T*, const T*,  \
                                        const int64_t*, T*, int, hipStream_t);                                         \
+    template void launch_sub_finalize_tab_b<T>(int64_t, int64_t, const int32_t*, const T*, const int32_t*, T*, int, \
+                                               hipStream_t);                                                          \
     template void launch_sub_finalize_b<T>(int64_t, int64_t, const int32_t*, const int64_t*, const int64_t*,         \
                                            const T*, const int32_t*, T*, bool, int, int, hipStream_t);                \
     template void launch_restrict_b<T>(int64_t, const int32_t*, const int64_t*, const int32_t*, const int64_t*,      \

@@ -31,6 +31,11 @@ void launch_csr_spmv_b(int64_t n, const int64_t* rowptr, const int32_t* col, con
 template <typename T>
 void launch_sub_symv_b(int64_t n_items, const int32_t* items, const int64_t* sub_off, const int64_t* tp_off,
                        const T* tiles, const T* rloc, const int64_t* scr_off, T* scr, int chl, hipStream_t st);
+// the block finalize from the single-vector finalize's address table (int4 per entry);
+// accumulates into x
+template <typename T>
+void launch_sub_finalize_tab_b(int64_t r0, int64_t r1, const int32_t* tab, const T* scr, const int32_t* sub_dofs,
+                               T* x, int fl, hipStream_t st);
 template <typename T>
 void launch_sub_finalize_b(int64_t r0, int64_t r1, const int32_t* pos_sub, const int64_t* sub_off,
                            const int64_t* scr_off, const T* scr, const int32_t* sub_dofs, T* x, bool accumulate,

@@ -1602,8 +1602,9 @@ struct Cyc {
     // x += the large-overlap corrections of colour c of a sweep (scatter list dofs)
     static void finalize_colour(Level& lv, int32_t c, const T* scr, const int32_t* dofs, T* x, hipStream_t st) {
         const int64_t r0 = lv.color_row0[c], rm = lv.color_rmid[c];
-        if (NR == 1 && lv.d_fin_tab) {
+        if (lv.d_fin_tab && dofs) {
             if constexpr (NR == 1) launch_sub_finalize_tab<T>(r0, rm, lv.d_fin_tab, scr, dofs, x, lv.fl, st);
+            else launch_sub_finalize_tab_b<T>(r0, rm, lv.d_fin_tab, scr, dofs, x, lv.fl, st);
             return;
         }
         finalize(r0, rm, lv.d_pos_sub, lv.d_sw_sub_off, lv.d_scr_off, scr, dofs, x, true, lv.chl, lv.fl, st);
